@@ -1,0 +1,195 @@
+/*
+ * mad.h -- C ABI of the MI355X (gfx950) diamond-sampling library.
+ *
+ * Problem (Ballard, Kolda, Pinar, Seshadhri, "Diamond Sampling for
+ * Approximate Maximum All-pairs Dot-product (MAD) Search", Definition 1):
+ * given vectors a_1..a_m and b_1..b_n in R^d, find the t pairs (i, j) with
+ * the largest |a_i . b_j|.  The library runs diamond sampling (Alg. 2) and
+ * its postprocessing (Alg. 3) on one GPU, plus an exhaustive brute force.
+ *
+ * Conventions for every entry point:
+ *  - Layout: vectors are ROWS.  A is m x d row-major fp32 (a_i = A[i*d ..]),
+ *    B is n x d row-major fp32.  This is the same memory as the paper's
+ *    column-vector d x m matrices (Sec. 2).
+ *  - Pointers marked (device) are device memory on the current HIP device;
+ *    (host) pointers are host memory.  The caller owns every array it passes.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls enqueue their work on it and return without waiting, except where
+ *    a call says it synchronises.
+ *  - Return value: MAD_OK or a negative MAD_E* code; mad_last_error() then
+ *    describes the failure (thread-local).  No exception crosses the ABI.
+ *  - Results are a deterministic function of the inputs, t, s, t' and seed:
+ *    the sampler draws sample l from the Philox4x64-10 block with counter
+ *    (l, query, 0, 0) and key (seed, 0), and scores are exact int64 fixed
+ *    point, so launch shapes and atomics ordering never change a result.
+ */
+#ifndef MAD_H
+#define MAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One result pair.  c = a_i . b_j computed in fp32 (Alg. 3 line "post2");
+ * x = the sampler's score x_ij (Alg. 2 line "dx") converted to fp32. */
+typedef struct mad_pair {
+  int64_t i;
+  int64_t j;
+  float c;
+  float x;
+} mad_pair;
+
+enum {
+  MAD_OK = 0,
+  MAD_EINVAL = -1,       /* bad argument (shape, pointer, t' < t, NaN/Inf) */
+  MAD_ENOMEM = -2,       /* device allocation failed                       */
+  MAD_EHIP = -3,         /* a HIP runtime call failed                      */
+  MAD_EOVERFLOW = -4,    /* an internal capacity was exceeded              */
+  MAD_EUNSUPPORTED = -5  /* option not available                           */
+};
+
+/* Arithmetic of the exhaustive brute force (mad_bruteforce_topk). */
+enum { MAD_FP32 = 0, MAD_BF16 = 1, MAD_FP8_E4M3 = 2 };
+
+/* Plan flags. */
+enum {
+  MAD_FLAG_NONE = 0,
+  MAD_FLAG_NO_CHECK = 1u << 0  /* skip the NaN/Inf scan of the inputs */
+};
+
+typedef struct mad_plan mad_plan;
+
+/* ---------------------------------------------------------------------------
+ * mad_plan_create_dense -- preprocessing of Alg. 2 (line "dw" and the
+ * cumulative tables of Sec. 3.3 "Preprocessing" / Sec. 5.2) for dense A, B.
+ *
+ * Builds, in FP64 on the GPU, na_i = ||a_i||_1, nb_k = ||B_k*||_1,
+ * v_k = sum_i |a_ki| na_i and the stage weights nb_k v_k (their total is
+ * ||W||_1 with w_ki = |a_ki| ||a_i||_1 ||B_k*||_1), then one alias table per
+ * stage distribution: T0 over k (weight nb_k v_k), T1[k] over i (weight
+ * |a_ki| na_i), T2[k] over j (weight |b_kj|), T3[i] over k' (weight |a_k'i|).
+ *   A (device) m x d fp32, B (device) n x d fp32; 1 <= m, n < 2^31, d >= 1.
+ *   The plan BORROWS A and B: they must stay allocated and unchanged until
+ *   mad_plan_destroy (mad_plan_refresh re-reads them after a change).
+ *   flags: MAD_FLAG_*.  *plan (host) receives the new plan.
+ * Allocates device memory and synchronises `stream` once (to report
+ * non-finite inputs as MAD_EINVAL).
+ * ------------------------------------------------------------------------- */
+int mad_plan_create_dense(const float* A, int64_t m, const float* B,
+                          int64_t n, int64_t d, uint32_t flags, void* stream,
+                          mad_plan** plan);
+
+/* ---------------------------------------------------------------------------
+ * mad_plan_create_csr -- the same preprocessing for sparse vectors given as
+ * compressed rows of the vector-major arrays: vector i of A has entries
+ * a_idx[a_ptr[i] .. a_ptr[i+1]) (coordinates, strictly increasing, in
+ * [0, d)) with values a_val[...]; likewise B.  All arrays (device);
+ * ptr arrays hold m+1 (n+1) int64 entries.  Borrowed like the dense form.
+ * Returns MAD_EINVAL for unsorted/duplicate/out-of-range coordinates.
+ * ------------------------------------------------------------------------- */
+int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
+                        const float* a_val, int64_t m, const int64_t* b_ptr,
+                        const int32_t* b_idx, const float* b_val, int64_t n,
+                        int64_t d, uint32_t flags, void* stream,
+                        mad_plan** plan);
+
+/* Rebuild every table of `plan` from the (same-shaped) borrowed inputs,
+ * e.g. after their contents changed.  No allocation; synchronises once
+ * unless the plan was made with MAD_FLAG_NO_CHECK. */
+int mad_plan_refresh(mad_plan* plan, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * mad_plan_topk -- Alg. 2 sampling loop + Alg. 3 postprocessing.
+ *   s        number of three-path samples (Alg. 2 loop over l), s >= 0
+ *   t_prime  budget of exact dot products (Alg. 3), t_prime >= t
+ *   t        number of pairs returned, t >= 1, t <= m*n
+ *   seed     Philox key word 0
+ *   out      (device) capacity t, filled in order of |c| descending, then
+ *            (i, j) ascending
+ *   n_out    (device) one int64: number of pairs written (<= t; fewer when
+ *            fewer than t pairs have a positive score, Alg. 3)
+ * Scores: x_ij accumulates sgn(a_ki b_kj a_k'i) b_k'j as int64 fixed point
+ * with 2^F units, F = 62 - e - ceil(log2 max(s, 2)) where max|b| < 2^e.
+ * Candidates are the pairs with x_ij > 0, the top t' of them by x
+ * (ties by (i, j) ascending) are verified with fp32 dot products.
+ * The first call for a given size allocates workspace; later calls with
+ * the same or smaller (s, t', t) neither allocate nor synchronise.
+ * ------------------------------------------------------------------------- */
+int mad_plan_topk(mad_plan* plan, int64_t t, int64_t s, int64_t t_prime,
+                  uint64_t seed, mad_pair* out, int64_t* n_out, void* stream);
+
+/* One-shot form of the two calls above for dense inputs:
+ * create + topk + destroy.  Synchronises `stream` before returning. */
+int mad_topk(const float* A, int64_t m, const float* B, int64_t n, int64_t d,
+             int64_t t, int64_t s, int64_t t_prime, uint64_t seed,
+             mad_pair* out, int64_t* n_out, void* stream);
+
+/* Release a plan and its device memory (synchronises the device first). */
+void mad_plan_destroy(mad_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Plan statistics of the last mad_plan_topk (host outputs, synchronises):
+ *   wnorm    ||W||_1 (FP64, Alg. 2 line "dw" summed)
+ *   closed   closed three-paths (diamonds) among the s samples
+ *   distinct pairs with at least one closed diamond (nnz(X) <= s, Sec. 3.1)
+ *   n_pos    pairs with x_ij > 0 (|Omega_s|, Alg. 3)
+ *   n_cand   verified candidates (|Omega_t'|)
+ * Any pointer may be NULL.
+ * ------------------------------------------------------------------------- */
+int mad_plan_stats(mad_plan* plan, double* wnorm, int64_t* closed,
+                   int64_t* distinct, int64_t* n_pos, int64_t* n_cand);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* mad_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Parity / debug entry points (not on the hot path).  All synchronise.
+ *
+ * mad_debug_table: copy one alias table.  which = 0: T0; 1: T1[idx] (over
+ * i for coordinate idx); 2: T2[idx] (over j); 3: T3[idx] (over k' for
+ * vector idx).  thr, alias (host) receive 2^L words each (capacity cap);
+ * entry r gives item r with probability thr/2^31 and alias[r] otherwise
+ * (positions; item (host, optional, capacity cap) maps position -> index).
+ * *nslots (host) = 2^L.  Returns MAD_EINVAL if cap < 2^L.
+ * ------------------------------------------------------------------------- */
+int mad_debug_table(mad_plan* plan, int which, int64_t idx, uint32_t* thr,
+                    uint32_t* alias, int32_t* item, int64_t cap,
+                    int64_t* nslots);
+
+/* FP64 norms: na (host, m), nb (host, d), v (host, d), om (host, d); any
+ * may be NULL. */
+int mad_debug_norms(mad_plan* plan, double* na, double* nb, double* v,
+                    double* om);
+
+/* Per-sample stream of samples l0 .. l0+count-1 (Alg. 2 lines ds1..dx):
+ * k, i, j, kp (device int32) and inc (device int64: the fixed-point
+ * increment, 0 when b_k'j = 0).  F is the fixed-point exponent to use;
+ * qid is the query word of the counter (0 for MAD). */
+int mad_debug_samples(mad_plan* plan, uint64_t seed, uint64_t qid,
+                      int64_t l0, int64_t count, int F, int32_t* k,
+                      int32_t* i, int32_t* j, int32_t* kp, int64_t* inc,
+                      void* stream);
+
+/* Score table X of the last mad_plan_topk: every pair with a closed
+ * diamond, unordered.  keys (device int64, i*n + j), xfix (device int64),
+ * capacity cap; *n (host) = number of pairs; *F (host) = fixed-point
+ * exponent used.  Returns MAD_EOVERFLOW if cap is too small. */
+int mad_debug_scores(mad_plan* plan, int64_t* keys, int64_t* xfix,
+                     int64_t cap, int64_t* n, int* F);
+
+/* Candidates Omega_t' of the last mad_plan_topk, unordered: keys, xfix
+ * (device int64), c (device fp32), capacity cap; *n (host). */
+int mad_debug_candidates(mad_plan* plan, int64_t* keys, int64_t* xfix,
+                         float* c, int64_t cap, int64_t* n);
+
+/* Fixed-point exponent F the plan uses for s samples (host). */
+int mad_fix_exponent(mad_plan* plan, int64_t s, int* F);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAD_H */

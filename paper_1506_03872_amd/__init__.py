@@ -1,0 +1,266 @@
+"""Python binding of libmad.so (include/mad.h): diamond sampling for MAD
+search on one MI355X.
+
+Argument marshalling only: every step runs in the HIP library.  Tensors are
+torch CUDA (ROCm) tensors; the current torch stream is passed to the
+library.  Importing this module does not need a GPU, but loading the library
+does need the built ``libmad.so``: call ``paper_1506_03872_amd.build.build()``
+first.  There is no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmad.so")
+
+MAD_OK, MAD_EINVAL, MAD_ENOMEM, MAD_EHIP, MAD_EOVERFLOW, MAD_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+MAD_FP32, MAD_BF16, MAD_FP8_E4M3 = 0, 1, 2
+MAD_FLAG_NONE, MAD_FLAG_NO_CHECK = 0, 1
+
+# every symbol include/mad.h declares
+EXPORTS = (
+    "mad_plan_create_dense", "mad_plan_create_csr", "mad_plan_refresh",
+    "mad_plan_topk", "mad_topk", "mad_plan_destroy", "mad_plan_stats",
+    "mad_last_error", "mad_debug_table", "mad_debug_norms",
+    "mad_debug_samples", "mad_debug_scores", "mad_debug_candidates",
+    "mad_fix_exponent",
+)
+
+
+class MadError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+_lib = None
+_P, _i64, _u64, _i32, _u32 = (C.c_void_p, C.c_int64, C.c_uint64, C.c_int32,
+                              C.c_uint32)
+
+
+def lib():
+    """Load libmad.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmad.so is not built: run "
+                              "python -m paper_1506_03872_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.mad_last_error.restype = C.c_char_p
+        L.mad_plan_create_dense.argtypes = [_P, _i64, _P, _i64, _i64, _u32,
+                                            _P, C.POINTER(_P)]
+        L.mad_plan_create_csr.argtypes = [_P, _P, _P, _i64, _P, _P, _P, _i64,
+                                          _i64, _u32, _P, C.POINTER(_P)]
+        L.mad_plan_refresh.argtypes = [_P, _P]
+        L.mad_plan_topk.argtypes = [_P, _i64, _i64, _i64, _u64, _P, _P, _P]
+        L.mad_topk.argtypes = [_P, _i64, _P, _i64, _i64, _i64, _i64, _i64,
+                               _u64, _P, _P, _P]
+        L.mad_plan_destroy.argtypes = [_P]
+        L.mad_plan_destroy.restype = None
+        L.mad_plan_stats.argtypes = [_P, _P, _P, _P, _P, _P]
+        L.mad_debug_table.argtypes = [_P, C.c_int, _i64, _P, _P, _P, _i64, _P]
+        L.mad_debug_norms.argtypes = [_P, _P, _P, _P, _P]
+        L.mad_debug_samples.argtypes = [_P, _u64, _u64, _i64, _i64, C.c_int,
+                                        _P, _P, _P, _P, _P, _P]
+        L.mad_debug_scores.argtypes = [_P, _P, _P, _i64, _P, _P]
+        L.mad_debug_candidates.argtypes = [_P, _P, _P, _P, _i64, _P]
+        L.mad_fix_exponent.argtypes = [_P, _i64, _P]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MAD_OK:
+        raise MadError(rc, lib().mad_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be contiguous %s" % (name, dtype))
+    return C.c_void_p(t.data_ptr())
+
+
+def unpack_pairs(raw, n):
+    """mad_pair records (a (t, 3) int64 tensor) -> dict of i, j, c, x."""
+    import torch
+    r = raw[:n]
+    if n == 0:
+        e = torch.empty(0, dtype=torch.int64, device=raw.device)
+        f = torch.empty(0, dtype=torch.float32, device=raw.device)
+        return dict(i=e, j=e.clone(), c=f, x=f.clone())
+    cx = r[:, 2].clone(memory_format=torch.contiguous_format)
+    cx = cx.view(torch.float32).view(-1, 2)
+    return dict(i=r[:, 0].clone(), j=r[:, 1].clone(), c=cx[:, 0].clone(),
+                x=cx[:, 1].clone())
+
+
+class Plan:
+    """Owning handle of a mad_plan (tables of Alg. 2 for one A, B)."""
+
+    def __init__(self, handle, keep, m, n, d):
+        self._h = handle
+        self._keep = keep
+        self.m, self.n, self.d = m, n, d
+
+    @classmethod
+    def dense(cls, A, B, flags=MAD_FLAG_NONE, stream=None):
+        import torch
+        m, d = A.shape
+        n, d2 = B.shape
+        if d != d2:
+            raise ValueError("A and B must have the same dimension")
+        h = C.c_void_p()
+        _check(lib().mad_plan_create_dense(
+            _dev(A, torch.float32, "A"), m, _dev(B, torch.float32, "B"), n, d,
+            flags, _stream(stream), C.byref(h)))
+        return cls(h, (A, B), m, n, d)
+
+    def refresh(self, stream=None):
+        _check(lib().mad_plan_refresh(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().mad_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def topk_raw(self, t, s, t_prime, seed, out, n_out, stream=None):
+        """Enqueue mad_plan_topk into caller-owned out ((t,3) int64) and
+        n_out ((1,) int64) without synchronising."""
+        import torch
+        _check(lib().mad_plan_topk(self._h, t, s, t_prime, seed,
+                                   _dev(out, torch.int64, "out"),
+                                   _dev(n_out, torch.int64, "n_out"),
+                                   _stream(stream)))
+
+    def topk(self, t, s, t_prime, seed=0, stream=None):
+        import torch
+        out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
+        n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.topk_raw(t, s, t_prime, seed, out, n_out, stream)
+        torch.cuda.synchronize()
+        return unpack_pairs(out, int(n_out.item()))
+
+    def stats(self):
+        w = C.c_double()
+        cl, di, npos, nc = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().mad_plan_stats(self._h, C.byref(w), C.byref(cl),
+                                    C.byref(di), C.byref(npos), C.byref(nc)))
+        return dict(wnorm=w.value, closed=cl.value, distinct=di.value,
+                    n_pos=npos.value, n_cand=nc.value)
+
+    def fix_exponent(self, s):
+        F = C.c_int()
+        _check(lib().mad_fix_exponent(self._h, s, C.byref(F)))
+        return F.value
+
+    # ---- parity / debug ----------------------------------------------------
+    def table(self, which, idx=0):
+        import numpy as np
+        ns = C.c_int64()
+        _check(lib().mad_debug_table(self._h, which, idx, None, None, None, 0,
+                                     C.byref(ns)))
+        thr = np.zeros(ns.value, np.uint32)
+        al = np.zeros(ns.value, np.uint32)
+        item = np.zeros(ns.value, np.int32)
+        _check(lib().mad_debug_table(
+            self._h, which, idx, thr.ctypes.data_as(_P), al.ctypes.data_as(_P),
+            item.ctypes.data_as(_P), ns.value, C.byref(ns)))
+        return thr, al, item
+
+    def norms(self):
+        import numpy as np
+        na = np.zeros(self.m, np.float64)
+        nb = np.zeros(self.d, np.float64)
+        v = np.zeros(self.d, np.float64)
+        om = np.zeros(self.d, np.float64)
+        _check(lib().mad_debug_norms(self._h, na.ctypes.data_as(_P),
+                                     nb.ctypes.data_as(_P),
+                                     v.ctypes.data_as(_P),
+                                     om.ctypes.data_as(_P)))
+        return na, nb, v, om
+
+    def samples(self, seed, l0, count, F, qid=0, stream=None):
+        import torch
+        dev = "cuda"
+        k = torch.empty(count, dtype=torch.int32, device=dev)
+        i = torch.empty(count, dtype=torch.int32, device=dev)
+        j = torch.empty(count, dtype=torch.int32, device=dev)
+        kp = torch.empty(count, dtype=torch.int32, device=dev)
+        inc = torch.empty(count, dtype=torch.int64, device=dev)
+        _check(lib().mad_debug_samples(
+            self._h, seed, qid, l0, count, F, C.c_void_p(k.data_ptr()),
+            C.c_void_p(i.data_ptr()), C.c_void_p(j.data_ptr()),
+            C.c_void_p(kp.data_ptr()), C.c_void_p(inc.data_ptr()),
+            _stream(stream)))
+        return dict(k=k.cpu().numpy(), i=i.cpu().numpy(), j=j.cpu().numpy(),
+                    kp=kp.cpu().numpy(), inc=inc.cpu().numpy())
+
+    def scores(self):
+        """X of the last topk: (keys, x_fix) sorted by key, and F."""
+        import numpy as np
+        import torch
+        n = C.c_int64()
+        F = C.c_int()
+        _check(lib().mad_debug_scores(self._h, None, None, 0, C.byref(n),
+                                      C.byref(F)))
+        cap = max(n.value, 1)
+        keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+        x = torch.empty(cap, dtype=torch.int64, device="cuda")
+        _check(lib().mad_debug_scores(self._h, C.c_void_p(keys.data_ptr()),
+                                      C.c_void_p(x.data_ptr()), cap,
+                                      C.byref(n), C.byref(F)))
+        keys = keys[:n.value].cpu().numpy()
+        x = x[:n.value].cpu().numpy()
+        o = np.argsort(keys, kind="stable")
+        return keys[o], x[o], F.value
+
+    def candidates(self):
+        """Omega_t' of the last topk, sorted by key: keys, x_fix, c."""
+        import numpy as np
+        import torch
+        n = C.c_int64()
+        _check(lib().mad_debug_candidates(self._h, None, None, None, 0,
+                                          C.byref(n)))
+        cap = max(n.value, 1)
+        keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+        x = torch.empty(cap, dtype=torch.int64, device="cuda")
+        c = torch.empty(cap, dtype=torch.float32, device="cuda")
+        _check(lib().mad_debug_candidates(
+            self._h, C.c_void_p(keys.data_ptr()), C.c_void_p(x.data_ptr()),
+            C.c_void_p(c.data_ptr()), cap, C.byref(n)))
+        keys = keys[:n.value].cpu().numpy()
+        o = np.argsort(keys, kind="stable")
+        return keys[o], x[:n.value].cpu().numpy()[o], c[:n.value].cpu().numpy()[o]
+
+
+def topk(A, B, t, s, t_prime, seed=0, stream=None):
+    """One-shot mad_topk: returns dict(i, j, c, x) (synchronises)."""
+    import torch
+    m, d = A.shape
+    n = B.shape[0]
+    out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _check(lib().mad_topk(_dev(A, torch.float32, "A"), m,
+                          _dev(B, torch.float32, "B"), n, d, t, s, t_prime,
+                          seed, C.c_void_p(out.data_ptr()),
+                          C.c_void_p(n_out.data_ptr()), _stream(stream)))
+    return unpack_pairs(out, int(n_out.item()))

@@ -1,0 +1,121 @@
+// plan.hpp -- host-side plan and workspace structures of the library, and
+// the launchers each kernel file exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace mad {
+
+// One family of equally sized alias tables (dense inputs): S tables of N
+// items each, 2^L slots per table, entries at ent[s << L ...].
+struct Family {
+  int64_t S = 0;
+  int64_t N = 0;
+  int L = 0;
+  uint64_t* ent = nullptr;  // S << L packed entries (device)
+  double* tot = nullptr;    // S table totals (device)
+};
+
+// Sparse families: table s covers items [off[s], off[s+1]) of a position
+// array (item ids in pos_item) and slots [soff[s], soff[s] + 2^L[s]).
+struct RaggedFamily {
+  int64_t S = 0;
+  int64_t items = 0;         // off[S]
+  int64_t slots = 0;         // soff[S]
+  const int64_t* off = nullptr;  // S + 1 (device)
+  int64_t* soff = nullptr;   // S + 1 (device)
+  int8_t* L = nullptr;       // S (device)
+  int32_t* item = nullptr;   // position -> vector or coordinate id (device)
+  uint64_t* ent = nullptr;   // slots packed entries (device)
+  double* tot = nullptr;     // S totals (device)
+};
+
+struct DeviceBuffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+hipError_t dev_alloc(DeviceBuffer& b, size_t bytes);
+void dev_free(DeviceBuffer& b);
+
+// ---- tables.hip ----------------------------------------------------------
+// Dense preprocessing: na (m), nb (d), v (d), om (d); families T0 (S=1,
+// N=d), T1 (S=d, N=m), T2 (S=d, N=n), T3 (S=m, N=d); bmax = max |b|;
+// bad != 0 when A or B holds NaN/Inf (only if check).
+struct DenseTables {
+  int64_t m = 0, n = 0, d = 0;
+  Family T0, T1, T2, T3;
+  double* na = nullptr;  // == T3.tot
+  double* nb = nullptr;  // == T2.tot
+  double* v = nullptr;   // == T1.tot
+  double* om = nullptr;  // d
+  float* bmax = nullptr; // 1
+  int* bad = nullptr;    // 1
+};
+
+hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,
+                              int64_t d);
+void dense_tables_free(DenseTables& t);
+hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
+                              bool check, DeviceBuffer& scratch,
+                              hipStream_t st);
+
+// generic launchers reused by other files
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
+
+// ---- sampler.hip ---------------------------------------------------------
+struct HashTable {
+  uint64_t* keys = nullptr;
+  int64_t* vals = nullptr;
+  int64_t cap = 0;  // power of two
+};
+
+struct SampleCounters {
+  unsigned long long closed;
+  unsigned long long pad[7];
+};
+
+hipError_t launch_sample_dense(const DenseTables& t, const float* B,
+                               uint64_t seed, uint64_t qid, int64_t l0,
+                               int64_t count, int64_t s_for_F,
+                               HashTable h, SampleCounters* ctr,
+                               hipStream_t st);
+hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
+                                     uint64_t seed, uint64_t qid, int64_t l0,
+                                     int64_t count, int F, int32_t* k,
+                                     int32_t* i, int32_t* j, int32_t* kp,
+                                     int64_t* inc, hipStream_t st);
+
+// ---- select.hip ----------------------------------------------------------
+struct SelectWork {
+  uint64_t* x = nullptr;     // candidate primary keys
+  uint64_t* key = nullptr;   // candidate secondary keys
+  uint64_t* x2 = nullptr;    // selected primary
+  uint64_t* key2 = nullptr;  // selected secondary
+  float* c = nullptr;        // verified dot products
+  int64_t cap = 0;           // capacity of x / key
+  int64_t cap2 = 0;          // capacity of x2 / key2 / c
+  void* state = nullptr;     // device select state
+  unsigned int* hist = nullptr;
+  int64_t* counts = nullptr; // device counters
+};
+
+// SelectWork::counts slots
+enum { kCountPos = 0, kCountDistinct = 1, kCountCand = 2, kCountFinal = 3 };
+constexpr size_t kSelStateBytes = 256;
+constexpr int kSelBins = 2048;
+
+hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,
+                              int64_t* xfix, int64_t out_cap, int64_t* count,
+                              hipStream_t st);
+
+hipError_t launch_postprocess(const HashTable& h, const float* A,
+                              const float* B, int64_t n, int64_t d,
+                              int64_t t_prime, int64_t t, const float* bmax,
+                              int64_t s, SelectWork& w, void* out,
+                              int64_t* n_out, hipStream_t st);
+
+}  // namespace mad

@@ -1,0 +1,214 @@
+// sampler.hip -- the sampling loop of Alg. 2 (lines "ds1".."dx") for dense
+// inputs, and score accumulation into an open-addressing hash table X.
+//
+// Sample l uses the Philox4x64-10 block with counter (l, qid, 0, 0) and key
+// (seed, 0): word 0 draws k from T0, word 1 draws i from T1[k], word 2 draws
+// j from T2[k], word 3 draws k' from T3[i] (the two-stage form of line
+// "ds1": k with weight ||B_k*||_1 v_k, then i with weight |a_ki| ||a_i||_1).
+// The alias entries carry the sign bits of a_ki, b_kj and a_k'i, so the only
+// value read from the inputs is the fourth edge b_k'j.  A closed three-path
+// (b_k'j != 0) adds sgn(a_ki b_kj a_k'i) * rne(b_k'j * 2^F) to the int64
+// score of key i*n + j; integer sums make X independent of the order in
+// which threads reach the table.
+#include "mad_common.hpp"
+#include "plan.hpp"
+
+namespace mad {
+
+constexpr int kT0Lds = 4096;  // stage-0 table kept in LDS up to this size
+
+struct DenseSampleArgs {
+  const uint64_t* T0;
+  const uint64_t* T1;
+  const uint64_t* T2;
+  const uint64_t* T3;
+  int L0, L1, L2, L3;
+  const float* B;
+  int64_t d, n;
+  uint64_t seed, qid;
+  int64_t l0, count;
+};
+
+struct OneSample {
+  uint32_t k, i, j, kp;
+  int64_t inc;
+  bool closed;
+};
+
+// hash insert: linear probing on mix64(key); keys go EMPTY -> key once
+__device__ __forceinline__ void hash_add(uint64_t* keys, int64_t* vals,
+                                         uint64_t mask, uint64_t key,
+                                         int64_t inc) {
+  uint64_t h = mix64(key) & mask;
+  while (true) {
+    uint64_t cur = __hip_atomic_load(keys + h, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kEmptyKey) {
+      cur = atomicCAS((unsigned long long*)(keys + h),
+                      (unsigned long long)kEmptyKey,
+                      (unsigned long long)key);
+      if (cur == kEmptyKey) cur = key;
+    }
+    if (cur == key) {
+      if (inc != 0)
+        atomicAdd((unsigned long long*)(vals + h), (unsigned long long)inc);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+template <int U, bool DEBUG>
+__global__ __launch_bounds__(256) void k_sample_dense(
+    DenseSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
+    int F_debug,
+    uint64_t* hkeys, int64_t* hvals, uint64_t hmask,
+    unsigned long long* closed_ctr, int32_t* ok, int32_t* oi, int32_t* oj,
+    int32_t* okp, int64_t* oinc) {
+  __shared__ uint64_t t0s[kT0Lds];
+  if (!(wtot[0] > 0.0)) return;  // ||W||_1 = 0: nothing can be sampled
+  const int N0 = 1 << a.L0;
+  const bool t0_lds = N0 <= kT0Lds;
+  if (t0_lds)
+    for (int e = threadIdx.x; e < N0; e += blockDim.x) t0s[e] = a.T0[e];
+  __syncthreads();
+  const uint64_t* T0 = t0_lds ? t0s : a.T0;
+  const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
+
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long nclosed = 0;
+  for (int64_t base = tid; base < a.count; base += nthreads * U) {
+    OneSample smp[U];
+    uint64_t U1[U], U2[U], U3[U];
+    // ds1 (stage 0): k from the LDS copy of T0
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)u * nthreads;
+      const uint64_t l = (uint64_t)(a.l0 + (e < a.count ? e : 0));
+      const Philox4 r = philox4x64_10(l, a.qid, 0ull, 0ull, a.seed, 0ull);
+      const uint32_t s0 = slot_of(r.w0, a.L0);
+      smp[u].k = draw_entry(T0[s0], s0, r.w0).pos;
+      U1[u] = r.w1;
+      U2[u] = r.w2;
+      U3[u] = r.w3;
+    }
+    // ds1 (stage 1) and ds2: i from T1[k], j from T2[k]
+    uint64_t e1[U], e2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      e1[u] = a.T1[((uint64_t)smp[u].k << a.L1) + slot_of(U1[u], a.L1)];
+      e2[u] = a.T2[((uint64_t)smp[u].k << a.L2) + slot_of(U2[u], a.L2)];
+    }
+    uint32_t sgn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const Drawn di = draw_entry(e1[u], slot_of(U1[u], a.L1), U1[u]);
+      const Drawn dj = draw_entry(e2[u], slot_of(U2[u], a.L2), U2[u]);
+      smp[u].i = di.pos;
+      smp[u].j = dj.pos;
+      sgn[u] = di.sgn ^ dj.sgn;
+    }
+    // ds3: k' from T3[i]
+    uint64_t e3[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      e3[u] = a.T3[((uint64_t)smp[u].i << a.L3) + slot_of(U3[u], a.L3)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const Drawn dk = draw_entry(e3[u], slot_of(U3[u], a.L3), U3[u]);
+      smp[u].kp = dk.pos;
+      sgn[u] ^= dk.sgn;
+    }
+    // dx: the fourth edge b_k'j and the increment
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = a.B[(int64_t)smp[u].j * a.d + smp[u].kp];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)u * nthreads;
+      const bool live = e < a.count;
+      smp[u].closed = live && v[u] != 0.0f;
+      int64_t inc = 0;
+      if (smp[u].closed) {
+        const int64_t mag = (int64_t)rint(ldexp((double)v[u], F));
+        inc = sgn[u] ? -mag : mag;
+      }
+      smp[u].inc = inc;
+      if (DEBUG) {
+        if (live) {
+          ok[e] = (int32_t)smp[u].k;
+          oi[e] = (int32_t)smp[u].i;
+          oj[e] = (int32_t)smp[u].j;
+          okp[e] = (int32_t)smp[u].kp;
+          oinc[e] = inc;
+        }
+      } else if (smp[u].closed) {
+        ++nclosed;
+        hash_add(hkeys, hvals, hmask,
+                 (uint64_t)smp[u].i * (uint64_t)a.n + smp[u].j, inc);
+      }
+    }
+  }
+  if (!DEBUG) {
+    nclosed = wave_sum(nclosed);
+    if ((threadIdx.x & 63) == 0 && nclosed) atomicAdd(closed_ctr, nclosed);
+  }
+}
+
+static DenseSampleArgs dense_args(const DenseTables& t, const float* B,
+                                  uint64_t seed, uint64_t qid, int64_t l0,
+                                  int64_t count) {
+  DenseSampleArgs a;
+  a.T0 = t.T0.ent;
+  a.T1 = t.T1.ent;
+  a.T2 = t.T2.ent;
+  a.T3 = t.T3.ent;
+  a.L0 = t.T0.L;
+  a.L1 = t.T1.L;
+  a.L2 = t.T2.L;
+  a.L3 = t.T3.L;
+  a.B = B;
+  a.d = t.d;
+  a.n = t.n;
+  a.seed = seed;
+  a.qid = qid;
+  a.l0 = l0;
+  a.count = count;
+  return a;
+}
+
+static unsigned sample_grid(int64_t count, int per_thread) {
+  int64_t blocks = (count + 256LL * per_thread - 1) / (256LL * per_thread);
+  if (blocks > 8192) blocks = 8192;
+  return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+constexpr int kUnroll = 2;
+
+hipError_t launch_sample_dense(const DenseTables& t, const float* B,
+                               uint64_t seed, uint64_t qid, int64_t l0,
+                               int64_t count, int64_t s_for_F, HashTable h,
+                               SampleCounters* ctr, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
+  k_sample_dense<kUnroll, false><<<sample_grid(count, kUnroll), 256, 0, st>>>(
+      a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, (uint64_t)h.cap - 1,
+      &ctr->closed, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
+                                     uint64_t seed, uint64_t qid, int64_t l0,
+                                     int64_t count, int F, int32_t* k,
+                                     int32_t* i, int32_t* j, int32_t* kp,
+                                     int64_t* inc, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
+  k_sample_dense<kUnroll, true><<<sample_grid(count, kUnroll), 256, 0, st>>>(
+      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp, inc);
+  return hipGetLastError();
+}
+
+}  // namespace mad

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded
+inputs, through the C ABI.
+
+Bar: integer and index results (tables, per-sample streams, scores X, the
+candidate set Omega_t') are bit-exact; fp32 dot products match the oracle's
+FP64 values within 1e-5 of sum_k |a_ik b_jk| (the fp32 dot-product error
+scale); the final top-t equals the oracle's except for swaps
+among pairs whose |c| differ by less than that tolerance."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mad_gpu(gpu):
+    import paper_1506_03872_amd as mad
+    mad.lib()  # fails loudly when the library is missing
+    return mad
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def make_plans(mad, A, B):
+    say("plans m=%d n=%d d=%d" % (A.shape[0], B.shape[0], A.shape[1]))
+    gp = mad.Plan.dense(to_dev(A), to_dev(B))
+    op = oracle.Plan.dense(A, B)
+    return gp, op
+
+
+CASES = {
+    # name: (generator, kwargs)
+    "c1": lambda: workloads.make("C1")[1].values(),
+    "ragged": lambda: workloads.dense_gaussian(3001, 2049, 37, seed=3),
+    "wide_d": lambda: workloads.dense_gaussian(300, 500, 600, seed=4),
+    "zeros": lambda: _with_zeros(),
+    "binary": lambda: workloads.binary(700, 900, 48, density=0.3, seed=5),
+    "tiny": lambda: workloads.tiny(3, 2, 1, seed=6),
+}
+
+
+def _with_zeros():
+    A, B = workloads.tiny(1200, 1100, 20, seed=7)
+    A[A < -1.0] = 0.0
+    B[B > 1.2] = 0.0
+    A[5] = 0.0
+    B[:, 3] = 0.0
+    return A, B
+
+
+def _inputs(name):
+    A, B = list(CASES[name]())[:2]
+    return np.ascontiguousarray(A, np.float32), np.ascontiguousarray(B, np.float32)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_norms_and_tables_bitexact(mad_gpu, name):
+    A, B = _inputs(name)
+    gp, op = make_plans(mad_gpu, A, B)
+    gna, gnb, gv, gom = gp.norms()
+    ona, onb, ov, oom = op.norms()
+    assert np.array_equal(gna, ona)
+    assert np.array_equal(gnb, onb)
+    assert np.array_equal(gv, ov)
+    assert np.array_equal(gom, oom)
+    m, d = A.shape
+    checks = [(0, 0)]
+    for k in sorted({0, 1, d // 2, d - 1} & set(range(d))):
+        checks += [(1, k), (2, k)]
+    for i in sorted({0, 1, m // 2, m - 1} & set(range(m))):
+        checks.append((3, i))
+    for which, idx in checks:
+        gthr, gal, _ = gp.table(which, idx)
+        othr, oal, _, _, live, _ = op.table(which, idx)
+        assert np.array_equal(gthr, othr), (which, idx)
+        assert np.array_equal(gal, oal), (which, idx)
+    gp.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sample_stream_bitexact(mad_gpu, name):
+    A, B = _inputs(name)
+    gp, op = make_plans(mad_gpu, A, B)
+    s = 100_000
+    F = op.fix_exponent(s)
+    assert gp.fix_exponent(s) == F
+    for l0, cnt in ((0, 5000), (s // 2 - 777, 4000), (s - 3000, 3000),
+                    ((1 << 40) - 50, 100)):
+        g = gp.samples(seed=123, l0=l0, count=cnt, F=F)
+        o = op.samples(123, l0, cnt, F)
+        for key in ("k", "i", "j", "kp", "inc"):
+            assert np.array_equal(g[key], o[key]), (key, l0)
+    # a query word other than 0 changes the stream and still agrees
+    g = gp.samples(seed=9, l0=10, count=2000, F=F, qid=77)
+    o = op.samples(9, 10, 2000, F, qid=77)
+    assert np.array_equal(g["i"], o["i"]) and np.array_equal(g["inc"], o["inc"])
+    gp.close()
+
+
+def _c_scale(A, B, keys):
+    n = B.shape[0]
+    a = np.abs(A[keys // n].astype(np.float64))
+    b = np.abs(B[keys % n].astype(np.float64))
+    return (a * b).sum(axis=1)
+
+
+def _check_topk(A, B, gres, ores, t):
+    n = B.shape[0]
+    gkey = gres["i"].cpu().numpy() * n + gres["j"].cpu().numpy()
+    gc = gres["c"].cpu().numpy().astype(np.float64)
+    assert len(gkey) == len(ores["key"])
+    # every returned c within tolerance of its FP64 value
+    c64 = (A[gkey // n].astype(np.float64) * B[gkey % n].astype(np.float64)).sum(1)
+    assert np.all(np.abs(gc - c64) <= TOL * _c_scale(A, B, gkey) + 1e-30)
+    if np.array_equal(gkey, ores["key"]):
+        return
+    # otherwise: same set up to pairs within tolerance of the boundary
+    ok = dict(zip(ores["key"].tolist(), ores["c"].tolist()))
+    tau = np.abs(ores["c"]).min() if len(ores["c"]) else 0.0
+    for kk, c in zip(gkey.tolist(), c64.tolist()):
+        if kk not in ok:
+            scale = _c_scale(A, B, np.array([kk]))[0]
+            assert abs(abs(c) - tau) <= 2 * TOL * scale, kk
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_topk_scores_candidates_bitexact(mad_gpu, name):
+    A, B = _inputs(name)
+    gp, op = make_plans(mad_gpu, A, B)
+    m, n = A.shape[0], B.shape[0]
+    for s, tp, t in ((100_000, 100, 10), (20_000, 5000, 50),
+                     (3000, 10**9, 3), (0, 10, 5)):
+        t = min(t, m * n)
+        say("topk", name, s, tp, t)
+        g = gp.topk(t=t, s=s, t_prime=tp, seed=42)
+        o = op.topk(seed=42, s=s, t_prime=tp, t=t)
+        st = gp.stats()
+        assert st["n_pos"] == o["n_pos"]
+        assert st["closed"] == o["closed"]
+        if s:
+            gk, gx, F = gp.scores()
+            ok, ox, _ = op.scores(seed=42, s=s, F=o["F"])
+            assert F == o["F"]
+            assert np.array_equal(gk, ok) and np.array_equal(gx, ox)
+            assert st["distinct"] == len(ok)
+        # Omega_t' as a set, with its scores
+        ck, cx, cc = gp.candidates()
+        order = np.argsort(o["tp_key"])
+        assert np.array_equal(ck, o["tp_key"][order])
+        assert np.array_equal(cx, o["tp_x"][order])
+        if len(ck):
+            err = np.abs(cc.astype(np.float64) - o["tp_c"][order])
+            assert np.all(err <= TOL * _c_scale(A, B, ck) + 1e-30)
+        _check_topk(A, B, g, o, t)
+        if len(o["key"]):
+            gx = g["x"].cpu().numpy().astype(np.float64)
+            n_ = B.shape[0]
+            gkey = g["i"].cpu().numpy() * n_ + g["j"].cpu().numpy()
+            xo = dict(zip(o["tp_key"].tolist(), (o["tp_x"] * 2.0 ** -o["F"]).tolist()))
+            for kk, xv in zip(gkey.tolist(), gx.tolist()):
+                assert abs(xv - xo[kk]) <= 1e-6 * abs(xo[kk])
+    gp.close()
+
+
+def test_empty_support_returns_nothing(mad_gpu):
+    A = np.zeros((50, 8), np.float32)
+    B = np.ones((40, 8), np.float32)
+    gp, op = make_plans(mad_gpu, A, B)
+    g = gp.topk(t=5, s=1000, t_prime=20, seed=1)
+    assert len(g["i"]) == 0
+    assert gp.stats()["wnorm"] == 0.0
+    gp.close()
+
+
+def test_invalid_arguments_on_device(mad_gpu):
+    import torch
+    mad = mad_gpu
+    A = torch.randn(10, 4, device="cuda")
+    B = torch.randn(12, 4, device="cuda")
+    with pytest.raises(ValueError):
+        mad.Plan.dense(A, torch.randn(12, 5, device="cuda"))
+    Abad = A.clone()
+    Abad[3, 1] = float("nan")
+    with pytest.raises(mad.MadError) as ei:
+        mad.Plan.dense(Abad, B)
+    assert ei.value.code == mad.MAD_EINVAL
+    p = mad.Plan.dense(A, B)
+    with pytest.raises(mad.MadError):
+        p.topk(t=5, s=100, t_prime=4)        # t' < t
+    with pytest.raises(mad.MadError):
+        p.topk(t=121, s=100, t_prime=200)    # t > m n
+    p.close()
+    # a host pointer is rejected by the library itself
+    import ctypes as C
+    host = np.zeros((10, 4), np.float32)
+    h = C.c_void_p()
+    rc = mad.lib().mad_plan_create_dense(host.ctypes.data_as(C.c_void_p), 10,
+                                         C.c_void_p(B.data_ptr()), 12, 4, 0,
+                                         None, C.byref(h))
+    assert rc == mad.MAD_EINVAL
+
+
+def test_refresh_after_inputs_change(mad_gpu):
+    import torch
+    mad = mad_gpu
+    A, B = workloads.dense_gaussian(500, 400, 16, seed=11)
+    Ad, Bd = to_dev(A), to_dev(B)
+    gp = mad.Plan.dense(Ad, Bd)
+    A2, B2 = workloads.dense_gaussian(500, 400, 16, seed=12)
+    Ad.copy_(torch.from_numpy(A2))
+    Bd.copy_(torch.from_numpy(B2))
+    gp.refresh()
+    op = oracle.Plan.dense(A2, B2)
+    g = gp.topk(t=10, s=50_000, t_prime=200, seed=3)
+    o = op.topk(seed=3, s=50_000, t_prime=200, t=10)
+    _check_topk(A2, B2, g, o, 10)
+    gp.close()
+
+
+def test_one_shot_entry_point(mad_gpu):
+    A, B = workloads.dense_gaussian(800, 700, 24, seed=13)
+    g = mad_gpu.topk(to_dev(A), to_dev(B), t=20, s=60_000, t_prime=400, seed=5)
+    o = oracle.Plan.dense(A, B).topk(seed=5, s=60_000, t_prime=400, t=20)
+    _check_topk(A, B, g, o, 20)
