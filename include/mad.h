@@ -57,7 +57,8 @@ enum { MAD_FP32 = 0, MAD_BF16 = 1, MAD_FP8_E4M3 = 2 };
 /* Plan flags. */
 enum {
   MAD_FLAG_NONE = 0,
-  MAD_FLAG_NO_CHECK = 1u << 0  /* skip the NaN/Inf scan of the inputs */
+  MAD_FLAG_NO_CHECK = 1u << 0, /* skip the NaN/Inf scan of the inputs      */
+  MAD_FLAG_TIMING = 1u << 1    /* record HIP events around each phase      */
 };
 
 typedef struct mad_plan mad_plan;
@@ -141,6 +142,34 @@ void mad_plan_destroy(mad_plan* plan);
  * ------------------------------------------------------------------------- */
 int mad_plan_stats(mad_plan* plan, double* wnorm, int64_t* closed,
                    int64_t* distinct, int64_t* n_pos, int64_t* n_cand);
+
+/* ---------------------------------------------------------------------------
+ * Phase durations (milliseconds, host array `ms` of capacity n) of the last
+ * mad_plan_refresh / mad_plan_topk of a plan made with MAD_FLAG_TIMING,
+ * measured with HIP events recorded on the launch stream:
+ *   ms[0] table construction (mad_plan_refresh or creation)
+ *   ms[1] sampling kernel (Alg. 2 loop, including the score table updates)
+ *   ms[2] postprocessing (Alg. 3: selections, verification, output)
+ *   ms[3] clearing the score table before sampling
+ * Synchronises on the last event.  MAD_EINVAL without MAD_FLAG_TIMING.
+ * ------------------------------------------------------------------------- */
+int mad_plan_phase_ms(mad_plan* plan, double* ms, int n);
+
+/* ---------------------------------------------------------------------------
+ * mad_probe_memory -- measurement kernels for the memory ceilings the
+ * sampler works against (used by the benchmark's roofline).  buf (device)
+ * holds nwords 64-bit words, nwords a power of two; nops operations at
+ * addresses mix64(op index ^ seed) mod nwords:
+ *   kind 0 random 8-byte loads        kind 1 random 4-byte loads
+ *   kind 2 random 64-bit atomic adds  kind 3 random 64-bit compare-and-swaps
+ *   kind 4 compare-and-swap on an aligned word pair followed by an add to
+ *          its second word (one insert of a new key into the score table)
+ *   kind 5 streaming copy of words [0, nops) to [nwords/2, nwords/2 + nops)
+ *          (nops <= nwords/2)
+ * Kinds 2-5 modify buf.  Enqueued on `stream`; MAD_EINVAL on bad arguments.
+ * ------------------------------------------------------------------------- */
+int mad_probe_memory(int kind, void* buf, int64_t nwords, int64_t nops,
+                     uint64_t seed, void* stream);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* mad_last_error(void);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmad.so")
 MAD_OK, MAD_EINVAL, MAD_ENOMEM, MAD_EHIP, MAD_EOVERFLOW, MAD_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 MAD_FP32, MAD_BF16, MAD_FP8_E4M3 = 0, 1, 2
-MAD_FLAG_NONE, MAD_FLAG_NO_CHECK = 0, 1
+MAD_FLAG_NONE, MAD_FLAG_NO_CHECK, MAD_FLAG_TIMING = 0, 1, 2
 
 # every symbol include/mad.h declares
 EXPORTS = (
@@ -26,7 +26,7 @@ EXPORTS = (
     "mad_plan_topk", "mad_topk", "mad_plan_destroy", "mad_plan_stats",
     "mad_last_error", "mad_debug_table", "mad_debug_norms",
     "mad_debug_samples", "mad_debug_scores", "mad_debug_candidates",
-    "mad_fix_exponent",
+    "mad_fix_exponent", "mad_plan_phase_ms", "mad_probe_memory",
 )
 
 
@@ -68,6 +68,8 @@ def lib():
         L.mad_debug_scores.argtypes = [_P, _P, _P, _i64, _P, _P]
         L.mad_debug_candidates.argtypes = [_P, _P, _P, _P, _i64, _P]
         L.mad_fix_exponent.argtypes = [_P, _i64, _P]
+        L.mad_plan_phase_ms.argtypes = [_P, _P, C.c_int]
+        L.mad_probe_memory.argtypes = [C.c_int, _P, _i64, _i64, _u64, _P]
         _lib = L
     return _lib
 
@@ -167,6 +169,13 @@ class Plan:
         return dict(wnorm=w.value, closed=cl.value, distinct=di.value,
                     n_pos=npos.value, n_cand=nc.value)
 
+    def phase_ms(self):
+        """[tables, sampler, postprocess, clear] ms of the last calls (needs
+        MAD_FLAG_TIMING)."""
+        arr = (C.c_double * 4)()
+        _check(lib().mad_plan_phase_ms(self._h, arr, 4))
+        return list(arr)
+
     def fix_exponent(self, s):
         F = C.c_int()
         _check(lib().mad_fix_exponent(self._h, s, C.byref(F)))
@@ -250,6 +259,14 @@ class Plan:
         keys = keys[:n.value].cpu().numpy()
         o = np.argsort(keys, kind="stable")
         return keys[o], x[:n.value].cpu().numpy()[o], c[:n.value].cpu().numpy()[o]
+
+
+def probe_memory(kind, buf, nops, seed=0, stream=None):
+    """Enqueue one mad_probe_memory run over buf (a CUDA int64 tensor whose
+    length is a power of two)."""
+    import torch
+    _check(lib().mad_probe_memory(kind, _dev(buf, torch.int64, "buf"),
+                                  buf.numel(), nops, seed, _stream(stream)))
 
 
 def topk(A, B, t, s, t_prime, seed=0, stream=None):

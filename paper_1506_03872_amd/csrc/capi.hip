@@ -72,7 +72,15 @@ struct mad_plan {
   // last run
   int64_t last_s = -1;
   bool ran = false;
+  // phase events (MAD_FLAG_TIMING): 0 tables start, 1 tables end, 2 clear
+  // start, 3 sampler start, 4 sampler end, 5 postprocessing end
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timed_tables = false, timed_topk = false;
 };
+
+static void record(mad_plan* p, int idx, hipStream_t st) {
+  if (p->ev[idx]) (void)hipEventRecord(p->ev[idx], st);
+}
 
 static void plan_free_all(mad_plan* p) {
   mad::dense_tables_free(p->dt);
@@ -85,6 +93,11 @@ static void plan_free_all(mad_plan* p) {
   mad::dev_free(p->ck2);
   mad::dev_free(p->cc);
   mad::dev_free(p->misc);
+  for (hipEvent_t& e : p->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
 }
 
 static int check_bad_inputs(mad_plan* p, hipStream_t st) {
@@ -125,6 +138,9 @@ int mad_plan_create_dense(const float* A, int64_t m, const float* B,
   p->d = d;
   p->flags = flags;
   hipError_t e = mad::dense_tables_alloc(p->dt, m, n, d);
+  if (e == hipSuccess && (flags & MAD_FLAG_TIMING))
+    for (hipEvent_t& ev : p->ev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) break;
   if (e != hipSuccess) {
     plan_free_all(p);
     delete p;
@@ -147,8 +163,11 @@ int mad_plan_refresh(mad_plan* p, void* stream) {
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
   hipStream_t st = (hipStream_t)stream;
   const bool check = !(p->flags & MAD_FLAG_NO_CHECK);
+  record(p, 0, st);
   HIP_TRY(mad::dense_tables_build(p->dt, p->A, p->B, check, p->build, st),
           "building tables");
+  record(p, 1, st);
+  p->timed_tables = p->ev[0] != nullptr;
   p->ran = false;
   return check_bad_inputs(p, st);
 }
@@ -168,9 +187,10 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   const double mn = (double)p->m * (double)p->n;
   const int64_t pairs = (double)s2 < mn ? s2 : (int64_t)mn;
   int64_t hcap = next_pow2(2 * (pairs > 512 ? pairs : 512));
+  // candidates / boundary lists: post1 needs |Omega_s| <= pairs entries,
+  // post3 needs 4 t (final set) + 4 t' (boundary of the candidates)
   int64_t ccap = pairs > 1 ? pairs : 1;
-  if (ccap < 3 * t2) ccap = 3 * t2;
-  if (ccap < tp2) ccap = tp2;
+  if (ccap < 4 * t2 + 4 * tp2) ccap = 4 * t2 + 4 * tp2;
   const int64_t ccap2 = tp2 > 1 ? tp2 : 1;
   (void)hipDeviceSynchronize();
   hipError_t e;
@@ -229,18 +249,23 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   if (tp_eff < t) tp_eff = t;
   int rc = ensure_workspace(p, s, tp_eff, t);
   if (rc != MAD_OK) return rc;
+  record(p, 2, st);
   HIP_TRY(mad::launch_fill_u64(p->h.keys, p->h.cap, mad::kEmptyKey, st),
           "clearing X");
   HIP_TRY(mad::launch_fill_u64((uint64_t*)p->h.vals, p->h.cap, 0ull, st),
           "clearing X");
   HIP_TRY(mad::launch_fill_u64((uint64_t*)p->ctr, 8, 0ull, st),
           "clearing counters");
+  record(p, 3, st);
   HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, p->h,
                                    p->ctr, st),
           "sampling");
+  record(p, 4, st);
   HIP_TRY(mad::launch_postprocess(p->h, p->A, p->B, p->n, p->d, tp_eff, t,
                                   p->dt.bmax, s, p->w, out, n_out, st),
           "postprocessing");
+  record(p, 5, st);
+  p->timed_topk = p->ev[0] != nullptr;
   p->last_s = s;
   p->ran = true;
   return MAD_OK;
@@ -271,17 +296,37 @@ int mad_plan_stats(mad_plan* p, double* wnorm, int64_t* closed,
     HIP_TRY(hipMemcpy(wnorm, p->dt.T0.tot, sizeof(double),
                       hipMemcpyDeviceToHost), "stats");
   int64_t cnt[4] = {0, 0, 0, 0};
-  unsigned long long cl = 0;
+  mad::SampleCounters sc;
+  memset(&sc, 0, sizeof sc);
   if (p->ran) {
     HIP_TRY(hipMemcpy(cnt, p->w.counts, sizeof cnt, hipMemcpyDeviceToHost),
             "stats");
-    HIP_TRY(hipMemcpy(&cl, &p->ctr->closed, sizeof cl, hipMemcpyDeviceToHost),
+    HIP_TRY(hipMemcpy(&sc, p->ctr, sizeof sc, hipMemcpyDeviceToHost),
             "stats");
   }
-  if (closed) *closed = (int64_t)cl;
-  if (distinct) *distinct = cnt[mad::kCountDistinct];
+  if (closed) *closed = (int64_t)sc.closed;
+  if (distinct) *distinct = (int64_t)sc.distinct;
   if (n_pos) *n_pos = cnt[mad::kCountPos];
   if (n_cand) *n_cand = cnt[mad::kCountCand];
+  return MAD_OK;
+}
+
+int mad_plan_phase_ms(mad_plan* p, double* ms, int n) {
+  if (!p || !ms) return fail(MAD_EINVAL, "plan and ms are required");
+  if (!p->ev[0]) return fail(MAD_EINVAL, "plan was made without MAD_FLAG_TIMING");
+  const int pairs[4][2] = {{0, 1}, {3, 4}, {4, 5}, {2, 3}};
+  const bool have[4] = {p->timed_tables, p->timed_topk, p->timed_topk,
+                        p->timed_topk};
+  const hipEvent_t last = p->timed_topk ? p->ev[5] : p->ev[1];
+  HIP_TRY(hipEventSynchronize(last), "phase timing");
+  for (int q = 0; q < n && q < 4; ++q) {
+    ms[q] = -1.0;
+    if (!have[q]) continue;
+    float f = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&f, p->ev[pairs[q][0]], p->ev[pairs[q][1]]),
+            "phase timing");
+    ms[q] = f;
+  }
   return MAD_OK;
 }
 

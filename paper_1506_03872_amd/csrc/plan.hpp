@@ -74,8 +74,9 @@ struct HashTable {
 };
 
 struct SampleCounters {
-  unsigned long long closed;
-  unsigned long long pad[7];
+  unsigned long long closed;    // closed three-paths (diamonds)
+  unsigned long long distinct;  // keys inserted into X
+  unsigned long long pad[6];
 };
 
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,

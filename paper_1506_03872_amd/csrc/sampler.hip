@@ -35,24 +35,21 @@ struct OneSample {
   bool closed;
 };
 
-// hash insert: linear probing on mix64(key); keys go EMPTY -> key once
-__device__ __forceinline__ void hash_add(uint64_t* keys, int64_t* vals,
-                                         uint64_t mask, uint64_t key,
-                                         int64_t inc) {
+// hash insert: linear probing on mix64(key); a slot's key goes from EMPTY
+// to its final value once, so a compare-and-swap that finds EMPTY or the
+// key itself owns the slot.  Returns 1 when this call created the key.
+__device__ __forceinline__ int hash_add(uint64_t* keys, int64_t* vals,
+                                        uint64_t mask, uint64_t key,
+                                        int64_t inc) {
   uint64_t h = mix64(key) & mask;
   while (true) {
-    uint64_t cur = __hip_atomic_load(keys + h, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == kEmptyKey) {
-      cur = atomicCAS((unsigned long long*)(keys + h),
-                      (unsigned long long)kEmptyKey,
-                      (unsigned long long)key);
-      if (cur == kEmptyKey) cur = key;
-    }
-    if (cur == key) {
+    const uint64_t prev = atomicCAS((unsigned long long*)(keys + h),
+                                    (unsigned long long)kEmptyKey,
+                                    (unsigned long long)key);
+    if (prev == kEmptyKey || prev == key) {
       if (inc != 0)
         atomicAdd((unsigned long long*)(vals + h), (unsigned long long)inc);
-      return;
+      return prev == kEmptyKey;
     }
     h = (h + 1) & mask;
   }
@@ -63,9 +60,9 @@ __global__ __launch_bounds__(256) void k_sample_dense(
     DenseSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
     int F_debug,
     uint64_t* hkeys, int64_t* hvals, uint64_t hmask,
-    unsigned long long* closed_ctr, int32_t* ok, int32_t* oi, int32_t* oj,
+    SampleCounters* ctr, int32_t* ok, int32_t* oi, int32_t* oj,
     int32_t* okp, int64_t* oinc) {
-  __shared__ uint64_t t0s[kT0Lds];
+  extern __shared__ uint64_t t0s[];  // T0 when it fits (kT0Lds entries)
   if (!(wtot[0] > 0.0)) return;  // ||W||_1 = 0: nothing can be sampled
   const int N0 = 1 << a.L0;
   const bool t0_lds = N0 <= kT0Lds;
@@ -77,7 +74,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
 
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long nclosed = 0;
+  unsigned long long nclosed = 0, ncreated = 0;
   for (int64_t base = tid; base < a.count; base += nthreads * U) {
     OneSample smp[U];
     uint64_t U1[U], U2[U], U3[U];
@@ -146,14 +143,30 @@ __global__ __launch_bounds__(256) void k_sample_dense(
         }
       } else if (smp[u].closed) {
         ++nclosed;
-        hash_add(hkeys, hvals, hmask,
-                 (uint64_t)smp[u].i * (uint64_t)a.n + smp[u].j, inc);
+        ncreated += hash_add(hkeys, hvals, hmask,
+                             (uint64_t)smp[u].i * (uint64_t)a.n + smp[u].j,
+                             inc);
       }
     }
   }
   if (!DEBUG) {
+    // one pair of counter atomics per block
+    __shared__ unsigned long long part[2][4];
     nclosed = wave_sum(nclosed);
-    if ((threadIdx.x & 63) == 0 && nclosed) atomicAdd(closed_ctr, nclosed);
+    ncreated = wave_sum(ncreated);
+    if ((threadIdx.x & 63) == 0) {
+      part[0][threadIdx.x >> 6] = nclosed;
+      part[1][threadIdx.x >> 6] = ncreated;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long c = part[0][0] + part[0][1] + part[0][2] +
+                                   part[0][3];
+      const unsigned long long dd = part[1][0] + part[1][1] + part[1][2] +
+                                    part[1][3];
+      if (c) atomicAdd(&ctr->closed, c);
+      if (dd) atomicAdd(&ctr->distinct, dd);
+    }
   }
 }
 
@@ -187,15 +200,21 @@ static unsigned sample_grid(int64_t count, int per_thread) {
 
 constexpr int kUnroll = 2;
 
+static size_t t0_lds_bytes(const DenseTables& t) {
+  const int64_t N0 = int64_t(1) << t.T0.L;
+  return N0 <= kT0Lds ? (size_t)N0 * 8 : 0;
+}
+
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F, HashTable h,
                                SampleCounters* ctr, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
-  k_sample_dense<kUnroll, false><<<sample_grid(count, kUnroll), 256, 0, st>>>(
+  k_sample_dense<kUnroll, false>
+      <<<sample_grid(count, kUnroll), 256, t0_lds_bytes(t), st>>>(
       a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, (uint64_t)h.cap - 1,
-      &ctr->closed, nullptr, nullptr, nullptr, nullptr, nullptr);
+      ctr, nullptr, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -206,7 +225,8 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t* inc, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
-  k_sample_dense<kUnroll, true><<<sample_grid(count, kUnroll), 256, 0, st>>>(
+  k_sample_dense<kUnroll, true>
+      <<<sample_grid(count, kUnroll), 256, t0_lds_bytes(t), st>>>(
       a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp, inc);
   return hipGetLastError();
 }

@@ -6,42 +6,41 @@
 //   post3  Omega_t = the t largest by |c|, ties by key ascending, written in
 //          that order.
 //
-// Both selections are radix selects on a (primary descending, key
-// ascending) order: 11-bit digits of the primary from its highest set bit
-// down, each pass a histogram of the elements that still match the chosen
-// prefix; when the chosen bin holds exactly the number still needed, or the
-// primary is fully fixed, the ties are split the same way on the key.  Every
-// count lives in device memory, so the sequence of launches needs no host
-// synchronisation.
+// Each selection of k elements by (primary descending, key ascending) runs
+// in three steps, with every count kept in device memory:
+//   1. while the elements are produced (the score table scan for post1, the
+//      verification kernel for post3) a 2048-bin histogram of a monotone
+//      "float" digit of the primary (its highest set bit and the 5 bits
+//      below it) is accumulated;
+//   2. one pass splits the elements: bins above the bin that holds the k-th
+//      element are taken outright, that bin's elements go to a boundary list;
+//   3. one workgroup selects exactly the remaining count from the boundary
+//      list with 11-bit radix passes over the primary and then the key.
 #include "mad_common.hpp"
 #include "plan.hpp"
 
 namespace mad {
 
+constexpr int kBins = 2048;
 constexpr int kDigit = 11;
-constexpr int kBins = 1 << kDigit;
 constexpr uint64_t kDigitMask = kBins - 1;
 
-struct SelState {
-  int64_t n;          // elements
-  int64_t k;          // how many to select
-  int64_t k_rem;      // still to take among the matching elements
-  uint64_t maxp;      // largest primary
-  uint64_t pprefix, pmask;  // fixed primary bits
-  uint64_t kprefix, kmask;  // fixed key bits (tie split)
-  int shift;          // current digit position
-  int phase;          // 0 primary digits, 1 key digits, 2 done
-  int take_all;       // n <= k
-  int key_split;      // ties at the primary threshold split on the key
+// SelectWork::counts slots
+enum {
+  kCntPos = kCountPos,           // |Omega_s|
+  kCntDistinct = kCountDistinct, // nnz(X) (filled by the sampler)
+  kCntCand = kCountCand,         // |Omega_t'|
+  kCntFinal = kCountFinal,       // |Omega_t|
+  kCntBound = 4,                 // boundary list length
+  kCntWin = 5                    // elements taken outright
 };
 
-// counters in SelectWork::counts
-enum {
-  kCntPos = 0,      // |Omega_s|
-  kCntDistinct = 1, // nnz(X)
-  kCntCand = 2,     // |Omega_t'|
-  kCntFinal = 3,    // |Omega_t|
-  kCntMax = 4       // largest primary (as u64) of the current selection
+// coarse decision of one selection
+struct Coarse {
+  int64_t n;      // elements
+  int64_t k;      // to select
+  int64_t k_rem;  // still to select inside the boundary bin
+  int64_t bin;    // boundary bin (-1: take everything)
 };
 
 static inline unsigned blocks_for(int64_t n, int per_block, int cap) {
@@ -50,125 +49,67 @@ static inline unsigned blocks_for(int64_t n, int per_block, int cap) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// ---------------------------------------------------------------------------
-// post1 input: compact the hash table to (x, key) with x > 0
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_compact_scores(
-    const uint64_t* hkeys, const int64_t* hvals, int64_t cap, uint64_t* x,
-    uint64_t* key, int64_t* counts) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int lane = threadIdx.x & 63;
-  unsigned long long distinct = 0;
-  uint64_t mx = 0;
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < cap; b += stride) {
-    const int64_t e = b + threadIdx.x;
-    uint64_t kk = kEmptyKey;
-    int64_t v = 0;
-    if (e < cap) {
-      kk = hkeys[e];
-      v = hvals[e];
-    }
-    distinct += kk != kEmptyKey;
-    const bool take = kk != kEmptyKey && v > 0;
-    const uint64_t ball = __ballot(take);
-    const int cnt = __popcll(ball);
-    unsigned long long base = 0;
-    if (cnt) {
-      if (lane == 0)
-        base = atomicAdd((unsigned long long*)&counts[kCntPos],
-                         (unsigned long long)cnt);
-      base = __shfl(base, 0, 64);
-    }
-    if (take) {
-      const int r = __popcll(ball & ((1ull << lane) - 1));
-      x[base + r] = (uint64_t)v;
-      key[base + r] = kk;
-      mx = (uint64_t)v > mx ? (uint64_t)v : mx;
-    }
-  }
-  distinct = wave_sum(distinct);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t o = __shfl_xor(mx, off, 64);
-    mx = o > mx ? o : mx;
-  }
-  if (lane == 0) {
-    if (distinct)
-      atomicAdd((unsigned long long*)&counts[kCntDistinct], distinct);
-    if (mx) atomicMax((unsigned long long*)&counts[kCntMax], mx);
-  }
+// monotone 11-bit digit of a positive value: (msb, next 5 bits)
+__device__ __forceinline__ int fbin(uint64_t p) {
+  if (p == 0) return 0;
+  const int msb = 63 - __clzll((long long)p);
+  const uint64_t mant = msb >= 5 ? (p >> (msb - 5)) : (p << (5 - msb));
+  return msb * 32 + (int)(mant & 31);
 }
 
-// ---------------------------------------------------------------------------
-// radix select
-// ---------------------------------------------------------------------------
-__global__ void k_sel_init(SelState* s, const int64_t* n_ptr, int64_t k,
-                           const int64_t* counts, unsigned* hist) {
-  const int64_t n = *n_ptr;
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
-  if (threadIdx.x != 0) return;
-  s->n = n;
-  s->k = k;
-  s->k_rem = k;
-  s->maxp = (uint64_t)counts[kCntMax];
-  s->pprefix = s->pmask = s->kprefix = s->kmask = 0;
-  s->take_all = n <= k;
-  s->key_split = 0;
-  s->phase = n <= k ? 2 : 0;
-  const int hi = s->maxp ? 64 - __clzll((long long)s->maxp) : 1;
-  s->shift = hi > kDigit ? hi - kDigit : 0;
-}
-
-__global__ __launch_bounds__(256) void k_sel_hist(const SelState* s,
-                                                  const uint64_t* prim,
-                                                  const uint64_t* key,
-                                                  unsigned* hist) {
-  const int phase = s->phase;
-  if (phase == 2) return;
-  __shared__ unsigned h[kBins];
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
-  __syncthreads();
-  const int64_t n = s->n;
-  const int shift = s->shift;
-  const uint64_t pp = s->pprefix, pm = s->pmask;
-  const uint64_t kp = s->kprefix, km = s->kmask;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += stride) {
-    const uint64_t p = prim[e];
-    if ((p & pm) != pp) continue;
-    if (phase == 0) {
-      atomicAdd(&h[(p >> shift) & kDigitMask], 1u);
-    } else {
-      const uint64_t kk = key[e];
-      if ((kk & km) != kp) continue;
-      atomicAdd(&h[(kk >> shift) & kDigitMask], 1u);
-    }
-  }
+__device__ void block_hist_flush(unsigned* lds, unsigned* gh) {
   __syncthreads();
   for (int b = threadIdx.x; b < kBins; b += blockDim.x)
-    if (h[b]) atomicAdd(&hist[b], h[b]);
+    if (lds[b]) atomicAdd(&gh[b], lds[b]);
 }
 
-// one block: pick the digit, update the state, clear the histogram
-__global__ __launch_bounds__(256) void k_sel_decide(SelState* s,
-                                                    unsigned* hist) {
+// ---------------------------------------------------------------------------
+// post1 step 1: histogram of x > 0 straight from the score table
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_score_hist(const int64_t* hvals,
+                                                    int64_t cap,
+                                                    unsigned* hist,
+                                                    int64_t* counts) {
+  __shared__ unsigned h[kBins];
+  __shared__ unsigned long long part[4];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long npos = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cap;
+       e += stride) {
+    const int64_t v = hvals[e];
+    if (v > 0) {
+      ++npos;
+      atomicAdd(&h[fbin((uint64_t)v)], 1u);
+    }
+  }
+  block_hist_flush(h, hist);
+  npos = wave_sum(npos);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = npos;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+    if (t) atomicAdd((unsigned long long*)&counts[kCntPos], t);
+  }
+}
+
+// step 2a (one block): the boundary bin from the histogram, then clear it
+__global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
+                                                       const int64_t* n_ptr,
+                                                       int64_t k,
+                                                       Coarse* out) {
   __shared__ unsigned long long part[256];
   __shared__ int chosen;
   __shared__ unsigned long long before;
-  if (s->phase == 2) return;
-  const int phase = s->phase;
-  // phase 0 counts from the top bin down (descending primary); phase 1 from
-  // the bottom up (ascending key).  Each thread owns 8 consecutive bins in
-  // scan order.
   const int t = threadIdx.x;
+  const int64_t n = *n_ptr;
   if (t == 0) chosen = -1;
+  // thread t owns 8 consecutive bins in descending order
   unsigned v[8];
   unsigned long long sum = 0;
   for (int q = 0; q < 8; ++q) {
-    const int idx = t * 8 + q;
-    const int b = phase == 0 ? kBins - 1 - idx : idx;
-    v[q] = hist[b];
+    v[q] = hist[kBins - 1 - (t * 8 + q)];
     sum += v[q];
   }
   part[t] = sum;
@@ -182,111 +123,226 @@ __global__ __launch_bounds__(256) void k_sel_decide(SelState* s,
     }
   }
   __syncthreads();
-  const long long need = s->k_rem;
-  {
+  if (n > k) {
     unsigned long long acc = part[t];
     for (int q = 0; q < 8; ++q) {
-      if ((long long)acc < need && (long long)(acc + v[q]) >= need) {
-        const int idx = t * 8 + q;
-        chosen = phase == 0 ? kBins - 1 - idx : idx;
+      if ((long long)acc < k && (long long)(acc + v[q]) >= k) {
+        chosen = kBins - 1 - (t * 8 + q);
         before = acc;
       }
       acc += v[q];
     }
   }
   __syncthreads();
-  const int b = chosen;
-  if (b < 0) {  // cannot happen when k_rem <= matching count; stop safely
-    if (t == 0) s->phase = 2;
-    return;
-  }
-  const unsigned nb = hist[b];
-  __syncthreads();
-  for (int q = t; q < kBins; q += 256) hist[q] = 0;
-  if (t != 0) return;
-  const int shift = s->shift;
-  const int64_t k_rem = need - (long long)before;
-  s->k_rem = k_rem;
-  if (phase == 0) {
-    s->pprefix |= (uint64_t)b << shift;
-    s->pmask |= kDigitMask << shift;
-    if ((int64_t)nb == k_rem) {
-      s->phase = 2;  // every element matching the prefix is taken
-    } else if (shift == 0) {
-      s->phase = 1;  // primary fixed: split the ties on the key
-      s->key_split = 1;
-      s->shift = 64 - kDigit;
+  for (int b = t; b < kBins; b += 256) hist[b] = 0;  // ready for reuse
+  if (t == 0) {
+    out->n = n;
+    out->k = k;
+    if (n <= k || chosen < 0) {
+      out->bin = -1;
+      out->k_rem = 0;
     } else {
-      s->shift = shift > kDigit ? shift - kDigit : 0;
+      out->bin = chosen;
+      out->k_rem = k - (int64_t)before;
     }
-  } else {
-    s->kprefix |= (uint64_t)b << shift;
-    s->kmask |= kDigitMask << shift;
-    if ((int64_t)nb == k_rem || shift == 0) s->phase = 2;
-    else s->shift = shift > kDigit ? shift - kDigit : 0;
   }
 }
 
-__device__ __forceinline__ bool sel_take(const SelState& s, uint64_t p,
-                                         uint64_t kk) {
-  if (s.take_all) return true;
-  const uint64_t pm = p & s.pmask;
-  if (pm != s.pprefix) return pm > s.pprefix;
-  if (!s.key_split) return true;
-  const uint64_t km = kk & s.kmask;
-  return km <= s.kprefix;
+// block-aggregated append (256 threads): this thread's slot when take
+__device__ __forceinline__ int64_t block_append(bool take,
+                                                unsigned long long* ctr,
+                                                unsigned* wcount,
+                                                unsigned long long* wbase) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t ball = __ballot(take);
+  if (lane == 0) wcount[wv] = (unsigned)__popcll(ball);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      const unsigned c = wcount[w];
+      wbase[w] = tot;
+      tot += c;
+    }
+    wbase[4] = tot ? atomicAdd(ctr, tot) : 0ull;
+  }
+  __syncthreads();
+  const int64_t slot = (int64_t)(wbase[4] + wbase[wv] +
+                                 __popcll(ball & ((1ull << lane) - 1)));
+  __syncthreads();
+  return slot;
 }
 
-// post1 emit: copy the selected (x, key) pairs
-__global__ __launch_bounds__(256) void k_emit_candidates(
-    const SelState* sp, const uint64_t* x, const uint64_t* key, uint64_t* x2,
-    uint64_t* key2, int64_t cap2, int64_t* counts) {
-  const SelState s = *sp;
+// ---------------------------------------------------------------------------
+// post1 step 2b: split the score table (winners -> w*, boundary -> b*)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_score_split(
+    const uint64_t* hkeys, const int64_t* hvals, int64_t cap,
+    const Coarse* cz, uint64_t* wx, uint64_t* wkey, int64_t wcap,
+    uint64_t* bx, uint64_t* bkey, int64_t bcap, int64_t* counts) {
+  __shared__ unsigned wcount[4];
+  __shared__ unsigned long long wbase[5];
+  const Coarse c = *cz;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int lane = threadIdx.x & 63;
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < s.n; b += stride) {
-    const int64_t e = b + threadIdx.x;
-    bool take = false;
-    uint64_t xv = 0, kv = 0;
-    if (e < s.n) {
-      xv = x[e];
-      kv = key[e];
-      take = sel_take(s, xv, kv);
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < cap; b0 += stride) {
+    const int64_t e = b0 + threadIdx.x;
+    const int64_t v = e < cap ? hvals[e] : 0;
+    const int bin = v > 0 ? fbin((uint64_t)v) : -2;
+    const bool win = v > 0 && (c.bin < 0 || bin > c.bin);
+    const bool bnd = v > 0 && c.bin >= 0 && bin == c.bin;
+    const int64_t ws = block_append(
+        win, (unsigned long long*)&counts[kCntWin], wcount, wbase);
+    if (win && ws < wcap) {
+      wx[ws] = (uint64_t)v;
+      wkey[ws] = hkeys[e];
     }
-    const uint64_t ball = __ballot(take);
-    const int cnt = __popcll(ball);
-    if (!cnt) continue;
-    unsigned long long base = 0;
-    if (lane == 0)
-      base = atomicAdd((unsigned long long*)&counts[kCntCand],
-                       (unsigned long long)cnt);
-    base = __shfl(base, 0, 64);
-    if (take) {
-      const int64_t r = base + __popcll(ball & ((1ull << lane) - 1));
-      if (r < cap2) {  // the select takes exactly min(n, t') elements
-        x2[r] = xv;
-        key2[r] = kv;
+    const int64_t bs = block_append(
+        bnd, (unsigned long long*)&counts[kCntBound], wcount, wbase);
+    if (bnd && bs < bcap) {
+      bx[bs] = (uint64_t)v;
+      bkey[bs] = hkeys[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step 3: one workgroup selects k_rem of the boundary list exactly, by
+// (primary desc, key asc), and appends them after the winners
+// ---------------------------------------------------------------------------
+constexpr int kFineThreads = 1024;
+
+__global__ __launch_bounds__(kFineThreads) void k_fine_select(
+    const Coarse* cz, const uint64_t* bx, const uint64_t* bkey,
+    const uint64_t* bextra, const float* bc, int64_t bcap, int64_t* counts,
+    int win_slot, uint64_t* ox, uint64_t* okey, uint64_t* oextra, float* oc,
+    int64_t ocap, int out_count_slot) {
+  __shared__ unsigned h[kBins];
+  __shared__ unsigned long long scan[kFineThreads];
+  __shared__ int chosen;
+  __shared__ unsigned long long before;
+  __shared__ unsigned long long emitted;
+  const Coarse c = *cz;
+  const int t = threadIdx.x;
+  const int64_t nwin = counts[win_slot] < ocap ? counts[win_slot] : ocap;
+  int64_t nb = counts[kCntBound];
+  if (nb > bcap) nb = bcap;
+  const bool none = c.bin < 0 || c.k_rem <= 0;
+  int64_t k_rem = none ? 0 : c.k_rem;
+  uint64_t pp = 0, pm = 0, kp = 0, km = 0;
+  bool key_phase = false;
+  bool done = none || k_rem >= nb;
+  // primary digits from the top of the 64-bit range, then key digits
+  int shift = 64 - kDigit;
+  while (!done) {
+    for (int b = t; b < kBins; b += kFineThreads) h[b] = 0;
+    __syncthreads();
+    for (int64_t e = t; e < nb; e += kFineThreads) {
+      const uint64_t p = bx[e];
+      if ((p & pm) != pp) continue;
+      if (!key_phase) {
+        atomicAdd(&h[(p >> shift) & kDigitMask], 1u);
+      } else {
+        const uint64_t kk = bkey[e];
+        if ((kk & km) != kp) continue;
+        atomicAdd(&h[(kk >> shift) & kDigitMask], 1u);
       }
     }
+    __syncthreads();
+    // bins in selection order (descending primary, ascending key); thread t
+    // owns positions 2t and 2t+1 of that order
+    const int b0 = key_phase ? 2 * t : kBins - 1 - 2 * t;
+    const int b1 = key_phase ? 2 * t + 1 : kBins - 2 - 2 * t;
+    const unsigned v0 = h[b0], v1 = h[b1];
+    scan[t] = (unsigned long long)v0 + v1;
+    if (t == 0) chosen = -1;
+    __syncthreads();
+    for (int off = 1; off < kFineThreads; off <<= 1) {
+      const unsigned long long o = t >= off ? scan[t - off] : 0ull;
+      __syncthreads();
+      scan[t] += o;
+      __syncthreads();
+    }
+    const unsigned long long excl = scan[t] - v0 - v1;
+    if ((long long)excl < k_rem && (long long)(excl + v0) >= k_rem) {
+      chosen = b0;
+      before = excl;
+    } else if ((long long)(excl + v0) < k_rem &&
+               (long long)(excl + v0 + v1) >= k_rem) {
+      chosen = b1;
+      before = excl + v0;
+    }
+    __syncthreads();
+    const int b = chosen;
+    const unsigned nbin = b >= 0 ? h[b] : 0u;
+    const unsigned long long bef = before;
+    __syncthreads();
+    if (b < 0) break;  // cannot happen while k_rem <= matching count
+    k_rem -= (int64_t)bef;
+    if (!key_phase) {
+      pp |= (uint64_t)b << shift;
+      pm |= kDigitMask << shift;
+    } else {
+      kp |= (uint64_t)b << shift;
+      km |= kDigitMask << shift;
+    }
+    if ((int64_t)nbin == k_rem) {
+      done = true;
+    } else if (shift == 0) {
+      if (key_phase) done = true;  // keys are unique: cannot recur
+      key_phase = true;
+      shift = 64 - kDigit;
+    } else {
+      shift = shift > kDigit ? shift - kDigit : 0;
+    }
+  }
+  // emit the boundary elements ordered before the threshold and those
+  // matching it (exactly k_rem of the original count in total)
+  if (t == 0) emitted = 0;
+  __syncthreads();
+  for (int64_t e = t; e < nb && !none; e += kFineThreads) {
+    const uint64_t p = bx[e];
+    const uint64_t kk = bkey[e];
+    const uint64_t pmv = p & pm;
+    bool take;
+    if (pmv != pp) take = pmv > pp;
+    else if (!key_phase) take = true;
+    else take = (kk & km) <= kp;
+    if (!take) continue;
+    const int64_t slot = nwin + (int64_t)atomicAdd(&emitted, 1ull);
+    if (slot >= ocap) continue;
+    ox[slot] = p;
+    okey[slot] = kk;
+    if (oextra) oextra[slot] = bextra[e];
+    if (oc) oc[slot] = bc[e];
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int64_t tot = nwin + (int64_t)emitted;
+    counts[out_count_slot] = tot < ocap ? tot : ocap;
   }
 }
 
-// post2: c = a_i . b_j in fp32, one wave per candidate; also |c| as bits
+// ---------------------------------------------------------------------------
+// post2: c = a_i . b_j in fp32, one wave per candidate; histogram of |c|
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
                                                 const int64_t* counts,
                                                 const float* A, const float* B,
                                                 int64_t n, int64_t d,
                                                 int64_t cap2, float* c,
                                                 uint64_t* absbits,
-                                                int64_t* maxbits) {
+                                                unsigned* hist) {
+  __shared__ unsigned h[kBins];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
   const int64_t ncand = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  uint64_t mx = 0;
   for (int64_t e = wave; e < ncand; e += nwaves) {
     const uint64_t kk = key2[e];
-    const int64_t i = (int64_t)(kk / (uint64_t)n), j = (int64_t)(kk % (uint64_t)n);
+    const int64_t i = (int64_t)(kk / (uint64_t)n);
+    const int64_t j = (int64_t)(kk % (uint64_t)n);
     const float* a = A + i * d;
     const float* b = B + j * d;
     float acc = 0.0f;
@@ -296,28 +352,46 @@ __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
       c[e] = acc;
       const uint64_t ab = __float_as_uint(fabsf(acc));
       absbits[e] = ab;
-      mx = ab > mx ? ab : mx;
+      atomicAdd(&h[fbin(ab)], 1u);
     }
   }
-  if (lane == 0 && mx) atomicMax((unsigned long long*)maxbits, mx);
+  block_hist_flush(h, hist);
 }
 
-// post3 emit: the selected candidates into the final buffer
-__global__ __launch_bounds__(256) void k_emit_final(
-    const SelState* sp, const uint64_t* absbits, const uint64_t* key2,
-    const uint64_t* x2, const float* c, uint64_t* fkey, uint64_t* fx,
-    float* fc, int64_t tcap, int64_t* counts) {
-  const SelState s = *sp;
+// post3 step 2b: split the candidates
+__global__ __launch_bounds__(256) void k_cand_split(
+    const Coarse* cz, const uint64_t* absbits, const uint64_t* key2,
+    const uint64_t* x2, const float* c, int64_t cap2, uint64_t* fp,
+    uint64_t* fkey, uint64_t* fx, float* fc, int64_t tcap, uint64_t* bp,
+    uint64_t* bkey, uint64_t* bx, float* bc, int64_t bcap, int64_t* counts) {
+  __shared__ unsigned wcount[4];
+  __shared__ unsigned long long wbase[5];
+  const Coarse cc = *cz;
+  const int64_t n = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < s.n;
-       e += stride) {
-    if (!sel_take(s, absbits[e], key2[e])) continue;
-    const unsigned long long p =
-        atomicAdd((unsigned long long*)&counts[kCntFinal], 1ull);
-    if ((int64_t)p >= tcap) continue;
-    fkey[p] = key2[e];
-    fx[p] = x2[e];
-    fc[p] = c[e];
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
+    const int64_t e = b0 + threadIdx.x;
+    const bool live = e < n;
+    const uint64_t p = live ? absbits[e] : 0;
+    const int bin = fbin(p);
+    const bool win = live && (cc.bin < 0 || bin > cc.bin);
+    const bool bnd = live && cc.bin >= 0 && bin == cc.bin;
+    const int64_t ws = block_append(
+        win, (unsigned long long*)&counts[kCntWin], wcount, wbase);
+    if (win && ws < tcap) {
+      fp[ws] = p;
+      fkey[ws] = key2[e];
+      fx[ws] = x2[e];
+      fc[ws] = c[e];
+    }
+    const int64_t bs = block_append(
+        bnd, (unsigned long long*)&counts[kCntBound], wcount, wbase);
+    if (bnd && bs < bcap) {
+      bp[bs] = p;
+      bkey[bs] = key2[e];
+      bx[bs] = x2[e];
+      bc[bs] = c[e];
+    }
   }
 }
 
@@ -381,52 +455,57 @@ hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,
   return hipGetLastError();
 }
 
-static hipError_t run_select(SelState* st_dev, const int64_t* n_ptr,
-                             int64_t k, const int64_t* counts,
-                             const uint64_t* prim, const uint64_t* key,
-                             unsigned* hist, int64_t n_ub, hipStream_t st) {
-  k_sel_init<<<1, 256, 0, st>>>(st_dev, n_ptr, k, counts, hist);
-  const unsigned g = blocks_for(n_ub, 256 * 16, 1024);
-  // up to 6 primary digits and 6 key digits; idle passes return at once
-  for (int pass = 0; pass < 12; ++pass) {
-    k_sel_hist<<<g, 256, 0, st>>>(st_dev, prim, key, hist);
-    k_sel_decide<<<1, 256, 0, st>>>(st_dev, hist);
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_postprocess(const HashTable& h, const float* A,
                               const float* B, int64_t n, int64_t d,
                               int64_t t_prime, int64_t t, const float* bmax,
                               int64_t s, SelectWork& w, void* out,
                               int64_t* n_out, hipStream_t st) {
-  SelState* ss = (SelState*)w.state;
+  Coarse* cz = (Coarse*)w.state;
   int64_t* counts = w.counts;
-  hipError_t e = launch_fill_u64((uint64_t*)counts, 8, 0ull, st);
+  // keep counts[kCntDistinct] (the sampler's), clear the others
+  hipError_t e = launch_fill_u64((uint64_t*)counts, 1, 0ull, st);
+  if (e == hipSuccess)
+    e = launch_fill_u64((uint64_t*)&counts[kCntCand], 4, 0ull, st);
+  // the histogram is cleared by each decision; clear it here as well so a
+  // fresh (or previously interrupted) workspace starts from zero
+  if (e == hipSuccess)
+    e = launch_fill_u64((uint64_t*)w.hist, kBins / 2, 0ull, st);
   if (e != hipSuccess) return e;
-  // post1
-  k_compact_scores<<<blocks_for(h.cap, 256 * 8, 4096), 256, 0, st>>>(
-      h.keys, h.vals, h.cap, w.x, w.key, counts);
-  const int64_t n_ub = w.cap;
-  e = run_select(ss, &counts[kCntPos], t_prime, counts, w.x, w.key, w.hist,
-                 n_ub, st);
+  // ---- post1: top t' of x over x > 0 ------------------------------------
+  k_score_hist<<<blocks_for(h.cap, 256 * 16, 2048), 256, 0, st>>>(
+      h.vals, h.cap, w.hist, counts);
+  k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntPos], t_prime, cz);
+  // winners go straight to (x2, key2); the boundary bin to (x, key)
+  k_score_split<<<blocks_for(h.cap, 256 * 16, 2048), 256, 0, st>>>(
+      h.keys, h.vals, h.cap, cz, w.x2, w.key2, w.cap2, w.x, w.key, w.cap,
+      counts);
+  k_fine_select<<<1, kFineThreads, 0, st>>>(
+      cz, w.x, w.key, nullptr, nullptr, w.cap, counts, kCntWin, w.x2, w.key2,
+      nullptr, nullptr, w.cap2, kCntCand);
+  // ---- post2: fp32 dot products and the |c| histogram --------------------
+  // (|c| bits go to w.x, free after post1)
+  k_verify<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
+      w.key2, counts, A, B, n, d, w.cap2, w.c, w.x, w.hist);
+  // ---- post3: top t by |c| ----------------------------------------------
+  e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
   if (e != hipSuccess) return e;
-  k_emit_candidates<<<blocks_for(n_ub, 256 * 8, 4096), 256, 0, st>>>(
-      ss, w.x, w.key, w.x2, w.key2, w.cap2, counts);
-  // post2: |c| bits go to w.x (free now), the running max to counts[kCntMax]
-  e = launch_fill_u64((uint64_t*)&counts[kCntMax], 1, 0ull, st);
-  if (e != hipSuccess) return e;
-  k_verify<<<blocks_for(t_prime * 64, 256, 4096), 256, 0, st>>>(
-      w.key2, counts, A, B, n, d, w.cap2, w.c, w.x, &counts[kCntMax]);
-  // post3
-  e = run_select(ss, &counts[kCntCand], t, counts, w.x, w.key2, w.hist,
-                 t_prime, st);
-  if (e != hipSuccess) return e;
-  uint64_t* fkey = w.key;  // reuse: first t entries
-  uint64_t* fx = w.key + t;
-  float* fc = (float*)(w.key + 2 * t);
-  k_emit_final<<<blocks_for(t_prime, 256, 1024), 256, 0, st>>>(
-      ss, w.x, w.key2, w.x2, w.c, fkey, fx, fc, t, counts);
+  k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntCand], t, cz + 1);
+  // final set in w.key[0 .. 4t): |c| bits, key, x, c; boundary after it
+  uint64_t* fp = w.key;
+  uint64_t* fkey = w.key + t;
+  uint64_t* fx = w.key + 2 * t;
+  float* fc = (float*)(w.key + 3 * t);
+  const int64_t bcap = (w.cap - 4 * t) / 4;
+  uint64_t* bp = w.key + 4 * t;
+  uint64_t* bkey = bp + bcap;
+  uint64_t* bx = bkey + bcap;
+  float* bc = (float*)(bx + bcap);
+  k_cand_split<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
+      cz + 1, w.x, w.key2, w.x2, w.c, w.cap2, fp, fkey, fx, fc, t, bp, bkey,
+      bx, bc, bcap, counts);
+  k_fine_select<<<1, kFineThreads, 0, st>>>(
+      cz + 1, bp, bkey, bx, bc, bcap, counts, kCntWin, fp, fkey, fx, fc, t,
+      kCntFinal);
   k_final_sort<<<blocks_for(t, 256, 1024), 256, 0, st>>>(
       fkey, fx, fc, counts, t, n, bmax, s, (PairOut*)out, n_out);
   return hipGetLastError();

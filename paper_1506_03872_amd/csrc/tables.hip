@@ -47,31 +47,15 @@ struct WRowAbs {  // table per vector i over coordinates r: |X[i][r]|
   __device__ double operator()(int64_t seg, int64_t r) const {
     return fabs((double)X[seg * d + r]);
   }
+  __device__ uint32_t sgn(int64_t seg, int64_t r) const {
+    return sign_bit(X[seg * d + r]);
+  }
 };
 
 struct WExplicit {  // one table over explicit FP64 weights
   const double* w;
   __device__ double operator()(int64_t, int64_t r) const { return w[r]; }
-};
-
-struct SignCol {
-  const float* X;
-  int64_t d;
-  __device__ uint32_t operator()(int64_t seg, int64_t r) const {
-    return sign_bit(X[r * d + seg]);
-  }
-};
-
-struct SignRow {
-  const float* X;
-  int64_t d;
-  __device__ uint32_t operator()(int64_t seg, int64_t r) const {
-    return sign_bit(X[seg * d + r]);
-  }
-};
-
-struct SignNone {
-  __device__ uint32_t operator()(int64_t, int64_t) const { return 0u; }
+  __device__ uint32_t sgn(int64_t, int64_t) const { return 0u; }
 };
 
 static inline int ceil_log2_host(int64_t N) {
@@ -121,7 +105,17 @@ __global__ void k_scan_inputs(const float* X, int64_t n, float* amax,
     mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     nonfinite |= __shfl_xor(nonfinite, off, 64);
   }
+  // one pair of atomics per block
+  __shared__ float bmx[4];
+  __shared__ int bnf[4];
   if ((threadIdx.x & 63) == 0) {
+    bmx[threadIdx.x >> 6] = mx;
+    bnf[threadIdx.x >> 6] = nonfinite;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
+    nonfinite = bnf[0] | bnf[1] | bnf[2] | bnf[3];
     if (amax && !nonfinite) atomicMax((unsigned int*)amax, __float_as_uint(mx));
     if (nonfinite) atomicOr(bad, 1);
   }
@@ -137,6 +131,8 @@ __global__ void k_stage0_weights(const double* nb, const double* v,
 // two-level sums and quanta for S equal tables of N items (R runs each)
 // thread t handles run c = t / S of table seg = t % S
 // ---------------------------------------------------------------------------
+constexpr int kRowGroup = 16;
+
 template <class W>
 __global__ void k_run_sums(W w, int64_t S, int64_t N, int64_t R,
                            double* Ssum) {
@@ -145,9 +141,16 @@ __global__ void k_run_sums(W w, int64_t S, int64_t N, int64_t R,
   const int64_t seg = t % S, c = t / S;
   const int64_t r0 = c * kRun;
   const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
-  double l = w(seg, r0);
-#pragma unroll 8
-  for (int64_t r = r0 + 1; r < r1; ++r) l = l + w(seg, r);
+  double l = 0.0;
+  for (int64_t g0 = r0; g0 < r1; g0 += kRowGroup) {
+    double v[kRowGroup];
+#pragma unroll
+    for (int q = 0; q < kRowGroup; ++q)
+      v[q] = w(seg, g0 + q < r1 ? g0 + q : r1 - 1);
+#pragma unroll
+    for (int q = 0; q < kRowGroup; ++q)
+      if (g0 + q < r1) l = g0 + q == r0 ? v[q] : l + v[q];
+  }
   Ssum[c * S + seg] = l;
 }
 
@@ -163,6 +166,7 @@ __global__ void k_run_offsets(const double* Ssum, int64_t S, int64_t R,
   tot[seg] = e;
 }
 
+// quanta with the item's sign bit in bit 63 (quanta are below 2^62)
 template <class W>
 __global__ void k_quantize(W w, int64_t S, int64_t N, int64_t R, int L,
                            const double* E, const double* tot, uint64_t* q) {
@@ -179,14 +183,144 @@ __global__ void k_quantize(W w, int64_t S, int64_t N, int64_t R, int L,
   uint64_t Fprev = c == 0 ? 0ull : (uint64_t)floor(ldexp(e / T, K));
   uint64_t* qs = q + (seg << L);
   double l = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const double wr = w(seg, r);
-    l = r == r0 ? wr : l + wr;
-    const double P = e + l;
-    const uint64_t F = (uint64_t)floor(ldexp(P / T, K));
-    qs[r] = F - Fprev;
-    Fprev = F;
+  for (int64_t g0 = r0; g0 < r1; g0 += kRowGroup) {
+    double v[kRowGroup];
+    uint32_t sg[kRowGroup];
+#pragma unroll
+    for (int u = 0; u < kRowGroup; ++u) {
+      const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
+      v[u] = w(seg, r);
+      sg[u] = w.sgn(seg, r);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowGroup; ++u) {
+      const int64_t r = g0 + u;
+      if (r >= r1) continue;
+      l = r == r0 ? v[u] : l + v[u];
+      const double P = e + l;
+      const uint64_t F = (uint64_t)floor(ldexp(P / T, K));
+      qs[r] = (F - Fprev) | ((uint64_t)sg[u] << 63);
+      Fprev = F;
+    }
   }
+}
+
+// Column families (one table per coordinate k over the vectors): a wave
+// handles one run of 64 consecutive tables, lane = table, so every load reads
+// 64 consecutive floats of one vector.  Loads are issued kColGroup at a time
+// (clamped to the last row, so they carry no branch and stay in flight
+// together) ahead of the sequential adds, and quanta go out through an LDS
+// transpose so each store writes 64 consecutive slots of one table.  The
+// sign bit of each item is kept in bit 63 of its quantum (quanta are below
+// 2^62) for the alias construction.
+constexpr int kColGroup = 32;
+
+__global__ __launch_bounds__(64) void k_col_sums(const float* X, int64_t d,
+                                                 const double* scale,
+                                                 int64_t S, int64_t N,
+                                                 int64_t R, double* Ssum) {
+  const int64_t tiles = (S + 63) / 64;
+  const int64_t c = blockIdx.x / tiles;
+  const int64_t seg = (blockIdx.x % tiles) * 64 + threadIdx.x;
+  if (seg >= S || c >= R) return;
+  const int64_t r0 = c * kRun;
+  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
+  double l = 0.0;
+  for (int64_t g0 = r0; g0 < r1; g0 += kColGroup) {
+    float xv[kColGroup];
+    double sv[kColGroup];
+#pragma unroll
+    for (int q = 0; q < kColGroup; ++q) {
+      const int64_t r = g0 + q < r1 ? g0 + q : r1 - 1;
+      xv[q] = X[r * d + seg];
+      sv[q] = scale ? scale[r] : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kColGroup; ++q) {
+      if (g0 + q < r1) {
+        const double w = scale ? fabs((double)xv[q]) * sv[q]
+                               : fabs((double)xv[q]);
+        l = g0 + q == r0 ? w : l + w;
+      }
+    }
+  }
+  Ssum[c * S + seg] = l;
+}
+
+__global__ __launch_bounds__(64) void k_col_quantize(
+    const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
+    int64_t R, int L, const double* E, const double* tot, uint64_t* q) {
+  __shared__ uint64_t buf[64][65];
+  const int64_t tiles = (S + 63) / 64;
+  const int64_t c = blockIdx.x / tiles;
+  const int64_t seg0 = (blockIdx.x % tiles) * 64;
+  const int lane = threadIdx.x;
+  const int64_t seg = seg0 + lane;
+  const bool ok = seg < S;
+  const int64_t segc = ok ? seg : S - 1;
+  const double T = tot[segc];
+  const bool live = ok && T > 0.0;
+  const int K = L + kCapBits;
+  const double e = E[c * S + segc];
+  const int64_t r0 = c * kRun;
+  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
+  // the prefix before this run is exactly E_c (end of the previous run)
+  uint64_t Fprev = (c == 0 || !live) ? 0ull : (uint64_t)floor(ldexp(e / T, K));
+  double l = 0.0;
+  for (int64_t g0 = r0; g0 < r1; g0 += 64) {
+#pragma unroll
+    for (int h = 0; h < 64; h += kColGroup) {
+      float xv[kColGroup];
+      double sv[kColGroup];
+#pragma unroll
+      for (int u = 0; u < kColGroup; ++u) {
+        const int64_t r = g0 + h + u < r1 ? g0 + h + u : r1 - 1;
+        xv[u] = X[r * d + segc];
+        sv[u] = scale ? scale[r] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kColGroup; ++u) {
+        const int64_t r = g0 + h + u;
+        uint64_t qq = 0;
+        if (live && r < r1) {
+          const double w = scale ? fabs((double)xv[u]) * sv[u]
+                                 : fabs((double)xv[u]);
+          l = r == r0 ? w : l + w;
+          const double P = e + l;
+          const uint64_t F = (uint64_t)floor(ldexp(P / T, K));
+          qq = (F - Fprev) | ((uint64_t)sign_bit(xv[u]) << 63);
+          Fprev = F;
+        }
+        buf[h + u][lane] = qq;
+      }
+    }
+    __syncthreads();
+    const int64_t r = g0 + lane;
+    if (r < r1)
+      for (int sl = 0; sl < 64 && seg0 + sl < S; ++sl)
+        q[((seg0 + sl) << L) + r] = buf[lane][sl];
+    __syncthreads();
+  }
+}
+
+static hipError_t col_quanta(WColAbs w, int64_t S, int64_t N, int L,
+                             double* tot, uint64_t* q, double* runbuf,
+                             hipStream_t st) {
+  const float* X = w.X;
+  const int64_t d = w.d;
+  const double* scale = w.scale;
+  const int64_t R = (N + kRun - 1) / kRun;
+  const int64_t tiles = (S + 63) / 64;
+  double* Ssum = runbuf;          // R * S
+  double* E = runbuf + R * S;     // R * S
+  hipError_t e = launch_fill_u64(q, S << L, 0ull, st);
+  if (e != hipSuccess) return e;
+  k_col_sums<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, R,
+                                                   Ssum);
+  k_run_offsets<<<grid_for(S, 256), 256, 0, st>>>(Ssum, S, R, E, tot);
+  k_col_quantize<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, R,
+                                                       L, E, tot, q);
+  return hipGetLastError();
 }
 
 template <class W>
@@ -206,14 +340,17 @@ static hipError_t uniform_quanta(W w, int64_t S, int64_t N, int L,
 }
 
 // ---------------------------------------------------------------------------
-// alias construction, one wave per table (2^L <= 64 * SPL <= 512 slots;
-// 4 tables per block use at most 40 KB of LDS)
+// alias construction.  Each quantum carries its item's sign bit in bit 63;
+// the lists below carry it in bit 31 of the slot id.
 // ---------------------------------------------------------------------------
-template <int SPL, class Sign>
+constexpr uint64_t kQMask = ~(1ull << 63);
+
+// one wave per table (2^L <= 64 * SPL <= 512 slots; 4 tables per block use
+// at most 40 KB of LDS)
+template <int SPL>
 __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
                                                     const double* tot,
-                                                    int64_t S, int64_t N,
-                                                    int L, Sign sign,
+                                                    int64_t S, int L,
                                                     uint64_t* ent) {
   extern __shared__ uint64_t smem64[];
   const int Np = 1 << L;
@@ -222,16 +359,19 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
   const bool active = seg < S && tot[seg < S ? seg : 0] > 0.0;
   uint64_t* Ld = smem64 + (int64_t)wv * 2 * Np;  // inclusive light deficits
   uint64_t* He = Ld + Np;                         // inclusive heavy excesses
-  uint32_t* Hi = (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np;  // heavy ids
+  uint32_t* Hi = (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np;  // ids
 
   uint64_t qv[SPL];
+  uint32_t sg[SPL];
   uint32_t nl = 0, nh = 0;
   uint64_t sd = 0, se = 0;
 #pragma unroll
   for (int s = 0; s < SPL; ++s) {
     const int r = lane * SPL + s;
     const bool ok = active && r < Np;
-    qv[s] = ok ? q[(seg << L) + r] : 0ull;
+    const uint64_t raw = ok ? q[(seg << L) + r] : 0ull;
+    qv[s] = raw & kQMask;
+    sg[s] = (uint32_t)(raw >> 63);
     if (ok) {
       if (qv[s] < kCap) { ++nl; sd += kCap - qv[s]; }
       else { ++nh; se += qv[s] - kCap; }
@@ -255,7 +395,7 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
       } else {
         ea += qv[s] - kCap;
         He[hp] = ea;
-        Hi[hp] = (uint32_t)r;
+        Hi[hp] = (uint32_t)r | (sg[s] << 31);
         mypos[s] = hp++;
       }
     }
@@ -265,7 +405,6 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
   for (int s = 0; s < SPL; ++s) {
     const int r = lane * SPL + s;
     if (!(active && r < Np)) continue;
-    const uint32_t sg = r < N ? sign(seg, r) : 0u;
     uint64_t e;
     if (qv[s] < kCap) {
       const uint64_t Dx = Ld[mypos[s]] - (kCap - qv[s]);
@@ -274,8 +413,9 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
         const uint32_t mid = (lo + hi) >> 1;
         if (He[mid] >= Dx) hi = mid; else lo = mid + 1;
       }
-      const uint32_t a = NH ? Hi[lo < NH ? lo : NH - 1] : (uint32_t)r;
-      e = pack_entry((uint32_t)qv[s], sg, a, sign(seg, a));
+      const uint32_t a = NH ? Hi[lo < NH ? lo : NH - 1]
+                            : (uint32_t)r | (sg[s] << 31);
+      e = pack_entry((uint32_t)qv[s], sg[s], a & kLow31, a >> 31);
     } else {
       const uint64_t Eh = He[mypos[s]];
       uint32_t lo = 0, hi = NL;
@@ -285,37 +425,34 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
       }
       if (lo < NL && mypos[s] + 1 < NH) {
         const uint32_t a = Hi[mypos[s] + 1];
-        e = pack_entry((uint32_t)(Eh + kCap - Ld[lo]), sg, a, sign(seg, a));
+        e = pack_entry((uint32_t)(Eh + kCap - Ld[lo]), sg[s], a & kLow31,
+                       a >> 31);
       } else {
-        e = pack_entry(0u, sg, (uint32_t)r, sg);
+        e = pack_entry(0u, sg[s], (uint32_t)r, sg[s]);
       }
     }
     ent[(seg << L) + r] = e;
   }
 }
 
-template <class Sign>
 static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
-                              int64_t N, int L, Sign sign, uint64_t* ent,
-                              hipStream_t st) {
+                              int L, uint64_t* ent, hipStream_t st) {
   const int Np = 1 << L;
   const size_t lds = (size_t)4 * Np * 20;
   const unsigned blocks = grid_for(S, 4);
   if (Np <= 64)
-    k_alias_wave<1, Sign><<<blocks, 256, lds, st>>>(q, tot, S, N, L, sign, ent);
+    k_alias_wave<1><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
   else if (Np <= 128)
-    k_alias_wave<2, Sign><<<blocks, 256, lds, st>>>(q, tot, S, N, L, sign, ent);
+    k_alias_wave<2><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
   else if (Np <= 256)
-    k_alias_wave<4, Sign><<<blocks, 256, lds, st>>>(q, tot, S, N, L, sign, ent);
+    k_alias_wave<4><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
   else
-    k_alias_wave<8, Sign><<<blocks, 256, lds, st>>>(q, tot, S, N, L, sign, ent);
+    k_alias_wave<8><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// alias construction for large tables (2^L >= 1024 slots): blocks of 1024
-// slots (256 threads x 4) never straddle a table.
-// ---------------------------------------------------------------------------
+// large tables (2^L >= 1024 slots): blocks of 1024 slots (256 threads x 4)
+// never straddle a table
 constexpr int kAliasBlk = 1024;
 
 struct Quad {
@@ -355,14 +492,15 @@ __global__ __launch_bounds__(256) void k_alias_blocksum(const uint64_t* q,
   const int64_t base = (int64_t)blockIdx.x * kAliasBlk + threadIdx.x * 4;
   Quad a{0, 0, 0, 0};
 #pragma unroll
-  for (int s = 0; s < 4; ++s) slot_stats(q[base + s], a);
+  for (int s = 0; s < 4; ++s) slot_stats(q[base + s] & kQMask, a);
   Quad all = block_excl_scan(a);
   if (threadIdx.x == 0) bs[blockIdx.x] = all;
 }
 
-// per table: exclusive scan of its block sums, and its light/heavy counts
+// per table: exclusive scan of its block sums; light/heavy counts and the
+// total deficit
 __global__ void k_alias_blockscan(Quad* bs, int64_t S, int64_t B,
-                                  uint64_t* NL, uint64_t* NH) {
+                                  uint64_t* NL, uint64_t* NH, uint64_t* Dt) {
   const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (seg >= S) return;
   Quad acc{0, 0, 0, 0};
@@ -373,20 +511,25 @@ __global__ void k_alias_blockscan(Quad* bs, int64_t S, int64_t B,
   }
   NL[seg] = acc.nl;
   NH[seg] = acc.nh;
+  Dt[seg] = acc.sd;
 }
 
-// scatter light inclusive deficits (Ld) and heavy inclusive excesses/ids
-// (He/Hi) into per-table lists; pos[slot] = rank among lights or heavies
+// per table lists in index order: lights with their exclusive deficit
+// prefix (Ld) and slot id (Li); heavies with their inclusive excess prefix
+// (He) and slot id (Hi); ids carry the item's sign in bit 31
 __global__ __launch_bounds__(256) void k_alias_scatter(
-    const uint64_t* q, const Quad* bo, int L, uint64_t* Ld, uint64_t* He,
-    uint32_t* Hi, uint32_t* pos) {
+    const uint64_t* q, const Quad* bo, int L, uint64_t* Ld, uint32_t* Li,
+    uint64_t* He, uint32_t* Hi) {
   const int64_t base = (int64_t)blockIdx.x * kAliasBlk + threadIdx.x * 4;
   const int64_t tb = (base >> L) << L;  // first slot of the table
   uint64_t qv[4];
+  uint32_t sg[4];
   Quad a{0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    qv[s] = q[base + s];
+    const uint64_t raw = q[base + s];
+    qv[s] = raw & kQMask;
+    sg[s] = (uint32_t)(raw >> 63);
     slot_stats(qv[s], a);
   }
   (void)block_excl_scan(a);
@@ -395,76 +538,122 @@ __global__ __launch_bounds__(256) void k_alias_scatter(
   uint64_t da = o.sd + a.sd, ea = o.se + a.se;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const int64_t slot = base + s;
+    const uint32_t id = (uint32_t)(base + s - tb) | (sg[s] << 31);
     if (qv[s] < kCap) {
-      da += kCap - qv[s];
       Ld[tb + lp] = da;
-      pos[slot] = (uint32_t)lp++;
+      Li[tb + lp] = id;
+      da += kCap - qv[s];
+      ++lp;
     } else {
       ea += qv[s] - kCap;
       He[tb + hp] = ea;
-      Hi[tb + hp] = (uint32_t)(slot - tb);
-      pos[slot] = (uint32_t)hp++;
+      Hi[tb + hp] = id;
+      ++hp;
     }
   }
 }
 
-template <class Sign>
-__global__ void k_alias_resolve(const uint64_t* q, const uint64_t* Ld,
-                                const uint64_t* He, const uint32_t* Hi,
-                                const uint32_t* pos, const uint64_t* NLa,
-                                const uint64_t* NHa, const double* tot,
-                                int64_t seg0, int64_t nslots, int L,
-                                int64_t N, Sign sign, uint64_t* ent) {
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
-  const int64_t segl = slot >> L;  // table index within the batch
+// The sweep as a merge of the light deficits D (exclusive) and the heavy
+// excesses E (inclusive), a light first on ties: light l is filled by the
+// heavy that follows all heavies merged before it; heavy h closes against
+// the light merged right after it.  A block merges kMergeBlk consecutive
+// positions: one merge-path search per block edge in global memory, the
+// block's slices of both lists in LDS, one search per thread in LDS, then
+// kMergeP sequential merge steps per thread.
+constexpr int kMergeP = 4;
+constexpr int kMergeBlk = 256 * kMergeP;
+
+__device__ __forceinline__ int64_t merge_split(const uint64_t* D, int64_t NL,
+                                               const uint64_t* E, int64_t NH,
+                                               int64_t di) {
+  int64_t lo = di - NH > 0 ? di - NH : 0;
+  int64_t hi = di < NL ? di : NL;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (D[mid] <= E[di - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_alias_merge(
+    const uint64_t* Ld, const uint32_t* Li, const uint64_t* He,
+    const uint32_t* Hi, const uint64_t* NLa, const uint64_t* NHa,
+    const uint64_t* Dta, const double* tot, int64_t seg0, int L,
+    uint64_t* ent) {
+  __shared__ uint64_t sD[kMergeBlk + 1], sE[kMergeBlk + 1];
+  __shared__ uint32_t sLi[kMergeBlk + 1], sHi[kMergeBlk + 1];
+  __shared__ int64_t edge[2];
+  const int64_t Np = int64_t(1) << L;
+  const int64_t blocks_per = Np / kMergeBlk;
+  const int64_t segl = blockIdx.x / blocks_per;
   const int64_t seg = seg0 + segl;
-  if (!(tot[seg] > 0.0)) return;
+  if (!(tot[seg] > 0.0)) return;  // uniform per block
   const int64_t tb = segl << L;
-  const uint32_t r = (uint32_t)(slot - tb);
-  const uint64_t NL = NLa[segl], NH = NHa[segl];
-  const uint64_t qv = q[slot];
-  const uint32_t sg = (int64_t)r < N ? sign(seg, r) : 0u;
-  const uint32_t p = pos[slot];
-  uint64_t e;
-  if (qv < kCap) {
-    const uint64_t Dx = Ld[tb + p] - (kCap - qv);
-    uint64_t lo = 0, hi = NH;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (He[tb + mid] >= Dx) hi = mid; else lo = mid + 1;
-    }
-    const uint32_t a = NH ? Hi[tb + (lo < NH ? lo : NH - 1)] : r;
-    e = pack_entry((uint32_t)qv, sg, a, sign(seg, a));
-  } else {
-    const uint64_t Eh = He[tb + p];
-    uint64_t lo = 0, hi = NL;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (Ld[tb + mid] > Eh) hi = mid; else lo = mid + 1;
-    }
-    if (lo < NL && (uint64_t)p + 1 < NH) {
-      const uint32_t a = Hi[tb + p + 1];
-      e = pack_entry((uint32_t)(Eh + kCap - Ld[tb + lo]), sg, a, sign(seg, a));
+  const int64_t NL = (int64_t)NLa[segl], NH = (int64_t)NHa[segl];
+  const uint64_t Dt = Dta[segl];
+  const uint64_t* D = Ld + tb;
+  const uint64_t* E = He + tb;
+  const int64_t d0 = (blockIdx.x % blocks_per) * kMergeBlk;
+  if (threadIdx.x < 2)
+    edge[threadIdx.x] = merge_split(D, NL, E, NH, d0 + threadIdx.x * kMergeBlk);
+  __syncthreads();
+  const int64_t a0 = edge[0], b0 = d0 - edge[0];
+  const int64_t na = edge[1] - a0, nb = (d0 + kMergeBlk - edge[1]) - b0;
+  // slices, plus one element past each end (the next D bounds a light's
+  // quantum; the next heavy id closes a heavy)
+  for (int u = threadIdx.x; u <= na; u += 256) {
+    sD[u] = a0 + u < NL ? D[a0 + u] : Dt;
+    sLi[u] = a0 + u < NL ? Li[tb + a0 + u] : 0u;
+  }
+  for (int u = threadIdx.x; u <= nb; u += 256) {
+    sE[u] = b0 + u < NH ? E[b0 + u] : ~0ull;
+    sHi[u] = b0 + u < NH ? Hi[tb + b0 + u] : 0u;
+  }
+  __syncthreads();
+  // this thread's split inside the block's slices
+  const int64_t dl = (int64_t)threadIdx.x * kMergeP;
+  int64_t lo = dl - nb > 0 ? dl - nb : 0, hi = dl < na ? dl : na;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sD[mid] <= sE[dl - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  int64_t a = lo, b = dl - lo;
+  uint64_t* et = ent + ((seg0 + segl) << L);
+  for (int step = 0; step < kMergeP; ++step) {
+    if (a < na && (b >= nb || sD[a] <= sE[b])) {
+      const uint32_t id = sLi[a];
+      const uint32_t r = id & kLow31;
+      const uint32_t qv = (uint32_t)(kCap - (sD[a + 1] - sD[a]));
+      // the donor: the first heavy not merged before this light
+      const uint32_t dn = b0 + b < NH ? sHi[b] : id;
+      et[r] = pack_entry(qv, id >> 31, dn & kLow31, dn >> 31);
+      ++a;
     } else {
-      e = pack_entry(0u, sg, r, sg);
+      const uint32_t id = sHi[b];
+      const uint32_t r = id & kLow31;
+      const uint64_t Eh = sE[b];
+      const uint64_t Dn = sD[a];  // D of the next light, or Dt past the end
+      if (Dn > Eh && b0 + b + 1 < NH) {
+        const uint32_t nx = sHi[b + 1];
+        et[r] = pack_entry((uint32_t)(Eh + kCap - Dn), id >> 31, nx & kLow31,
+                           nx >> 31);
+      } else {
+        et[r] = pack_entry(0u, id >> 31, r, id >> 31);
+      }
+      ++b;
     }
   }
-  ent[(seg0 << L) + slot] = e;
 }
 
 // scratch layout for a batch of `slots` slots and `tables` tables
 static size_t alias_scratch_bytes(int64_t slots, int64_t tables) {
-  return (size_t)slots * (8 + 8 + 4 + 4) + (size_t)(slots / kAliasBlk) *
-         sizeof(Quad) + (size_t)tables * 16 + 256;
+  return (size_t)slots * (8 + 4 + 8 + 4) + (size_t)(slots / kAliasBlk) *
+         sizeof(Quad) + (size_t)tables * 24 + 256;
 }
 
-template <class Sign>
 static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
-                              int64_t N, int L, Sign sign, uint64_t* ent,
-                              void* scratch, size_t scratch_bytes,
-                              hipStream_t st) {
+                              int L, uint64_t* ent, void* scratch,
+                              size_t scratch_bytes, hipStream_t st) {
   const int64_t Np = int64_t(1) << L;
   int64_t per = (int64_t)(scratch_bytes / (alias_scratch_bytes(Np, 1)));
   if (per < 1) return hipErrorOutOfMemory;
@@ -475,33 +664,32 @@ static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
     char* p = (char*)scratch;
     uint64_t* Ld = (uint64_t*)p; p += slots * 8;
     uint64_t* He = (uint64_t*)p; p += slots * 8;
+    uint32_t* Li = (uint32_t*)p; p += slots * 4;
     uint32_t* Hi = (uint32_t*)p; p += slots * 4;
-    uint32_t* pos = (uint32_t*)p; p += slots * 4;
     Quad* bs = (Quad*)p; p += nblk * sizeof(Quad);
     uint64_t* NL = (uint64_t*)p; p += ns * 8;
-    uint64_t* NH = (uint64_t*)p;
+    uint64_t* NH = (uint64_t*)p; p += ns * 8;
+    uint64_t* Dt = (uint64_t*)p;
     const uint64_t* qb = q + (s0 << L);
     k_alias_blocksum<<<(unsigned)nblk, 256, 0, st>>>(qb, bs);
     k_alias_blockscan<<<grid_for(ns, 64), 64, 0, st>>>(bs, ns, Np / kAliasBlk,
-                                                       NL, NH);
-    k_alias_scatter<<<(unsigned)nblk, 256, 0, st>>>(qb, bs, L, Ld, He, Hi, pos);
-    k_alias_resolve<Sign><<<grid_for(slots, 256), 256, 0, st>>>(
-        qb, Ld, He, Hi, pos, NL, NH, tot, s0, slots, L, N, sign, ent);
+                                                       NL, NH, Dt);
+    k_alias_scatter<<<(unsigned)nblk, 256, 0, st>>>(qb, bs, L, Ld, Li, He, Hi);
+    k_alias_merge<<<(unsigned)(slots / kMergeBlk), 256, 0, st>>>(
+        Ld, Li, He, Hi, NL, NH, Dt, tot, s0, L, ent);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-template <class Sign>
 static hipError_t build_alias(const uint64_t* q, const double* tot, int64_t S,
-                              int64_t N, int L, Sign sign, uint64_t* ent,
-                              void* scratch, size_t scratch_bytes,
-                              hipStream_t st) {
+                              int L, uint64_t* ent, void* scratch,
+                              size_t scratch_bytes, hipStream_t st) {
   hipError_t e = launch_fill_u64(ent, S << L, 0ull, st);
   if (e != hipSuccess) return e;
-  if (L <= 9) return alias_small(q, tot, S, N, L, sign, ent, st);
-  return alias_large(q, tot, S, N, L, sign, ent, scratch, scratch_bytes, st);
+  if (L <= 9) return alias_small(q, tot, S, L, ent, st);
+  return alias_large(q, tot, S, L, ent, scratch, scratch_bytes, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -627,38 +815,35 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
       (e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess)
     return e;
   if (check)
-    k_scan_inputs<<<grid_for(m * d, 256) > 4096 ? 4096 : grid_for(m * d, 256),
-                    256, 0, st>>>(A, m * d, nullptr, t.bad);
-  k_scan_inputs<<<grid_for(n * d, 256) > 4096 ? 4096 : grid_for(n * d, 256),
-                  256, 0, st>>>(B, n * d, t.bmax, t.bad);
+    k_scan_inputs<<<grid_for(m * d, 256 * 16) > 1024 ? 1024
+                        : grid_for(m * d, 256 * 16), 256, 0, st>>>(
+        A, m * d, nullptr, t.bad);
+  k_scan_inputs<<<grid_for(n * d, 256 * 16) > 1024 ? 1024
+                      : grid_for(n * d, 256 * 16), 256, 0, st>>>(
+      B, n * d, t.bmax, t.bad);
 
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
   e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
   if (e == hipSuccess)
-    e = build_alias(q, t.T3.tot, m, d, t.T3.L, SignRow{A, d}, t.T3.ent, abuf,
-                    alias_bytes, st);
+    e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, abuf, alias_bytes, st);
   // T1[k]: i given k, weight |a_ki| na_i; totals v_k
   if (e == hipSuccess)
-    e = uniform_quanta(WColAbs{A, d, t.na}, d, m, t.T1.L, t.T1.tot, q, runbuf,
-                       st);
+    e = col_quanta(WColAbs{A, d, t.na}, d, m, t.T1.L, t.T1.tot, q, runbuf, st);
   if (e == hipSuccess)
-    e = build_alias(q, t.T1.tot, d, m, t.T1.L, SignCol{A, d}, t.T1.ent, abuf,
-                    alias_bytes, st);
+    e = build_alias(q, t.T1.tot, d, t.T1.L, t.T1.ent, abuf, alias_bytes, st);
   // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
   if (e == hipSuccess)
-    e = uniform_quanta(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot, q,
-                       runbuf, st);
+    e = col_quanta(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot, q, runbuf,
+                   st);
   if (e == hipSuccess)
-    e = build_alias(q, t.T2.tot, d, n, t.T2.L, SignCol{B, d}, t.T2.ent, abuf,
-                    alias_bytes, st);
+    e = build_alias(q, t.T2.tot, d, t.T2.L, t.T2.ent, abuf, alias_bytes, st);
   // T0: k with weight nb_k v_k; total ||W||_1 (Alg. 2 lines "dw", "ds1")
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
     e = uniform_quanta(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, runbuf, st);
   }
   if (e == hipSuccess)
-    e = build_alias(q, t.T0.tot, 1, d, t.T0.L, SignNone{}, t.T0.ent, abuf,
-                    alias_bytes, st);
+    e = build_alias(q, t.T0.tot, 1, t.T0.L, t.T0.ent, abuf, alias_bytes, st);
   return e;
 }
 
