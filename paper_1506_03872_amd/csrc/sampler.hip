@@ -10,6 +10,8 @@
 // (b_k'j != 0) adds sgn(a_ki b_kj a_k'i) * rne(b_k'j * 2^F) to the int64
 // score of key i*n + j; integer sums make X independent of the order in
 // which threads reach the table.
+#include <stdlib.h>
+
 #include "mad_common.hpp"
 #include "plan.hpp"
 
@@ -34,26 +36,6 @@ struct OneSample {
   int64_t inc;
   bool closed;
 };
-
-// hash insert: linear probing on mix64(key); a slot's key goes from EMPTY
-// to its final value once, so a compare-and-swap that finds EMPTY or the
-// key itself owns the slot.  Returns 1 when this call created the key.
-__device__ __forceinline__ int hash_add(uint64_t* keys, int64_t* vals,
-                                        uint64_t mask, uint64_t key,
-                                        int64_t inc) {
-  uint64_t h = mix64(key) & mask;
-  while (true) {
-    const uint64_t prev = atomicCAS((unsigned long long*)(keys + h),
-                                    (unsigned long long)kEmptyKey,
-                                    (unsigned long long)key);
-    if (prev == kEmptyKey || prev == key) {
-      if (inc != 0)
-        atomicAdd((unsigned long long*)(vals + h), (unsigned long long)inc);
-      return prev == kEmptyKey;
-    }
-    h = (h + 1) & mask;
-  }
-}
 
 template <int U, bool DEBUG>
 __global__ __launch_bounds__(256) void k_sample_dense(
@@ -133,20 +115,54 @@ __global__ __launch_bounds__(256) void k_sample_dense(
         inc = sgn[u] ? -mag : mag;
       }
       smp[u].inc = inc;
-      if (DEBUG) {
-        if (live) {
-          ok[e] = (int32_t)smp[u].k;
-          oi[e] = (int32_t)smp[u].i;
-          oj[e] = (int32_t)smp[u].j;
-          okp[e] = (int32_t)smp[u].kp;
-          oinc[e] = inc;
-        }
-      } else if (smp[u].closed) {
-        ++nclosed;
-        ncreated += hash_add(hkeys, hvals, hmask,
-                             (uint64_t)smp[u].i * (uint64_t)a.n + smp[u].j,
-                             inc);
+      if (DEBUG && live) {
+        ok[e] = (int32_t)smp[u].k;
+        oi[e] = (int32_t)smp[u].i;
+        oj[e] = (int32_t)smp[u].j;
+        okp[e] = (int32_t)smp[u].kp;
+        oinc[e] = inc;
       }
+    }
+    if (!DEBUG) {
+      // score updates: the U compare-and-swaps go out together, then the
+      // adds; a slot's key changes from EMPTY to its final value once, so a
+      // swap that finds EMPTY or the key itself owns the slot
+      uint64_t key[U], slot[U];
+      bool pend[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        key[u] = (uint64_t)smp[u].i * (uint64_t)a.n + smp[u].j;
+        slot[u] = mix64(key[u]) & hmask;
+        pend[u] = smp[u].closed;
+        nclosed += smp[u].closed;
+      }
+      bool any = true;
+      while (any) {
+        uint64_t prev[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          prev[u] = pend[u] ? atomicCAS((unsigned long long*)(hkeys + slot[u]),
+                                        (unsigned long long)kEmptyKey,
+                                        (unsigned long long)key[u])
+                            : 0ull;
+        any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (!pend[u]) continue;
+          if (prev[u] == kEmptyKey || prev[u] == key[u]) {
+            ncreated += prev[u] == kEmptyKey;
+            pend[u] = false;
+          } else {
+            slot[u] = (slot[u] + 1) & hmask;
+            any = true;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (smp[u].closed && smp[u].inc != 0)
+          atomicAdd((unsigned long long*)(hvals + slot[u]),
+                    (unsigned long long)smp[u].inc);
     }
   }
   if (!DEBUG) {
@@ -198,7 +214,16 @@ static unsigned sample_grid(int64_t count, int per_thread) {
   return (unsigned)(blocks < 1 ? 1 : blocks);
 }
 
-constexpr int kUnroll = 2;
+// samples in flight per thread (result-invariant; MAD_SAMPLER_UNROLL
+// selects 1, 2, 4 or 8 for tuning)
+static int sampler_unroll() {
+  static int u = [] {
+    const char* e = getenv("MAD_SAMPLER_UNROLL");
+    const int v = e ? atoi(e) : 4;
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 4;
+  }();
+  return u;
+}
 
 static size_t t0_lds_bytes(const DenseTables& t) {
   const int64_t N0 = int64_t(1) << t.T0.L;
@@ -211,10 +236,22 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                SampleCounters* ctr, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
-  k_sample_dense<kUnroll, false>
-      <<<sample_grid(count, kUnroll), 256, t0_lds_bytes(t), st>>>(
-      a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, (uint64_t)h.cap - 1,
-      ctr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  const size_t lds = t0_lds_bytes(t);
+  const uint64_t hm = (uint64_t)h.cap - 1;
+  switch (sampler_unroll()) {
+#define MAD_SAMPLE_CASE(UU)                                                \
+  case UU:                                                                 \
+    k_sample_dense<UU, false><<<sample_grid(count, UU), 256, lds, st>>>(   \
+        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, ctr, nullptr, \
+        nullptr, nullptr, nullptr, nullptr);                               \
+    break;
+    MAD_SAMPLE_CASE(1)
+    MAD_SAMPLE_CASE(2)
+    MAD_SAMPLE_CASE(8)
+    default:
+    MAD_SAMPLE_CASE(4)
+#undef MAD_SAMPLE_CASE
+  }
   return hipGetLastError();
 }
 
@@ -225,8 +262,8 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t* inc, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
-  k_sample_dense<kUnroll, true>
-      <<<sample_grid(count, kUnroll), 256, t0_lds_bytes(t), st>>>(
+  k_sample_dense<2, true>
+      <<<sample_grid(count, 2), 256, t0_lds_bytes(t), st>>>(
       a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp, inc);
   return hipGetLastError();
 }

@@ -215,57 +215,24 @@ __global__ void k_quantize(W w, int64_t S, int64_t N, int64_t R, int L,
 // 2^62) for the alias construction.
 constexpr int kColGroup = 32;
 
-__global__ __launch_bounds__(64) void k_col_sums(const float* X, int64_t d,
-                                                 const double* scale,
-                                                 int64_t S, int64_t N,
-                                                 int64_t R, double* Ssum) {
-  const int64_t tiles = (S + 63) / 64;
-  const int64_t c = blockIdx.x / tiles;
-  const int64_t seg = (blockIdx.x % tiles) * 64 + threadIdx.x;
-  if (seg >= S || c >= R) return;
-  const int64_t r0 = c * kRun;
-  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
-  double l = 0.0;
-  for (int64_t g0 = r0; g0 < r1; g0 += kColGroup) {
-    float xv[kColGroup];
-    double sv[kColGroup];
-#pragma unroll
-    for (int q = 0; q < kColGroup; ++q) {
-      const int64_t r = g0 + q < r1 ? g0 + q : r1 - 1;
-      xv[q] = X[r * d + seg];
-      sv[q] = scale ? scale[r] : 1.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kColGroup; ++q) {
-      if (g0 + q < r1) {
-        const double w = scale ? fabs((double)xv[q]) * sv[q]
-                               : fabs((double)xv[q]);
-        l = g0 + q == r0 ? w : l + w;
-      }
-    }
-  }
-  Ssum[c * S + seg] = l;
-}
-
-__global__ __launch_bounds__(64) void k_col_quantize(
+// Column run walk: a wave handles one run of 64 consecutive tables, lane =
+// table, and writes each item's run-local prefix l_r (FP64 bits, the item's
+// sign bit in bit 63; l >= 0) through an LDS transpose into the
+// table-major layout of the quanta.  The run total is l at the run's last
+// item.  Loads are issued kColGroup at a time, clamped to the last row so
+// they carry no branch and stay in flight together.
+__global__ __launch_bounds__(64) void k_col_local(
     const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
-    int64_t R, int L, const double* E, const double* tot, uint64_t* q) {
+    int L, uint64_t* Lbuf) {
   __shared__ uint64_t buf[64][65];
   const int64_t tiles = (S + 63) / 64;
   const int64_t c = blockIdx.x / tiles;
   const int64_t seg0 = (blockIdx.x % tiles) * 64;
   const int lane = threadIdx.x;
   const int64_t seg = seg0 + lane;
-  const bool ok = seg < S;
-  const int64_t segc = ok ? seg : S - 1;
-  const double T = tot[segc];
-  const bool live = ok && T > 0.0;
-  const int K = L + kCapBits;
-  const double e = E[c * S + segc];
+  const int64_t segc = seg < S ? seg : S - 1;
   const int64_t r0 = c * kRun;
   const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
-  // the prefix before this run is exactly E_c (end of the previous run)
-  uint64_t Fprev = (c == 0 || !live) ? 0ull : (uint64_t)floor(ldexp(e / T, K));
   double l = 0.0;
   for (int64_t g0 = r0; g0 < r1; g0 += 64) {
 #pragma unroll
@@ -281,46 +248,41 @@ __global__ __launch_bounds__(64) void k_col_quantize(
 #pragma unroll
       for (int u = 0; u < kColGroup; ++u) {
         const int64_t r = g0 + h + u;
-        uint64_t qq = 0;
-        if (live && r < r1) {
+        uint64_t bits = 0;
+        if (r < r1) {
           const double w = scale ? fabs((double)xv[u]) * sv[u]
                                  : fabs((double)xv[u]);
           l = r == r0 ? w : l + w;
-          const double P = e + l;
-          const uint64_t F = (uint64_t)floor(ldexp(P / T, K));
-          qq = (F - Fprev) | ((uint64_t)sign_bit(xv[u]) << 63);
-          Fprev = F;
+          bits = (uint64_t)__double_as_longlong(l) |
+                 ((uint64_t)sign_bit(xv[u]) << 63);
         }
-        buf[h + u][lane] = qq;
+        buf[h + u][lane] = bits;
       }
     }
     __syncthreads();
     const int64_t r = g0 + lane;
     if (r < r1)
       for (int sl = 0; sl < 64 && seg0 + sl < S; ++sl)
-        q[((seg0 + sl) << L) + r] = buf[lane][sl];
+        Lbuf[((seg0 + sl) << L) + r] = buf[lane][sl];
     __syncthreads();
   }
 }
 
-static hipError_t col_quanta(WColAbs w, int64_t S, int64_t N, int L,
-                             double* tot, uint64_t* q, double* runbuf,
-                             hipStream_t st) {
-  const float* X = w.X;
-  const int64_t d = w.d;
-  const double* scale = w.scale;
+// run offsets from the stored run-local prefixes: E_0 = 0,
+// E_{c+1} = E_c + l(last item of run c); total T = E_R
+__global__ void k_col_offsets(const uint64_t* Lbuf, int64_t S, int64_t N,
+                              int L, double* E, double* tot) {
+  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= S) return;
   const int64_t R = (N + kRun - 1) / kRun;
-  const int64_t tiles = (S + 63) / 64;
-  double* Ssum = runbuf;          // R * S
-  double* E = runbuf + R * S;     // R * S
-  hipError_t e = launch_fill_u64(q, S << L, 0ull, st);
-  if (e != hipSuccess) return e;
-  k_col_sums<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, R,
-                                                   Ssum);
-  k_run_offsets<<<grid_for(S, 256), 256, 0, st>>>(Ssum, S, R, E, tot);
-  k_col_quantize<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, R,
-                                                       L, E, tot, q);
-  return hipGetLastError();
+  double e = 0.0;
+  for (int64_t c = 0; c < R; ++c) {
+    E[c * S + seg] = e;
+    const int64_t last = (N < (c + 1) * kRun ? N : (c + 1) * kRun) - 1;
+    const uint64_t raw = Lbuf[(seg << L) + last] & ~(1ull << 63);
+    e = e + __longlong_as_double((long long)raw);
+  }
+  tot[seg] = e;
 }
 
 template <class W>
@@ -345,34 +307,22 @@ static hipError_t uniform_quanta(W w, int64_t S, int64_t N, int L,
 // ---------------------------------------------------------------------------
 constexpr uint64_t kQMask = ~(1ull << 63);
 
-// one wave per table (2^L <= 64 * SPL <= 512 slots; 4 tables per block use
-// at most 40 KB of LDS)
+// One wave builds the alias table of one table from its quanta qv (lane
+// holds slots lane*SPL ..) and sign bits sg; LDS scratch Ld/He (2^L u64
+// each) and Hi (2^L u32) belongs to this wave.  The caller synchronises the
+// block (every wave of the block calls this).
 template <int SPL>
-__global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
-                                                    const double* tot,
-                                                    int64_t S, int L,
-                                                    uint64_t* ent) {
-  extern __shared__ uint64_t smem64[];
+__device__ void wave_alias(const uint64_t (&qv)[SPL], const uint32_t (&sg)[SPL],
+                           bool active, int L, uint64_t* Ld, uint64_t* He,
+                           uint32_t* Hi, uint64_t* et) {
   const int Np = 1 << L;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
-  const bool active = seg < S && tot[seg < S ? seg : 0] > 0.0;
-  uint64_t* Ld = smem64 + (int64_t)wv * 2 * Np;  // inclusive light deficits
-  uint64_t* He = Ld + Np;                         // inclusive heavy excesses
-  uint32_t* Hi = (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np;  // ids
-
-  uint64_t qv[SPL];
-  uint32_t sg[SPL];
+  const int lane = threadIdx.x & 63;
   uint32_t nl = 0, nh = 0;
   uint64_t sd = 0, se = 0;
 #pragma unroll
   for (int s = 0; s < SPL; ++s) {
     const int r = lane * SPL + s;
-    const bool ok = active && r < Np;
-    const uint64_t raw = ok ? q[(seg << L) + r] : 0ull;
-    qv[s] = raw & kQMask;
-    sg[s] = (uint32_t)(raw >> 63);
-    if (ok) {
+    if (active && r < Np) {
       if (qv[s] < kCap) { ++nl; sd += kCap - qv[s]; }
       else { ++nh; se += qv[s] - kCap; }
     }
@@ -431,8 +381,126 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
         e = pack_entry(0u, sg[s], (uint32_t)r, sg[s]);
       }
     }
-    ent[(seg << L) + r] = e;
+    et[r] = e;
   }
+}
+
+// one wave per table from stored quanta (2^L <= 64 * SPL <= 512 slots;
+// 4 tables per block use at most 40 KB of LDS)
+template <int SPL>
+__global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
+                                                    const double* tot,
+                                                    int64_t S, int L,
+                                                    uint64_t* ent) {
+  extern __shared__ uint64_t smem64[];
+  const int Np = 1 << L;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
+  const bool active = seg < S && tot[seg < S ? seg : 0] > 0.0;
+  if (seg < S && !active)  // dead table: never sampled, entries zero
+    for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
+  uint64_t qv[SPL];
+  uint32_t sg[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    const uint64_t raw = active && r < Np ? q[(seg << L) + r] : 0ull;
+    qv[s] = raw & kQMask;
+    sg[s] = (uint32_t)(raw >> 63);
+  }
+  wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * Np,
+                  smem64 + (int64_t)wv * 2 * Np + Np,
+                  (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np,
+                  ent + (seg << L));
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int k) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Small tables end to end, one wave per table (N <= 2^L <= 64 * SPL <= 512,
+// a single run of the two-level order): lane l holds items l*SPL ..; the
+// left-to-right prefix walks the lanes in order with the running sum passed
+// on by readlane; quanta in parallel, then the alias table.  Writes the
+// table total to tot.
+template <int SPL, class W>
+__global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
+                                                      int64_t N, int L,
+                                                      double* tot,
+                                                      uint64_t* ent) {
+  extern __shared__ uint64_t smem64[];
+  const int Np = 1 << L;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
+  const bool ok = seg < S;
+  const int64_t segc = ok ? seg : S - 1;
+  double P[SPL];
+  uint32_t sg[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    const int rc = r < N ? r : (int)N - 1;
+    P[s] = r < N ? w(segc, rc) : 0.0;
+    sg[s] = r < N ? w.sgn(segc, rc) : 0u;
+  }
+  // prefix: lane k adds its items to the running sum of lanes < k
+  const int last_lane = (int)((N - 1) / SPL);
+  double carry = 0.0;
+  for (int k = 0; k <= last_lane; ++k) {
+    if (lane == k) {
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        carry = carry + P[s];
+        P[s] = carry;
+      }
+    }
+    carry = readlane_f64(carry, k);
+  }
+  const double T = carry;  // prefix of item N-1 (padding adds zeros)
+  if (ok && lane == 0) tot[seg] = T;
+  const bool active = ok && T > 0.0;
+  const int K = L + kCapBits;
+  uint64_t F[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    F[s] = active && r < N ? (uint64_t)floor(ldexp(P[s] / T, K)) : 0ull;
+  }
+  // F of the item before this lane's first item
+  const uint64_t Fin = __shfl_up(F[SPL - 1], 1, 64);
+  uint64_t qv[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    const uint64_t Fp = s > 0 ? F[s - 1] : (lane > 0 ? Fin : 0ull);
+    qv[s] = active && r < N ? F[s] - Fp : 0ull;
+  }
+  if (ok && !active)  // dead table: never sampled, entries zero
+    for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
+  wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * Np,
+                  smem64 + (int64_t)wv * 2 * Np + Np,
+                  (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np,
+                  ent + (segc << L));
+}
+
+template <class W>
+static hipError_t small_tables(W w, int64_t S, int64_t N, int L, double* tot,
+                               uint64_t* ent, hipStream_t st) {
+  const int Np = 1 << L;
+  const size_t lds = (size_t)4 * Np * 20;
+  const unsigned blocks = grid_for(S, 4);
+  if (Np <= 64)
+    k_small_tables<1, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
+  else if (Np <= 128)
+    k_small_tables<2, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
+  else if (Np <= 256)
+    k_small_tables<4, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
+  else
+    k_small_tables<8, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
+  return hipGetLastError();
 }
 
 static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
@@ -485,6 +553,56 @@ __device__ Quad block_excl_scan(Quad& v) {
   v = Quad{off.nl + inc.nl - v.nl, off.nh + inc.nh - v.nh,
            off.sd + inc.sd - v.sd, off.se + inc.se - v.se};
   return all;
+}
+
+// Quanta from stored prefixes, one thread per 4 consecutive slots:
+// q_r = F_r - F_{r-1}, F_r = floor(2^K P_r / T) (F_{-1} = 0); padding and
+// dead tables get q = 0.  Blocks cover 1024 slots; when bs is given (tables
+// of >= 1024 slots) each block also writes its alias statistics.
+__global__ __launch_bounds__(256) void k_q_from_prefix(
+    const uint64_t* Lbuf, const double* E, const double* tot, int64_t S,
+    int64_t N, int L, uint64_t* q, Quad* bs) {
+  const int64_t total = S << L;
+  const int64_t base = (int64_t)blockIdx.x * kAliasBlk + threadIdx.x * 4;
+  const int64_t Np = int64_t(1) << L;
+  const int K = L + kCapBits;
+  Quad a{0, 0, 0, 0};
+  uint64_t Fp = 0;  // F of the previous item of the same table
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t slot = base + s;
+    if (slot >= total) break;
+    const int64_t seg = slot >> L;
+    const int64_t r = slot & (Np - 1);
+    const double T = tot[seg];
+    const bool live = T > 0.0;
+    if (s == 0 || r == 0) {
+      // the prefix of item r-1; at a run start it is exactly E_c
+      Fp = 0;
+      if (live && r > 0 && r - 1 < N) {
+        const int64_t cp = (r - 1) / kRun;
+        const uint64_t raw = Lbuf[slot - 1] & kQMask;
+        const double Pp = E[cp * S + seg] +
+                          __longlong_as_double((long long)raw);
+        Fp = (uint64_t)floor(ldexp(Pp / T, K));
+      }
+    }
+    uint64_t qq = 0;
+    if (live && r < N) {
+      const uint64_t raw = Lbuf[slot];
+      const double Pv = E[(r / kRun) * S + seg] +
+                        __longlong_as_double((long long)(raw & kQMask));
+      const uint64_t F = (uint64_t)floor(ldexp(Pv / T, K));
+      qq = (F - Fp) | (raw & ~kQMask);
+      Fp = F;
+    }
+    q[slot] = qq;
+    slot_stats(qq & kQMask, a);
+  }
+  if (bs) {
+    Quad all = block_excl_scan(a);
+    if (threadIdx.x == 0) bs[blockIdx.x] = all;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_alias_blocksum(const uint64_t* q,
@@ -575,30 +693,46 @@ __device__ __forceinline__ int64_t merge_split(const uint64_t* D, int64_t NL,
   return lo;
 }
 
+// merge-path split of every block edge (kMergeBlk positions apart)
+__global__ void k_alias_edges(const uint64_t* Ld, const uint64_t* He,
+                              const uint64_t* NLa, const uint64_t* NHa,
+                              int64_t ntab, int L, int64_t* edges) {
+  const int64_t Np = int64_t(1) << L;
+  const int64_t per = Np / kMergeBlk + 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ntab * per) return;
+  const int64_t segl = gid / per, b = gid % per;
+  const int64_t tb = segl << L;
+  edges[gid] = merge_split(Ld + tb, (int64_t)NLa[segl], He + tb,
+                           (int64_t)NHa[segl], b * kMergeBlk);
+}
+
 __global__ __launch_bounds__(256) void k_alias_merge(
     const uint64_t* Ld, const uint32_t* Li, const uint64_t* He,
     const uint32_t* Hi, const uint64_t* NLa, const uint64_t* NHa,
-    const uint64_t* Dta, const double* tot, int64_t seg0, int L,
-    uint64_t* ent) {
+    const uint64_t* Dta, const int64_t* edges, const double* tot,
+    int64_t seg0, int L, uint64_t* ent) {
   __shared__ uint64_t sD[kMergeBlk + 1], sE[kMergeBlk + 1];
   __shared__ uint32_t sLi[kMergeBlk + 1], sHi[kMergeBlk + 1];
-  __shared__ int64_t edge[2];
   const int64_t Np = int64_t(1) << L;
   const int64_t blocks_per = Np / kMergeBlk;
   const int64_t segl = blockIdx.x / blocks_per;
+  const int64_t bi = blockIdx.x % blocks_per;
   const int64_t seg = seg0 + segl;
-  if (!(tot[seg] > 0.0)) return;  // uniform per block
+  const int64_t d0 = bi * kMergeBlk;
+  uint64_t* et = ent + (seg << L);
+  if (!(tot[seg] > 0.0)) {  // dead table: never sampled, entries zero
+    for (int u = threadIdx.x; u < kMergeBlk; u += 256) et[d0 + u] = 0ull;
+    return;
+  }
   const int64_t tb = segl << L;
   const int64_t NL = (int64_t)NLa[segl], NH = (int64_t)NHa[segl];
   const uint64_t Dt = Dta[segl];
   const uint64_t* D = Ld + tb;
   const uint64_t* E = He + tb;
-  const int64_t d0 = (blockIdx.x % blocks_per) * kMergeBlk;
-  if (threadIdx.x < 2)
-    edge[threadIdx.x] = merge_split(D, NL, E, NH, d0 + threadIdx.x * kMergeBlk);
-  __syncthreads();
-  const int64_t a0 = edge[0], b0 = d0 - edge[0];
-  const int64_t na = edge[1] - a0, nb = (d0 + kMergeBlk - edge[1]) - b0;
+  const int64_t* ed = edges + segl * (blocks_per + 1) + bi;
+  const int64_t a0 = ed[0], b0 = d0 - ed[0];
+  const int64_t na = ed[1] - a0, nb = (d0 + kMergeBlk - ed[1]) - b0;
   // slices, plus one element past each end (the next D bounds a light's
   // quantum; the next heavy id closes a heavy)
   for (int u = threadIdx.x; u <= na; u += 256) {
@@ -618,7 +752,6 @@ __global__ __launch_bounds__(256) void k_alias_merge(
     if (sD[mid] <= sE[dl - mid - 1]) lo = mid + 1; else hi = mid;
   }
   int64_t a = lo, b = dl - lo;
-  uint64_t* et = ent + ((seg0 + segl) << L);
   for (int step = 0; step < kMergeP; ++step) {
     if (a < na && (b >= nb || sD[a] <= sE[b])) {
       const uint32_t id = sLi[a];
@@ -648,11 +781,14 @@ __global__ __launch_bounds__(256) void k_alias_merge(
 // scratch layout for a batch of `slots` slots and `tables` tables
 static size_t alias_scratch_bytes(int64_t slots, int64_t tables) {
   return (size_t)slots * (8 + 4 + 8 + 4) + (size_t)(slots / kAliasBlk) *
-         sizeof(Quad) + (size_t)tables * 24 + 256;
+         sizeof(Quad) + (size_t)tables * 24 +
+         (size_t)(slots / kMergeBlk + tables) * 8 + 256;
 }
 
+// bsf: block statistics of the whole family (from k_q_from_prefix), or
+// null to compute them here
 static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
-                              int L, uint64_t* ent, void* scratch,
+                              int L, uint64_t* ent, Quad* bsf, void* scratch,
                               size_t scratch_bytes, hipStream_t st) {
   const int64_t Np = int64_t(1) << L;
   int64_t per = (int64_t)(scratch_bytes / (alias_scratch_bytes(Np, 1)));
@@ -669,14 +805,19 @@ static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
     Quad* bs = (Quad*)p; p += nblk * sizeof(Quad);
     uint64_t* NL = (uint64_t*)p; p += ns * 8;
     uint64_t* NH = (uint64_t*)p; p += ns * 8;
-    uint64_t* Dt = (uint64_t*)p;
+    uint64_t* Dt = (uint64_t*)p; p += ns * 8;
+    int64_t* edges = (int64_t*)p;
     const uint64_t* qb = q + (s0 << L);
-    k_alias_blocksum<<<(unsigned)nblk, 256, 0, st>>>(qb, bs);
+    if (bsf) bs = bsf + (s0 << L) / kAliasBlk;
+    else k_alias_blocksum<<<(unsigned)nblk, 256, 0, st>>>(qb, bs);
     k_alias_blockscan<<<grid_for(ns, 64), 64, 0, st>>>(bs, ns, Np / kAliasBlk,
                                                        NL, NH, Dt);
     k_alias_scatter<<<(unsigned)nblk, 256, 0, st>>>(qb, bs, L, Ld, Li, He, Hi);
+    const int64_t nedge = ns * (Np / kMergeBlk + 1);
+    k_alias_edges<<<grid_for(nedge, 256), 256, 0, st>>>(Ld, He, NL, NH, ns, L,
+                                                        edges);
     k_alias_merge<<<(unsigned)(slots / kMergeBlk), 256, 0, st>>>(
-        Ld, Li, He, Hi, NL, NH, Dt, tot, s0, L, ent);
+        Ld, Li, He, Hi, NL, NH, Dt, edges, tot, s0, L, ent);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -684,12 +825,29 @@ static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
 }
 
 static hipError_t build_alias(const uint64_t* q, const double* tot, int64_t S,
-                              int L, uint64_t* ent, void* scratch,
+                              int L, uint64_t* ent, Quad* bsf, void* scratch,
                               size_t scratch_bytes, hipStream_t st) {
-  hipError_t e = launch_fill_u64(ent, S << L, 0ull, st);
-  if (e != hipSuccess) return e;
   if (L <= 9) return alias_small(q, tot, S, L, ent, st);
-  return alias_large(q, tot, S, L, ent, scratch, scratch_bytes, st);
+  return alias_large(q, tot, S, L, ent, bsf, scratch, scratch_bytes, st);
+}
+
+// Column families: one serial pass of run-local prefixes, the run offsets,
+// then quanta (and, for tables of >= 1024 slots, the alias block
+// statistics) in parallel.
+static hipError_t col_quanta(const float* X, int64_t d, const double* scale,
+                             int64_t S, int64_t N, int L, double* tot,
+                             uint64_t* q, uint64_t* Lbuf, double* runbuf,
+                             Quad* bsf, hipStream_t st) {
+  const int64_t R = (N + kRun - 1) / kRun;
+  const int64_t tiles = (S + 63) / 64;
+  double* E = runbuf;  // R * S
+  k_col_local<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, L,
+                                                    Lbuf);
+  k_col_offsets<<<grid_for(S, 64), 64, 0, st>>>(Lbuf, S, N, L, E, tot);
+  const int64_t total = S << L;
+  k_q_from_prefix<<<grid_for(total, kAliasBlk), 256, 0, st>>>(
+      Lbuf, E, tot, S, N, L, q, L >= 10 ? bsf : nullptr);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -780,22 +938,20 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
                               bool check, DeviceBuffer& scratch_buf,
                               hipStream_t st) {
   const int64_t m = t.m, n = t.n, d = t.d;
-  // scratch sizes
-  size_t qslots = 0, runs = 0;
+  // scratch: quanta and prefixes of the largest family, run sums, block
+  // statistics, alias lists (batched to at most 2^26 slots)
+  size_t qslots = 0, runs = 0, blks = 0, alias_slots = 0;
   const Family* fams[4] = {&t.T0, &t.T1, &t.T2, &t.T3};
   for (const Family* f : fams) {
-    const size_t s = (size_t)(f->S << f->L);
-    if (s > qslots) qslots = s;
+    const size_t sl = (size_t)(f->S << f->L);
+    if (sl > qslots) qslots = sl;
     const size_t r = run_doubles(f->S, f->N);
     if (r > runs) runs = r;
-  }
-  // alias lists for large families, batched to at most 2^26 slots
-  size_t alias_slots = 0;
-  for (const Family* f : fams)
     if (f->L > 9) {
-      size_t s = (size_t)(f->S << f->L);
-      if (s > alias_slots) alias_slots = s;
+      if (sl / kAliasBlk > blks) blks = sl / kAliasBlk;
+      if (sl > alias_slots) alias_slots = sl;
     }
+  }
   if (alias_slots > ((size_t)1 << 26)) alias_slots = (size_t)1 << 26;
   for (const Family* f : fams)  // at least one table per batch
     if (f->L > 9 && alias_slots < ((size_t)1 << f->L))
@@ -803,13 +959,16 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   const size_t alias_bytes =
       alias_slots ? alias_scratch_bytes((int64_t)alias_slots,
                                         (int64_t)alias_slots / kAliasBlk) : 0;
-  const size_t total = qslots * 8 + runs * 8 + alias_bytes + 1024;
+  const size_t total = 2 * qslots * 8 + runs * 8 + blks * sizeof(Quad) +
+                       alias_bytes + 1024;
   hipError_t e = dev_alloc(scratch_buf, total);
   if (e != hipSuccess) return e;
-  char* scratch = (char*)scratch_buf.p;
-  uint64_t* q = (uint64_t*)scratch;
-  double* runbuf = (double*)(scratch + qslots * 8);
-  void* abuf = scratch + qslots * 8 + runs * 8;
+  char* p = (char*)scratch_buf.p;
+  uint64_t* q = (uint64_t*)p; p += qslots * 8;
+  uint64_t* Pbuf = (uint64_t*)p; p += qslots * 8;
+  double* runbuf = (double*)p; p += runs * 8;
+  Quad* bsf = (Quad*)p; p += blks * sizeof(Quad);
+  void* abuf = p;
 
   if ((e = launch_fill_u64((uint64_t*)t.bmax, 1, 0ull, st)) != hipSuccess ||
       (e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess)
@@ -823,27 +982,41 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
       B, n * d, t.bmax, t.bad);
 
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
-  e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
-  if (e == hipSuccess)
-    e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, abuf, alias_bytes, st);
+  if (t.T3.L <= 9) {
+    e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
+  } else {
+    e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
+    if (e == hipSuccess)
+      e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, nullptr, abuf,
+                      alias_bytes, st);
+  }
   // T1[k]: i given k, weight |a_ki| na_i; totals v_k
   if (e == hipSuccess)
-    e = col_quanta(WColAbs{A, d, t.na}, d, m, t.T1.L, t.T1.tot, q, runbuf, st);
-  if (e == hipSuccess)
-    e = build_alias(q, t.T1.tot, d, t.T1.L, t.T1.ent, abuf, alias_bytes, st);
-  // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
-  if (e == hipSuccess)
-    e = col_quanta(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot, q, runbuf,
+    e = col_quanta(A, d, t.na, d, m, t.T1.L, t.T1.tot, q, Pbuf, runbuf, bsf,
                    st);
   if (e == hipSuccess)
-    e = build_alias(q, t.T2.tot, d, t.T2.L, t.T2.ent, abuf, alias_bytes, st);
+    e = build_alias(q, t.T1.tot, d, t.T1.L, t.T1.ent, bsf, abuf, alias_bytes,
+                    st);
+  // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
+  if (e == hipSuccess)
+    e = col_quanta(B, d, nullptr, d, n, t.T2.L, t.T2.tot, q, Pbuf, runbuf,
+                   bsf, st);
+  if (e == hipSuccess)
+    e = build_alias(q, t.T2.tot, d, t.T2.L, t.T2.ent, bsf, abuf, alias_bytes,
+                    st);
   // T0: k with weight nb_k v_k; total ||W||_1 (Alg. 2 lines "dw", "ds1")
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
-    e = uniform_quanta(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, runbuf, st);
+    if (t.T0.L <= 9) {
+      e = small_tables(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, t.T0.ent, st);
+    } else {
+      e = uniform_quanta(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, runbuf,
+                         st);
+      if (e == hipSuccess)
+        e = build_alias(q, t.T0.tot, 1, t.T0.L, t.T0.ent, nullptr, abuf,
+                        alias_bytes, st);
+    }
   }
-  if (e == hipSuccess)
-    e = build_alias(q, t.T0.tot, 1, t.T0.L, t.T0.ent, abuf, alias_bytes, st);
   return e;
 }
 
