@@ -156,6 +156,43 @@ int mad_plan_stats(mad_plan* plan, double* wnorm, int64_t* closed,
 int mad_plan_phase_ms(mad_plan* plan, double* ms, int n);
 
 /* ---------------------------------------------------------------------------
+ * mad_bruteforce_topk -- exhaustive t-MAD (Definition 1) on the matrix
+ * cores: every pair's a_i . b_j, top t by |c| (ties by (i, j) ascending),
+ * the role of the exact baseline of Sec. 5.3.  The m x n product is never
+ * stored: a GEMM over every 64th row of A (or 8th / all rows when m is
+ * small) gives a threshold, a second GEMM keeps only the pairs whose
+ * computed value plus an a-priori error bound reaches it, and those
+ * survivors are re-ranked with fp32 dot products (the same arithmetic as
+ * the sampled path's verification).
+ *   precision  MAD_FP32, MAD_BF16 or MAD_FP8_E4M3: input type of the GEMM
+ *              (fp32 accumulation; fp8 with a per-vector power-of-two scale)
+ *   t_screen   0: certified mode: the filter adds an a-priori bound on the
+ *              GEMM's rounding error, so the result is the exact top t of
+ *              the fp32 products for every precision (for fp8 on data with
+ *              small |c| relative to ||a|| ||b|| the bound keeps many pairs).
+ *              > 0 with MAD_BF16 / MAD_FP8_E4M3: screening mode: the
+ *              t_screen pairs with the largest low-precision |c| are
+ *              re-ranked in fp32 (not certified; callers report recall).
+ *   out, n_out (device) as for mad_plan_topk (x = 0)
+ *   stats      (host, optional) phase times and survivor count
+ * Synchronises `stream`.  Keeps a process-wide workspace between calls.
+ * ------------------------------------------------------------------------- */
+typedef struct mad_bf_stats {
+  double ms_screen;    /* conversion + threshold GEMM                     */
+  double ms_filter;    /* all-pairs GEMM with the bound filter            */
+  double ms_rerank;    /* fp32 re-rank and the exact selection            */
+  int64_t candidates;  /* survivors of the filter                         */
+  float tau;           /* filter threshold                                */
+  int64_t row_stride;  /* the threshold GEMM used every row_stride-th row */
+  int64_t reranked;    /* pairs re-ranked in fp32                         */
+} mad_bf_stats;
+
+int mad_bruteforce_topk(const float* A, int64_t m, const float* B, int64_t n,
+                        int64_t d, int precision, int64_t t, int64_t t_screen,
+                        mad_pair* out, int64_t* n_out, mad_bf_stats* stats,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
  * mad_probe_memory -- measurement kernels for the memory ceilings the
  * sampler works against (used by the benchmark's roofline).  buf (device)
  * holds nwords 64-bit words, nwords a power of two; nops operations at

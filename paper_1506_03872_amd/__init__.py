@@ -27,6 +27,7 @@ EXPORTS = (
     "mad_last_error", "mad_debug_table", "mad_debug_norms",
     "mad_debug_samples", "mad_debug_scores", "mad_debug_candidates",
     "mad_fix_exponent", "mad_plan_phase_ms", "mad_probe_memory",
+    "mad_bruteforce_topk",
 )
 
 
@@ -70,6 +71,8 @@ def lib():
         L.mad_fix_exponent.argtypes = [_P, _i64, _P]
         L.mad_plan_phase_ms.argtypes = [_P, _P, C.c_int]
         L.mad_probe_memory.argtypes = [C.c_int, _P, _i64, _i64, _u64, _P]
+        L.mad_bruteforce_topk.argtypes = [_P, _i64, _P, _i64, _i64, C.c_int,
+                                          _i64, _i64, _P, _P, _P, _P]
         _lib = L
     return _lib
 
@@ -259,6 +262,30 @@ class Plan:
         keys = keys[:n.value].cpu().numpy()
         o = np.argsort(keys, kind="stable")
         return keys[o], x[:n.value].cpu().numpy()[o], c[:n.value].cpu().numpy()[o]
+
+
+class BfStats(C.Structure):
+    _fields_ = [("ms_screen", C.c_double), ("ms_filter", C.c_double),
+                ("ms_rerank", C.c_double), ("candidates", C.c_int64),
+                ("tau", C.c_float), ("row_stride", C.c_int64),
+                ("reranked", C.c_int64)]
+
+
+def bruteforce_topk(A, B, t, precision=MAD_FP32, t_screen=0, stream=None):
+    """Exhaustive top-t by |a_i . b_j| on the matrix cores (synchronises).
+    Returns (dict of i, j, c, x, stats dict)."""
+    import torch
+    m, d = A.shape
+    n = B.shape[0]
+    out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = BfStats()
+    _check(lib().mad_bruteforce_topk(
+        _dev(A, torch.float32, "A"), m, _dev(B, torch.float32, "B"), n, d,
+        precision, t, t_screen, C.c_void_p(out.data_ptr()),
+        C.c_void_p(n_out.data_ptr()), C.byref(st), _stream(stream)))
+    stats = {f: getattr(st, f) for f, _ in BfStats._fields_}
+    return unpack_pairs(out, int(n_out.item())), stats
 
 
 def probe_memory(kind, buf, nops, seed=0, stream=None):

@@ -447,6 +447,39 @@ int mad_debug_candidates(mad_plan* p, int64_t* keys, int64_t* xfix, float* c,
   return MAD_OK;
 }
 
+int mad_bruteforce_topk(const float* A, int64_t m, const float* B, int64_t n,
+                        int64_t d, int precision, int64_t t, int64_t t_screen,
+                        mad_pair* out, int64_t* n_out, mad_bf_stats* stats,
+                        void* stream) {
+  g_err.clear();
+  if (m < 1 || n < 1 || d < 1 || m >= (int64_t(1) << 31) ||
+      n >= (int64_t(1) << 31))
+    return fail(MAD_EINVAL, "need 1 <= m, n < 2^31 and d >= 1");
+  if (t < 1 || (double)t > (double)m * (double)n)
+    return fail(MAD_EINVAL, "need 1 <= t <= m*n");
+  if (precision != MAD_FP32 && precision != MAD_BF16 &&
+      precision != MAD_FP8_E4M3)
+    return fail(MAD_EINVAL, "unknown precision %d", precision);
+  if (!out || !n_out) return fail(MAD_EINVAL, "out and n_out are required");
+  if (!is_device_ptr(A) || !is_device_ptr(B))
+    return fail(MAD_EINVAL, "A and B must be device pointers");
+  mad::BfStats bs;
+  memset(&bs, 0, sizeof bs);
+  hipError_t e = mad::bruteforce_topk(A, m, B, n, d, precision, t, t_screen,
+                                      out, n_out, &bs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "brute force");
+  if (stats) {
+    stats->ms_screen = bs.ms_screen;
+    stats->ms_filter = bs.ms_filter;
+    stats->ms_rerank = bs.ms_rerank;
+    stats->candidates = bs.candidates;
+    stats->tau = bs.tau;
+    stats->row_stride = bs.row_stride;
+    stats->reranked = bs.reranked;
+  }
+  return MAD_OK;
+}
+
 int mad_plan_create_csr(const int64_t*, const int32_t*, const float*, int64_t,
                         const int64_t*, const int32_t*, const float*, int64_t,
                         int64_t, uint32_t, void*, mad_plan** plan) {

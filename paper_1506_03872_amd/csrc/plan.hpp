@@ -119,4 +119,34 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
                               int64_t s, SelectWork& w, void* out,
                               int64_t* n_out, hipStream_t st);
 
+// fp32 re-rank of candidate keys (count known on the host) and the exact
+// top t by |c| into mad_pair records; buf is grown as needed
+hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
+                              const float* A, const float* B, int64_t n,
+                              int64_t d, int64_t t, DeviceBuffer& buf,
+                              void* out, int64_t* n_out, hipStream_t st);
+
+// the k keys with the largest |v| (ties by key ascending) into out_keys
+// (device, capacity k), unordered; count known on the host
+hipError_t launch_select_keys_by_absval(const uint64_t* keys, const float* v,
+                                        int64_t count, int64_t k,
+                                        DeviceBuffer& buf, uint64_t* out_keys,
+                                        hipStream_t st);
+
+// ---- bruteforce.hip ------------------------------------------------------
+struct BfStats {
+  double ms_screen;   // conversion + pass A (threshold)
+  double ms_filter;   // pass B (all pairs)
+  double ms_rerank;   // fp32 re-rank and selection
+  int64_t candidates; // pairs that passed the bound
+  float tau;          // threshold of pass B
+  int64_t row_stride; // rows of A used by pass A: every row_stride-th
+  int64_t reranked;   // pairs re-ranked in fp32
+};
+
+hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,
+                           int64_t n, int64_t d, int prec, int64_t t,
+                           int64_t cap_hint, void* out, int64_t* n_out,
+                           BfStats* stats, hipStream_t st);
+
 }  // namespace mad

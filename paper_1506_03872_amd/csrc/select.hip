@@ -57,6 +57,12 @@ __device__ __forceinline__ int fbin(uint64_t p) {
   return msb * 32 + (int)(mant & 31);
 }
 
+// monotone 11-bit digit of a non-negative float given as its bits: the
+// exponent and the top 3 mantissa bits (1/8-octave bins)
+__device__ __forceinline__ int fbin_float(uint64_t bits) {
+  return (int)(bits >> 20) & (kBins - 1);
+}
+
 __device__ void block_hist_flush(unsigned* lds, unsigned* gh) {
   __syncthreads();
   for (int b = threadIdx.x; b < kBins; b += blockDim.x)
@@ -352,7 +358,7 @@ __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
       c[e] = acc;
       const uint64_t ab = __float_as_uint(fabsf(acc));
       absbits[e] = ab;
-      atomicAdd(&h[fbin(ab)], 1u);
+      atomicAdd(&h[fbin_float(ab)], 1u);
     }
   }
   block_hist_flush(h, hist);
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(256) void k_cand_split(
     const int64_t e = b0 + threadIdx.x;
     const bool live = e < n;
     const uint64_t p = live ? absbits[e] : 0;
-    const int bin = fbin(p);
+    const int bin = fbin_float(p);
     const bool win = live && (cc.bin < 0 || bin > cc.bin);
     const bool bnd = live && cc.bin >= 0 && bin == cc.bin;
     const int64_t ws = block_append(
@@ -406,7 +412,7 @@ __global__ void k_final_sort(const uint64_t* fkey, const uint64_t* fx,
                              int64_t tcap, int64_t n, const float* bmax,
                              int64_t s_for_F, PairOut* out, int64_t* n_out) {
   const int64_t nf = counts[kCntFinal] < tcap ? counts[kCntFinal] : tcap;
-  const int F = fix_exponent(*bmax, s_for_F);
+  const int F = bmax ? fix_exponent(*bmax, s_for_F) : 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf;
        e += stride) {
@@ -452,6 +458,117 @@ hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,
   if (e != hipSuccess) return e;
   k_dump_scores<<<blocks_for(h.cap, 256, 4096), 256, 0, st>>>(
       h.keys, h.vals, h.cap, keys, xfix, out_cap, count);
+  return hipGetLastError();
+}
+
+// histogram of |v| (float digit) and |v| bits, for a selection on values
+__global__ __launch_bounds__(256) void k_absval_hist(const float* v,
+                                                     int64_t n,
+                                                     uint64_t* absbits,
+                                                     unsigned* hist) {
+  __shared__ unsigned h[kBins];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += stride) {
+    const uint64_t ab = __float_as_uint(fabsf(v[e]));
+    absbits[e] = ab;
+    atomicAdd(&h[fbin_float(ab)], 1u);
+  }
+  block_hist_flush(h, hist);
+}
+
+hipError_t launch_select_keys_by_absval(const uint64_t* keys, const float* v,
+                                        int64_t count, int64_t k,
+                                        DeviceBuffer& buf, uint64_t* out_keys,
+                                        hipStream_t st) {
+  const int64_t cnt = count > 1 ? count : 1;
+  const size_t need = 256 + 256 + kBins * 4 + (size_t)cnt * (8 + 8) +
+                      (size_t)(4 * k + 4 * cnt) * 8 + 1024;
+  hipError_t e = dev_alloc(buf, need);
+  if (e != hipSuccess) return e;
+  char* p = (char*)buf.p;
+  int64_t* counts = (int64_t*)p; p += 256;
+  Coarse* cz = (Coarse*)p; p += 256;
+  unsigned* hist = (unsigned*)p; p += kBins * 4;
+  uint64_t* x2 = (uint64_t*)p; p += (size_t)cnt * 8;
+  uint64_t* absbits = (uint64_t*)p; p += (size_t)cnt * 8;
+  uint64_t* key = (uint64_t*)p;
+  if ((e = launch_fill_u64((uint64_t*)counts, 32, 0ull, st)) != hipSuccess ||
+      (e = launch_fill_u64((uint64_t*)hist, kBins / 2, 0ull, st)) != hipSuccess ||
+      (e = launch_fill_u64(x2, cnt, 0ull, st)) != hipSuccess ||
+      (e = launch_fill_u64((uint64_t*)&counts[kCntCand], 1, (uint64_t)count,
+                           st)) != hipSuccess)
+    return e;
+  k_absval_hist<<<blocks_for(cnt, 256 * 8, 2048), 256, 0, st>>>(v, count,
+                                                                absbits, hist);
+  k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], k, cz);
+  uint64_t* fp = key;
+  uint64_t* fkey = out_keys;
+  uint64_t* fx = key + k;
+  float* fc = (float*)(key + 2 * k);
+  const int64_t bcap = cnt;
+  uint64_t* bp = key + 4 * k;
+  uint64_t* bkey = bp + bcap;
+  uint64_t* bx = bkey + bcap;
+  float* bc = (float*)(bx + bcap);
+  k_cand_split<<<blocks_for(cnt, 256 * 4, 1024), 256, 0, st>>>(
+      cz, absbits, keys, x2, v, cnt, fp, fkey, fx, fc, k, bp, bkey, bx, bc,
+      bcap, counts);
+  k_fine_select<<<1, kFineThreads, 0, st>>>(cz, bp, bkey, bx, bc, bcap,
+                                            counts, kCntWin, fp, fkey, fx, fc,
+                                            k, kCntFinal);
+  return hipGetLastError();
+}
+
+hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
+                              const float* A, const float* B, int64_t n,
+                              int64_t d, int64_t t, DeviceBuffer& buf,
+                              void* out, int64_t* n_out, hipStream_t st) {
+  // layout: counts, Coarse, hist, x2 (zeros), c, |c| bits, final + boundary
+  const int64_t cnt = count > 1 ? count : 1;
+  const size_t need = 256 + 256 + kBins * 4 + (size_t)cnt * (8 + 4 + 8) +
+                      (size_t)(4 * t + 4 * cnt) * 8 + 1024;
+  hipError_t e = dev_alloc(buf, need);
+  if (e != hipSuccess) return e;
+  char* p = (char*)buf.p;
+  int64_t* counts = (int64_t*)p; p += 256;
+  Coarse* cz = (Coarse*)p; p += 256;
+  unsigned* hist = (unsigned*)p; p += kBins * 4;
+  uint64_t* x2 = (uint64_t*)p; p += (size_t)cnt * 8;
+  float* c = (float*)p; p += (size_t)cnt * 4;
+  p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+  uint64_t* absbits = (uint64_t*)p; p += (size_t)cnt * 8;
+  uint64_t* key = (uint64_t*)p;
+  if ((e = launch_fill_u64((uint64_t*)counts, 32, 0ull, st)) != hipSuccess ||
+      (e = launch_fill_u64((uint64_t*)hist, kBins / 2, 0ull, st)) != hipSuccess ||
+      (e = launch_fill_u64(x2, cnt, 0ull, st)) != hipSuccess)
+    return e;
+  // the candidate count goes where the verification kernel reads it
+  e = launch_fill_u64((uint64_t*)&counts[kCntCand], 1, (uint64_t)count, st);
+  if (e != hipSuccess) return e;
+  k_verify<<<blocks_for(cnt * 64, 256, 2048), 256, 0, st>>>(
+      keys, counts, A, B, n, d, cnt, c, absbits, hist);
+  k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], t, cz);
+  uint64_t* fp = key;
+  uint64_t* fkey = key + t;
+  uint64_t* fx = key + 2 * t;
+  float* fc = (float*)(key + 3 * t);
+  const int64_t bcap = cnt;
+  uint64_t* bp = key + 4 * t;
+  uint64_t* bkey = bp + bcap;
+  uint64_t* bx = bkey + bcap;
+  float* bc = (float*)(bx + bcap);
+  k_cand_split<<<blocks_for(cnt, 256 * 4, 1024), 256, 0, st>>>(
+      cz, absbits, keys, x2, c, cnt, fp, fkey, fx, fc, t, bp, bkey, bx, bc,
+      bcap, counts);
+  k_fine_select<<<1, kFineThreads, 0, st>>>(cz, bp, bkey, bx, bc, bcap,
+                                            counts, kCntWin, fp, fkey, fx, fc,
+                                            t, kCntFinal);
+  // x = 0 for brute-force results (no sampler score); F is irrelevant
+  k_final_sort<<<blocks_for(t, 256, 1024), 256, 0, st>>>(
+      fkey, fx, fc, counts, t, n, nullptr, 0, (PairOut*)out, n_out);
   return hipGetLastError();
 }
 
