@@ -208,6 +208,77 @@ int mad_bruteforce_topk(const float* A, int64_t m, const float* B, int64_t n,
 int mad_probe_memory(int kind, void* buf, int64_t nwords, int64_t nops,
                      uint64_t seed, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * MIPS (maximum inner product search): Sec. 2 notes that MAD with a single
+ * vector on one side is MIPS, and Sec. 6 runs Alg. 2 + Alg. 3 once per
+ * query vector with a sample budget s and a dot-product budget t'.
+ *
+ * mips_plan_create -- preprocessing of the database side of Alg. 2:
+ * na_i = ||a_i||_1, v_k, and the alias tables T1[k] (i given k, weight
+ * |a_ki| na_i) and T3[i] (k' given i, weight |a_k'i|), shared by every
+ * query.  A (device) m x d fp32 row-major, borrowed as by
+ * mad_plan_create_dense; 1 <= m < 2^31, 1 <= d <= 4096 (MAD_EUNSUPPORTED
+ * above).  Destroy with mad_plan_destroy; mad_plan_refresh rebuilds the
+ * tables after A changed.  Synchronises once (input check).
+ * ------------------------------------------------------------------------- */
+int mips_plan_create(const float* A, int64_t m, int64_t d, uint32_t flags,
+                     void* stream, mad_plan** plan);
+
+/* ---------------------------------------------------------------------------
+ * mips_topk_batch -- nq queries in one batch.  Query q (row q of Q) gets
+ * exactly the result of mad_plan_topk on a plan with B = {q} (n = 1) using
+ * s = s_per_query[q], t' = tprime_per_query[q], the same t and seed, and
+ * Philox counter word 1 = q: its own stage-0 table (weight |q_k| v_k), its
+ * own fixed-point exponent F_q from max|q_k| and s_q, scores keyed by i.
+ *   Q                  (device) nq x d fp32 row-major; 0 <= nq < 2^31
+ *   s_per_query        (host) nq budgets, 0 <= s_q < 2^31
+ *   tprime_per_query   (host) nq candidate budgets, each >= t
+ *   t                  1 <= t <= min(1024, m)
+ *   out                (device) nq x t mad_pair; row q holds the top t of
+ *                      query q by |c| (ties by i ascending), j = q
+ *   n_out              (device) nq int64: pairs written for each query;
+ *                      -1 for a query holding NaN or Inf
+ * The launches of a batch (per-query exponents and stage-0 tables, the
+ * clearing of the score tables, one persistent sampling launch over chunks
+ * of every query's samples, one postprocessing launch with a workgroup per
+ * query) are captured once into a HIP graph, which later calls with the
+ * same Q, out, n_out, seed and budgets replay on `stream`.  A new budget
+ * vector re-plans the batch (host work, uploads and allocation: the call
+ * then synchronises).  With MAD_FLAG_TIMING the launches run directly,
+ * with phase events read by mad_plan_phase_ms.
+ * ------------------------------------------------------------------------- */
+int mips_topk_batch(mad_plan* plan, const float* Q, int64_t nq,
+                    const int64_t* s_per_query, const int64_t* tprime_per_query,
+                    int64_t t, uint64_t seed, mad_pair* out, int64_t* n_out,
+                    void* stream);
+
+/* Launch shape of the batch (never changes a result): samples per chunk
+ * (multiple of 256), samples in flight per thread (1, 2, 4, 8) and
+ * workgroups of the persistent sampling launch. */
+int mips_get_config(mad_plan* plan, int* chunk, int* unroll, int* grid);
+int mips_set_config(mad_plan* plan, int chunk, int unroll, int grid);
+
+/* Autotuner: runs the batch (arguments as mips_topk_batch) under a set of
+ * launch shapes, `reps` timed replays each, keeps the fastest in the plan
+ * and reports its time per batch in *best_ms (host, optional).  Results
+ * are identical under every shape.  Synchronises. */
+int mips_autotune(mad_plan* plan, const float* Q, int64_t nq,
+                  const int64_t* s_per_query, const int64_t* tprime_per_query,
+                  int64_t t, uint64_t seed, mad_pair* out, int64_t* n_out,
+                  int reps, void* stream, double* best_ms);
+
+/* Statistics of the last batch (synchronises): n_pos[q] = |Omega_s| and
+ * n_cand[q] = verified candidates (host arrays of nq, optional), closed
+ * diamonds and distinct (query, i) keys over the batch. */
+int mips_stats(mad_plan* plan, int64_t* n_pos, int64_t* n_cand,
+               int64_t* closed, int64_t* distinct);
+
+/* Score table of query q after the last batch: keys i (device int64) and
+ * x_fix (device int64), capacity cap, unordered; *n (host) = count,
+ * *F (host) = the query's fixed-point exponent.  Synchronises. */
+int mips_debug_scores(mad_plan* plan, int64_t q, int64_t* keys, int64_t* xfix,
+                      int64_t cap, int64_t* n, int* F);
+
 /* Thread-local description of the last error (empty string if none). */
 const char* mad_last_error(void);
 

@@ -27,7 +27,9 @@ EXPORTS = (
     "mad_last_error", "mad_debug_table", "mad_debug_norms",
     "mad_debug_samples", "mad_debug_scores", "mad_debug_candidates",
     "mad_fix_exponent", "mad_plan_phase_ms", "mad_probe_memory",
-    "mad_bruteforce_topk",
+    "mad_bruteforce_topk", "mips_plan_create", "mips_topk_batch",
+    "mips_get_config", "mips_set_config", "mips_autotune", "mips_stats",
+    "mips_debug_scores",
 )
 
 
@@ -73,6 +75,16 @@ def lib():
         L.mad_probe_memory.argtypes = [C.c_int, _P, _i64, _i64, _u64, _P]
         L.mad_bruteforce_topk.argtypes = [_P, _i64, _P, _i64, _i64, C.c_int,
                                           _i64, _i64, _P, _P, _P, _P]
+        L.mips_plan_create.argtypes = [_P, _i64, _i64, _u32, _P,
+                                       C.POINTER(_P)]
+        L.mips_topk_batch.argtypes = [_P, _P, _i64, _P, _P, _i64, _u64, _P,
+                                      _P, _P]
+        L.mips_get_config.argtypes = [_P, _P, _P, _P]
+        L.mips_set_config.argtypes = [_P, C.c_int, C.c_int, C.c_int]
+        L.mips_autotune.argtypes = [_P, _P, _i64, _P, _P, _i64, _u64, _P, _P,
+                                    C.c_int, _P, _P]
+        L.mips_stats.argtypes = [_P, _P, _P, _P, _P]
+        L.mips_debug_scores.argtypes = [_P, _i64, _P, _P, _i64, _P, _P]
         _lib = L
     return _lib
 
@@ -262,6 +274,113 @@ class Plan:
         keys = keys[:n.value].cpu().numpy()
         o = np.argsort(keys, kind="stable")
         return keys[o], x[:n.value].cpu().numpy()[o], c[:n.value].cpu().numpy()[o]
+
+
+class MipsPlan(Plan):
+    """Owning handle of a MIPS plan: the database tables (A side of Alg. 2)
+    shared by batches of queries."""
+
+    @classmethod
+    def create(cls, A, flags=MAD_FLAG_NONE, stream=None):
+        import torch
+        m, d = A.shape
+        h = C.c_void_p()
+        _check(lib().mips_plan_create(_dev(A, torch.float32, "A"), m, d,
+                                      flags, _stream(stream), C.byref(h)))
+        return cls(h, (A,), m, 1, d)
+
+    @staticmethod
+    def _budgets(s, tp):
+        import numpy as np
+        s = np.ascontiguousarray(s, dtype=np.int64)
+        tp = np.ascontiguousarray(tp, dtype=np.int64)
+        return s, tp
+
+    def batch_raw(self, Q, s, tp, t, seed, out, n_out, stream=None):
+        """Enqueue mips_topk_batch: Q (nq, d) fp32, s / tp host int64
+        arrays, out (nq*t, 3) int64, n_out (nq,) int64."""
+        import torch
+        s, tp = self._budgets(s, tp)
+        nq = Q.shape[0]
+        self._keep_q = (Q, s, tp, out, n_out)
+        _check(lib().mips_topk_batch(
+            self._h, _dev(Q, torch.float32, "Q"), nq, s.ctypes.data_as(_P),
+            tp.ctypes.data_as(_P), t, seed, _dev(out, torch.int64, "out"),
+            _dev(n_out, torch.int64, "n_out"), _stream(stream)))
+
+    def batch(self, Q, s, tp, t, seed=0, stream=None):
+        """Synchronous batch: list of dicts (i, j, c, x) per query; a query
+        with non-finite values gives None."""
+        import torch
+        nq = Q.shape[0]
+        out = torch.empty((max(nq, 1) * t, 3), dtype=torch.int64,
+                          device="cuda")
+        n_out = torch.zeros(max(nq, 1), dtype=torch.int64, device="cuda")
+        self.batch_raw(Q, s, tp, t, seed, out, n_out, stream)
+        torch.cuda.synchronize()
+        cnt = n_out.cpu().tolist()
+        res = []
+        for q in range(nq):
+            if cnt[q] < 0:
+                res.append(None)
+            else:
+                res.append(unpack_pairs(out[q * t:(q + 1) * t], cnt[q]))
+        return res
+
+    def config(self):
+        c, u, g = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().mips_get_config(self._h, C.byref(c), C.byref(u),
+                                     C.byref(g)))
+        return dict(chunk=c.value, unroll=u.value, grid=g.value)
+
+    def set_config(self, chunk, unroll, grid):
+        _check(lib().mips_set_config(self._h, chunk, unroll, grid))
+
+    def autotune(self, Q, s, tp, t, seed=0, reps=2, stream=None):
+        import torch
+        s, tp = self._budgets(s, tp)
+        nq = Q.shape[0]
+        out = torch.empty((max(nq, 1) * t, 3), dtype=torch.int64,
+                          device="cuda")
+        n_out = torch.zeros(max(nq, 1), dtype=torch.int64, device="cuda")
+        best = C.c_double()
+        _check(lib().mips_autotune(
+            self._h, _dev(Q, torch.float32, "Q"), nq, s.ctypes.data_as(_P),
+            tp.ctypes.data_as(_P), t, seed, _dev(out, torch.int64, "out"),
+            _dev(n_out, torch.int64, "n_out"), reps, _stream(stream),
+            C.byref(best)))
+        return dict(self.config(), ms=best.value)
+
+    def mips_stats(self, nq):
+        import numpy as np
+        npos = np.zeros(max(nq, 1), np.int64)
+        ncand = np.zeros(max(nq, 1), np.int64)
+        cl, di = C.c_int64(), C.c_int64()
+        _check(lib().mips_stats(self._h, npos.ctypes.data_as(_P),
+                                ncand.ctypes.data_as(_P), C.byref(cl),
+                                C.byref(di)))
+        return dict(n_pos=npos[:nq], n_cand=ncand[:nq], closed=cl.value,
+                    distinct=di.value)
+
+    def query_scores(self, q):
+        """Score table of query q after the last batch: (keys i, x_fix)
+        sorted by key, and F."""
+        import numpy as np
+        import torch
+        n = C.c_int64()
+        F = C.c_int()
+        _check(lib().mips_debug_scores(self._h, q, None, None, 0, C.byref(n),
+                                       C.byref(F)))
+        cap = max(n.value, 1)
+        keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+        x = torch.empty(cap, dtype=torch.int64, device="cuda")
+        _check(lib().mips_debug_scores(self._h, q, C.c_void_p(keys.data_ptr()),
+                                       C.c_void_p(x.data_ptr()), cap,
+                                       C.byref(n), C.byref(F)))
+        keys = keys[:n.value].cpu().numpy()
+        x = x[:n.value].cpu().numpy()
+        o = np.argsort(keys, kind="stable")
+        return keys[o], x[o], F.value
 
 
 class BfStats(C.Structure):

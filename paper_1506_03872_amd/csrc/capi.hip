@@ -4,8 +4,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/mad.h"
 #include "mad_common.hpp"
@@ -55,8 +57,36 @@ int64_t next_pow2(int64_t v) {
 
 }  // namespace
 
+// MIPS batch state: per-query layout, workspace, the captured launch graph
+// and the tuned launch shape
+struct MipsState {
+  mad::Family T0q;  // stage-0 table per query (capacity nq_cap tables)
+  int64_t nq_cap = 0;
+  mad::DeviceBuffer qscratch, qinfo, order, chunks, hkeys, hvals, cx, ck, sx,
+      sk, sc, sab, qstats, ctr;
+  // layout of the prepared batch
+  std::vector<int64_t> s, tp;
+  int64_t nq = -1, t = -1;
+  int64_t hslots = 0, nchunks = 0;
+  int chunk_prepared = -1;
+  // launch shape (result-invariant)
+  int chunk = 4096, unroll = 4, grid = 2048;
+  // captured graph and what it was captured for
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const float* g_Q = nullptr;
+  const void* g_out = nullptr;
+  const void* g_nout = nullptr;
+  uint64_t g_seed = 0;
+  int g_chunk = -1, g_unroll = -1, g_grid = -1;
+  int64_t g_layout = -1;
+  int64_t layout_version = 0;
+  bool ran = false;
+};
+
 struct mad_plan {
-  int kind = 0;  // 0 dense
+  int kind = 0;  // 0 dense MAD, 1 MIPS database
   const float* A = nullptr;
   const float* B = nullptr;
   int64_t m = 0, n = 0, d = 0;
@@ -76,13 +106,30 @@ struct mad_plan {
   // start, 3 sampler start, 4 sampler end, 5 postprocessing end
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed_tables = false, timed_topk = false;
+  MipsState* mips = nullptr;
 };
+
+static void mips_free(MipsState* ms) {
+  if (!ms) return;
+  if (ms->exec) (void)hipGraphExecDestroy(ms->exec);
+  if (ms->graph) (void)hipGraphDestroy(ms->graph);
+  if (ms->cap_stream) (void)hipStreamDestroy(ms->cap_stream);
+  mad::family_free_pub(ms->T0q);
+  mad::DeviceBuffer* bufs[] = {&ms->qscratch, &ms->qinfo, &ms->order,
+                               &ms->chunks, &ms->hkeys, &ms->hvals, &ms->cx,
+                               &ms->ck, &ms->sx, &ms->sk, &ms->sc, &ms->sab,
+                               &ms->qstats, &ms->ctr};
+  for (mad::DeviceBuffer* b : bufs) mad::dev_free(*b);
+  delete ms;
+}
 
 static void record(mad_plan* p, int idx, hipStream_t st) {
   if (p->ev[idx]) (void)hipEventRecord(p->ev[idx], st);
 }
 
 static void plan_free_all(mad_plan* p) {
+  mips_free(p->mips);
+  p->mips = nullptr;
   mad::dense_tables_free(p->dt);
   mad::dev_free(p->build);
   mad::dev_free(p->hk);
@@ -232,6 +279,7 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
                   uint64_t seed, mad_pair* out, int64_t* n_out, void* stream) {
   g_err.clear();
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind != 0) return fail(MAD_EINVAL, "not a MAD plan (use mips_topk_batch)");
   if (!out || !n_out) return fail(MAD_EINVAL, "out and n_out are required");
   if (t < 1) return fail(MAD_EINVAL, "t must be >= 1");
   if (t_prime < t)
@@ -291,6 +339,7 @@ int mad_topk(const float* A, int64_t m, const float* B, int64_t n, int64_t d,
 int mad_plan_stats(mad_plan* p, double* wnorm, int64_t* closed,
                    int64_t* distinct, int64_t* n_pos, int64_t* n_cand) {
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind != 0) return fail(MAD_EINVAL, "not a MAD plan (use mips_stats)");
   HIP_TRY(hipDeviceSynchronize(), "stats");
   if (wnorm)
     HIP_TRY(hipMemcpy(wnorm, p->dt.T0.tot, sizeof(double),
@@ -380,6 +429,8 @@ int mad_debug_table(mad_plan* p, int which, int64_t idx, uint32_t* thr,
 int mad_debug_norms(mad_plan* p, double* na, double* nb, double* v,
                     double* om) {
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind == 1 && (nb || om))
+    return fail(MAD_EINVAL, "a MIPS plan has no nb or om");
   HIP_TRY(hipDeviceSynchronize(), "debug norms");
   if (na) HIP_TRY(hipMemcpy(na, p->dt.na, 8 * (size_t)p->m,
                             hipMemcpyDeviceToHost), "debug norms");
@@ -485,6 +536,448 @@ int mad_plan_create_csr(const int64_t*, const int32_t*, const float*, int64_t,
                         int64_t, uint32_t, void*, mad_plan** plan) {
   if (plan) *plan = nullptr;
   return fail(MAD_EUNSUPPORTED, "sparse plans are not built yet");
+}
+
+// ---------------------------------------------------------------------------
+// MIPS
+// ---------------------------------------------------------------------------
+int mips_plan_create(const float* A, int64_t m, int64_t d, uint32_t flags,
+                     void* stream, mad_plan** plan) {
+  g_err.clear();
+  if (!plan) return fail(MAD_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  if (m < 1 || d < 1)
+    return fail(MAD_EINVAL, "need m, d >= 1 (got %lld, %lld)", (long long)m,
+                (long long)d);
+  if (m >= (int64_t(1) << 31) || d > 4096)
+    return fail(m >= (int64_t(1) << 31) ? MAD_EINVAL : MAD_EUNSUPPORTED,
+                "MIPS needs m < 2^31 and d <= 4096");
+  if (!is_device_ptr(A)) return fail(MAD_EINVAL, "A must be a device pointer");
+  mad_plan* p = new (std::nothrow) mad_plan();
+  MipsState* ms = new (std::nothrow) MipsState();
+  if (!p || !ms) {
+    delete p;
+    delete ms;
+    return fail(MAD_ENOMEM, "host allocation failed");
+  }
+  p->kind = 1;
+  p->A = A;
+  p->B = nullptr;
+  p->m = m;
+  p->n = 1;
+  p->d = d;
+  p->flags = flags;
+  p->mips = ms;
+  hipError_t e = mad::dense_tables_alloc(p->dt, m, 1, d);
+  if (e == hipSuccess && (flags & MAD_FLAG_TIMING))
+    for (hipEvent_t& ev : p->ev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) break;
+  if (e == hipSuccess)
+    e = hipStreamCreateWithFlags(&ms->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    plan_free_all(p);
+    delete p;
+    return hip_fail(e, "allocating tables");
+  }
+  int rc = mad_plan_refresh(p, stream);
+  if (rc != MAD_OK) {
+    std::string keep = g_err;
+    (void)hipDeviceSynchronize();
+    plan_free_all(p);
+    delete p;
+    g_err = keep;
+    return rc;
+  }
+  *plan = p;
+  return MAD_OK;
+}
+
+static void mips_drop_graph(MipsState* ms) {
+  if (ms->exec) (void)hipGraphExecDestroy(ms->exec);
+  if (ms->graph) (void)hipGraphDestroy(ms->graph);
+  ms->exec = nullptr;
+  ms->graph = nullptr;
+}
+
+// Host layout of a batch: per-query regions, the chunk list (queries by
+// descending budget, chunks of ms->chunk samples) and the workspace.
+static int mips_prepare(mad_plan* p, int64_t nq, const int64_t* s,
+                        const int64_t* tp, int64_t t) {
+  MipsState* ms = p->mips;
+  const bool same = nq == ms->nq && t == ms->t &&
+                    ms->chunk_prepared == ms->chunk &&
+                    std::equal(s, s + nq, ms->s.begin()) &&
+                    std::equal(tp, tp + nq, ms->tp.begin());
+  if (same) return MAD_OK;
+  const int64_t m = p->m;
+  std::vector<mad::MipsQuery> qi((size_t)nq);
+  std::vector<int32_t> order((size_t)nq);
+  int64_t hs = 0, cs = 0, ss = 0;
+  for (int64_t q = 0; q < nq; ++q) {
+    mad::MipsQuery& x = qi[(size_t)q];
+    memset(&x, 0, sizeof x);
+    const int64_t sq = s[q];
+    const int64_t pairs = sq < m ? sq : m;
+    // a t' above the pairs or the samples cannot be used (as mad_plan_topk)
+    int64_t tpe = tp[q] < m ? tp[q] : m;
+    const int64_t sc1 = sq > 0 ? sq : 1;
+    if (tpe > sc1) tpe = sc1;
+    if (tpe < t) tpe = t;
+    const int64_t hcap = next_pow2(2 * (pairs > 512 ? pairs : 512));
+    x.s = sq;
+    x.tp = tpe;
+    x.hoff = hs;
+    x.hmask = (uint32_t)(hcap - 1);
+    x.coff = cs;
+    x.ccap = pairs > 1 ? pairs : 1;
+    x.soff = ss;
+    x.scap = x.ccap < tpe ? x.ccap : tpe;
+    hs += hcap;
+    cs += x.ccap;
+    ss += x.scap;
+    order[(size_t)q] = (int32_t)q;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return s[a] > s[b];
+  });
+  std::vector<mad::MipsChunk> ch;
+  for (int32_t q : order)
+    for (int64_t l0 = 0; l0 < s[q]; l0 += ms->chunk) {
+      mad::MipsChunk c;
+      c.q = q;
+      c.count = (int32_t)(s[q] - l0 < ms->chunk ? s[q] - l0 : ms->chunk);
+      c.l0 = l0;
+      ch.push_back(c);
+    }
+  (void)hipDeviceSynchronize();
+  mips_drop_graph(ms);
+  hipError_t e = hipSuccess;
+  if (nq > ms->nq_cap) {
+    mad::family_free_pub(ms->T0q);
+    e = mad::family_alloc_pub(ms->T0q, nq, p->d);
+    if (e != hipSuccess) return hip_fail(e, "allocating query tables");
+    ms->nq_cap = nq;
+  }
+  ms->T0q.S = nq;
+  const size_t qsb = mad::query_tables_scratch_bytes(nq, p->d);
+  const size_t nqa = (size_t)(nq > 0 ? nq : 1);
+  if ((e = mad::dev_alloc(ms->qscratch, qsb)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->qinfo, nqa * sizeof(mad::MipsQuery))) != hipSuccess ||
+      (e = mad::dev_alloc(ms->order, nqa * 4)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->chunks, (ch.size() + 1) * sizeof(mad::MipsChunk))) != hipSuccess ||
+      (e = mad::dev_alloc(ms->hkeys, (size_t)(hs + 2) * 4)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->hvals, (size_t)(hs + 1) * 8)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->cx, (size_t)(cs + 1) * 8)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->ck, (size_t)(cs + 1) * 4)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->sx, (size_t)(ss + 1) * 8)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->sk, (size_t)(ss + 1) * 4)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->sc, (size_t)(ss + 1) * 4)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->sab, (size_t)(ss + 1) * 8)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->qstats, nqa * sizeof(mad::MipsQueryStats))) != hipSuccess ||
+      (e = mad::dev_alloc(ms->ctr, sizeof(mad::SampleCounters))) != hipSuccess) {
+    ms->nq = -1;
+    return hip_fail(e, "allocating the MIPS workspace");
+  }
+  if (nq > 0) {
+    HIP_TRY(hipMemcpy(ms->qinfo.p, qi.data(), qi.size() * sizeof qi[0],
+                      hipMemcpyHostToDevice), "uploading the batch layout");
+    HIP_TRY(hipMemcpy(ms->order.p, order.data(), order.size() * 4,
+                      hipMemcpyHostToDevice), "uploading the batch layout");
+  }
+  if (!ch.empty())
+    HIP_TRY(hipMemcpy(ms->chunks.p, ch.data(), ch.size() * sizeof ch[0],
+                      hipMemcpyHostToDevice), "uploading the batch layout");
+  ms->s.assign(s, s + nq);
+  ms->tp.assign(tp, tp + nq);
+  ms->nq = nq;
+  ms->t = t;
+  ms->hslots = hs;
+  ms->nchunks = (int64_t)ch.size();
+  ms->chunk_prepared = ms->chunk;
+  ++ms->layout_version;
+  return MAD_OK;
+}
+
+static mad::MipsArgs mips_args(mad_plan* p, const float* Q, uint64_t seed,
+                               void* out, int64_t* n_out) {
+  MipsState* ms = p->mips;
+  mad::MipsArgs a;
+  a.T0q = ms->T0q.ent;
+  a.t0tot = ms->T0q.tot;
+  a.T1 = p->dt.T1.ent;
+  a.T3 = p->dt.T3.ent;
+  a.L0 = ms->T0q.L;
+  a.L1 = p->dt.T1.L;
+  a.L3 = p->dt.T3.L;
+  a.A = p->A;
+  a.Q = Q;
+  a.m = p->m;
+  a.d = p->d;
+  a.nq = ms->nq;
+  a.t = ms->t;
+  a.seed = seed;
+  a.qi = (const mad::MipsQuery*)ms->qinfo.p;
+  a.order = (const int32_t*)ms->order.p;
+  a.chunks = (const mad::MipsChunk*)ms->chunks.p;
+  a.nchunks = ms->nchunks;
+  a.hkeys = (uint32_t*)ms->hkeys.p;
+  a.hvals = (int64_t*)ms->hvals.p;
+  a.cx = (uint64_t*)ms->cx.p;
+  a.ck = (uint32_t*)ms->ck.p;
+  a.sx = (uint64_t*)ms->sx.p;
+  a.sk = (uint32_t*)ms->sk.p;
+  a.sc = (float*)ms->sc.p;
+  a.sab = (uint64_t*)ms->sab.p;
+  a.ctr = (mad::SampleCounters*)ms->ctr.p;
+  a.qstats = (mad::MipsQueryStats*)ms->qstats.p;
+  a.out = out;
+  a.n_out = n_out;
+  return a;
+}
+
+// the launch sequence of one batch (captured into a graph, or run eagerly
+// with phase events when the plan records timings)
+static hipError_t mips_enqueue(mad_plan* p, const mad::MipsArgs& a,
+                               hipStream_t st, bool events) {
+  MipsState* ms = p->mips;
+  hipError_t e;
+  if (events) record(p, 0, st);
+  if ((e = mad::launch_mips_query_info(a.Q, a.nq, a.d,
+                                       (mad::MipsQuery*)ms->qinfo.p, st)) !=
+          hipSuccess ||
+      (e = mad::query_tables_build(a.Q, a.nq, a.d, p->dt.v, ms->T0q,
+                                   ms->qscratch.p, ms->qscratch.bytes, st)) !=
+          hipSuccess)
+    return e;
+  if (events) {
+    record(p, 1, st);
+    record(p, 2, st);
+  }
+  if ((e = mad::launch_fill_u64((uint64_t*)ms->hkeys.p, (ms->hslots + 1) / 2,
+                                ~0ull, st)) != hipSuccess ||
+      (e = mad::launch_fill_u64((uint64_t*)ms->hvals.p, ms->hslots, 0ull,
+                                st)) != hipSuccess ||
+      (e = mad::launch_fill_u64((uint64_t*)ms->ctr.p, 8, 0ull, st)) !=
+          hipSuccess)
+    return e;
+  if (events) record(p, 3, st);
+  if ((e = mad::launch_sample_mips(a, ms->unroll, ms->grid, st)) != hipSuccess)
+    return e;
+  if (events) record(p, 4, st);
+  if ((e = mad::launch_mips_post(a, st)) != hipSuccess) return e;
+  if (events) record(p, 5, st);
+  return hipSuccess;
+}
+
+static int mips_check_batch(mad_plan* p, const float* Q, int64_t nq,
+                            const int64_t* s, const int64_t* tp, int64_t t,
+                            mad_pair* out, int64_t* n_out) {
+  if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  if (nq < 0 || nq >= (int64_t(1) << 31))
+    return fail(MAD_EINVAL, "need 0 <= nq < 2^31");
+  if (t < 1 || t > 1024 || t > p->m)
+    return fail(MAD_EINVAL, "need 1 <= t <= min(1024, m)");
+  if (nq == 0) return MAD_OK;
+  if (!s || !tp) return fail(MAD_EINVAL, "budgets are required");
+  if (!is_device_ptr(Q) || !is_device_ptr(out) || !is_device_ptr(n_out))
+    return fail(MAD_EINVAL, "Q, out and n_out must be device pointers");
+  for (int64_t q = 0; q < nq; ++q) {
+    if (s[q] < 0 || s[q] >= (int64_t(1) << 31))
+      return fail(MAD_EINVAL, "query %lld: need 0 <= s < 2^31", (long long)q);
+    if (tp[q] < t)
+      return fail(MAD_EINVAL, "query %lld: t' (%lld) < t (%lld)",
+                  (long long)q, (long long)tp[q], (long long)t);
+  }
+  return MAD_OK;
+}
+
+int mips_topk_batch(mad_plan* p, const float* Q, int64_t nq,
+                    const int64_t* s_per_query, const int64_t* tprime_per_query,
+                    int64_t t, uint64_t seed, mad_pair* out, int64_t* n_out,
+                    void* stream) {
+  g_err.clear();
+  int rc = mips_check_batch(p, Q, nq, s_per_query, tprime_per_query, t, out,
+                            n_out);
+  if (rc != MAD_OK || nq == 0) return rc;
+  MipsState* ms = p->mips;
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = mips_prepare(p, nq, s_per_query, tprime_per_query, t)) != MAD_OK)
+    return rc;
+  const mad::MipsArgs a = mips_args(p, Q, seed, out, n_out);
+  ms->ran = true;
+  if (p->flags & MAD_FLAG_TIMING) {  // eager, with phase events
+    HIP_TRY(mips_enqueue(p, a, st, true), "MIPS batch");
+    p->timed_tables = p->timed_topk = true;
+    return MAD_OK;
+  }
+  const bool fresh = ms->exec && ms->g_Q == Q && ms->g_out == out &&
+                     ms->g_nout == n_out && ms->g_seed == seed &&
+                     ms->g_chunk == ms->chunk && ms->g_unroll == ms->unroll &&
+                     ms->g_grid == ms->grid &&
+                     ms->g_layout == ms->layout_version;
+  if (!fresh) {
+    mips_drop_graph(ms);
+    HIP_TRY(hipStreamBeginCapture(ms->cap_stream,
+                                  hipStreamCaptureModeThreadLocal),
+            "capturing the MIPS batch");
+    hipError_t e = mips_enqueue(p, a, ms->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ms->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(e != hipSuccess ? e : e2, "capturing the MIPS batch");
+    }
+    ms->graph = g;
+    e = hipGraphInstantiate(&ms->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      mips_drop_graph(ms);
+      return hip_fail(e, "instantiating the MIPS graph");
+    }
+    ms->g_Q = Q;
+    ms->g_out = out;
+    ms->g_nout = n_out;
+    ms->g_seed = seed;
+    ms->g_chunk = ms->chunk;
+    ms->g_unroll = ms->unroll;
+    ms->g_grid = ms->grid;
+    ms->g_layout = ms->layout_version;
+  }
+  HIP_TRY(hipGraphLaunch(ms->exec, st), "launching the MIPS graph");
+  return MAD_OK;
+}
+
+int mips_get_config(mad_plan* p, int* chunk, int* unroll, int* grid) {
+  if (!p || p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  if (chunk) *chunk = p->mips->chunk;
+  if (unroll) *unroll = p->mips->unroll;
+  if (grid) *grid = p->mips->grid;
+  return MAD_OK;
+}
+
+int mips_set_config(mad_plan* p, int chunk, int unroll, int grid) {
+  if (!p || p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  if (chunk < 256 || chunk > (1 << 24) || (chunk & 255))
+    return fail(MAD_EINVAL, "chunk must be a multiple of 256 in [256, 2^24]");
+  if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+    return fail(MAD_EINVAL, "unroll must be 1, 2, 4 or 8");
+  if (grid < 1 || grid > (1 << 20)) return fail(MAD_EINVAL, "bad grid");
+  p->mips->chunk = chunk;
+  p->mips->unroll = unroll;
+  p->mips->grid = grid;
+  return MAD_OK;
+}
+
+int mips_autotune(mad_plan* p, const float* Q, int64_t nq,
+                  const int64_t* s_per_query, const int64_t* tprime_per_query,
+                  int64_t t, uint64_t seed, mad_pair* out, int64_t* n_out,
+                  int reps, void* stream, double* best_ms) {
+  g_err.clear();
+  int rc = mips_check_batch(p, Q, nq, s_per_query, tprime_per_query, t, out,
+                            n_out);
+  if (rc != MAD_OK) return rc;
+  if (nq == 0) return MAD_OK;
+  if (p->flags & MAD_FLAG_TIMING)
+    return fail(MAD_EINVAL, "autotune needs a plan without MAD_FLAG_TIMING");
+  if (reps < 1) reps = 1;
+  hipStream_t st = (hipStream_t)stream;
+  MipsState* ms = p->mips;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "autotune");
+  HIP_TRY(hipEventCreate(&e1), "autotune");
+  static const int chunks[] = {1024, 4096, 16384, 65536};
+  static const int unrolls[] = {2, 4, 8};
+  static const int grids[] = {1024, 2048, 4096};
+  double best = 1e300;
+  int bc = ms->chunk, bu = ms->unroll, bg = ms->grid;
+  auto trial = [&](int c, int u, int g) -> int {
+    ms->chunk = c;
+    ms->unroll = u;
+    ms->grid = g;
+    int r = mips_topk_batch(p, Q, nq, s_per_query, tprime_per_query, t, seed,
+                            out, n_out, stream);  // warm (and capture)
+    if (r != MAD_OK) return r;
+    HIP_TRY(hipEventRecord(e0, st), "autotune");
+    for (int k = 0; k < reps; ++k)
+      if ((r = mips_topk_batch(p, Q, nq, s_per_query, tprime_per_query, t,
+                               seed, out, n_out, stream)) != MAD_OK)
+        return r;
+    HIP_TRY(hipEventRecord(e1, st), "autotune");
+    HIP_TRY(hipEventSynchronize(e1), "autotune");
+    float ms_ = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms_, e0, e1), "autotune");
+    const double per = ms_ / reps;
+    if (per < best) {
+      best = per;
+      bc = c;
+      bu = u;
+      bg = g;
+    }
+    return MAD_OK;
+  };
+  // chunk and unroll at the default grid, then the grid
+  for (int c : chunks)
+    for (int u : unrolls)
+      if ((rc = trial(c, u, 2048)) != MAD_OK) break;
+  if (rc == MAD_OK)
+    for (int g : grids)
+      if (g != 2048 && (rc = trial(bc, bu, g)) != MAD_OK) break;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ms->chunk = bc;
+  ms->unroll = bu;
+  ms->grid = bg;
+  if (rc != MAD_OK) return rc;
+  if (best_ms) *best_ms = best;
+  return MAD_OK;
+}
+
+int mips_stats(mad_plan* p, int64_t* n_pos, int64_t* n_cand, int64_t* closed,
+               int64_t* distinct) {
+  if (!p || p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  MipsState* ms = p->mips;
+  if (!ms->ran) return fail(MAD_EINVAL, "no batch has run");
+  HIP_TRY(hipDeviceSynchronize(), "MIPS stats");
+  if (n_pos || n_cand) {
+    std::vector<mad::MipsQueryStats> qs((size_t)ms->nq);
+    HIP_TRY(hipMemcpy(qs.data(), ms->qstats.p, qs.size() * sizeof qs[0],
+                      hipMemcpyDeviceToHost), "MIPS stats");
+    for (int64_t q = 0; q < ms->nq; ++q) {
+      if (n_pos) n_pos[q] = qs[(size_t)q].n_pos;
+      if (n_cand) n_cand[q] = qs[(size_t)q].n_cand;
+    }
+  }
+  mad::SampleCounters sc;
+  HIP_TRY(hipMemcpy(&sc, ms->ctr.p, sizeof sc, hipMemcpyDeviceToHost),
+          "MIPS stats");
+  if (closed) *closed = (int64_t)sc.closed;
+  if (distinct) *distinct = (int64_t)sc.distinct;
+  return MAD_OK;
+}
+
+int mips_debug_scores(mad_plan* p, int64_t q, int64_t* keys, int64_t* xfix,
+                      int64_t cap, int64_t* n, int* F) {
+  if (!p || p->kind != 1 || !n) return fail(MAD_EINVAL, "MIPS plan and n are required");
+  MipsState* ms = p->mips;
+  if (!ms->ran) return fail(MAD_EINVAL, "no batch has run");
+  if (q < 0 || q >= ms->nq) return fail(MAD_EINVAL, "query out of range");
+  HIP_TRY(hipDeviceSynchronize(), "MIPS debug scores");
+  const mad::MipsArgs a = mips_args(p, nullptr, 0, nullptr, nullptr);
+  int64_t* cnt = (int64_t*)ms->ctr.p + 4;
+  HIP_TRY(mad::launch_mips_dump(a, q, keys, xfix, keys ? cap : 0, cnt, 0),
+          "MIPS debug scores");
+  HIP_TRY(hipDeviceSynchronize(), "MIPS debug scores");
+  int64_t total = 0;
+  HIP_TRY(hipMemcpy(&total, cnt, 8, hipMemcpyDeviceToHost), "MIPS debug scores");
+  *n = total;
+  if (F) {
+    mad::MipsQuery qi;
+    HIP_TRY(hipMemcpy(&qi, (const mad::MipsQuery*)ms->qinfo.p + q, sizeof qi,
+                      hipMemcpyDeviceToHost), "MIPS debug scores");
+    *F = qi.F;
+  }
+  if (keys && total > cap) return fail(MAD_EOVERFLOW, "capacity too small");
+  return MAD_OK;
 }
 
 }  // extern "C"

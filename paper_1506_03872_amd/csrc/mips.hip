@@ -1,0 +1,497 @@
+// mips.hip -- batched maximum inner product search (MIPS) with diamond
+// sampling.
+//
+// A MIPS query is the MAD problem with a single vector on the B side
+// (Sec. 2: a one-column matrix gives MIPS; Sec. 6 runs Alg. 2 once per
+// query column).  Query q with budget s_q is exactly the general plan with
+// B = {q}: the database tables T1 (i given k) and T3 (k' given i) are shared,
+// stage 0 draws k with weight |q_k| v_k from the query's own table, the j
+// draw of a one-vector B always returns 0 (its random word is still
+// consumed, so sample l of query q uses the Philox block with counter
+// (l, q, 0, 0) as in the general plan), the sign of b_kj is the sign of
+// q_k, and the fourth edge is q_k'.  Scores are keyed by i alone.
+//
+// Three launches serve a whole batch of queries with uneven budgets:
+//   k_mips_query_info   per query: fixed-point exponent, finiteness;
+//   k_sample_mips       persistent: workgroups walk a list of sample chunks
+//                       (contiguous l ranges of one query), with the query
+//                       row and its stage-0 table staged in LDS;
+//   k_mips_post         one workgroup per query (largest budgets first):
+//                       Alg. 3 on the query's score table -- keys with
+//                       x > 0, the t'_q largest (ties by i), fp32 dot
+//                       products, the t largest |c| (ties by i), in order.
+#include "mad_common.hpp"
+#include "plan.hpp"
+
+namespace mad {
+
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+constexpr int kPostThreads = 1024;
+constexpr int kPostWaves = kPostThreads / 64;
+constexpr int kSelBinsM = 2048;
+constexpr int kSelDigit = 11;
+constexpr int kMaxOutT = 1024;  // t per query
+
+// ---------------------------------------------------------------------------
+// per query: F from max |q_k| and s_q; live = all entries finite
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mips_query_info(const float* Q,
+                                                         int64_t nq,
+                                                         int64_t d,
+                                                         MipsQuery* qi) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wv;
+  if (q >= nq) return;
+  float mx = 0.0f;
+  int nonfinite = 0;
+  for (int64_t k = lane; k < d; k += 64) {
+    const float v = Q[q * d + k];
+    nonfinite |= !isfinite(v);
+    mx = fmaxf(mx, fabsf(v));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    nonfinite |= __shfl_xor(nonfinite, off, 64);
+  }
+  if (lane == 0) {
+    qi[q].F = fix_exponent(mx, qi[q].s);
+    qi[q].live = nonfinite ? 0 : 1;
+  }
+}
+
+hipError_t launch_mips_query_info(const float* Q, int64_t nq, int64_t d,
+                                  MipsQuery* qi, hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  k_mips_query_info<<<(unsigned)((nq + 3) / 4), 256, 0, st>>>(Q, nq, d, qi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sampling: a persistent grid over the chunk list
+// ---------------------------------------------------------------------------
+size_t mips_sample_lds_bytes(int L0, int64_t d) {
+  return ((size_t)8 << L0) + (size_t)4 * (size_t)d;
+}
+
+template <int U>
+__global__ __launch_bounds__(256) void k_sample_mips(MipsArgs a) {
+  extern __shared__ uint64_t sm[];
+  const int N0 = 1 << a.L0;
+  uint64_t* t0s = sm;
+  float* qs = (float*)(sm + N0);
+  unsigned long long nclosed = 0, ncreated = 0;
+  for (int64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+    const MipsChunk ch = a.chunks[c];
+    const MipsQuery qi = a.qi[ch.q];
+    if (!qi.live || !(a.t0tot[ch.q] > 0.0)) continue;  // uniform per block
+    __syncthreads();  // the previous chunk is done with the LDS copies
+    const uint64_t* t0g = a.T0q + ((int64_t)ch.q << a.L0);
+    for (int e = threadIdx.x; e < N0; e += blockDim.x) t0s[e] = t0g[e];
+    for (int64_t k = threadIdx.x; k < a.d; k += blockDim.x)
+      qs[k] = a.Q[(int64_t)ch.q * a.d + k];
+    __syncthreads();
+    uint32_t* hk = a.hkeys + qi.hoff;
+    int64_t* hv = a.hvals + qi.hoff;
+    const uint32_t hmask = qi.hmask;
+    for (int base = threadIdx.x; base < ch.count; base += 256 * U) {
+      uint32_t key[U], slot[U];
+      int64_t inc[U];
+      bool closed[U];
+      uint64_t e1[U], e3[U], U1[U], U3[U];
+      uint32_t sg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * 256;
+        const uint64_t l = (uint64_t)(ch.l0 + (e < ch.count ? e : 0));
+        const Philox4 r = philox4x64_10(l, (uint64_t)ch.q, 0ull, 0ull,
+                                        a.seed, 0ull);
+        const uint32_t s0 = slot_of(r.w0, a.L0);
+        const uint32_t k = draw_entry(t0s[s0], s0, r.w0).pos;
+        U1[u] = r.w1;
+        U3[u] = r.w3;
+        sg[u] = sign_bit(qs[k]);  // b_kj of the one-vector B is q_k
+        e1[u] = a.T1[((uint64_t)k << a.L1) + slot_of(r.w1, a.L1)];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const Drawn di = draw_entry(e1[u], slot_of(U1[u], a.L1), U1[u]);
+        key[u] = di.pos;
+        sg[u] ^= di.sgn;
+        e3[u] = a.T3[((uint64_t)di.pos << a.L3) + slot_of(U3[u], a.L3)];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const Drawn dk = draw_entry(e3[u], slot_of(U3[u], a.L3), U3[u]);
+        const float v = qs[dk.pos];
+        sg[u] ^= dk.sgn;
+        closed[u] = base + u * 256 < ch.count && v != 0.0f;
+        inc[u] = 0;
+        if (closed[u]) {
+          const int64_t mag = (int64_t)rint(ldexp((double)v, qi.F));
+          inc[u] = sg[u] ? -mag : mag;
+        }
+        slot[u] = (uint32_t)mix64(key[u]) & hmask;
+        nclosed += closed[u];
+      }
+      bool pend[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pend[u] = closed[u];
+      bool any = true;
+      while (any) {
+        uint32_t prev[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          prev[u] = pend[u] ? atomicCAS(hk + slot[u], kEmpty32, key[u]) : 0u;
+        any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (!pend[u]) continue;
+          if (prev[u] == kEmpty32 || prev[u] == key[u]) {
+            ncreated += prev[u] == kEmpty32;
+            pend[u] = false;
+          } else {
+            slot[u] = (slot[u] + 1) & hmask;
+            any = true;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (closed[u] && inc[u] != 0)
+          atomicAdd((unsigned long long*)(hv + slot[u]),
+                    (unsigned long long)inc[u]);
+    }
+  }
+  __shared__ unsigned long long part[2][4];
+  nclosed = wave_sum(nclosed);
+  ncreated = wave_sum(ncreated);
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = nclosed;
+    part[1][threadIdx.x >> 6] = ncreated;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long cc = part[0][0] + part[0][1] + part[0][2] +
+                                  part[0][3];
+    const unsigned long long dd = part[1][0] + part[1][1] + part[1][2] +
+                                  part[1][3];
+    if (cc) atomicAdd(&a.ctr->closed, cc);
+    if (dd) atomicAdd(&a.ctr->distinct, dd);
+  }
+}
+
+hipError_t launch_sample_mips(const MipsArgs& a, int unroll, int grid,
+                              hipStream_t st) {
+  if (a.nchunks <= 0) return hipSuccess;
+  const size_t lds = mips_sample_lds_bytes(a.L0, a.d);
+  int64_t g = grid < a.nchunks ? grid : a.nchunks;
+  if (g < 1) g = 1;
+  switch (unroll) {
+    case 1: k_sample_mips<1><<<(unsigned)g, 256, lds, st>>>(a); break;
+    case 2: k_sample_mips<2><<<(unsigned)g, 256, lds, st>>>(a); break;
+    case 8: k_sample_mips<8><<<(unsigned)g, 256, lds, st>>>(a); break;
+    default: k_sample_mips<4><<<(unsigned)g, 256, lds, st>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// postprocessing helpers (1024 threads)
+// ---------------------------------------------------------------------------
+struct PostShared {
+  unsigned h[kSelBinsM];
+  unsigned long long scan[kPostThreads];
+  unsigned wcnt[kPostWaves];
+  unsigned long long base;
+  int chosen;
+  unsigned long long before;
+};
+
+// Slot of this thread among the takers of one round of the whole block, in
+// thread order, after `ps.base`; advances ps.base by the round's count.
+__device__ int64_t block_take(bool take, PostShared& ps) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t ball = __ballot(take);
+  if (lane == 0) ps.wcnt[wv] = (unsigned)__popcll(ball);
+  __syncthreads();
+  unsigned before = 0, total = 0;
+  for (int w = 0; w < kPostWaves; ++w) {
+    const unsigned c = ps.wcnt[w];
+    before += w < wv ? c : 0u;
+    total += c;
+  }
+  const int64_t slot = (int64_t)ps.base + before +
+                       __popcll(ball & ((1ull << lane) - 1));
+  __syncthreads();
+  if (threadIdx.x == 0) ps.base += total;
+  __syncthreads();
+  return slot;
+}
+
+// Threshold of an exact selection of k of n elements by (primary desc,
+// key asc): the elements taken are those with take(p, key) true.  Digits
+// of kSelDigit bits, from bit `top` of the primary down, then the 32-bit
+// key.  Keys are unique, so the key phase always ends the search.
+struct SelThr {
+  uint64_t pp, pm;
+  uint32_t kp, km;
+  int key_phase;
+};
+
+__device__ __forceinline__ bool sel_take(uint64_t p, uint32_t kk,
+                                         const SelThr& s) {
+  const uint64_t pmv = p & s.pm;
+  if (pmv != s.pp) return pmv > s.pp;
+  if (!s.key_phase) return true;
+  return (kk & s.km) <= s.kp;
+}
+
+__device__ SelThr block_select(const uint64_t* prim, const uint32_t* key,
+                               int64_t n, int64_t k, int top,
+                               PostShared& ps) {
+  const int t = threadIdx.x;
+  SelThr s{0, 0, 0, 0, 0};
+  int64_t k_rem = k;
+  int shift = top - kSelDigit > 0 ? top - kSelDigit : 0;
+  bool done = k_rem >= n;
+  while (!done) {
+    for (int b = t; b < kSelBinsM; b += kPostThreads) ps.h[b] = 0;
+    __syncthreads();
+    for (int64_t e = t; e < n; e += kPostThreads) {
+      const uint64_t p = prim[e];
+      if ((p & s.pm) != s.pp) continue;
+      if (!s.key_phase) {
+        atomicAdd(&ps.h[(p >> shift) & (kSelBinsM - 1)], 1u);
+      } else {
+        const uint32_t kk = key[e];
+        if ((kk & s.km) != s.kp) continue;
+        atomicAdd(&ps.h[(kk >> shift) & (kSelBinsM - 1)], 1u);
+      }
+    }
+    __syncthreads();
+    // bins in selection order; thread t owns positions 2t, 2t + 1
+    const int b0 = s.key_phase ? 2 * t : kSelBinsM - 1 - 2 * t;
+    const int b1 = s.key_phase ? 2 * t + 1 : kSelBinsM - 2 - 2 * t;
+    const unsigned v0 = ps.h[b0], v1 = ps.h[b1];
+    ps.scan[t] = (unsigned long long)v0 + v1;
+    if (t == 0) ps.chosen = -1;
+    __syncthreads();
+    for (int off = 1; off < kPostThreads; off <<= 1) {
+      const unsigned long long o = t >= off ? ps.scan[t - off] : 0ull;
+      __syncthreads();
+      ps.scan[t] += o;
+      __syncthreads();
+    }
+    const unsigned long long excl = ps.scan[t] - v0 - v1;
+    if ((long long)excl < k_rem && (long long)(excl + v0) >= k_rem) {
+      ps.chosen = b0;
+      ps.before = excl;
+    } else if ((long long)(excl + v0) < k_rem &&
+               (long long)(excl + v0 + v1) >= k_rem) {
+      ps.chosen = b1;
+      ps.before = excl + v0;
+    }
+    __syncthreads();
+    const int b = ps.chosen;
+    const unsigned nbin = b >= 0 ? ps.h[b] : 0u;
+    const unsigned long long bef = ps.before;
+    __syncthreads();
+    if (b < 0) break;  // cannot happen while k_rem <= matching count
+    k_rem -= (int64_t)bef;
+    if (!s.key_phase) {
+      s.pp |= (uint64_t)b << shift;
+      s.pm |= (uint64_t)(kSelBinsM - 1) << shift;
+    } else {
+      s.kp |= (uint32_t)b << shift;
+      s.km |= (uint32_t)(kSelBinsM - 1) << shift;
+    }
+    if ((int64_t)nbin == k_rem) {
+      done = true;
+    } else if (shift == 0) {
+      if (s.key_phase) done = true;
+      s.key_phase = 1;
+      shift = 32 - kSelDigit;
+    } else {
+      shift = shift > kSelDigit ? shift - kSelDigit : 0;
+    }
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// post: one workgroup per query
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
+  extern __shared__ float qs[];  // the query row (d floats)
+  __shared__ PostShared ps;
+  __shared__ uint32_t fk[kMaxOutT];
+  __shared__ uint64_t fx[kMaxOutT];
+  __shared__ float fc[kMaxOutT];
+  const int t = threadIdx.x;
+  const int64_t q = a.order[blockIdx.x];
+  const MipsQuery qi = a.qi[q];
+  if (!qi.live || !(a.t0tot[q] > 0.0) || qi.s <= 0) {
+    if (t == 0) {
+      a.n_out[q] = qi.live ? 0 : -1;
+      a.qstats[q].n_pos = 0;
+      a.qstats[q].n_cand = 0;
+    }
+    return;
+  }
+  for (int64_t k = t; k < a.d; k += kPostThreads) qs[k] = a.Q[q * a.d + k];
+  // post1 (Omega_s): keys with x > 0, compacted in slot order
+  const uint32_t* hk = a.hkeys + qi.hoff;
+  const int64_t* hv = a.hvals + qi.hoff;
+  uint64_t* cx = a.cx + qi.coff;
+  uint32_t* ck = a.ck + qi.coff;
+  const int64_t cap = (int64_t)qi.hmask + 1;
+  if (t == 0) ps.base = 0;
+  __syncthreads();
+  for (int64_t r0 = 0; r0 < cap; r0 += kPostThreads) {
+    const int64_t e = r0 + t;
+    const uint32_t kk = e < cap ? hk[e] : kEmpty32;
+    const int64_t v = kk != kEmpty32 ? hv[e] : 0;
+    const bool take = v > 0;
+    const int64_t pos = block_take(take, ps);
+    if (take && pos < qi.ccap) {
+      cx[pos] = (uint64_t)v;
+      ck[pos] = kk;
+    }
+  }
+  int64_t npos = (int64_t)ps.base;
+  if (npos > qi.ccap) npos = qi.ccap;  // cannot happen: distinct <= s_q, m
+  // post1 (Omega_t'): the t'_q largest x, ties by i ascending
+  uint64_t* sx = a.sx + qi.soff;
+  uint32_t* sk = a.sk + qi.soff;
+  float* sc = a.sc + qi.soff;
+  uint64_t* sab = a.sab + qi.soff;
+  int64_t nsel = npos;
+  const bool cut = npos > qi.tp;
+  SelThr thr{0, 0, 0, 0, 0};
+  if (cut) {
+    thr = block_select(cx, ck, npos, qi.tp, 64, ps);
+    nsel = qi.tp;
+  }
+  __syncthreads();
+  if (t == 0) ps.base = 0;
+  __syncthreads();
+  for (int64_t r0 = 0; r0 < npos; r0 += kPostThreads) {
+    const int64_t e = r0 + t;
+    const bool live = e < npos;
+    const uint64_t p = live ? cx[e] : 0;
+    const uint32_t kk = live ? ck[e] : 0;
+    const bool take = live && (!cut || sel_take(p, kk, thr));
+    const int64_t pos = block_take(take, ps);
+    if (take && pos < qi.scap) {
+      sx[pos] = p;
+      sk[pos] = kk;
+    }
+  }
+  if (nsel > qi.scap) nsel = qi.scap;
+  __syncthreads();
+  // post2: c = a_i . q in fp32, one wave per candidate
+  const int lane = t & 63, wv = t >> 6;
+  for (int64_t e = wv; e < nsel; e += kPostWaves) {
+    const float* ar = a.A + (int64_t)sk[e] * a.d;
+    float acc = 0.0f;
+    for (int64_t k = lane; k < a.d; k += 64) acc = fmaf(ar[k], qs[k], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      sc[e] = acc;
+      sab[e] = __float_as_uint(fabsf(acc));
+    }
+  }
+  __syncthreads();
+  // post3: the t largest |c|, ties by i ascending
+  const int64_t tq = a.t < nsel ? a.t : nsel;
+  SelThr thr3{0, 0, 0, 0, 0};
+  const bool cut3 = nsel > tq;
+  if (cut3) thr3 = block_select(sab, sk, nsel, tq, 32, ps);
+  __syncthreads();
+  if (t == 0) ps.base = 0;
+  __syncthreads();
+  for (int64_t r0 = 0; r0 < nsel; r0 += kPostThreads) {
+    const int64_t e = r0 + t;
+    const bool live = e < nsel;
+    const uint64_t p = live ? sab[e] : 0;
+    const uint32_t kk = live ? sk[e] : 0;
+    const bool take = live && (!cut3 || sel_take(p, kk, thr3));
+    const int64_t pos = block_take(take, ps);
+    if (take && pos < tq) {
+      fk[pos] = kk;
+      fx[pos] = sx[e];
+      fc[pos] = sc[e];
+    }
+  }
+  __syncthreads();
+  // rank order (|c| desc, i asc) and output
+  struct Pair {
+    int64_t i, j;
+    float c, x;
+  };
+  Pair* o = (Pair*)a.out + q * a.t;
+  for (int64_t e = t; e < tq; e += kPostThreads) {
+    const float ae = fabsf(fc[e]);
+    const uint32_t ke = fk[e];
+    int64_t rank = 0;
+    for (int64_t u = 0; u < tq; ++u) {
+      const float au = fabsf(fc[u]);
+      rank += au > ae || (au == ae && fk[u] < ke);
+    }
+    Pair pr;
+    pr.i = (int64_t)ke;
+    pr.j = q;
+    pr.c = fc[e];
+    pr.x = (float)ldexp((double)(int64_t)fx[e], -qi.F);
+    o[rank] = pr;
+  }
+  if (t == 0) {
+    a.n_out[q] = tq;
+    a.qstats[q].n_pos = npos;
+    a.qstats[q].n_cand = nsel;
+  }
+}
+
+hipError_t launch_mips_post(const MipsArgs& a, hipStream_t st) {
+  if (a.nq <= 0) return hipSuccess;
+  if (a.t > kMaxOutT) return hipErrorInvalidValue;
+  k_mips_post<<<(unsigned)a.nq, kPostThreads, (size_t)4 * a.d, st>>>(a);
+  return hipGetLastError();
+}
+
+// every key of query q's score table, for parity checks
+__global__ void k_mips_dump(const uint32_t* hk, const int64_t* hv,
+                            int64_t cap, int64_t* keys, int64_t* xfix,
+                            int64_t out_cap, int64_t* count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cap;
+       e += stride) {
+    const uint32_t kk = hk[e];
+    if (kk == kEmpty32) continue;
+    const unsigned long long p = atomicAdd((unsigned long long*)count, 1ull);
+    if ((int64_t)p < out_cap) {
+      keys[p] = (int64_t)kk;
+      xfix[p] = hv[e];
+    }
+  }
+}
+
+hipError_t launch_mips_dump(const MipsArgs& a, int64_t q, int64_t* keys,
+                            int64_t* xfix, int64_t cap, int64_t* count,
+                            hipStream_t st) {
+  MipsQuery qi;
+  hipError_t e = hipMemcpy(&qi, a.qi + q, sizeof qi, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  if ((e = launch_fill_u64((uint64_t*)count, 1, 0ull, st)) != hipSuccess)
+    return e;
+  const int64_t hcap = (int64_t)qi.hmask + 1;
+  int64_t blocks = (hcap + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_mips_dump<<<(unsigned)blocks, 256, 0, st>>>(a.hkeys + qi.hoff,
+                                                a.hvals + qi.hoff, hcap, keys,
+                                                xfix, cap, count);
+  return hipGetLastError();
+}
+
+}  // namespace mad

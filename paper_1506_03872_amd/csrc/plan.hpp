@@ -63,6 +63,15 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
                               bool check, DeviceBuffer& scratch,
                               hipStream_t st);
 
+// MIPS: per-query stage-0 tables (S = nq tables over d coordinates, weight
+// |q_k| v_k); scratch only when 2^ceil(log2 d) > 512
+size_t query_tables_scratch_bytes(int64_t nq, int64_t d);
+hipError_t query_tables_build(const float* Q, int64_t nq, int64_t d,
+                              const double* v, Family& T0q, void* scratch,
+                              size_t scratch_bytes, hipStream_t st);
+hipError_t family_alloc_pub(Family& f, int64_t S, int64_t N);
+void family_free_pub(Family& f);
+
 // generic launchers reused by other files
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 
@@ -89,6 +98,75 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t count, int F, int32_t* k,
                                      int32_t* i, int32_t* j, int32_t* kp,
                                      int64_t* inc, hipStream_t st);
+
+// ---- mips.hip ------------------------------------------------------------
+// Per-query state of a MIPS batch.  The host fills everything but F and
+// live; k_mips_query_info fills those from the query vector.
+struct MipsQuery {
+  int64_t s;       // sample budget s_q
+  int64_t tp;      // candidate budget t'_q (>= t)
+  int64_t hoff;    // first slot of the query's score table
+  int64_t coff;    // first entry of its candidate list (capacity ccap)
+  int64_t ccap;    // min(s_q, m) (>= 1)
+  int64_t soff;    // first entry of its verified list (capacity scap)
+  int64_t scap;    // min(ccap, t'_q)
+  uint32_t hmask;  // table capacity - 1 (a power of two minus one)
+  int F;           // fixed-point exponent (device)
+  int live;        // 1: finite query (device)
+  int pad;
+};
+
+// a contiguous range of one query's samples
+struct MipsChunk {
+  int32_t q;
+  int32_t count;
+  int64_t l0;
+};
+
+// per-query results of the postprocessing (device)
+struct MipsQueryStats {
+  int64_t n_pos;   // |Omega_s|: keys with x > 0
+  int64_t n_cand;  // verified candidates
+};
+
+struct MipsArgs {
+  // database tables (A side of a dense plan) and the query stage-0 tables
+  const uint64_t* T0q;
+  const double* t0tot;
+  const uint64_t* T1;
+  const uint64_t* T3;
+  int L0, L1, L3;
+  const float* A;   // database, m x d
+  const float* Q;   // queries, nq x d
+  int64_t m, d, nq, t;
+  uint64_t seed;
+  const MipsQuery* qi;
+  const int32_t* order;  // queries by descending budget
+  const MipsChunk* chunks;
+  int64_t nchunks;
+  uint32_t* hkeys;
+  int64_t* hvals;
+  uint64_t* cx;  // candidate scores
+  uint32_t* ck;  // candidate keys (i)
+  uint64_t* sx;  // verified: scores
+  uint32_t* sk;  //           keys
+  float* sc;     //           c
+  uint64_t* sab; //           |c| bits
+  SampleCounters* ctr;
+  MipsQueryStats* qstats;
+  void* out;       // nq x t mad_pair
+  int64_t* n_out;  // nq
+};
+
+hipError_t launch_mips_query_info(const float* Q, int64_t nq, int64_t d,
+                                  MipsQuery* qi, hipStream_t st);
+hipError_t launch_sample_mips(const MipsArgs& a, int unroll, int grid,
+                              hipStream_t st);
+hipError_t launch_mips_post(const MipsArgs& a, hipStream_t st);
+hipError_t launch_mips_dump(const MipsArgs& a, int64_t q, int64_t* keys,
+                            int64_t* xfix, int64_t cap, int64_t* count,
+                            hipStream_t st);
+size_t mips_sample_lds_bytes(int L0, int64_t d);
 
 // ---- select.hip ----------------------------------------------------------
 struct SelectWork {

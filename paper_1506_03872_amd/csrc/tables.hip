@@ -52,6 +52,16 @@ struct WRowAbs {  // table per vector i over coordinates r: |X[i][r]|
   }
 };
 
+struct WQuery {  // MIPS stage 0 of query seg over coordinates r: |q_r| v_r
+  const float* Q;   // nq x d, row-major
+  int64_t d;
+  const double* v;  // d
+  __device__ double operator()(int64_t seg, int64_t r) const {
+    return fabs((double)Q[seg * d + r]) * v[r];
+  }
+  __device__ uint32_t sgn(int64_t, int64_t) const { return 0u; }
+};
+
 struct WExplicit {  // one table over explicit FP64 weights
   const double* w;
   __device__ double operator()(int64_t, int64_t r) const { return w[r]; }
@@ -977,9 +987,10 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
     k_scan_inputs<<<grid_for(m * d, 256 * 16) > 1024 ? 1024
                         : grid_for(m * d, 256 * 16), 256, 0, st>>>(
         A, m * d, nullptr, t.bad);
-  k_scan_inputs<<<grid_for(n * d, 256 * 16) > 1024 ? 1024
-                      : grid_for(n * d, 256 * 16), 256, 0, st>>>(
-      B, n * d, t.bmax, t.bad);
+  if (B)
+    k_scan_inputs<<<grid_for(n * d, 256 * 16) > 1024 ? 1024
+                        : grid_for(n * d, 256 * 16), 256, 0, st>>>(
+        B, n * d, t.bmax, t.bad);
 
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
   if (t.T3.L <= 9) {
@@ -997,6 +1008,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   if (e == hipSuccess)
     e = build_alias(q, t.T1.tot, d, t.T1.L, t.T1.ent, bsf, abuf, alias_bytes,
                     st);
+  // without B (MIPS) only the A side is built
+  if (e != hipSuccess || !B) return e;
   // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
   if (e == hipSuccess)
     e = col_quanta(B, d, nullptr, d, n, t.T2.L, t.T2.tot, q, Pbuf, runbuf,
@@ -1019,5 +1032,42 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   }
   return e;
 }
+
+// ---------------------------------------------------------------------------
+// MIPS stage-0 tables: one table per query over the d coordinates with
+// weight |q_k| v_k (a one-vector B has ||B_k*||_1 = |q_k|, so this is
+// nb_k v_k of the general plan).  Scratch is used only when 2^L > 512.
+// ---------------------------------------------------------------------------
+size_t query_tables_scratch_bytes(int64_t nq, int64_t d) {
+  const int L = ceil_log2_host(d);
+  if (L <= 9) return 0;
+  const int64_t slots = nq << L;
+  int64_t batch = slots < ((int64_t)1 << 26) ? slots : ((int64_t)1 << 26);
+  if (batch < ((int64_t)1 << L)) batch = (int64_t)1 << L;
+  return (size_t)slots * 8 + run_doubles(nq, d) * 8 +
+         alias_scratch_bytes(batch, batch / kAliasBlk) + 1024;
+}
+
+hipError_t query_tables_build(const float* Q, int64_t nq, int64_t d,
+                              const double* v, Family& T0q, void* scratch,
+                              size_t scratch_bytes, hipStream_t st) {
+  const WQuery w{Q, d, v};
+  if (T0q.L <= 9) return small_tables(w, nq, d, T0q.L, T0q.tot, T0q.ent, st);
+  char* p = (char*)scratch;
+  uint64_t* q = (uint64_t*)p; p += (size_t)(nq << T0q.L) * 8;
+  double* runbuf = (double*)p; p += run_doubles(nq, d) * 8;
+  const size_t used = (size_t)(p - (char*)scratch);
+  if (!scratch || scratch_bytes < used) return hipErrorInvalidValue;
+  hipError_t e = uniform_quanta(w, nq, d, T0q.L, T0q.tot, q, runbuf, st);
+  if (e != hipSuccess) return e;
+  return build_alias(q, T0q.tot, nq, T0q.L, T0q.ent, nullptr, p,
+                     scratch_bytes - used, st);
+}
+
+hipError_t family_alloc_pub(Family& f, int64_t S, int64_t N) {
+  return family_alloc(f, S, N);
+}
+
+void family_free_pub(Family& f) { family_free(f); }
 
 }  // namespace mad
