@@ -390,14 +390,30 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
   }
   if (nsel > qi.scap) nsel = qi.scap;
   __syncthreads();
-  // post2: c = a_i . q in fp32, one wave per candidate
-  const int lane = t & 63, wv = t >> 6;
-  for (int64_t e = wv; e < nsel; e += kPostWaves) {
-    const float* ar = a.A + (int64_t)sk[e] * a.d;
+  // post2: c = a_i . q in fp32; 16 lanes per candidate and 4 candidates
+  // per wave, rows read as float4 when d is a multiple of 4
+  const int lane = t & 63, wv = t >> 6, grp = lane >> 4, gl = lane & 15;
+  const bool vec = (a.d & 3) == 0 && ((uintptr_t)a.A & 15) == 0;
+  for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += kPostWaves * 4) {
+    const int64_t e = e0 + grp;
+    const bool ok = e < nsel;
+    const float* ar = a.A + (int64_t)sk[ok ? e : e0] * a.d;
     float acc = 0.0f;
-    for (int64_t k = lane; k < a.d; k += 64) acc = fmaf(ar[k], qs[k], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) {
+    if (vec) {
+      for (int64_t k = gl * 4; k < a.d; k += 64) {
+        const float4 x = *(const float4*)(ar + k);
+        const float4 y = *(const float4*)(qs + k);
+        acc = fmaf(x.x, y.x, acc);
+        acc = fmaf(x.y, y.y, acc);
+        acc = fmaf(x.z, y.z, acc);
+        acc = fmaf(x.w, y.w, acc);
+      }
+    } else {
+      for (int64_t k = gl; k < a.d; k += 16) acc = fmaf(ar[k], qs[k], acc);
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (ok && gl == 0) {
       sc[e] = acc;
       sab[e] = __float_as_uint(fabsf(acc));
     }
