@@ -110,6 +110,13 @@ def _dev(t, dtype, name):
     return C.c_void_p(t.data_ptr())
 
 
+def _dev_opt(t, dtype, name):
+    """_dev, allowing an empty tensor (null data pointer)."""
+    if t.numel() == 0:
+        return C.c_void_p(0)
+    return _dev(t, dtype, name)
+
+
 def unpack_pairs(raw, n):
     """mad_pair records (a (t, 3) int64 tensor) -> dict of i, j, c, x."""
     import torch
@@ -144,6 +151,21 @@ class Plan:
             _dev(A, torch.float32, "A"), m, _dev(B, torch.float32, "B"), n, d,
             flags, _stream(stream), C.byref(h)))
         return cls(h, (A, B), m, n, d)
+
+    @classmethod
+    def csr(cls, a, b, m, n, d, flags=MAD_FLAG_NONE, stream=None):
+        """Sparse plan: a = (ptr int64 m+1, idx int32, val fp32) CUDA tensors
+        of A's compressed rows, b likewise for B."""
+        import torch
+        (ap, ai, av), (bp, bi, bv) = a, b
+        h = C.c_void_p()
+        _check(lib().mad_plan_create_csr(
+            _dev(ap, torch.int64, "a_ptr"), _dev_opt(ai, torch.int32, "a_idx"),
+            _dev_opt(av, torch.float32, "a_val"), m,
+            _dev(bp, torch.int64, "b_ptr"), _dev_opt(bi, torch.int32, "b_idx"),
+            _dev_opt(bv, torch.float32, "b_val"), n, d, flags,
+            _stream(stream), C.byref(h)))
+        return cls(h, (a, b), m, n, d)
 
     def refresh(self, stream=None):
         _check(lib().mad_plan_refresh(self._h, _stream(stream)))

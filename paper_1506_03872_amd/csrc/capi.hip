@@ -86,12 +86,13 @@ struct MipsState {
 };
 
 struct mad_plan {
-  int kind = 0;  // 0 dense MAD, 1 MIPS database
+  int kind = 0;  // 0 dense MAD, 1 MIPS database, 2 sparse (CSR) MAD
   const float* A = nullptr;
   const float* B = nullptr;
   int64_t m = 0, n = 0, d = 0;
   uint32_t flags = 0;
   mad::DenseTables dt;
+  mad::CsrTables ct;
   mad::DeviceBuffer build;
   // workspace of mad_plan_topk
   mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc;
@@ -127,10 +128,20 @@ static void record(mad_plan* p, int idx, hipStream_t st) {
   if (p->ev[idx]) (void)hipEventRecord(p->ev[idx], st);
 }
 
+// per-kind accessors: stage-0 totals (||W||_1), max |b|
+static const double* plan_wtot(const mad_plan* p) {
+  return p->kind == 2 ? p->ct.T0.tot : p->dt.T0.tot;
+}
+
+static const float* plan_bmax(const mad_plan* p) {
+  return p->kind == 2 ? p->ct.bmax : p->dt.bmax;
+}
+
 static void plan_free_all(mad_plan* p) {
   mips_free(p->mips);
   p->mips = nullptr;
   mad::dense_tables_free(p->dt);
+  mad::csr_tables_free(p->ct);
   mad::dev_free(p->build);
   mad::dev_free(p->hk);
   mad::dev_free(p->hv);
@@ -211,6 +222,23 @@ int mad_plan_refresh(mad_plan* p, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const bool check = !(p->flags & MAD_FLAG_NO_CHECK);
   record(p, 0, st);
+  if (p->kind == 2) {
+    hipError_t e = mad::csr_tables_build(p->ct, check, st);
+    if (e == hipErrorInvalidValue) {
+      int bad = 0;
+      (void)hipMemcpy(&bad, p->ct.bad, sizeof bad, hipMemcpyDeviceToHost);
+      if (bad & 2)
+        return fail(MAD_EINVAL, "malformed CSR input (pointers not "
+                    "non-decreasing, or coordinates not strictly increasing "
+                    "within a vector and in [0, d))");
+      return fail(MAD_EINVAL, "A or B holds NaN or Inf");
+    }
+    if (e != hipSuccess) return hip_fail(e, "building sparse tables");
+    record(p, 1, st);
+    p->timed_tables = p->ev[0] != nullptr;
+    p->ran = false;
+    return MAD_OK;
+  }
   HIP_TRY(mad::dense_tables_build(p->dt, p->A, p->B, check, p->build, st),
           "building tables");
   record(p, 1, st);
@@ -279,7 +307,7 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
                   uint64_t seed, mad_pair* out, int64_t* n_out, void* stream) {
   g_err.clear();
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
-  if (p->kind != 0) return fail(MAD_EINVAL, "not a MAD plan (use mips_topk_batch)");
+  if (p->kind == 1) return fail(MAD_EINVAL, "not a MAD plan (use mips_topk_batch)");
   if (!out || !n_out) return fail(MAD_EINVAL, "out and n_out are required");
   if (t < 1) return fail(MAD_EINVAL, "t must be >= 1");
   if (t_prime < t)
@@ -305,12 +333,18 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   HIP_TRY(mad::launch_fill_u64((uint64_t*)p->ctr, 8, 0ull, st),
           "clearing counters");
   record(p, 3, st);
-  HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, p->h,
-                                   p->ctr, st),
-          "sampling");
+  if (p->kind == 2)
+    HIP_TRY(mad::launch_sample_csr(p->ct, seed, 0, 0, s, s, p->h, p->ctr, st),
+            "sampling");
+  else
+    HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, p->h,
+                                     p->ctr, st),
+            "sampling");
   record(p, 4, st);
-  HIP_TRY(mad::launch_postprocess(p->h, p->A, p->B, p->n, p->d, tp_eff, t,
-                                  p->dt.bmax, s, p->w, out, n_out, st),
+  HIP_TRY(mad::launch_postprocess(p->h, p->A, p->B,
+                                  p->kind == 2 ? &p->ct.in : nullptr, p->n,
+                                  p->d, tp_eff, t, plan_bmax(p), s, p->w, out,
+                                  n_out, st),
           "postprocessing");
   record(p, 5, st);
   p->timed_topk = p->ev[0] != nullptr;
@@ -339,10 +373,10 @@ int mad_topk(const float* A, int64_t m, const float* B, int64_t n, int64_t d,
 int mad_plan_stats(mad_plan* p, double* wnorm, int64_t* closed,
                    int64_t* distinct, int64_t* n_pos, int64_t* n_cand) {
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
-  if (p->kind != 0) return fail(MAD_EINVAL, "not a MAD plan (use mips_stats)");
+  if (p->kind == 1) return fail(MAD_EINVAL, "not a MAD plan (use mips_stats)");
   HIP_TRY(hipDeviceSynchronize(), "stats");
   if (wnorm)
-    HIP_TRY(hipMemcpy(wnorm, p->dt.T0.tot, sizeof(double),
+    HIP_TRY(hipMemcpy(wnorm, plan_wtot(p), sizeof(double),
                       hipMemcpyDeviceToHost), "stats");
   int64_t cnt[4] = {0, 0, 0, 0};
   mad::SampleCounters sc;
@@ -383,7 +417,7 @@ int mad_fix_exponent(mad_plan* p, int64_t s, int* F) {
   if (!p || !F) return fail(MAD_EINVAL, "plan and F are required");
   float bmax = 0.0f;
   HIP_TRY(hipDeviceSynchronize(), "fix exponent");
-  HIP_TRY(hipMemcpy(&bmax, p->dt.bmax, sizeof(float), hipMemcpyDeviceToHost),
+  HIP_TRY(hipMemcpy(&bmax, plan_bmax(p), sizeof(float), hipMemcpyDeviceToHost),
           "fix exponent");
   *F = mad::fix_exponent(bmax, s);
   return MAD_OK;
@@ -393,9 +427,36 @@ int mad_debug_table(mad_plan* p, int which, int64_t idx, uint32_t* thr,
                     uint32_t* alias, int32_t* item, int64_t cap,
                     int64_t* nslots) {
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind == 2 && which != 0) {
+    const mad::Ragged* R = which == 1 ? &p->ct.T1
+                         : which == 2 ? &p->ct.T2
+                         : which == 3 ? &p->ct.T3 : nullptr;
+    if (!R) return fail(MAD_EINVAL, "which must be 0..3");
+    if (idx < 0 || idx >= R->S) return fail(MAD_EINVAL, "table index out of range");
+    HIP_TRY(hipDeviceSynchronize(), "debug table");
+    uint64_t mt = 0;
+    HIP_TRY(hipMemcpy(&mt, R->meta + idx, 8, hipMemcpyDeviceToHost),
+            "debug table");
+    const int64_t Np = int64_t(1) << (mt >> 56);
+    if (nslots) *nslots = Np;
+    if (!thr && !alias && !item) return MAD_OK;
+    if (cap < Np) return fail(MAD_EINVAL, "capacity %lld < %lld slots",
+                              (long long)cap, (long long)Np);
+    std::vector<mad::Ent16> host((size_t)Np);
+    HIP_TRY(hipMemcpy(host.data(), R->ent + (mt & mad::kSlotMask),
+                      sizeof(mad::Ent16) * (size_t)Np, hipMemcpyDeviceToHost),
+            "debug table");
+    for (int64_t r = 0; r < Np; ++r) {
+      const mad::Ent16& x = host[(size_t)r];
+      if (thr) thr[r] = (uint32_t)x.w & mad::kLow31;
+      if (alias) alias[r] = x.alias;
+      if (item) item[r] = (int32_t)x.self;
+    }
+    return MAD_OK;
+  }
   const mad::Family* f;
   switch (which) {
-    case 0: f = &p->dt.T0; idx = 0; break;
+    case 0: f = p->kind == 2 ? &p->ct.T0 : &p->dt.T0; idx = 0; break;
     case 1: f = &p->dt.T1; break;
     case 2: f = &p->dt.T2; break;
     case 3: f = &p->dt.T3; break;
@@ -431,6 +492,18 @@ int mad_debug_norms(mad_plan* p, double* na, double* nb, double* v,
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
   if (p->kind == 1 && (nb || om))
     return fail(MAD_EINVAL, "a MIPS plan has no nb or om");
+  if (p->kind == 2) {
+    HIP_TRY(hipDeviceSynchronize(), "debug norms");
+    if (na) HIP_TRY(hipMemcpy(na, p->ct.T3.tot, 8 * (size_t)p->m,
+                              hipMemcpyDeviceToHost), "debug norms");
+    if (nb) HIP_TRY(hipMemcpy(nb, p->ct.T2.tot, 8 * (size_t)p->d,
+                              hipMemcpyDeviceToHost), "debug norms");
+    if (v) HIP_TRY(hipMemcpy(v, p->ct.T1.tot, 8 * (size_t)p->d,
+                             hipMemcpyDeviceToHost), "debug norms");
+    if (om) HIP_TRY(hipMemcpy(om, p->ct.om, 8 * (size_t)p->d,
+                              hipMemcpyDeviceToHost), "debug norms");
+    return MAD_OK;
+  }
   HIP_TRY(hipDeviceSynchronize(), "debug norms");
   if (na) HIP_TRY(hipMemcpy(na, p->dt.na, 8 * (size_t)p->m,
                             hipMemcpyDeviceToHost), "debug norms");
@@ -451,9 +524,14 @@ int mad_debug_samples(mad_plan* p, uint64_t seed, uint64_t qid, int64_t l0,
   if (count && (!k || !i || !j || !kp || !inc))
     return fail(MAD_EINVAL, "output arrays are required");
   hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(mad::launch_sample_dense_debug(p->dt, p->B, seed, qid, l0, count, F,
-                                         k, i, j, kp, inc, st),
-          "debug samples");
+  if (p->kind == 2)
+    HIP_TRY(mad::launch_sample_csr_debug(p->ct, seed, qid, l0, count, F, k, i,
+                                         j, kp, inc, st),
+            "debug samples");
+  else
+    HIP_TRY(mad::launch_sample_dense_debug(p->dt, p->B, seed, qid, l0, count,
+                                           F, k, i, j, kp, inc, st),
+            "debug samples");
   HIP_TRY(hipStreamSynchronize(st), "debug samples");
   return MAD_OK;
 }
@@ -531,11 +609,61 @@ int mad_bruteforce_topk(const float* A, int64_t m, const float* B, int64_t n,
   return MAD_OK;
 }
 
-int mad_plan_create_csr(const int64_t*, const int32_t*, const float*, int64_t,
-                        const int64_t*, const int32_t*, const float*, int64_t,
-                        int64_t, uint32_t, void*, mad_plan** plan) {
-  if (plan) *plan = nullptr;
-  return fail(MAD_EUNSUPPORTED, "sparse plans are not built yet");
+int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
+                        const float* a_val, int64_t m, const int64_t* b_ptr,
+                        const int32_t* b_idx, const float* b_val, int64_t n,
+                        int64_t d, uint32_t flags, void* stream,
+                        mad_plan** plan) {
+  g_err.clear();
+  if (!plan) return fail(MAD_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  if (m < 1 || n < 1 || d < 1 || m >= (int64_t(1) << 31) ||
+      n >= (int64_t(1) << 31) || d >= (int64_t(1) << 31))
+    return fail(MAD_EINVAL, "need 1 <= m, n, d < 2^31");
+  if (!is_device_ptr(a_ptr) || !is_device_ptr(b_ptr))
+    return fail(MAD_EINVAL, "CSR arrays must be device pointers");
+  int64_t nnzA = 0, nnzB = 0;
+  HIP_TRY(hipMemcpy(&nnzA, a_ptr + m, 8, hipMemcpyDeviceToHost), "reading nnz");
+  HIP_TRY(hipMemcpy(&nnzB, b_ptr + n, 8, hipMemcpyDeviceToHost), "reading nnz");
+  if (nnzA < 0 || nnzB < 0 || nnzA >= (int64_t(1) << 31) ||
+      nnzB >= (int64_t(1) << 31))
+    return fail(MAD_EINVAL, "need 0 <= nnz < 2^31 (a_ptr[m], b_ptr[n])");
+  if ((nnzA && (!is_device_ptr(a_idx) || !is_device_ptr(a_val))) ||
+      (nnzB && (!is_device_ptr(b_idx) || !is_device_ptr(b_val))))
+    return fail(MAD_EINVAL, "CSR arrays must be device pointers");
+  mad_plan* p = new (std::nothrow) mad_plan();
+  if (!p) return fail(MAD_ENOMEM, "host allocation failed");
+  p->kind = 2;
+  p->m = m;
+  p->n = n;
+  p->d = d;
+  p->flags = flags;
+  p->ct.m = m;
+  p->ct.n = n;
+  p->ct.d = d;
+  p->ct.nnzA = nnzA;
+  p->ct.nnzB = nnzB;
+  p->ct.in = mad::CsrView{a_ptr, a_idx, a_val, b_ptr, b_idx, b_val};
+  hipError_t e = hipSuccess;
+  if (flags & MAD_FLAG_TIMING)
+    for (hipEvent_t& ev : p->ev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) break;
+  if (e != hipSuccess) {
+    plan_free_all(p);
+    delete p;
+    return hip_fail(e, "creating events");
+  }
+  int rc = mad_plan_refresh(p, stream);
+  if (rc != MAD_OK) {
+    std::string keep = g_err;
+    (void)hipDeviceSynchronize();
+    plan_free_all(p);
+    delete p;
+    g_err = keep;
+    return rc;
+  }
+  *plan = p;
+  return MAD_OK;
 }
 
 // ---------------------------------------------------------------------------

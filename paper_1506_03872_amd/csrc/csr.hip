@@ -1,0 +1,1106 @@
+// csr.hip -- sparse inputs: vectors as compressed rows (coordinates
+// strictly increasing within a vector), the setting of the paper's graph and
+// rating experiments (Sec. 6).
+//
+// Preprocessing builds the same four stage distributions as the dense plan
+// (Alg. 2 line "dw" in the two-stage form), but over the non-zeros only:
+//   T3[i]  over the entries of a_i            weight |a_k'i|
+//   T1[k]  over the vectors i with an entry k weight |a_ki| na_i
+//   T2[k]  over the vectors j with an entry k weight |b_kj|
+//   T0     over the coordinates               weight ||B_k*||_1 v_k
+// T1 and T2 need, per coordinate, its vectors in ascending order: a stable
+// LSD radix sort of the entries by coordinate (4-bit digits) gives the
+// transposes.  Tables have 2^ceil(log2 N) slots of 16-byte entries that
+// carry the item ids, so a draw is one load.  Tables of at most 512 items
+// are built one wave per table; larger ones one workgroup per table
+// (two-level FP64 sums, integer quanta, then the alias lists and their
+// merge, as in the dense builder).
+//
+// The sampler draws k, i, j, k' as the dense one does and finds the fourth
+// edge b_k'j by binary search among the coordinates of b_j.
+#include <algorithm>
+#include <vector>
+
+#include "alias_common.hpp"
+#include "mad_common.hpp"
+#include "plan.hpp"
+
+namespace mad {
+
+static inline unsigned blocks_of(int64_t n, int per) {
+  int64_t g = (n + per - 1) / per;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+static inline int ceil_log2_i(int64_t N) {
+  int L = 0;
+  while ((int64_t(1) << L) < N) ++L;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// validation (one thread per vector): structure errors set bit 2 of *bad,
+// non-finite values bit 1; amax (optional) receives max |value|
+// ---------------------------------------------------------------------------
+__global__ void k_csr_check(const int64_t* ptr, const int32_t* idx,
+                            const float* val, int64_t rows, int64_t d,
+                            int64_t nnz, float* amax, int* bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float mx = 0.0f;
+  int flag = 0;
+  if (r < rows) {
+    const int64_t p0 = ptr[r], p1 = ptr[r + 1];
+    if (r == 0 && p0 != 0) flag |= 2;
+    if (p0 < 0 || p1 < p0 || p1 > nnz) {
+      flag |= 2;
+    } else {
+      int64_t prev = -1;
+      for (int64_t e = p0; e < p1; ++e) {
+        const int64_t k = idx[e];
+        const float v = val[e];
+        if (k <= prev || k >= d) flag |= 2;
+        prev = k;
+        if (!isfinite(v)) flag |= 1;
+        mx = fmaxf(mx, fabsf(v));
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    flag |= __shfl_xor(flag, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (flag) atomicOr(bad, flag);
+    else if (amax) atomicMax((unsigned int*)amax, __float_as_uint(mx));
+  }
+}
+
+// row id of every entry (one wave per vector)
+__global__ void k_row_ids(const int64_t* ptr, int64_t rows, uint32_t* rowid) {
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= rows) return;
+  for (int64_t e = ptr[r] + lane; e < ptr[r + 1]; e += 64)
+    rowid[e] = (uint32_t)r;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive prefix sums of u64 (tiles of 4096, recursive over tile sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 1024;
+constexpr int kScanTile = kScanThreads * 4;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(
+    const uint64_t* in, uint64_t* out, int64_t n, uint64_t* tile_sums) {
+  __shared__ uint64_t wsum[kScanThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * 4;
+  uint64_t v[4], sum = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    v[u] = base + u < n ? in[base + u] : 0ull;
+    sum += v[u];
+  }
+  const uint64_t inc = wave_incl_scan(sum);
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  uint64_t off = 0, all = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    off += w < wv ? wsum[w] : 0ull;
+    all += wsum[w];
+  }
+  uint64_t run = off + inc - sum;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (base + u < n) out[base + u] = run;
+    run += v[u];
+  }
+  if (t == 0) tile_sums[blockIdx.x] = all;
+}
+
+__global__ void k_scan_add(uint64_t* out, int64_t n, const uint64_t* offs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] += offs[e / kScanTile];
+}
+
+static size_t scan_tmp_words(int64_t n) {
+  size_t w = 0;
+  while (n > 1) {
+    n = (n + kScanTile - 1) / kScanTile;
+    w += (size_t)n;
+  }
+  return w + 1;
+}
+
+// in may equal out; tmp holds scan_tmp_words(n) words
+static hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n,
+                           uint64_t* tmp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  k_scan_tiles<<<(unsigned)nt, kScanThreads, 0, st>>>(in, out, n, tmp);
+  if (nt > 1) {
+    hipError_t e = scan_u64(tmp, tmp, nt, tmp + nt, st);
+    if (e != hipSuccess) return e;
+    k_scan_add<<<blocks_of(n, 256), 256, 0, st>>>(out, n, tmp);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (key, value) u32 pairs by key, 4-bit digits.
+// A tile of 4096 pairs is 256 threads x 16 consecutive pairs; per-thread
+// digit counts are 16-bit fields of four u64, so a block scan of the four
+// words ranks every pair after all pairs before it in input order.
+// ---------------------------------------------------------------------------
+constexpr int kRsThreads = 256;
+constexpr int kRsPer = 16;
+constexpr int kRsTile = kRsThreads * kRsPer;
+
+struct Cnt16 {
+  uint64_t c[4];
+};
+
+__device__ __forceinline__ void cnt_add(Cnt16& c, uint32_t dg) {
+  const uint64_t inc = 1ull << (16 * (dg & 3));
+  switch (dg >> 2) {
+    case 0: c.c[0] += inc; break;
+    case 1: c.c[1] += inc; break;
+    case 2: c.c[2] += inc; break;
+    default: c.c[3] += inc; break;
+  }
+}
+
+__device__ __forceinline__ uint32_t cnt_get(const Cnt16& c, int dg) {
+  uint64_t w;
+  switch (dg >> 2) {
+    case 0: w = c.c[0]; break;
+    case 1: w = c.c[1]; break;
+    case 2: w = c.c[2]; break;
+    default: w = c.c[3]; break;
+  }
+  return (uint32_t)(w >> (16 * (dg & 3))) & 0xFFFFu;
+}
+
+// block exclusive scan of the packed counts (256 threads); returns totals
+__device__ Cnt16 cnt_block_scan(Cnt16& v) {
+  __shared__ uint64_t ws[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  Cnt16 inc;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) inc.c[x] = wave_incl_scan(v.c[x]);
+  if (lane == 63)
+    for (int x = 0; x < 4; ++x) ws[wv][x] = inc.c[x];
+  __syncthreads();
+  Cnt16 all;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    uint64_t off = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wv ? ws[w][x] : 0ull;
+      tot += ws[w][x];
+    }
+    v.c[x] = off + inc.c[x] - v.c[x];
+    all.c[x] = tot;
+  }
+  __syncthreads();
+  return all;
+}
+
+__device__ __forceinline__ Cnt16 tile_counts(const uint32_t* key, int64_t n,
+                                             int shift, int64_t base) {
+  Cnt16 c{{0, 0, 0, 0}};
+#pragma unroll
+  for (int u = 0; u < kRsPer; ++u)
+    if (base + u < n) cnt_add(c, (key[base + u] >> shift) & 15u);
+  return c;
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_count(const uint32_t* key,
+                                                         int64_t n, int shift,
+                                                         uint64_t* counts,
+                                                         int64_t ntiles) {
+  const int64_t base =
+      (int64_t)blockIdx.x * kRsTile + (int64_t)threadIdx.x * kRsPer;
+  Cnt16 c = tile_counts(key, n, shift, base);
+  const Cnt16 all = cnt_block_scan(c);
+  if (threadIdx.x < 16)
+    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] =
+        cnt_get(all, threadIdx.x);
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const uint32_t* kin, const uint32_t* vin, int64_t n, int shift,
+    const uint64_t* offs, int64_t ntiles, uint32_t* kout, uint32_t* vout) {
+  __shared__ uint32_t pos[kRsThreads][17];
+  __shared__ uint64_t tbase[16];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)t * kRsPer;
+  if (t < 16) tbase[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+  Cnt16 c = tile_counts(kin, n, shift, base);
+  (void)cnt_block_scan(c);  // c := this thread's exclusive prefix
+#pragma unroll
+  for (int dg = 0; dg < 16; ++dg)
+    pos[t][dg] = (uint32_t)(tbase[dg] + cnt_get(c, dg));
+  for (int u = 0; u < kRsPer; ++u) {
+    const int64_t e = base + u;
+    if (e >= n) break;
+    const uint32_t k = kin[e];
+    const uint32_t dg = (k >> shift) & 15u;
+    const uint32_t p = pos[t][dg]++;
+    kout[p] = k;
+    vout[p] = vin[e];
+  }
+}
+
+__global__ void k_sort_init(const int32_t* idx, int64_t n, uint32_t* key,
+                            uint32_t* val) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) {
+    key[e] = (uint32_t)idx[e];
+    val[e] = (uint32_t)e;
+  }
+}
+
+// tptr[k] = first sorted position with key >= k, for k in [0, d]
+__global__ void k_lower_bound(const uint32_t* key, int64_t n, int64_t d,
+                              int64_t* tptr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > d) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < k) lo = mid + 1; else hi = mid;
+  }
+  tptr[k] = lo;
+}
+
+__global__ void k_trans_gather(const uint32_t* pos, const uint32_t* rowid,
+                               const float* val, int64_t n, uint32_t* trow,
+                               float* tval) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) {
+    const uint32_t e = pos[p];
+    trow[p] = rowid[e];
+    tval[p] = val[e];
+  }
+}
+
+struct SortBufs {
+  uint32_t* k0;
+  uint32_t* k1;
+  uint32_t* v0;
+  uint32_t* v1;
+  uint32_t* rowid;
+  uint64_t* counts;  // 16 * tiles
+  uint64_t* tmp;     // scan scratch
+};
+
+static size_t sort_bytes(int64_t nnz) {
+  const int64_t tiles = (nnz + kRsTile - 1) / kRsTile;
+  return (size_t)nnz * 4 * 5 + (size_t)(16 * tiles + 1) * 8 +
+         scan_tmp_words(16 * tiles) * 8 + 1024;
+}
+
+static SortBufs sort_carve(void* p, int64_t nnz) {
+  const int64_t tiles = (nnz + kRsTile - 1) / kRsTile;
+  char* c = (char*)p;
+  SortBufs b;
+  auto take = [&](size_t bytes) {
+    char* r = c;
+    c += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  b.k0 = (uint32_t*)take((size_t)nnz * 4);
+  b.k1 = (uint32_t*)take((size_t)nnz * 4);
+  b.v0 = (uint32_t*)take((size_t)nnz * 4);
+  b.v1 = (uint32_t*)take((size_t)nnz * 4);
+  b.rowid = (uint32_t*)take((size_t)nnz * 4);
+  b.counts = (uint64_t*)take((size_t)(16 * tiles + 1) * 8);
+  b.tmp = (uint64_t*)take(scan_tmp_words(16 * tiles) * 8);
+  return b;
+}
+
+// the transpose of one input: tptr (d + 1), trow, tval (nnz)
+static hipError_t csr_transpose(const int64_t* ptr, const int32_t* idx,
+                                const float* val, int64_t rows, int64_t d,
+                                int64_t nnz, int64_t* tptr, uint32_t* trow,
+                                float* tval, SortBufs b, hipStream_t st) {
+  if (nnz > 0) {
+    k_row_ids<<<blocks_of(rows * 64, 256), 256, 0, st>>>(ptr, rows, b.rowid);
+    k_sort_init<<<blocks_of(nnz, 256), 256, 0, st>>>(idx, nnz, b.k0, b.v0);
+    const int bits = ceil_log2_i(d);
+    const int passes = bits > 0 ? (bits + 3) / 4 : 1;
+    const int64_t tiles = (nnz + kRsTile - 1) / kRsTile;
+    uint32_t *ka = b.k0, *va = b.v0, *kb = b.k1, *vb = b.v1;
+    for (int ps = 0; ps < passes; ++ps) {
+      k_rs_count<<<(unsigned)tiles, kRsThreads, 0, st>>>(ka, nnz, 4 * ps,
+                                                         b.counts, tiles);
+      hipError_t e = scan_u64(b.counts, b.counts, 16 * tiles, b.tmp, st);
+      if (e != hipSuccess) return e;
+      k_rs_scatter<<<(unsigned)tiles, kRsThreads, 0, st>>>(
+          ka, va, nnz, 4 * ps, b.counts, tiles, kb, vb);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
+    k_trans_gather<<<blocks_of(nnz, 256), 256, 0, st>>>(va, b.rowid, val, nnz,
+                                                        trow, tval);
+    k_lower_bound<<<blocks_of(d + 1, 256), 256, 0, st>>>(ka, nnz, d, tptr);
+  } else {
+    k_lower_bound<<<blocks_of(d + 1, 256), 256, 0, st>>>(nullptr, 0, d, tptr);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// weight / sign / item functors over item positions p
+// ---------------------------------------------------------------------------
+struct RowItems {  // T3: entries of a_i; item = coordinate
+  const float* val;
+  const int32_t* idx;
+  __device__ double w(int64_t p) const { return fabs((double)val[p]); }
+  __device__ uint32_t sgn(int64_t p) const { return sign_bit(val[p]); }
+  __device__ uint32_t item(int64_t p) const { return (uint32_t)idx[p]; }
+};
+
+struct ColItems {  // T1 / T2: vectors with an entry at k; item = vector
+  const float* tval;
+  const uint32_t* trow;
+  const double* scale;  // na for T1, null for T2
+  __device__ double w(int64_t p) const {
+    const double a = fabs((double)tval[p]);
+    return scale ? a * scale[trow[p]] : a;
+  }
+  __device__ uint32_t sgn(int64_t p) const { return sign_bit(tval[p]); }
+  __device__ uint32_t item(int64_t p) const { return trow[p]; }
+};
+
+template <class W>
+struct EmitItems {
+  Ent16* et;
+  W w;
+  int64_t o;
+  int64_t N;
+  __device__ void operator()(int r, uint32_t thr, uint32_t ss, uint32_t al,
+                             uint32_t sa) const {
+    Ent16 e;
+    e.w = pack_entry(thr, ss, al, sa);
+    e.self = r < N ? w.item(o + r) : 0u;
+    e.alias = w.item(o + (int64_t)al);
+    et[r] = e;
+  }
+};
+
+__device__ __forceinline__ int spl_of(int L) {
+  return L <= 6 ? 1 : (L == 7 ? 2 : (L == 8 ? 4 : 8));
+}
+
+// ---------------------------------------------------------------------------
+// tables of at most 512 items: one wave per table; a launch serves the
+// tables whose slots need SPL slots per lane (every wave of the block
+// still calls wave_alias, which synchronises the block)
+// ---------------------------------------------------------------------------
+template <int SPL, class W>
+__global__ __launch_bounds__(256) void k_ragged_small(W w, const int64_t* off,
+                                                      const uint64_t* meta,
+                                                      int64_t S, double* tot,
+                                                      Ent16* ent) {
+  extern __shared__ uint64_t smem64[];
+  constexpr int NpMax = 64 * SPL;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t segc = seg < S ? seg : S - 1;
+  const uint64_t mt = meta[segc];
+  const int L = (int)(mt >> 56);
+  const int64_t so = (int64_t)(mt & kSlotMask);
+  const int64_t o = off[segc];
+  const int64_t N64 = off[segc + 1] - o;
+  const bool mine = seg < S && N64 <= 512 && spl_of(L) == SPL;
+  const int N = mine ? (int)N64 : 0;
+  const int Np = 1 << L;
+  double P[SPL];
+  uint32_t sg[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    P[s] = r < N ? w.w(o + r) : 0.0;
+    sg[s] = r < N ? w.sgn(o + r) : 0u;
+  }
+  // left-to-right prefix: lane k adds its items to the sum of lanes < k
+  const int last_lane = N > 0 ? (N - 1) / SPL : 0;
+  double carry = 0.0;
+  for (int k = 0; k <= last_lane; ++k) {
+    if (lane == k) {
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        carry = carry + P[s];
+        P[s] = carry;
+      }
+    }
+    carry = readlane_f64(carry, k);
+  }
+  const double T = carry;
+  if (mine && lane == 0) tot[seg] = T;
+  const bool active = mine && T > 0.0;
+  const int K = L + kCapBits;
+  uint64_t F[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    F[s] = active && r < N ? (uint64_t)floor(ldexp(P[s] / T, K)) : 0ull;
+  }
+  const uint64_t Fin = __shfl_up(F[SPL - 1], 1, 64);
+  uint64_t qv[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int r = lane * SPL + s;
+    const uint64_t Fp = s > 0 ? F[s - 1] : (lane > 0 ? Fin : 0ull);
+    qv[s] = active && r < N ? F[s] - Fp : 0ull;
+  }
+  if (mine && !active)  // dead table: never sampled, entries zero
+    for (int r = lane; r < Np; r += 64) ent[so + r] = Ent16{0ull, 0u, 0u};
+  wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * NpMax,
+                  smem64 + (int64_t)wv * 2 * NpMax + NpMax,
+                  (uint32_t*)(smem64 + 8 * NpMax) + (int64_t)wv * NpMax,
+                  EmitItems<W>{ent + so, w, o, N});
+}
+
+// ---------------------------------------------------------------------------
+// tables of more than 512 items: one workgroup (512 threads) per table
+// ---------------------------------------------------------------------------
+constexpr int kBigThreads = 512;
+constexpr int kBigWaves = kBigThreads / 64;
+
+struct BigScratch {
+  uint64_t* Lb;  // run-local prefix bits (sign in bit 63), per slot
+  uint64_t* q;   // quanta (sign in bit 63), per slot
+  uint64_t* Ld;  // light deficit prefixes (exclusive)
+  uint64_t* He;  // heavy excess prefixes (inclusive)
+  uint32_t* Li;  // light slot ids (sign in bit 31)
+  uint32_t* Hi;  // heavy slot ids (sign in bit 31)
+  double* E;     // run offsets
+};
+
+// block-wide exclusive scan of a Quad over the workgroup; returns the total
+__device__ Quad block_excl_scan_big(Quad& v) {
+  __shared__ Quad wt[kBigWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  Quad inc{wave_incl_scan(v.nl), wave_incl_scan(v.nh), wave_incl_scan(v.sd),
+           wave_incl_scan(v.se)};
+  if (lane == 63) wt[wv] = inc;
+  __syncthreads();
+  Quad off{0, 0, 0, 0}, all{0, 0, 0, 0};
+  for (int w = 0; w < kBigWaves; ++w) {
+    const Quad x = wt[w];
+    if (w < wv) {
+      off.nl += x.nl; off.nh += x.nh; off.sd += x.sd; off.se += x.se;
+    }
+    all.nl += x.nl; all.nh += x.nh; all.sd += x.sd; all.se += x.se;
+  }
+  __syncthreads();
+  v = Quad{off.nl + inc.nl - v.nl, off.nh + inc.nh - v.nh,
+           off.sd + inc.sd - v.sd, off.se + inc.se - v.se};
+  return all;
+}
+
+template <class W>
+__global__ __launch_bounds__(kBigThreads) void k_ragged_big(
+    W w, const int64_t* off, const uint64_t* meta, const uint32_t* bigids,
+    const int64_t* runoff, double* tot, Ent16* ent, BigScratch sc) {
+  __shared__ double sT;
+  const int t = threadIdx.x;
+  const uint32_t s = bigids[blockIdx.x];
+  const int64_t o = off[s];
+  const int64_t N = off[s + 1] - o;
+  const uint64_t mt = meta[s];
+  const int L = (int)(mt >> 56);
+  const int64_t so = (int64_t)(mt & kSlotMask);
+  const int64_t Np = int64_t(1) << L;
+  const int64_t R = (N + kRun - 1) / kRun;
+  double* E = sc.E + runoff[blockIdx.x];  // R + 1 entries
+  uint64_t* Lb = sc.Lb + so;
+  uint64_t* q = sc.q + so;
+  uint64_t* Ld = sc.Ld + so;
+  uint64_t* He = sc.He + so;
+  uint32_t* Li = sc.Li + so;
+  uint32_t* Hi = sc.Hi + so;
+  Ent16* et = ent + so;
+  // run-local prefixes, one thread per run, loads 8 at a time
+  for (int64_t c = t; c < R; c += kBigThreads) {
+    const int64_t r0 = c * kRun;
+    const int64_t r1 = r0 + kRun < N ? r0 + kRun : N;
+    double l = 0.0;
+    for (int64_t r = r0; r < r1; r += 8) {
+      double wv[8];
+      uint32_t sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t rr = r + u < r1 ? r + u : r1 - 1;
+        wv[u] = w.w(o + rr);
+        sv[u] = w.sgn(o + rr);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (r + u < r1) {
+          l = l + wv[u];
+          Lb[r + u] = (uint64_t)__double_as_longlong(l) |
+                      ((uint64_t)sv[u] << 63);
+        }
+      }
+    }
+    E[c + 1] = l;  // run total, turned into the offset below
+  }
+  __syncthreads();
+  if (t == 0) {  // E_0 = 0, E_{c+1} = E_c + S_c, left to right
+    double acc = 0.0;
+    E[0] = 0.0;
+    for (int64_t c = 0; c < R; ++c) {
+      acc = acc + E[c + 1];
+      E[c + 1] = acc;
+    }
+    tot[s] = acc;
+    sT = acc;
+  }
+  __syncthreads();
+  const double T = sT;
+  if (!(T > 0.0)) {  // dead table: never sampled, entries zero
+    for (int64_t r = t; r < Np; r += kBigThreads) et[r] = Ent16{0ull, 0u, 0u};
+    return;
+  }
+  // quanta
+  const int K = L + kCapBits;
+  for (int64_t r = t; r < Np; r += kBigThreads) {
+    uint64_t qq = 0;
+    if (r < N) {
+      const uint64_t raw = Lb[r];
+      const double Pv = E[r / kRun] +
+                        __longlong_as_double((long long)(raw & kQMask));
+      const uint64_t F = (uint64_t)floor(ldexp(Pv / T, K));
+      uint64_t Fp = 0;
+      if (r > 0) {
+        const double Pp = E[(r - 1) / kRun] +
+                          __longlong_as_double((long long)(Lb[r - 1] & kQMask));
+        Fp = (uint64_t)floor(ldexp(Pp / T, K));
+      }
+      qq = (F - Fp) | (raw & ~kQMask);
+    }
+    q[r] = qq;
+  }
+  __syncthreads();
+  // light and heavy lists in slot order, 4 slots per thread per round
+  Quad carry{0, 0, 0, 0};
+  for (int64_t base = 0; base < Np; base += 4 * kBigThreads) {
+    const int64_t r0 = base + (int64_t)t * 4;
+    uint64_t qv[4];
+    uint32_t sg[4];
+    Quad a{0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t raw = r0 + u < Np ? q[r0 + u] : 0ull;
+      qv[u] = raw & kQMask;
+      sg[u] = (uint32_t)(raw >> 63);
+      if (r0 + u < Np) slot_stats(qv[u], a);
+    }
+    const Quad all = block_excl_scan_big(a);
+    uint64_t lp = carry.nl + a.nl, hp = carry.nh + a.nh;
+    uint64_t da = carry.sd + a.sd, ea = carry.se + a.se;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (r0 + u >= Np) continue;
+      const uint32_t id = (uint32_t)(r0 + u) | (sg[u] << 31);
+      if (qv[u] < kCap) {
+        Ld[lp] = da;
+        Li[lp] = id;
+        da += kCap - qv[u];
+        ++lp;
+      } else {
+        ea += qv[u] - kCap;
+        He[hp] = ea;
+        Hi[hp] = id;
+        ++hp;
+      }
+    }
+    carry.nl += all.nl;
+    carry.nh += all.nh;
+    carry.sd += all.sd;
+    carry.se += all.se;
+  }
+  __syncthreads();
+  const int64_t NL = (int64_t)carry.nl, NH = (int64_t)carry.nh;
+  const uint64_t Dt = carry.sd;
+  // merge: each thread Np / kBigThreads consecutive merged positions
+  const int64_t per = Np / kBigThreads;
+  const int64_t d0 = (int64_t)t * per;
+  int64_t a = merge_split(Ld, NL, He, NH, d0), b = d0 - a;
+  const EmitItems<W> emit{et, w, o, N};
+  for (int64_t step = 0; step < per; ++step) {
+    if (a < NL && (b >= NH || Ld[a] <= He[b])) {
+      const uint32_t id = Li[a];
+      const uint32_t r = id & kLow31;
+      const uint64_t Dn = a + 1 < NL ? Ld[a + 1] : Dt;
+      const uint32_t qv = (uint32_t)(kCap - (Dn - Ld[a]));
+      const uint32_t dn = b < NH ? Hi[b] : id;
+      emit((int)r, qv, id >> 31, dn & kLow31, dn >> 31);
+      ++a;
+    } else {
+      const uint32_t id = Hi[b];
+      const uint32_t r = id & kLow31;
+      const uint64_t Eh = He[b];
+      const uint64_t Dn = a < NL ? Ld[a] : Dt;
+      if (Dn > Eh && b + 1 < NH) {
+        const uint32_t nx = Hi[b + 1];
+        emit((int)r, (uint32_t)(Eh + kCap - Dn), id >> 31, nx & kLow31,
+             nx >> 31);
+      } else {
+        emit((int)r, 0u, id >> 31, r, id >> 31);
+      }
+      ++b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host: layout of a family (slot offsets, big tables, run offsets)
+// ---------------------------------------------------------------------------
+static void ragged_free(Ragged& R) {
+  if (R.meta) (void)hipFree(R.meta);
+  if (R.ent) (void)hipFree(R.ent);
+  if (R.tot) (void)hipFree(R.tot);
+  if (R.bigids) (void)hipFree(R.bigids);
+  if (R.runoff) (void)hipFree(R.runoff);
+  R = Ragged{};
+}
+
+static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
+                                hipStream_t st) {
+  std::vector<int64_t> off((size_t)S + 1);
+  hipError_t e = hipMemcpyAsync(off.data(), off_dev, off.size() * 8,
+                                hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  std::vector<uint64_t> meta((size_t)S);
+  std::vector<uint32_t> big;
+  std::vector<int64_t> runoff(1, 0);
+  int64_t bs = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t N = off[(size_t)s + 1] - off[(size_t)s];
+    if (N > 512) {
+      const int L = ceil_log2_i(N);
+      meta[(size_t)s] = (uint64_t)bs | ((uint64_t)L << 56);
+      bs += int64_t(1) << L;
+      big.push_back((uint32_t)s);
+      runoff.push_back(runoff.back() + (N + kRun - 1) / kRun + 1);
+    }
+  }
+  int64_t ss = bs;
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t N = off[(size_t)s + 1] - off[(size_t)s];
+    if (N <= 512) {
+      const int L = ceil_log2_i(N);
+      meta[(size_t)s] = (uint64_t)ss | ((uint64_t)L << 56);
+      ss += int64_t(1) << L;
+    }
+  }
+  ragged_free(R);
+  R.S = S;
+  R.off = off_dev;
+  R.slots = ss;
+  R.big_slots = bs;
+  R.nbig = (int64_t)big.size();
+  R.runs = runoff.back();
+  if ((e = hipMalloc(&R.meta, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess ||
+      (e = hipMalloc(&R.ent, sizeof(Ent16) * (size_t)(ss > 0 ? ss : 1))) !=
+          hipSuccess ||
+      (e = hipMalloc(&R.tot, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess ||
+      (e = hipMalloc(&R.bigids, 4 * (big.size() + 1))) != hipSuccess ||
+      (e = hipMalloc(&R.runoff, 8 * runoff.size())) != hipSuccess)
+    return e;
+  if (S > 0 &&
+      (e = hipMemcpy(R.meta, meta.data(), 8 * (size_t)S,
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  if (!big.empty() &&
+      (e = hipMemcpy(R.bigids, big.data(), 4 * big.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  return hipMemcpy(R.runoff, runoff.data(), 8 * runoff.size(),
+                   hipMemcpyHostToDevice);
+}
+
+static size_t big_scratch_bytes(const Ragged& R) {
+  return (size_t)R.big_slots * (8 + 8 + 8 + 8 + 4 + 4) +
+         (size_t)R.runs * 8 + 8 * 256;
+}
+
+static BigScratch big_carve(void* p, const Ragged& R) {
+  char* c = (char*)p;
+  auto take = [&](size_t bytes) {
+    char* r = c;
+    c += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  BigScratch b;
+  const size_t n = (size_t)R.big_slots;
+  b.Lb = (uint64_t*)take(n * 8);
+  b.q = (uint64_t*)take(n * 8);
+  b.Ld = (uint64_t*)take(n * 8);
+  b.He = (uint64_t*)take(n * 8);
+  b.Li = (uint32_t*)take(n * 4);
+  b.Hi = (uint32_t*)take(n * 4);
+  b.E = (double*)take((size_t)R.runs * 8);
+  return b;
+}
+
+template <class W>
+static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
+                               hipStream_t st) {
+  if (R.S <= 0) return hipSuccess;
+  const unsigned blocks = blocks_of(R.S, 4);
+  k_ragged_small<1, W><<<blocks, 256, 4 * 64 * 20, st>>>(w, R.off, R.meta,
+                                                          R.S, R.tot, R.ent);
+  k_ragged_small<2, W><<<blocks, 256, 4 * 128 * 20, st>>>(w, R.off, R.meta,
+                                                          R.S, R.tot, R.ent);
+  k_ragged_small<4, W><<<blocks, 256, 4 * 256 * 20, st>>>(w, R.off, R.meta,
+                                                          R.S, R.tot, R.ent);
+  k_ragged_small<8, W><<<blocks, 256, 4 * 512 * 20, st>>>(w, R.off, R.meta,
+                                                          R.S, R.tot, R.ent);
+  if (R.nbig > 0)
+    k_ragged_big<W><<<(unsigned)R.nbig, kBigThreads, 0, st>>>(
+        w, R.off, R.meta, R.bigids, R.runoff, R.tot, R.ent,
+        big_carve(scratch, R));
+  return hipGetLastError();
+}
+
+__global__ void k_stage0_csr(const double* nb, const double* v, int64_t d,
+                             double* om) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < d) om[k] = nb[k] * v[k];
+}
+
+void csr_tables_free(CsrTables& t) {
+  ragged_free(t.T1);
+  ragged_free(t.T2);
+  ragged_free(t.T3);
+  family_free_pub(t.T0);
+  void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.bt_ptr, t.bt_row, t.bt_val,
+                t.om, t.bmax, t.bad};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  t.at_ptr = t.bt_ptr = nullptr;
+  t.at_row = t.bt_row = nullptr;
+  t.at_val = t.bt_val = nullptr;
+  t.om = nullptr;
+  t.bmax = nullptr;
+  t.bad = nullptr;
+  dev_free(t.work);
+}
+
+hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
+  hipError_t e;
+  const int64_t m = t.m, n = t.n, d = t.d;
+  // first build: fixed-size arrays
+  if (!t.bad) {
+    if ((e = hipMalloc(&t.bad, 256)) != hipSuccess ||
+        (e = hipMalloc(&t.bmax, 256)) != hipSuccess ||
+        (e = hipMalloc(&t.om, 8 * (size_t)d)) != hipSuccess ||
+        (e = hipMalloc(&t.at_ptr, 8 * (size_t)(d + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bt_ptr, 8 * (size_t)(d + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.at_row, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.at_val, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bt_row, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bt_val, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
+        (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
+      return e;
+  }
+  // validation (structure always: every later index relies on it)
+  if ((e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess ||
+      (e = launch_fill_u64((uint64_t*)t.bmax, 1, 0ull, st)) != hipSuccess)
+    return e;
+  k_csr_check<<<blocks_of(m, 256), 256, 0, st>>>(
+      t.in.a_ptr, t.in.a_idx, t.in.a_val, m, d, t.nnzA, nullptr, t.bad);
+  k_csr_check<<<blocks_of(n, 256), 256, 0, st>>>(
+      t.in.b_ptr, t.in.b_idx, t.in.b_val, n, d, t.nnzB, t.bmax, t.bad);
+  int bad = 0;
+  if ((e = hipMemcpyAsync(&bad, t.bad, 4, hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  if ((bad & 2) || (check && (bad & 1))) return hipErrorInvalidValue;
+  // transposes
+  const int64_t nz = t.nnzA > t.nnzB ? t.nnzA : t.nnzB;
+  if ((e = dev_alloc(t.work, sort_bytes(nz))) != hipSuccess) return e;
+  const SortBufs sb = sort_carve(t.work.p, nz);
+  if ((e = csr_transpose(t.in.a_ptr, t.in.a_idx, t.in.a_val, m, d, t.nnzA,
+                         t.at_ptr, t.at_row, t.at_val, sb, st)) != hipSuccess ||
+      (e = csr_transpose(t.in.b_ptr, t.in.b_idx, t.in.b_val, n, d, t.nnzB,
+                         t.bt_ptr, t.bt_row, t.bt_val, sb, st)) != hipSuccess)
+    return e;
+  // layouts (host)
+  if ((e = ragged_layout(t.T3, t.in.a_ptr, m, st)) != hipSuccess ||
+      (e = ragged_layout(t.T1, t.at_ptr, d, st)) != hipSuccess ||
+      (e = ragged_layout(t.T2, t.bt_ptr, d, st)) != hipSuccess)
+    return e;
+  size_t need = big_scratch_bytes(t.T3);
+  need = std::max(need, big_scratch_bytes(t.T1));
+  need = std::max(need, big_scratch_bytes(t.T2));
+  need = std::max(need, stage0_scratch_bytes(d));
+  need = std::max(need, sort_bytes(nz));
+  if ((e = dev_alloc(t.work, need)) != hipSuccess) return e;
+  // T3 (totals na), T1 (weights |a_ki| na_i, totals v), T2 (totals nb), T0
+  if ((e = ragged_build(t.T3, RowItems{t.in.a_val, t.in.a_idx}, t.work.p,
+                        st)) != hipSuccess ||
+      (e = ragged_build(t.T1, ColItems{t.at_val, t.at_row, t.T3.tot},
+                        t.work.p, st)) != hipSuccess ||
+      (e = ragged_build(t.T2, ColItems{t.bt_val, t.bt_row, nullptr},
+                        t.work.p, st)) != hipSuccess)
+    return e;
+  k_stage0_csr<<<blocks_of(d, 256), 256, 0, st>>>(t.T2.tot, t.T1.tot, d,
+                                                  t.om);
+  return stage0_table_build(t.om, d, t.T0, t.work.p, t.work.bytes, st);
+}
+
+// ---------------------------------------------------------------------------
+// the sampler
+// ---------------------------------------------------------------------------
+constexpr int kT0LdsCsr = 4096;
+
+struct CsrSampleArgs {
+  const uint64_t* T0;
+  int L0;
+  const uint64_t* m1;
+  const Ent16* e1;
+  const uint64_t* m2;
+  const Ent16* e2;
+  const uint64_t* m3;
+  const Ent16* e3;
+  CsrView in;
+  int64_t n;
+  uint64_t seed, qid;
+  int64_t l0, count;
+};
+
+__device__ __forceinline__ Drawn draw16(const Ent16& e, uint64_t U) {
+  const uint32_t lo = (uint32_t)e.w, hi = (uint32_t)(e.w >> 32);
+  const uint32_t coin = (uint32_t)U & kLow31;
+  const bool self = coin < (lo & kLow31);
+  return {self ? e.self : e.alias, (self ? lo : hi) >> 31};
+}
+
+__device__ __forceinline__ uint64_t meta_slot(uint64_t mt, uint64_t U) {
+  return (mt & kSlotMask) + slot_of(U, (int)(mt >> 56));
+}
+
+template <int U, bool DEBUG>
+__global__ __launch_bounds__(256) void k_sample_csr(
+    CsrSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
+    int F_debug, uint64_t* hkeys, int64_t* hvals, uint64_t hmask,
+    SampleCounters* ctr, int32_t* ok, int32_t* oi, int32_t* oj,
+    int32_t* okp, int64_t* oinc) {
+  extern __shared__ uint64_t t0s[];
+  if (!(wtot[0] > 0.0)) return;
+  const int N0 = 1 << a.L0;
+  const bool t0_lds = N0 <= kT0LdsCsr;
+  if (t0_lds)
+    for (int e = threadIdx.x; e < N0; e += blockDim.x) t0s[e] = a.T0[e];
+  __syncthreads();
+  const uint64_t* T0 = t0_lds ? t0s : a.T0;
+  const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long nclosed = 0, ncreated = 0;
+  for (int64_t base = tid; base < a.count; base += nthreads * U) {
+    uint32_t k[U], i[U], j[U], kp[U], sg[U];
+    uint64_t W1[U], W2[U], W3[U], mt1[U], mt2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)u * nthreads;
+      const uint64_t l = (uint64_t)(a.l0 + (e < a.count ? e : 0));
+      const Philox4 r = philox4x64_10(l, a.qid, 0ull, 0ull, a.seed, 0ull);
+      const uint32_t s0 = slot_of(r.w0, a.L0);
+      k[u] = draw_entry(T0[s0], s0, r.w0).pos;
+      W1[u] = r.w1;
+      W2[u] = r.w2;
+      W3[u] = r.w3;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      mt1[u] = a.m1[k[u]];
+      mt2[u] = a.m2[k[u]];
+    }
+    Ent16 x1[U], x2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x1[u] = a.e1[meta_slot(mt1[u], W1[u])];
+      x2[u] = a.e2[meta_slot(mt2[u], W2[u])];
+    }
+    uint64_t mt3[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const Drawn di = draw16(x1[u], W1[u]);
+      const Drawn dj = draw16(x2[u], W2[u]);
+      i[u] = di.pos;
+      j[u] = dj.pos;
+      sg[u] = di.sgn ^ dj.sgn;
+      mt3[u] = a.m3[i[u]];
+    }
+    int64_t lo[U], hi[U];
+    Ent16 x3[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x3[u] = a.e3[meta_slot(mt3[u], W3[u])];
+      lo[u] = a.in.b_ptr[j[u]];
+      hi[u] = a.in.b_ptr[j[u] + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const Drawn dk = draw16(x3[u], W3[u]);
+      kp[u] = dk.pos;
+      sg[u] ^= dk.sgn;
+    }
+    // dx: the fourth edge b_k'j by binary search among b_j's coordinates
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int64_t l = lo[u], h = hi[u];
+      const int32_t key = (int32_t)kp[u];
+      while (l < h) {
+        const int64_t mid = (l + h) >> 1;
+        if (a.in.b_idx[mid] < key) l = mid + 1; else h = mid;
+      }
+      v[u] = (l < hi[u] && a.in.b_idx[l] == key) ? a.in.b_val[l] : 0.0f;
+    }
+    int64_t inc[U];
+    bool closed[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + (int64_t)u * nthreads;
+      const bool live = e < a.count;
+      closed[u] = live && v[u] != 0.0f;
+      inc[u] = 0;
+      if (closed[u]) {
+        const int64_t mag = (int64_t)rint(ldexp((double)v[u], F));
+        inc[u] = sg[u] ? -mag : mag;
+      }
+      if (DEBUG && live) {
+        ok[e] = (int32_t)k[u];
+        oi[e] = (int32_t)i[u];
+        oj[e] = (int32_t)j[u];
+        okp[e] = (int32_t)kp[u];
+        oinc[e] = inc[u];
+      }
+    }
+    if (!DEBUG) {
+      uint64_t key[U], slot[U];
+      bool pend[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        key[u] = (uint64_t)i[u] * (uint64_t)a.n + j[u];
+        slot[u] = mix64(key[u]) & hmask;
+        pend[u] = closed[u];
+        nclosed += closed[u];
+      }
+      bool any = true;
+      while (any) {
+        uint64_t prev[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          prev[u] = pend[u] ? atomicCAS((unsigned long long*)(hkeys + slot[u]),
+                                        (unsigned long long)kEmptyKey,
+                                        (unsigned long long)key[u])
+                            : 0ull;
+        any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (!pend[u]) continue;
+          if (prev[u] == kEmptyKey || prev[u] == key[u]) {
+            ncreated += prev[u] == kEmptyKey;
+            pend[u] = false;
+          } else {
+            slot[u] = (slot[u] + 1) & hmask;
+            any = true;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (closed[u] && inc[u] != 0)
+          atomicAdd((unsigned long long*)(hvals + slot[u]),
+                    (unsigned long long)inc[u]);
+    }
+  }
+  if (!DEBUG) {
+    __shared__ unsigned long long part[2][4];
+    nclosed = wave_sum(nclosed);
+    ncreated = wave_sum(ncreated);
+    if ((threadIdx.x & 63) == 0) {
+      part[0][threadIdx.x >> 6] = nclosed;
+      part[1][threadIdx.x >> 6] = ncreated;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long c = part[0][0] + part[0][1] + part[0][2] +
+                                   part[0][3];
+      const unsigned long long dd = part[1][0] + part[1][1] + part[1][2] +
+                                    part[1][3];
+      if (c) atomicAdd(&ctr->closed, c);
+      if (dd) atomicAdd(&ctr->distinct, dd);
+    }
+  }
+}
+
+static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
+                              int64_t l0, int64_t count) {
+  CsrSampleArgs a;
+  a.T0 = t.T0.ent;
+  a.L0 = t.T0.L;
+  a.m1 = t.T1.meta;
+  a.e1 = t.T1.ent;
+  a.m2 = t.T2.meta;
+  a.e2 = t.T2.ent;
+  a.m3 = t.T3.meta;
+  a.e3 = t.T3.ent;
+  a.in = t.in;
+  a.n = t.n;
+  a.seed = seed;
+  a.qid = qid;
+  a.l0 = l0;
+  a.count = count;
+  return a;
+}
+
+static unsigned csr_grid(int64_t count, int per_thread) {
+  int64_t blocks = (count + 256LL * per_thread - 1) / (256LL * per_thread);
+  if (blocks > 8192) blocks = 8192;
+  return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+static size_t csr_t0_lds(const CsrTables& t) {
+  const int64_t N0 = int64_t(1) << t.T0.L;
+  return N0 <= kT0LdsCsr ? (size_t)N0 * 8 : 0;
+}
+
+hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
+                             int64_t l0, int64_t count, int64_t s_for_F,
+                             HashTable h, SampleCounters* ctr,
+                             hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
+  k_sample_csr<4, false><<<csr_grid(count, 4), 256, csr_t0_lds(t), st>>>(
+      a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, (uint64_t)h.cap - 1,
+      ctr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_csr_debug(const CsrTables& t, uint64_t seed,
+                                   uint64_t qid, int64_t l0, int64_t count,
+                                   int F, int32_t* k, int32_t* i, int32_t* j,
+                                   int32_t* kp, int64_t* inc, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
+  k_sample_csr<2, true><<<csr_grid(count, 2), 256, csr_t0_lds(t), st>>>(
+      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp,
+      inc);
+  return hipGetLastError();
+}
+
+}  // namespace mad

@@ -19,20 +19,6 @@ struct Family {
   double* tot = nullptr;    // S table totals (device)
 };
 
-// Sparse families: table s covers items [off[s], off[s+1]) of a position
-// array (item ids in pos_item) and slots [soff[s], soff[s] + 2^L[s]).
-struct RaggedFamily {
-  int64_t S = 0;
-  int64_t items = 0;         // off[S]
-  int64_t slots = 0;         // soff[S]
-  const int64_t* off = nullptr;  // S + 1 (device)
-  int64_t* soff = nullptr;   // S + 1 (device)
-  int8_t* L = nullptr;       // S (device)
-  int32_t* item = nullptr;   // position -> vector or coordinate id (device)
-  uint64_t* ent = nullptr;   // slots packed entries (device)
-  double* tot = nullptr;     // S totals (device)
-};
-
 struct DeviceBuffer {
   void* p = nullptr;
   size_t bytes = 0;
@@ -98,6 +84,83 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t count, int F, int32_t* k,
                                      int32_t* i, int32_t* j, int32_t* kp,
                                      int64_t* inc, hipStream_t st);
+
+// ---- csr.hip -------------------------------------------------------------
+// A 16-byte alias entry of a sparse table: the packed word of a dense entry
+// (threshold, alias position, two sign bits) plus the item ids (vector or
+// coordinate) of the slot's own item and of its alias.
+struct Ent16 {
+  uint64_t w;
+  uint32_t self;
+  uint32_t alias;
+};
+
+constexpr uint64_t kSlotMask = (1ull << 56) - 1;
+
+// Tables of different sizes: table s covers item positions [off[s],
+// off[s+1]) and 2^L_s slots from meta[s] & kSlotMask (L_s = meta[s] >> 56).
+// Tables of more than 512 items ("big", 2^L >= 1024 slots) come first, in
+// index order, then the others in index order.
+struct Ragged {
+  int64_t S = 0;
+  int64_t slots = 0, big_slots = 0, nbig = 0, runs = 0;
+  const int64_t* off = nullptr;  // S + 1 (device)
+  uint64_t* meta = nullptr;      // S (device)
+  Ent16* ent = nullptr;          // slots (device)
+  double* tot = nullptr;         // S table totals (device)
+  uint32_t* bigids = nullptr;    // nbig big tables (device)
+  int64_t* runoff = nullptr;     // nbig + 1: first run-offset slot (device)
+};
+
+// sparse inputs as compressed rows of the vector-major arrays
+struct CsrView {
+  const int64_t* a_ptr;
+  const int32_t* a_idx;
+  const float* a_val;
+  const int64_t* b_ptr;
+  const int32_t* b_idx;
+  const float* b_val;
+};
+
+// Sparse plan tables: T0 over coordinates (dense family), T1[k] over the
+// vectors i with an entry at k (weight |a_ki| na_i), T2[k] over the j with
+// an entry at k (weight |b_kj|), T3[i] over the coordinates of a_i (weight
+// |a_k'i|).  The transposes list, per coordinate, its vectors in ascending
+// order with their values.
+struct CsrTables {
+  int64_t m = 0, n = 0, d = 0, nnzA = 0, nnzB = 0;
+  CsrView in{};
+  int64_t* at_ptr = nullptr;  // d + 1
+  uint32_t* at_row = nullptr; // nnzA
+  float* at_val = nullptr;    // nnzA
+  int64_t* bt_ptr = nullptr;
+  uint32_t* bt_row = nullptr;
+  float* bt_val = nullptr;
+  Ragged T1, T2, T3;
+  Family T0;
+  double* om = nullptr;   // d
+  float* bmax = nullptr;  // 1
+  int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
+  DeviceBuffer work;      // transposes' and tables' scratch
+};
+
+// Allocates and builds every table (synchronises: the layout of the
+// sparse tables is planned on the host).  Returns hipErrorInvalidValue when
+// the inputs are malformed or hold NaN/Inf, with t.bad set.
+hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st);
+void csr_tables_free(CsrTables& t);
+hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
+                             int64_t l0, int64_t count, int64_t s_for_F,
+                             HashTable h, SampleCounters* ctr, hipStream_t st);
+hipError_t launch_sample_csr_debug(const CsrTables& t, uint64_t seed,
+                                   uint64_t qid, int64_t l0, int64_t count,
+                                   int F, int32_t* k, int32_t* i, int32_t* j,
+                                   int32_t* kp, int64_t* inc, hipStream_t st);
+// stage-0 table over explicit weights (any size); scratch for 2^L > 512
+size_t stage0_scratch_bytes(int64_t N);
+hipError_t stage0_table_build(const double* w, int64_t N, Family& T,
+                              void* scratch, size_t scratch_bytes,
+                              hipStream_t st);
 
 // ---- mips.hip ------------------------------------------------------------
 // Per-query state of a MIPS batch.  The host fills everything but F and
@@ -191,11 +254,12 @@ hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,
                               int64_t* xfix, int64_t out_cap, int64_t* count,
                               hipStream_t st);
 
+// csr: sparse inputs for the verification (A, B unused), or null
 hipError_t launch_postprocess(const HashTable& h, const float* A,
-                              const float* B, int64_t n, int64_t d,
-                              int64_t t_prime, int64_t t, const float* bmax,
-                              int64_t s, SelectWork& w, void* out,
-                              int64_t* n_out, hipStream_t st);
+                              const float* B, const CsrView* csr, int64_t n,
+                              int64_t d, int64_t t_prime, int64_t t,
+                              const float* bmax, int64_t s, SelectWork& w,
+                              void* out, int64_t* n_out, hipStream_t st);
 
 // fp32 re-rank of candidate keys (count known on the host) and the exact
 // top t by |c| into mad_pair records; buf is grown as needed

@@ -364,6 +364,48 @@ __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
   block_hist_flush(h, hist);
 }
 
+// post2 for sparse vectors: one wave per candidate, each lane takes entries
+// of a_i and finds their coordinate in b_j by binary search
+__global__ __launch_bounds__(256) void k_verify_csr(const uint64_t* key2,
+                                                    const int64_t* counts,
+                                                    CsrView v, int64_t n,
+                                                    int64_t cap2, float* c,
+                                                    uint64_t* absbits,
+                                                    unsigned* hist) {
+  __shared__ unsigned h[kBins];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const int64_t ncand = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t e = wave; e < ncand; e += nwaves) {
+    const uint64_t kk = key2[e];
+    const int64_t i = (int64_t)(kk / (uint64_t)n);
+    const int64_t j = (int64_t)(kk % (uint64_t)n);
+    const int64_t a0 = v.a_ptr[i], a1 = v.a_ptr[i + 1];
+    const int64_t b0 = v.b_ptr[j], b1 = v.b_ptr[j + 1];
+    float acc = 0.0f;
+    for (int64_t p = a0 + lane; p < a1; p += 64) {
+      const int32_t k = v.a_idx[p];
+      int64_t lo = b0, hi = b1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (v.b_idx[mid] < k) lo = mid + 1; else hi = mid;
+      }
+      if (lo < b1 && v.b_idx[lo] == k) acc = fmaf(v.a_val[p], v.b_val[lo], acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      c[e] = acc;
+      const uint64_t ab = __float_as_uint(fabsf(acc));
+      absbits[e] = ab;
+      atomicAdd(&h[fbin_float(ab)], 1u);
+    }
+  }
+  block_hist_flush(h, hist);
+}
+
 // post3 step 2b: split the candidates
 __global__ __launch_bounds__(256) void k_cand_split(
     const Coarse* cz, const uint64_t* absbits, const uint64_t* key2,
@@ -573,10 +615,10 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
 }
 
 hipError_t launch_postprocess(const HashTable& h, const float* A,
-                              const float* B, int64_t n, int64_t d,
-                              int64_t t_prime, int64_t t, const float* bmax,
-                              int64_t s, SelectWork& w, void* out,
-                              int64_t* n_out, hipStream_t st) {
+                              const float* B, const CsrView* csr, int64_t n,
+                              int64_t d, int64_t t_prime, int64_t t,
+                              const float* bmax, int64_t s, SelectWork& w,
+                              void* out, int64_t* n_out, hipStream_t st) {
   Coarse* cz = (Coarse*)w.state;
   int64_t* counts = w.counts;
   // keep counts[kCntDistinct] (the sampler's), clear the others
@@ -601,8 +643,12 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
       nullptr, nullptr, w.cap2, kCntCand);
   // ---- post2: fp32 dot products and the |c| histogram --------------------
   // (|c| bits go to w.x, free after post1)
-  k_verify<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
-      w.key2, counts, A, B, n, d, w.cap2, w.c, w.x, w.hist);
+  if (csr)
+    k_verify_csr<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
+        w.key2, counts, *csr, n, w.cap2, w.c, w.x, w.hist);
+  else
+    k_verify<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
+        w.key2, counts, A, B, n, d, w.cap2, w.c, w.x, w.hist);
   // ---- post3: top t by |c| ----------------------------------------------
   e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
   if (e != hipSuccess) return e;

@@ -23,6 +23,7 @@
 // work that any parallel schedule reproduces bit for bit (the
 // prefix-sum formulation of the sweep follows Huebschle-Schneider and
 // Sanders, "Parallel Weighted Random Sampling", ACM TOMS 2022).
+#include "alias_common.hpp"
 #include "mad_common.hpp"
 #include "plan.hpp"
 
@@ -315,86 +316,6 @@ static hipError_t uniform_quanta(W w, int64_t S, int64_t N, int L,
 // alias construction.  Each quantum carries its item's sign bit in bit 63;
 // the lists below carry it in bit 31 of the slot id.
 // ---------------------------------------------------------------------------
-constexpr uint64_t kQMask = ~(1ull << 63);
-
-// One wave builds the alias table of one table from its quanta qv (lane
-// holds slots lane*SPL ..) and sign bits sg; LDS scratch Ld/He (2^L u64
-// each) and Hi (2^L u32) belongs to this wave.  The caller synchronises the
-// block (every wave of the block calls this).
-template <int SPL>
-__device__ void wave_alias(const uint64_t (&qv)[SPL], const uint32_t (&sg)[SPL],
-                           bool active, int L, uint64_t* Ld, uint64_t* He,
-                           uint32_t* Hi, uint64_t* et) {
-  const int Np = 1 << L;
-  const int lane = threadIdx.x & 63;
-  uint32_t nl = 0, nh = 0;
-  uint64_t sd = 0, se = 0;
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    if (active && r < Np) {
-      if (qv[s] < kCap) { ++nl; sd += kCap - qv[s]; }
-      else { ++nh; se += qv[s] - kCap; }
-    }
-  }
-  const uint32_t nl_in = wave_incl_scan(nl), nh_in = wave_incl_scan(nh);
-  const uint64_t sd_in = wave_incl_scan(sd), se_in = wave_incl_scan(se);
-  const uint32_t NL = __shfl(nl_in, 63, 64), NH = __shfl(nh_in, 63, 64);
-  uint32_t lp = nl_in - nl, hp = nh_in - nh;
-  uint64_t da = sd_in - sd, ea = se_in - se;
-  uint32_t mypos[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    mypos[s] = 0;
-    if (active && r < Np) {
-      if (qv[s] < kCap) {
-        da += kCap - qv[s];
-        Ld[lp] = da;
-        mypos[s] = lp++;
-      } else {
-        ea += qv[s] - kCap;
-        He[hp] = ea;
-        Hi[hp] = (uint32_t)r | (sg[s] << 31);
-        mypos[s] = hp++;
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    if (!(active && r < Np)) continue;
-    uint64_t e;
-    if (qv[s] < kCap) {
-      const uint64_t Dx = Ld[mypos[s]] - (kCap - qv[s]);
-      uint32_t lo = 0, hi = NH;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (He[mid] >= Dx) hi = mid; else lo = mid + 1;
-      }
-      const uint32_t a = NH ? Hi[lo < NH ? lo : NH - 1]
-                            : (uint32_t)r | (sg[s] << 31);
-      e = pack_entry((uint32_t)qv[s], sg[s], a & kLow31, a >> 31);
-    } else {
-      const uint64_t Eh = He[mypos[s]];
-      uint32_t lo = 0, hi = NL;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (Ld[mid] > Eh) hi = mid; else lo = mid + 1;
-      }
-      if (lo < NL && mypos[s] + 1 < NH) {
-        const uint32_t a = Hi[mypos[s] + 1];
-        e = pack_entry((uint32_t)(Eh + kCap - Ld[lo]), sg[s], a & kLow31,
-                       a >> 31);
-      } else {
-        e = pack_entry(0u, sg[s], (uint32_t)r, sg[s]);
-      }
-    }
-    et[r] = e;
-  }
-}
-
 // one wave per table from stored quanta (2^L <= 64 * SPL <= 512 slots;
 // 4 tables per block use at most 40 KB of LDS)
 template <int SPL>
@@ -421,15 +342,9 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
   wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * Np,
                   smem64 + (int64_t)wv * 2 * Np + Np,
                   (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np,
-                  ent + (seg << L));
+                  EmitPacked{ent + (seg << L)});
 }
 
-__device__ __forceinline__ double readlane_f64(double x, int k) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), k);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 // Small tables end to end, one wave per table (N <= 2^L <= 64 * SPL <= 512,
 // a single run of the two-level order): lane l holds items l*SPL ..; the
@@ -493,7 +408,7 @@ __global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
   wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * Np,
                   smem64 + (int64_t)wv * 2 * Np + Np,
                   (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np,
-                  ent + (segc << L));
+                  EmitPacked{ent + (segc << L)});
 }
 
 template <class W>
@@ -532,15 +447,6 @@ static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
 // large tables (2^L >= 1024 slots): blocks of 1024 slots (256 threads x 4)
 // never straddle a table
 constexpr int kAliasBlk = 1024;
-
-struct Quad {
-  uint64_t nl, nh, sd, se;
-};
-
-__device__ __forceinline__ void slot_stats(uint64_t q, Quad& a) {
-  if (q < kCap) { a.nl += 1; a.sd += kCap - q; }
-  else { a.nh += 1; a.se += q - kCap; }
-}
 
 // block-wide exclusive scan of a Quad (256 threads); returns the block total
 __device__ Quad block_excl_scan(Quad& v) {
@@ -690,18 +596,6 @@ __global__ __launch_bounds__(256) void k_alias_scatter(
 // kMergeP sequential merge steps per thread.
 constexpr int kMergeP = 4;
 constexpr int kMergeBlk = 256 * kMergeP;
-
-__device__ __forceinline__ int64_t merge_split(const uint64_t* D, int64_t NL,
-                                               const uint64_t* E, int64_t NH,
-                                               int64_t di) {
-  int64_t lo = di - NH > 0 ? di - NH : 0;
-  int64_t hi = di < NL ? di : NL;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (D[mid] <= E[di - mid - 1]) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
 
 // merge-path split of every block edge (kMergeBlk positions apart)
 __global__ void k_alias_edges(const uint64_t* Ld, const uint64_t* He,
@@ -1062,6 +956,26 @@ hipError_t query_tables_build(const float* Q, int64_t nq, int64_t d,
   if (e != hipSuccess) return e;
   return build_alias(q, T0q.tot, nq, T0q.L, T0q.ent, nullptr, p,
                      scratch_bytes - used, st);
+}
+
+size_t stage0_scratch_bytes(int64_t N) {
+  return query_tables_scratch_bytes(1, N);
+}
+
+hipError_t stage0_table_build(const double* w, int64_t N, Family& T,
+                              void* scratch, size_t scratch_bytes,
+                              hipStream_t st) {
+  const WExplicit wf{w};
+  if (T.L <= 9) return small_tables(wf, 1, N, T.L, T.tot, T.ent, st);
+  char* p = (char*)scratch;
+  uint64_t* q = (uint64_t*)p; p += (size_t)8 << T.L;
+  double* runbuf = (double*)p; p += run_doubles(1, N) * 8;
+  const size_t used = (size_t)(p - (char*)scratch);
+  if (!scratch || scratch_bytes < used) return hipErrorInvalidValue;
+  hipError_t e = uniform_quanta(wf, 1, N, T.L, T.tot, q, runbuf, st);
+  if (e != hipSuccess) return e;
+  return build_alias(q, T.tot, 1, T.L, T.ent, nullptr, p, scratch_bytes - used,
+                     st);
 }
 
 hipError_t family_alloc_pub(Family& f, int64_t S, int64_t N) {
