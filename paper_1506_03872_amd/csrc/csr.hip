@@ -18,6 +18,8 @@
 //
 // The sampler draws k, i, j, k' as the dense one does and finds the fourth
 // edge b_k'j by binary search among the coordinates of b_j.
+#include <string.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -148,10 +150,13 @@ static hipError_t scan_u64(const uint64_t* in, uint64_t* out, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (key, value) u32 pairs by key, 4-bit digits.
-// A tile of 4096 pairs is 256 threads x 16 consecutive pairs; per-thread
-// digit counts are 16-bit fields of four u64, so a block scan of the four
-// words ranks every pair after all pairs before it in input order.
+// Stable LSD radix sort of (coordinate, payload) pairs by coordinate, 4-bit
+// digits; the payload is (vector id << 32 | value bits), so the sorted
+// payload is the transpose itself.  A tile of 4096 pairs is 256 threads x
+// 16 consecutive pairs.  Per-thread digit counts are 16-bit fields of four
+// u64, so one block scan of the four words gives every pair its rank in
+// input order; the tile is reordered by digit in LDS and written out in
+// runs of consecutive addresses.
 // ---------------------------------------------------------------------------
 constexpr int kRsThreads = 256;
 constexpr int kRsPer = 16;
@@ -216,6 +221,18 @@ __device__ __forceinline__ Cnt16 tile_counts(const uint32_t* key, int64_t n,
   return c;
 }
 
+// exclusive prefix over the 16 digit fields of packed totals
+__device__ __forceinline__ Cnt16 digit_excl(const Cnt16& all) {
+  Cnt16 r{{0, 0, 0, 0}};
+  uint64_t run = 0;
+#pragma unroll
+  for (int dg = 0; dg < 16; ++dg) {
+    r.c[dg >> 2] |= run << (16 * (dg & 3));
+    run += cnt_get(all, dg);
+  }
+  return r;
+}
+
 __global__ __launch_bounds__(kRsThreads) void k_rs_count(const uint32_t* key,
                                                          int64_t n, int shift,
                                                          uint64_t* counts,
@@ -224,41 +241,59 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_count(const uint32_t* key,
       (int64_t)blockIdx.x * kRsTile + (int64_t)threadIdx.x * kRsPer;
   Cnt16 c = tile_counts(key, n, shift, base);
   const Cnt16 all = cnt_block_scan(c);
-  if (threadIdx.x < 16)
-    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] =
-        cnt_get(all, threadIdx.x);
+#pragma unroll
+  for (int dg = 0; dg < 16; ++dg)
+    if (threadIdx.x == dg)
+      counts[(int64_t)dg * ntiles + blockIdx.x] = cnt_get(all, dg);
 }
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
-    const uint32_t* kin, const uint32_t* vin, int64_t n, int shift,
-    const uint64_t* offs, int64_t ntiles, uint32_t* kout, uint32_t* vout) {
-  __shared__ uint32_t pos[kRsThreads][17];
-  __shared__ uint64_t tbase[16];
+    const uint32_t* kin, const uint64_t* vin, int64_t n, int shift,
+    const uint64_t* offs, int64_t ntiles, uint32_t* kout, uint64_t* vout) {
+  __shared__ uint32_t sk[kRsTile];
+  __shared__ uint64_t sv[kRsTile];
+  __shared__ uint64_t gbase[16];
   const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)t * kRsPer;
-  if (t < 16) tbase[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+  const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+  const int64_t base = tile0 + (int64_t)t * kRsPer;
+  const int cnt_tile = n - tile0 < kRsTile ? (int)(n - tile0) : kRsTile;
+  if (t < 16) gbase[t] = offs[(int64_t)t * ntiles + blockIdx.x];
   Cnt16 c = tile_counts(kin, n, shift, base);
-  (void)cnt_block_scan(c);  // c := this thread's exclusive prefix
+  const Cnt16 all = cnt_block_scan(c);  // c := this thread's prefix
+  const Cnt16 dstart = digit_excl(all);
+  // local position of each pair: digit start + earlier pairs of the digit
+  Cnt16 run;
 #pragma unroll
-  for (int dg = 0; dg < 16; ++dg)
-    pos[t][dg] = (uint32_t)(tbase[dg] + cnt_get(c, dg));
+  for (int x = 0; x < 4; ++x) run.c[x] = dstart.c[x] + c.c[x];
+#pragma unroll
   for (int u = 0; u < kRsPer; ++u) {
     const int64_t e = base + u;
     if (e >= n) break;
     const uint32_t k = kin[e];
     const uint32_t dg = (k >> shift) & 15u;
-    const uint32_t p = pos[t][dg]++;
-    kout[p] = k;
-    vout[p] = vin[e];
+    const uint32_t lp = cnt_get(run, (int)dg);
+    cnt_add(run, dg);
+    sk[lp] = k;
+    sv[lp] = vin[e];
+  }
+  __syncthreads();
+  for (int p = t; p < cnt_tile; p += kRsThreads) {
+    const uint32_t k = sk[p];
+    const int dg = (int)((k >> shift) & 15u);
+    const int64_t g = (int64_t)gbase[dg] + (p - (int)cnt_get(dstart, dg));
+    kout[g] = k;
+    vout[g] = sv[p];
   }
 }
 
-__global__ void k_sort_init(const int32_t* idx, int64_t n, uint32_t* key,
-                            uint32_t* val) {
+// keys = coordinates, payload = (vector id << 32) | value bits
+__global__ void k_sort_init(const int32_t* idx, const float* val,
+                            const uint32_t* rowid, int64_t n, uint32_t* key,
+                            uint64_t* pay) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) {
     key[e] = (uint32_t)idx[e];
-    val[e] = (uint32_t)e;
+    pay[e] = ((uint64_t)rowid[e] << 32) | __float_as_uint(val[e]);
   }
 }
 
@@ -275,22 +310,21 @@ __global__ void k_lower_bound(const uint32_t* key, int64_t n, int64_t d,
   tptr[k] = lo;
 }
 
-__global__ void k_trans_gather(const uint32_t* pos, const uint32_t* rowid,
-                               const float* val, int64_t n, uint32_t* trow,
-                               float* tval) {
+__global__ void k_trans_split(const uint64_t* pay, int64_t n, uint32_t* trow,
+                              float* tval) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) {
-    const uint32_t e = pos[p];
-    trow[p] = rowid[e];
-    tval[p] = val[e];
+    const uint64_t v = pay[p];
+    trow[p] = (uint32_t)(v >> 32);
+    tval[p] = __uint_as_float((uint32_t)v);
   }
 }
 
 struct SortBufs {
   uint32_t* k0;
   uint32_t* k1;
-  uint32_t* v0;
-  uint32_t* v1;
+  uint64_t* v0;
+  uint64_t* v1;
   uint32_t* rowid;
   uint64_t* counts;  // 16 * tiles
   uint64_t* tmp;     // scan scratch
@@ -298,8 +332,8 @@ struct SortBufs {
 
 static size_t sort_bytes(int64_t nnz) {
   const int64_t tiles = (nnz + kRsTile - 1) / kRsTile;
-  return (size_t)nnz * 4 * 5 + (size_t)(16 * tiles + 1) * 8 +
-         scan_tmp_words(16 * tiles) * 8 + 1024;
+  return (size_t)nnz * (4 + 4 + 8 + 8 + 4) + (size_t)(16 * tiles + 1) * 8 +
+         scan_tmp_words(16 * tiles) * 8 + 8 * 256;
 }
 
 static SortBufs sort_carve(void* p, int64_t nnz) {
@@ -313,8 +347,8 @@ static SortBufs sort_carve(void* p, int64_t nnz) {
   };
   b.k0 = (uint32_t*)take((size_t)nnz * 4);
   b.k1 = (uint32_t*)take((size_t)nnz * 4);
-  b.v0 = (uint32_t*)take((size_t)nnz * 4);
-  b.v1 = (uint32_t*)take((size_t)nnz * 4);
+  b.v0 = (uint64_t*)take((size_t)nnz * 8);
+  b.v1 = (uint64_t*)take((size_t)nnz * 8);
   b.rowid = (uint32_t*)take((size_t)nnz * 4);
   b.counts = (uint64_t*)take((size_t)(16 * tiles + 1) * 8);
   b.tmp = (uint64_t*)take(scan_tmp_words(16 * tiles) * 8);
@@ -328,11 +362,13 @@ static hipError_t csr_transpose(const int64_t* ptr, const int32_t* idx,
                                 float* tval, SortBufs b, hipStream_t st) {
   if (nnz > 0) {
     k_row_ids<<<blocks_of(rows * 64, 256), 256, 0, st>>>(ptr, rows, b.rowid);
-    k_sort_init<<<blocks_of(nnz, 256), 256, 0, st>>>(idx, nnz, b.k0, b.v0);
+    k_sort_init<<<blocks_of(nnz, 256), 256, 0, st>>>(idx, val, b.rowid, nnz,
+                                                     b.k0, b.v0);
     const int bits = ceil_log2_i(d);
     const int passes = bits > 0 ? (bits + 3) / 4 : 1;
     const int64_t tiles = (nnz + kRsTile - 1) / kRsTile;
-    uint32_t *ka = b.k0, *va = b.v0, *kb = b.k1, *vb = b.v1;
+    uint32_t *ka = b.k0, *kb = b.k1;
+    uint64_t *va = b.v0, *vb = b.v1;
     for (int ps = 0; ps < passes; ++ps) {
       k_rs_count<<<(unsigned)tiles, kRsThreads, 0, st>>>(ka, nnz, 4 * ps,
                                                          b.counts, tiles);
@@ -343,8 +379,7 @@ static hipError_t csr_transpose(const int64_t* ptr, const int32_t* idx,
       std::swap(ka, kb);
       std::swap(va, vb);
     }
-    k_trans_gather<<<blocks_of(nnz, 256), 256, 0, st>>>(va, b.rowid, val, nnz,
-                                                        trow, tval);
+    k_trans_split<<<blocks_of(nnz, 256), 256, 0, st>>>(va, nnz, trow, tval);
     k_lower_bound<<<blocks_of(d + 1, 256), 256, 0, st>>>(ka, nnz, d, tptr);
   } else {
     k_lower_bound<<<blocks_of(d + 1, 256), 256, 0, st>>>(nullptr, 0, d, tptr);
@@ -395,28 +430,30 @@ __device__ __forceinline__ int spl_of(int L) {
   return L <= 6 ? 1 : (L == 7 ? 2 : (L == 8 ? 4 : 8));
 }
 
+static inline int spl_class_host(int L) {  // 0..3 for 1, 2, 4, 8 slots/lane
+  return L <= 6 ? 0 : L - 6;
+}
+
 // ---------------------------------------------------------------------------
 // tables of at most 512 items: one wave per table; a launch serves the
-// tables whose slots need SPL slots per lane (every wave of the block
-// still calls wave_alias, which synchronises the block)
+// tables of one slots-per-lane class (ids[0 .. count)); every wave of the
+// block calls wave_alias, which synchronises the block
 // ---------------------------------------------------------------------------
 template <int SPL, class W>
-__global__ __launch_bounds__(256) void k_ragged_small(W w, const int64_t* off,
-                                                      const uint64_t* meta,
-                                                      int64_t S, double* tot,
-                                                      Ent16* ent) {
+__global__ __launch_bounds__(256) void k_ragged_small(
+    W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
+    int64_t count, double* tot, Ent16* ent) {
   extern __shared__ uint64_t smem64[];
   constexpr int NpMax = 64 * SPL;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t segc = seg < S ? seg : S - 1;
-  const uint64_t mt = meta[segc];
+  const int64_t g = (int64_t)blockIdx.x * 4 + wv;
+  const bool mine = g < count;
+  const int64_t seg = ids[mine ? g : count - 1];
+  const uint64_t mt = meta[seg];
   const int L = (int)(mt >> 56);
   const int64_t so = (int64_t)(mt & kSlotMask);
-  const int64_t o = off[segc];
-  const int64_t N64 = off[segc + 1] - o;
-  const bool mine = seg < S && N64 <= 512 && spl_of(L) == SPL;
-  const int N = mine ? (int)N64 : 0;
+  const int64_t o = off[seg];
+  const int N = mine ? (int)(off[seg + 1] - o) : 0;
   const int Np = 1 << L;
   double P[SPL];
   uint32_t sg[SPL];
@@ -466,31 +503,56 @@ __global__ __launch_bounds__(256) void k_ragged_small(W w, const int64_t* off,
 }
 
 // ---------------------------------------------------------------------------
-// tables of more than 512 items: one workgroup (512 threads) per table
+// tables of more than 512 items: the large-table pipeline of the dense
+// builder over the "big" slot region (tables back to back, each a multiple
+// of 1024 slots), with a table lookup per 1024-slot block:
+//   runs     one thread per run of 1024 items: run-local prefixes, totals
+//   offsets  one workgroup per table: E_{c+1} = E_c + S_c left to right
+//   quanta   one thread per 4 slots; 1024-slot block alias statistics
+//   scan     one workgroup per table: exclusive scan of its block stats
+//   scatter  light / heavy lists in slot order
+//   edges    merge-path split at every 1024th merged position
+//   merge    1024 merged positions per workgroup -> 16-byte entries
 // ---------------------------------------------------------------------------
-constexpr int kBigThreads = 512;
-constexpr int kBigWaves = kBigThreads / 64;
-
-struct BigScratch {
-  uint64_t* Lb;  // run-local prefix bits (sign in bit 63), per slot
-  uint64_t* q;   // quanta (sign in bit 63), per slot
-  uint64_t* Ld;  // light deficit prefixes (exclusive)
-  uint64_t* He;  // heavy excess prefixes (inclusive)
-  uint32_t* Li;  // light slot ids (sign in bit 31)
-  uint32_t* Hi;  // heavy slot ids (sign in bit 31)
-  double* E;     // run offsets
+struct BigInfo {
+  int64_t so;     // first slot (in the big region, a multiple of 1024)
+  int64_t o;      // first item position
+  int64_t N;      // items
+  int64_t R;      // runs of kRun items
+  int64_t run0;   // first global run id
+  int64_t eoff;   // first run offset in E (R + 1 entries)
+  int64_t edge0;  // first merge edge (2^L / 1024 + 1 per table)
+  int32_t L;
+  int32_t s;      // table id
 };
 
-// block-wide exclusive scan of a Quad over the workgroup; returns the total
-__device__ Quad block_excl_scan_big(Quad& v) {
-  __shared__ Quad wt[kBigWaves];
+constexpr int kBigBlk = 1024;  // slots per block of the big pipeline
+
+struct BigScratch {
+  uint64_t* Lb;   // run-local prefix bits (sign in bit 63), per slot
+  uint64_t* q;    // quanta (sign in bit 63), per slot
+  uint64_t* Ld;   // light deficit prefixes (exclusive)
+  uint64_t* He;   // heavy excess prefixes (inclusive)
+  uint32_t* Li;   // light slot ids (sign in bit 31)
+  uint32_t* Hi;   // heavy slot ids (sign in bit 31)
+  Quad* bs;       // per 1024-slot block statistics
+  double* E;      // run offsets
+  uint64_t* NL;   // per big table
+  uint64_t* NH;
+  uint64_t* Dt;
+  int64_t* edges;
+};
+
+// block-wide exclusive scan of a Quad over 256 threads; returns the total
+__device__ Quad quad_scan256(Quad& v) {
+  __shared__ Quad wt[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Quad inc{wave_incl_scan(v.nl), wave_incl_scan(v.nh), wave_incl_scan(v.sd),
            wave_incl_scan(v.se)};
   if (lane == 63) wt[wv] = inc;
   __syncthreads();
   Quad off{0, 0, 0, 0}, all{0, 0, 0, 0};
-  for (int w = 0; w < kBigWaves; ++w) {
+  for (int w = 0; w < 4; ++w) {
     const Quad x = wt[w];
     if (w < wv) {
       off.nl += x.nl; off.nh += x.nh; off.sd += x.sd; off.se += x.se;
@@ -504,151 +566,253 @@ __device__ Quad block_excl_scan_big(Quad& v) {
 }
 
 template <class W>
-__global__ __launch_bounds__(kBigThreads) void k_ragged_big(
-    W w, const int64_t* off, const uint64_t* meta, const uint32_t* bigids,
-    const int64_t* runoff, double* tot, Ent16* ent, BigScratch sc) {
-  __shared__ double sT;
-  const int t = threadIdx.x;
-  const uint32_t s = bigids[blockIdx.x];
-  const int64_t o = off[s];
-  const int64_t N = off[s + 1] - o;
-  const uint64_t mt = meta[s];
-  const int L = (int)(mt >> 56);
-  const int64_t so = (int64_t)(mt & kSlotMask);
-  const int64_t Np = int64_t(1) << L;
-  const int64_t R = (N + kRun - 1) / kRun;
-  double* E = sc.E + runoff[blockIdx.x];  // R + 1 entries
-  uint64_t* Lb = sc.Lb + so;
-  uint64_t* q = sc.q + so;
-  uint64_t* Ld = sc.Ld + so;
-  uint64_t* He = sc.He + so;
-  uint32_t* Li = sc.Li + so;
-  uint32_t* Hi = sc.Hi + so;
-  Ent16* et = ent + so;
-  // run-local prefixes, one thread per run, loads 8 at a time
-  for (int64_t c = t; c < R; c += kBigThreads) {
-    const int64_t r0 = c * kRun;
-    const int64_t r1 = r0 + kRun < N ? r0 + kRun : N;
-    double l = 0.0;
-    for (int64_t r = r0; r < r1; r += 8) {
-      double wv[8];
-      uint32_t sv[8];
+__global__ __launch_bounds__(256) void k_big_runs(W w, const BigInfo* big,
+                                                  const uint32_t* runtab,
+                                                  int64_t runs, BigScratch sc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= runs) return;
+  const BigInfo B = big[runtab[r]];
+  const int64_t c = r - B.run0;
+  const int64_t r0 = c * kRun;
+  const int64_t r1 = r0 + kRun < B.N ? r0 + kRun : B.N;
+  uint64_t* Lb = sc.Lb + B.so;
+  double l = 0.0;
+  for (int64_t x = r0; x < r1; x += 8) {
+    double wv[8];
+    uint32_t sv[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t rr = r + u < r1 ? r + u : r1 - 1;
-        wv[u] = w.w(o + rr);
-        sv[u] = w.sgn(o + rr);
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int64_t rr = x + u < r1 ? x + u : r1 - 1;
+      wv[u] = w.w(B.o + rr);
+      sv[u] = w.sgn(B.o + rr);
+    }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (r + u < r1) {
-          l = l + wv[u];
-          Lb[r + u] = (uint64_t)__double_as_longlong(l) |
-                      ((uint64_t)sv[u] << 63);
-        }
+    for (int u = 0; u < 8; ++u) {
+      if (x + u < r1) {
+        l = l + wv[u];
+        Lb[x + u] = (uint64_t)__double_as_longlong(l) | ((uint64_t)sv[u] << 63);
       }
     }
-    E[c + 1] = l;  // run total, turned into the offset below
   }
-  __syncthreads();
-  if (t == 0) {  // E_0 = 0, E_{c+1} = E_c + S_c, left to right
-    double acc = 0.0;
+  sc.E[B.eoff + c + 1] = l;  // run total, turned into an offset next
+}
+
+// one workgroup per big table: the run offsets, left to right, through LDS
+__global__ __launch_bounds__(256) void k_big_offsets(const BigInfo* big,
+                                                     BigScratch sc,
+                                                     double* tot) {
+  __shared__ double buf[4096];
+  __shared__ double carry;
+  const BigInfo B = big[blockIdx.x];
+  double* E = sc.E + B.eoff;
+  if (threadIdx.x == 0) {
+    carry = 0.0;
     E[0] = 0.0;
-    for (int64_t c = 0; c < R; ++c) {
-      acc = acc + E[c + 1];
-      E[c + 1] = acc;
-    }
-    tot[s] = acc;
-    sT = acc;
   }
   __syncthreads();
-  const double T = sT;
-  if (!(T > 0.0)) {  // dead table: never sampled, entries zero
-    for (int64_t r = t; r < Np; r += kBigThreads) et[r] = Ent16{0ull, 0u, 0u};
-    return;
+  for (int64_t c0 = 0; c0 < B.R; c0 += 4096) {
+    const int64_t nc = B.R - c0 < 4096 ? B.R - c0 : 4096;
+    for (int64_t u = threadIdx.x; u < nc; u += blockDim.x)
+      buf[u] = E[c0 + u + 1];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double acc = carry;
+      for (int64_t u = 0; u < nc; ++u) {
+        acc = acc + buf[u];
+        buf[u] = acc;
+      }
+      carry = acc;
+    }
+    __syncthreads();
+    for (int64_t u = threadIdx.x; u < nc; u += blockDim.x)
+      E[c0 + u + 1] = buf[u];
+    __syncthreads();
   }
-  // quanta
-  const int K = L + kCapBits;
-  for (int64_t r = t; r < Np; r += kBigThreads) {
+  if (threadIdx.x == 0) tot[B.s] = carry;
+}
+
+// quanta of 4 slots per thread, 1024 slots per block, block statistics
+__global__ __launch_bounds__(256) void k_big_quanta(const BigInfo* big,
+                                                    const uint32_t* btab,
+                                                    const double* tot,
+                                                    BigScratch sc) {
+  const BigInfo B = big[btab[blockIdx.x]];
+  const int64_t g0 = (int64_t)blockIdx.x * kBigBlk + threadIdx.x * 4;
+  const int64_t r0 = g0 - B.so;  // table-relative slot
+  const double T = tot[B.s];
+  const bool live = T > 0.0;
+  const int K = B.L + kCapBits;
+  const double* E = sc.E + B.eoff;
+  const uint64_t* Lb = sc.Lb + B.so;
+  Quad a{0, 0, 0, 0};
+  uint64_t Fp = 0;
+  if (live && r0 > 0 && r0 - 1 < B.N) {
+    const double Pp = E[(r0 - 1) / kRun] +
+                      __longlong_as_double((long long)(Lb[r0 - 1] & kQMask));
+    Fp = (uint64_t)floor(ldexp(Pp / T, K));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = r0 + u;
     uint64_t qq = 0;
-    if (r < N) {
+    if (live && r < B.N) {
       const uint64_t raw = Lb[r];
       const double Pv = E[r / kRun] +
                         __longlong_as_double((long long)(raw & kQMask));
       const uint64_t F = (uint64_t)floor(ldexp(Pv / T, K));
-      uint64_t Fp = 0;
-      if (r > 0) {
-        const double Pp = E[(r - 1) / kRun] +
-                          __longlong_as_double((long long)(Lb[r - 1] & kQMask));
-        Fp = (uint64_t)floor(ldexp(Pp / T, K));
-      }
       qq = (F - Fp) | (raw & ~kQMask);
+      Fp = F;
     }
-    q[r] = qq;
+    sc.q[g0 + u] = qq;
+    slot_stats(qq & kQMask, a);
   }
-  __syncthreads();
-  // light and heavy lists in slot order, 4 slots per thread per round
+  const Quad all = quad_scan256(a);
+  if (threadIdx.x == 0) sc.bs[blockIdx.x] = all;
+}
+
+// one workgroup per big table: exclusive scan of its block statistics
+__global__ __launch_bounds__(256) void k_big_scan(const BigInfo* big,
+                                                  BigScratch sc) {
+  const BigInfo B = big[blockIdx.x];
+  const int64_t b0 = B.so / kBigBlk;
+  const int64_t nb = (int64_t(1) << B.L) / kBigBlk;
   Quad carry{0, 0, 0, 0};
-  for (int64_t base = 0; base < Np; base += 4 * kBigThreads) {
-    const int64_t r0 = base + (int64_t)t * 4;
-    uint64_t qv[4];
-    uint32_t sg[4];
-    Quad a{0, 0, 0, 0};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint64_t raw = r0 + u < Np ? q[r0 + u] : 0ull;
-      qv[u] = raw & kQMask;
-      sg[u] = (uint32_t)(raw >> 63);
-      if (r0 + u < Np) slot_stats(qv[u], a);
-    }
-    const Quad all = block_excl_scan_big(a);
-    uint64_t lp = carry.nl + a.nl, hp = carry.nh + a.nh;
-    uint64_t da = carry.sd + a.sd, ea = carry.se + a.se;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (r0 + u >= Np) continue;
-      const uint32_t id = (uint32_t)(r0 + u) | (sg[u] << 31);
-      if (qv[u] < kCap) {
-        Ld[lp] = da;
-        Li[lp] = id;
-        da += kCap - qv[u];
-        ++lp;
-      } else {
-        ea += qv[u] - kCap;
-        He[hp] = ea;
-        Hi[hp] = id;
-        ++hp;
-      }
-    }
+  for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+    const int64_t i = c0 + threadIdx.x;
+    Quad v = i < nb ? sc.bs[b0 + i] : Quad{0, 0, 0, 0};
+    const Quad all = quad_scan256(v);
+    if (i < nb)
+      sc.bs[b0 + i] = Quad{carry.nl + v.nl, carry.nh + v.nh, carry.sd + v.sd,
+                           carry.se + v.se};
     carry.nl += all.nl;
     carry.nh += all.nh;
     carry.sd += all.sd;
     carry.se += all.se;
   }
+  if (threadIdx.x == 0) {
+    sc.NL[blockIdx.x] = carry.nl;
+    sc.NH[blockIdx.x] = carry.nh;
+    sc.Dt[blockIdx.x] = carry.sd;
+  }
+}
+
+// light / heavy lists in slot order (ids carry the sign in bit 31)
+__global__ __launch_bounds__(256) void k_big_scatter(const BigInfo* big,
+                                                     const uint32_t* btab,
+                                                     BigScratch sc) {
+  const BigInfo B = big[btab[blockIdx.x]];
+  const int64_t g0 = (int64_t)blockIdx.x * kBigBlk + threadIdx.x * 4;
+  uint64_t qv[4];
+  uint32_t sg[4];
+  Quad a{0, 0, 0, 0};
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const uint64_t raw = sc.q[g0 + u];
+    qv[u] = raw & kQMask;
+    sg[u] = (uint32_t)(raw >> 63);
+    slot_stats(qv[u], a);
+  }
+  (void)quad_scan256(a);
+  const Quad o = sc.bs[blockIdx.x];
+  uint64_t lp = o.nl + a.nl, hp = o.nh + a.nh;
+  uint64_t da = o.sd + a.sd, ea = o.se + a.se;
+  uint64_t* Ld = sc.Ld + B.so;
+  uint64_t* He = sc.He + B.so;
+  uint32_t* Li = sc.Li + B.so;
+  uint32_t* Hi = sc.Hi + B.so;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const uint32_t id = (uint32_t)(g0 + u - B.so) | (sg[u] << 31);
+    if (qv[u] < kCap) {
+      Ld[lp] = da;
+      Li[lp] = id;
+      da += kCap - qv[u];
+      ++lp;
+    } else {
+      ea += qv[u] - kCap;
+      He[hp] = ea;
+      Hi[hp] = id;
+      ++hp;
+    }
+  }
+}
+
+// merge-path split at every kBigBlk-th merged position of every big table
+__global__ void k_big_edges(const BigInfo* big, int64_t nbig, int64_t nedges,
+                            BigScratch sc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nedges) return;
+  int64_t lo = 0, hi = nbig - 1;  // last table with edge0 <= e
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (big[mid].edge0 <= e) lo = mid; else hi = mid - 1;
+  }
+  const BigInfo B = big[lo];
+  const int64_t d0 = (e - B.edge0) * kBigBlk;
+  sc.edges[e] = merge_split(sc.Ld + B.so, (int64_t)sc.NL[lo], sc.He + B.so,
+                            (int64_t)sc.NH[lo], d0);
+}
+
+constexpr int kBigMergeP = kBigBlk / 256;
+
+template <class W>
+__global__ __launch_bounds__(256) void k_big_merge(W w, const BigInfo* big,
+                                                   const uint32_t* btab,
+                                                   const double* tot,
+                                                   BigScratch sc, Ent16* ent) {
+  __shared__ uint64_t sD[kBigBlk + 1], sE[kBigBlk + 1];
+  __shared__ uint32_t sLi[kBigBlk + 1], sHi[kBigBlk + 1];
+  const uint32_t bt = btab[blockIdx.x];
+  const BigInfo B = big[bt];
+  const int64_t bi = (int64_t)blockIdx.x - B.so / kBigBlk;
+  const int64_t d0 = bi * kBigBlk;
+  Ent16* et = ent + B.so;
+  if (!(tot[B.s] > 0.0)) {  // dead table: never sampled, entries zero
+    for (int u = threadIdx.x; u < kBigBlk; u += 256)
+      et[d0 + u] = Ent16{0ull, 0u, 0u};
+    return;
+  }
+  const int64_t NL = (int64_t)sc.NL[bt], NH = (int64_t)sc.NH[bt];
+  const uint64_t Dt = sc.Dt[bt];
+  const uint64_t* D = sc.Ld + B.so;
+  const uint64_t* E = sc.He + B.so;
+  const uint32_t* Li = sc.Li + B.so;
+  const uint32_t* Hi = sc.Hi + B.so;
+  const int64_t* ed = sc.edges + B.edge0 + bi;
+  const int64_t a0 = ed[0], b0 = d0 - ed[0];
+  const int64_t na = ed[1] - a0, nb = (d0 + kBigBlk - ed[1]) - b0;
+  for (int u = threadIdx.x; u <= na; u += 256) {
+    sD[u] = a0 + u < NL ? D[a0 + u] : Dt;
+    sLi[u] = a0 + u < NL ? Li[a0 + u] : 0u;
+  }
+  for (int u = threadIdx.x; u <= nb; u += 256) {
+    sE[u] = b0 + u < NH ? E[b0 + u] : ~0ull;
+    sHi[u] = b0 + u < NH ? Hi[b0 + u] : 0u;
+  }
   __syncthreads();
-  const int64_t NL = (int64_t)carry.nl, NH = (int64_t)carry.nh;
-  const uint64_t Dt = carry.sd;
-  // merge: each thread Np / kBigThreads consecutive merged positions
-  const int64_t per = Np / kBigThreads;
-  const int64_t d0 = (int64_t)t * per;
-  int64_t a = merge_split(Ld, NL, He, NH, d0), b = d0 - a;
-  const EmitItems<W> emit{et, w, o, N};
-  for (int64_t step = 0; step < per; ++step) {
-    if (a < NL && (b >= NH || Ld[a] <= He[b])) {
-      const uint32_t id = Li[a];
+  const int64_t dl = (int64_t)threadIdx.x * kBigMergeP;
+  int64_t lo = dl - nb > 0 ? dl - nb : 0, hi = dl < na ? dl : na;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sD[mid] <= sE[dl - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  int64_t a = lo, b = dl - lo;
+  const EmitItems<W> emit{et, w, B.o, B.N};
+  for (int step = 0; step < kBigMergeP; ++step) {
+    if (a < na && (b >= nb || sD[a] <= sE[b])) {
+      const uint32_t id = sLi[a];
       const uint32_t r = id & kLow31;
-      const uint64_t Dn = a + 1 < NL ? Ld[a + 1] : Dt;
-      const uint32_t qv = (uint32_t)(kCap - (Dn - Ld[a]));
-      const uint32_t dn = b < NH ? Hi[b] : id;
+      const uint32_t qv = (uint32_t)(kCap - (sD[a + 1] - sD[a]));
+      const uint32_t dn = b0 + b < NH ? sHi[b] : id;
       emit((int)r, qv, id >> 31, dn & kLow31, dn >> 31);
       ++a;
     } else {
-      const uint32_t id = Hi[b];
+      const uint32_t id = sHi[b];
       const uint32_t r = id & kLow31;
-      const uint64_t Eh = He[b];
-      const uint64_t Dn = a < NL ? Ld[a] : Dt;
-      if (Dn > Eh && b + 1 < NH) {
-        const uint32_t nx = Hi[b + 1];
+      const uint64_t Eh = sE[b];
+      const uint64_t Dn = sD[a];  // D of the next light, or Dt past the end
+      if (Dn > Eh && b0 + b + 1 < NH) {
+        const uint32_t nx = sHi[b + 1];
         emit((int)r, (uint32_t)(Eh + kCap - Dn), id >> 31, nx & kLow31,
              nx >> 31);
       } else {
@@ -660,16 +824,16 @@ __global__ __launch_bounds__(kBigThreads) void k_ragged_big(
 }
 
 // ---------------------------------------------------------------------------
-// host: layout of a family (slot offsets, big tables, run offsets)
+// host: layout of a family (slot offsets, big tables, small-table classes)
 // ---------------------------------------------------------------------------
 static void ragged_free(Ragged& R) {
-  if (R.meta) (void)hipFree(R.meta);
-  if (R.ent) (void)hipFree(R.ent);
-  if (R.tot) (void)hipFree(R.tot);
-  if (R.bigids) (void)hipFree(R.bigids);
-  if (R.runoff) (void)hipFree(R.runoff);
+  dev_free(R.lay);
+  dev_free(R.ent_buf);
+  dev_free(R.tot_buf);
   R = Ragged{};
 }
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
                                 hipStream_t st) {
@@ -679,64 +843,103 @@ static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
   if (e != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess)
     return e;
   std::vector<uint64_t> meta((size_t)S);
-  std::vector<uint32_t> big;
-  std::vector<int64_t> runoff(1, 0);
-  int64_t bs = 0;
+  std::vector<BigInfo> big;
+  std::vector<uint32_t> btab, runtab;
+  std::vector<uint32_t> cls[4];
+  int64_t bs = 0, runs = 0, eoff = 0, edges = 0;
   for (int64_t s = 0; s < S; ++s) {
     const int64_t N = off[(size_t)s + 1] - off[(size_t)s];
-    if (N > 512) {
-      const int L = ceil_log2_i(N);
-      meta[(size_t)s] = (uint64_t)bs | ((uint64_t)L << 56);
-      bs += int64_t(1) << L;
-      big.push_back((uint32_t)s);
-      runoff.push_back(runoff.back() + (N + kRun - 1) / kRun + 1);
-    }
+    if (N <= 512) continue;
+    const int L = ceil_log2_i(N);
+    BigInfo B;
+    B.so = bs;
+    B.o = off[(size_t)s];
+    B.N = N;
+    B.R = (N + kRun - 1) / kRun;
+    B.run0 = runs;
+    B.eoff = eoff;
+    B.edge0 = edges;
+    B.L = L;
+    B.s = (int32_t)s;
+    meta[(size_t)s] = (uint64_t)bs | ((uint64_t)L << 56);
+    const int64_t Np = int64_t(1) << L;
+    for (int64_t b = 0; b < Np / kBigBlk; ++b)
+      btab.push_back((uint32_t)big.size());
+    for (int64_t c = 0; c < B.R; ++c) runtab.push_back((uint32_t)big.size());
+    big.push_back(B);
+    bs += Np;
+    runs += B.R;
+    eoff += B.R + 1;
+    edges += Np / kBigBlk + 1;
   }
   int64_t ss = bs;
   for (int64_t s = 0; s < S; ++s) {
     const int64_t N = off[(size_t)s + 1] - off[(size_t)s];
-    if (N <= 512) {
-      const int L = ceil_log2_i(N);
-      meta[(size_t)s] = (uint64_t)ss | ((uint64_t)L << 56);
-      ss += int64_t(1) << L;
-    }
+    if (N > 512) continue;
+    const int L = ceil_log2_i(N);
+    meta[(size_t)s] = (uint64_t)ss | ((uint64_t)L << 56);
+    ss += int64_t(1) << L;
+    cls[spl_class_host(L)].push_back((uint32_t)s);
   }
-  ragged_free(R);
   R.S = S;
   R.off = off_dev;
   R.slots = ss;
   R.big_slots = bs;
   R.nbig = (int64_t)big.size();
-  R.runs = runoff.back();
-  if ((e = hipMalloc(&R.meta, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess ||
-      (e = hipMalloc(&R.ent, sizeof(Ent16) * (size_t)(ss > 0 ? ss : 1))) !=
+  R.runs = runs;
+  R.edges = edges;
+  R.cls_off[0] = 0;
+  for (int c = 0; c < 4; ++c)
+    R.cls_off[c + 1] = R.cls_off[c] + (int64_t)cls[c].size();
+  // one layout buffer: meta | big | btab | runtab | small ids
+  const size_t b_meta = al256(8 * (size_t)(S > 0 ? S : 1));
+  const size_t b_big = al256(sizeof(BigInfo) * (big.size() + 1));
+  const size_t b_btab = al256(4 * (btab.size() + 1));
+  const size_t b_run = al256(4 * (runtab.size() + 1));
+  const size_t b_ids = al256(4 * (size_t)(R.cls_off[4] + 1));
+  if ((e = dev_alloc(R.lay, b_meta + b_big + b_btab + b_run + b_ids)) !=
           hipSuccess ||
-      (e = hipMalloc(&R.tot, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess ||
-      (e = hipMalloc(&R.bigids, 4 * (big.size() + 1))) != hipSuccess ||
-      (e = hipMalloc(&R.runoff, 8 * runoff.size())) != hipSuccess)
+      (e = dev_alloc(R.ent_buf, sizeof(Ent16) * (size_t)(ss > 0 ? ss : 1))) !=
+          hipSuccess ||
+      (e = dev_alloc(R.tot_buf, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess)
     return e;
-  if (S > 0 &&
-      (e = hipMemcpy(R.meta, meta.data(), 8 * (size_t)S,
-                     hipMemcpyHostToDevice)) != hipSuccess)
-    return e;
-  if (!big.empty() &&
-      (e = hipMemcpy(R.bigids, big.data(), 4 * big.size(),
-                     hipMemcpyHostToDevice)) != hipSuccess)
-    return e;
-  return hipMemcpy(R.runoff, runoff.data(), 8 * runoff.size(),
-                   hipMemcpyHostToDevice);
+  char* p = (char*)R.lay.p;
+  R.meta = (uint64_t*)p;
+  R.big = p + b_meta;
+  R.btab = (uint32_t*)(p + b_meta + b_big);
+  R.runtab = (uint32_t*)(p + b_meta + b_big + b_btab);
+  R.small_ids = (uint32_t*)(p + b_meta + b_big + b_btab + b_run);
+  R.ent = (Ent16*)R.ent_buf.p;
+  R.tot = (double*)R.tot_buf.p;
+  std::vector<char> host(b_meta + b_big + b_btab + b_run + b_ids, 0);
+  memcpy(host.data(), meta.data(), 8 * meta.size());
+  memcpy(host.data() + b_meta, big.data(), sizeof(BigInfo) * big.size());
+  memcpy(host.data() + b_meta + b_big, btab.data(), 4 * btab.size());
+  memcpy(host.data() + b_meta + b_big + b_btab, runtab.data(),
+         4 * runtab.size());
+  char* ids = host.data() + b_meta + b_big + b_btab + b_run;
+  for (int c = 0; c < 4; ++c)
+    memcpy(ids + 4 * R.cls_off[c], cls[c].data(), 4 * cls[c].size());
+  return hipMemcpyAsync(R.lay.p, host.data(), host.size(),
+                        hipMemcpyHostToDevice, st) == hipSuccess
+             ? hipStreamSynchronize(st)
+             : hipErrorInvalidValue;
 }
 
 static size_t big_scratch_bytes(const Ragged& R) {
-  return (size_t)R.big_slots * (8 + 8 + 8 + 8 + 4 + 4) +
-         (size_t)R.runs * 8 + 8 * 256;
+  const size_t n = (size_t)R.big_slots;
+  return al256(n * 8) * 4 + al256(n * 4) * 2 +
+         al256(sizeof(Quad) * (n / kBigBlk + 1)) +
+         al256(8 * (size_t)(R.runs + R.nbig + 1)) +
+         al256(8 * (size_t)(R.nbig + 1)) * 3 +
+         al256(8 * (size_t)(R.edges + 1)) + 256;
 }
 
 static BigScratch big_carve(void* p, const Ragged& R) {
   char* c = (char*)p;
   auto take = [&](size_t bytes) {
     char* r = c;
-    c += (bytes + 255) & ~(size_t)255;
+    c += al256(bytes);
     return r;
   };
   BigScratch b;
@@ -747,7 +950,12 @@ static BigScratch big_carve(void* p, const Ragged& R) {
   b.He = (uint64_t*)take(n * 8);
   b.Li = (uint32_t*)take(n * 4);
   b.Hi = (uint32_t*)take(n * 4);
-  b.E = (double*)take((size_t)R.runs * 8);
+  b.bs = (Quad*)take(sizeof(Quad) * (n / kBigBlk + 1));
+  b.E = (double*)take(8 * (size_t)(R.runs + R.nbig + 1));
+  b.NL = (uint64_t*)take(8 * (size_t)(R.nbig + 1));
+  b.NH = (uint64_t*)take(8 * (size_t)(R.nbig + 1));
+  b.Dt = (uint64_t*)take(8 * (size_t)(R.nbig + 1));
+  b.edges = (int64_t*)take(8 * (size_t)(R.edges + 1));
   return b;
 }
 
@@ -755,19 +963,33 @@ template <class W>
 static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
                                hipStream_t st) {
   if (R.S <= 0) return hipSuccess;
-  const unsigned blocks = blocks_of(R.S, 4);
-  k_ragged_small<1, W><<<blocks, 256, 4 * 64 * 20, st>>>(w, R.off, R.meta,
-                                                          R.S, R.tot, R.ent);
-  k_ragged_small<2, W><<<blocks, 256, 4 * 128 * 20, st>>>(w, R.off, R.meta,
-                                                          R.S, R.tot, R.ent);
-  k_ragged_small<4, W><<<blocks, 256, 4 * 256 * 20, st>>>(w, R.off, R.meta,
-                                                          R.S, R.tot, R.ent);
-  k_ragged_small<8, W><<<blocks, 256, 4 * 512 * 20, st>>>(w, R.off, R.meta,
-                                                          R.S, R.tot, R.ent);
-  if (R.nbig > 0)
-    k_ragged_big<W><<<(unsigned)R.nbig, kBigThreads, 0, st>>>(
-        w, R.off, R.meta, R.bigids, R.runoff, R.tot, R.ent,
-        big_carve(scratch, R));
+  const int64_t* c = R.cls_off;
+  if (c[1] > c[0])
+    k_ragged_small<1, W><<<blocks_of(c[1] - c[0], 4), 256, 4 * 64 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, R.ent);
+  if (c[2] > c[1])
+    k_ragged_small<2, W><<<blocks_of(c[2] - c[1], 4), 256, 4 * 128 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, R.ent);
+  if (c[3] > c[2])
+    k_ragged_small<4, W><<<blocks_of(c[3] - c[2], 4), 256, 4 * 256 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, R.ent);
+  if (c[4] > c[3])
+    k_ragged_small<8, W><<<blocks_of(c[4] - c[3], 4), 256, 4 * 512 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, R.ent);
+  if (R.nbig > 0) {
+    const BigScratch sc = big_carve(scratch, R);
+    const BigInfo* big = (const BigInfo*)R.big;
+    const unsigned nblk = (unsigned)(R.big_slots / kBigBlk);
+    k_big_runs<W><<<blocks_of(R.runs, 256), 256, 0, st>>>(w, big, R.runtab,
+                                                           R.runs, sc);
+    k_big_offsets<<<(unsigned)R.nbig, 256, 0, st>>>(big, sc, R.tot);
+    k_big_quanta<<<nblk, 256, 0, st>>>(big, R.btab, R.tot, sc);
+    k_big_scan<<<(unsigned)R.nbig, 256, 0, st>>>(big, sc);
+    k_big_scatter<<<nblk, 256, 0, st>>>(big, R.btab, sc);
+    k_big_edges<<<blocks_of(R.edges, 256), 256, 0, st>>>(big, R.nbig,
+                                                         R.edges, sc);
+    k_big_merge<W><<<nblk, 256, 0, st>>>(w, big, R.btab, R.tot, sc, R.ent);
+  }
   return hipGetLastError();
 }
 

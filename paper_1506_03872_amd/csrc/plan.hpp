@@ -100,16 +100,21 @@ constexpr uint64_t kSlotMask = (1ull << 56) - 1;
 // Tables of different sizes: table s covers item positions [off[s],
 // off[s+1]) and 2^L_s slots from meta[s] & kSlotMask (L_s = meta[s] >> 56).
 // Tables of more than 512 items ("big", 2^L >= 1024 slots) come first, in
-// index order, then the others in index order.
+// index order, then the others in index order.  The host plans the layout;
+// device arrays are reused across rebuilds while they are large enough.
 struct Ragged {
   int64_t S = 0;
-  int64_t slots = 0, big_slots = 0, nbig = 0, runs = 0;
+  int64_t slots = 0, big_slots = 0, nbig = 0, runs = 0, edges = 0;
+  int64_t cls_off[5] = {0, 0, 0, 0, 0};  // small tables by slots per lane
   const int64_t* off = nullptr;  // S + 1 (device)
   uint64_t* meta = nullptr;      // S (device)
   Ent16* ent = nullptr;          // slots (device)
   double* tot = nullptr;         // S table totals (device)
-  uint32_t* bigids = nullptr;    // nbig big tables (device)
-  int64_t* runoff = nullptr;     // nbig + 1: first run-offset slot (device)
+  void* big = nullptr;           // per big table layout (device)
+  uint32_t* btab = nullptr;      // big table of each 1024-slot block
+  uint32_t* runtab = nullptr;    // big table of each 1024-item run
+  uint32_t* small_ids = nullptr; // small tables grouped by class
+  DeviceBuffer lay, ent_buf, tot_buf;
 };
 
 // sparse inputs as compressed rows of the vector-major arrays

@@ -75,31 +75,37 @@ def powerlaw_csr(rows: int, d: int, nnz_per_vec: int, zipf_a: float = 1.5,
     """CSR (ptr int64, idx int32 ascending, val float32) of ``rows`` vectors,
     each with exactly ``nnz_per_vec`` distinct coordinates.  Coordinates are
     Zipf(zipf_a) ranks 1..d mapped through a fixed random permutation of
-    [0, d) (draws above d are redrawn); duplicates within a vector are
-    redrawn.  Magnitudes lognormal(0,1), signs +-1 with probability 1/2."""
+    [0, d): each vector keeps the first nnz_per_vec distinct draws of rank
+    <= d, in draw order (draws above d and repeats are rejected).
+    Magnitudes lognormal(0,1), signs +-1 with probability 1/2."""
     g = rng("powerlaw_csr", role, seed)
     perm = rng("powerlaw_csr", 100, seed).permutation(d).astype(np.int32)
     z = nnz_per_vec
+    assert z <= d
     idx = np.empty((rows, z), np.int64)
-    filled = np.zeros(rows, np.int64)
     todo = np.arange(rows)
+    draws = np.zeros((rows, 0), np.int64)
+    K = 4 * z
     while todo.size:
-        draw = g.zipf(zipf_a, size=(todo.size, 2 * z))
-        for col in range(2 * z):
-            r = draw[:, col]
-            ok = r <= d
-            cand = np.where(ok, r - 1, -1)
-            f = filled[todo]
-            need = f < z
-            # reject duplicates already in the row
-            dup = np.zeros(todo.size, bool)
-            for c in range(z):
-                dup |= (c < f) & (idx[todo, np.minimum(c, z - 1)] == cand)
-            take = need & ok & ~dup
-            rows_t = todo[take]
-            idx[rows_t, f[take]] = cand[take]
-            filled[rows_t] += 1
-        todo = todo[filled[todo] < z]
+        new = g.zipf(zipf_a, size=(todo.size, K)).astype(np.int64)
+        D = np.concatenate([draws, new], axis=1) if draws.shape[1] else new
+        width = D.shape[1]
+        valid = D <= d
+        # rejected draws get distinct sentinels above d
+        key = np.where(valid, D, d + 1 + np.arange(width)[None, :])
+        order = np.argsort(key, axis=1, kind="stable")
+        ks = np.take_along_axis(key, order, axis=1)
+        first = np.ones_like(ks, dtype=bool)
+        first[:, 1:] = ks[:, 1:] != ks[:, :-1]
+        keep_sorted = first & (ks <= d)
+        keep = np.zeros_like(keep_sorted)
+        np.put_along_axis(keep, order, keep_sorted, axis=1)
+        take = keep & (np.cumsum(keep, axis=1) <= z)
+        done = take.sum(axis=1) == z
+        rows_done = todo[done]
+        idx[rows_done] = D[done][take[done]].reshape(-1, z) - 1
+        todo = todo[~done]
+        draws = D[~done]
     idx = perm[idx]
     idx.sort(axis=1)
     val = g.lognormal(0.0, 1.0, size=(rows, z)).astype(np.float32)
