@@ -122,6 +122,30 @@ int mad_plan_refresh(mad_plan* plan, void* stream);
 int mad_plan_topk(mad_plan* plan, int64_t t, int64_t s, int64_t t_prime,
                   uint64_t seed, mad_pair* out, int64_t* n_out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * mad_plan_set_verify_precision -- arithmetic of the verification of Alg. 3
+ * line "post2" for later mad_plan_topk calls on a dense plan:
+ *   MAD_FP32      (default) fp32 dot products of every candidate;
+ *   MAD_BF16, MAD_FP8_E4M3  every candidate is first computed from bf16 /
+ *                 fp8-e4m3 copies of A and B (per-vector power-of-two scale
+ *                 for fp8, fp32 accumulation) together with an a-priori
+ *                 bound on its error (input rounding, fp32 accumulation of
+ *                 d terms and the fp32 re-rank's own error; Higham,
+ *                 "Accuracy and Stability of Numerical Algorithms", Sec. 3.1);
+ *                 only candidates whose upper bound reaches the t-th largest
+ *                 lower bound are verified in fp32.  The result is the same
+ *                 as with MAD_FP32, with fewer fp32 rows read.
+ * Builds the copies (device memory, kept in the plan and rebuilt by
+ * mad_plan_refresh).  MAD_EUNSUPPORTED for sparse plans.
+ * ------------------------------------------------------------------------- */
+int mad_plan_set_verify_precision(mad_plan* plan, int precision, void* stream);
+
+/* Candidates of the last mad_plan_topk (host outputs, synchronises):
+ * n_cand = |Omega_t'|, n_reranked = how many were verified in fp32 (equal
+ * to n_cand under MAD_FP32 verification).  Either pointer may be NULL. */
+int mad_plan_verify_stats(mad_plan* plan, int64_t* n_cand,
+                          int64_t* n_reranked);
+
 /* One-shot form of the two calls above for dense inputs:
  * create + topk + destroy.  Synchronises `stream` before returning. */
 int mad_topk(const float* A, int64_t m, const float* B, int64_t n, int64_t d,

@@ -29,7 +29,8 @@ EXPORTS = (
     "mad_fix_exponent", "mad_plan_phase_ms", "mad_probe_memory",
     "mad_bruteforce_topk", "mips_plan_create", "mips_topk_batch",
     "mips_get_config", "mips_set_config", "mips_autotune", "mips_stats",
-    "mips_debug_scores",
+    "mips_debug_scores", "mad_plan_set_verify_precision",
+    "mad_plan_verify_stats",
 )
 
 
@@ -75,6 +76,8 @@ def lib():
         L.mad_probe_memory.argtypes = [C.c_int, _P, _i64, _i64, _u64, _P]
         L.mad_bruteforce_topk.argtypes = [_P, _i64, _P, _i64, _i64, C.c_int,
                                           _i64, _i64, _P, _P, _P, _P]
+        L.mad_plan_set_verify_precision.argtypes = [_P, C.c_int, _P]
+        L.mad_plan_verify_stats.argtypes = [_P, _P, _P]
         L.mips_plan_create.argtypes = [_P, _i64, _i64, _u32, _P,
                                        C.POINTER(_P)]
         L.mips_topk_batch.argtypes = [_P, _P, _i64, _P, _P, _i64, _u64, _P,
@@ -205,6 +208,15 @@ class Plan:
                                     C.byref(di), C.byref(npos), C.byref(nc)))
         return dict(wnorm=w.value, closed=cl.value, distinct=di.value,
                     n_pos=npos.value, n_cand=nc.value)
+
+    def set_verify_precision(self, precision, stream=None):
+        _check(lib().mad_plan_set_verify_precision(self._h, precision,
+                                                   _stream(stream)))
+
+    def verify_stats(self):
+        nc, nr = C.c_int64(), C.c_int64()
+        _check(lib().mad_plan_verify_stats(self._h, C.byref(nc), C.byref(nr)))
+        return dict(n_cand=nc.value, n_reranked=nr.value)
 
     def phase_ms(self):
         """[tables, sampler, postprocess, clear] ms of the last calls (needs

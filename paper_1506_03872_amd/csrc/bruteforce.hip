@@ -56,13 +56,6 @@ constexpr int kLdsStride = kRowBytes + 16;
 // per-vector scale (fp8: a power of two), L2 and L1 norms of the fp32
 // vector and the absolute rounding floor eta (in the vector's own units)
 // ---------------------------------------------------------------------------
-struct VecInfo {
-  float n2;     // ||x||_2, rounded up
-  float n1;     // ||x||_1, rounded up
-  float eta;    // absolute rounding floor of one element
-  float inv_s;  // 1 / scale applied before rounding
-};
-
 __device__ __forceinline__ uint8_t to_fp8(float x) {
   // round to nearest even into e4m3; |x| < 2^7 after scaling
   const unsigned pk = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false);
@@ -384,6 +377,36 @@ static void launch_gemm(const GemmArgs& a, bool hist, hipStream_t st) {
   if (grid < 1) grid = 1;
   if (hist) k_gemm_topk<P, true><<<(unsigned)grid, 256, 0, st>>>(a);
   else k_gemm_topk<P, false><<<(unsigned)grid, 256, 0, st>>>(a);
+}
+
+hipError_t lowp_prepare(const float* X, int64_t rows, int64_t d, int prec,
+                        DeviceBuffer& data, DeviceBuffer& info, int64_t* Kp,
+                        hipStream_t st) {
+  const int KC = prec == kBF16 ? 64 : 128;
+  const int EB = prec == kBF16 ? 2 : 1;
+  if (prec != kBF16 && prec != kFP8) return hipErrorInvalidValue;
+  const int64_t kp = (d + KC - 1) / KC * KC;
+  hipError_t e;
+  if ((e = dev_alloc(data, (size_t)rows * kp * EB)) != hipSuccess ||
+      (e = dev_alloc(info, (size_t)rows * sizeof(VecInfo))) != hipSuccess)
+    return e;
+  const unsigned g = (unsigned)((rows + 3) / 4);
+  if (prec == kBF16)
+    k_prep<kBF16><<<g, 256, 0, st>>>(X, rows, d, kp, data.p,
+                                      (VecInfo*)info.p);
+  else
+    k_prep<kFP8><<<g, 256, 0, st>>>(X, rows, d, kp, data.p,
+                                     (VecInfo*)info.p);
+  *Kp = kp;
+  return hipGetLastError();
+}
+
+void lowp_consts(int prec, int64_t d, float* kappa, float* onepu) {
+  const double u = prec == kF32 ? 0.0 : prec == kBF16 ? ldexp(1.0, -8)
+                                                       : ldexp(1.0, -4);
+  const double g = gamma_d(d);
+  *kappa = (float)((2 * u + u * u + g * (1 + u) * (1 + u) + g) * (1 + 1e-5));
+  *onepu = (float)((1 + u) * (1 + 1e-5));
 }
 
 hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,

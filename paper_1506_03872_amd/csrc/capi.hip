@@ -94,6 +94,10 @@ struct mad_plan {
   mad::DenseTables dt;
   mad::CsrTables ct;
   mad::DeviceBuffer build;
+  // low-precision copies for the verification filter (dense plans)
+  int verify_prec = MAD_FP32;
+  mad::DeviceBuffer lpA, lpB, lpIA, lpIB;
+  mad::LowpView lv{};
   // workspace of mad_plan_topk
   mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc;
   mad::HashTable h;
@@ -151,6 +155,10 @@ static void plan_free_all(mad_plan* p) {
   mad::dev_free(p->ck2);
   mad::dev_free(p->cc);
   mad::dev_free(p->misc);
+  mad::dev_free(p->lpA);
+  mad::dev_free(p->lpB);
+  mad::dev_free(p->lpIA);
+  mad::dev_free(p->lpIB);
   for (hipEvent_t& e : p->ev)
     if (e) {
       (void)hipEventDestroy(e);
@@ -241,6 +249,13 @@ int mad_plan_refresh(mad_plan* p, void* stream) {
   }
   HIP_TRY(mad::dense_tables_build(p->dt, p->A, p->B, check, p->build, st),
           "building tables");
+  if (p->verify_prec != MAD_FP32) {
+    int64_t kp = 0;
+    HIP_TRY(mad::lowp_prepare(p->A, p->m, p->d, p->verify_prec, p->lpA,
+                              p->lpIA, &kp, st), "low-precision copies");
+    HIP_TRY(mad::lowp_prepare(p->B, p->n, p->d, p->verify_prec, p->lpB,
+                              p->lpIB, &kp, st), "low-precision copies");
+  }
   record(p, 1, st);
   p->timed_tables = p->ev[0] != nullptr;
   p->ran = false;
@@ -342,9 +357,10 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
             "sampling");
   record(p, 4, st);
   HIP_TRY(mad::launch_postprocess(p->h, p->A, p->B,
-                                  p->kind == 2 ? &p->ct.in : nullptr, p->n,
-                                  p->d, tp_eff, t, plan_bmax(p), s, p->w, out,
-                                  n_out, st),
+                                  p->kind == 2 ? &p->ct.in : nullptr,
+                                  p->verify_prec != MAD_FP32 ? &p->lv : nullptr,
+                                  p->n, p->d, tp_eff, t, plan_bmax(p), s, p->w,
+                                  out, n_out, st),
           "postprocessing");
   record(p, 5, st);
   p->timed_topk = p->ev[0] != nullptr;
@@ -378,7 +394,7 @@ int mad_plan_stats(mad_plan* p, double* wnorm, int64_t* closed,
   if (wnorm)
     HIP_TRY(hipMemcpy(wnorm, plan_wtot(p), sizeof(double),
                       hipMemcpyDeviceToHost), "stats");
-  int64_t cnt[4] = {0, 0, 0, 0};
+  int64_t cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   mad::SampleCounters sc;
   memset(&sc, 0, sizeof sc);
   if (p->ran) {
@@ -390,7 +406,8 @@ int mad_plan_stats(mad_plan* p, double* wnorm, int64_t* closed,
   if (closed) *closed = (int64_t)sc.closed;
   if (distinct) *distinct = (int64_t)sc.distinct;
   if (n_pos) *n_pos = cnt[mad::kCountPos];
-  if (n_cand) *n_cand = cnt[mad::kCountCand];
+  if (n_cand) *n_cand = p->verify_prec != MAD_FP32 ? cnt[7]
+                                                   : cnt[mad::kCountCand];
   return MAD_OK;
 }
 
@@ -410,6 +427,46 @@ int mad_plan_phase_ms(mad_plan* p, double* ms, int n) {
             "phase timing");
     ms[q] = f;
   }
+  return MAD_OK;
+}
+
+int mad_plan_set_verify_precision(mad_plan* p, int precision, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (precision != MAD_FP32 && precision != MAD_BF16 &&
+      precision != MAD_FP8_E4M3)
+    return fail(MAD_EINVAL, "unknown precision %d", precision);
+  if (p->kind != 0 && precision != MAD_FP32)
+    return fail(MAD_EUNSUPPORTED, "low-precision verification needs a dense plan");
+  p->verify_prec = precision;
+  if (precision == MAD_FP32) return MAD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int64_t kp = 0;
+  HIP_TRY(mad::lowp_prepare(p->A, p->m, p->d, precision, p->lpA, p->lpIA, &kp,
+                            st), "low-precision copies");
+  HIP_TRY(mad::lowp_prepare(p->B, p->n, p->d, precision, p->lpB, p->lpIB, &kp,
+                            st), "low-precision copies");
+  p->lv.A = p->lpA.p;
+  p->lv.B = p->lpB.p;
+  p->lv.ia = (const mad::VecInfo*)p->lpIA.p;
+  p->lv.ib = (const mad::VecInfo*)p->lpIB.p;
+  p->lv.Kp = kp;
+  p->lv.prec = precision;
+  p->lv.d_f = (float)p->d;
+  mad::lowp_consts(precision, p->d, &p->lv.kappa, &p->lv.onepu);
+  return MAD_OK;
+}
+
+int mad_plan_verify_stats(mad_plan* p, int64_t* n_cand, int64_t* n_reranked) {
+  if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (!p->ran) return fail(MAD_EINVAL, "no mad_plan_topk has run");
+  HIP_TRY(hipDeviceSynchronize(), "verify stats");
+  int64_t cnt[9];
+  HIP_TRY(hipMemcpy(cnt, p->w.counts, sizeof cnt, hipMemcpyDeviceToHost),
+          "verify stats");
+  const bool lp = p->verify_prec != MAD_FP32;
+  if (n_cand) *n_cand = lp ? cnt[7] : cnt[mad::kCountCand];
+  if (n_reranked) *n_reranked = lp ? cnt[8] : cnt[mad::kCountCand];
   return MAD_OK;
 }
 

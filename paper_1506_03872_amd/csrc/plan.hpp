@@ -259,12 +259,45 @@ hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,
                               int64_t* xfix, int64_t out_cap, int64_t* count,
                               hipStream_t st);
 
-// csr: sparse inputs for the verification (A, B unused), or null
+// Per-vector data of a low-precision copy: norms of the fp32 vector, the
+// absolute rounding floor of one element and the inverse of the
+// power-of-two scale applied before rounding.
+struct VecInfo {
+  float n2;     // ||x||_2, rounded up
+  float n1;     // ||x||_1, rounded up
+  float eta;    // absolute rounding floor of one element
+  float inv_s;  // 1 / scale applied before rounding
+};
+
+// low-precision copies of A and B (rows of Kp elements) for the
+// verification filter, with the margin constants of their error bound
+struct LowpView {
+  const void* A;
+  const void* B;
+  const VecInfo* ia;
+  const VecInfo* ib;
+  int64_t Kp;
+  int prec;      // MAD_BF16 or MAD_FP8_E4M3
+  float kappa;   // relative margin factor on ||a||_2 ||b||_2
+  float onepu;   // 1 + u (absolute-floor terms)
+  float d_f;     // d
+};
+
+// bruteforce.hip: the padded low-precision copy of X and its VecInfo
+hipError_t lowp_prepare(const float* X, int64_t rows, int64_t d, int prec,
+                        DeviceBuffer& data, DeviceBuffer& info, int64_t* Kp,
+                        hipStream_t st);
+void lowp_consts(int prec, int64_t d, float* kappa, float* onepu);
+
+// csr: sparse inputs for the verification (A, B unused), or null; lowp:
+// low-precision filter of the candidates before the fp32 verification, or
+// null
 hipError_t launch_postprocess(const HashTable& h, const float* A,
-                              const float* B, const CsrView* csr, int64_t n,
-                              int64_t d, int64_t t_prime, int64_t t,
-                              const float* bmax, int64_t s, SelectWork& w,
-                              void* out, int64_t* n_out, hipStream_t st);
+                              const float* B, const CsrView* csr,
+                              const LowpView* lowp, int64_t n, int64_t d,
+                              int64_t t_prime, int64_t t, const float* bmax,
+                              int64_t s, SelectWork& w, void* out,
+                              int64_t* n_out, hipStream_t st);
 
 // fp32 re-rank of candidate keys (count known on the host) and the exact
 // top t by |c| into mad_pair records; buf is grown as needed

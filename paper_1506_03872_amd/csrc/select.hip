@@ -32,7 +32,9 @@ enum {
   kCntCand = kCountCand,         // |Omega_t'|
   kCntFinal = kCountFinal,       // |Omega_t|
   kCntBound = 4,                 // boundary list length
-  kCntWin = 5                    // elements taken outright
+  kCntWin = 5,                   // elements taken outright
+  kCntPreFilter = 7,             // |Omega_t'| before the low-precision filter
+  kCntReranked = 8               // candidates left for fp32 verification
 };
 
 // coarse decision of one selection
@@ -406,6 +408,140 @@ __global__ __launch_bounds__(256) void k_verify_csr(const uint64_t* key2,
   block_hist_flush(h, hist);
 }
 
+// ---------------------------------------------------------------------------
+// low-precision filter of Omega_t' (between post1 and post2): c^ from the
+// bf16 / fp8 copies with an a-priori bound mg on |c^ - c_fp32| (input
+// rounding, fp32 accumulation, and the fp32 re-rank's own error).  With
+// tau <= the t-th largest lower bound |c^| - mg, a candidate whose upper
+// bound |c^| + mg is below tau has |c_fp32| < tau while t others have
+// |c_fp32| >= tau, so dropping it leaves the fp32 top t unchanged.
+// 16 lanes per candidate, 16-byte loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float lowp_dot16(const uint4 x, const uint4 y,
+                                            int prec, float acc) {
+  const uint32_t xa[4] = {x.x, x.y, x.z, x.w};
+  const uint32_t ya[4] = {y.x, y.y, y.z, y.w};
+  if (prec == 1) {  // bf16: 8 per load
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc = fmaf(__uint_as_float(xa[q] << 16), __uint_as_float(ya[q] << 16),
+                 acc);
+      acc = fmaf(__uint_as_float(xa[q] & 0xFFFF0000u),
+                 __uint_as_float(ya[q] & 0xFFFF0000u), acc);
+    }
+  } else {  // fp8 e4m3: 16 per load
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 0),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 0), acc);
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 1),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 1), acc);
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 2),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 2), acc);
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 3),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 3), acc);
+    }
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_verify_lowp(const uint64_t* key2,
+                                                     int64_t* counts,
+                                                     LowpView v, int64_t n,
+                                                     int64_t cap2, float* hi,
+                                                     unsigned* hist) {
+  __shared__ unsigned h[kBins];
+  __shared__ unsigned long long part[4];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const int64_t ncand = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
+  const int lane = threadIdx.x & 63, grp = lane >> 4, gl = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int eb = v.prec == 1 ? 2 : 1;
+  const int64_t row_bytes = v.Kp * eb;
+  unsigned long long npos = 0;
+  for (int64_t e0 = wave * 4; e0 < ncand; e0 += nwaves * 4) {
+    const int64_t e = e0 + grp;
+    const bool ok = e < ncand;
+    const uint64_t kk = key2[ok ? e : e0];
+    const int64_t i = (int64_t)(kk / (uint64_t)n);
+    const int64_t j = (int64_t)(kk % (uint64_t)n);
+    const char* ar = (const char*)v.A + i * row_bytes;
+    const char* br = (const char*)v.B + j * row_bytes;
+    float acc = 0.0f;
+    for (int64_t b0 = (int64_t)gl * 16; b0 < row_bytes; b0 += 256) {
+      const uint4 x = *(const uint4*)(ar + b0);
+      const uint4 y = *(const uint4*)(br + b0);
+      acc = lowp_dot16(x, y, v.prec, acc);
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (ok && gl == 0) {
+      const VecInfo va = v.ia[i], vb = v.ib[j];
+      const float c = acc * va.inv_s * vb.inv_s;
+      const float mg = v.kappa * va.n2 * vb.n2 +
+                       v.onepu * (va.eta * vb.n1 + vb.eta * va.n1) +
+                       v.d_f * va.eta * vb.eta;
+      const float lo = fabsf(c) - mg;
+      hi[e] = fabsf(c) + mg;
+      if (lo > 0.0f) {
+        ++npos;
+        atomicAdd(&h[fbin_float(__float_as_uint(lo))], 1u);
+      }
+    }
+  }
+  block_hist_flush(h, hist);
+  npos = wave_sum(npos);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = npos;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long tt = part[0] + part[1] + part[2] + part[3];
+    if (tt) atomicAdd((unsigned long long*)&counts[kCntWin], tt);
+  }
+}
+
+// keep the candidates whose upper bound reaches tau (lower edge of the bin
+// of the t-th largest lower bound; 0 when fewer than t are positive)
+__global__ __launch_bounds__(256) void k_lowp_filter(
+    const Coarse* cz, const uint64_t* key2, const uint64_t* x2,
+    const float* hi, int64_t cap2, uint64_t* okey, uint64_t* ox,
+    int64_t* counts) {
+  __shared__ unsigned wcount[4];
+  __shared__ unsigned long long wbase[5];
+  const Coarse c = *cz;
+  const float tau = c.bin >= 0 ? __uint_as_float((uint32_t)c.bin << 20) : 0.0f;
+  const int64_t n = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
+    const int64_t e = b0 + threadIdx.x;
+    const bool keep = e < n && hi[e] >= tau;
+    const int64_t p = block_append(
+        keep, (unsigned long long*)&counts[kCntBound], wcount, wbase);
+    if (keep) {
+      okey[p] = key2[e];
+      ox[p] = x2[e];
+    }
+  }
+}
+
+// the kept candidates become Omega for post2 / post3
+__global__ void k_lowp_copy(const uint64_t* key, const uint64_t* x,
+                            uint64_t* key2, uint64_t* x2, int64_t* counts) {
+  const int64_t kept = counts[kCntBound];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < kept;
+       e += stride) {
+    key2[e] = key[e];
+    x2[e] = x[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counts[kCntPreFilter] = counts[kCntCand];
+    counts[kCntReranked] = kept;
+    counts[kCntCand] = kept;
+  }
+}
+
 // post3 step 2b: split the candidates
 __global__ __launch_bounds__(256) void k_cand_split(
     const Coarse* cz, const uint64_t* absbits, const uint64_t* key2,
@@ -615,10 +751,11 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
 }
 
 hipError_t launch_postprocess(const HashTable& h, const float* A,
-                              const float* B, const CsrView* csr, int64_t n,
-                              int64_t d, int64_t t_prime, int64_t t,
-                              const float* bmax, int64_t s, SelectWork& w,
-                              void* out, int64_t* n_out, hipStream_t st) {
+                              const float* B, const CsrView* csr,
+                              const LowpView* lowp, int64_t n, int64_t d,
+                              int64_t t_prime, int64_t t, const float* bmax,
+                              int64_t s, SelectWork& w, void* out,
+                              int64_t* n_out, hipStream_t st) {
   Coarse* cz = (Coarse*)w.state;
   int64_t* counts = w.counts;
   // keep counts[kCntDistinct] (the sampler's), clear the others
@@ -641,6 +778,18 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   k_fine_select<<<1, kFineThreads, 0, st>>>(
       cz, w.x, w.key, nullptr, nullptr, w.cap, counts, kCntWin, w.x2, w.key2,
       nullptr, nullptr, w.cap2, kCntCand);
+  // ---- low-precision filter of Omega_t' ----------------------------------
+  if (lowp) {
+    e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
+    if (e != hipSuccess) return e;
+    k_verify_lowp<<<blocks_for(t_prime * 16, 256, 2048), 256, 0, st>>>(
+        w.key2, counts, *lowp, n, w.cap2, w.c, w.hist);
+    k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntWin], t, cz + 2);
+    k_lowp_filter<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
+        cz + 2, w.key2, w.x2, w.c, w.cap2, w.x, w.key, counts);
+    k_lowp_copy<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
+        w.x, w.key, w.key2, w.x2, counts);
+  }
   // ---- post2: fp32 dot products and the |c| histogram --------------------
   // (|c| bits go to w.x, free after post1)
   if (csr)
