@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the time-to-recall sweep")
     return ap.parse_args()
 
 
@@ -420,6 +422,11 @@ def main():
     t_sample = (3.0 / ceil["rand_load_8B"] + 1.0 / ceil["rand_load_4B"] +
                 1.0 / ceil["rand_cas_then_add_16B"]) * 1e-9
     bound_rate = 1.0 / t_sample
+    if traffic:
+        roofline["line_traffic_GBps"] = round(traffic / (sampler_ms * 1e-3)
+                                              / 1e9, 1)
+        roofline["line_traffic_frac"] = round(
+            roofline["line_traffic_GBps"] / HBM_PEAK_GBS, 4)
     roofline["random_access"] = {
         "ceilings_Gops": {k: round(v, 3) for k, v in ceil.items()},
         "bound_samples_per_s": round(bound_rate, 1),
@@ -429,15 +436,24 @@ def main():
     if not args.no_recall:
         log("exact top-t for recall")
         ek, ev = exact_topk_gpu(A, B, t)
-        keys = (res["i"].cpu().numpy() * n + res["j"].cpu().numpy())
-        c64 = (A_h[keys // n].astype(np.float64) *
-               B_h[keys % n].astype(np.float64)).sum(1)
         tau = float(np.sort(ev)[::-1][t - 1])
-        extra["recall_at_t"] = float(np.count_nonzero(np.abs(c64) >= tau)) / t
+
+        def recall_of(i_arr, j_arr):
+            keys = i_arr * n + j_arr
+            c64 = (A_h[keys // n].astype(np.float64) *
+                   B_h[keys % n].astype(np.float64)).sum(1)
+            return float(np.count_nonzero(np.abs(c64) >= tau)) / t, keys
+
+        rec, keys = recall_of(res["i"].cpu().numpy(), res["j"].cpu().numpy())
+        extra["recall_at_t"] = rec
         if "planted_i" in data:
             pk = set((data["planted_i"] * n + data["planted_j"]).tolist())
             extra["planted_found"] = len(pk & set(keys.tolist()))
             extra["planted_total"] = len(pk)
+        if not args.no_sweep:
+            extra["time_to_recall"] = time_to_recall(
+                args, mad, plan, A, B, t, tp, recall_of)
+    plan.close()
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -472,8 +488,77 @@ def main():
         "cpu_baseline": base,
     }
     line.update(extra)
-    plan.close()
     print(json.dumps(line))
+
+
+def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, target=0.95,
+                   seeds=5):
+    """Median wall time of whole steps (tables + sampling + Alg. 3) to reach
+    mean threshold-recall@t >= target over `seeds` seeds, s on a x sqrt(10)
+    grid, against the MFMA brute force (median of 5).  The sweep stops when
+    a step takes 10x the fp32 brute force."""
+    import numpy as np
+    import torch
+    bf = {}
+    for name, prec, ts in (("fp32", mad.MAD_FP32, 0),
+                           ("bf16", mad.MAD_BF16, 0),
+                           ("bf16_screen", mad.MAD_BF16, 20 * t),
+                           ("fp8_screen", mad.MAD_FP8_E4M3, 20 * t)):
+        times = []
+        for r in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, st = mad.bruteforce_topk(A, B, t, precision=prec,
+                                          t_screen=ts)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        rec, _ = recall_of(res["i"].cpu().numpy(), res["j"].cpu().numpy())
+        bf[name] = {"ms": round(float(np.median(times)), 3),
+                    "recall": rec, "candidates": st["candidates"]}
+        log("brute force %s: %.2f ms recall %.3f" % (name, bf[name]["ms"], rec))
+    limit = 10 * bf["fp32"]["ms"]
+    out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sweep, reached = [], None
+    s = 100_000
+    while True:
+        recs, walls, amort = [], [], []
+        for seed in range(seeds):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.refresh()
+            plan.topk_raw(t, s, tp, seed, out, n_out)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+            ph = plan.phase_ms()
+            amort.append(ph[1] + ph[2] + ph[3])
+            r = mad.unpack_pairs(out, int(n_out.item()))
+            recs.append(recall_of(r["i"].cpu().numpy(),
+                                  r["j"].cpu().numpy())[0])
+        pt = {"s": s, "recall_mean": round(float(np.mean(recs)), 4),
+              "ms_end_to_end": round(float(np.median(walls)), 3),
+              "ms_amortized": round(float(np.median(amort)), 3)}
+        sweep.append(pt)
+        log("sweep s=%d recall %.3f %.2f ms" % (s, pt["recall_mean"],
+                                                pt["ms_end_to_end"]))
+        if pt["recall_mean"] >= target:
+            reached = pt
+            break
+        nxt = int(round(s * 10 ** 0.5))
+        # the score table holds 2 min(s, mn) 16-byte slots: stay below 64 GB
+        if pt["ms_end_to_end"] > limit or 32 * nxt > (64 << 30):
+            break
+        s = nxt
+    best = max(sweep, key=lambda p: p["recall_mean"])
+    return {"target": target, "seeds": seeds, "t_prime": tp,
+            "reached": reached is not None,
+            "s_at_target": reached["s"] if reached else None,
+            "ms_at_target": reached["ms_end_to_end"] if reached else None,
+            "ms_at_target_amortized": (reached["ms_amortized"]
+                                       if reached else None),
+            "best_recall": best["recall_mean"], "best_s": best["s"],
+            "stop_rule": "step time > 10x fp32 brute force (%.1f ms)" % limit,
+            "bruteforce": bf, "sweep": sweep}
 
 
 if __name__ == "__main__":
