@@ -53,6 +53,8 @@ _P = C.c_void_p
 def _declare(L):
     L.orc_philox4x64_10.argtypes = [_P, _P, _P]
     L.orc_prefix.argtypes = [_P, _i64, _P]
+    L.orc_run_length.argtypes = []
+    L.orc_run_length.restype = C.c_int
     L.orc_quanta.argtypes = [_P, _i64, _P]
     L.orc_quanta.restype = C.c_int
     L.orc_alias.argtypes = [_P, C.c_int, _P, _P]
@@ -101,6 +103,11 @@ def philox4x64_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, np.uint64)
     lib().orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def run_length() -> int:
+    """Run length of the two-level summation order (reading R3)."""
+    return int(lib().orc_run_length())
 
 
 def prefix(w) -> np.ndarray:

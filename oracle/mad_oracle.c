@@ -48,7 +48,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define RUN 1024               /* R3: run length of the two-level sum      */
+#define RUN 128                /* R3: run length of the two-level sum      */
 #define CAP_BITS 31            /* R4: alias slot capacity 2^31             */
 #define CAP ((uint64_t)1 << CAP_BITS)
 #define COIN_MASK (CAP - 1)
@@ -102,6 +102,9 @@ void orc_prefix(const double *w, int64_t N, double *P) {
     E = E + l; /* offset of the next run */
   }
 }
+
+/* the run length of R3 (for the tests) */
+int orc_run_length(void) { return RUN; }
 
 static int ceil_log2(int64_t N) {
   int L = 0;

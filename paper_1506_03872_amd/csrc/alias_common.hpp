@@ -111,14 +111,6 @@ __device__ __forceinline__ int64_t merge_split(const uint64_t* D, int64_t NL,
   return lo;
 }
 
-// FP64 value of lane k (wave-uniform result)
-__device__ __forceinline__ double readlane_f64(double x, int k) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), k);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 // emitter of packed 8-byte entries into et[r]
 struct EmitPacked {
   uint64_t* et;

@@ -435,14 +435,83 @@ static inline int spl_class_host(int L) {  // 0..3 for 1, 2, 4, 8 slots/lane
 }
 
 // ---------------------------------------------------------------------------
-// tables of at most 512 items: one wave per table; a launch serves the
-// tables of one slots-per-lane class (ids[0 .. count)); every wave of the
-// block calls wave_alias, which synchronises the block
+// tables of at most 512 items.  Quanta: one lane per table (ids of every
+// small table), the total in the two-level order, then the prefix again
+// with F_r and q_r (sign bit in bit 63), into q at the table's slots.  Alias: one wave
+// per table of one slots-per-lane class; every wave of the block calls
+// wave_alias, which synchronises the block.
 // ---------------------------------------------------------------------------
-template <int SPL, class W>
-__global__ __launch_bounds__(256) void k_ragged_small(
+template <class W>
+__global__ __launch_bounds__(64) void k_ragged_lane_quanta(
     W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
-    int64_t count, double* tot, Ent16* ent) {
+    int64_t count, double* tot, uint64_t* q) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const int64_t seg = ids[g];
+  const uint64_t mt = meta[seg];
+  const int L = (int)(mt >> 56);
+  const int64_t Np = int64_t(1) << L;
+  uint64_t* qs = q + (int64_t)(mt & kSlotMask);
+  const int64_t o = off[seg];
+  const int64_t N = off[seg + 1] - o;
+  // two-level order: l restarts at each run, P_r = E + l_r
+  double E = 0.0, l = 0.0;
+  for (int64_t r0 = 0; r0 < N; r0 += 8) {
+    double wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) wv[u] = w.w(o + (r0 + u < N ? r0 + u : N - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + u;
+      if (r < N) {
+        if (r > 0 && r % kRun == 0) {
+          E = E + l;
+          l = 0.0;
+        }
+        l = l + wv[u];
+      }
+    }
+  }
+  const double T = E + l;
+  tot[seg] = T;
+  const bool live = T > 0.0;
+  const int K = L + kCapBits;
+  E = 0.0;
+  l = 0.0;
+  uint64_t Fp = 0;
+  for (int64_t r0 = 0; r0 < Np; r0 += 8) {
+    double wv[8];
+    uint32_t sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t rr = o + (r0 + u < N ? r0 + u : N - 1);
+      wv[u] = live ? w.w(rr) : 0.0;
+      sv[u] = live ? w.sgn(rr) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + u;
+      if (r >= Np) break;
+      uint64_t qq = 0;
+      if (live && r < N) {
+        if (r > 0 && r % kRun == 0) {
+          E = E + l;
+          l = 0.0;
+        }
+        l = l + wv[u];
+        const uint64_t F = (uint64_t)floor(ldexp((E + l) / T, K));
+        qq = (F - Fp) | ((uint64_t)sv[u] << 63);
+        Fp = F;
+      }
+      qs[r] = qq;
+    }
+  }
+}
+
+template <int SPL, class W>
+__global__ __launch_bounds__(256) void k_ragged_alias(
+    W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
+    int64_t count, const double* tot, const uint64_t* q, Ent16* ent) {
   extern __shared__ uint64_t smem64[];
   constexpr int NpMax = 64 * SPL;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -453,49 +522,20 @@ __global__ __launch_bounds__(256) void k_ragged_small(
   const int L = (int)(mt >> 56);
   const int64_t so = (int64_t)(mt & kSlotMask);
   const int64_t o = off[seg];
-  const int N = mine ? (int)(off[seg + 1] - o) : 0;
+  const int64_t N = off[seg + 1] - o;
   const int Np = 1 << L;
-  double P[SPL];
+  const bool active = mine && tot[seg] > 0.0;
+  if (mine && !active)  // dead table: never sampled, entries zero
+    for (int r = lane; r < Np; r += 64) ent[so + r] = Ent16{0ull, 0u, 0u};
+  uint64_t qv[SPL];
   uint32_t sg[SPL];
 #pragma unroll
   for (int s = 0; s < SPL; ++s) {
     const int r = lane * SPL + s;
-    P[s] = r < N ? w.w(o + r) : 0.0;
-    sg[s] = r < N ? w.sgn(o + r) : 0u;
+    const uint64_t raw = active && r < Np ? q[so + r] : 0ull;
+    qv[s] = raw & kQMask;
+    sg[s] = (uint32_t)(raw >> 63);
   }
-  // left-to-right prefix: lane k adds its items to the sum of lanes < k
-  const int last_lane = N > 0 ? (N - 1) / SPL : 0;
-  double carry = 0.0;
-  for (int k = 0; k <= last_lane; ++k) {
-    if (lane == k) {
-#pragma unroll
-      for (int s = 0; s < SPL; ++s) {
-        carry = carry + P[s];
-        P[s] = carry;
-      }
-    }
-    carry = readlane_f64(carry, k);
-  }
-  const double T = carry;
-  if (mine && lane == 0) tot[seg] = T;
-  const bool active = mine && T > 0.0;
-  const int K = L + kCapBits;
-  uint64_t F[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    F[s] = active && r < N ? (uint64_t)floor(ldexp(P[s] / T, K)) : 0ull;
-  }
-  const uint64_t Fin = __shfl_up(F[SPL - 1], 1, 64);
-  uint64_t qv[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    const uint64_t Fp = s > 0 ? F[s - 1] : (lane > 0 ? Fin : 0ull);
-    qv[s] = active && r < N ? F[s] - Fp : 0ull;
-  }
-  if (mine && !active)  // dead table: never sampled, entries zero
-    for (int r = lane; r < Np; r += 64) ent[so + r] = Ent16{0ull, 0u, 0u};
   wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * NpMax,
                   smem64 + (int64_t)wv * 2 * NpMax + NpMax,
                   (uint32_t*)(smem64 + 8 * NpMax) + (int64_t)wv * NpMax,
@@ -935,6 +975,16 @@ static size_t big_scratch_bytes(const Ragged& R) {
          al256(8 * (size_t)(R.edges + 1)) + 256;
 }
 
+// quanta of the small tables live after the big-table scratch, indexed by
+// slot like the entries
+static size_t small_q_offset(const Ragged& R) {
+  return al256(big_scratch_bytes(R));
+}
+
+static size_t ragged_scratch_bytes(const Ragged& R) {
+  return small_q_offset(R) + al256(8 * (size_t)(R.slots + 1));
+}
+
 static BigScratch big_carve(void* p, const Ragged& R) {
   char* c = (char*)p;
   auto take = [&](size_t bytes) {
@@ -964,18 +1014,22 @@ static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
                                hipStream_t st) {
   if (R.S <= 0) return hipSuccess;
   const int64_t* c = R.cls_off;
+  uint64_t* qs = (uint64_t*)((char*)scratch + small_q_offset(R));
+  if (c[4] > 0)
+    k_ragged_lane_quanta<W><<<blocks_of(c[4], 64), 64, 0, st>>>(
+        w, R.off, R.meta, R.small_ids, c[4], R.tot, qs);
   if (c[1] > c[0])
-    k_ragged_small<1, W><<<blocks_of(c[1] - c[0], 4), 256, 4 * 64 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, R.ent);
+    k_ragged_alias<1, W><<<blocks_of(c[1] - c[0], 4), 256, 4 * 64 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, qs, R.ent);
   if (c[2] > c[1])
-    k_ragged_small<2, W><<<blocks_of(c[2] - c[1], 4), 256, 4 * 128 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, R.ent);
+    k_ragged_alias<2, W><<<blocks_of(c[2] - c[1], 4), 256, 4 * 128 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, qs, R.ent);
   if (c[3] > c[2])
-    k_ragged_small<4, W><<<blocks_of(c[3] - c[2], 4), 256, 4 * 256 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, R.ent);
+    k_ragged_alias<4, W><<<blocks_of(c[3] - c[2], 4), 256, 4 * 256 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, qs, R.ent);
   if (c[4] > c[3])
-    k_ragged_small<8, W><<<blocks_of(c[4] - c[3], 4), 256, 4 * 512 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, R.ent);
+    k_ragged_alias<8, W><<<blocks_of(c[4] - c[3], 4), 256, 4 * 512 * 20, st>>>(
+        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, qs, R.ent);
   if (R.nbig > 0) {
     const BigScratch sc = big_carve(scratch, R);
     const BigInfo* big = (const BigInfo*)R.big;
@@ -1062,9 +1116,9 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
       (e = ragged_layout(t.T1, t.at_ptr, d, st)) != hipSuccess ||
       (e = ragged_layout(t.T2, t.bt_ptr, d, st)) != hipSuccess)
     return e;
-  size_t need = big_scratch_bytes(t.T3);
-  need = std::max(need, big_scratch_bytes(t.T1));
-  need = std::max(need, big_scratch_bytes(t.T2));
+  size_t need = ragged_scratch_bytes(t.T3);
+  need = std::max(need, ragged_scratch_bytes(t.T1));
+  need = std::max(need, ragged_scratch_bytes(t.T2));
   need = std::max(need, stage0_scratch_bytes(d));
   need = std::max(need, sort_bytes(nz));
   if ((e = dev_alloc(t.work, need)) != hipSuccess) return e;

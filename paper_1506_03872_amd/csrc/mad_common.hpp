@@ -13,7 +13,7 @@ namespace mad {
 // The prefix at item r of run c is E_c + l_r, l_r the run-local sum.  This
 // order is non-decreasing and keeps a zero weight's prefix equal to its
 // predecessor's, so integer quanta of zero-weight items are exactly zero.
-constexpr int kRun = 1024;
+constexpr int kRun = 128;
 
 // Alias tables: 2^L slots of capacity 2^31; a draw uses the top L bits of a
 // 64-bit random word as the slot and its low 31 bits as the coin.

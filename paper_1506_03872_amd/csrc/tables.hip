@@ -99,14 +99,28 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v,
   return hipGetLastError();
 }
 
-// max |x| (as float bits, atomically) and a flag for non-finite entries
+// max |x| (as float bits, atomically) and a flag for non-finite entries;
+// float4 loads when X is 16-byte aligned
 __global__ void k_scan_inputs(const float* X, int64_t n, float* amax,
                               int* bad) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float mx = 0.0f;
   int nonfinite = 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += stride) {
+  int64_t done = 0;
+  if (((uintptr_t)X & 15) == 0) {
+    const float4* X4 = (const float4*)X;
+    const int64_t n4 = n / 4;
+    for (int64_t e = tid; e < n4; e += stride) {
+      const float4 v = X4[e];
+      nonfinite |= !isfinite(v.x) | !isfinite(v.y) | !isfinite(v.z) |
+                   !isfinite(v.w);
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)),
+                           fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    done = n4 * 4;
+  }
+  for (int64_t e = done + tid; e < n; e += stride) {
     const float v = X[e];
     nonfinite |= !isfinite(v);
     mx = fmaxf(mx, fabsf(v));
@@ -280,20 +294,40 @@ __global__ __launch_bounds__(64) void k_col_local(
 }
 
 // run offsets from the stored run-local prefixes: E_0 = 0,
-// E_{c+1} = E_c + l(last item of run c); total T = E_R
-__global__ void k_col_offsets(const uint64_t* Lbuf, int64_t S, int64_t N,
-                              int L, double* E, double* tot) {
-  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= S) return;
+// E_{c+1} = E_c + l(last item of run c); total T = E_R.  One 64-thread
+// block per table: the run totals are gathered in parallel into LDS, then
+// one lane adds them left to right.
+constexpr int kOffChunk = 2048;
+
+__global__ __launch_bounds__(64) void k_col_offsets(const uint64_t* Lbuf,
+                                                    int64_t S, int64_t N,
+                                                    int L, double* E,
+                                                    double* tot) {
+  __shared__ double buf[kOffChunk];
+  const int64_t seg = blockIdx.x;
   const int64_t R = (N + kRun - 1) / kRun;
-  double e = 0.0;
-  for (int64_t c = 0; c < R; ++c) {
-    E[c * S + seg] = e;
-    const int64_t last = (N < (c + 1) * kRun ? N : (c + 1) * kRun) - 1;
-    const uint64_t raw = Lbuf[(seg << L) + last] & ~(1ull << 63);
-    e = e + __longlong_as_double((long long)raw);
+  double e = 0.0;  // lane 0's running offset
+  for (int64_t c0 = 0; c0 < R; c0 += kOffChunk) {
+    const int64_t nc = R - c0 < kOffChunk ? R - c0 : kOffChunk;
+    for (int64_t u = threadIdx.x; u < nc; u += 64) {
+      const int64_t c = c0 + u;
+      const int64_t last = (N < (c + 1) * kRun ? N : (c + 1) * kRun) - 1;
+      const uint64_t raw = Lbuf[(seg << L) + last] & ~(1ull << 63);
+      buf[u] = __longlong_as_double((long long)raw);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int64_t u = 0; u < nc; ++u) {
+        const double sc = buf[u];
+        buf[u] = e;  // E_c
+        e = e + sc;
+      }
+    }
+    __syncthreads();
+    for (int64_t u = threadIdx.x; u < nc; u += 64) E[(c0 + u) * S + seg] = buf[u];
+    __syncthreads();
   }
-  tot[seg] = e;
+  if (threadIdx.x == 0) tot[seg] = e;
 }
 
 template <class W>
@@ -346,88 +380,6 @@ __global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
 }
 
 
-// Small tables end to end, one wave per table (N <= 2^L <= 64 * SPL <= 512,
-// a single run of the two-level order): lane l holds items l*SPL ..; the
-// left-to-right prefix walks the lanes in order with the running sum passed
-// on by readlane; quanta in parallel, then the alias table.  Writes the
-// table total to tot.
-template <int SPL, class W>
-__global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
-                                                      int64_t N, int L,
-                                                      double* tot,
-                                                      uint64_t* ent) {
-  extern __shared__ uint64_t smem64[];
-  const int Np = 1 << L;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
-  const bool ok = seg < S;
-  const int64_t segc = ok ? seg : S - 1;
-  double P[SPL];
-  uint32_t sg[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    const int rc = r < N ? r : (int)N - 1;
-    P[s] = r < N ? w(segc, rc) : 0.0;
-    sg[s] = r < N ? w.sgn(segc, rc) : 0u;
-  }
-  // prefix: lane k adds its items to the running sum of lanes < k
-  const int last_lane = (int)((N - 1) / SPL);
-  double carry = 0.0;
-  for (int k = 0; k <= last_lane; ++k) {
-    if (lane == k) {
-#pragma unroll
-      for (int s = 0; s < SPL; ++s) {
-        carry = carry + P[s];
-        P[s] = carry;
-      }
-    }
-    carry = readlane_f64(carry, k);
-  }
-  const double T = carry;  // prefix of item N-1 (padding adds zeros)
-  if (ok && lane == 0) tot[seg] = T;
-  const bool active = ok && T > 0.0;
-  const int K = L + kCapBits;
-  uint64_t F[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    F[s] = active && r < N ? (uint64_t)floor(ldexp(P[s] / T, K)) : 0ull;
-  }
-  // F of the item before this lane's first item
-  const uint64_t Fin = __shfl_up(F[SPL - 1], 1, 64);
-  uint64_t qv[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    const uint64_t Fp = s > 0 ? F[s - 1] : (lane > 0 ? Fin : 0ull);
-    qv[s] = active && r < N ? F[s] - Fp : 0ull;
-  }
-  if (ok && !active)  // dead table: never sampled, entries zero
-    for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
-  wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * Np,
-                  smem64 + (int64_t)wv * 2 * Np + Np,
-                  (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np,
-                  EmitPacked{ent + (segc << L)});
-}
-
-template <class W>
-static hipError_t small_tables(W w, int64_t S, int64_t N, int L, double* tot,
-                               uint64_t* ent, hipStream_t st) {
-  const int Np = 1 << L;
-  const size_t lds = (size_t)4 * Np * 20;
-  const unsigned blocks = grid_for(S, 4);
-  if (Np <= 64)
-    k_small_tables<1, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
-  else if (Np <= 128)
-    k_small_tables<2, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
-  else if (Np <= 256)
-    k_small_tables<4, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
-  else
-    k_small_tables<8, W><<<blocks, 256, lds, st>>>(w, S, N, L, tot, ent);
-  return hipGetLastError();
-}
-
 static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
                               int L, uint64_t* ent, hipStream_t st) {
   const int Np = 1 << L;
@@ -442,6 +394,82 @@ static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
   else
     k_alias_wave<8><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
   return hipGetLastError();
+}
+
+// Small tables (N <= 2^L <= 512 items), one lane per table: the total in
+// the two-level order, then the same prefix again with F_r = floor(2^K P_r
+// / T) and q_r = F_r - F_{r-1} (the item's sign bit in bit 63); padding
+// slots and dead tables get q = 0.  Every lane walks its own table, so the
+// sequential FP64 chain keeps all lanes busy.  Two-level order inside one
+// lane: l restarts at each run, E collects the run totals, P_r = E + l_r
+// (E = 0 in the first run, where 0 + l_r = l_r exactly).
+template <class W>
+__global__ __launch_bounds__(64) void k_lane_quanta(W w, int64_t S, int64_t N,
+                                                    int L, double* tot,
+                                                    uint64_t* q) {
+  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= S) return;
+  const int64_t Np = int64_t(1) << L;
+  uint64_t* qs = q + (seg << L);
+  double E = 0.0, l = 0.0;
+  for (int64_t r0 = 0; r0 < N; r0 += 8) {
+    double wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) wv[u] = w(seg, r0 + u < N ? r0 + u : N - 1);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + u;
+      if (r < N) {
+        if (r > 0 && r % kRun == 0) {
+          E = E + l;
+          l = 0.0;
+        }
+        l = l + wv[u];
+      }
+    }
+  }
+  const double T = E + l;
+  tot[seg] = T;
+  const bool live = T > 0.0;
+  const int K = L + kCapBits;
+  E = 0.0;
+  l = 0.0;
+  uint64_t Fp = 0;
+  for (int64_t r0 = 0; r0 < Np; r0 += 8) {
+    double wv[8];
+    uint32_t sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t rr = r0 + u < N ? r0 + u : N - 1;
+      wv[u] = live ? w(seg, rr) : 0.0;
+      sv[u] = live ? w.sgn(seg, rr) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + u;
+      if (r >= Np) break;
+      uint64_t qq = 0;
+      if (live && r < N) {
+        if (r > 0 && r % kRun == 0) {
+          E = E + l;
+          l = 0.0;
+        }
+        l = l + wv[u];
+        const uint64_t F = (uint64_t)floor(ldexp((E + l) / T, K));
+        qq = (F - Fp) | ((uint64_t)sv[u] << 63);
+        Fp = F;
+      }
+      qs[r] = qq;
+    }
+  }
+}
+
+template <class W>
+static hipError_t small_tables_q(W w, int64_t S, int64_t N, int L,
+                                 double* tot, uint64_t* q, uint64_t* ent,
+                                 hipStream_t st) {
+  k_lane_quanta<W><<<grid_for(S, 64), 64, 0, st>>>(w, S, N, L, tot, q);
+  return alias_small(q, tot, S, L, ent, st);
 }
 
 // large tables (2^L >= 1024 slots): blocks of 1024 slots (256 threads x 4)
@@ -532,20 +560,31 @@ __global__ __launch_bounds__(256) void k_alias_blocksum(const uint64_t* q,
 }
 
 // per table: exclusive scan of its block sums; light/heavy counts and the
-// total deficit
-__global__ void k_alias_blockscan(Quad* bs, int64_t S, int64_t B,
-                                  uint64_t* NL, uint64_t* NH, uint64_t* Dt) {
-  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= S) return;
-  Quad acc{0, 0, 0, 0};
-  for (int64_t b = seg * B; b < (seg + 1) * B; ++b) {
-    const Quad v = bs[b];
-    bs[b] = acc;
-    acc.nl += v.nl; acc.nh += v.nh; acc.sd += v.sd; acc.se += v.se;
+// total deficit (one 256-thread block per table)
+__global__ __launch_bounds__(256) void k_alias_blockscan(Quad* bs, int64_t S,
+                                                         int64_t B,
+                                                         uint64_t* NL,
+                                                         uint64_t* NH,
+                                                         uint64_t* Dt) {
+  const int64_t seg = blockIdx.x;
+  Quad carry{0, 0, 0, 0};
+  for (int64_t c0 = 0; c0 < B; c0 += 256) {
+    const int64_t b = c0 + threadIdx.x;
+    Quad v = b < B ? bs[seg * B + b] : Quad{0, 0, 0, 0};
+    const Quad all = block_excl_scan(v);
+    if (b < B)
+      bs[seg * B + b] = Quad{carry.nl + v.nl, carry.nh + v.nh,
+                             carry.sd + v.sd, carry.se + v.se};
+    carry.nl += all.nl;
+    carry.nh += all.nh;
+    carry.sd += all.sd;
+    carry.se += all.se;
   }
-  NL[seg] = acc.nl;
-  NH[seg] = acc.nh;
-  Dt[seg] = acc.sd;
+  if (threadIdx.x == 0) {
+    NL[seg] = carry.nl;
+    NH[seg] = carry.nh;
+    Dt[seg] = carry.sd;
+  }
 }
 
 // per table lists in index order: lights with their exclusive deficit
@@ -714,8 +753,8 @@ static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
     const uint64_t* qb = q + (s0 << L);
     if (bsf) bs = bsf + (s0 << L) / kAliasBlk;
     else k_alias_blocksum<<<(unsigned)nblk, 256, 0, st>>>(qb, bs);
-    k_alias_blockscan<<<grid_for(ns, 64), 64, 0, st>>>(bs, ns, Np / kAliasBlk,
-                                                       NL, NH, Dt);
+    k_alias_blockscan<<<(unsigned)ns, 256, 0, st>>>(bs, ns, Np / kAliasBlk,
+                                                    NL, NH, Dt);
     k_alias_scatter<<<(unsigned)nblk, 256, 0, st>>>(qb, bs, L, Ld, Li, He, Hi);
     const int64_t nedge = ns * (Np / kMergeBlk + 1);
     k_alias_edges<<<grid_for(nedge, 256), 256, 0, st>>>(Ld, He, NL, NH, ns, L,
@@ -747,7 +786,7 @@ static hipError_t col_quanta(const float* X, int64_t d, const double* scale,
   double* E = runbuf;  // R * S
   k_col_local<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, L,
                                                     Lbuf);
-  k_col_offsets<<<grid_for(S, 64), 64, 0, st>>>(Lbuf, S, N, L, E, tot);
+  k_col_offsets<<<(unsigned)S, 64, 0, st>>>(Lbuf, S, N, L, E, tot);
   const int64_t total = S << L;
   k_q_from_prefix<<<grid_for(total, kAliasBlk), 256, 0, st>>>(
       Lbuf, E, tot, S, N, L, q, L >= 10 ? bsf : nullptr);
@@ -888,7 +927,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
 
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
   if (t.T3.L <= 9) {
-    e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
+    e = small_tables_q(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, t.T3.ent,
+                       st);
   } else {
     e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
     if (e == hipSuccess)
@@ -915,7 +955,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
     if (t.T0.L <= 9) {
-      e = small_tables(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, t.T0.ent, st);
+      e = small_tables_q(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, t.T0.ent,
+                         st);
     } else {
       e = uniform_quanta(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, runbuf,
                          st);
@@ -934,7 +975,7 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
 // ---------------------------------------------------------------------------
 size_t query_tables_scratch_bytes(int64_t nq, int64_t d) {
   const int L = ceil_log2_host(d);
-  if (L <= 9) return 0;
+  if (L <= 9) return (size_t)(nq << L) * 8 + 256;
   const int64_t slots = nq << L;
   int64_t batch = slots < ((int64_t)1 << 26) ? slots : ((int64_t)1 << 26);
   if (batch < ((int64_t)1 << L)) batch = (int64_t)1 << L;
@@ -946,7 +987,12 @@ hipError_t query_tables_build(const float* Q, int64_t nq, int64_t d,
                               const double* v, Family& T0q, void* scratch,
                               size_t scratch_bytes, hipStream_t st) {
   const WQuery w{Q, d, v};
-  if (T0q.L <= 9) return small_tables(w, nq, d, T0q.L, T0q.tot, T0q.ent, st);
+  if (T0q.L <= 9) {
+    if (!scratch || scratch_bytes < (size_t)(nq << T0q.L) * 8)
+      return hipErrorInvalidValue;
+    return small_tables_q(w, nq, d, T0q.L, T0q.tot, (uint64_t*)scratch,
+                          T0q.ent, st);
+  }
   char* p = (char*)scratch;
   uint64_t* q = (uint64_t*)p; p += (size_t)(nq << T0q.L) * 8;
   double* runbuf = (double*)p; p += run_doubles(nq, d) * 8;
@@ -966,7 +1012,11 @@ hipError_t stage0_table_build(const double* w, int64_t N, Family& T,
                               void* scratch, size_t scratch_bytes,
                               hipStream_t st) {
   const WExplicit wf{w};
-  if (T.L <= 9) return small_tables(wf, 1, N, T.L, T.tot, T.ent, st);
+  if (T.L <= 9) {
+    if (!scratch || scratch_bytes < ((size_t)8 << T.L)) return hipErrorInvalidValue;
+    return small_tables_q(wf, 1, N, T.L, T.tot, (uint64_t*)scratch, T.ent,
+                          st);
+  }
   char* p = (char*)scratch;
   uint64_t* q = (uint64_t*)p; p += (size_t)8 << T.L;
   double* runbuf = (double*)p; p += run_doubles(1, N) * 8;

@@ -12,11 +12,15 @@ CAP = 1 << 31
 
 
 # ---------------------------------------------------------------- prefix sums
+RUN = oracle.run_length()
+
+
 def test_prefix_exact_on_small_integers():
     # every partial sum of small integers is exact in FP64, so any order of
     # addition must give the integer cumulative sum
     g = np.random.default_rng(1)
-    for N in (1, 2, 63, 64, 65, 1023, 1024, 1025, 5000, 70001):
+    for N in (1, 2, 63, 64, 65, RUN - 1, RUN, RUN + 1, 1023, 1024, 1025,
+              5000, 70001):
         w = g.integers(0, 1000, size=N).astype(np.float64)
         P = oracle.prefix(w)
         assert np.array_equal(P, np.cumsum(w.astype(np.int64)).astype(np.float64))
@@ -25,14 +29,16 @@ def test_prefix_exact_on_small_integers():
 def test_prefix_run_structure_on_dyadics():
     # 1.0 followed by terms of 2^-60: inside the first run each tiny term is
     # rounded away (half an ulp of 1.0 is 2^-53), but the second run sums its
-    # 1024 tiny terms on their own (exactly 2^-50) before the run offset 1.0
-    # is added.  A single left-to-right sum would stay at 1.0.
-    w = np.full(3000, 2.0 ** -60)
+    # RUN tiny terms on their own (exactly RUN * 2^-60) before the run offset
+    # 1.0 is added.  A single left-to-right sum would stay at 1.0.
+    R = RUN
+    N = 2 * R + R // 2
+    w = np.full(N, 2.0 ** -60)
     w[0] = 1.0
     P = oracle.prefix(w)
-    assert P[1023] == 1.0
-    assert P[2047] == 1.0 + 2.0 ** -50
-    assert P[2999] == 1.0 + 2.0 ** -50 + (3000 - 2048) * 2.0 ** -60
+    assert P[R - 1] == 1.0
+    assert P[2 * R - 1] == 1.0 + R * 2.0 ** -60
+    assert P[N - 1] == 1.0 + R * 2.0 ** -60 + (N - 2 * R) * 2.0 ** -60
 
 
 def test_prefix_monotone_and_zero_preserving():
@@ -40,8 +46,8 @@ def test_prefix_monotone_and_zero_preserving():
     for N in (1000, 1024, 4097, 30000):
         w = g.lognormal(0, 3, size=N)
         w[g.random(N) < 0.2] = 0.0
-        w[::1024] = 0.0                   # zeros at run starts
-        w[1023::1024] = 1e-300            # tiny terms at run ends
+        w[::RUN] = 0.0                    # zeros at run starts
+        w[RUN - 1::RUN] = 1e-300          # tiny terms at run ends
         P = oracle.prefix(w)
         assert np.all(np.diff(P) >= 0)
         z = np.nonzero(w[1:] == 0)[0] + 1
@@ -54,7 +60,8 @@ def test_prefix_close_to_exact_sum():
     P = oracle.prefix(w)
     exact = math.fsum(w)
     # two-level order: error bounded by about (runs + run length) * eps * sum
-    assert abs(P[-1] - exact) <= (1024 + 100) * 2.3e-16 * exact
+    runs = -(-len(w) // RUN)
+    assert abs(P[-1] - exact) <= (RUN + runs) * 2.3e-16 * exact
 
 
 # --------------------------------------------------------------------- quanta
