@@ -402,15 +402,20 @@ static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
 // slots and dead tables get q = 0.  Every lane walks its own table, so the
 // sequential FP64 chain keeps all lanes busy.  Two-level order inside one
 // lane: l restarts at each run, E collects the run totals, P_r = E + l_r
-// (E = 0 in the first run, where 0 + l_r = l_r exactly).
+// (E = 0 in the first run, where 0 + l_r = l_r exactly).  Loads go 8 at a
+// time; every 8 slots the block's quanta pass through LDS so that each
+// store writes 64 consecutive bytes of 8 tables.
 template <class W>
 __global__ __launch_bounds__(64) void k_lane_quanta(W w, int64_t S, int64_t N,
                                                     int L, double* tot,
                                                     uint64_t* q) {
-  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= S) return;
+  __shared__ uint64_t tq[64][9];
+  const int lane = threadIdx.x;
+  const int64_t seg0 = (int64_t)blockIdx.x * 64;
+  const int64_t nseg = S - seg0 < 64 ? S - seg0 : 64;
+  const int64_t seg = seg0 + (lane < nseg ? lane : nseg - 1);
+  const bool mine = lane < nseg;
   const int64_t Np = int64_t(1) << L;
-  uint64_t* qs = q + (seg << L);
   double E = 0.0, l = 0.0;
   for (int64_t r0 = 0; r0 < N; r0 += 8) {
     double wv[8];
@@ -429,8 +434,8 @@ __global__ __launch_bounds__(64) void k_lane_quanta(W w, int64_t S, int64_t N,
     }
   }
   const double T = E + l;
-  tot[seg] = T;
-  const bool live = T > 0.0;
+  if (mine) tot[seg] = T;
+  const bool live = mine && T > 0.0;
   const int K = L + kCapBits;
   E = 0.0;
   l = 0.0;
@@ -447,7 +452,6 @@ __global__ __launch_bounds__(64) void k_lane_quanta(W w, int64_t S, int64_t N,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t r = r0 + u;
-      if (r >= Np) break;
       uint64_t qq = 0;
       if (live && r < N) {
         if (r > 0 && r % kRun == 0) {
@@ -459,8 +463,16 @@ __global__ __launch_bounds__(64) void k_lane_quanta(W w, int64_t S, int64_t N,
         qq = (F - Fp) | ((uint64_t)sv[u] << 63);
         Fp = F;
       }
-      qs[r] = qq;
+      tq[lane][u] = qq;
     }
+    __syncthreads();
+    // lanes 8t .. 8t+7 write slots r0 .. r0+7 of table t (8 tables a pass)
+    const int64_t nc = Np - r0 < 8 ? Np - r0 : 8;
+    for (int t0 = 0; t0 < 64; t0 += 8) {
+      const int sl = t0 + (lane >> 3), u = lane & 7;
+      if (sl < nseg && u < nc) q[((seg0 + sl) << L) + r0 + u] = tq[sl][u];
+    }
+    __syncthreads();
   }
 }
 
