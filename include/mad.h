@@ -58,7 +58,14 @@ enum { MAD_FP32 = 0, MAD_BF16 = 1, MAD_FP8_E4M3 = 2 };
 enum {
   MAD_FLAG_NONE = 0,
   MAD_FLAG_NO_CHECK = 1u << 0, /* skip the NaN/Inf scan of the inputs      */
-  MAD_FLAG_TIMING = 1u << 1    /* record HIP events around each phase      */
+  MAD_FLAG_TIMING = 1u << 1,   /* record HIP events around each phase      */
+  /* Gram matrix (Sec. 3.3, equal inputs): B must be A (same arrays, n = m).
+   * The scores are symmetrised before Alg. 3, X <- (X + X^T) / 2, kept as
+   * the exact sum x_ij + x_ji under the pair with i < j, and the diagonal
+   * (a vector with itself) is left out, as in the paper's A^T A
+   * experiments; results list pairs with i < j and report x = (x_ij +
+   * x_ji) / 2. */
+  MAD_FLAG_GRAM = 1u << 2
 };
 
 typedef struct mad_plan mad_plan;

@@ -53,6 +53,8 @@ _P = C.c_void_p
 def _declare(L):
     L.orc_philox4x64_10.argtypes = [_P, _P, _P]
     L.orc_prefix.argtypes = [_P, _i64, _P]
+    L.orc_plan_set_gram.argtypes = [_P, C.c_int]
+    L.orc_plan_set_gram.restype = None
     L.orc_run_length.argtypes = []
     L.orc_run_length.restype = C.c_int
     L.orc_quanta.argtypes = [_P, _i64, _P]
@@ -199,6 +201,11 @@ class Plan:
         lib().orc_plan_set_dense_b(self._h, _ptr(B), n)
         self.n = n
         self._keep = (self._keep[0], B) if len(self._keep) == 2 else self._keep
+
+    def set_gram(self, gram: bool = True):
+        """B = A: X <- (X + X^T) / 2 before Alg. 3 (kept as x_ij + x_ji
+        on i < j), diagonal dropped (Sec. 3.3)."""
+        lib().orc_plan_set_gram(self._h, 1 if gram else 0)
 
     def close(self):
         if self._h:

@@ -348,6 +348,7 @@ typedef struct orc_plan {
   otable T0;
   otable *T1, *T2, *T3;
   float bmax;   /* max |b| over all entries */
+  int gram;     /* B = A: symmetrise X and drop the diagonal (Sec. 3.3) */
 } orc_plan;
 
 static void plan_build_aside(orc_plan *p) {
@@ -567,6 +568,45 @@ static int cmp_kv_key(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
+/* Sec. 3.3, equal inputs: X <- (X + X^T) / 2 before Alg. 3.  Kept exact as
+ * the integer sum x_ij + x_ji (twice the symmetric entry) under the key of
+ * the pair with i < j; the diagonal (a vector paired with itself) is
+ * dropped, as in the paper's A^T A experiments.  X is sorted by key; the
+ * result is sorted by key too. */
+static int64_t find_key(const kv *X, int64_t nd, int64_t key) {
+  int64_t lo = 0, hi = nd;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (X[mid].key < key) lo = mid + 1; else hi = mid;
+  }
+  return (lo < nd && X[lo].key == key) ? lo : -1;
+}
+
+static int64_t symmetrise(kv *X, int64_t nd, int64_t n) {
+  kv *Y = (kv *)malloc(sizeof(kv) * (size_t)(nd > 0 ? nd : 1));
+  int64_t ny = 0;
+  for (int64_t e = 0; e < nd; ++e) {
+    int64_t i = X[e].key / n, j = X[e].key % n;
+    if (i == j) continue;
+    int64_t t = find_key(X, nd, j * n + i);
+    if (i < j) {
+      Y[ny].key = X[e].key;
+      Y[ny].inc = X[e].inc + (t >= 0 ? X[t].inc : 0);
+      ++ny;
+    } else if (t < 0) { /* only (i, j) with i > j was sampled */
+      Y[ny].key = j * n + i;
+      Y[ny].inc = X[e].inc;
+      ++ny;
+    }
+  }
+  qsort(Y, (size_t)ny, sizeof(kv), cmp_kv_key);
+  memcpy(X, Y, sizeof(kv) * (size_t)ny);
+  free(Y);
+  return ny;
+}
+
+void orc_plan_set_gram(orc_plan *p, int gram) { p->gram = gram; }
+
 static int64_t build_scores(const orc_plan *p, uint64_t seed, uint64_t qid,
                             int64_t s, int F, kv **out, int64_t *closed_out) {
   kv *all = (kv *)malloc(sizeof(kv) * (size_t)(s > 0 ? s : 1));
@@ -588,6 +628,7 @@ static int64_t build_scores(const orc_plan *p, uint64_t seed, uint64_t qid,
     if (nd > 0 && all[nd - 1].key == all[e].key) all[nd - 1].inc += all[e].inc;
     else all[nd++] = all[e];
   }
+  if (p->gram) nd = symmetrise(all, nd, p->n);
   *out = all;
   if (closed_out) *closed_out = nc;
   return nd;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmad.so")
 MAD_OK, MAD_EINVAL, MAD_ENOMEM, MAD_EHIP, MAD_EOVERFLOW, MAD_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 MAD_FP32, MAD_BF16, MAD_FP8_E4M3 = 0, 1, 2
-MAD_FLAG_NONE, MAD_FLAG_NO_CHECK, MAD_FLAG_TIMING = 0, 1, 2
+MAD_FLAG_NONE, MAD_FLAG_NO_CHECK, MAD_FLAG_TIMING, MAD_FLAG_GRAM = 0, 1, 2, 4
 
 # every symbol include/mad.h declares
 EXPORTS = (

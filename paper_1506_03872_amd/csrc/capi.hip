@@ -99,7 +99,7 @@ struct mad_plan {
   mad::DeviceBuffer lpA, lpB, lpIA, lpIB;
   mad::LowpView lv{};
   // workspace of mad_plan_topk
-  mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc;
+  mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc, ord;
   mad::HashTable h;
   mad::SelectWork w;
   mad::SampleCounters* ctr = nullptr;
@@ -155,6 +155,7 @@ static void plan_free_all(mad_plan* p) {
   mad::dev_free(p->ck2);
   mad::dev_free(p->cc);
   mad::dev_free(p->misc);
+  mad::dev_free(p->ord);
   mad::dev_free(p->lpA);
   mad::dev_free(p->lpB);
   mad::dev_free(p->lpIA);
@@ -194,6 +195,8 @@ int mad_plan_create_dense(const float* A, int64_t m, const float* B,
     return fail(MAD_EINVAL, "m, n and d must be below 2^31");
   if (!is_device_ptr(A) || !is_device_ptr(B))
     return fail(MAD_EINVAL, "A and B must be device pointers");
+  if ((flags & MAD_FLAG_GRAM) && (A != B || m != n))
+    return fail(MAD_EINVAL, "MAD_FLAG_GRAM needs B == A (same pointer, n == m)");
   mad_plan* p = new (std::nothrow) mad_plan();
   if (!p) return fail(MAD_ENOMEM, "host allocation failed");
   p->kind = 0;
@@ -204,6 +207,7 @@ int mad_plan_create_dense(const float* A, int64_t m, const float* B,
   p->d = d;
   p->flags = flags;
   hipError_t e = mad::dense_tables_alloc(p->dt, m, n, d);
+  p->dt.gram = (flags & MAD_FLAG_GRAM) ? 1 : 0;
   if (e == hipSuccess && (flags & MAD_FLAG_TIMING))
     for (hipEvent_t& ev : p->ev)
       if ((e = hipEventCreate(&ev)) != hipSuccess) break;
@@ -292,7 +296,10 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
       (e = mad::dev_alloc(p->ck2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->cc, 4 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->misc, mad::kSelStateBytes + 4 * mad::kSelBins +
-                                       256 + 256)) != hipSuccess) {
+                                       256 + 256)) != hipSuccess ||
+      (p->kind == 0 &&
+       (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(s2, p->d))) !=
+           hipSuccess)) {
     p->ws_s = p->ws_tp = p->ws_t = -1;
     return hip_fail(e, "allocating workspace");
   }
@@ -353,13 +360,14 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
             "sampling");
   else
     HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, p->h,
-                                     p->ctr, st),
+                                     p->ctr, p->ord.p, p->ord.bytes, st),
             "sampling");
   record(p, 4, st);
   HIP_TRY(mad::launch_postprocess(p->h, p->A, p->B,
                                   p->kind == 2 ? &p->ct.in : nullptr,
                                   p->verify_prec != MAD_FP32 ? &p->lv : nullptr,
-                                  p->n, p->d, tp_eff, t, plan_bmax(p), s, p->w,
+                                  p->n, p->d, tp_eff, t, plan_bmax(p), s,
+                                  (p->flags & MAD_FLAG_GRAM) ? 1 : 0, p->w,
                                   out, n_out, st),
           "postprocessing");
   record(p, 5, st);
@@ -688,6 +696,9 @@ int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
   if ((nnzA && (!is_device_ptr(a_idx) || !is_device_ptr(a_val))) ||
       (nnzB && (!is_device_ptr(b_idx) || !is_device_ptr(b_val))))
     return fail(MAD_EINVAL, "CSR arrays must be device pointers");
+  if ((flags & MAD_FLAG_GRAM) &&
+      (a_ptr != b_ptr || a_idx != b_idx || a_val != b_val || m != n))
+    return fail(MAD_EINVAL, "MAD_FLAG_GRAM needs B == A (same arrays, n == m)");
   mad_plan* p = new (std::nothrow) mad_plan();
   if (!p) return fail(MAD_ENOMEM, "host allocation failed");
   p->kind = 2;
@@ -701,6 +712,7 @@ int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
   p->ct.nnzA = nnzA;
   p->ct.nnzB = nnzB;
   p->ct.in = mad::CsrView{a_ptr, a_idx, a_val, b_ptr, b_idx, b_val};
+  p->ct.gram = (flags & MAD_FLAG_GRAM) ? 1 : 0;
   hipError_t e = hipSuccess;
   if (flags & MAD_FLAG_TIMING)
     for (hipEvent_t& ev : p->ev)

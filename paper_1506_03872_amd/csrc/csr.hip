@@ -1153,6 +1153,7 @@ struct CsrSampleArgs {
   int64_t n;
   uint64_t seed, qid;
   int64_t l0, count;
+  int gram;  // B = A: key of the pair with i < j, diagonal left out
 };
 
 __device__ __forceinline__ Drawn draw16(const Ent16& e, uint64_t U) {
@@ -1267,12 +1268,22 @@ __global__ __launch_bounds__(256) void k_sample_csr(
     }
     if (!DEBUG) {
       uint64_t key[U], slot[U];
-      bool pend[U];
+      bool pend[U], ins[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        key[u] = (uint64_t)i[u] * (uint64_t)a.n + j[u];
+        uint64_t ii = i[u], jj = j[u];
+        ins[u] = closed[u];
+        if (a.gram) {  // Sec. 3.3: X + X^T on i < j, diagonal dropped
+          if (ii == jj) ins[u] = false;
+          if (ii > jj) {
+            const uint64_t tmp = ii;
+            ii = jj;
+            jj = tmp;
+          }
+        }
+        key[u] = ii * (uint64_t)a.n + jj;
         slot[u] = mix64(key[u]) & hmask;
-        pend[u] = closed[u];
+        pend[u] = ins[u];
         nclosed += closed[u];
       }
       bool any = true;
@@ -1299,7 +1310,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (closed[u] && inc[u] != 0)
+        if (ins[u] && inc[u] != 0)
           atomicAdd((unsigned long long*)(hvals + slot[u]),
                     (unsigned long long)inc[u]);
     }
@@ -1341,6 +1352,7 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.qid = qid;
   a.l0 = l0;
   a.count = count;
+  a.gram = t.gram;
   return a;
 }
 

@@ -40,6 +40,7 @@ struct DenseTables {
   double* om = nullptr;  // d
   float* bmax = nullptr; // 1
   int* bad = nullptr;    // 1
+  int gram = 0;          // B = A, symmetrised scores (Sec. 3.3)
 };
 
 hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,
@@ -74,10 +75,14 @@ struct SampleCounters {
   unsigned long long pad[6];
 };
 
+// order_ws (order_bytes >= sample_order_bytes(count, d)) enables the
+// k-ordered sampling launch; null samples in index order
+size_t sample_order_bytes(int64_t count, int64_t d);
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F,
                                HashTable h, SampleCounters* ctr,
+                               void* order_ws, size_t order_bytes,
                                hipStream_t st);
 hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      uint64_t seed, uint64_t qid, int64_t l0,
@@ -147,6 +152,7 @@ struct CsrTables {
   float* bmax = nullptr;  // 1
   int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
   DeviceBuffer work;      // transposes' and tables' scratch
+  int gram = 0;           // B = A, symmetrised scores (Sec. 3.3)
 };
 
 // Allocates and builds every table (synchronises: the layout of the
@@ -292,12 +298,14 @@ void lowp_consts(int prec, int64_t d, float* kappa, float* onepu);
 // csr: sparse inputs for the verification (A, B unused), or null; lowp:
 // low-precision filter of the candidates before the fp32 verification, or
 // null
+// x_shift: reported x = x_fix * 2^-(F + x_shift) (1 for symmetrised
+// scores, which hold x_ij + x_ji)
 hipError_t launch_postprocess(const HashTable& h, const float* A,
                               const float* B, const CsrView* csr,
                               const LowpView* lowp, int64_t n, int64_t d,
                               int64_t t_prime, int64_t t, const float* bmax,
-                              int64_t s, SelectWork& w, void* out,
-                              int64_t* n_out, hipStream_t st);
+                              int64_t s, int x_shift, SelectWork& w,
+                              void* out, int64_t* n_out, hipStream_t st);
 
 // fp32 re-rank of candidate keys (count known on the host) and the exact
 // top t by |c| into mad_pair records; buf is grown as needed

@@ -18,6 +18,8 @@
 namespace mad {
 
 constexpr int kT0Lds = 4096;  // stage-0 table kept in LDS up to this size
+constexpr int64_t kOrderMaxD = 1024;          // k ordering for d up to this
+constexpr int64_t kOrderChunk = int64_t(1) << 28;  // samples per ordering
 
 struct DenseSampleArgs {
   const uint64_t* T0;
@@ -29,6 +31,7 @@ struct DenseSampleArgs {
   int64_t d, n;
   uint64_t seed, qid;
   int64_t l0, count;
+  int gram;  // B = A: key of the pair with i < j, diagonal left out
 };
 
 struct OneSample {
@@ -37,13 +40,24 @@ struct OneSample {
   bool closed;
 };
 
-template <int U, bool DEBUG>
+// Samples in k order (the locality ordering of Sec. 5.2, Alg. 4's first
+// step): `ell` lists sample offsets sorted by their stage-0 draw k.  The
+// sampling launch then gives each XCD (workgroups are dispatched to the 8
+// XCDs round robin) a contiguous eighth of that list, walked in order by
+// its workgroups, so the rows T1[k] and T2[k] being drawn from stay in that
+// XCD's L2.  Results do not depend on the order.
+struct GroupOrder {
+  const uint32_t* ell;  // sample offsets (from l0), sorted by k
+  int64_t chunk;        // samples per workgroup step (256 * U)
+};
+
+template <int U, bool DEBUG, bool GROUPED>
 __global__ __launch_bounds__(256) void k_sample_dense(
     DenseSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
     int F_debug,
     uint64_t* hkeys, int64_t* hvals, uint64_t hmask,
     SampleCounters* ctr, int32_t* ok, int32_t* oi, int32_t* oj,
-    int32_t* okp, int64_t* oinc) {
+    int32_t* okp, int64_t* oinc, GroupOrder go) {
   extern __shared__ uint64_t t0s[];  // T0 when it fits (kT0Lds entries)
   if (!(wtot[0] > 0.0)) return;  // ||W||_1 = 0: nothing can be sampled
   const int N0 = 1 << a.L0;
@@ -54,17 +68,26 @@ __global__ __launch_bounds__(256) void k_sample_dense(
   const uint64_t* T0 = t0_lds ? t0s : a.T0;
   const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
 
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // ungrouped: grid-stride over samples; grouped: chunks of the k-sorted
+  // list, XCD x = blockIdx % 8 takes chunks [x, x+1) * nch / 8 in order
+  const int64_t nthreads = GROUPED ? 256 : (int64_t)gridDim.x * blockDim.x;
+  const int64_t nch = GROUPED ? (a.count + go.chunk - 1) / go.chunk : 0;
+  const int64_t xcd = blockIdx.x & 7, g8 = gridDim.x >> 3;
+  const int64_t ch_lo = GROUPED ? xcd * nch / 8 : 0;
+  const int64_t ch_hi = GROUPED ? (xcd + 1) * nch / 8 : 0;
+  int64_t ch = GROUPED ? ch_lo + (blockIdx.x >> 3) : 0;
+  int64_t base = GROUPED ? ch * go.chunk + threadIdx.x
+                         : (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long nclosed = 0, ncreated = 0;
-  for (int64_t base = tid; base < a.count; base += nthreads * U) {
+  while (GROUPED ? ch < ch_hi : base < a.count) {
     OneSample smp[U];
     uint64_t U1[U], U2[U], U3[U];
     // ds1 (stage 0): k from the LDS copy of T0
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = base + (int64_t)u * nthreads;
-      const uint64_t l = (uint64_t)(a.l0 + (e < a.count ? e : 0));
+      const int64_t ec = e < a.count ? e : 0;
+      const uint64_t l = (uint64_t)(a.l0 + (GROUPED ? (int64_t)go.ell[ec] : ec));
       const Philox4 r = philox4x64_10(l, a.qid, 0ull, 0ull, a.seed, 0ull);
       const uint32_t s0 = slot_of(r.w0, a.L0);
       smp[u].k = draw_entry(T0[s0], s0, r.w0).pos;
@@ -128,12 +151,22 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       // adds; a slot's key changes from EMPTY to its final value once, so a
       // swap that finds EMPTY or the key itself owns the slot
       uint64_t key[U], slot[U];
-      bool pend[U];
+      bool pend[U], ins[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        key[u] = (uint64_t)smp[u].i * (uint64_t)a.n + smp[u].j;
+        uint64_t ii = smp[u].i, jj = smp[u].j;
+        ins[u] = smp[u].closed;
+        if (a.gram) {  // Sec. 3.3: X + X^T on i < j, diagonal dropped
+          if (ii == jj) ins[u] = false;
+          if (ii > jj) {
+            const uint64_t tmp = ii;
+            ii = jj;
+            jj = tmp;
+          }
+        }
+        key[u] = ii * (uint64_t)a.n + jj;
         slot[u] = mix64(key[u]) & hmask;
-        pend[u] = smp[u].closed;
+        pend[u] = ins[u];
         nclosed += smp[u].closed;
       }
       bool any = true;
@@ -160,9 +193,15 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (smp[u].closed && smp[u].inc != 0)
+        if (ins[u] && smp[u].inc != 0)
           atomicAdd((unsigned long long*)(hvals + slot[u]),
                     (unsigned long long)smp[u].inc);
+    }
+    if (GROUPED) {
+      ch += g8;
+      base = ch * go.chunk + threadIdx.x;
+    } else {
+      base += nthreads * U;
     }
   }
   if (!DEBUG) {
@@ -205,6 +244,7 @@ static DenseSampleArgs dense_args(const DenseTables& t, const float* B,
   a.qid = qid;
   a.l0 = l0;
   a.count = count;
+  a.gram = t.gram;
   return a;
 }
 
@@ -230,29 +270,200 @@ static size_t t0_lds_bytes(const DenseTables& t) {
   return N0 <= kT0Lds ? (size_t)N0 * 8 : 0;
 }
 
+// ---------------------------------------------------------------------------
+// the k order: per block of kOrdPer consecutive samples, counts of each k
+// (pass 1); per k, exclusive prefix of those counts over the blocks and the
+// k's total (pass 2); the start of each k's range (pass 3); every sample's
+// offset written into its k's range (pass 4).  The order inside one
+// block's share of a k is whatever the LDS counter gives; it does not
+// matter.
+// ---------------------------------------------------------------------------
+constexpr int kOrdU = 8;
+constexpr int kOrdPer = 256 * kOrdU;
+
+template <bool PLACE>
+__global__ __launch_bounds__(256) void k_order_pass(DenseSampleArgs a,
+                                                   uint32_t* cnt,
+                                                   const uint32_t* start,
+                                                   uint32_t* ell) {
+  extern __shared__ uint64_t sm[];
+  const int N0 = 1 << a.L0;
+  uint64_t* t0s = sm;
+  uint32_t* lc = (uint32_t*)(sm + N0);
+  const int64_t d = a.d;
+  for (int e = threadIdx.x; e < N0; e += 256) t0s[e] = a.T0[e];
+  for (int64_t k = threadIdx.x; k < d; k += 256) lc[k] = 0;
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * kOrdPer;
+  uint32_t kk[kOrdU], rank[kOrdU];
+#pragma unroll
+  for (int u = 0; u < kOrdU; ++u) {
+    const int64_t e = b0 + u * 256 + threadIdx.x;
+    kk[u] = 0;
+    rank[u] = 0;
+    if (e < a.count) {
+      const Philox4 r = philox4x64_10((uint64_t)(a.l0 + e), a.qid, 0ull, 0ull,
+                                      a.seed, 0ull);
+      const uint32_t s0 = slot_of(r.w0, a.L0);
+      kk[u] = draw_entry(t0s[s0], s0, r.w0).pos;
+      rank[u] = atomicAdd(&lc[kk[u]], 1u);
+    }
+  }
+  __syncthreads();
+  if (!PLACE) {
+    for (int64_t k = threadIdx.x; k < d; k += 256)
+      cnt[(int64_t)blockIdx.x * d + k] = lc[k];
+  } else {
+#pragma unroll
+    for (int u = 0; u < kOrdU; ++u) {
+      const int64_t e = b0 + u * 256 + threadIdx.x;
+      if (e < a.count)
+        ell[(int64_t)start[kk[u]] + cnt[(int64_t)blockIdx.x * d + kk[u]] +
+            rank[u]] = (uint32_t)e;
+    }
+  }
+}
+
+// per k: exclusive prefix of the block counts (one workgroup per k)
+__global__ __launch_bounds__(256) void k_order_colscan(uint32_t* cnt,
+                                                      int64_t nblk,
+                                                      int64_t d,
+                                                      uint32_t* tot) {
+  __shared__ uint32_t wt[4];
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblk; b0 += 256) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nblk ? cnt[b * d + k] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wt[wv] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wv ? wt[w] : 0u;
+      all += wt[w];
+    }
+    if (b < nblk) cnt[b * d + k] = carry + off + inc - v;
+    carry += all;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[k] = carry;
+}
+
+// start of each k's range: exclusive prefix of the totals (one workgroup)
+__global__ __launch_bounds__(256) void k_order_starts(const uint32_t* tot,
+                                                     int64_t d,
+                                                     uint32_t* start) {
+  __shared__ uint32_t wt[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int64_t k0 = 0; k0 < d; k0 += 256) {
+    const int64_t k = k0 + threadIdx.x;
+    const uint32_t v = k < d ? tot[k] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wt[wv] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wv ? wt[w] : 0u;
+      all += wt[w];
+    }
+    if (k < d) start[k] = carry + off + inc - v;
+    carry += all;
+    __syncthreads();
+  }
+}
+
+size_t sample_order_bytes(int64_t count, int64_t d) {
+  if (d > kOrderMaxD) return 0;
+  const int64_t c = count < kOrderChunk ? count : kOrderChunk;
+  const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
+  return (size_t)c * 4 + (size_t)nblk * d * 4 + (size_t)d * 8 + 1024;
+}
+
+// The k order is off by default: on dense 1e5 x 1e5 x 100 with s = 1e7 it
+// takes the sampling kernel from 1.41 to 1.30 ms but the four ordering
+// passes cost 0.16 ms, because the score-table atomics, not the T1 / T2
+// loads, bound the sampler.  MAD_SAMPLER_ORDER=1 turns it on and
+// MAD_SAMPLER_G8 sets the workgroups per XCD (both result-invariant).
+static int order_enabled() {
+  static int v = [] {
+    const char* e = getenv("MAD_SAMPLER_ORDER");
+    return e ? atoi(e) : 0;
+  }();
+  return v;
+}
+
+static int order_g8() {
+  static int v = [] {
+    const char* e = getenv("MAD_SAMPLER_G8");
+    const int x = e ? atoi(e) : 128;
+    return x >= 1 && x <= 4096 ? x : 128;
+  }();
+  return v;
+}
+
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F, HashTable h,
-                               SampleCounters* ctr, hipStream_t st) {
+                               SampleCounters* ctr, void* order_ws,
+                               size_t order_bytes, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
   const size_t lds = t0_lds_bytes(t);
   const uint64_t hm = (uint64_t)h.cap - 1;
-  switch (sampler_unroll()) {
+  const bool ordered = order_enabled() && t.d <= kOrderMaxD && order_ws &&
+                       order_bytes >= sample_order_bytes(count, t.d) &&
+                       (int64_t(1) << t.T0.L) <= kT0Lds;
+  if (!ordered) {
+    const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
+    switch (sampler_unroll()) {
 #define MAD_SAMPLE_CASE(UU)                                                \
   case UU:                                                                 \
-    k_sample_dense<UU, false><<<sample_grid(count, UU), 256, lds, st>>>(   \
-        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, ctr, nullptr, \
-        nullptr, nullptr, nullptr, nullptr);                               \
+    k_sample_dense<UU, false, false>                                       \
+        <<<sample_grid(count, UU), 256, lds, st>>>(                        \
+            a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, ctr,      \
+            nullptr, nullptr, nullptr, nullptr, nullptr, GroupOrder{});    \
     break;
-    MAD_SAMPLE_CASE(1)
-    MAD_SAMPLE_CASE(2)
-    MAD_SAMPLE_CASE(8)
-    default:
-    MAD_SAMPLE_CASE(4)
+      MAD_SAMPLE_CASE(1)
+      MAD_SAMPLE_CASE(2)
+      MAD_SAMPLE_CASE(8)
+      default:
+      MAD_SAMPLE_CASE(4)
 #undef MAD_SAMPLE_CASE
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  // ordered: chunks of at most kOrderChunk samples
+  const int64_t d = t.d;
+  const size_t lds_ord = ((size_t)8 << t.T0.L) + 4 * (size_t)d;
+  for (int64_t c0 = 0; c0 < count; c0 += kOrderChunk) {
+    const int64_t c = count - c0 < kOrderChunk ? count - c0 : kOrderChunk;
+    const DenseSampleArgs a = dense_args(t, B, seed, qid, l0 + c0, c);
+    const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
+    char* p = (char*)order_ws;
+    uint32_t* ell = (uint32_t*)p;
+    uint32_t* cnt = (uint32_t*)(p + ((size_t)c * 4 + 255) / 256 * 256);
+    uint32_t* tot = cnt + nblk * d;
+    uint32_t* start = tot + d;
+    k_order_pass<false><<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, nullptr,
+                                                              nullptr);
+    k_order_colscan<<<(unsigned)d, 256, 0, st>>>(cnt, nblk, d, tot);
+    k_order_starts<<<1, 256, 0, st>>>(tot, d, start);
+    k_order_pass<true><<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, start,
+                                                             ell);
+    GroupOrder go{ell, 256 * 4};
+    int64_t g8 = order_g8();
+    const int64_t nch = (c + go.chunk - 1) / go.chunk;
+    if (g8 * 8 > nch) g8 = (nch + 7) / 8;
+    if (g8 < 1) g8 = 1;
+    k_sample_dense<4, false, true><<<(unsigned)(8 * g8), 256, lds, st>>>(
+        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, ctr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, go);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
@@ -262,9 +473,10 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t* inc, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
-  k_sample_dense<2, true>
+  k_sample_dense<2, true, false>
       <<<sample_grid(count, 2), 256, t0_lds_bytes(t), st>>>(
-      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp, inc);
+      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp, inc,
+      GroupOrder{});
   return hipGetLastError();
 }
 

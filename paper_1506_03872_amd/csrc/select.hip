@@ -588,9 +588,10 @@ struct PairOut {
 __global__ void k_final_sort(const uint64_t* fkey, const uint64_t* fx,
                              const float* fc, const int64_t* counts,
                              int64_t tcap, int64_t n, const float* bmax,
-                             int64_t s_for_F, PairOut* out, int64_t* n_out) {
+                             int64_t s_for_F, int x_shift, PairOut* out,
+                             int64_t* n_out) {
   const int64_t nf = counts[kCntFinal] < tcap ? counts[kCntFinal] : tcap;
-  const int F = bmax ? fix_exponent(*bmax, s_for_F) : 0;
+  const int F = (bmax ? fix_exponent(*bmax, s_for_F) : 0) + x_shift;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf;
        e += stride) {
@@ -746,7 +747,7 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
                                             t, kCntFinal);
   // x = 0 for brute-force results (no sampler score); F is irrelevant
   k_final_sort<<<blocks_for(t, 256, 1024), 256, 0, st>>>(
-      fkey, fx, fc, counts, t, n, nullptr, 0, (PairOut*)out, n_out);
+      fkey, fx, fc, counts, t, n, nullptr, 0, 0, (PairOut*)out, n_out);
   return hipGetLastError();
 }
 
@@ -754,8 +755,8 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
                               const float* B, const CsrView* csr,
                               const LowpView* lowp, int64_t n, int64_t d,
                               int64_t t_prime, int64_t t, const float* bmax,
-                              int64_t s, SelectWork& w, void* out,
-                              int64_t* n_out, hipStream_t st) {
+                              int64_t s, int x_shift, SelectWork& w,
+                              void* out, int64_t* n_out, hipStream_t st) {
   Coarse* cz = (Coarse*)w.state;
   int64_t* counts = w.counts;
   // keep counts[kCntDistinct] (the sampler's), clear the others
@@ -819,7 +820,7 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
       cz + 1, bp, bkey, bx, bc, bcap, counts, kCntWin, fp, fkey, fx, fc, t,
       kCntFinal);
   k_final_sort<<<blocks_for(t, 256, 1024), 256, 0, st>>>(
-      fkey, fx, fc, counts, t, n, bmax, s, (PairOut*)out, n_out);
+      fkey, fx, fc, counts, t, n, bmax, s, x_shift, (PairOut*)out, n_out);
   return hipGetLastError();
 }
 
