@@ -1,0 +1,447 @@
+// accum.hip -- the score matrix X of Alg. 2 (line "dx") built from the
+// closed samples without per-sample global atomics.
+//
+// Sample l writes its (key = i*n + j, inc) pair at index l of a pair array
+// (key EMPTY when the three-path is open), so the sampler needs no atomics.
+// X is the sum of the increments per key, computed as:
+//   count    per tile of pairs, a histogram of the bin = top B1 bits of
+//            mix64(key) (bins are disjoint in keys); open samples dropped;
+//   scan     exclusive prefix of the tile counts in bin-major order;
+//   place    every closed pair written into its bin's range;
+//   split    (large s) one workgroup per bin partitions it again by the next
+//            B2 hash bits, so that bins hold about 1024 pairs;
+//   reduce   one workgroup per bin sums equal keys in an LDS hash table and
+//            appends the distinct (key, x) to the output list.  A bin with
+//            more distinct keys than the LDS table holds is split by the
+//            next hash bits into sub-bins, each reduced on its own, so the
+//            output never holds a key twice.
+// The sums are int64 fixed point, so X is the same in any order.
+#include "mad_common.hpp"
+#include "plan.hpp"
+
+namespace mad {
+
+constexpr int kAccThreads = 1024;
+constexpr int kAccPer = 8;                // pairs per thread of a tile
+constexpr int kAccTile = kAccThreads * kAccPer;  // count / place tile
+constexpr int kAccMaxBits = 8;            // first level: up to 256 bins
+constexpr int kAcc2MaxBits = 12;          // second level: up to 4096 sub-bins
+constexpr int kRedThreads = 256;
+constexpr int kRedSlots = 1024;           // LDS table of a reduce workgroup
+constexpr int kRedPer = 4;                // pairs loaded per thread at once
+
+static inline unsigned acc_blocks(int64_t n, int per) {
+  int64_t g = (n + per - 1) / per;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// bits of the bin index: B1 for the global partition, B2 for the second
+// partition inside each first-level bin, so that bins hold ~512 pairs
+static int acc_total_bits(int64_t s) {
+  int b = 0;
+  while (b < kAccMaxBits + kAcc2MaxBits && (int64_t(512) << b) < s) ++b;
+  return b;
+}
+
+static int acc_b1(int64_t s) {
+  const int b = acc_total_bits(s);
+  return b < kAccMaxBits ? b : kAccMaxBits;
+}
+
+static int acc_b2(int64_t s) { return acc_total_bits(s) - acc_b1(s); }
+
+size_t accum_bytes(int64_t s) {
+  const int B1 = acc_b1(s), B2 = acc_b2(s);
+  const int64_t tiles = (s + kAccTile - 1) / kAccTile;
+  const size_t cnt = (size_t)(tiles << B1) + 1;
+  const size_t starts = ((size_t)1 << (B1 + B2)) + 1;
+  return (size_t)s * 16 + cnt * 8 * 2 + starts * 8 * 3 + 8192;
+}
+
+__device__ __forceinline__ uint32_t bin_of(uint64_t key, int B) {
+  return B ? (uint32_t)(mix64(key) >> (64 - B)) : 0u;
+}
+
+// count: per tile, histogram of bins -> cnt[bin * tiles + tile]; the
+// entry after the last, cnt[tiles << B], is set to 0 so that the exclusive
+// scan leaves the number of closed pairs there.  Each thread loads its
+// kAccPer pairs of the tile before any of them is counted.
+__global__ __launch_bounds__(kAccThreads) void k_acc_count(
+    const uint64_t* pk, int64_t n, int B, int64_t tiles, uint64_t* cnt) {
+  __shared__ unsigned h[1 << kAccMaxBits];
+  const int nb = 1 << B;
+  for (int b = threadIdx.x; b < nb; b += kAccThreads) h[b] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kAccTile + threadIdx.x;
+  uint64_t key[kAccPer];
+#pragma unroll
+  for (int u = 0; u < kAccPer; ++u) {
+    const int64_t e = t0 + (int64_t)u * kAccThreads;
+    key[u] = e < n ? pk[2 * e] : kEmptyKey;
+  }
+#pragma unroll
+  for (int u = 0; u < kAccPer; ++u)
+    if (key[u] != kEmptyKey) atomicAdd(&h[bin_of(key[u], B)], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += kAccThreads)
+    cnt[(int64_t)b * tiles + blockIdx.x] = h[b];
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[tiles << B] = 0;
+}
+
+// place: every pair into its bin's range (order inside a tile's share of a
+// bin is whatever the LDS counter gives; it does not matter)
+__global__ __launch_bounds__(kAccThreads) void k_acc_place(
+    const uint64_t* pk, int64_t n, int B, int64_t tiles,
+    const uint64_t* offs, uint64_t* out) {
+  __shared__ unsigned long long base[1 << kAccMaxBits];
+  __shared__ unsigned h[1 << kAccMaxBits];
+  const int nb = 1 << B;
+  for (int b = threadIdx.x; b < nb; b += kAccThreads) {
+    h[b] = 0;
+    base[b] = offs[(int64_t)b * tiles + blockIdx.x];
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * kAccTile + threadIdx.x;
+  ulonglong2 pr[kAccPer];
+#pragma unroll
+  for (int u = 0; u < kAccPer; ++u) {
+    const int64_t e = t0 + (int64_t)u * kAccThreads;
+    if (e < n) {
+      pr[u] = *(const ulonglong2*)(pk + 2 * e);
+    } else {
+      pr[u].x = kEmptyKey;
+      pr[u].y = 0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kAccPer; ++u) {
+    if (pr[u].x == kEmptyKey) continue;
+    const uint32_t b = bin_of(pr[u].x, B);
+    const int64_t p = (int64_t)base[b] + atomicAdd(&h[b], 1u);
+    *(ulonglong2*)(out + 2 * p) = pr[u];
+  }
+}
+
+// one workgroup per bin: sum equal keys in an LDS table and write the
+// distinct (key, x) at the front of the bin's own range [lo, hi) of the
+// output (a bin has no more distinct keys than pairs), EMPTY after them, so
+// the output is a table of n entries and no global atomics are needed.  The
+// bin's keys share the top B hash bits.  The thread that claims a slot for
+// a new key stores its increment; increments of keys already present are
+// added after a barrier, so most pairs cost one LDS atomic.
+__global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
+    const uint64_t* pairs, const uint64_t* starts, int B, int64_t n,
+    uint64_t* okey, int64_t* oval, uint64_t* bin_distinct) {
+  constexpr int kPer = kRedSlots / kRedThreads;  // slots owned per thread
+  constexpr int kW = kRedThreads / 64;
+  __shared__ unsigned long long sk[kRedSlots];
+  __shared__ unsigned long long sv[kRedSlots];
+  __shared__ int full;
+  __shared__ unsigned wc[kPer][kW];
+  const int64_t bin = blockIdx.x;
+  const int64_t lo = (int64_t)starts[bin];
+  const int64_t hi = (int64_t)starts[bin + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t wpos = lo;  // next output position (uniform)
+  // sub-bins: the hash bits below the bin's B bits
+  int R = 1;  // sub-bins in the current split (a power of two)
+  int64_t sub = 0;
+  while (hi > lo && sub < R) {
+    for (int q = threadIdx.x; q < kRedSlots; q += kRedThreads)
+      sk[q] = kEmptyKey;
+    if (threadIdx.x == 0) full = 0;
+    __syncthreads();
+    const int rb = 31 - __clz(R);  // log2 R
+    for (int64_t b0 = lo; b0 < hi; b0 += kRedThreads * kRedPer) {
+      ulonglong2 pr[kRedPer];
+#pragma unroll
+      for (int u = 0; u < kRedPer; ++u) {
+        const int64_t e = b0 + threadIdx.x + (int64_t)u * kRedThreads;
+        if (e < hi) {
+          pr[u] = *(const ulonglong2*)(pairs + 2 * e);
+        } else {
+          pr[u].x = kEmptyKey;
+          pr[u].y = 0;
+        }
+      }
+      int dq[kRedPer];  // slot of a key found present (-1: none)
+#pragma unroll
+      for (int u = 0; u < kRedPer; ++u) {
+        dq[u] = -1;
+        const uint64_t key = pr[u].x;
+        if (key == kEmptyKey) continue;
+        const uint64_t h = mix64(key);
+        if (rb && (int64_t)((h << B) >> (64 - rb)) != sub) continue;
+        uint32_t q = (uint32_t)(h ^ (h >> 29)) & (kRedSlots - 1);
+        int probes = 0;
+        while (true) {
+          const unsigned long long prev =
+              atomicCAS(&sk[q], (unsigned long long)kEmptyKey,
+                        (unsigned long long)key);
+          if (prev == kEmptyKey) {
+            sv[q] = pr[u].y;
+            break;
+          }
+          if (prev == key) {
+            dq[u] = (int)q;
+            break;
+          }
+          if (++probes == kRedSlots / 2) {  // table nearly full: split finer
+            full = 1;
+            break;
+          }
+          q = (q + 1) & (kRedSlots - 1);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kRedPer; ++u)
+        if (dq[u] >= 0) atomicAdd(&sv[dq[u]], pr[u].y);
+      __syncthreads();
+    }
+    if (full) {
+      // sub-bin `sub` of R becomes sub-bins 2 sub and 2 sub + 1 of 2R (the
+      // hash bits are taken from the top, so the ranges nest)
+      __syncthreads();
+      if (rb + B >= 60) break;  // cannot split further (not reachable)
+      R *= 2;
+      sub *= 2;
+      continue;
+    }
+    // compact the table: thread t owns slots u kRedThreads + t
+    uint64_t ball[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      ball[u] = __ballot(sk[u * kRedThreads + threadIdx.x] != kEmptyKey);
+      if (lane == 0) wc[u][wv] = (unsigned)__popcll(ball[u]);
+    }
+    __syncthreads();
+    int64_t base = wpos;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      unsigned before = 0, all = 0;
+#pragma unroll
+      for (int w = 0; w < kW; ++w) {
+        before += w < wv ? wc[u][w] : 0u;
+        all += wc[u][w];
+      }
+      const int q = u * kRedThreads + threadIdx.x;
+      if ((ball[u] >> lane) & 1) {
+        const int64_t o =
+            base + before + __popcll(ball[u] & ((1ull << lane) - 1));
+        okey[o] = sk[q];
+        oval[o] = (int64_t)sv[q];
+      }
+      base += all;
+    }
+    wpos = base;
+    __syncthreads();
+    ++sub;
+  }
+  // the last bin also clears the open samples' share [closed, n)
+  const int64_t end = bin == (int64_t)gridDim.x - 1 ? n : hi;
+  for (int64_t e = wpos + threadIdx.x; e < end; e += kRedThreads) {
+    okey[e] = kEmptyKey;
+    oval[e] = 0;
+  }
+  // one count per bin: atomics of every workgroup on one counter would
+  // serialize
+  if (threadIdx.x == 0) bin_distinct[bin] = (uint64_t)(wpos - lo);
+}
+
+// *out = sum of v[0 .. n) (one workgroup)
+__global__ __launch_bounds__(1024) void k_acc_sum(const uint64_t* v, int64_t n,
+                                                  int64_t* out) {
+  __shared__ unsigned long long ws[16];
+  unsigned long long x = 0;
+  for (int64_t e = threadIdx.x; e < n; e += 1024) x += v[e];
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < 16; ++w) t += ws[w];
+    *out = (int64_t)t;
+  }
+}
+
+// exclusive prefix of a u64 array (one 1024-thread workgroup per 4096
+// values, then the tile sums recursively)
+__global__ __launch_bounds__(1024) void k_acc_scan_tiles(const uint64_t* in,
+                                                        uint64_t* out,
+                                                        int64_t n,
+                                                        uint64_t* sums) {
+  __shared__ uint64_t ws[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t base = (int64_t)blockIdx.x * 4096 + (int64_t)t * 4;
+  uint64_t v[4], sum = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    v[u] = base + u < n ? in[base + u] : 0ull;
+    sum += v[u];
+  }
+  const uint64_t inc = wave_incl_scan(sum);
+  if (lane == 63) ws[wv] = inc;
+  __syncthreads();
+  uint64_t off = 0, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    off += w < wv ? ws[w] : 0ull;
+    all += ws[w];
+  }
+  uint64_t run = off + inc - sum;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (base + u < n) out[base + u] = run;
+    run += v[u];
+  }
+  if (t == 0) sums[blockIdx.x] = all;
+}
+
+__global__ void k_acc_scan_add(uint64_t* out, int64_t n,
+                               const uint64_t* offs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] += offs[e / 4096];
+}
+
+static hipError_t acc_scan(uint64_t* a, int64_t n, uint64_t* tmp,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nt = (n + 4095) / 4096;
+  k_acc_scan_tiles<<<(unsigned)nt, 1024, 0, st>>>(a, a, n, tmp);
+  if (nt > 1) {
+    hipError_t e = acc_scan(tmp, nt, tmp + nt, st);
+    if (e != hipSuccess) return e;
+    k_acc_scan_add<<<acc_blocks(n, 256), 256, 0, st>>>(a, n, tmp);
+  }
+  return hipGetLastError();
+}
+
+// first-level bin starts: starts[b] = offs[b * tiles] (b <= nb; the last
+// is the number of closed pairs)
+__global__ void k_acc_starts1(const uint64_t* offs, int64_t tiles, int B1,
+                              uint64_t* starts) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= (int64_t(1) << B1)) starts[b] = offs[b * tiles];
+}
+
+// second level: one workgroup per first-level bin partitions its pairs by
+// the next B2 hash bits (LDS counts, scan, place) and writes the sub-bin
+// starts; starts2[(b << B2) + r] for every sub-bin, starts2[end] = n
+constexpr int kAcc2Threads = 1024;
+
+__global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
+    const uint64_t* in, const uint64_t* starts1, int B1, int B2,
+    uint64_t* out, uint64_t* starts2) {
+  __shared__ unsigned h[1 << kAcc2MaxBits];
+  __shared__ unsigned wt[kAcc2Threads / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t lo = (int64_t)starts1[b], hi = (int64_t)starts1[b + 1];
+  const int nb2 = 1 << B2;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int r = t; r < nb2; r += kAcc2Threads) h[r] = 0;
+  __syncthreads();
+  for (int64_t e0 = lo + t; e0 < hi; e0 += kAcc2Threads * 4) {
+    uint64_t key[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + (int64_t)u * kAcc2Threads;
+      key[u] = e < hi ? in[2 * e] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + (int64_t)u * kAcc2Threads < hi)
+        atomicAdd(&h[(uint32_t)((mix64(key[u]) << B1) >> (64 - B2))], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of h: thread t owns sub-bins [t kPer2, (t + 1) kPer2)
+  constexpr int kPer2 = (1 << kAcc2MaxBits) / kAcc2Threads;
+  unsigned v[kPer2], sum = 0;
+#pragma unroll
+  for (int u = 0; u < kPer2; ++u) {
+    const int r = t * kPer2 + u;
+    v[u] = r < nb2 ? h[r] : 0u;
+    sum += v[u];
+  }
+  const unsigned inc = wave_incl_scan(sum);
+  if (lane == 63) wt[wv] = inc;
+  __syncthreads();
+  unsigned ex = inc - sum;
+  for (int w = 0; w < wv; ++w) ex += wt[w];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer2; ++u) {
+    const int r = t * kPer2 + u;
+    if (r < nb2) {
+      h[r] = ex;  // cursor
+      starts2[(b << B2) + r] = (uint64_t)(lo + ex);
+    }
+    ex += v[u];
+  }
+  if (b == (int64_t(1) << B1) - 1 && t == 0)
+    starts2[(int64_t)1 << (B1 + B2)] = starts1[b + 1];
+  __syncthreads();
+  for (int64_t e0 = lo + t; e0 < hi; e0 += kAcc2Threads * 4) {
+    ulonglong2 pr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = e0 + (int64_t)u * kAcc2Threads;
+      if (e < hi) pr[u] = *(const ulonglong2*)(in + 2 * e);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (e0 + (int64_t)u * kAcc2Threads >= hi) continue;
+      const uint32_t r = (uint32_t)((mix64(pr[u].x) << B1) >> (64 - B2));
+      const int64_t p = lo + atomicAdd(&h[r], 1u);
+      *(ulonglong2*)(out + 2 * p) = pr[u];
+    }
+  }
+}
+
+// pairs: n (key, inc) pairs, key EMPTY for none; work: accum_bytes(n);
+// output: okey / oval (n entries: the distinct keys, EMPTY elsewhere) and
+// *o_count (device) distinct keys.  The pair array is overwritten.
+hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
+                             size_t work_bytes, uint64_t* okey, int64_t* oval,
+                             int64_t* o_count, hipStream_t st) {
+  hipError_t e = launch_fill_u64((uint64_t*)o_count, 1, 0ull, st);
+  if (e != hipSuccess || n <= 0) return e;
+  if (work_bytes < accum_bytes(n)) return hipErrorInvalidValue;
+  const int B1 = acc_b1(n), B2 = acc_b2(n);
+  const int64_t tiles = (n + kAccTile - 1) / kAccTile;
+  const int64_t ncnt = tiles << B1;
+  const int64_t nb1 = int64_t(1) << B1;
+  char* p = (char*)work;
+  uint64_t* placed = (uint64_t*)p;
+  p += (size_t)n * 16;
+  uint64_t* cnt = (uint64_t*)p;
+  p += ((size_t)ncnt + 1) * 8;
+  uint64_t* starts = (uint64_t*)p;
+  p += (((size_t)1 << (B1 + B2)) + 1) * 8;
+  uint64_t* starts1 = (uint64_t*)p;
+  p += (((size_t)1 << (B1 + B2)) + 1) * 8;
+  uint64_t* bin_distinct = (uint64_t*)p;
+  p += (((size_t)1 << (B1 + B2)) + 1) * 8;
+  uint64_t* tmp = (uint64_t*)p;  // scan partial sums
+  k_acc_count<<<(unsigned)tiles, kAccThreads, 0, st>>>(pairs, n, B1, tiles,
+                                                       cnt);
+  if ((e = acc_scan(cnt, ncnt + 1, tmp, st)) != hipSuccess) return e;
+  k_acc_place<<<(unsigned)tiles, kAccThreads, 0, st>>>(pairs, n, B1, tiles,
+                                                       cnt, placed);
+  if (B2 == 0) {
+    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
+                                                            starts);
+    k_acc_reduce<<<(unsigned)nb1, kRedThreads, 0, st>>>(
+        placed, starts, B1, n, okey, oval, bin_distinct);
+  } else {
+    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
+                                                            starts1);
+    k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
+        placed, starts1, B1, B2, pairs, starts);
+    k_acc_reduce<<<(unsigned)(nb1 << B2), kRedThreads, 0, st>>>(
+        pairs, starts, B1 + B2, n, okey, oval, bin_distinct);
+  }
+  k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count);
+  return hipGetLastError();
+}
+
+}  // namespace mad

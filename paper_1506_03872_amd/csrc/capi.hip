@@ -1,6 +1,7 @@
 // capi.hip -- the C ABI (include/mad.h): argument checks, plan lifetime,
 // workspace management and the launch sequence of Alg. 2 + Alg. 3.
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -99,8 +100,10 @@ struct mad_plan {
   mad::DeviceBuffer lpA, lpB, lpIA, lpIB;
   mad::LowpView lv{};
   // workspace of mad_plan_topk
-  mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc, ord;
+  mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc, ord, acc;
   mad::HashTable h;
+  bool pairs = false;  // X built from per-sample pairs (else a hash table)
+  mad::HashTable h_run;  // X as the last run left it
   mad::SelectWork w;
   mad::SampleCounters* ctr = nullptr;
   int64_t ws_s = -1, ws_tp = -1, ws_t = -1;
@@ -156,6 +159,7 @@ static void plan_free_all(mad_plan* p) {
   mad::dev_free(p->cc);
   mad::dev_free(p->misc);
   mad::dev_free(p->ord);
+  mad::dev_free(p->acc);
   mad::dev_free(p->lpA);
   mad::dev_free(p->lpB);
   mad::dev_free(p->lpIA);
@@ -273,6 +277,17 @@ void mad_plan_destroy(mad_plan* p) {
   delete p;
 }
 
+// How X is built (result-invariant): from per-sample pairs by partitioned
+// accumulation (default), or in an open-addressing hash table updated by the
+// sampler with atomics (MAD_ACCUM=hash).
+static bool accum_pairs() {
+  static const bool v = [] {
+    const char* e = getenv("MAD_ACCUM");
+    return !(e && strcmp(e, "hash") == 0);
+  }();
+  return v;
+}
+
 static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   if (s <= p->ws_s && tp <= p->ws_tp && t <= p->ws_t) return MAD_OK;
   const int64_t s2 = s > p->ws_s ? s : p->ws_s;
@@ -280,7 +295,12 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   const int64_t t2 = t > p->ws_t ? t : p->ws_t;
   const double mn = (double)p->m * (double)p->n;
   const int64_t pairs = (double)s2 < mn ? s2 : (int64_t)mn;
-  int64_t hcap = next_pow2(2 * (pairs > 512 ? pairs : 512));
+  const bool use_pairs = accum_pairs();
+  // pair form: X is a table of s entries (each bin of pairs leaves its
+  // distinct keys in its own range); hash form: a table of twice min(s, mn)
+  // slots, rounded up to a power of two
+  const int64_t hcap = use_pairs ? (s2 > 1 ? s2 : 1)
+                                 : next_pow2(2 * (pairs > 512 ? pairs : 512));
   // candidates / boundary lists: post1 needs |Omega_s| <= pairs entries,
   // post3 needs 4 t (final set) + 4 t' (boundary of the candidates)
   int64_t ccap = pairs > 1 ? pairs : 1;
@@ -299,6 +319,10 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
                                        256 + 256)) != hipSuccess ||
       (p->kind == 0 &&
        (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(s2, p->d))) !=
+           hipSuccess) ||
+      (use_pairs &&
+       (e = mad::dev_alloc(p->acc, 16 * (size_t)(s2 > 1 ? s2 : 1) +
+                                       mad::accum_bytes(s2))) !=
            hipSuccess)) {
     p->ws_s = p->ws_tp = p->ws_t = -1;
     return hip_fail(e, "allocating workspace");
@@ -306,6 +330,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   p->h.keys = (uint64_t*)p->hk.p;
   p->h.vals = (int64_t*)p->hv.p;
   p->h.cap = hcap;
+  p->pairs = use_pairs;
   p->w.x = (uint64_t*)p->cx.p;
   p->w.key = (uint64_t*)p->ck.p;
   p->w.x2 = (uint64_t*)p->cx2.p;
@@ -348,22 +373,37 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   int rc = ensure_workspace(p, s, tp_eff, t);
   if (rc != MAD_OK) return rc;
   record(p, 2, st);
-  HIP_TRY(mad::launch_fill_u64(p->h.keys, p->h.cap, mad::kEmptyKey, st),
-          "clearing X");
-  HIP_TRY(mad::launch_fill_u64((uint64_t*)p->h.vals, p->h.cap, 0ull, st),
-          "clearing X");
+  mad::HashTable h = p->h;
+  if (p->pairs) {
+    h.pairs = (uint64_t*)p->acc.p;
+    h.cap = s;
+  } else {
+    HIP_TRY(mad::launch_fill_u64(h.keys, h.cap, mad::kEmptyKey, st),
+            "clearing X");
+    HIP_TRY(mad::launch_fill_u64((uint64_t*)h.vals, h.cap, 0ull, st),
+            "clearing X");
+  }
   HIP_TRY(mad::launch_fill_u64((uint64_t*)p->ctr, 8, 0ull, st),
           "clearing counters");
   record(p, 3, st);
   if (p->kind == 2)
-    HIP_TRY(mad::launch_sample_csr(p->ct, seed, 0, 0, s, s, p->h, p->ctr, st),
+    HIP_TRY(mad::launch_sample_csr(p->ct, seed, 0, 0, s, s, h, p->ctr, st),
             "sampling");
   else
-    HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, p->h,
+    HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, h,
                                      p->ctr, p->ord.p, p->ord.bytes, st),
             "sampling");
+  if (p->pairs) {
+    const size_t pb = 16 * (size_t)(s > 1 ? s : 1);
+    HIP_TRY(mad::launch_accumulate(h.pairs, s, (char*)p->acc.p + pb,
+                                   p->acc.bytes - pb, h.keys, h.vals,
+                                   (int64_t*)&p->ctr->distinct, st),
+            "accumulating X");
+  }
+  h.pairs = nullptr;
+  p->h_run = h;
   record(p, 4, st);
-  HIP_TRY(mad::launch_postprocess(p->h, p->A, p->B,
+  HIP_TRY(mad::launch_postprocess(h, p->A, p->B,
                                   p->kind == 2 ? &p->ct.in : nullptr,
                                   p->verify_prec != MAD_FP32 ? &p->lv : nullptr,
                                   p->n, p->d, tp_eff, t, plan_bmax(p), s,
@@ -606,7 +646,7 @@ int mad_debug_scores(mad_plan* p, int64_t* keys, int64_t* xfix, int64_t cap,
   if (!p || !n) return fail(MAD_EINVAL, "plan and n are required");
   if (!p->ran) return fail(MAD_EINVAL, "no mad_plan_topk has run");
   int64_t* cnt = p->w.counts + 6;
-  HIP_TRY(mad::launch_dump_scores(p->h, keys, xfix, keys ? cap : 0, cnt, 0),
+  HIP_TRY(mad::launch_dump_scores(p->h_run, keys, xfix, keys ? cap : 0, cnt, 0),
           "debug scores");
   HIP_TRY(hipDeviceSynchronize(), "debug scores");
   int64_t total = 0;

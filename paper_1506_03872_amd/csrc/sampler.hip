@@ -55,11 +55,17 @@ template <int U, bool DEBUG, bool GROUPED>
 __global__ __launch_bounds__(256) void k_sample_dense(
     DenseSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
     int F_debug,
-    uint64_t* hkeys, int64_t* hvals, uint64_t hmask,
+    uint64_t* hkeys, int64_t* hvals, uint64_t hmask, uint64_t* pairs,
     SampleCounters* ctr, int32_t* ok, int32_t* oi, int32_t* oj,
     int32_t* okp, int64_t* oinc, GroupOrder go) {
   extern __shared__ uint64_t t0s[];  // T0 when it fits (kT0Lds entries)
-  if (!(wtot[0] > 0.0)) return;  // ||W||_1 = 0: nothing can be sampled
+  if (!(wtot[0] > 0.0)) {  // ||W||_1 = 0: nothing can be sampled
+    if (pairs)
+      for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+           e < a.count; e += (int64_t)gridDim.x * blockDim.x)
+        *(ulonglong2*)(pairs + 2 * e) = make_ulonglong2(kEmptyKey, 0ull);
+    return;
+  }
   const int N0 = 1 << a.L0;
   const bool t0_lds = N0 <= kT0Lds;
   if (t0_lds)
@@ -169,7 +175,22 @@ __global__ __launch_bounds__(256) void k_sample_dense(
         pend[u] = ins[u];
         nclosed += smp[u].closed;
       }
-      bool any = true;
+      if (pairs) {
+        // pair form: (key, inc) at the sample's place in the walk, which is
+        // one-to-one with the samples of this launch
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = base + (int64_t)u * nthreads;
+          if (e < a.count) {
+            ulonglong2 pr;
+            pr.x = ins[u] ? key[u] : kEmptyKey;
+            pr.y = (unsigned long long)smp[u].inc;
+            *(ulonglong2*)(pairs + 2 * e) = pr;
+          }
+          pend[u] = false;
+        }
+      }
+      bool any = !pairs;
       while (any) {
         uint64_t prev[U];
 #pragma unroll
@@ -193,7 +214,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (ins[u] && smp[u].inc != 0)
+        if (!pairs && ins[u] && smp[u].inc != 0)
           atomicAdd((unsigned long long*)(hvals + slot[u]),
                     (unsigned long long)smp[u].inc);
     }
@@ -248,9 +269,20 @@ static DenseSampleArgs dense_args(const DenseTables& t, const float* B,
   return a;
 }
 
+// most workgroups of a sampling launch (result-invariant;
+// MAD_SAMPLER_GRID overrides for tuning)
+static int64_t sampler_max_grid() {
+  static const int64_t g = [] {
+    const char* e = getenv("MAD_SAMPLER_GRID");
+    const long long v = e ? atoll(e) : 8192;
+    return (int64_t)(v >= 8 && v <= 65536 ? v : 8192);
+  }();
+  return g;
+}
+
 static unsigned sample_grid(int64_t count, int per_thread) {
   int64_t blocks = (count + 256LL * per_thread - 1) / (256LL * per_thread);
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > sampler_max_grid()) blocks = sampler_max_grid();
   return (unsigned)(blocks < 1 ? 1 : blocks);
 }
 
@@ -422,8 +454,8 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
   case UU:                                                                 \
     k_sample_dense<UU, false, false>                                       \
         <<<sample_grid(count, UU), 256, lds, st>>>(                        \
-            a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, ctr,      \
-            nullptr, nullptr, nullptr, nullptr, nullptr, GroupOrder{});    \
+            a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, h.pairs,  \
+            ctr, nullptr, nullptr, nullptr, nullptr, nullptr, GroupOrder{}); \
     break;
       MAD_SAMPLE_CASE(1)
       MAD_SAMPLE_CASE(2)
@@ -458,8 +490,9 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     if (g8 * 8 > nch) g8 = (nch + 7) / 8;
     if (g8 < 1) g8 = 1;
     k_sample_dense<4, false, true><<<(unsigned)(8 * g8), 256, lds, st>>>(
-        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, ctr, nullptr,
-        nullptr, nullptr, nullptr, nullptr, go);
+        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm,
+        h.pairs ? h.pairs + 2 * c0 : nullptr, ctr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, go);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -475,8 +508,8 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
   k_sample_dense<2, true, false>
       <<<sample_grid(count, 2), 256, t0_lds_bytes(t), st>>>(
-      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, k, i, j, kp, inc,
-      GroupOrder{});
+      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, nullptr, k, i, j,
+      kp, inc, GroupOrder{});
   return hipGetLastError();
 }
 

@@ -72,46 +72,47 @@ __device__ void block_hist_flush(unsigned* lds, unsigned* gh) {
 }
 
 // ---------------------------------------------------------------------------
-// post1 step 1: histogram of x > 0 straight from the score table
+// post1 step 1: histogram of x > 0 straight from the score table (the
+// number of positive scores is the histogram's total)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_score_hist(const int64_t* hvals,
                                                     int64_t cap,
-                                                    unsigned* hist,
-                                                    int64_t* counts) {
+                                                    const int64_t* live,
+                                                    unsigned* hist) {
   __shared__ unsigned h[kBins];
-  __shared__ unsigned long long part[4];
   for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  unsigned long long npos = 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cap;
-       e += stride) {
-    const int64_t v = hvals[e];
-    if (v > 0) {
-      ++npos;
-      atomicAdd(&h[fbin((uint64_t)v)], 1u);
+  if (live && *live < cap) cap = *live;
+  constexpr int kU = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kU;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x * kU + threadIdx.x;
+       e0 < cap; e0 += stride) {
+    int64_t v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = e0 + (int64_t)u * blockDim.x;
+      v[u] = e < cap ? hvals[e] : 0;
     }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (v[u] > 0) atomicAdd(&h[fbin((uint64_t)v[u])], 1u);
   }
   block_hist_flush(h, hist);
-  npos = wave_sum(npos);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = npos;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long t = part[0] + part[1] + part[2] + part[3];
-    if (t) atomicAdd((unsigned long long*)&counts[kCntPos], t);
-  }
 }
 
-// step 2a (one block): the boundary bin from the histogram, then clear it
+// step 2a (one block): the boundary bin from the histogram, then clear it.
+// The element count is *n_ptr, or the histogram's total when n_ptr is
+// null; n_store (if set) receives it.
 __global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
                                                        const int64_t* n_ptr,
                                                        int64_t k,
-                                                       Coarse* out) {
+                                                       Coarse* out,
+                                                       int64_t* n_store) {
   __shared__ unsigned long long part[256];
   __shared__ int chosen;
   __shared__ unsigned long long before;
+  __shared__ long long total;
   const int t = threadIdx.x;
-  const int64_t n = *n_ptr;
   if (t == 0) chosen = -1;
   // thread t owns 8 consecutive bins in descending order
   unsigned v[8];
@@ -129,8 +130,10 @@ __global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
       part[u] = acc;
       acc += x;
     }
+    total = (long long)acc;
   }
   __syncthreads();
+  const int64_t n = n_ptr ? *n_ptr : (int64_t)total;
   if (n > k) {
     unsigned long long acc = part[t];
     for (int q = 0; q < 8; ++q) {
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
   __syncthreads();
   for (int b = t; b < kBins; b += 256) hist[b] = 0;  // ready for reuse
   if (t == 0) {
+    if (n_store) *n_store = n;
     out->n = n;
     out->k = k;
     if (n <= k || chosen < 0) {
@@ -182,33 +186,77 @@ __device__ __forceinline__ int64_t block_append(bool take,
 }
 
 // ---------------------------------------------------------------------------
-// post1 step 2b: split the score table (winners -> w*, boundary -> b*)
+// post1 step 2b: split the score table (winners -> w*, boundary -> b*).
+// Each block stages its finds in LDS and reserves output space once per
+// flush: one global atomic per list and flush, not per wave or element.
 // ---------------------------------------------------------------------------
+constexpr int kSplitU = 4;       // elements per thread and step
+constexpr int kStage = 2048;     // staged entries per list
+
 __global__ __launch_bounds__(256) void k_score_split(
     const uint64_t* hkeys, const int64_t* hvals, int64_t cap,
-    const Coarse* cz, uint64_t* wx, uint64_t* wkey, int64_t wcap,
-    uint64_t* bx, uint64_t* bkey, int64_t bcap, int64_t* counts) {
-  __shared__ unsigned wcount[4];
-  __shared__ unsigned long long wbase[5];
+    const int64_t* live, const Coarse* cz, uint64_t* wx, uint64_t* wkey,
+    int64_t wcap, uint64_t* bx, uint64_t* bkey, int64_t bcap,
+    int64_t* counts) {
+  __shared__ unsigned long long sx[2][kStage];
+  __shared__ unsigned long long sk[2][kStage];
+  __shared__ unsigned scnt[2];
+  __shared__ unsigned long long gbase[2];
   const Coarse c = *cz;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < cap; b0 += stride) {
-    const int64_t e = b0 + threadIdx.x;
-    const int64_t v = e < cap ? hvals[e] : 0;
-    const int bin = v > 0 ? fbin((uint64_t)v) : -2;
-    const bool win = v > 0 && (c.bin < 0 || bin > c.bin);
-    const bool bnd = v > 0 && c.bin >= 0 && bin == c.bin;
-    const int64_t ws = block_append(
-        win, (unsigned long long*)&counts[kCntWin], wcount, wbase);
-    if (win && ws < wcap) {
-      wx[ws] = (uint64_t)v;
-      wkey[ws] = hkeys[e];
+  if (live && *live < cap) cap = *live;
+  const int t = threadIdx.x;
+  if (t == 0) scnt[0] = scnt[1] = 0;
+  __syncthreads();
+  uint64_t* ox[2] = {wx, bx};
+  uint64_t* ok[2] = {wkey, bkey};
+  const int64_t ocap[2] = {wcap, bcap};
+  const int64_t step = 256 * kSplitU;
+  const int64_t stride = (int64_t)gridDim.x * step;
+  for (int64_t b0 = (int64_t)blockIdx.x * step; b0 < cap + stride;
+       b0 += stride) {
+    const bool last = b0 >= cap;  // one extra (uniform) round to flush
+    if (!last) {
+      int64_t v[kSplitU];
+#pragma unroll
+      for (int u = 0; u < kSplitU; ++u) {
+        const int64_t e = b0 + t + (int64_t)u * 256;
+        v[u] = e < cap ? hvals[e] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kSplitU; ++u) {
+        if (v[u] <= 0) continue;
+        const int bin = fbin((uint64_t)v[u]);
+        const int L = (c.bin < 0 || bin > c.bin) ? 0 : (bin == c.bin ? 1 : -1);
+        if (L < 0) continue;
+        const unsigned p = atomicAdd(&scnt[L], 1u);
+        sx[L][p] = (unsigned long long)v[u];
+        sk[L][p] = hkeys[b0 + t + (int64_t)u * 256];
+      }
     }
-    const int64_t bs = block_append(
-        bnd, (unsigned long long*)&counts[kCntBound], wcount, wbase);
-    if (bnd && bs < bcap) {
-      bx[bs] = (uint64_t)v;
-      bkey[bs] = hkeys[e];
+    __syncthreads();
+    const unsigned n0 = scnt[0], n1 = scnt[1];
+    if (last || n0 > kStage - step || n1 > kStage - step) {
+      if (t < 2) {
+        const unsigned nl = t ? n1 : n0;
+        gbase[t] = nl ? atomicAdd((unsigned long long*)&counts[t ? kCntBound
+                                                                 : kCntWin],
+                                  (unsigned long long)nl)
+                      : 0ull;
+      }
+      __syncthreads();
+      for (int L = 0; L < 2; ++L) {
+        const unsigned nl = L ? n1 : n0;
+        for (unsigned i = t; i < nl; i += 256) {
+          const int64_t d = (int64_t)gbase[L] + i;
+          if (d < ocap[L]) {
+            ox[L][d] = sx[L][i];
+            ok[L][d] = sk[L][i];
+          }
+        }
+      }
+      __syncthreads();
+      if (t == 0) scnt[0] = scnt[1] = 0;
+      __syncthreads();
     }
   }
 }
@@ -614,9 +662,10 @@ __global__ void k_final_sort(const uint64_t* fkey, const uint64_t* fx,
 
 // every key of X (closed diamonds), for parity checks
 __global__ void k_dump_scores(const uint64_t* hkeys, const int64_t* hvals,
-                              int64_t cap, int64_t* keys, int64_t* xfix,
-                              int64_t out_cap, int64_t* count) {
+                              int64_t cap, const int64_t* live, int64_t* keys,
+                              int64_t* xfix, int64_t out_cap, int64_t* count) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (live && *live < cap) cap = *live;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cap;
        e += stride) {
     const uint64_t kk = hkeys[e];
@@ -636,7 +685,7 @@ hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,
   hipError_t e = launch_fill_u64((uint64_t*)count, 1, 0ull, st);
   if (e != hipSuccess) return e;
   k_dump_scores<<<blocks_for(h.cap, 256, 4096), 256, 0, st>>>(
-      h.keys, h.vals, h.cap, keys, xfix, out_cap, count);
+      h.keys, h.vals, h.cap, h.live, keys, xfix, out_cap, count);
   return hipGetLastError();
 }
 
@@ -682,7 +731,8 @@ hipError_t launch_select_keys_by_absval(const uint64_t* keys, const float* v,
     return e;
   k_absval_hist<<<blocks_for(cnt, 256 * 8, 2048), 256, 0, st>>>(v, count,
                                                                 absbits, hist);
-  k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], k, cz);
+  k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], k, cz,
+                                     nullptr);
   uint64_t* fp = key;
   uint64_t* fkey = out_keys;
   uint64_t* fx = key + k;
@@ -729,7 +779,8 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
   if (e != hipSuccess) return e;
   k_verify<<<blocks_for(cnt * 64, 256, 2048), 256, 0, st>>>(
       keys, counts, A, B, n, d, cnt, c, absbits, hist);
-  k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], t, cz);
+  k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], t, cz,
+                                     nullptr);
   uint64_t* fp = key;
   uint64_t* fkey = key + t;
   uint64_t* fx = key + 2 * t;
@@ -770,12 +821,13 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   if (e != hipSuccess) return e;
   // ---- post1: top t' of x over x > 0 ------------------------------------
   k_score_hist<<<blocks_for(h.cap, 256 * 16, 2048), 256, 0, st>>>(
-      h.vals, h.cap, w.hist, counts);
-  k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntPos], t_prime, cz);
+      h.vals, h.cap, h.live, w.hist);
+  k_coarse_decide<<<1, 256, 0, st>>>(w.hist, nullptr, t_prime, cz,
+                                     &counts[kCntPos]);
   // winners go straight to (x2, key2); the boundary bin to (x, key)
-  k_score_split<<<blocks_for(h.cap, 256 * 16, 2048), 256, 0, st>>>(
-      h.keys, h.vals, h.cap, cz, w.x2, w.key2, w.cap2, w.x, w.key, w.cap,
-      counts);
+  k_score_split<<<blocks_for(h.cap, 256 * 16, 1024), 256, 0, st>>>(
+      h.keys, h.vals, h.cap, h.live, cz, w.x2, w.key2, w.cap2, w.x, w.key,
+      w.cap, counts);
   k_fine_select<<<1, kFineThreads, 0, st>>>(
       cz, w.x, w.key, nullptr, nullptr, w.cap, counts, kCntWin, w.x2, w.key2,
       nullptr, nullptr, w.cap2, kCntCand);
@@ -785,7 +837,8 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
     if (e != hipSuccess) return e;
     k_verify_lowp<<<blocks_for(t_prime * 16, 256, 2048), 256, 0, st>>>(
         w.key2, counts, *lowp, n, w.cap2, w.c, w.hist);
-    k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntWin], t, cz + 2);
+    k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntWin], t, cz + 2,
+                                       nullptr);
     k_lowp_filter<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
         cz + 2, w.key2, w.x2, w.c, w.cap2, w.x, w.key, counts);
     k_lowp_copy<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
@@ -802,7 +855,8 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   // ---- post3: top t by |c| ----------------------------------------------
   e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
   if (e != hipSuccess) return e;
-  k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntCand], t, cz + 1);
+  k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntCand], t, cz + 1,
+                                     nullptr);
   // final set in w.key[0 .. 4t): |c| bits, key, x, c; boundary after it
   uint64_t* fp = w.key;
   uint64_t* fkey = w.key + t;
