@@ -41,6 +41,10 @@ struct DenseTables {
   float* bmax = nullptr; // 1
   int* bad = nullptr;    // 1
   int gram = 0;          // B = A, symmetrised scores (Sec. 3.3)
+  // the B-side family T2 is built on a stream of its own, forked from and
+  // joined back into the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,

@@ -23,6 +23,8 @@
 // work that any parallel schedule reproduces bit for bit (the
 // prefix-sum formulation of the sweep follows Huebschle-Schneider and
 // Sanders, "Parallel Weighted Random Sampling", ACM TOMS 2022).
+#include <stdlib.h>
+
 #include "alias_common.hpp"
 #include "mad_common.hpp"
 #include "plan.hpp"
@@ -39,6 +41,9 @@ struct WColAbs {  // table per coordinate k over vectors r: |X[r][k]| * scale_r
   __device__ double operator()(int64_t seg, int64_t r) const {
     const double w = fabs((double)X[r * d + seg]);
     return scale ? w * scale[r] : w;
+  }
+  __device__ uint32_t sgn(int64_t seg, int64_t r) const {
+    return sign_bit(X[r * d + seg]);
   }
 };
 
@@ -230,106 +235,6 @@ __global__ void k_quantize(W w, int64_t S, int64_t N, int64_t R, int L,
   }
 }
 
-// Column families (one table per coordinate k over the vectors): a wave
-// handles one run of 64 consecutive tables, lane = table, so every load reads
-// 64 consecutive floats of one vector.  Loads are issued kColGroup at a time
-// (clamped to the last row, so they carry no branch and stay in flight
-// together) ahead of the sequential adds, and quanta go out through an LDS
-// transpose so each store writes 64 consecutive slots of one table.  The
-// sign bit of each item is kept in bit 63 of its quantum (quanta are below
-// 2^62) for the alias construction.
-constexpr int kColGroup = 32;
-
-// Column run walk: a wave handles one run of 64 consecutive tables, lane =
-// table, and writes each item's run-local prefix l_r (FP64 bits, the item's
-// sign bit in bit 63; l >= 0) through an LDS transpose into the
-// table-major layout of the quanta.  The run total is l at the run's last
-// item.  Loads are issued kColGroup at a time, clamped to the last row so
-// they carry no branch and stay in flight together.
-__global__ __launch_bounds__(64) void k_col_local(
-    const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
-    int L, uint64_t* Lbuf) {
-  __shared__ uint64_t buf[64][65];
-  const int64_t tiles = (S + 63) / 64;
-  const int64_t c = blockIdx.x / tiles;
-  const int64_t seg0 = (blockIdx.x % tiles) * 64;
-  const int lane = threadIdx.x;
-  const int64_t seg = seg0 + lane;
-  const int64_t segc = seg < S ? seg : S - 1;
-  const int64_t r0 = c * kRun;
-  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
-  double l = 0.0;
-  for (int64_t g0 = r0; g0 < r1; g0 += 64) {
-#pragma unroll
-    for (int h = 0; h < 64; h += kColGroup) {
-      float xv[kColGroup];
-      double sv[kColGroup];
-#pragma unroll
-      for (int u = 0; u < kColGroup; ++u) {
-        const int64_t r = g0 + h + u < r1 ? g0 + h + u : r1 - 1;
-        xv[u] = X[r * d + segc];
-        sv[u] = scale ? scale[r] : 1.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kColGroup; ++u) {
-        const int64_t r = g0 + h + u;
-        uint64_t bits = 0;
-        if (r < r1) {
-          const double w = scale ? fabs((double)xv[u]) * sv[u]
-                                 : fabs((double)xv[u]);
-          l = r == r0 ? w : l + w;
-          bits = (uint64_t)__double_as_longlong(l) |
-                 ((uint64_t)sign_bit(xv[u]) << 63);
-        }
-        buf[h + u][lane] = bits;
-      }
-    }
-    __syncthreads();
-    const int64_t r = g0 + lane;
-    if (r < r1)
-      for (int sl = 0; sl < 64 && seg0 + sl < S; ++sl)
-        Lbuf[((seg0 + sl) << L) + r] = buf[lane][sl];
-    __syncthreads();
-  }
-}
-
-// run offsets from the stored run-local prefixes: E_0 = 0,
-// E_{c+1} = E_c + l(last item of run c); total T = E_R.  One 64-thread
-// block per table: the run totals are gathered in parallel into LDS, then
-// one lane adds them left to right.
-constexpr int kOffChunk = 2048;
-
-__global__ __launch_bounds__(64) void k_col_offsets(const uint64_t* Lbuf,
-                                                    int64_t S, int64_t N,
-                                                    int L, double* E,
-                                                    double* tot) {
-  __shared__ double buf[kOffChunk];
-  const int64_t seg = blockIdx.x;
-  const int64_t R = (N + kRun - 1) / kRun;
-  double e = 0.0;  // lane 0's running offset
-  for (int64_t c0 = 0; c0 < R; c0 += kOffChunk) {
-    const int64_t nc = R - c0 < kOffChunk ? R - c0 : kOffChunk;
-    for (int64_t u = threadIdx.x; u < nc; u += 64) {
-      const int64_t c = c0 + u;
-      const int64_t last = (N < (c + 1) * kRun ? N : (c + 1) * kRun) - 1;
-      const uint64_t raw = Lbuf[(seg << L) + last] & ~(1ull << 63);
-      buf[u] = __longlong_as_double((long long)raw);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int64_t u = 0; u < nc; ++u) {
-        const double sc = buf[u];
-        buf[u] = e;  // E_c
-        e = e + sc;
-      }
-    }
-    __syncthreads();
-    for (int64_t u = threadIdx.x; u < nc; u += 64) E[(c0 + u) * S + seg] = buf[u];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) tot[seg] = e;
-}
-
 template <class W>
 static hipError_t uniform_quanta(W w, int64_t S, int64_t N, int L,
                                  double* tot, uint64_t* q, double* runbuf,
@@ -350,138 +255,145 @@ static hipError_t uniform_quanta(W w, int64_t S, int64_t N, int L,
 // alias construction.  Each quantum carries its item's sign bit in bit 63;
 // the lists below carry it in bit 31 of the slot id.
 // ---------------------------------------------------------------------------
-// one wave per table from stored quanta (2^L <= 64 * SPL <= 512 slots;
-// 4 tables per block use at most 40 KB of LDS)
-template <int SPL>
-__global__ __launch_bounds__(256) void k_alias_wave(const uint64_t* q,
-                                                    const double* tot,
-                                                    int64_t S, int L,
-                                                    uint64_t* ent) {
+// Small tables (N <= 2^L <= 512 items), entirely on chip, TB tables per
+// 256-thread block (small_tables picks TB for the LDS budget):
+//   phase 1  the block loads its tables' weights (with the sign bits in
+//            bit 63; weights are >= 0) into LDS together; then lanes of wave
+//            0, one per table, walk the items left to right and overwrite
+//            them with the run-local prefixes l_r (sign bits kept); the
+//            totals of the runs of kRun items go to LDS as well;
+//   phase 2  each wave takes a table at a time: E_c and T from the run
+//            totals in the two-level order (E_0 = 0, E_{c+1} = E_c + l of
+//            run c's last item, T = E_R), then per slot in parallel P_r =
+//            E_c + l_r (0 + l_r = l_r exactly in the first run), F_r =
+//            floor(2^K P_r / T) and q_r = F_r - F_{r-1} (F of the slot
+//            before a lane's first comes from the previous lane), and the
+//            alias table from the quanta in registers.
+// Padding slots and dead tables get q = 0.
+template <int SPL, class W>
+__global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
+                                                      int64_t N, int L,
+                                                      int TB, double* tot,
+                                                      uint64_t* ent) {
   extern __shared__ uint64_t smem64[];
   const int Np = 1 << L;
+  const int ld = Np + 1;  // row stride of the prefixes (bank spread)
+  const int R = (int)((N + kRun - 1) / kRun);
+  uint64_t* lb = smem64;                        // TB x ld
+  double* rt = (double*)(smem64 + TB * ld);     // TB x 4 run totals
+  uint64_t* ascr = smem64 + TB * ld + TB * 4;   // alias scratch, 4 waves
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
-  const bool active = seg < S && tot[seg < S ? seg : 0] > 0.0;
-  if (seg < S && !active)  // dead table: never sampled, entries zero
-    for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
-  uint64_t qv[SPL];
-  uint32_t sg[SPL];
-#pragma unroll
-  for (int s = 0; s < SPL; ++s) {
-    const int r = lane * SPL + s;
-    const uint64_t raw = active && r < Np ? q[(seg << L) + r] : 0ull;
-    qv[s] = raw & kQMask;
-    sg[s] = (uint32_t)(raw >> 63);
-  }
-  wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * Np,
-                  smem64 + (int64_t)wv * 2 * Np + Np,
-                  (uint32_t*)(smem64 + 8 * Np) + (int64_t)wv * Np,
-                  EmitPacked{ent + (seg << L)});
-}
-
-
-static hipError_t alias_small(const uint64_t* q, const double* tot, int64_t S,
-                              int L, uint64_t* ent, hipStream_t st) {
-  const int Np = 1 << L;
-  const size_t lds = (size_t)4 * Np * 20;
-  const unsigned blocks = grid_for(S, 4);
-  if (Np <= 64)
-    k_alias_wave<1><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
-  else if (Np <= 128)
-    k_alias_wave<2><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
-  else if (Np <= 256)
-    k_alias_wave<4><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
-  else
-    k_alias_wave<8><<<blocks, 256, lds, st>>>(q, tot, S, L, ent);
-  return hipGetLastError();
-}
-
-// Small tables (N <= 2^L <= 512 items), one lane per table: the total in
-// the two-level order, then the same prefix again with F_r = floor(2^K P_r
-// / T) and q_r = F_r - F_{r-1} (the item's sign bit in bit 63); padding
-// slots and dead tables get q = 0.  Every lane walks its own table, so the
-// sequential FP64 chain keeps all lanes busy.  Two-level order inside one
-// lane: l restarts at each run, E collects the run totals, P_r = E + l_r
-// (E = 0 in the first run, where 0 + l_r = l_r exactly).  Loads go 8 at a
-// time; every 8 slots the block's quanta pass through LDS so that each
-// store writes 64 consecutive bytes of 8 tables.
-template <class W>
-__global__ __launch_bounds__(64) void k_lane_quanta(W w, int64_t S, int64_t N,
-                                                    int L, double* tot,
-                                                    uint64_t* q) {
-  __shared__ uint64_t tq[64][9];
-  const int lane = threadIdx.x;
-  const int64_t seg0 = (int64_t)blockIdx.x * 64;
-  const int64_t nseg = S - seg0 < 64 ? S - seg0 : 64;
-  const int64_t seg = seg0 + (lane < nseg ? lane : nseg - 1);
-  const bool mine = lane < nseg;
-  const int64_t Np = int64_t(1) << L;
-  double E = 0.0, l = 0.0;
-  for (int64_t r0 = 0; r0 < N; r0 += 8) {
-    double wv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) wv[u] = w(seg, r0 + u < N ? r0 + u : N - 1);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t r = r0 + u;
-      if (r < N) {
-        if (r > 0 && r % kRun == 0) {
-          E = E + l;
-          l = 0.0;
-        }
-        l = l + wv[u];
-      }
-    }
-  }
-  const double T = E + l;
-  if (mine) tot[seg] = T;
-  const bool live = mine && T > 0.0;
   const int K = L + kCapBits;
-  E = 0.0;
-  l = 0.0;
-  uint64_t Fp = 0;
-  for (int64_t r0 = 0; r0 < Np; r0 += 8) {
-    double wv[8];
-    uint32_t sv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t rr = r0 + u < N ? r0 + u : N - 1;
-      wv[u] = live ? w(seg, rr) : 0.0;
-      sv[u] = live ? w.sgn(seg, rr) : 0u;
+  uint64_t* Ld = ascr + (int64_t)wv * 2 * Np;
+  uint64_t* He = Ld + Np;
+  uint32_t* Hi = (uint32_t*)(ascr + 8 * Np) + (int64_t)wv * Np;
+  {  // this block's chunk of TB tables
+    const int64_t chunk = blockIdx.x;
+    const int64_t seg0 = chunk * TB;
+    // ---- phase 1 -----------------------------------------------------------
+    // the block's weights and sign bits, all loads in flight together
+    const int ntab = S - seg0 < TB ? (int)(S - seg0) : TB;
+    for (int i = threadIdx.x; i < ntab * (int)N; i += 256) {
+      const int tb = i / (int)N, r = i - tb * (int)N;
+      lb[tb * ld + r] = (uint64_t)__double_as_longlong(w(seg0 + tb, r)) |
+                        ((uint64_t)w.sgn(seg0 + tb, r) << 63);
     }
+    __syncthreads();
+    if (wv == 0 && lane < ntab) {
+      uint64_t* row = lb + lane * ld;
+      double l = 0.0;
+      for (int r0 = 0; r0 < N; r0 += 8) {
+        uint64_t x[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t r = r0 + u;
-      uint64_t qq = 0;
-      if (live && r < N) {
-        if (r > 0 && r % kRun == 0) {
-          E = E + l;
-          l = 0.0;
+        for (int u = 0; u < 8; ++u) x[u] = row[r0 + u < N ? r0 + u : N - 1];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = r0 + u;
+          if (r < N) {
+            const double wr = __longlong_as_double((long long)(x[u] & kQMask));
+            l = r % kRun == 0 ? wr : l + wr;
+            row[r] = (uint64_t)__double_as_longlong(l) | (x[u] & ~kQMask);
+            if (r % kRun == kRun - 1 || r == N - 1) rt[lane * 4 + r / kRun] = l;
+          }
         }
-        l = l + wv[u];
-        const uint64_t F = (uint64_t)floor(ldexp((E + l) / T, K));
-        qq = (F - Fp) | ((uint64_t)sv[u] << 63);
-        Fp = F;
       }
-      tq[lane][u] = qq;
     }
     __syncthreads();
-    // lanes 8t .. 8t+7 write slots r0 .. r0+7 of table t (8 tables a pass)
-    const int64_t nc = Np - r0 < 8 ? Np - r0 : 8;
-    for (int t0 = 0; t0 < 64; t0 += 8) {
-      const int sl = t0 + (lane >> 3), u = lane & 7;
-      if (sl < nseg && u < nc) q[((seg0 + sl) << L) + r0 + u] = tq[sl][u];
+    // ---- phase 2 -----------------------------------------------------------
+    for (int t0 = 0; t0 < TB; t0 += 4) {  // every wave runs every round
+      const int tb = t0 + wv;
+      const int64_t seg = seg0 + tb;
+      const bool have = tb < TB && seg < S;
+      double Ec[4] = {0.0, 0.0, 0.0, 0.0};
+      double T = 0.0;
+      if (have)
+        for (int c = 0; c < R; ++c) {
+          Ec[c] = T;
+          T = T + rt[tb * 4 + c];
+        }
+      const bool live = have && T > 0.0;
+      if (have && lane == 0) tot[seg] = T;
+      if (have && !live)  // dead table: never sampled, entries zero
+        for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
+      uint64_t F[SPL];
+      uint32_t sg[SPL];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        const int r = lane * SPL + s;
+        F[s] = 0;
+        sg[s] = 0;
+        if (live && r < N) {
+          const uint64_t raw = lb[tb * ld + r];
+          const double lr = __longlong_as_double((long long)(raw & kQMask));
+          F[s] = (uint64_t)floor(ldexp((Ec[r / kRun] + lr) / T, K));
+          sg[s] = (uint32_t)(raw >> 63);
+        }
+      }
+      uint64_t Fp = __shfl_up(F[SPL - 1], 1, 64);
+      if (lane == 0) Fp = 0;
+      uint64_t qv[SPL];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        const int r = lane * SPL + s;
+        qv[s] = live && r < N ? F[s] - Fp : 0ull;
+        Fp = F[s];
+      }
+      wave_alias<SPL>(qv, sg, live, L, Ld, He, Hi,
+                      EmitPacked{ent + ((have ? seg : 0) << L)});
+      __syncthreads();  // the wave's alias scratch is reused next round
     }
-    __syncthreads();
   }
 }
 
 template <class W>
-static hipError_t small_tables_q(W w, int64_t S, int64_t N, int L,
-                                 double* tot, uint64_t* q, uint64_t* ent,
-                                 hipStream_t st) {
-  k_lane_quanta<W><<<grid_for(S, 64), 64, 0, st>>>(w, S, N, L, tot, q);
-  return alias_small(q, tot, S, L, ent, st);
+static hipError_t small_tables(W w, int64_t S, int64_t N, int L, double* tot,
+                               uint64_t* ent, hipStream_t st) {
+  if (S <= 0 || N <= 0) return hipSuccess;
+  const int Np = 1 << L;
+  // the most tables per block (a power of two, 4 .. 64) within the LDS
+  // budget; about 20 KB measured best (MAD_SMALL_LDS overrides it for
+  // tuning)
+  static const size_t budget = [] {
+    const char* e = getenv("MAD_SMALL_LDS");
+    const long v = e ? atol(e) : 20480;
+    return (size_t)(v >= 4096 && v <= 65536 ? v : 20480);
+  }();
+  auto lds_for = [Np](int tb) {
+    return ((size_t)tb * (Np + 1) + (size_t)tb * 4 + (size_t)Np * 10) * 8;
+  };
+  int TB = 64;
+  while (TB > 4 && lds_for(TB) > budget) TB /= 2;
+  const size_t lds = lds_for(TB);
+  const unsigned blocks = grid_for(S, TB);
+  if (Np <= 64)
+    k_small_tables<1, W><<<blocks, 256, lds, st>>>(w, S, N, L, TB, tot, ent);
+  else if (Np <= 128)
+    k_small_tables<2, W><<<blocks, 256, lds, st>>>(w, S, N, L, TB, tot, ent);
+  else if (Np <= 256)
+    k_small_tables<4, W><<<blocks, 256, lds, st>>>(w, S, N, L, TB, tot, ent);
+  else
+    k_small_tables<8, W><<<blocks, 256, lds, st>>>(w, S, N, L, TB, tot, ent);
+  return hipGetLastError();
 }
 
 // large tables (2^L >= 1024 slots): blocks of 1024 slots (256 threads x 4)
@@ -509,56 +421,6 @@ __device__ Quad block_excl_scan(Quad& v) {
   v = Quad{off.nl + inc.nl - v.nl, off.nh + inc.nh - v.nh,
            off.sd + inc.sd - v.sd, off.se + inc.se - v.se};
   return all;
-}
-
-// Quanta from stored prefixes, one thread per 4 consecutive slots:
-// q_r = F_r - F_{r-1}, F_r = floor(2^K P_r / T) (F_{-1} = 0); padding and
-// dead tables get q = 0.  Blocks cover 1024 slots; when bs is given (tables
-// of >= 1024 slots) each block also writes its alias statistics.
-__global__ __launch_bounds__(256) void k_q_from_prefix(
-    const uint64_t* Lbuf, const double* E, const double* tot, int64_t S,
-    int64_t N, int L, uint64_t* q, Quad* bs) {
-  const int64_t total = S << L;
-  const int64_t base = (int64_t)blockIdx.x * kAliasBlk + threadIdx.x * 4;
-  const int64_t Np = int64_t(1) << L;
-  const int K = L + kCapBits;
-  Quad a{0, 0, 0, 0};
-  uint64_t Fp = 0;  // F of the previous item of the same table
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int64_t slot = base + s;
-    if (slot >= total) break;
-    const int64_t seg = slot >> L;
-    const int64_t r = slot & (Np - 1);
-    const double T = tot[seg];
-    const bool live = T > 0.0;
-    if (s == 0 || r == 0) {
-      // the prefix of item r-1; at a run start it is exactly E_c
-      Fp = 0;
-      if (live && r > 0 && r - 1 < N) {
-        const int64_t cp = (r - 1) / kRun;
-        const uint64_t raw = Lbuf[slot - 1] & kQMask;
-        const double Pp = E[cp * S + seg] +
-                          __longlong_as_double((long long)raw);
-        Fp = (uint64_t)floor(ldexp(Pp / T, K));
-      }
-    }
-    uint64_t qq = 0;
-    if (live && r < N) {
-      const uint64_t raw = Lbuf[slot];
-      const double Pv = E[(r / kRun) * S + seg] +
-                        __longlong_as_double((long long)(raw & kQMask));
-      const uint64_t F = (uint64_t)floor(ldexp(Pv / T, K));
-      qq = (F - Fp) | (raw & ~kQMask);
-      Fp = F;
-    }
-    q[slot] = qq;
-    slot_stats(qq & kQMask, a);
-  }
-  if (bs) {
-    Quad all = block_excl_scan(a);
-    if (threadIdx.x == 0) bs[blockIdx.x] = all;
-  }
 }
 
 __global__ __launch_bounds__(256) void k_alias_blocksum(const uint64_t* q,
@@ -740,10 +602,10 @@ static size_t alias_scratch_bytes(int64_t slots, int64_t tables) {
          (size_t)(slots / kMergeBlk + tables) * 8 + 256;
 }
 
-// bsf: block statistics of the whole family (from k_q_from_prefix), or
-// null to compute them here
+// tables of 2^L >= 1024 slots from stored quanta, in batches of tables that
+// fit the scratch
 static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
-                              int L, uint64_t* ent, Quad* bsf, void* scratch,
+                              int L, uint64_t* ent, void* scratch,
                               size_t scratch_bytes, hipStream_t st) {
   const int64_t Np = int64_t(1) << L;
   int64_t per = (int64_t)(scratch_bytes / (alias_scratch_bytes(Np, 1)));
@@ -763,8 +625,7 @@ static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
     uint64_t* Dt = (uint64_t*)p; p += ns * 8;
     int64_t* edges = (int64_t*)p;
     const uint64_t* qb = q + (s0 << L);
-    if (bsf) bs = bsf + (s0 << L) / kAliasBlk;
-    else k_alias_blocksum<<<(unsigned)nblk, 256, 0, st>>>(qb, bs);
+    k_alias_blocksum<<<(unsigned)nblk, 256, 0, st>>>(qb, bs);
     k_alias_blockscan<<<(unsigned)ns, 256, 0, st>>>(bs, ns, Np / kAliasBlk,
                                                     NL, NH, Dt);
     k_alias_scatter<<<(unsigned)nblk, 256, 0, st>>>(qb, bs, L, Ld, Li, He, Hi);
@@ -780,29 +641,275 @@ static hipError_t alias_large(const uint64_t* q, const double* tot, int64_t S,
 }
 
 static hipError_t build_alias(const uint64_t* q, const double* tot, int64_t S,
-                              int L, uint64_t* ent, Quad* bsf, void* scratch,
+                              int L, uint64_t* ent, void* scratch,
                               size_t scratch_bytes, hipStream_t st) {
-  if (L <= 9) return alias_small(q, tot, S, L, ent, st);
-  return alias_large(q, tot, S, L, ent, bsf, scratch, scratch_bytes, st);
+  return alias_large(q, tot, S, L, ent, scratch, scratch_bytes, st);
 }
 
-// Column families: one serial pass of run-local prefixes, the run offsets,
-// then quanta (and, for tables of >= 1024 slots, the alias block
-// statistics) in parallel.
-static hipError_t col_quanta(const float* X, int64_t d, const double* scale,
-                             int64_t S, int64_t N, int L, double* tot,
-                             uint64_t* q, uint64_t* Lbuf, double* runbuf,
-                             Quad* bsf, hipStream_t st) {
-  const int64_t R = (N + kRun - 1) / kRun;
+// ---------------------------------------------------------------------------
+// Column families of 2^L >= 1024 slots without stored prefixes or quanta.
+// The prefixes are recomputed from X, which is cheaper than writing and
+// reading them back:
+//   run totals   per table and run of kRun items, the left-to-right sum;
+//   offsets      E_c and T per table in the two-level order;
+//   statistics   per table and run of kRun slots (slot runs = item runs,
+//                padding after the items): light / heavy counts, deficit
+//                and excess, from q_r = F_r - F_{r-1} walked in order;
+//   block scan   exclusive offsets of those statistics per table;
+//   lists        the same walk again, writing each light's exclusive
+//                deficit prefix and slot id and each heavy's inclusive
+//                excess prefix and slot id at their offsets;
+//   merge        as for any large table.
+// The prefix of the item before a run start is E_c itself (E_c = E_{c-1}
+// + l of run c-1's last item is the same operation), so each run starts
+// from F_{r-1} = floor(2^K E_c / T) (0 in the first run).
+// ---------------------------------------------------------------------------
+// loads of a column walk issued together (clamped to the run's last row,
+// so they carry no branch)
+constexpr int kColGroup = 32;
+
+__global__ __launch_bounds__(64) void k_col_runtot(const float* X, int64_t d,
+                                                   const double* scale,
+                                                   int64_t S, int64_t N,
+                                                   double* rtot) {
   const int64_t tiles = (S + 63) / 64;
-  double* E = runbuf;  // R * S
-  k_col_local<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, L,
-                                                    Lbuf);
-  k_col_offsets<<<(unsigned)S, 64, 0, st>>>(Lbuf, S, N, L, E, tot);
-  const int64_t total = S << L;
-  k_q_from_prefix<<<grid_for(total, kAliasBlk), 256, 0, st>>>(
-      Lbuf, E, tot, S, N, L, q, L >= 10 ? bsf : nullptr);
-  return hipGetLastError();
+  const int64_t c = blockIdx.x / tiles;
+  const int64_t seg = (blockIdx.x % tiles) * 64 + threadIdx.x;
+  const int64_t segc = seg < S ? seg : S - 1;
+  const int64_t r0 = c * kRun;
+  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;
+  double l = 0.0;
+  for (int64_t g0 = r0; g0 < r1; g0 += kColGroup) {
+    float xv[kColGroup];
+    double sv[kColGroup];
+#pragma unroll
+    for (int u = 0; u < kColGroup; ++u) {
+      const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
+      xv[u] = X[r * d + segc];
+      sv[u] = scale ? scale[r] : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kColGroup; ++u) {
+      const int64_t r = g0 + u;
+      if (r < r1) {
+        const double w = scale ? fabs((double)xv[u]) * sv[u]
+                               : fabs((double)xv[u]);
+        l = r == r0 ? w : l + w;
+      }
+    }
+  }
+  if (seg < S) rtot[c * S + seg] = l;
+}
+
+// E_c (c < R) and T per table: E_0 = 0, E_{c+1} = E_c + rtot_c, T = E_R.
+// One 64-thread block per table: the run totals are gathered into LDS in
+// parallel, then one lane adds them left to right.
+constexpr int kOffChunk = 2048;
+
+__global__ __launch_bounds__(64) void k_col_runoffsets(const double* rtot,
+                                                       int64_t S, int64_t R,
+                                                       double* E,
+                                                       double* tot) {
+  __shared__ double buf[kOffChunk];
+  const int64_t seg = blockIdx.x;
+  double e = 0.0;  // lane 0's running offset
+  for (int64_t c0 = 0; c0 < R; c0 += kOffChunk) {
+    const int64_t nc = R - c0 < kOffChunk ? R - c0 : kOffChunk;
+    for (int64_t u = threadIdx.x; u < nc; u += 64)
+      buf[u] = rtot[(c0 + u) * S + seg];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int64_t u = 0; u < nc; ++u) {
+        const double x = buf[u];
+        buf[u] = e;  // E_c
+        e = e + x;
+      }
+    }
+    __syncthreads();
+    for (int64_t u = threadIdx.x; u < nc; u += 64) E[(c0 + u) * S + seg] = buf[u];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[seg] = e;
+}
+
+// One wave per (slot run c, 64 consecutive tables of [s0, s0 + ns)), lane
+// = table.  LISTS = false: the run's statistics into bs[t * B + c];
+// LISTS = true: bs holds the exclusive offsets and the lists are written
+// (positions relative to table t's base t << L).  Each group of kColGroup
+// items passes through LDS as (list value with the heavy flag in bit 63,
+// slot id with the sign in bit 31) per (item, table); then, two tables at
+// a time (one per half-wave, lane = item), ballots give every entry its
+// place and each table's lights and heavies of the group are stored as
+// contiguous runs.
+template <bool LISTS>
+__global__ __launch_bounds__(64) void k_col_walk(
+    const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
+    int L, const double* E, const double* tot, int64_t s0, int64_t ns,
+    Quad* bs, uint64_t* Ld, uint32_t* Li, uint64_t* He, uint32_t* Hi) {
+  static_assert(kColGroup == 32, "two tables per wave in the write-out");
+  __shared__ uint64_t tv[LISTS ? kColGroup : 1][65];
+  __shared__ uint32_t ti[LISTS ? kColGroup : 1][65];
+  __shared__ uint64_t cnt0[LISTS ? 64 : 1][2];  // lights / heavies before
+  const int64_t B = (int64_t(1) << L) / kRun;  // slot runs per table
+  const int64_t tiles = (ns + 63) / 64;
+  const int64_t c = blockIdx.x / tiles;
+  const int64_t t0 = (blockIdx.x % tiles) * 64;
+  const int lane = threadIdx.x;
+  const int64_t t = t0 + lane;
+  const bool mine = t < ns;
+  const int64_t tc = mine ? t : ns - 1;
+  const int64_t seg = s0 + tc;
+  const double T = tot[seg];
+  const bool live = T > 0.0;
+  const int K = L + kCapBits;
+  const int64_t r0 = c * kRun;
+  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;  // items of this run
+  const int64_t R = (N + kRun - 1) / kRun;
+  const double Ec = c < R ? E[c * S + seg] : 0.0;
+  uint64_t Fp = 0;
+  if (live && c > 0 && c < R) Fp = (uint64_t)floor(ldexp(Ec / T, K));
+  uint64_t nl = 0, nh = 0, da = 0, ea = 0;
+  if (LISTS) {
+    const Quad o = bs[tc * B + c];
+    nl = o.nl;
+    nh = o.nh;
+    da = o.sd;
+    ea = o.se;
+  }
+  double l = 0.0;
+  for (int64_t g0 = r0; g0 < r0 + kRun; g0 += kColGroup) {
+    float xv[kColGroup];
+    double sv[kColGroup];
+    if (g0 < r1) {
+#pragma unroll
+      for (int u = 0; u < kColGroup; ++u) {
+        const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
+        xv[u] = X[r * d + seg];
+        sv[u] = scale ? scale[r] : 1.0;
+      }
+    }
+    if (LISTS) {
+      cnt0[lane][0] = nl;
+      cnt0[lane][1] = nh;
+    }
+#pragma unroll
+    for (int u = 0; u < kColGroup; ++u) {
+      const int64_t r = g0 + u;
+      uint64_t q = 0;
+      uint32_t sg = 0;
+      if (r < r1 && live) {
+        const double w = scale ? fabs((double)xv[u]) * sv[u]
+                               : fabs((double)xv[u]);
+        l = r == r0 ? w : l + w;
+        const uint64_t F = (uint64_t)floor(ldexp((Ec + l) / T, K));
+        q = F - Fp;
+        Fp = F;
+        sg = sign_bit(xv[u]);
+      }
+      if (q < kCap) {
+        if (LISTS) tv[u][lane] = da;
+        ++nl;
+        da += kCap - q;
+      } else {
+        ea += q - kCap;
+        if (LISTS) tv[u][lane] = ea | (1ull << 63);
+        ++nh;
+      }
+      if (LISTS) ti[u][lane] = (uint32_t)r | (sg << 31);
+    }
+    if (LISTS) {
+      __syncthreads();
+      // write-out: half-wave h takes table j = p2 + h, lane & 31 = item
+      const int h = lane >> 5, u = lane & 31;
+      const uint64_t lt = (1ull << lane) - 1;
+      const uint64_t half = h ? 0xFFFFFFFF00000000ull : 0xFFFFFFFFull;
+      for (int p2 = 0; p2 < 64; p2 += 2) {
+        const int j = p2 + h;
+        const bool ok = t0 + j < ns;
+        const uint64_t v = tv[u][j];
+        const uint32_t id = ti[u][j];
+        const bool heavy = (v >> 63) != 0;
+        const uint64_t bh = __ballot(ok && heavy) & half;
+        const uint64_t bl = __ballot(ok && !heavy) & half;
+        const int64_t tb = (t0 + j) << L;
+        if (ok) {
+          if (heavy) {
+            const int64_t pos = (int64_t)cnt0[j][1] + __popcll(bh & lt);
+            He[tb + pos] = v & ~(1ull << 63);
+            Hi[tb + pos] = id;
+          } else {
+            const int64_t pos = (int64_t)cnt0[j][0] + __popcll(bl & lt);
+            Ld[tb + pos] = v;
+            Li[tb + pos] = id;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (!LISTS && mine) bs[tc * B + c] = Quad{nl, nh, da, ea};
+}
+
+// scratch of col_tables: run totals and offsets (2 R S doubles), the run
+// statistics (S B Quads), then the alias lists of a batch of tables
+static size_t col_tables_fixed_bytes(int64_t S, int64_t N, int L) {
+  const int64_t R = (N + kRun - 1) / kRun;
+  const int64_t B = (int64_t(1) << L) / kRun;
+  return (size_t)(2 * R * S) * 8 + (size_t)(S * B) * sizeof(Quad) + 256;
+}
+
+static hipError_t col_tables(const float* X, int64_t d, const double* scale,
+                             int64_t S, int64_t N, int L, Family& f,
+                             void* scratch, size_t scratch_bytes,
+                             hipStream_t st) {
+  const int64_t R = (N + kRun - 1) / kRun;
+  const int64_t Np = int64_t(1) << L;
+  const int64_t B = Np / kRun;
+  const size_t fixed = col_tables_fixed_bytes(S, N, L);
+  if (scratch_bytes < fixed) return hipErrorInvalidValue;
+  char* p = (char*)scratch;
+  double* rtot = (double*)p; p += (size_t)(R * S) * 8;
+  double* E = (double*)p; p += (size_t)(R * S) * 8;
+  Quad* bs = (Quad*)(((uintptr_t)p + 31) & ~(uintptr_t)31);
+  p = (char*)(bs + S * B);
+  const size_t left = scratch_bytes - (size_t)(p - (char*)scratch);
+  // tables per batch of alias lists
+  const size_t per_tab = alias_scratch_bytes(Np, 1);
+  int64_t per = (int64_t)(left / per_tab);
+  if (per < 1) return hipErrorOutOfMemory;
+  const int64_t tiles = (S + 63) / 64;
+  k_col_runtot<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, rtot);
+  k_col_runoffsets<<<(unsigned)S, 64, 0, st>>>(rtot, S, R, E, f.tot);
+  k_col_walk<false><<<(unsigned)(B * tiles), 64, 0, st>>>(
+      X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
+      nullptr);
+  for (int64_t s0 = 0; s0 < S; s0 += per) {
+    const int64_t ns = S - s0 < per ? S - s0 : per;
+    const int64_t slots = ns * Np;
+    char* a = p;
+    uint64_t* Ld = (uint64_t*)a; a += slots * 8;
+    uint64_t* He = (uint64_t*)a; a += slots * 8;
+    uint32_t* Li = (uint32_t*)a; a += slots * 4;
+    uint32_t* Hi = (uint32_t*)a; a += slots * 4;
+    a += (slots / kAliasBlk) * sizeof(Quad);
+    uint64_t* NL = (uint64_t*)a; a += ns * 8;
+    uint64_t* NH = (uint64_t*)a; a += ns * 8;
+    uint64_t* Dt = (uint64_t*)a; a += ns * 8;
+    int64_t* edges = (int64_t*)a;
+    Quad* bsb = bs + s0 * B;
+    k_alias_blockscan<<<(unsigned)ns, 256, 0, st>>>(bsb, ns, B, NL, NH, Dt);
+    const int64_t btiles = (ns + 63) / 64;
+    k_col_walk<true><<<(unsigned)(B * btiles), 64, 0, st>>>(
+        X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
+    const int64_t nedge = ns * (Np / kMergeBlk + 1);
+    k_alias_edges<<<grid_for(nedge, 256), 256, 0, st>>>(Ld, He, NL, NH, ns, L,
+                                                        edges);
+    k_alias_merge<<<(unsigned)(slots / kMergeBlk), 256, 0, st>>>(
+        Ld, Li, He, Hi, NL, NH, Dt, edges, f.tot, s0, L, f.ent);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -860,7 +967,14 @@ hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,
   if ((e = hipMalloc(&t.om, sizeof(double) * (size_t)d)) != hipSuccess)
     return e;
   if ((e = hipMalloc(&t.bmax, 256)) != hipSuccess) return e;
-  return hipMalloc(&t.bad, 256);
+  if ((e = hipMalloc(&t.bad, 256)) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&t.side, hipStreamNonBlocking)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipEventCreateWithFlags(&t.fork, hipEventDisableTiming)) !=
+      hipSuccess)
+    return e;
+  return hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
 }
 
 void dense_tables_free(DenseTables& t) {
@@ -871,18 +985,15 @@ void dense_tables_free(DenseTables& t) {
   if (t.om) (void)hipFree(t.om);
   if (t.bmax) (void)hipFree(t.bmax);
   if (t.bad) (void)hipFree(t.bad);
+  if (t.fork) (void)hipEventDestroy(t.fork);
+  if (t.join) (void)hipEventDestroy(t.join);
+  if (t.side) (void)hipStreamDestroy(t.side);
   t.om = nullptr;
   t.bmax = nullptr;
   t.bad = nullptr;
+  t.fork = t.join = nullptr;
+  t.side = nullptr;
 }
-
-// scratch: quanta of the largest family, run sums, alias lists
-struct BuildBuffers {
-  uint64_t* q;
-  double* runs;
-  void* alias;
-  size_t alias_bytes;
-};
 
 static size_t run_doubles(int64_t S, int64_t N) {
   const int64_t R = (N + kRun - 1) / kRun;
@@ -893,37 +1004,50 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
                               bool check, DeviceBuffer& scratch_buf,
                               hipStream_t st) {
   const int64_t m = t.m, n = t.n, d = t.d;
-  // scratch: quanta and prefixes of the largest family, run sums, block
-  // statistics, alias lists (batched to at most 2^26 slots)
-  size_t qslots = 0, runs = 0, blks = 0, alias_slots = 0;
-  const Family* fams[4] = {&t.T0, &t.T1, &t.T2, &t.T3};
-  for (const Family* f : fams) {
-    const size_t sl = (size_t)(f->S << f->L);
-    if (sl > qslots) qslots = sl;
-    const size_t r = run_doubles(f->S, f->N);
-    if (r > runs) runs = r;
+  // scratch: for a row family (T3, T0) of 2^L > 512 slots its quanta, run
+  // sums and alias lists; for a column family (T1, T2) of 2^L > 512 slots
+  // its run data and statistics and alias lists.  Alias lists are batched
+  // to at most 2^26 slots (at least one table).
+  auto alias_for = [](const Family& f) {
+    size_t sl = (size_t)(f.S << f.L);
+    if (sl > ((size_t)1 << 26)) sl = (size_t)1 << 26;
+    if (sl < ((size_t)1 << f.L)) sl = (size_t)1 << f.L;
+    return alias_scratch_bytes((int64_t)sl, (int64_t)sl / kAliasBlk);
+  };
+  // main region: row families and T1; side region (B given): T2
+  size_t need = 1024;
+  for (const Family* f : {&t.T3, &t.T0})
     if (f->L > 9) {
-      if (sl / kAliasBlk > blks) blks = sl / kAliasBlk;
-      if (sl > alias_slots) alias_slots = sl;
+      const size_t b = (size_t)(f->S << f->L) * 8 +
+                       run_doubles(f->S, f->N) * 8 + alias_for(*f) + 1024;
+      if (b > need) need = b;
     }
+  if (t.T1.L > 9) {
+    const size_t b = col_tables_fixed_bytes(t.T1.S, t.T1.N, t.T1.L) +
+                     alias_for(t.T1) + 1024;
+    if (b > need) need = b;
   }
-  if (alias_slots > ((size_t)1 << 26)) alias_slots = (size_t)1 << 26;
-  for (const Family* f : fams)  // at least one table per batch
-    if (f->L > 9 && alias_slots < ((size_t)1 << f->L))
-      alias_slots = (size_t)1 << f->L;
-  const size_t alias_bytes =
-      alias_slots ? alias_scratch_bytes((int64_t)alias_slots,
-                                        (int64_t)alias_slots / kAliasBlk) : 0;
-  const size_t total = 2 * qslots * 8 + runs * 8 + blks * sizeof(Quad) +
-                       alias_bytes + 1024;
-  hipError_t e = dev_alloc(scratch_buf, total);
+  need = (need + 255) & ~(size_t)255;
+  size_t need_side = 0;
+  if (B && t.T2.L > 9)
+    need_side = col_tables_fixed_bytes(t.T2.S, t.T2.N, t.T2.L) +
+                alias_for(t.T2) + 1024;
+  hipError_t e = dev_alloc(scratch_buf, need + need_side);
   if (e != hipSuccess) return e;
+  // row-family layout of the main region
   char* p = (char*)scratch_buf.p;
+  const size_t qslots = (size_t)(t.T3.S << t.T3.L) > (size_t)(t.T0.S << t.T0.L)
+                            ? (size_t)(t.T3.S << t.T3.L)
+                            : (size_t)(t.T0.S << t.T0.L);
+  const size_t runs = run_doubles(t.T3.S, t.T3.N) > run_doubles(1, t.T0.N)
+                          ? run_doubles(t.T3.S, t.T3.N)
+                          : run_doubles(1, t.T0.N);
   uint64_t* q = (uint64_t*)p; p += qslots * 8;
-  uint64_t* Pbuf = (uint64_t*)p; p += qslots * 8;
   double* runbuf = (double*)p; p += runs * 8;
-  Quad* bsf = (Quad*)p; p += blks * sizeof(Quad);
   void* abuf = p;
+  const size_t used = (size_t)(p - (char*)scratch_buf.p);
+  const size_t alias_bytes = need > used ? need - used : 0;
+  void* side_scratch = (char*)scratch_buf.p + need;
 
   if ((e = launch_fill_u64((uint64_t*)t.bmax, 1, 0ull, st)) != hipSuccess ||
       (e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess)
@@ -932,48 +1056,58 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
     k_scan_inputs<<<grid_for(m * d, 256 * 16) > 1024 ? 1024
                         : grid_for(m * d, 256 * 16), 256, 0, st>>>(
         A, m * d, nullptr, t.bad);
-  if (B)
+
+  // B side on the side stream: max |b| (and the finiteness check), then
+  // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
+  if (B) {
+    if ((e = hipEventRecord(t.fork, st)) != hipSuccess ||
+        (e = hipStreamWaitEvent(t.side, t.fork, 0)) != hipSuccess)
+      return e;
     k_scan_inputs<<<grid_for(n * d, 256 * 16) > 1024 ? 1024
-                        : grid_for(n * d, 256 * 16), 256, 0, st>>>(
+                        : grid_for(n * d, 256 * 16), 256, 0, t.side>>>(
         B, n * d, t.bmax, t.bad);
+    e = t.T2.L <= 9
+            ? small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,
+                           t.T2.ent, t.side)
+            : col_tables(B, d, nullptr, d, n, t.T2.L, t.T2, side_scratch,
+                         need_side, t.side);
+    const hipError_t ej = hipEventRecord(t.join, t.side);
+    if (e == hipSuccess) e = ej;
+    if (e != hipSuccess) return e;
+  }
 
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
   if (t.T3.L <= 9) {
-    e = small_tables_q(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, t.T3.ent,
-                       st);
+    e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
   } else {
     e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
     if (e == hipSuccess)
-      e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, nullptr, abuf,
+      e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, abuf,
                       alias_bytes, st);
   }
   // T1[k]: i given k, weight |a_ki| na_i; totals v_k
   if (e == hipSuccess)
-    e = col_quanta(A, d, t.na, d, m, t.T1.L, t.T1.tot, q, Pbuf, runbuf, bsf,
-                   st);
-  if (e == hipSuccess)
-    e = build_alias(q, t.T1.tot, d, t.T1.L, t.T1.ent, bsf, abuf, alias_bytes,
-                    st);
-  // without B (MIPS) only the A side is built
+    e = t.T1.L <= 9
+            ? small_tables(WColAbs{A, d, t.na}, d, m, t.T1.L, t.T1.tot,
+                           t.T1.ent, st)
+            : col_tables(A, d, t.na, d, m, t.T1.L, t.T1, scratch_buf.p,
+                         need, st);
+  // the B side joins here; without B (MIPS) only the A side is built
+  if (B) {
+    const hipError_t ew = hipStreamWaitEvent(st, t.join, 0);
+    if (e == hipSuccess) e = ew;
+  }
   if (e != hipSuccess || !B) return e;
-  // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
-  if (e == hipSuccess)
-    e = col_quanta(B, d, nullptr, d, n, t.T2.L, t.T2.tot, q, Pbuf, runbuf,
-                   bsf, st);
-  if (e == hipSuccess)
-    e = build_alias(q, t.T2.tot, d, t.T2.L, t.T2.ent, bsf, abuf, alias_bytes,
-                    st);
   // T0: k with weight nb_k v_k; total ||W||_1 (Alg. 2 lines "dw", "ds1")
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
     if (t.T0.L <= 9) {
-      e = small_tables_q(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, t.T0.ent,
-                         st);
+      e = small_tables(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, t.T0.ent, st);
     } else {
       e = uniform_quanta(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, q, runbuf,
                          st);
       if (e == hipSuccess)
-        e = build_alias(q, t.T0.tot, 1, t.T0.L, t.T0.ent, nullptr, abuf,
+        e = build_alias(q, t.T0.tot, 1, t.T0.L, t.T0.ent, abuf,
                         alias_bytes, st);
     }
   }
@@ -987,7 +1121,7 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
 // ---------------------------------------------------------------------------
 size_t query_tables_scratch_bytes(int64_t nq, int64_t d) {
   const int L = ceil_log2_host(d);
-  if (L <= 9) return (size_t)(nq << L) * 8 + 256;
+  if (L <= 9) return 256;  // small tables need no scratch
   const int64_t slots = nq << L;
   int64_t batch = slots < ((int64_t)1 << 26) ? slots : ((int64_t)1 << 26);
   if (batch < ((int64_t)1 << L)) batch = (int64_t)1 << L;
@@ -999,12 +1133,7 @@ hipError_t query_tables_build(const float* Q, int64_t nq, int64_t d,
                               const double* v, Family& T0q, void* scratch,
                               size_t scratch_bytes, hipStream_t st) {
   const WQuery w{Q, d, v};
-  if (T0q.L <= 9) {
-    if (!scratch || scratch_bytes < (size_t)(nq << T0q.L) * 8)
-      return hipErrorInvalidValue;
-    return small_tables_q(w, nq, d, T0q.L, T0q.tot, (uint64_t*)scratch,
-                          T0q.ent, st);
-  }
+  if (T0q.L <= 9) return small_tables(w, nq, d, T0q.L, T0q.tot, T0q.ent, st);
   char* p = (char*)scratch;
   uint64_t* q = (uint64_t*)p; p += (size_t)(nq << T0q.L) * 8;
   double* runbuf = (double*)p; p += run_doubles(nq, d) * 8;
@@ -1012,7 +1141,7 @@ hipError_t query_tables_build(const float* Q, int64_t nq, int64_t d,
   if (!scratch || scratch_bytes < used) return hipErrorInvalidValue;
   hipError_t e = uniform_quanta(w, nq, d, T0q.L, T0q.tot, q, runbuf, st);
   if (e != hipSuccess) return e;
-  return build_alias(q, T0q.tot, nq, T0q.L, T0q.ent, nullptr, p,
+  return build_alias(q, T0q.tot, nq, T0q.L, T0q.ent, p,
                      scratch_bytes - used, st);
 }
 
@@ -1024,11 +1153,7 @@ hipError_t stage0_table_build(const double* w, int64_t N, Family& T,
                               void* scratch, size_t scratch_bytes,
                               hipStream_t st) {
   const WExplicit wf{w};
-  if (T.L <= 9) {
-    if (!scratch || scratch_bytes < ((size_t)8 << T.L)) return hipErrorInvalidValue;
-    return small_tables_q(wf, 1, N, T.L, T.tot, (uint64_t*)scratch, T.ent,
-                          st);
-  }
+  if (T.L <= 9) return small_tables(wf, 1, N, T.L, T.tot, T.ent, st);
   char* p = (char*)scratch;
   uint64_t* q = (uint64_t*)p; p += (size_t)8 << T.L;
   double* runbuf = (double*)p; p += run_doubles(1, N) * 8;
@@ -1036,7 +1161,7 @@ hipError_t stage0_table_build(const double* w, int64_t N, Family& T,
   if (!scratch || scratch_bytes < used) return hipErrorInvalidValue;
   hipError_t e = uniform_quanta(wf, 1, N, T.L, T.tot, q, runbuf, st);
   if (e != hipSuccess) return e;
-  return build_alias(q, T.tot, 1, T.L, T.ent, nullptr, p, scratch_bytes - used,
+  return build_alias(q, T.tot, 1, T.L, T.ent, p, scratch_bytes - used,
                      st);
 }
 
