@@ -57,7 +57,11 @@ enum { MAD_FP32 = 0, MAD_BF16 = 1, MAD_FP8_E4M3 = 2 };
 /* Plan flags. */
 enum {
   MAD_FLAG_NONE = 0,
-  MAD_FLAG_NO_CHECK = 1u << 0, /* skip the NaN/Inf scan of the inputs      */
+  /* skip the NaN/Inf check of the inputs; for sparse plans also the
+   * structure check after the plan's first build (the caller vouches that
+   * the arrays keep a structure that passed it).  Builds then never
+   * synchronise with the host. */
+  MAD_FLAG_NO_CHECK = 1u << 0,
   MAD_FLAG_TIMING = 1u << 1,   /* record HIP events around each phase      */
   /* Gram matrix (Sec. 3.3, equal inputs): B must be A (same arrays, n = m).
    * The scores are symmetrised before Alg. 3, X <- (X + X^T) / 2, kept as
@@ -179,9 +183,11 @@ int mad_plan_stats(mad_plan* plan, double* wnorm, int64_t* closed,
  * mad_plan_refresh / mad_plan_topk of a plan made with MAD_FLAG_TIMING,
  * measured with HIP events recorded on the launch stream:
  *   ms[0] table construction (mad_plan_refresh or creation)
- *   ms[1] sampling kernel (Alg. 2 loop, including the score table updates)
+ *   ms[1] sampling kernel (Alg. 2 loop; with the hash form of X it
+ *         includes the score table updates)
  *   ms[2] postprocessing (Alg. 3: selections, verification, output)
- *   ms[3] clearing the score table before sampling
+ *   ms[3] clearing the score table before sampling (hash form)
+ *   ms[4] score accumulation from the per-sample pairs (pair form)
  * Synchronises on the last event.  MAD_EINVAL without MAD_FLAG_TIMING.
  * ------------------------------------------------------------------------- */
 int mad_plan_phase_ms(mad_plan* plan, double* ms, int n);

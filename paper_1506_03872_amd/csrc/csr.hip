@@ -1088,7 +1088,10 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
       return e;
   }
-  // validation (structure always: every later index relies on it)
+  // validation: the structure on the first build of a plan and on every
+  // checked build (every later index relies on it; without the check the
+  // caller vouches that the arrays keep the structure they were validated
+  // with), values when checked.  The scan also gives max |b|.
   if ((e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess ||
       (e = launch_fill_u64((uint64_t*)t.bmax, 1, 0ull, st)) != hipSuccess)
     return e;
@@ -1096,12 +1099,15 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
       t.in.a_ptr, t.in.a_idx, t.in.a_val, m, d, t.nnzA, nullptr, t.bad);
   k_csr_check<<<blocks_of(n, 256), 256, 0, st>>>(
       t.in.b_ptr, t.in.b_idx, t.in.b_val, n, d, t.nnzB, t.bmax, t.bad);
-  int bad = 0;
-  if ((e = hipMemcpyAsync(&bad, t.bad, 4, hipMemcpyDeviceToHost, st)) !=
-          hipSuccess ||
-      (e = hipStreamSynchronize(st)) != hipSuccess)
-    return e;
-  if ((bad & 2) || (check && (bad & 1))) return hipErrorInvalidValue;
+  if (check || !t.validated) {
+    int bad = 0;
+    if ((e = hipMemcpyAsync(&bad, t.bad, 4, hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return e;
+    if ((bad & 2) || (check && (bad & 1))) return hipErrorInvalidValue;
+    t.validated = true;
+  }
   // transposes
   const int64_t nz = t.nnzA > t.nnzB ? t.nnzA : t.nnzB;
   if ((e = dev_alloc(t.work, sort_bytes(nz))) != hipSuccess) return e;

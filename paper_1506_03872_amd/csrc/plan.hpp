@@ -173,6 +173,7 @@ struct CsrTables {
   int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.3)
+  bool validated = false; // the structure passed a check on this plan
 };
 
 // Allocates and builds every table (synchronises: the layout of the

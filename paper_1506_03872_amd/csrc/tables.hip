@@ -1057,12 +1057,23 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
                         : grid_for(m * d, 256 * 16), 256, 0, st>>>(
         A, m * d, nullptr, t.bad);
 
+  // the B side forks from here (after the clears above)
+  if (B && (e = hipEventRecord(t.fork, st)) != hipSuccess) return e;
+  // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
+  // (enqueued before the B side so that this stream has work at once)
+  if (t.T3.L <= 9) {
+    e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
+  } else {
+    e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
+    if (e == hipSuccess)
+      e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, abuf,
+                      alias_bytes, st);
+  }
+  if (e != hipSuccess) return e;
   // B side on the side stream: max |b| (and the finiteness check), then
   // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
   if (B) {
-    if ((e = hipEventRecord(t.fork, st)) != hipSuccess ||
-        (e = hipStreamWaitEvent(t.side, t.fork, 0)) != hipSuccess)
-      return e;
+    if ((e = hipStreamWaitEvent(t.side, t.fork, 0)) != hipSuccess) return e;
     k_scan_inputs<<<grid_for(n * d, 256 * 16) > 1024 ? 1024
                         : grid_for(n * d, 256 * 16), 256, 0, t.side>>>(
         B, n * d, t.bmax, t.bad);
@@ -1076,15 +1087,6 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
     if (e != hipSuccess) return e;
   }
 
-  // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
-  if (t.T3.L <= 9) {
-    e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
-  } else {
-    e = uniform_quanta(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, q, runbuf, st);
-    if (e == hipSuccess)
-      e = build_alias(q, t.T3.tot, m, t.T3.L, t.T3.ent, abuf,
-                      alias_bytes, st);
-  }
   // T1[k]: i given k, weight |a_ki| na_i; totals v_k
   if (e == hipSuccess)
     e = t.T1.L <= 9
