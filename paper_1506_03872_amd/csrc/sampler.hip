@@ -303,21 +303,20 @@ static size_t t0_lds_bytes(const DenseTables& t) {
 }
 
 // ---------------------------------------------------------------------------
-// the k order: per block of kOrdPer consecutive samples, counts of each k
-// (pass 1); per k, exclusive prefix of those counts over the blocks and the
-// k's total (pass 2); the start of each k's range (pass 3); every sample's
-// offset written into its k's range (pass 4).  The order inside one
-// block's share of a k is whatever the LDS counter gives; it does not
-// matter.
+// the k order: per block of kOrdPer consecutive samples, each sample's k
+// and the counts of each k (pass 1); per k, exclusive prefix of those
+// counts over the blocks and the k's total (pass 2); the start of each k's
+// range (pass 3); every sample's offset written into its k's range (pass
+// 4).  The order inside one block's share of a k does not matter.
 // ---------------------------------------------------------------------------
-constexpr int kOrdU = 8;
+constexpr int kOrdU = 16;
 constexpr int kOrdPer = 256 * kOrdU;
 
-template <bool PLACE>
-__global__ __launch_bounds__(256) void k_order_pass(DenseSampleArgs a,
-                                                   uint32_t* cnt,
-                                                   const uint32_t* start,
-                                                   uint32_t* ell) {
+// pass 1: each sample's k (Philox word 0 on T0) stored as 16 bits, and the
+// counts of each k per block of kOrdPer samples
+__global__ __launch_bounds__(256) void k_order_count(DenseSampleArgs a,
+                                                    uint32_t* cnt,
+                                                    uint16_t* kbuf) {
   extern __shared__ uint64_t sm[];
   const int N0 = 1 << a.L0;
   uint64_t* t0s = sm;
@@ -327,31 +326,91 @@ __global__ __launch_bounds__(256) void k_order_pass(DenseSampleArgs a,
   for (int64_t k = threadIdx.x; k < d; k += 256) lc[k] = 0;
   __syncthreads();
   const int64_t b0 = (int64_t)blockIdx.x * kOrdPer;
-  uint32_t kk[kOrdU], rank[kOrdU];
-#pragma unroll
+#pragma unroll 4
   for (int u = 0; u < kOrdU; ++u) {
     const int64_t e = b0 + u * 256 + threadIdx.x;
-    kk[u] = 0;
-    rank[u] = 0;
     if (e < a.count) {
       const Philox4 r = philox4x64_10((uint64_t)(a.l0 + e), a.qid, 0ull, 0ull,
                                       a.seed, 0ull);
       const uint32_t s0 = slot_of(r.w0, a.L0);
-      kk[u] = draw_entry(t0s[s0], s0, r.w0).pos;
-      rank[u] = atomicAdd(&lc[kk[u]], 1u);
+      const uint32_t k = draw_entry(t0s[s0], s0, r.w0).pos;
+      kbuf[e] = (uint16_t)k;
+      atomicAdd(&lc[k], 1u);
     }
   }
   __syncthreads();
-  if (!PLACE) {
-    for (int64_t k = threadIdx.x; k < d; k += 256)
-      cnt[(int64_t)blockIdx.x * d + k] = lc[k];
-  } else {
+  for (int64_t k = threadIdx.x; k < d; k += 256)
+    cnt[(int64_t)blockIdx.x * d + k] = lc[k];
+}
+
+// pass 4: every sample's offset into its k's range.  The block's samples
+// are first sorted by k in LDS (the order inside one block's share of a k
+// does not matter), so that each k's share is stored as one contiguous run.
+__global__ __launch_bounds__(256) void k_order_place(DenseSampleArgs a,
+                                                    const uint32_t* cnt,
+                                                    const uint32_t* start,
+                                                    const uint16_t* kbuf,
+                                                    uint32_t* ell) {
+  extern __shared__ uint64_t sm[];
+  const int64_t d = a.d;
+  uint32_t* lc = (uint32_t*)sm;        // d: counts, then local starts
+  uint32_t* gs = lc + d;               // d: global start of the share
+  uint32_t* se = gs + d;               // kOrdPer: sorted sample offsets
+  uint16_t* sk = (uint16_t*)(se + kOrdPer);  // kOrdPer: their k
+  __shared__ uint32_t wt[4];
+  for (int64_t k = threadIdx.x; k < d; k += 256) {
+    lc[k] = 0;
+    gs[k] = start[k] + cnt[(int64_t)blockIdx.x * d + k];
+  }
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * kOrdPer;
+  const int n = a.count - b0 < kOrdPer ? (int)(a.count - b0) : kOrdPer;
+  uint32_t kk[kOrdU], rank[kOrdU];
 #pragma unroll
-    for (int u = 0; u < kOrdU; ++u) {
-      const int64_t e = b0 + u * 256 + threadIdx.x;
-      if (e < a.count)
-        ell[(int64_t)start[kk[u]] + cnt[(int64_t)blockIdx.x * d + kk[u]] +
-            rank[u]] = (uint32_t)e;
+  for (int u = 0; u < kOrdU; ++u) {
+    const int i = u * 256 + threadIdx.x;
+    kk[u] = i < n ? kbuf[b0 + i] : 0u;
+  }
+#pragma unroll
+  for (int u = 0; u < kOrdU; ++u) {
+    const int i = u * 256 + threadIdx.x;
+    rank[u] = i < n ? atomicAdd(&lc[kk[u]], 1u) : 0u;
+  }
+  __syncthreads();
+  // local starts: exclusive prefix of lc, 256 ks at a time
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int64_t k0 = 0; k0 < d; k0 += 256) {
+    const int64_t k = k0 + threadIdx.x;
+    const uint32_t v = k < d ? lc[k] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wt[wv] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wv ? wt[w] : 0u;
+      all += wt[w];
+    }
+    if (k < d) lc[k] = carry + off + inc - v;
+    carry += all;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < kOrdU; ++u) {
+    const int i = u * 256 + threadIdx.x;
+    if (i < n) {
+      const uint32_t p = lc[kk[u]] + rank[u];
+      se[p] = (uint32_t)(b0 + i);
+      sk[p] = (uint16_t)kk[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kOrdU; ++u) {
+    const int i = u * 256 + threadIdx.x;
+    if (i < n) {
+      const uint32_t k = sk[i];
+      ell[gs[k] + (uint32_t)i - lc[k]] = se[i];
     }
   }
 }
@@ -411,18 +470,18 @@ size_t sample_order_bytes(int64_t count, int64_t d) {
   if (d > kOrderMaxD) return 0;
   const int64_t c = count < kOrderChunk ? count : kOrderChunk;
   const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
-  return (size_t)c * 4 + (size_t)nblk * d * 4 + (size_t)d * 8 + 1024;
+  return (size_t)c * 6 + (size_t)nblk * d * 4 + (size_t)d * 8 + 2048;
 }
 
-// The k order is off by default: on dense 1e5 x 1e5 x 100 with s = 1e7 it
-// takes the sampling kernel from 1.41 to 1.30 ms but the four ordering
-// passes cost 0.16 ms, because the score-table atomics, not the T1 / T2
-// loads, bound the sampler.  MAD_SAMPLER_ORDER=1 turns it on and
+// The k order is on by default for d <= kOrderMaxD: on dense 1e5 x 1e5 x
+// 100 with s = 1e7 it takes the sampling kernel from 0.75 to 0.52 ms (the
+// rows T1[k], T2[k] being drawn from stay in the XCD's L2) for about 0.1
+// ms of ordering passes.  MAD_SAMPLER_ORDER=0 turns it off and
 // MAD_SAMPLER_G8 sets the workgroups per XCD (both result-invariant).
 static int order_enabled() {
   static int v = [] {
     const char* e = getenv("MAD_SAMPLER_ORDER");
-    return e ? atoi(e) : 0;
+    return e ? atoi(e) : 1;
   }();
   return v;
 }
@@ -430,8 +489,8 @@ static int order_enabled() {
 static int order_g8() {
   static int v = [] {
     const char* e = getenv("MAD_SAMPLER_G8");
-    const int x = e ? atoi(e) : 128;
-    return x >= 1 && x <= 4096 ? x : 128;
+    const int x = e ? atoi(e) : 32;
+    return x >= 1 && x <= 4096 ? x : 32;
   }();
   return v;
 }
@@ -475,15 +534,17 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
     char* p = (char*)order_ws;
     uint32_t* ell = (uint32_t*)p;
-    uint32_t* cnt = (uint32_t*)(p + ((size_t)c * 4 + 255) / 256 * 256);
+    uint16_t* kbuf = (uint16_t*)(p + ((size_t)c * 4 + 255) / 256 * 256);
+    uint32_t* cnt =
+        (uint32_t*)((char*)kbuf + ((size_t)c * 2 + 255) / 256 * 256);
     uint32_t* tot = cnt + nblk * d;
     uint32_t* start = tot + d;
-    k_order_pass<false><<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, nullptr,
-                                                              nullptr);
+    k_order_count<<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, kbuf);
     k_order_colscan<<<(unsigned)d, 256, 0, st>>>(cnt, nblk, d, tot);
     k_order_starts<<<1, 256, 0, st>>>(tot, d, start);
-    k_order_pass<true><<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, start,
-                                                             ell);
+    const size_t lds_place = 8 * (size_t)d + 6 * (size_t)kOrdPer;
+    k_order_place<<<(unsigned)nblk, 256, lds_place, st>>>(a, cnt, start, kbuf,
+                                                         ell);
     GroupOrder go{ell, 256 * 4};
     int64_t g8 = order_g8();
     const int64_t nch = (c + go.chunk - 1) / go.chunk;
