@@ -188,6 +188,8 @@ int mad_plan_stats(mad_plan* plan, double* wnorm, int64_t* closed,
  *   ms[2] postprocessing (Alg. 3: selections, verification, output)
  *   ms[3] clearing the score table before sampling (hash form)
  *   ms[4] score accumulation from the per-sample pairs (pair form)
+ *   ms[5] the sampling kernel alone (ms[1] less the k-order passes; dense
+ *         plans)
  * Synchronises on the last event.  MAD_EINVAL without MAD_FLAG_TIMING.
  * ------------------------------------------------------------------------- */
 int mad_plan_phase_ms(mad_plan* plan, double* ms, int n);

@@ -219,10 +219,10 @@ class Plan:
         return dict(n_cand=nc.value, n_reranked=nr.value)
 
     def phase_ms(self):
-        """[tables, sampler, postprocess, clear, accumulate] ms of the last
-        calls (needs MAD_FLAG_TIMING)."""
-        arr = (C.c_double * 5)()
-        _check(lib().mad_plan_phase_ms(self._h, arr, 5))
+        """[tables, sampling, postprocess, clear, accumulate, sampling
+        kernel] ms of the last calls (needs MAD_FLAG_TIMING)."""
+        arr = (C.c_double * 6)()
+        _check(lib().mad_plan_phase_ms(self._h, arr, 6))
         return list(arr)
 
     def fix_exponent(self, s):

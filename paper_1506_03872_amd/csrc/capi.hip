@@ -111,10 +111,10 @@ struct mad_plan {
   int64_t last_s = -1;
   bool ran = false;
   // phase events (MAD_FLAG_TIMING): 0 tables start, 1 tables end, 2 clear
-  // start, 3 sampler start, 4 sampler end, 6 score accumulation end,
-  // 5 postprocessing end
-  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr,
-                      nullptr, nullptr, nullptr};
+  // start, 3 sampling start, 7 sampling kernel start (after the k-order
+  // passes), 4 sampling end, 6 score accumulation end, 5 postprocessing end
+  hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, nullptr, nullptr};
   bool timed_tables = false, timed_topk = false;
   MipsState* mips = nullptr;
 };
@@ -393,7 +393,8 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
             "sampling");
   else
     HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, h,
-                                     p->ctr, p->ord.p, p->ord.bytes, st),
+                                     p->ctr, p->ord.p, p->ord.bytes, p->ev[7],
+                                     st),
             "sampling");
   record(p, 4, st);
   if (p->pairs) {
@@ -465,14 +466,17 @@ int mad_plan_stats(mad_plan* p, double* wnorm, int64_t* closed,
 int mad_plan_phase_ms(mad_plan* p, double* ms, int n) {
   if (!p || !ms) return fail(MAD_EINVAL, "plan and ms are required");
   if (!p->ev[0]) return fail(MAD_EINVAL, "plan was made without MAD_FLAG_TIMING");
-  // MIPS plans record no accumulation event: their postprocessing is 4..5
+  // MIPS plans record no accumulation event (their postprocessing is
+  // 4..5); only dense plans record the sampling kernel's start
   const int post0 = p->kind == 1 ? 4 : 6;
-  const int pairs[5][2] = {{0, 1}, {3, 4}, {post0, 5}, {2, 3}, {4, 6}};
-  const bool have[5] = {p->timed_tables, p->timed_topk, p->timed_topk,
-                        p->timed_topk, p->timed_topk && p->kind != 1};
+  const int pairs[6][2] = {{0, 1}, {3, 4}, {post0, 5}, {2, 3}, {4, 6},
+                           {7, 4}};
+  const bool have[6] = {p->timed_tables, p->timed_topk, p->timed_topk,
+                        p->timed_topk, p->timed_topk && p->kind != 1,
+                        p->timed_topk && p->kind == 0};
   const hipEvent_t last = p->timed_topk ? p->ev[5] : p->ev[1];
   HIP_TRY(hipEventSynchronize(last), "phase timing");
-  for (int q = 0; q < n && q < 5; ++q) {
+  for (int q = 0; q < n && q < 6; ++q) {
     ms[q] = -1.0;
     if (!have[q]) continue;
     float f = 0.0f;

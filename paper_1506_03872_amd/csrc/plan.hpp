@@ -98,12 +98,14 @@ struct SampleCounters {
 // order_ws (order_bytes >= sample_order_bytes(count, d)) enables the
 // k-ordered sampling launch; null samples in index order
 size_t sample_order_bytes(int64_t count, int64_t d);
+// main_start (optional) is recorded between the k-ordering passes and the
+// sampling kernel
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F,
                                HashTable h, SampleCounters* ctr,
                                void* order_ws, size_t order_bytes,
-                               hipStream_t st);
+                               hipEvent_t main_start, hipStream_t st);
 hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      uint64_t seed, uint64_t qid, int64_t l0,
                                      int64_t count, int F, int32_t* k,

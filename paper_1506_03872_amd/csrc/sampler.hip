@@ -499,7 +499,8 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F, HashTable h,
                                SampleCounters* ctr, void* order_ws,
-                               size_t order_bytes, hipStream_t st) {
+                               size_t order_bytes, hipEvent_t main_start,
+                               hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const size_t lds = t0_lds_bytes(t);
   const uint64_t hm = (uint64_t)h.cap - 1;
@@ -507,6 +508,7 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                        order_bytes >= sample_order_bytes(count, t.d) &&
                        (int64_t(1) << t.T0.L) <= kT0Lds;
   if (!ordered) {
+    if (main_start) (void)hipEventRecord(main_start, st);
     const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
     switch (sampler_unroll()) {
 #define MAD_SAMPLE_CASE(UU)                                                \
@@ -545,6 +547,7 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     const size_t lds_place = 8 * (size_t)d + 6 * (size_t)kOrdPer;
     k_order_place<<<(unsigned)nblk, 256, lds_place, st>>>(a, cnt, start, kbuf,
                                                          ell);
+    if (main_start && c0 == 0) (void)hipEventRecord(main_start, st);
     GroupOrder go{ell, 256 * 4};
     int64_t g8 = order_g8();
     const int64_t nch = (c + go.chunk - 1) / go.chunk;
