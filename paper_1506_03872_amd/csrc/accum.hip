@@ -130,8 +130,8 @@ __global__ __launch_bounds__(kAccThreads) void k_acc_place(
 // a new key stores its increment; increments of keys already present are
 // added after a barrier, so most pairs cost one LDS atomic.
 __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
-    const uint64_t* pairs, const uint64_t* starts, int B, int64_t n,
-    uint64_t* okey, int64_t* oval, uint64_t* bin_distinct) {
+    const uint64_t* pairs, const uint64_t* starts, int B, uint64_t* okey,
+    int64_t* oval, uint64_t* bin_distinct) {
   constexpr int kPer = kRedSlots / kRedThreads;  // slots owned per thread
   constexpr int kW = kRedThreads / 64;
   __shared__ unsigned long long sk[kRedSlots];
@@ -238,9 +238,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
     __syncthreads();
     ++sub;
   }
-  // the last bin also clears the open samples' share [closed, n)
-  const int64_t end = bin == (int64_t)gridDim.x - 1 ? n : hi;
-  for (int64_t e = wpos + threadIdx.x; e < end; e += kRedThreads) {
+  for (int64_t e = wpos + threadIdx.x; e < hi; e += kRedThreads) {
     okey[e] = kEmptyKey;
     oval[e] = 0;
   }
@@ -249,9 +247,11 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
   if (threadIdx.x == 0) bin_distinct[bin] = (uint64_t)(wpos - lo);
 }
 
-// *out = sum of v[0 .. n) (one workgroup)
+// *out = sum of v[0 .. n), *len = *last (one workgroup)
 __global__ __launch_bounds__(1024) void k_acc_sum(const uint64_t* v, int64_t n,
-                                                  int64_t* out) {
+                                                  int64_t* out,
+                                                  const uint64_t* last,
+                                                  int64_t* len) {
   __shared__ unsigned long long ws[16];
   unsigned long long x = 0;
   for (int64_t e = threadIdx.x; e < n; e += 1024) x += v[e];
@@ -262,6 +262,7 @@ __global__ __launch_bounds__(1024) void k_acc_sum(const uint64_t* v, int64_t n,
     unsigned long long t = 0;
     for (int w = 0; w < 16; ++w) t += ws[w];
     *out = (int64_t)t;
+    *len = (int64_t)*last;
   }
 }
 
@@ -398,12 +399,14 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
 }
 
 // pairs: n (key, inc) pairs, key EMPTY for none; work: accum_bytes(n);
-// output: okey / oval (n entries: the distinct keys, EMPTY elsewhere) and
-// *o_count (device) distinct keys.  The pair array is overwritten.
+// output: okey / oval, *o_len (device) entries = closed pairs holding the
+// *o_count (device) distinct keys, EMPTY elsewhere.  The pair array is
+// overwritten.
 hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
                              size_t work_bytes, uint64_t* okey, int64_t* oval,
-                             int64_t* o_count, hipStream_t st) {
+                             int64_t* o_count, int64_t* o_len, hipStream_t st) {
   hipError_t e = launch_fill_u64((uint64_t*)o_count, 1, 0ull, st);
+  if (e == hipSuccess) e = launch_fill_u64((uint64_t*)o_len, 1, 0ull, st);
   if (e != hipSuccess || n <= 0) return e;
   if (work_bytes < accum_bytes(n)) return hipErrorInvalidValue;
   const int B1 = acc_b1(n), B2 = acc_b2(n);
@@ -431,16 +434,18 @@ hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts);
     k_acc_reduce<<<(unsigned)nb1, kRedThreads, 0, st>>>(
-        placed, starts, B1, n, okey, oval, bin_distinct);
+        placed, starts, B1, okey, oval, bin_distinct);
   } else {
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts1);
     k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
         placed, starts1, B1, B2, pairs, starts);
     k_acc_reduce<<<(unsigned)(nb1 << B2), kRedThreads, 0, st>>>(
-        pairs, starts, B1 + B2, n, okey, oval, bin_distinct);
+        pairs, starts, B1 + B2, okey, oval, bin_distinct);
   }
-  k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count);
+  // entries written = closed pairs = the end of the last bin
+  k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count,
+                                starts + (nb1 << B2), o_len);
   return hipGetLastError();
 }
 

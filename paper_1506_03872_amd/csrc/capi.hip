@@ -401,8 +401,10 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
     const size_t pb = 16 * (size_t)(s > 1 ? s : 1);
     HIP_TRY(mad::launch_accumulate(h.pairs, s, (char*)p->acc.p + pb,
                                    p->acc.bytes - pb, h.keys, h.vals,
-                                   (int64_t*)&p->ctr->distinct, st),
+                                   (int64_t*)&p->ctr->distinct,
+                                   (int64_t*)&p->ctr->entries, st),
             "accumulating X");
+    h.live = (const int64_t*)&p->ctr->entries;
   }
   h.pairs = nullptr;
   p->h_run = h;

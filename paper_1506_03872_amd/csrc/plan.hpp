@@ -68,11 +68,11 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 
 // ---- sampler.hip ---------------------------------------------------------
 // The score table X.  Hash form: open addressing over `cap` slots (a power
-// of two), EMPTY keys unused.  List form (`live` set): entries
-// [0, *live) hold distinct keys, the rest is unused.  With `pairs` set the
-// samplers write sample e's (key, inc) at pairs[2e], pairs[2e + 1] (key
-// EMPTY for an open three-path) instead of updating the table; the list is
-// then built by launch_accumulate.
+// of two), EMPTY keys unused.  With `live` set only entries [0, *live) are
+// read (EMPTY keys among them are unused).  With `pairs` set the samplers
+// write sample e's (key, inc) at pairs[2e], pairs[2e + 1] (key EMPTY for an
+// open three-path) instead of updating the table; X is then built by
+// launch_accumulate.
 struct HashTable {
   uint64_t* keys = nullptr;
   int64_t* vals = nullptr;
@@ -81,18 +81,20 @@ struct HashTable {
   uint64_t* pairs = nullptr;
 };
 
-// sum of the increments per key over n pairs (key EMPTY: skipped) into the
-// list okey / oval, *o_count distinct keys; work of accum_bytes(n) bytes;
-// the pair array is overwritten
+// sum of the increments per key over n pairs (key EMPTY: skipped) into
+// okey / oval: *o_len entries (one per non-EMPTY pair) holding the *o_count
+// distinct keys and EMPTY elsewhere; work of accum_bytes(n) bytes; the pair
+// array is overwritten
 size_t accum_bytes(int64_t n);
 hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
                              size_t work_bytes, uint64_t* okey, int64_t* oval,
-                             int64_t* o_count, hipStream_t st);
+                             int64_t* o_count, int64_t* o_len, hipStream_t st);
 
 struct SampleCounters {
   unsigned long long closed;    // closed three-paths (diamonds)
   unsigned long long distinct;  // keys inserted into X
-  unsigned long long pad[6];
+  unsigned long long entries;   // pair form: entries of X written
+  unsigned long long pad[5];
 };
 
 // order_ws (order_bytes >= sample_order_bytes(count, d)) enables the
