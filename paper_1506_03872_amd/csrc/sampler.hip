@@ -1,5 +1,8 @@
 // sampler.hip -- the sampling loop of Alg. 2 (lines "ds1".."dx") for dense
-// inputs, and score accumulation into an open-addressing hash table X.
+// inputs.  Each sample either writes its (key, increment) pair at its own
+// index (pair form; X is then summed by accum.hip) or adds its increment to
+// an open-addressing hash table X (hash form).  Samples can run in k order
+// (the grouping of Sec. 5.2, Alg. 4) so that T1[k] and T2[k] stay in L2.
 //
 // Sample l uses the Philox4x64-10 block with counter (l, qid, 0, 0) and key
 // (seed, 0): word 0 draws k from T0, word 1 draws i from T1[k], word 2 draws
@@ -9,7 +12,7 @@
 // value read from the inputs is the fourth edge b_k'j.  A closed three-path
 // (b_k'j != 0) adds sgn(a_ki b_kj a_k'i) * rne(b_k'j * 2^F) to the int64
 // score of key i*n + j; integer sums make X independent of the order in
-// which threads reach the table.
+// which the increments are added.
 #include <stdlib.h>
 
 #include "mad_common.hpp"
