@@ -188,7 +188,10 @@ __global__ __launch_bounds__(256) void k_sample_dense(
             ulonglong2 pr;
             pr.x = ins[u] ? key[u] : kEmptyKey;
             pr.y = (unsigned long long)smp[u].inc;
-            *(ulonglong2*)(pairs + 2 * e) = pr;
+            // streamed once: kept out of the caches that hold T3 and B
+            __builtin_nontemporal_store(pr.x, (unsigned long long*)(pairs + 2 * e));
+            __builtin_nontemporal_store(pr.y,
+                                        (unsigned long long*)(pairs + 2 * e + 1));
           }
           pend[u] = false;
         }

@@ -75,10 +75,14 @@ __device__ void block_hist_flush(unsigned* lds, unsigned* gh) {
 // post1 step 1: histogram of x > 0 straight from the score table (the
 // number of positive scores is the histogram's total)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_score_hist(const int64_t* hvals,
-                                                    int64_t cap,
-                                                    const int64_t* live,
-                                                    unsigned* hist) {
+// The grid is small (kHistBlocks workgroups of 1024 threads): every block
+// ends with one global atomic per non-empty bin, and the few bins that hold
+// most scores would serialise one atomic per block.
+constexpr int kHistBlocks = 256;
+constexpr int kHistThreads = 1024;
+
+__global__ __launch_bounds__(kHistThreads) void k_score_hist(
+    const int64_t* hvals, int64_t cap, const int64_t* live, unsigned* hist) {
   __shared__ unsigned h[kBins];
   for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
   __syncthreads();
@@ -820,12 +824,12 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
     e = launch_fill_u64((uint64_t*)w.hist, kBins / 2, 0ull, st);
   if (e != hipSuccess) return e;
   // ---- post1: top t' of x over x > 0 ------------------------------------
-  k_score_hist<<<blocks_for(h.cap, 256 * 16, 2048), 256, 0, st>>>(
-      h.vals, h.cap, h.live, w.hist);
+  k_score_hist<<<blocks_for(h.cap, kHistThreads * 16, kHistBlocks),
+                 kHistThreads, 0, st>>>(h.vals, h.cap, h.live, w.hist);
   k_coarse_decide<<<1, 256, 0, st>>>(w.hist, nullptr, t_prime, cz,
                                      &counts[kCntPos]);
   // winners go straight to (x2, key2); the boundary bin to (x, key)
-  k_score_split<<<blocks_for(h.cap, 256 * 16, 1024), 256, 0, st>>>(
+  k_score_split<<<blocks_for(h.cap, 256 * 16, 512), 256, 0, st>>>(
       h.keys, h.vals, h.cap, h.live, cz, w.x2, w.key2, w.cap2, w.x, w.key,
       w.cap, counts);
   k_fine_select<<<1, kFineThreads, 0, st>>>(

@@ -106,8 +106,9 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v,
 
 // max |x| (as float bits, atomically) and a flag for non-finite entries;
 // float4 loads when X is 16-byte aligned
-__global__ void k_scan_inputs(const float* X, int64_t n, float* amax,
-                              int* bad) {
+__global__ __launch_bounds__(1024) void k_scan_inputs(const float* X,
+                                                     int64_t n, float* amax,
+                                                     int* bad) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float mx = 0.0f;
@@ -116,12 +117,20 @@ __global__ void k_scan_inputs(const float* X, int64_t n, float* amax,
   if (((uintptr_t)X & 15) == 0) {
     const float4* X4 = (const float4*)X;
     const int64_t n4 = n / 4;
-    for (int64_t e = tid; e < n4; e += stride) {
-      const float4 v = X4[e];
-      nonfinite |= !isfinite(v.x) | !isfinite(v.y) | !isfinite(v.z) |
-                   !isfinite(v.w);
-      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)),
-                           fmaxf(fabsf(v.z), fabsf(v.w))));
+    for (int64_t e0 = tid; e0 < n4; e0 += 4 * stride) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t e = e0 + u * stride;
+        v[u] = e < n4 ? X4[e] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        nonfinite |= (int)!isfinite(v[u].x) | (int)!isfinite(v[u].y) |
+                     (int)!isfinite(v[u].z) | (int)!isfinite(v[u].w);
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)),
+                             fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+      }
     }
     done = n4 * 4;
   }
@@ -135,17 +144,22 @@ __global__ void k_scan_inputs(const float* X, int64_t n, float* amax,
     mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     nonfinite |= __shfl_xor(nonfinite, off, 64);
   }
-  // one pair of atomics per block
-  __shared__ float bmx[4];
-  __shared__ int bnf[4];
+  // one pair of atomics per block (a small grid: all blocks' atomics hit
+  // the same two words)
+  __shared__ float bmx[16];
+  __shared__ int bnf[16];
   if ((threadIdx.x & 63) == 0) {
     bmx[threadIdx.x >> 6] = mx;
     bnf[threadIdx.x >> 6] = nonfinite;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    mx = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3]));
-    nonfinite = bnf[0] | bnf[1] | bnf[2] | bnf[3];
+    mx = 0.0f;
+    nonfinite = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      mx = fmaxf(mx, bmx[w]);
+      nonfinite |= bnf[w];
+    }
     if (amax && !nonfinite) atomicMax((unsigned int*)amax, __float_as_uint(mx));
     if (nonfinite) atomicOr(bad, 1);
   }
@@ -1053,8 +1067,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
       (e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess)
     return e;
   if (check)
-    k_scan_inputs<<<grid_for(m * d, 256 * 16) > 1024 ? 1024
-                        : grid_for(m * d, 256 * 16), 256, 0, st>>>(
+    k_scan_inputs<<<grid_for(m * d, 1024 * 16) > 256 ? 256
+                        : grid_for(m * d, 1024 * 16), 1024, 0, st>>>(
         A, m * d, nullptr, t.bad);
 
   // the B side forks from here (after the clears above)
@@ -1074,8 +1088,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
   if (B) {
     if ((e = hipStreamWaitEvent(t.side, t.fork, 0)) != hipSuccess) return e;
-    k_scan_inputs<<<grid_for(n * d, 256 * 16) > 1024 ? 1024
-                        : grid_for(n * d, 256 * 16), 256, 0, t.side>>>(
+    k_scan_inputs<<<grid_for(n * d, 1024 * 16) > 256 ? 256
+                        : grid_for(n * d, 1024 * 16), 1024, 0, t.side>>>(
         B, n * d, t.bmax, t.bad);
     e = t.T2.L <= 9
             ? small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,
