@@ -1,9 +1,12 @@
 // accum.hip -- the score matrix X of Alg. 2 (line "dx") built from the
 // closed samples without per-sample global atomics.
 //
-// Sample l writes its (key = i*n + j, inc) pair at index l of a pair array
-// (key EMPTY when the three-path is open), so the sampler needs no atomics.
-// X is the sum of the increments per key, computed as:
+// Sample l writes its pair at index l of two arrays: the key i*n + j
+// (EMPTY when the three-path is open) and the fourth edge b_k'j as fp32 with
+// the sign of a_ki b_kj a_k'i applied, v; its increment is rne(v 2^F)
+// (exact in int64, rint is odd).  So the sampler needs no atomics and a
+// pair takes 12 bytes.  X is the sum of the increments per key, computed
+// as:
 //   count    per tile of pairs, a histogram of the bin = top B1 bits of
 //            mix64(key) (bins are disjoint in keys); open samples dropped;
 //   scan     exclusive prefix of the tile counts in bin-major order;
@@ -21,7 +24,7 @@
 
 namespace mad {
 
-constexpr int kAccThreads = 1024;
+constexpr int kAccThreads = 512;
 constexpr int kAccPer = 8;                // pairs per thread of a tile
 constexpr int kAccTile = kAccThreads * kAccPer;  // count / place tile
 constexpr int kAccMaxBits = 8;            // first level: up to 256 bins
@@ -55,7 +58,7 @@ size_t accum_bytes(int64_t s) {
   const int64_t tiles = (s + kAccTile - 1) / kAccTile;
   const size_t cnt = (size_t)(tiles << B1) + 1;
   const size_t starts = ((size_t)1 << (B1 + B2)) + 1;
-  return (size_t)s * 16 + cnt * 8 * 2 + starts * 8 * 3 + 8192;
+  return (size_t)s * 12 + cnt * 8 * 2 + starts * 8 * 3 + 8192;
 }
 
 __device__ __forceinline__ uint32_t bin_of(uint64_t key, int B) {
@@ -68,6 +71,7 @@ __device__ __forceinline__ uint32_t bin_of(uint64_t key, int B) {
 // kAccPer pairs of the tile before any of them is counted.
 __global__ __launch_bounds__(kAccThreads) void k_acc_count(
     const uint64_t* pk, int64_t n, int B, int64_t tiles, uint64_t* cnt) {
+  // pk: the keys
   __shared__ unsigned h[1 << kAccMaxBits];
   const int nb = 1 << B;
   for (int b = threadIdx.x; b < nb; b += kAccThreads) h[b] = 0;
@@ -77,7 +81,7 @@ __global__ __launch_bounds__(kAccThreads) void k_acc_count(
 #pragma unroll
   for (int u = 0; u < kAccPer; ++u) {
     const int64_t e = t0 + (int64_t)u * kAccThreads;
-    key[u] = e < n ? pk[2 * e] : kEmptyKey;
+    key[u] = e < n ? pk[e] : kEmptyKey;
   }
 #pragma unroll
   for (int u = 0; u < kAccPer; ++u)
@@ -88,37 +92,81 @@ __global__ __launch_bounds__(kAccThreads) void k_acc_count(
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt[tiles << B] = 0;
 }
 
-// place: every pair into its bin's range (order inside a tile's share of a
-// bin is whatever the LDS counter gives; it does not matter)
+// place: every pair into its bin's range.  The tile is first sorted by bin
+// in LDS (the order inside a tile's share of a bin does not matter), so
+// that each bin's share is stored as one contiguous run.
 __global__ __launch_bounds__(kAccThreads) void k_acc_place(
-    const uint64_t* pk, int64_t n, int B, int64_t tiles,
-    const uint64_t* offs, uint64_t* out) {
+    const uint64_t* pk, const float* pv, int64_t n, int B, int64_t tiles,
+    const uint64_t* offs, uint64_t* ok, float* ov) {
   __shared__ unsigned long long base[1 << kAccMaxBits];
   __shared__ unsigned h[1 << kAccMaxBits];
+  __shared__ unsigned long long sk[kAccTile];
+  __shared__ float sv[kAccTile];
+  __shared__ unsigned char sb[kAccTile];
   const int nb = 1 << B;
   for (int b = threadIdx.x; b < nb; b += kAccThreads) {
     h[b] = 0;
     base[b] = offs[(int64_t)b * tiles + blockIdx.x];
   }
-  const int64_t t0 = (int64_t)blockIdx.x * kAccTile + threadIdx.x;
-  ulonglong2 pr[kAccPer];
+  const int64_t t0 = (int64_t)blockIdx.x * kAccTile;
+  uint64_t key[kAccPer];
+  float val[kAccPer];
+  uint32_t bin[kAccPer], rank[kAccPer];
 #pragma unroll
   for (int u = 0; u < kAccPer; ++u) {
-    const int64_t e = t0 + (int64_t)u * kAccThreads;
-    if (e < n) {
-      pr[u] = *(const ulonglong2*)(pk + 2 * e);
-    } else {
-      pr[u].x = kEmptyKey;
-      pr[u].y = 0;
+    const int64_t e = t0 + u * kAccThreads + threadIdx.x;
+    key[u] = e < n ? pk[e] : kEmptyKey;
+    val[u] = e < n ? pv[e] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kAccPer; ++u) {
+    bin[u] = key[u] == kEmptyKey ? 0u : bin_of(key[u], B);
+    rank[u] = key[u] == kEmptyKey ? 0u : atomicAdd(&h[bin[u]], 1u);
+  }
+  __syncthreads();
+  // local starts: exclusive prefix of h (nb <= 256: one wave, 4 per lane)
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    unsigned v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = lane * 4 + q;
+      v[q] = b < nb ? h[b] : 0u;
+      sum += v[q];
+    }
+    unsigned ex = wave_incl_scan(sum) - sum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = lane * 4 + q;
+      if (b < nb) h[b] = ex;
+      ex += v[q];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < kAccPer; ++u) {
-    if (pr[u].x == kEmptyKey) continue;
-    const uint32_t b = bin_of(pr[u].x, B);
-    const int64_t p = (int64_t)base[b] + atomicAdd(&h[b], 1u);
-    *(ulonglong2*)(out + 2 * p) = pr[u];
+    if (key[u] == kEmptyKey) continue;
+    const unsigned p = h[bin[u]] + rank[u];
+    sk[p] = key[u];
+    sv[p] = val[u];
+    sb[p] = (unsigned char)bin[u];
+  }
+  // the tile's closed pairs are sk[0 .. total), total = its non-EMPTY keys
+  __shared__ unsigned total;
+  if (threadIdx.x == 0) total = 0;
+  __syncthreads();
+  unsigned mine = 0;
+#pragma unroll
+  for (int u = 0; u < kAccPer; ++u) mine += key[u] != kEmptyKey;
+  mine = wave_sum(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&total, mine);
+  __syncthreads();
+  for (unsigned i = threadIdx.x; i < total; i += kAccThreads) {
+    const unsigned b = sb[i];
+    const int64_t d = (int64_t)base[b] + (int64_t)(i - h[b]);
+    ok[d] = sk[i];
+    ov[d] = sv[i];
   }
 }
 
@@ -130,8 +178,9 @@ __global__ __launch_bounds__(kAccThreads) void k_acc_place(
 // a new key stores its increment; increments of keys already present are
 // added after a barrier, so most pairs cost one LDS atomic.
 __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
-    const uint64_t* pairs, const uint64_t* starts, int B, uint64_t* okey,
-    int64_t* oval, uint64_t* bin_distinct) {
+    const uint64_t* pk, const float* pv, const uint64_t* starts, int B,
+    const float* bmax, int64_t s_for_F, uint64_t* okey, int64_t* oval,
+    uint64_t* bin_distinct) {
   constexpr int kPer = kRedSlots / kRedThreads;  // slots owned per thread
   constexpr int kW = kRedThreads / 64;
   __shared__ unsigned long long sk[kRedSlots];
@@ -142,6 +191,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
   const int64_t lo = (int64_t)starts[bin];
   const int64_t hi = (int64_t)starts[bin + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int F = fix_exponent(*bmax, s_for_F);
   int64_t wpos = lo;  // next output position (uniform)
   // sub-bins: the hash bits below the bin's B bits
   int R = 1;  // sub-bins in the current split (a power of two)
@@ -153,22 +203,19 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
     __syncthreads();
     const int rb = 31 - __clz(R);  // log2 R
     for (int64_t b0 = lo; b0 < hi; b0 += kRedThreads * kRedPer) {
-      ulonglong2 pr[kRedPer];
+      uint64_t pkey[kRedPer];
+      int64_t pinc[kRedPer];
 #pragma unroll
       for (int u = 0; u < kRedPer; ++u) {
         const int64_t e = b0 + threadIdx.x + (int64_t)u * kRedThreads;
-        if (e < hi) {
-          pr[u] = *(const ulonglong2*)(pairs + 2 * e);
-        } else {
-          pr[u].x = kEmptyKey;
-          pr[u].y = 0;
-        }
+        pkey[u] = e < hi ? pk[e] : kEmptyKey;
+        pinc[u] = e < hi ? (int64_t)rint(ldexp((double)pv[e], F)) : 0;
       }
       int dq[kRedPer];  // slot of a key found present (-1: none)
 #pragma unroll
       for (int u = 0; u < kRedPer; ++u) {
         dq[u] = -1;
-        const uint64_t key = pr[u].x;
+        const uint64_t key = pkey[u];
         if (key == kEmptyKey) continue;
         const uint64_t h = mix64(key);
         if (rb && (int64_t)((h << B) >> (64 - rb)) != sub) continue;
@@ -179,7 +226,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
               atomicCAS(&sk[q], (unsigned long long)kEmptyKey,
                         (unsigned long long)key);
           if (prev == kEmptyKey) {
-            sv[q] = pr[u].y;
+            sv[q] = (unsigned long long)pinc[u];
             break;
           }
           if (prev == key) {
@@ -196,7 +243,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < kRedPer; ++u)
-        if (dq[u] >= 0) atomicAdd(&sv[dq[u]], pr[u].y);
+        if (dq[u] >= 0) atomicAdd(&sv[dq[u]], (unsigned long long)pinc[u]);
       __syncthreads();
     }
     if (full) {
@@ -329,12 +376,17 @@ __global__ void k_acc_starts1(const uint64_t* offs, int64_t tiles, int B1,
 // the next B2 hash bits (LDS counts, scan, place) and writes the sub-bin
 // starts; starts2[(b << B2) + r] for every sub-bin, starts2[end] = n
 constexpr int kAcc2Threads = 1024;
+constexpr int kChunk2 = 4 * kAcc2Threads;
 
 __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
-    const uint64_t* in, const uint64_t* starts1, int B1, int B2,
-    uint64_t* out, uint64_t* starts2) {
+    const uint64_t* ik, const float* iv, const uint64_t* starts1, int B1,
+    int B2, uint64_t* ok, float* ov, uint64_t* starts2) {
   __shared__ unsigned h[1 << kAcc2MaxBits];
+  __shared__ unsigned cc[1 << kAcc2MaxBits];
   __shared__ unsigned wt[kAcc2Threads / 64];
+  __shared__ unsigned long long sk[kChunk2];
+  __shared__ float sv[kChunk2];
+  __shared__ unsigned short sr[kChunk2];
   const int64_t b = blockIdx.x;
   const int64_t lo = (int64_t)starts1[b], hi = (int64_t)starts1[b + 1];
   const int nb2 = 1 << B2;
@@ -346,7 +398,7 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t e = e0 + (int64_t)u * kAcc2Threads;
-      key[u] = e < hi ? in[2 * e] : 0ull;
+      key[u] = e < hi ? ik[e] : 0ull;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -381,20 +433,67 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
   if (b == (int64_t(1) << B1) - 1 && t == 0)
     starts2[(int64_t)1 << (B1 + B2)] = starts1[b + 1];
   __syncthreads();
-  for (int64_t e0 = lo + t; e0 < hi; e0 += kAcc2Threads * 4) {
-    ulonglong2 pr[4];
+  // place, a chunk of kChunk2 pairs at a time: the chunk is sorted by
+  // sub-bin in LDS, then each sub-bin's share is stored as one run at its
+  // cursor (h[r], relative to lo), which then advances by that share
+  for (int64_t c0 = lo; c0 < hi; c0 += kChunk2) {
+    for (int r = t; r < nb2; r += kAcc2Threads) cc[r] = 0;
+    __syncthreads();
+    uint64_t key[4];
+    float val[4];
+    uint32_t sub[4], rank[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t e = e0 + (int64_t)u * kAcc2Threads;
-      if (e < hi) pr[u] = *(const ulonglong2*)(in + 2 * e);
+      const int64_t e = c0 + (int64_t)u * kAcc2Threads + t;
+      const bool in = e < hi;
+      key[u] = in ? ik[e] : 0ull;
+      val[u] = in ? iv[e] : 0.0f;
+      sub[u] = in ? (uint32_t)((mix64(key[u]) << B1) >> (64 - B2)) : 0u;
+      rank[u] = in ? atomicAdd(&cc[sub[u]], 1u) : 0u;
     }
+    __syncthreads();
+    unsigned cv[kPer2], csum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer2; ++u) {
+      const int r = t * kPer2 + u;
+      cv[u] = r < nb2 ? cc[r] : 0u;
+      csum += cv[u];
+    }
+    const unsigned cinc = wave_incl_scan(csum);
+    if (lane == 63) wt[wv] = cinc;
+    __syncthreads();
+    unsigned cex = cinc - csum;
+    for (int w = 0; w < wv; ++w) cex += wt[w];
+#pragma unroll
+    for (int u = 0; u < kPer2; ++u) {
+      const int r = t * kPer2 + u;
+      if (r < nb2) cc[r] = cex;  // the chunk's start of sub-bin r
+      cex += cv[u];
+    }
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (e0 + (int64_t)u * kAcc2Threads >= hi) continue;
-      const uint32_t r = (uint32_t)((mix64(pr[u].x) << B1) >> (64 - B2));
-      const int64_t p = lo + atomicAdd(&h[r], 1u);
-      *(ulonglong2*)(out + 2 * p) = pr[u];
+      if (c0 + (int64_t)u * kAcc2Threads + t >= hi) continue;
+      const unsigned q = cc[sub[u]] + rank[u];
+      sk[q] = key[u];
+      sv[q] = val[u];
+      sr[q] = (unsigned short)sub[u];
     }
+    __syncthreads();
+    const int nc = hi - c0 < kChunk2 ? (int)(hi - c0) : kChunk2;
+    for (int i = t; i < nc; i += kAcc2Threads) {
+      const unsigned r = sr[i];
+      const int64_t d = lo + (int64_t)h[r] + (int64_t)(i - (int)cc[r]);
+      ok[d] = sk[i];
+      ov[d] = sv[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer2; ++u) {
+      const int r = t * kPer2 + u;
+      if (r < nb2) h[r] += cv[u];
+    }
+    __syncthreads();
   }
 }
 
@@ -402,7 +501,8 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
 // output: okey / oval, *o_len (device) entries = closed pairs holding the
 // *o_count (device) distinct keys, EMPTY elsewhere.  The pair array is
 // overwritten.
-hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
+hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
+                             const float* bmax, int64_t s_for_F, void* work,
                              size_t work_bytes, uint64_t* okey, int64_t* oval,
                              int64_t* o_count, int64_t* o_len, hipStream_t st) {
   hipError_t e = launch_fill_u64((uint64_t*)o_count, 1, 0ull, st);
@@ -415,7 +515,9 @@ hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
   const int64_t nb1 = int64_t(1) << B1;
   char* p = (char*)work;
   uint64_t* placed = (uint64_t*)p;
-  p += (size_t)n * 16;
+  p += (size_t)n * 8;
+  float* placed_v = (float*)p;
+  p += ((size_t)n * 4 + 15) / 16 * 16;
   uint64_t* cnt = (uint64_t*)p;
   p += ((size_t)ncnt + 1) * 8;
   uint64_t* starts = (uint64_t*)p;
@@ -425,23 +527,25 @@ hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
   uint64_t* bin_distinct = (uint64_t*)p;
   p += (((size_t)1 << (B1 + B2)) + 1) * 8;
   uint64_t* tmp = (uint64_t*)p;  // scan partial sums
-  k_acc_count<<<(unsigned)tiles, kAccThreads, 0, st>>>(pairs, n, B1, tiles,
+  k_acc_count<<<(unsigned)tiles, kAccThreads, 0, st>>>(keys, n, B1, tiles,
                                                        cnt);
   if ((e = acc_scan(cnt, ncnt + 1, tmp, st)) != hipSuccess) return e;
-  k_acc_place<<<(unsigned)tiles, kAccThreads, 0, st>>>(pairs, n, B1, tiles,
-                                                       cnt, placed);
+  k_acc_place<<<(unsigned)tiles, kAccThreads, 0, st>>>(
+      keys, vals, n, B1, tiles, cnt, placed, placed_v);
   if (B2 == 0) {
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts);
     k_acc_reduce<<<(unsigned)nb1, kRedThreads, 0, st>>>(
-        placed, starts, B1, okey, oval, bin_distinct);
+        placed, placed_v, starts, B1, bmax, s_for_F, okey, oval,
+        bin_distinct);
   } else {
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts1);
     k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
-        placed, starts1, B1, B2, pairs, starts);
+        placed, placed_v, starts1, B1, B2, keys, vals, starts);
     k_acc_reduce<<<(unsigned)(nb1 << B2), kRedThreads, 0, st>>>(
-        pairs, starts, B1 + B2, okey, oval, bin_distinct);
+        keys, vals, starts, B1 + B2, bmax, s_for_F, okey, oval,
+        bin_distinct);
   }
   // entries written = closed pairs = the end of the last bin
   k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count,

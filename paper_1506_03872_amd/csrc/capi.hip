@@ -290,6 +290,12 @@ static bool accum_pairs() {
   return v;
 }
 
+// per-sample pairs: 8-byte keys, then 4-byte values (16-byte aligned end)
+static size_t pair_bytes(int64_t s) {
+  const size_t n = (size_t)(s > 1 ? s : 1);
+  return 8 * n + (4 * n + 15) / 16 * 16;
+}
+
 static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   if (s <= p->ws_s && tp <= p->ws_tp && t <= p->ws_t) return MAD_OK;
   const int64_t s2 = s > p->ws_s ? s : p->ws_s;
@@ -323,8 +329,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
        (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(s2, p->d))) !=
            hipSuccess) ||
       (use_pairs &&
-       (e = mad::dev_alloc(p->acc, 16 * (size_t)(s2 > 1 ? s2 : 1) +
-                                       mad::accum_bytes(s2))) !=
+       (e = mad::dev_alloc(p->acc, pair_bytes(s2) + mad::accum_bytes(s2))) !=
            hipSuccess)) {
     p->ws_s = p->ws_tp = p->ws_t = -1;
     return hip_fail(e, "allocating workspace");
@@ -377,7 +382,8 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   record(p, 2, st);
   mad::HashTable h = p->h;
   if (p->pairs) {
-    h.pairs = (uint64_t*)p->acc.p;
+    h.pkeys = (uint64_t*)p->acc.p;
+    h.pvals = (float*)((char*)p->acc.p + 8 * (size_t)s);
     h.cap = s;
   } else {
     HIP_TRY(mad::launch_fill_u64(h.keys, h.cap, mad::kEmptyKey, st),
@@ -398,15 +404,17 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
             "sampling");
   record(p, 4, st);
   if (p->pairs) {
-    const size_t pb = 16 * (size_t)(s > 1 ? s : 1);
-    HIP_TRY(mad::launch_accumulate(h.pairs, s, (char*)p->acc.p + pb,
-                                   p->acc.bytes - pb, h.keys, h.vals,
+    const size_t pb = pair_bytes(s);
+    HIP_TRY(mad::launch_accumulate(h.pkeys, h.pvals, s, plan_bmax(p), s,
+                                   (char*)p->acc.p + pb, p->acc.bytes - pb,
+                                   h.keys, h.vals,
                                    (int64_t*)&p->ctr->distinct,
                                    (int64_t*)&p->ctr->entries, st),
             "accumulating X");
     h.live = (const int64_t*)&p->ctr->entries;
   }
-  h.pairs = nullptr;
+  h.pkeys = nullptr;
+  h.pvals = nullptr;
   p->h_run = h;
   record(p, 6, st);
   HIP_TRY(mad::launch_postprocess(h, p->A, p->B,

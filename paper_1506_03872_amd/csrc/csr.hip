@@ -1177,14 +1177,15 @@ template <int U, bool DEBUG>
 __global__ __launch_bounds__(256) void k_sample_csr(
     CsrSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
     int F_debug, uint64_t* hkeys, int64_t* hvals, uint64_t hmask,
-    uint64_t* pairs, SampleCounters* ctr, int32_t* ok, int32_t* oi,
+    uint64_t* pkeys, float* pvals, SampleCounters* ctr, int32_t* ok,
+    int32_t* oi,
     int32_t* oj, int32_t* okp, int64_t* oinc) {
   extern __shared__ uint64_t t0s[];
   if (!(wtot[0] > 0.0)) {  // ||W||_1 = 0: nothing can be sampled
-    if (pairs)
+    if (pkeys)
       for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
            e < a.count; e += (int64_t)gridDim.x * blockDim.x)
-        *(ulonglong2*)(pairs + 2 * e) = make_ulonglong2(kEmptyKey, 0ull);
+        pkeys[e] = kEmptyKey;
     return;
   }
   const int N0 = 1 << a.L0;
@@ -1298,21 +1299,22 @@ __global__ __launch_bounds__(256) void k_sample_csr(
         pend[u] = ins[u];
         nclosed += closed[u];
       }
-      if (pairs) {
-        // pair form: (key, inc) at the sample's offset in this launch
+      if (pkeys) {
+        // pair form: the key and the signed fourth edge at the sample's
+        // offset in this launch
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t e = base + (int64_t)u * nthreads;
           if (e < a.count) {
-            ulonglong2 pr;
-            pr.x = ins[u] ? key[u] : kEmptyKey;
-            pr.y = (unsigned long long)inc[u];
-            *(ulonglong2*)(pairs + 2 * e) = pr;
+            __builtin_nontemporal_store(
+                (unsigned long long)(ins[u] ? key[u] : kEmptyKey),
+                (unsigned long long*)(pkeys + e));
+            __builtin_nontemporal_store(sg[u] ? -v[u] : v[u], pvals + e);
           }
           pend[u] = false;
         }
       }
-      bool any = !pairs;
+      bool any = !pkeys;
       while (any) {
         uint64_t prev[U];
 #pragma unroll
@@ -1336,7 +1338,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (!pairs && ins[u] && inc[u] != 0)
+        if (!pkeys && ins[u] && inc[u] != 0)
           atomicAdd((unsigned long long*)(hvals + slot[u]),
                     (unsigned long long)inc[u]);
     }
@@ -1401,7 +1403,7 @@ hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
   const CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
   k_sample_csr<4, false><<<csr_grid(count, 4), 256, csr_t0_lds(t), st>>>(
       a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, (uint64_t)h.cap - 1,
-      h.pairs, ctr, nullptr, nullptr, nullptr, nullptr, nullptr);
+      h.pkeys, h.pvals, ctr, nullptr, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1412,8 +1414,8 @@ hipError_t launch_sample_csr_debug(const CsrTables& t, uint64_t seed,
   if (count <= 0) return hipSuccess;
   const CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
   k_sample_csr<2, true><<<csr_grid(count, 2), 256, csr_t0_lds(t), st>>>(
-      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, nullptr, k, i,
-      j, kp, inc);
+      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, nullptr, nullptr,
+      k, i, j, kp, inc);
   return hipGetLastError();
 }
 

@@ -69,24 +69,27 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 // ---- sampler.hip ---------------------------------------------------------
 // The score table X.  Hash form: open addressing over `cap` slots (a power
 // of two), EMPTY keys unused.  With `live` set only entries [0, *live) are
-// read (EMPTY keys among them are unused).  With `pairs` set the samplers
-// write sample e's (key, inc) at pairs[2e], pairs[2e + 1] (key EMPTY for an
-// open three-path) instead of updating the table; X is then built by
-// launch_accumulate.
+// read (EMPTY keys among them are unused).  With `pkeys` set the samplers
+// write sample e's key at pkeys[e] (EMPTY for an open three-path) and its
+// signed fourth edge at pvals[e] (increment rne(v 2^F)) instead of updating
+// the table; X is then built by launch_accumulate.
 struct HashTable {
   uint64_t* keys = nullptr;
   int64_t* vals = nullptr;
   int64_t cap = 0;
   const int64_t* live = nullptr;
-  uint64_t* pairs = nullptr;
+  uint64_t* pkeys = nullptr;
+  float* pvals = nullptr;
 };
 
-// sum of the increments per key over n pairs (key EMPTY: skipped) into
-// okey / oval: *o_len entries (one per non-EMPTY pair) holding the *o_count
-// distinct keys and EMPTY elsewhere; work of accum_bytes(n) bytes; the pair
-// array is overwritten
+// sum of the increments rne(vals[e] 2^F) per key over n pairs (key EMPTY:
+// skipped; F from *bmax and s_for_F as in the samplers) into okey / oval:
+// *o_len entries (one per non-EMPTY pair) holding the *o_count distinct
+// keys and EMPTY elsewhere; work of accum_bytes(n) bytes; keys and vals are
+// overwritten
 size_t accum_bytes(int64_t n);
-hipError_t launch_accumulate(uint64_t* pairs, int64_t n, void* work,
+hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
+                             const float* bmax, int64_t s_for_F, void* work,
                              size_t work_bytes, uint64_t* okey, int64_t* oval,
                              int64_t* o_count, int64_t* o_len, hipStream_t st);
 

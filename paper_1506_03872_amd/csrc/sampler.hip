@@ -58,15 +58,15 @@ template <int U, bool DEBUG, bool GROUPED>
 __global__ __launch_bounds__(256) void k_sample_dense(
     DenseSampleArgs a, const double* wtot, const float* bmax, int64_t s_for_F,
     int F_debug,
-    uint64_t* hkeys, int64_t* hvals, uint64_t hmask, uint64_t* pairs,
-    SampleCounters* ctr, int32_t* ok, int32_t* oi, int32_t* oj,
+    uint64_t* hkeys, int64_t* hvals, uint64_t hmask, uint64_t* pkeys,
+    float* pvals, SampleCounters* ctr, int32_t* ok, int32_t* oi, int32_t* oj,
     int32_t* okp, int64_t* oinc, GroupOrder go) {
   extern __shared__ uint64_t t0s[];  // T0 when it fits (kT0Lds entries)
   if (!(wtot[0] > 0.0)) {  // ||W||_1 = 0: nothing can be sampled
-    if (pairs)
+    if (pkeys)
       for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
            e < a.count; e += (int64_t)gridDim.x * blockDim.x)
-        *(ulonglong2*)(pairs + 2 * e) = make_ulonglong2(kEmptyKey, 0ull);
+        pkeys[e] = kEmptyKey;
     return;
   }
   const int N0 = 1 << a.L0;
@@ -178,25 +178,23 @@ __global__ __launch_bounds__(256) void k_sample_dense(
         pend[u] = ins[u];
         nclosed += smp[u].closed;
       }
-      if (pairs) {
-        // pair form: (key, inc) at the sample's place in the walk, which is
-        // one-to-one with the samples of this launch
+      if (pkeys) {
+        // pair form: the key and the signed fourth edge at the sample's
+        // place in the walk, which is one-to-one with the samples of this
+        // launch; streamed once, kept out of the caches that hold T3 and B
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t e = base + (int64_t)u * nthreads;
           if (e < a.count) {
-            ulonglong2 pr;
-            pr.x = ins[u] ? key[u] : kEmptyKey;
-            pr.y = (unsigned long long)smp[u].inc;
-            // streamed once: kept out of the caches that hold T3 and B
-            __builtin_nontemporal_store(pr.x, (unsigned long long*)(pairs + 2 * e));
-            __builtin_nontemporal_store(pr.y,
-                                        (unsigned long long*)(pairs + 2 * e + 1));
+            __builtin_nontemporal_store(
+                (unsigned long long)(ins[u] ? key[u] : kEmptyKey),
+                (unsigned long long*)(pkeys + e));
+            __builtin_nontemporal_store(sgn[u] ? -v[u] : v[u], pvals + e);
           }
           pend[u] = false;
         }
       }
-      bool any = !pairs;
+      bool any = !pkeys;
       while (any) {
         uint64_t prev[U];
 #pragma unroll
@@ -220,7 +218,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (!pairs && ins[u] && smp[u].inc != 0)
+        if (!pkeys && ins[u] && smp[u].inc != 0)
           atomicAdd((unsigned long long*)(hvals + slot[u]),
                     (unsigned long long)smp[u].inc);
     }
@@ -521,8 +519,9 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
   case UU:                                                                 \
     k_sample_dense<UU, false, false>                                       \
         <<<sample_grid(count, UU), 256, lds, st>>>(                        \
-            a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, h.pairs,  \
-            ctr, nullptr, nullptr, nullptr, nullptr, nullptr, GroupOrder{}); \
+            a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm, h.pkeys,  \
+            h.pvals, ctr, nullptr, nullptr, nullptr, nullptr, nullptr,     \
+            GroupOrder{});                                                 \
     break;
       MAD_SAMPLE_CASE(1)
       MAD_SAMPLE_CASE(2)
@@ -561,8 +560,8 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     if (g8 < 1) g8 = 1;
     k_sample_dense<4, false, true><<<(unsigned)(8 * g8), 256, lds, st>>>(
         a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm,
-        h.pairs ? h.pairs + 2 * c0 : nullptr, ctr, nullptr, nullptr, nullptr,
-        nullptr, nullptr, go);
+        h.pkeys ? h.pkeys + c0 : nullptr, h.pvals ? h.pvals + c0 : nullptr,
+        ctr, nullptr, nullptr, nullptr, nullptr, nullptr, go);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -578,8 +577,8 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
   const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
   k_sample_dense<2, true, false>
       <<<sample_grid(count, 2), 256, t0_lds_bytes(t), st>>>(
-      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, nullptr, k, i, j,
-      kp, inc, GroupOrder{});
+      a, t.T0.tot, t.bmax, 0, F, nullptr, nullptr, 0, nullptr, nullptr, nullptr,
+      k, i, j, kp, inc, GroupOrder{});
   return hipGetLastError();
 }
 
