@@ -27,9 +27,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one dense sample: three 8-byte alias entries (T1[k],
 # T2[k], T3[i]; T0 sits in LDS) + the 4-byte fourth edge b_k'j read, and
-# the sample's 16-byte (key, increment) pair written.
+# the sample's 12-byte pair (8-byte key, 4-byte signed fourth edge) written.
 SAMPLE_READ_BYTES = 3 * 8 + 4
-PAIR_WRITE_BYTES = 16
+PAIR_WRITE_BYTES = 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sample_dense_traffic.json")
 SAMPLER_SRC = os.path.join(ROOT, "paper_1506_03872_amd", "csrc",
                            "sampler.hip")
@@ -262,8 +262,8 @@ def bench_mips(args, cfg, data, mad):
 # algorithmic bytes of one sparse sample: stage-0 entry (8 B, L2 resident
 # for d = 1e5), three table metas (8 B each), three 16-byte alias entries,
 # the two row pointers of b_j, its coordinate list searched (log2 nnz_j + 1
-# four-byte loads) and the fourth-edge value, then the 16-byte (key,
-# increment) pair written
+# four-byte loads) and the fourth-edge value, then the 12-byte pair
+# written
 def csr_sample_bytes(nnz_per_vec):
     import math
     probes = int(math.ceil(math.log2(max(nnz_per_vec, 2)))) + 1

@@ -505,9 +505,15 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
                              const float* bmax, int64_t s_for_F, void* work,
                              size_t work_bytes, uint64_t* okey, int64_t* oval,
                              int64_t* o_count, int64_t* o_len, hipStream_t st) {
-  hipError_t e = launch_fill_u64((uint64_t*)o_count, 1, 0ull, st);
-  if (e == hipSuccess) e = launch_fill_u64((uint64_t*)o_len, 1, 0ull, st);
-  if (e != hipSuccess || n <= 0) return e;
+  hipError_t e;
+  if (n <= 0) {  // otherwise k_acc_sum writes both
+    FillBatch f{};
+    f.p[0] = (uint64_t*)o_count;
+    f.p[1] = (uint64_t*)o_len;
+    f.n[0] = f.n[1] = 1;
+    f.count = 2;
+    return launch_fill_multi(f, st);
+  }
   if (work_bytes < accum_bytes(n)) return hipErrorInvalidValue;
   const int B1 = acc_b1(n), B2 = acc_b2(n);
   const int64_t tiles = (n + kAccTile - 1) / kAccTile;

@@ -391,8 +391,14 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
     HIP_TRY(mad::launch_fill_u64((uint64_t*)h.vals, h.cap, 0ull, st),
             "clearing X");
   }
-  HIP_TRY(mad::launch_fill_u64((uint64_t*)p->ctr, 8, 0ull, st),
-          "clearing counters");
+  {  // the sampler's counters and postprocessing's clears in one launch
+    mad::FillBatch f{};
+    f.p[0] = (uint64_t*)p->ctr;
+    f.n[0] = 8;
+    f.count = 1;
+    mad::post_fills(p->w, f);
+    HIP_TRY(mad::launch_fill_multi(f, st), "clearing counters");
+  }
   record(p, 3, st);
   if (p->kind == 2)
     HIP_TRY(mad::launch_sample_csr(p->ct, seed, 0, 0, s, s, h, p->ctr, st),
@@ -422,7 +428,7 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
                                   p->verify_prec != MAD_FP32 ? &p->lv : nullptr,
                                   p->n, p->d, tp_eff, t, plan_bmax(p), s,
                                   (p->flags & MAD_FLAG_GRAM) ? 1 : 0, p->w,
-                                  out, n_out, st),
+                                  out, n_out, true, st),
           "postprocessing");
   record(p, 5, st);
   p->timed_topk = p->ev[0] != nullptr;

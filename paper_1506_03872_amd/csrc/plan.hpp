@@ -65,6 +65,14 @@ void family_free_pub(Family& f);
 
 // generic launchers reused by other files
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
+constexpr int kFillMax = 4;
+struct FillBatch {  // fill p[q][0 .. n[q]) with v[q], q < count
+  uint64_t* p[kFillMax];
+  int64_t n[kFillMax];
+  uint64_t v[kFillMax];
+  int count;
+};
+hipError_t launch_fill_multi(const FillBatch& f, hipStream_t st);
 
 // ---- sampler.hip ---------------------------------------------------------
 // The score table X.  Hash form: open addressing over `cap` slots (a power
@@ -328,12 +336,15 @@ void lowp_consts(int prec, int64_t d, float* kappa, float* onepu);
 // null
 // x_shift: reported x = x_fix * 2^-(F + x_shift) (1 for symmetrised
 // scores, which hold x_ij + x_ji)
+// cleared: the caller has already run the fills of post_fills
+void post_fills(SelectWork& w, FillBatch& f);
 hipError_t launch_postprocess(const HashTable& h, const float* A,
                               const float* B, const CsrView* csr,
                               const LowpView* lowp, int64_t n, int64_t d,
                               int64_t t_prime, int64_t t, const float* bmax,
                               int64_t s, int x_shift, SelectWork& w,
-                              void* out, int64_t* n_out, hipStream_t st);
+                              void* out, int64_t* n_out, bool cleared,
+                              hipStream_t st);
 
 // fp32 re-rank of candidate keys (count known on the host) and the exact
 // top t by |c| into mad_pair records; buf is grown as needed

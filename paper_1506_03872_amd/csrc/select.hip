@@ -271,38 +271,80 @@ __global__ __launch_bounds__(256) void k_score_split(
 // ---------------------------------------------------------------------------
 constexpr int kFineThreads = 1024;
 
+constexpr int kFineLds = 4096;  // boundary lists up to this size sit in LDS
+
 __global__ __launch_bounds__(kFineThreads) void k_fine_select(
     const Coarse* cz, const uint64_t* bx, const uint64_t* bkey,
     const uint64_t* bextra, const float* bc, int64_t bcap, int64_t* counts,
     int win_slot, uint64_t* ox, uint64_t* okey, uint64_t* oextra, float* oc,
     int64_t ocap, int out_count_slot) {
   __shared__ unsigned h[kBins];
-  __shared__ unsigned long long scan[kFineThreads];
+  __shared__ unsigned long long wsum[kFineThreads / 64];
+  __shared__ uint64_t lx[kFineLds], lk[kFineLds];
+  __shared__ unsigned long long red_and, red_or;
   __shared__ int chosen;
   __shared__ unsigned long long before;
   __shared__ unsigned long long emitted;
   const Coarse c = *cz;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t nwin = counts[win_slot] < ocap ? counts[win_slot] : ocap;
   int64_t nb = counts[kCntBound];
   if (nb > bcap) nb = bcap;
   const bool none = c.bin < 0 || c.k_rem <= 0;
   int64_t k_rem = none ? 0 : c.k_rem;
+  // the list in LDS when it fits
+  const bool in_lds = nb <= kFineLds;
+  if (in_lds)
+    for (int64_t e = t; e < nb; e += kFineThreads) {
+      lx[e] = bx[e];
+      lk[e] = bkey[e];
+    }
+  const uint64_t* X = in_lds ? lx : bx;
+  const uint64_t* Kk = in_lds ? lk : bkey;
+  // bits shared by every primary value: the radix passes start below them
+  if (t == 0) {
+    red_and = ~0ull;
+    red_or = 0ull;
+  }
+  __syncthreads();
+  {
+    uint64_t va = ~0ull, vo = 0ull;
+    for (int64_t e = t; e < nb; e += kFineThreads) {
+      va &= X[e];
+      vo |= X[e];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      va &= __shfl_xor(va, off, 64);
+      vo |= __shfl_xor(vo, off, 64);
+    }
+    if (lane == 0 && nb > 0) {
+      atomicAnd(&red_and, (unsigned long long)va);
+      atomicOr(&red_or, (unsigned long long)vo);
+    }
+  }
+  __syncthreads();
+  const uint64_t diff = nb > 0 ? (uint64_t)(red_and ^ red_or) : 0ull;
   uint64_t pp = 0, pm = 0, kp = 0, km = 0;
-  bool key_phase = false;
-  bool done = none || k_rem >= nb;
-  // primary digits from the top of the 64-bit range, then key digits
+  bool key_phase = diff == 0;
   int shift = 64 - kDigit;
+  if (diff != 0) {
+    const int hd = 63 - __clzll((long long)diff);  // highest differing bit
+    shift = hd >= kDigit - 1 ? hd - (kDigit - 1) : 0;
+    pm = hd < 63 ? ~0ull << (hd + 1) : 0ull;
+    pp = (uint64_t)red_and & pm;
+  }
+  bool done = none || k_rem >= nb;
+  // primary digits from the highest differing bit down, then key digits
   while (!done) {
     for (int b = t; b < kBins; b += kFineThreads) h[b] = 0;
     __syncthreads();
     for (int64_t e = t; e < nb; e += kFineThreads) {
-      const uint64_t p = bx[e];
+      const uint64_t p = X[e];
       if ((p & pm) != pp) continue;
       if (!key_phase) {
         atomicAdd(&h[(p >> shift) & kDigitMask], 1u);
       } else {
-        const uint64_t kk = bkey[e];
+        const uint64_t kk = Kk[e];
         if ((kk & km) != kp) continue;
         atomicAdd(&h[(kk >> shift) & kDigitMask], 1u);
       }
@@ -313,16 +355,14 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
     const int b0 = key_phase ? 2 * t : kBins - 1 - 2 * t;
     const int b1 = key_phase ? 2 * t + 1 : kBins - 2 - 2 * t;
     const unsigned v0 = h[b0], v1 = h[b1];
-    scan[t] = (unsigned long long)v0 + v1;
+    const unsigned long long pair = (unsigned long long)v0 + v1;
+    const unsigned long long winc = wave_incl_scan(pair);
+    if (lane == 63) wsum[wv] = winc;
     if (t == 0) chosen = -1;
     __syncthreads();
-    for (int off = 1; off < kFineThreads; off <<= 1) {
-      const unsigned long long o = t >= off ? scan[t - off] : 0ull;
-      __syncthreads();
-      scan[t] += o;
-      __syncthreads();
-    }
-    const unsigned long long excl = scan[t] - v0 - v1;
+    unsigned long long woff = 0;
+    for (int w = 0; w < wv; ++w) woff += wsum[w];
+    const unsigned long long excl = woff + winc - pair;
     if ((long long)excl < k_rem && (long long)(excl + v0) >= k_rem) {
       chosen = b0;
       before = excl;
@@ -360,8 +400,8 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
   if (t == 0) emitted = 0;
   __syncthreads();
   for (int64_t e = t; e < nb && !none; e += kFineThreads) {
-    const uint64_t p = bx[e];
-    const uint64_t kk = bkey[e];
+    const uint64_t p = X[e];
+    const uint64_t kk = Kk[e];
     const uint64_t pmv = p & pm;
     bool take;
     if (pmv != pp) take = pmv > pp;
@@ -637,23 +677,36 @@ struct PairOut {
   float c, x;
 };
 
-__global__ void k_final_sort(const uint64_t* fkey, const uint64_t* fx,
-                             const float* fc, const int64_t* counts,
-                             int64_t tcap, int64_t n, const float* bmax,
-                             int64_t s_for_F, int x_shift, PairOut* out,
-                             int64_t* n_out) {
+// the final set ordered by (|c| desc, key asc): each element's rank is the
+// number of elements before it, counted against the set staged in LDS in
+// chunks
+constexpr int kSortChunk = 2048;
+
+__global__ __launch_bounds__(256) void k_final_sort(
+    const uint64_t* fkey, const uint64_t* fx, const float* fc,
+    const int64_t* counts, int64_t tcap, int64_t n, const float* bmax,
+    int64_t s_for_F, int x_shift, PairOut* out, int64_t* n_out) {
+  __shared__ float sa[kSortChunk];
+  __shared__ uint64_t sk[kSortChunk];
   const int64_t nf = counts[kCntFinal] < tcap ? counts[kCntFinal] : tcap;
   const int F = (bmax ? fix_exponent(*bmax, s_for_F) : 0) + x_shift;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf;
-       e += stride) {
-    const float ae = fabsf(fc[e]);
-    const uint64_t ke = fkey[e];
-    int64_t rank = 0;
-    for (int64_t o = 0; o < nf; ++o) {
-      const float ao = fabsf(fc[o]);
-      rank += ao > ae || (ao == ae && fkey[o] < ke);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float ae = e < nf ? fabsf(fc[e]) : 0.0f;
+  const uint64_t ke = e < nf ? fkey[e] : 0ull;
+  int64_t rank = 0;
+  for (int64_t o0 = 0; o0 < nf; o0 += kSortChunk) {
+    const int64_t no = nf - o0 < kSortChunk ? nf - o0 : kSortChunk;
+    __syncthreads();
+    for (int64_t o = threadIdx.x; o < no; o += blockDim.x) {
+      sa[o] = fabsf(fc[o0 + o]);
+      sk[o] = fkey[o0 + o];
     }
+    __syncthreads();
+    if (e < nf)
+      for (int64_t o = 0; o < no; ++o)
+        rank += sa[o] > ae || (sa[o] == ae && sk[o] < ke);
+  }
+  if (e < nf) {
     PairOut p;
     p.i = (int64_t)(ke / (uint64_t)n);
     p.j = (int64_t)(ke % (uint64_t)n);
@@ -801,9 +854,21 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
                                             counts, kCntWin, fp, fkey, fx, fc,
                                             t, kCntFinal);
   // x = 0 for brute-force results (no sampler score); F is irrelevant
-  k_final_sort<<<blocks_for(t, 256, 1024), 256, 0, st>>>(
+  k_final_sort<<<blocks_for(t, 256, 1 << 30), 256, 0, st>>>(
       fkey, fx, fc, counts, t, n, nullptr, 0, 0, (PairOut*)out, n_out);
   return hipGetLastError();
+}
+
+// The clears postprocessing starts from: the counts it accumulates and the
+// histogram (cleared by each decision, and here as well so that a fresh or
+// previously interrupted workspace starts from zero).  Appends 3 fills.
+void post_fills(SelectWork& w, FillBatch& f) {
+  f.p[f.count] = (uint64_t*)w.counts;
+  f.n[f.count++] = 1;
+  f.p[f.count] = (uint64_t*)&w.counts[kCntCand];
+  f.n[f.count++] = 4;
+  f.p[f.count] = (uint64_t*)w.hist;
+  f.n[f.count++] = kBins / 2;
 }
 
 hipError_t launch_postprocess(const HashTable& h, const float* A,
@@ -811,18 +876,17 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
                               const LowpView* lowp, int64_t n, int64_t d,
                               int64_t t_prime, int64_t t, const float* bmax,
                               int64_t s, int x_shift, SelectWork& w,
-                              void* out, int64_t* n_out, hipStream_t st) {
+                              void* out, int64_t* n_out, bool cleared,
+                              hipStream_t st) {
   Coarse* cz = (Coarse*)w.state;
   int64_t* counts = w.counts;
   // keep counts[kCntDistinct] (the sampler's), clear the others
-  hipError_t e = launch_fill_u64((uint64_t*)counts, 1, 0ull, st);
-  if (e == hipSuccess)
-    e = launch_fill_u64((uint64_t*)&counts[kCntCand], 4, 0ull, st);
-  // the histogram is cleared by each decision; clear it here as well so a
-  // fresh (or previously interrupted) workspace starts from zero
-  if (e == hipSuccess)
-    e = launch_fill_u64((uint64_t*)w.hist, kBins / 2, 0ull, st);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!cleared) {
+    FillBatch f{};
+    post_fills(w, f);
+    if ((e = launch_fill_multi(f, st)) != hipSuccess) return e;
+  }
   // ---- post1: top t' of x over x > 0 ------------------------------------
   k_score_hist<<<blocks_for(h.cap, kHistThreads * 16, kHistBlocks),
                  kHistThreads, 0, st>>>(h.vals, h.cap, h.live, w.hist);
@@ -877,7 +941,7 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   k_fine_select<<<1, kFineThreads, 0, st>>>(
       cz + 1, bp, bkey, bx, bc, bcap, counts, kCntWin, fp, fkey, fx, fc, t,
       kCntFinal);
-  k_final_sort<<<blocks_for(t, 256, 1024), 256, 0, st>>>(
+  k_final_sort<<<blocks_for(t, 256, 1 << 30), 256, 0, st>>>(
       fkey, fx, fc, counts, t, n, bmax, s, x_shift, (PairOut*)out, n_out);
   return hipGetLastError();
 }

@@ -104,6 +104,27 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v,
   return hipGetLastError();
 }
 
+// up to kFillMax fills in one launch (small clears would otherwise each pay
+// a launch)
+__global__ void k_fill_multi(FillBatch f) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int q = 0; q < f.count; ++q) {
+    for (; e < f.n[q]; e += stride) f.p[q][e] = f.v[q];
+    e -= f.n[q];
+  }
+}
+
+hipError_t launch_fill_multi(const FillBatch& f, hipStream_t st) {
+  int64_t tot = 0;
+  for (int q = 0; q < f.count; ++q) tot += f.n[q] > 0 ? f.n[q] : 0;
+  if (tot <= 0) return hipSuccess;
+  int64_t blocks = (tot + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  k_fill_multi<<<(unsigned)blocks, 256, 0, st>>>(f);
+  return hipGetLastError();
+}
+
 // max |x| (as float bits, atomically) and a flag for non-finite entries;
 // float4 loads when X is 16-byte aligned
 __global__ __launch_bounds__(1024) void k_scan_inputs(const float* X,
@@ -1063,9 +1084,14 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   const size_t alias_bytes = need > used ? need - used : 0;
   void* side_scratch = (char*)scratch_buf.p + need;
 
-  if ((e = launch_fill_u64((uint64_t*)t.bmax, 1, 0ull, st)) != hipSuccess ||
-      (e = launch_fill_u64((uint64_t*)t.bad, 1, 0ull, st)) != hipSuccess)
-    return e;
+  {
+    FillBatch f{};
+    f.p[0] = (uint64_t*)t.bmax;
+    f.p[1] = (uint64_t*)t.bad;
+    f.n[0] = f.n[1] = 1;
+    f.count = 2;
+    if ((e = launch_fill_multi(f, st)) != hipSuccess) return e;
+  }
   if (check)
     k_scan_inputs<<<grid_for(m * d, 1024 * 16) > 256 ? 256
                         : grid_for(m * d, 1024 * 16), 1024, 0, st>>>(
