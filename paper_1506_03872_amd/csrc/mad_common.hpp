@@ -39,14 +39,16 @@ __device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1,
   constexpr uint64_t M1 = 0xCA5A826395121157ull;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
-    const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
-    const uint64_t n0 = hi1 ^ c1 ^ k0;
-    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    // each 64 x 64 -> 128-bit product formed once (both halves share the
+    // partial products)
+    const __uint128_t p0 = (__uint128_t)M0 * c0;
+    const __uint128_t p1 = (__uint128_t)M1 * c2;
+    const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c1 ^ k0;
+    const uint64_t n2 = (uint64_t)(p0 >> 64) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint64_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint64_t)p0;
     k0 += 0x9E3779B97F4A7C15ull;
     k1 += 0xBB67AE8584CAA73Bull;
   }
