@@ -287,13 +287,13 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
 }
 
 // keys = coordinates, payload = (vector id << 32) | value bits
-__global__ void k_sort_init(const int32_t* idx, const float* val,
-                            const uint32_t* rowid, int64_t n, uint32_t* key,
-                            uint64_t* pay) {
+// key = coordinate, payload = (row, source position of the entry)
+__global__ void k_sort_init(const int32_t* idx, const uint32_t* rowid,
+                            int64_t n, uint32_t* key, uint64_t* pay) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) {
     key[e] = (uint32_t)idx[e];
-    pay[e] = ((uint64_t)rowid[e] << 32) | __float_as_uint(val[e]);
+    pay[e] = ((uint64_t)rowid[e] << 32) | (uint32_t)e;
   }
 }
 
@@ -311,12 +311,40 @@ __global__ void k_lower_bound(const uint32_t* key, int64_t n, int64_t d,
 }
 
 __global__ void k_trans_split(const uint64_t* pay, int64_t n, uint32_t* trow,
-                              float* tval) {
+                              uint32_t* tsrc) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) {
     const uint64_t v = pay[p];
     trow[p] = (uint32_t)(v >> 32);
-    tval[p] = __uint_as_float((uint32_t)v);
+    tsrc[p] = (uint32_t)v;
+  }
+}
+
+// transposed values from the vector-major ones: tval[p] = val[tsrc[p]]
+__global__ void k_trans_gather(const uint32_t* tsrc, const float* val,
+                               int64_t n, float* tval) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += stride)
+    tval[p] = val[tsrc[p]];
+}
+
+// max |v| over n values, into *amax (as float bits; values are finite)
+__global__ __launch_bounds__(1024) void k_absmax(const float* v, int64_t n,
+                                                 float* amax) {
+  __shared__ float wm[16];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  float mx = 0.0f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += stride)
+    mx = fmaxf(mx, fabsf(v[e]));
+  for (int off = 32; off > 0; off >>= 1)
+    mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmaxf(mx, wm[w]);
+    atomicMax((unsigned int*)amax, __float_as_uint(mx));
   }
 }
 
@@ -359,11 +387,12 @@ static SortBufs sort_carve(void* p, int64_t nnz) {
 static hipError_t csr_transpose(const int64_t* ptr, const int32_t* idx,
                                 const float* val, int64_t rows, int64_t d,
                                 int64_t nnz, int64_t* tptr, uint32_t* trow,
-                                float* tval, SortBufs b, hipStream_t st) {
+                                uint32_t* tsrc, float* tval, SortBufs b,
+                                hipStream_t st) {
   if (nnz > 0) {
     k_row_ids<<<blocks_of(rows * 64, 256), 256, 0, st>>>(ptr, rows, b.rowid);
-    k_sort_init<<<blocks_of(nnz, 256), 256, 0, st>>>(idx, val, b.rowid, nnz,
-                                                     b.k0, b.v0);
+    k_sort_init<<<blocks_of(nnz, 256), 256, 0, st>>>(idx, b.rowid, nnz, b.k0,
+                                                     b.v0);
     const int bits = ceil_log2_i(d);
     const int passes = bits > 0 ? (bits + 3) / 4 : 1;
     const int64_t tiles = (nnz + kRsTile - 1) / kRsTile;
@@ -379,7 +408,10 @@ static hipError_t csr_transpose(const int64_t* ptr, const int32_t* idx,
       std::swap(ka, kb);
       std::swap(va, vb);
     }
-    k_trans_split<<<blocks_of(nnz, 256), 256, 0, st>>>(va, nnz, trow, tval);
+    k_trans_split<<<blocks_of(nnz, 256), 256, 0, st>>>(va, nnz, trow, tsrc);
+    k_trans_gather<<<blocks_of(nnz, 256 * 8) < 2048 ? blocks_of(nnz, 256 * 8)
+                                                     : 2048,
+                     256, 0, st>>>(tsrc, val, nnz, tval);
     k_lower_bound<<<blocks_of(d + 1, 256), 256, 0, st>>>(ka, nnz, d, tptr);
   } else {
     k_lower_bound<<<blocks_of(d + 1, 256), 256, 0, st>>>(nullptr, 0, d, tptr);
@@ -1058,18 +1090,22 @@ void csr_tables_free(CsrTables& t) {
   ragged_free(t.T2);
   ragged_free(t.T3);
   family_free_pub(t.T0);
-  void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.bt_ptr, t.bt_row, t.bt_val,
-                t.om, t.bmax, t.bad};
+  void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
+                t.bt_val, t.bt_src, t.om, t.bmax, t.bad};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
   t.at_row = t.bt_row = nullptr;
   t.at_val = t.bt_val = nullptr;
+  t.at_src = t.bt_src = nullptr;
+  t.structured = false;
   t.om = nullptr;
   t.bmax = nullptr;
   t.bad = nullptr;
   dev_free(t.work);
 }
+
+static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st);
 
 hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
   hipError_t e;
@@ -1085,8 +1121,29 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = hipMalloc(&t.at_val, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = hipMalloc(&t.bt_row, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = hipMalloc(&t.bt_val, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.at_src, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bt_src, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
       return e;
+  }
+  if (!check && t.structured) {
+    // the caller vouches that the structure is the one of this plan's
+    // first build: regather the transposed values, then the tables
+    if ((e = launch_fill_u64((uint64_t*)t.bmax, 1, 0ull, st)) != hipSuccess)
+      return e;
+    const int64_t nzb = t.nnzB > 0 ? t.nnzB : 1;
+    k_absmax<<<blocks_of(nzb, 1024 * 16) < 256 ? blocks_of(nzb, 1024 * 16)
+                                               : 256,
+               1024, 0, st>>>(t.in.b_val, t.nnzB, t.bmax);
+    if (t.nnzA > 0)
+      k_trans_gather<<<blocks_of(t.nnzA, 256 * 8) < 2048
+                           ? blocks_of(t.nnzA, 256 * 8) : 2048,
+                       256, 0, st>>>(t.at_src, t.in.a_val, t.nnzA, t.at_val);
+    if (t.nnzB > 0)
+      k_trans_gather<<<blocks_of(t.nnzB, 256 * 8) < 2048
+                           ? blocks_of(t.nnzB, 256 * 8) : 2048,
+                       256, 0, st>>>(t.bt_src, t.in.b_val, t.nnzB, t.bt_val);
+    return csr_tables_from_transposes(t, st);
   }
   // validation: the structure on the first build of a plan and on every
   // checked build (every later index relies on it; without the check the
@@ -1113,9 +1170,11 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
   if ((e = dev_alloc(t.work, sort_bytes(nz))) != hipSuccess) return e;
   const SortBufs sb = sort_carve(t.work.p, nz);
   if ((e = csr_transpose(t.in.a_ptr, t.in.a_idx, t.in.a_val, m, d, t.nnzA,
-                         t.at_ptr, t.at_row, t.at_val, sb, st)) != hipSuccess ||
+                         t.at_ptr, t.at_row, t.at_src, t.at_val, sb,
+                         st)) != hipSuccess ||
       (e = csr_transpose(t.in.b_ptr, t.in.b_idx, t.in.b_val, n, d, t.nnzB,
-                         t.bt_ptr, t.bt_row, t.bt_val, sb, st)) != hipSuccess)
+                         t.bt_ptr, t.bt_row, t.bt_src, t.bt_val, sb,
+                         st)) != hipSuccess)
     return e;
   // layouts (host)
   if ((e = ragged_layout(t.T3, t.in.a_ptr, m, st)) != hipSuccess ||
@@ -1128,6 +1187,14 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
   need = std::max(need, stage0_scratch_bytes(d));
   need = std::max(need, sort_bytes(nz));
   if ((e = dev_alloc(t.work, need)) != hipSuccess) return e;
+  t.structured = true;
+  return csr_tables_from_transposes(t, st);
+}
+
+// the tables from the transposes and the layouts already in place
+static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
+  hipError_t e;
+  const int64_t d = t.d;
   // T3 (totals na), T1 (weights |a_ki| na_i, totals v), T2 (totals nb), T0
   if ((e = ragged_build(t.T3, RowItems{t.in.a_val, t.in.a_idx}, t.work.p,
                         st)) != hipSuccess ||

@@ -189,6 +189,13 @@ struct CsrTables {
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.3)
   bool validated = false; // the structure passed a check on this plan
+  // the transposes' structure (pointers, rows, and the source position of
+  // each entry) and the table layouts depend only on the sparsity
+  // structure: built once, reused by unchecked refreshes, which regather
+  // the values only
+  bool structured = false;
+  uint32_t* at_src = nullptr; // nnzA
+  uint32_t* bt_src = nullptr; // nnzB
 };
 
 // Allocates and builds every table (synchronises: the layout of the

@@ -224,3 +224,43 @@ def test_malformed_and_nonfinite_inputs_rejected(mad_gpu):
     gp = attempt(a, b)
     assert gp.stats()["wnorm"] > 0
     gp.close()
+
+
+def test_unchecked_refresh_regathers_values(mad_gpu):
+    """A plan made with MAD_FLAG_NO_CHECK keeps its first build's structure
+    (transposes, layouts) and only regathers values on refresh: after new
+    values are written into the borrowed arrays, its tables, samples and
+    results equal those of a fresh, checked plan on the new values."""
+    import torch
+    a, b, m, n, d = _powerlaw()
+    ta = tuple(to_dev(x) for x in a)
+    tb = tuple(to_dev(x) for x in b)
+    gp = mad_gpu.Plan.csr(ta, tb, m, n, d, flags=mad_gpu.MAD_FLAG_NO_CHECK)
+    gp.topk(t=10, s=50_000, t_prime=300, seed=3)
+    g = np.random.default_rng(21)
+    av = (g.standard_normal(len(a[2])) * 3).astype(np.float32)
+    bv = g.standard_normal(len(b[2])).astype(np.float32)
+    ta[2].copy_(torch.from_numpy(av))
+    tb[2].copy_(torch.from_numpy(bv))
+    torch.cuda.synchronize()
+    gp.refresh()
+    a2, b2 = (a[0], a[1], av), (b[0], b[1], bv)
+    fp = mad_gpu.Plan.csr(tuple(to_dev(x) for x in a2),
+                          tuple(to_dev(x) for x in b2), m, n, d)
+    for x, y in zip(gp.norms(), fp.norms()):
+        assert np.array_equal(x, y)
+    for which, idx in ((0, 0), (1, 0), (1, d // 2), (2, 7), (3, 5)):
+        for x, y in zip(gp.table(which, idx), fp.table(which, idx)):
+            assert np.array_equal(x, y), (which, idx)
+    F = fp.fix_exponent(100_000)
+    assert gp.fix_exponent(100_000) == F
+    g1 = gp.samples(seed=9, l0=0, count=20_000, F=F)
+    g2 = fp.samples(seed=9, l0=0, count=20_000, F=F)
+    for key in ("k", "i", "j", "kp", "inc"):
+        assert np.array_equal(g1[key], g2[key]), key
+    r1 = gp.topk(t=20, s=100_000, t_prime=500, seed=4)
+    r2 = fp.topk(t=20, s=100_000, t_prime=500, seed=4)
+    for k in ("i", "j", "c", "x"):
+        assert np.array_equal(r1[k].cpu().numpy(), r2[k].cpu().numpy()), k
+    gp.close()
+    fp.close()
