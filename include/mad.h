@@ -57,10 +57,11 @@ enum { MAD_FP32 = 0, MAD_BF16 = 1, MAD_FP8_E4M3 = 2 };
 /* Plan flags. */
 enum {
   MAD_FLAG_NONE = 0,
-  /* skip the NaN/Inf check of the inputs; for sparse plans also the
-   * structure check after the plan's first build (the caller vouches that
-   * the arrays keep a structure that passed it).  Builds then never
-   * synchronise with the host. */
+  /* skip the NaN/Inf check of the inputs.  For sparse plans the caller
+   * also vouches that the sparsity structure (pointers and coordinates)
+   * stays the one of the plan's first build, which is checked: later
+   * builds reuse its transposes and table layouts and only regather the
+   * values.  Builds then never synchronise with the host. */
   MAD_FLAG_NO_CHECK = 1u << 0,
   MAD_FLAG_TIMING = 1u << 1,   /* record HIP events around each phase      */
   /* Gram matrix (Sec. 3.3, equal inputs): B must be A (same arrays, n = m).
@@ -110,7 +111,10 @@ int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
 
 /* Rebuild every table of `plan` from the (same-shaped) borrowed inputs,
  * e.g. after their contents changed.  No allocation; synchronises once
- * unless the plan was made with MAD_FLAG_NO_CHECK. */
+ * unless the plan was made with MAD_FLAG_NO_CHECK.  A checked sparse plan
+ * re-validates and re-transposes the inputs; an unchecked one keeps the
+ * structure of its first build (values may change, the sparsity pattern
+ * may not). */
 int mad_plan_refresh(mad_plan* plan, void* stream);
 
 /* ---------------------------------------------------------------------------
