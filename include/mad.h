@@ -353,6 +353,16 @@ int mad_debug_samples(mad_plan* plan, uint64_t seed, uint64_t qid,
                       int32_t* i, int32_t* j, int32_t* kp, int64_t* inc,
                       void* stream);
 
+/* The score accumulation alone, for tests (the pair form of Alg. 2 line
+ * "dx"): over n pairs (keys: device uint64, ~0 = none; vals: device fp32)
+ * every key's sum of rne(val * 2^F) as int64, written unordered to
+ * out_keys / out_x (device int64, capacity cap); *n_out (host) = number of
+ * distinct keys.  The inputs are not modified.  Synchronises;
+ * MAD_EOVERFLOW if cap is too small. */
+int mad_debug_accumulate(const uint64_t* keys, const float* vals, int64_t n,
+                         int F, int64_t* out_keys, int64_t* out_x,
+                         int64_t cap, int64_t* n_out, void* stream);
+
 /* Score table X of the last mad_plan_topk: every pair with a closed
  * diamond, unordered.  keys (device int64, i*n + j), xfix (device int64),
  * capacity cap; *n (host) = number of pairs; *F (host) = fixed-point

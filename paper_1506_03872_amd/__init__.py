@@ -30,7 +30,7 @@ EXPORTS = (
     "mad_bruteforce_topk", "mips_plan_create", "mips_topk_batch",
     "mips_get_config", "mips_set_config", "mips_autotune", "mips_stats",
     "mips_debug_scores", "mad_plan_set_verify_precision",
-    "mad_plan_verify_stats",
+    "mad_plan_verify_stats", "mad_debug_accumulate",
 )
 
 
@@ -70,6 +70,8 @@ def lib():
         L.mad_debug_samples.argtypes = [_P, _u64, _u64, _i64, _i64, C.c_int,
                                         _P, _P, _P, _P, _P, _P]
         L.mad_debug_scores.argtypes = [_P, _P, _P, _i64, _P, _P]
+        L.mad_debug_accumulate.argtypes = [_P, _P, _i64, C.c_int, _P, _P,
+                                           _i64, _P, _P]
         L.mad_debug_candidates.argtypes = [_P, _P, _P, _P, _i64, _P]
         L.mad_fix_exponent.argtypes = [_P, _i64, _P]
         L.mad_plan_phase_ms.argtypes = [_P, _P, C.c_int]
@@ -439,6 +441,30 @@ def bruteforce_topk(A, B, t, precision=MAD_FP32, t_screen=0, stream=None):
         C.c_void_p(n_out.data_ptr()), C.byref(st), _stream(stream)))
     stats = {f: getattr(st, f) for f, _ in BfStats._fields_}
     return unpack_pairs(out, int(n_out.item())), stats
+
+
+def debug_accumulate(keys, vals, F):
+    """The score accumulation alone: keys (CUDA uint64 as int64, -1 = none)
+    and vals (CUDA float32) -> (distinct keys, int64 sums of rne(v 2^F))
+    as numpy arrays sorted by key."""
+    import numpy as np
+    import torch
+    n = int(keys.numel())
+    assert vals.numel() == n
+    kp = _dev(keys, torch.int64, "keys") if n else None
+    vp = _dev(vals, torch.float32, "vals") if n else None
+    got = C.c_int64()
+    cap = max(n, 1)
+    ok = torch.empty(cap, dtype=torch.int64, device="cuda")
+    ox = torch.empty(cap, dtype=torch.int64, device="cuda")
+    _check(lib().mad_debug_accumulate(kp, vp, n, F,
+                                      C.c_void_p(ok.data_ptr()),
+                                      C.c_void_p(ox.data_ptr()), cap,
+                                      C.byref(got), None))
+    k = ok[:got.value].cpu().numpy()
+    x = ox[:got.value].cpu().numpy()
+    o = np.argsort(k, kind="stable")
+    return k[o], x[o]
 
 
 def probe_memory(kind, buf, nops, seed=0, stream=None):

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
   const int64_t lo = (int64_t)starts[bin];
   const int64_t hi = (int64_t)starts[bin + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int F = fix_exponent(*bmax, s_for_F);
+  const int F = bmax ? fix_exponent(*bmax, s_for_F) : (int)s_for_F;
   int64_t wpos = lo;  // next output position (uniform)
   // sub-bins: the hash bits below the bin's B bits
   int R = 1;  // sub-bins in the current split (a power of two)

@@ -666,6 +666,58 @@ int mad_debug_samples(mad_plan* p, uint64_t seed, uint64_t qid, int64_t l0,
   return MAD_OK;
 }
 
+int mad_debug_accumulate(const uint64_t* keys, const float* vals, int64_t n,
+                         int F, int64_t* out_keys, int64_t* out_x,
+                         int64_t cap, int64_t* n_out, void* stream) {
+  g_err.clear();
+  if (!n_out) return fail(MAD_EINVAL, "n_out is required");
+  if (n < 0) return fail(MAD_EINVAL, "n must be >= 0");
+  if (n && (!is_device_ptr(keys) || !is_device_ptr(vals)))
+    return fail(MAD_EINVAL, "keys and vals must be device pointers");
+  if (cap && (!is_device_ptr(out_keys) || !is_device_ptr(out_x)))
+    return fail(MAD_EINVAL, "outputs must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nn = n > 1 ? n : 1;
+  // the pairs are overwritten by the accumulation: work on copies
+  mad::DeviceBuffer buf;
+  const size_t pk = 8 * (size_t)nn, pv = (4 * (size_t)nn + 15) / 16 * 16;
+  const size_t need = pk + pv + 16 * (size_t)nn + 64 + mad::accum_bytes(nn);
+  HIP_TRY(mad::dev_alloc(buf, need), "debug accumulate");
+  char* q = (char*)buf.p;
+  uint64_t* k2 = (uint64_t*)q; q += pk;
+  float* v2 = (float*)q; q += pv;
+  uint64_t* okey = (uint64_t*)q; q += 8 * (size_t)nn;
+  int64_t* oval = (int64_t*)q; q += 8 * (size_t)nn;
+  int64_t* cnt = (int64_t*)q; q += 64;
+  hipError_t e = hipSuccess;
+  if (n) {
+    e = hipMemcpyAsync(k2, keys, 8 * (size_t)n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(v2, vals, 4 * (size_t)n, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess)
+    e = mad::launch_accumulate(k2, v2, n, nullptr, F, q,
+                               need - (size_t)(q - (char*)buf.p), okey, oval,
+                               cnt, cnt + 1, st);
+  mad::HashTable h;
+  h.keys = okey;
+  h.vals = oval;
+  h.cap = n;
+  h.live = cnt + 1;
+  if (e == hipSuccess)
+    e = mad::launch_dump_scores(h, out_keys, out_x, out_keys ? cap : 0,
+                                cnt + 2, st);
+  int64_t got = 0;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess)
+    e = hipMemcpy(&got, cnt + 2, 8, hipMemcpyDeviceToHost);
+  mad::dev_free(buf);
+  if (e != hipSuccess) return hip_fail(e, "debug accumulate");
+  *n_out = got;
+  if (out_keys && got > cap) return fail(MAD_EOVERFLOW, "capacity too small");
+  return MAD_OK;
+}
+
 int mad_debug_scores(mad_plan* p, int64_t* keys, int64_t* xfix, int64_t cap,
                      int64_t* n, int* F) {
   if (!p || !n) return fail(MAD_EINVAL, "plan and n are required");

@@ -91,7 +91,8 @@ struct HashTable {
 };
 
 // sum of the increments rne(vals[e] 2^F) per key over n pairs (key EMPTY:
-// skipped; F from *bmax and s_for_F as in the samplers) into okey / oval:
+// skipped; F from *bmax and s_for_F as in the samplers, or F = s_for_F
+// when bmax is null) into okey / oval:
 // *o_len entries (one per non-EMPTY pair) holding the *o_count distinct
 // keys and EMPTY elsewhere; work of accum_bytes(n) bytes; keys and vals are
 // overwritten
