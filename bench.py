@@ -108,7 +108,9 @@ def exact_topk_gpu(A, B, t):
     B64T = B.double().t().contiguous()
     best_v = torch.empty(0, dtype=torch.float64, device=A.device)
     best_k = torch.empty(0, dtype=torch.int64, device=A.device)
-    blk = 4096
+    # torch.topk sorts at most INT_MAX elements: rows per block so that a
+    # block holds at most 2^30 products
+    blk = max(1, min(4096, (1 << 30) // n))
     for i0 in range(0, A.shape[0], blk):
         Cb = A[i0:i0 + blk].double() @ B64T
         v, idx = torch.topk(Cb.abs().flatten(), min(t, Cb.numel()))
@@ -471,6 +473,8 @@ def main():
             pk = set((data["planted_i"] * n + data["planted_j"]).tolist())
             extra["planted_found"] = len(pk & set(keys.tolist()))
             extra["planted_total"] = len(pk)
+        extra["verify_precision"] = verify_precisions(
+            args, mad, plan, step, out, n_out, recall_of)
         if not args.no_sweep:
             extra["time_to_recall"] = time_to_recall(
                 args, mad, plan, A, B, t, tp, recall_of)
@@ -513,6 +517,41 @@ def main():
     }
     line.update(extra)
     print(json.dumps(line))
+
+
+def verify_precisions(args, mad, plan, step, out, n_out, recall_of):
+    """Whole steps under each verification precision of Alg. 3 (fp32 rows
+    for every candidate, or bf16 / fp8 screening with error bounds first):
+    ms per step, candidates re-ranked in fp32, and whether the top-t is the
+    same pair list as under fp32 verification."""
+    import numpy as np
+    import torch
+    res = {}
+    ref = None
+    for name, prec in (("fp32", mad.MAD_FP32), ("bf16", mad.MAD_BF16),
+                       ("fp8_e4m3", mad.MAD_FP8_E4M3)):
+        plan.set_verify_precision(prec)
+        step()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        got = out[:int(n_out.item())].cpu().numpy().copy()
+        vs = plan.verify_stats()
+        r = mad.unpack_pairs(out, int(n_out.item()))
+        rec, _ = recall_of(r["i"].cpu().numpy(), r["j"].cpu().numpy())
+        if ref is None:
+            ref = got
+        res[name] = {"ms_per_step": round(ms, 3), "n_cand": vs["n_cand"],
+                     "n_reranked_fp32": vs["n_reranked"], "recall_at_t": rec,
+                     "same_top_t_as_fp32": bool(np.array_equal(got, ref))}
+        log("verify %s: %.2f ms, %d of %d candidates re-ranked in fp32" %
+            (name, ms, vs["n_reranked"], vs["n_cand"]))
+    plan.set_verify_precision(mad.MAD_FP32)
+    return res
 
 
 def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, target=0.95,
