@@ -19,6 +19,8 @@
 //            next hash bits into sub-bins, each reduced on its own, so the
 //            output never holds a key twice.
 // The sums are int64 fixed point, so X is the same in any order.
+#include <stdlib.h>
+
 #include "mad_common.hpp"
 #include "plan.hpp"
 
@@ -30,7 +32,9 @@ constexpr int kAccTile = kAccThreads * kAccPer;  // count / place tile
 constexpr int kAccMaxBits = 8;            // first level: up to 256 bins
 constexpr int kAcc2MaxBits = 12;          // second level: up to 4096 sub-bins
 constexpr int kRedThreads = 256;
-constexpr int kRedSlots = 1024;           // LDS table of a reduce workgroup
+// LDS table of a reduce workgroup: 1024 slots, 4096 or 8192 when the bins
+// hold more pairs than the partition bits can bring below ~400
+constexpr int kRedSlots = 1024;
 constexpr int kRedPer = 4;                // pairs loaded per thread at once
 
 static inline unsigned acc_blocks(int64_t n, int per) {
@@ -177,14 +181,15 @@ __global__ __launch_bounds__(kAccThreads) void k_acc_place(
 // bin's keys share the top B hash bits.  The thread that claims a slot for
 // a new key stores its increment; increments of keys already present are
 // added after a barrier, so most pairs cost one LDS atomic.
+template <int SLOTS>
 __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
     const uint64_t* pk, const float* pv, const uint64_t* starts, int B,
     const float* bmax, int64_t s_for_F, uint64_t* okey, int64_t* oval,
     uint64_t* bin_distinct) {
-  constexpr int kPer = kRedSlots / kRedThreads;  // slots owned per thread
+  constexpr int kPer = SLOTS / kRedThreads;  // slots owned per thread
   constexpr int kW = kRedThreads / 64;
-  __shared__ unsigned long long sk[kRedSlots];
-  __shared__ unsigned long long sv[kRedSlots];
+  __shared__ unsigned long long sk[SLOTS];
+  __shared__ unsigned long long sv[SLOTS];
   __shared__ int full;
   __shared__ unsigned wc[kPer][kW];
   const int64_t bin = blockIdx.x;
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
   int R = 1;  // sub-bins in the current split (a power of two)
   int64_t sub = 0;
   while (hi > lo && sub < R) {
-    for (int q = threadIdx.x; q < kRedSlots; q += kRedThreads)
+    for (int q = threadIdx.x; q < SLOTS; q += kRedThreads)
       sk[q] = kEmptyKey;
     if (threadIdx.x == 0) full = 0;
     __syncthreads();
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
         if (key == kEmptyKey) continue;
         const uint64_t h = mix64(key);
         if (rb && (int64_t)((h << B) >> (64 - rb)) != sub) continue;
-        uint32_t q = (uint32_t)(h ^ (h >> 29)) & (kRedSlots - 1);
+        uint32_t q = (uint32_t)(h ^ (h >> 29)) & (SLOTS - 1);
         int probes = 0;
         while (true) {
           const unsigned long long prev =
@@ -233,11 +238,11 @@ __global__ __launch_bounds__(kRedThreads) void k_acc_reduce(
             dq[u] = (int)q;
             break;
           }
-          if (++probes == kRedSlots / 2) {  // table nearly full: split finer
+          if (++probes == SLOTS / 2) {  // table nearly full: split finer
             full = 1;
             break;
           }
-          q = (q + 1) & (kRedSlots - 1);
+          q = (q + 1) & (SLOTS - 1);
         }
       }
       __syncthreads();
@@ -497,6 +502,33 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
   }
 }
 
+// the LDS table size for bins of about `per_bin` pairs (load <= ~0.4);
+// MAD_ACC_SLOTS = 1024, 4096 or 8192 forces one (the result is the same)
+static int reduce_slots(int64_t per_bin) {
+  if (const char* e = getenv("MAD_ACC_SLOTS")) {
+    const int v = atoi(e);
+    if (v == 1024 || v == 4096 || v == 8192) return v;
+  }
+  return per_bin <= 384 ? 1024 : per_bin <= 1536 ? 4096 : 8192;
+}
+
+static void launch_reduce(int64_t per_bin, int64_t bins, const uint64_t* pk,
+                          const float* pv, const uint64_t* starts, int B,
+                          const float* bmax, int64_t s_for_F, uint64_t* okey,
+                          int64_t* oval, uint64_t* bin_distinct,
+                          hipStream_t st) {
+  const int slots = reduce_slots(per_bin);
+  if (slots == kRedSlots)
+    k_acc_reduce<kRedSlots><<<(unsigned)bins, kRedThreads, 0, st>>>(
+        pk, pv, starts, B, bmax, s_for_F, okey, oval, bin_distinct);
+  else if (slots == 4096)
+    k_acc_reduce<4096><<<(unsigned)bins, kRedThreads, 0, st>>>(
+        pk, pv, starts, B, bmax, s_for_F, okey, oval, bin_distinct);
+  else
+    k_acc_reduce<8192><<<(unsigned)bins, kRedThreads, 0, st>>>(
+        pk, pv, starts, B, bmax, s_for_F, okey, oval, bin_distinct);
+}
+
 // pairs: n (key, inc) pairs, key EMPTY for none; work: accum_bytes(n);
 // output: okey / oval, *o_len (device) entries = closed pairs holding the
 // *o_count (device) distinct keys, EMPTY elsewhere.  The pair array is
@@ -541,17 +573,15 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
   if (B2 == 0) {
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts);
-    k_acc_reduce<<<(unsigned)nb1, kRedThreads, 0, st>>>(
-        placed, placed_v, starts, B1, bmax, s_for_F, okey, oval,
-        bin_distinct);
+    launch_reduce(n >> B1, nb1, placed, placed_v, starts, B1, bmax, s_for_F,
+                  okey, oval, bin_distinct, st);
   } else {
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts1);
     k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
         placed, placed_v, starts1, B1, B2, keys, vals, starts);
-    k_acc_reduce<<<(unsigned)(nb1 << B2), kRedThreads, 0, st>>>(
-        keys, vals, starts, B1 + B2, bmax, s_for_F, okey, oval,
-        bin_distinct);
+    launch_reduce(n >> (B1 + B2), nb1 << B2, keys, vals, starts, B1 + B2,
+                  bmax, s_for_F, okey, oval, bin_distinct, st);
   }
   // entries written = closed pairs = the end of the last bin
   k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count,

@@ -5,6 +5,7 @@ paths that sampled inputs rarely do: one key taking half of the pairs,
 thousands of distinct keys in one hash bin (the reduction's LDS table
 overflows and the bin is split), no closed pair at all, one pair, negative
 and vanishing increments, and sizes with a second partition level."""
+import os
 import sys
 
 import numpy as np
@@ -116,3 +117,31 @@ def test_edge_cases(mad_gpu):
     keys = g.integers(0, 50, 5000).astype(np.int64)
     vals = g.standard_normal(5000).astype(np.float32)
     run(mad_gpu, keys, vals, 40)
+
+
+@pytest.mark.parametrize("slots", [1024, 4096, 8192])
+def test_reduce_table_sizes(mad_gpu, slots):
+    # the reduction's LDS table is sized to the bins (1024 slots; 4096 or
+    # 8192 for bins of many pairs, at s near 1e9): each size forced on
+    # random keys and on 10000 distinct keys of one bin, more than any of
+    # the tables holds below its probe limit, so every size splits the bin
+    g = np.random.default_rng(6)
+    os.environ["MAD_ACC_SLOTS"] = str(slots)
+    try:
+        say("slots", slots)
+        keys = g.integers(0, 400_000, 600_000).astype(np.int64)
+        keys[g.random(len(keys)) < 0.1] = EMPTY
+        vals = g.standard_normal(len(keys)).astype(np.float32)
+        run(mad_gpu, keys, vals, 22)
+        # n = 16384 pairs: 32 first-level bins (top 5 hash bits)
+        cand = np.unique(g.integers(0, 1 << 40, 600_000, dtype=np.int64))
+        h = mix64(cand.astype(np.uint64))
+        same = cand[(h >> np.uint64(59)) == 0][:10_000]
+        assert len(same) == 10_000
+        n = 16384
+        keys = np.concatenate([same, g.choice(same, n - len(same))])
+        g.shuffle(keys)
+        vals = g.standard_normal(n).astype(np.float32)
+        assert run(mad_gpu, keys, vals, 18) == 10_000
+    finally:
+        del os.environ["MAD_ACC_SLOTS"]
