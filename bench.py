@@ -467,6 +467,16 @@ def main():
                    B_h[keys % n].astype(np.float64)).sum(1)
             return float(np.count_nonzero(np.abs(c64) >= tau)) / t, keys
 
+        def c_error(i_arr, j_arr, c_arr):
+            """largest |c - c64| / |c64| of reported dot products"""
+            if len(i_arr) == 0:
+                return None
+            c64 = (A_h[i_arr].astype(np.float64) *
+                   B_h[j_arr].astype(np.float64)).sum(1)
+            err = np.abs(c_arr.astype(np.float64) - c64) / np.maximum(
+                np.abs(c64), 1e-300)
+            return float(err.max())
+
         rec, keys = recall_of(res["i"].cpu().numpy(), res["j"].cpu().numpy())
         extra["recall_at_t"] = rec
         if "planted_i" in data:
@@ -474,10 +484,12 @@ def main():
             extra["planted_found"] = len(pk & set(keys.tolist()))
             extra["planted_total"] = len(pk)
         extra["verify_precision"] = verify_precisions(
-            args, mad, plan, step, out, n_out, recall_of)
+            args, mad, plan, step, out, n_out, recall_of, c_error)
+        extra["bruteforce"] = bruteforce_report(mad, A, B, t, recall_of,
+                                                c_error)
         if not args.no_sweep:
             extra["time_to_recall"] = time_to_recall(
-                args, mad, plan, A, B, t, tp, recall_of)
+                args, mad, plan, A, B, t, tp, recall_of, extra["bruteforce"])
     plan.close()
     base = None
     if not args.no_cpu_baseline:
@@ -519,7 +531,8 @@ def main():
     print(json.dumps(line))
 
 
-def verify_precisions(args, mad, plan, step, out, n_out, recall_of):
+def verify_precisions(args, mad, plan, step, out, n_out, recall_of,
+                      c_error):
     """Whole steps under each verification precision of Alg. 3 (fp32 rows
     for every candidate, or bf16 / fp8 screening with error bounds first):
     ms per step, candidates re-ranked in fp32, and whether the top-t is the
@@ -542,11 +555,14 @@ def verify_precisions(args, mad, plan, step, out, n_out, recall_of):
         got = out[:int(n_out.item())].cpu().numpy().copy()
         vs = plan.verify_stats()
         r = mad.unpack_pairs(out, int(n_out.item()))
-        rec, _ = recall_of(r["i"].cpu().numpy(), r["j"].cpu().numpy())
+        i_arr, j_arr = r["i"].cpu().numpy(), r["j"].cpu().numpy()
+        rec, _ = recall_of(i_arr, j_arr)
         if ref is None:
             ref = got
         res[name] = {"ms_per_step": round(ms, 3), "n_cand": vs["n_cand"],
                      "n_reranked_fp32": vs["n_reranked"], "recall_at_t": rec,
+                     "max_rel_err_c_vs_fp64": c_error(
+                         i_arr, j_arr, r["c"].cpu().numpy()),
                      "same_top_t_as_fp32": bool(np.array_equal(got, ref))}
         log("verify %s: %.2f ms, %d of %d candidates re-ranked in fp32" %
             (name, ms, vs["n_reranked"], vs["n_cand"]))
@@ -554,12 +570,10 @@ def verify_precisions(args, mad, plan, step, out, n_out, recall_of):
     return res
 
 
-def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, target=0.95,
-                   seeds=5):
-    """Median wall time of whole steps (tables + sampling + Alg. 3) to reach
-    mean threshold-recall@t >= target over `seeds` seeds, s on a x sqrt(10)
-    grid, against the MFMA brute force (median of 5).  The sweep stops when
-    a step takes 10x the fp32 brute force."""
+def bruteforce_report(mad, A, B, t, recall_of, c_error):
+    """The MFMA brute force of the same top-t in each precision (median of
+    5 runs): ms, recall@t, candidates re-ranked in fp32, and the largest
+    relative error of its reported c against FP64."""
     import numpy as np
     import torch
     bf = {}
@@ -575,10 +589,24 @@ def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, target=0.95,
                                           t_screen=ts)
             torch.cuda.synchronize()
             times.append((time.perf_counter() - t0) * 1e3)
-        rec, _ = recall_of(res["i"].cpu().numpy(), res["j"].cpu().numpy())
+        i_arr, j_arr = res["i"].cpu().numpy(), res["j"].cpu().numpy()
+        rec, _ = recall_of(i_arr, j_arr)
         bf[name] = {"ms": round(float(np.median(times)), 3),
-                    "recall": rec, "candidates": st["candidates"]}
+                    "recall": rec, "candidates": st["candidates"],
+                    "max_rel_err_c_vs_fp64": c_error(
+                        i_arr, j_arr, res["c"].cpu().numpy())}
         log("brute force %s: %.2f ms recall %.3f" % (name, bf[name]["ms"], rec))
+    return bf
+
+
+def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, bf,
+                   target=0.95, seeds=5):
+    """Median wall time of whole steps (tables + sampling + Alg. 3) to reach
+    mean threshold-recall@t >= target over `seeds` seeds, s on a x sqrt(10)
+    grid, against the MFMA brute force (median of 5).  The sweep stops when
+    a step takes 10x the fp32 brute force."""
+    import numpy as np
+    import torch
     limit = 10 * bf["fp32"]["ms"]
     out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
     n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -621,7 +649,7 @@ def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, target=0.95,
                                        if reached else None),
             "best_recall": best["recall_mean"], "best_s": best["s"],
             "stop_rule": "step time > 10x fp32 brute force (%.1f ms)" % limit,
-            "bruteforce": bf, "sweep": sweep}
+            "sweep": sweep}
 
 
 if __name__ == "__main__":
