@@ -93,7 +93,9 @@ __global__ __launch_bounds__(256) void k_prep(const float* X, int64_t rows,
   if (P == kFP8) {
     int e = 0;
     if (mx > 0.0f) (void)frexpf(mx, &e);  // mx < 2^e
-    scale = ldexpf(1.0f, 7 - e);          // scaled max < 2^7
+    // scaled max < 2^7; 1 / scale stays a normal float (an E8M0 exponent)
+    if (e < -119) e = -119;
+    scale = ldexpf(1.0f, 7 - e);
     eta = ldexpf(1.0f, -10) / scale;      // half the e4m3 subnormal step
   } else if (P == kBF16) {
     eta = ldexpf(1.0f, -134);
@@ -148,7 +150,8 @@ struct GemmArgs {
 template <int P>
 __device__ __forceinline__ void mfma_step(const char* la, const char* lb,
                                           int koff_bytes, f16v (&acc)[2][2],
-                                          int lane) {
+                                          int lane, const int (&sa)[2],
+                                          const int (&sb)[2]) {
   const int r = lane & 31, g = lane >> 5;
   if (P == kF32) {
     float a[2], b[2];
@@ -197,7 +200,7 @@ __device__ __forceinline__ void mfma_step(const char* la, const char* lb,
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj)
         acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            a[bi], b[bj], acc[bi][bj], 0, 0, 0, 0x7f7f7f7f, 0, 0x7f7f7f7f);
+            a[bi], b[bj], acc[bi][bj], 0, 0, 0, sa[bi], 0, sb[bj]);
   }
 }
 
@@ -207,11 +210,34 @@ __device__ __forceinline__ int fbin32(uint32_t bits) {
   return (int)(bits >> 20) & 2047;
 }
 
+// E8M0 byte of a vector's power-of-two inverse scale (the MFMA multiplies
+// the products of a lane's 32-element K block by 2^(byte - 127) per operand)
+__device__ __forceinline__ int e8m0_of(float inv_s) {
+  return (int)((__float_as_uint(inv_s) >> 23) & 0xff);
+}
+
+// Tiles of 128 x 128 in bands of 8 row-tiles; within a band the column
+// tiles advance.  Workgroups are dispatched to the 8 XCDs round robin, so
+// virtual block v = (blockIdx mod 8) G/8 + blockIdx / 8 gives each XCD a
+// contiguous run of G/8 tiles per sweep: a column tile (a slice of B) is
+// read by one XCD per band instead of by all eight.  K runs in stages of
+// 128-byte row slices through two LDS buffers: the next stage (or the next
+// tile's first) is loaded into registers while the current one computes.
+__device__ __forceinline__ void gemm_coords(int64_t tile, int64_t tiles_m,
+                                            int64_t tiles_n, int64_t& i0,
+                                            int64_t& j0) {
+  const int64_t band = tile / (8 * tiles_n);
+  const int64_t within = tile % (8 * tiles_n);
+  const int64_t band_rows = tiles_m - band * 8 < 8 ? tiles_m - band * 8 : 8;
+  i0 = (band * 8 + within % band_rows) * kBM;
+  j0 = (within / band_rows) * kBN;
+}
+
 template <int P, bool HIST>
 __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
   using PT = PrecT<P>;
-  __shared__ __attribute__((aligned(16))) char lds_a[kBM * kLdsStride];
-  __shared__ __attribute__((aligned(16))) char lds_b[kBN * kLdsStride];
+  __shared__ __attribute__((aligned(16))) char lds_a[2][kBM * kLdsStride];
+  __shared__ __attribute__((aligned(16))) char lds_b[2][kBN * kLdsStride];
   __shared__ unsigned hist[HIST ? 2048 : 1];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int wr = wv >> 1, wc = wv & 1;
@@ -223,18 +249,66 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
   const int64_t tiles_n = (g.n + kBN - 1) / kBN;
   const int64_t ntiles = tiles_m * tiles_n;
   const int64_t row_bytes = g.Kp * PT::EB;
+  const int64_t nst = row_bytes / kRowBytes;  // Kp EB is a multiple of 128
   const char* Ab = (const char*)g.A;
   const char* Bb = (const char*)g.B;
   const float tau = HIST ? 0.0f : __uint_as_float(*g.tau_bits);
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    // tiles in column bands of 8 row-tiles, so that concurrently running
-    // workgroups share B slices
-    const int64_t band = tile / (8 * tiles_n);
-    const int64_t within = tile % (8 * tiles_n);
-    const int64_t band_rows = tiles_m - band * 8 < 8 ? tiles_m - band * 8 : 8;
-    const int64_t tm = band * 8 + within % band_rows;
-    const int64_t tn = within / band_rows;
-    const int64_t i0 = tm * kBM, j0 = tn * kBN;
+  const int64_t G = gridDim.x;  // a multiple of 8
+  const int64_t v = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  // this thread's 4 x 16 bytes of each operand's stage: rows (t >> 3) +
+  // 32 q, bytes (t & 7) 16 of the 128-byte slice
+  const int seg = (t & 7) * 16;
+// one 16-byte piece q of each operand's stage (rows (t >> 3) + 32 q), and
+// its store to LDS; written out per q so that ra / rb stay in registers
+#define MAD_BF_GLOAD1(Q, I0, J0, KB)                                         \
+  {                                                                          \
+    const int row = (t >> 3) + 32 * (Q);                                     \
+    int64_t ia = (I0) + row;                                                 \
+    ia = ia < g.m_rows ? ia : g.m_rows - 1;                                  \
+    int64_t jb = (J0) + row;                                                 \
+    jb = jb < g.n ? jb : g.n - 1;                                            \
+    ra##Q = *(const uint4*)(Ab + ia * g.a_stride_rows * row_bytes + (KB) +   \
+                            seg);                                            \
+    rb##Q = *(const uint4*)(Bb + jb * row_bytes + (KB) + seg);               \
+  }
+#define MAD_BF_GLOAD(I0, J0, KB)                                             \
+  MAD_BF_GLOAD1(0, I0, J0, KB) MAD_BF_GLOAD1(1, I0, J0, KB)                  \
+  MAD_BF_GLOAD1(2, I0, J0, KB) MAD_BF_GLOAD1(3, I0, J0, KB)
+#define MAD_BF_LSTORE1(Q, BUF)                                               \
+  {                                                                          \
+    const int row = (t >> 3) + 32 * (Q);                                     \
+    *(uint4*)(lds_a[BUF] + row * kLdsStride + seg) = ra##Q;                  \
+    *(uint4*)(lds_b[BUF] + row * kLdsStride + seg) = rb##Q;                  \
+  }
+#define MAD_BF_LSTORE(BUF)                                                   \
+  MAD_BF_LSTORE1(0, BUF) MAD_BF_LSTORE1(1, BUF) MAD_BF_LSTORE1(2, BUF)       \
+  MAD_BF_LSTORE1(3, BUF)
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  int64_t tile = v;
+  int64_t i0 = 0, j0 = 0;
+  if (tile < ntiles) {
+    gemm_coords(tile, tiles_m, tiles_n, i0, j0);
+    MAD_BF_GLOAD(i0, j0, 0)
+  }
+  while (tile < ntiles) {
+    const int64_t next = tile + G;
+    int64_t ni0 = 0, nj0 = 0;
+    if (next < ntiles) gemm_coords(next, tiles_m, tiles_n, ni0, nj0);
+    // fp8: the per-vector scales of the rows this lane feeds the MFMA
+    int sa[2] = {127, 127}, sb[2] = {127, 127};
+    if (P == kFP8) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        int64_t ia = i0 + wr * 64 + u * 32 + (lane & 31);
+        ia = ia < g.m_rows ? ia : g.m_rows - 1;
+        int64_t jb = j0 + wc * 64 + u * 32 + (lane & 31);
+        jb = jb < g.n ? jb : g.n - 1;
+        sa[u] = e8m0_of(g.ia[ia * g.a_stride_rows].inv_s);
+        sb[u] = e8m0_of(g.ib[jb].inv_s);
+      }
+    }
+    MAD_BF_LSTORE(0)
+    __syncthreads();
     f16v acc[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -242,35 +316,46 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
       for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[bi][bj][e] = 0.0f;
-    for (int64_t kb = 0; kb < row_bytes; kb += kRowBytes) {
-      // 128 rows x 128 bytes per operand: 4 x 16 B per thread
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = (t >> 3) + 32 * q;
-        const int seg = (t & 7) * 16;
-        int64_t ia = i0 + row;
-        ia = ia < g.m_rows ? ia : g.m_rows - 1;
-        int64_t jb = j0 + row;
-        jb = jb < g.n ? jb : g.n - 1;
-        const uint4 va = *(const uint4*)(Ab + ia * g.a_stride_rows * row_bytes +
-                                         kb + seg);
-        const uint4 vb = *(const uint4*)(Bb + jb * row_bytes + kb + seg);
-        *(uint4*)(lds_a + row * kLdsStride + seg) = va;
-        *(uint4*)(lds_b + row * kLdsStride + seg) = vb;
-      }
-      __syncthreads();
-      const char* la = lds_a + (wr * 64) * kLdsStride;
-      const char* lb = lds_b + (wc * 64) * kLdsStride;
+    int cur = 0;
+    for (int64_t st = 0; st < nst; ++st) {
+      // the next stage, else the next tile's first, else (last tile) a
+      // harmless reload of this tile's first: unconditional loads keep
+      // ra / rb in registers
+      const bool more = st + 1 < nst;
+      const int64_t li0 = more ? i0 : (next < ntiles ? ni0 : i0);
+      const int64_t lj0 = more ? j0 : (next < ntiles ? nj0 : j0);
+      const int64_t lkb = more ? (st + 1) * kRowBytes : 0;
+      MAD_BF_GLOAD(li0, lj0, lkb)
+      const char* la = lds_a[cur] + (wr * 64) * kLdsStride;
+      const char* lb = lds_b[cur] + (wc * 64) * kLdsStride;
 #pragma unroll
       for (int ks = 0; ks < PT::KC / PT::KS; ++ks)
-        mfma_step<P>(la, lb, ks * PT::KS * PT::EB, acc, lane);
+        mfma_step<P>(la, lb, ks * PT::KS * PT::EB, acc, lane, sa, sb);
+      if (more) {
+        MAD_BF_LSTORE(cur ^ 1)
+      }
+      __syncthreads();
+      cur ^= 1;
     }
     // epilogue.  Pass B: |c| + margin >= tau only when |c| >= tau - mg_max,
     // which almost no pair meets; those few compute the exact margin.
     const int cl = lane & 31, rg = lane >> 5;
     // tau (1 - 2^-20) - mg_max absorbs the roundings of both comparisons
     const float pre = HIST ? 0.0f : fmaf(tau, 1.0f - 0x1p-20f, -g.mg_max);
+    // pass B: one max over the lane's 64 values first; the per-element
+    // work below runs only in waves where some lane passes
+    bool any = true;
+    if (!HIST) {
+      float mx = 0.0f;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) mx = fmaxf(mx, fabsf(acc[bi][bj][e]));
+      any = mx >= pre;
+    }
+    if (any) {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int64_t j = j0 + wc * 64 + bj * 32 + cl;
@@ -281,11 +366,7 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
         for (int e = 0; e < 16; ++e) {
           const int64_t i = i0 + wr * 64 + bi * 32 + 8 * (e >> 2) + 4 * rg +
                             (e & 3);
-          float c = acc[bi][bj][e];
-          if (P == kFP8) {
-            if (!(jok && i < g.m_rows)) continue;
-            c *= g.ia[i * g.a_stride_rows].inv_s * g.ib[j].inv_s;
-          }
+          const float c = acc[bi][bj][e];
           if (!HIST && !(fabsf(c) >= pre)) continue;
           if (!(jok && i < g.m_rows)) continue;
           const VecInfo va = g.ia[i * g.a_stride_rows];
@@ -308,6 +389,10 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
         }
       }
     }
+    }
+    tile = next;
+    i0 = ni0;
+    j0 = nj0;
   }
   if (HIST) {
     __syncthreads();
@@ -315,6 +400,10 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
       if (hist[b]) atomicAdd(&g.hist[b], hist[b]);
   }
 }
+#undef MAD_BF_GLOAD1
+#undef MAD_BF_GLOAD
+#undef MAD_BF_LSTORE1
+#undef MAD_BF_LSTORE
 
 // maxima of n2, n1 and eta over the vectors (float bits, atomically)
 __global__ void k_vecinfo_max(const VecInfo* v, int64_t rows, unsigned* mx) {
@@ -372,9 +461,16 @@ static double gamma_d(int64_t d) {
 
 template <int P>
 static void launch_gemm(const GemmArgs& a, bool hist, hipStream_t st) {
+  // persistent workgroups, two per CU (LDS), a multiple of 8 (one share
+  // per XCD); MAD_BF_GRID overrides the count (the result is the same)
   const int64_t tiles = ((a.m_rows + kBM - 1) / kBM) * ((a.n + kBN - 1) / kBN);
-  int64_t grid = tiles < 256 * 8 ? tiles : 256 * 8;
-  if (grid < 1) grid = 1;
+  int64_t grid = tiles < 256 * 2 ? (tiles + 7) / 8 * 8 : 256 * 2;
+  if (const char* ev = getenv("MAD_BF_GRID")) {
+    const int64_t gv = atoll(ev) / 8 * 8;
+    if (gv >= 8) grid = gv;
+  }
+  if (grid < 8) grid = 8;
+
   if (hist) k_gemm_topk<P, true><<<(unsigned)grid, 256, 0, st>>>(a);
   else k_gemm_topk<P, false><<<(unsigned)grid, 256, 0, st>>>(a);
 }
