@@ -101,6 +101,10 @@ def memory_ceilings(mad, footprint_words=1 << 26, nops=1 << 26, reps=3):
     return out
 
 
+# dense MFMA peaks of MI355X (TFLOP/s), no sparsity
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+
 def exact_topk_gpu(A, B, t):
     """Exhaustive top-t by |c| (FP64 products on the GPU, row blocks)."""
     import torch
@@ -591,7 +595,17 @@ def bruteforce_report(mad, A, B, t, recall_of, c_error):
             times.append((time.perf_counter() - t0) * 1e3)
         i_arr, j_arr = res["i"].cpu().numpy(), res["j"].cpu().numpy()
         rec, _ = recall_of(i_arr, j_arr)
-        bf[name] = {"ms": round(float(np.median(times)), 3),
+        ms = float(np.median(times))
+        # algorithmic 2 m n d flops against the dense MFMA peak of the
+        # precision the GEMM runs in
+        tflops = 2.0 * A.shape[0] * B.shape[0] * A.shape[1] / (ms * 1e-3) / 1e12
+        peak = {"fp32": MFMA_PEAK_TFLOPS["fp32"],
+                "bf16": MFMA_PEAK_TFLOPS["bf16"],
+                "bf16_screen": MFMA_PEAK_TFLOPS["bf16"],
+                "fp8_screen": MFMA_PEAK_TFLOPS["fp8"]}[name]
+        bf[name] = {"ms": round(ms, 3),
+                    "tflops": round(tflops, 1),
+                    "mfma_frac": round(tflops / peak, 4),
                     "recall": rec, "candidates": st["candidates"],
                     "max_rel_err_c_vs_fp64": c_error(
                         i_arr, j_arr, res["c"].cpu().numpy())}

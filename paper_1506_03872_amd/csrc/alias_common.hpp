@@ -30,10 +30,13 @@ __device__ void wave_alias(const uint64_t (&qv)[SPL], const uint32_t (&sg)[SPL],
       else { ++nh; se += qv[s] - kCap; }
     }
   }
-  const uint32_t nl_in = wave_incl_scan(nl), nh_in = wave_incl_scan(nh);
+  // light and heavy counts share one scan (each total is at most 2^L <=
+  // 512, so 16 bits apiece)
+  const uint32_t c_in = wave_incl_scan(nl | (nh << 16));
   const uint64_t sd_in = wave_incl_scan(sd), se_in = wave_incl_scan(se);
-  const uint32_t NL = __shfl(nl_in, 63, 64), NH = __shfl(nh_in, 63, 64);
-  uint32_t lp = nl_in - nl, hp = nh_in - nh;
+  const uint32_t c_all = __shfl(c_in, 63, 64);
+  const uint32_t NL = c_all & 0xFFFFu, NH = c_all >> 16;
+  uint32_t lp = (c_in & 0xFFFFu) - nl, hp = (c_in >> 16) - nh;
   uint64_t da = sd_in - sd, ea = se_in - se;
   uint32_t mypos[SPL];
 #pragma unroll
@@ -54,33 +57,34 @@ __device__ void wave_alias(const uint64_t (&qv)[SPL], const uint32_t (&sg)[SPL],
     }
   }
   __syncthreads();
+  // Each slot searches the other list once, with the same branch-free
+  // lower bound (a uniform loop of L + 1 halving steps): a light the first
+  // heavy whose inclusive excess reaches its exclusive deficit Dx, i.e.
+  // the count of heavies with He < Dx; a heavy the first light whose
+  // inclusive deficit exceeds its excess Eh, i.e. the count of lights with
+  // Ld < Eh + 1.
 #pragma unroll
   for (int s = 0; s < SPL; ++s) {
     const int r = lane * SPL + s;
-    if (!(active && r < Np)) continue;
-    if (qv[s] < kCap) {
-      const uint64_t Dx = Ld[mypos[s]] - (kCap - qv[s]);
-      uint32_t lo = 0, hi = NH;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (He[mid] >= Dx) hi = mid; else lo = mid + 1;
-      }
+    const bool ok = active && r < Np;
+    const bool light = qv[s] < kCap;
+    const uint64_t own = ok ? (light ? Ld[mypos[s]] : He[mypos[s]]) : 0ull;
+    const uint64_t key = light ? own - (kCap - qv[s]) : own + 1;
+    const uint64_t* lst = light ? He : Ld;
+    const uint32_t n = ok ? (light ? NH : NL) : 0u;
+    uint32_t lo = 0;
+    for (uint32_t step = (uint32_t)Np; step > 0; step >>= 1)
+      if (lo + step <= n && lst[lo + step - 1] < key) lo += step;
+    if (!ok) continue;
+    if (light) {
       const uint32_t a = NH ? Hi[lo < NH ? lo : NH - 1]
                             : (uint32_t)r | (sg[s] << 31);
       emit(r, (uint32_t)qv[s], sg[s], a & kLow31, a >> 31);
+    } else if (lo < NL && mypos[s] + 1 < NH) {
+      const uint32_t a = Hi[mypos[s] + 1];
+      emit(r, (uint32_t)(own + kCap - Ld[lo]), sg[s], a & kLow31, a >> 31);
     } else {
-      const uint64_t Eh = He[mypos[s]];
-      uint32_t lo = 0, hi = NL;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (Ld[mid] > Eh) hi = mid; else lo = mid + 1;
-      }
-      if (lo < NL && mypos[s] + 1 < NH) {
-        const uint32_t a = Hi[mypos[s] + 1];
-        emit(r, (uint32_t)(Eh + kCap - Ld[lo]), sg[s], a & kLow31, a >> 31);
-      } else {
-        emit(r, 0u, sg[s], (uint32_t)r, sg[s]);
-      }
+      emit(r, 0u, sg[s], (uint32_t)r, sg[s]);
     }
   }
 }

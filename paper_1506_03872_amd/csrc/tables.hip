@@ -326,12 +326,29 @@ __global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
     const int64_t chunk = blockIdx.x;
     const int64_t seg0 = chunk * TB;
     // ---- phase 1 -----------------------------------------------------------
-    // the block's weights and sign bits, all loads in flight together
+    // the block's weights and sign bits, kLoadPer loads per thread in
+    // flight together
+    constexpr int kLoadPer = 4;
     const int ntab = S - seg0 < TB ? (int)(S - seg0) : TB;
-    for (int i = threadIdx.x; i < ntab * (int)N; i += 256) {
-      const int tb = i / (int)N, r = i - tb * (int)N;
-      lb[tb * ld + r] = (uint64_t)__double_as_longlong(w(seg0 + tb, r)) |
-                        ((uint64_t)w.sgn(seg0 + tb, r) << 63);
+    const int total = ntab * (int)N;
+    for (int i0 = threadIdx.x; i0 < total; i0 += 256 * kLoadPer) {
+      double wv[kLoadPer];
+      uint32_t sv[kLoadPer];
+      int at[kLoadPer];
+#pragma unroll
+      for (int u = 0; u < kLoadPer; ++u) {
+        const int i = i0 + u * 256;
+        const int ic = i < total ? i : total - 1;
+        const int tb = ic / (int)N, r = ic - tb * (int)N;
+        wv[u] = w(seg0 + tb, r);
+        sv[u] = w.sgn(seg0 + tb, r);
+        at[u] = i < total ? tb * ld + r : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadPer; ++u)
+        if (at[u] >= 0)
+          lb[at[u]] = (uint64_t)__double_as_longlong(wv[u]) |
+                      ((uint64_t)sv[u] << 63);
     }
     __syncthreads();
     if (wv == 0 && lane < ntab) {
@@ -1098,7 +1115,15 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
         A, m * d, nullptr, t.bad);
 
   // the B side forks from here (after the clears above)
-  if (B && (e = hipEventRecord(t.fork, st)) != hipSuccess) return e;
+  // MAD_TABLES_ONE_STREAM=1 keeps the B side on the caller's stream (the
+  // tables are the same; for timing the kernels apart)
+  static const bool one_stream = [] {
+    const char* v = getenv("MAD_TABLES_ONE_STREAM");
+    return v && atoi(v) != 0;
+  }();
+  hipStream_t sd = one_stream ? st : t.side;
+  if (B && !one_stream && (e = hipEventRecord(t.fork, st)) != hipSuccess)
+    return e;
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
   // (enqueued before the B side so that this stream has work at once)
   if (t.T3.L <= 9) {
@@ -1113,16 +1138,18 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   // B side on the side stream: max |b| (and the finiteness check), then
   // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
   if (B) {
-    if ((e = hipStreamWaitEvent(t.side, t.fork, 0)) != hipSuccess) return e;
+    if (!one_stream && (e = hipStreamWaitEvent(sd, t.fork, 0)) != hipSuccess)
+      return e;
     k_scan_inputs<<<grid_for(n * d, 1024 * 16) > 256 ? 256
-                        : grid_for(n * d, 1024 * 16), 1024, 0, t.side>>>(
+                        : grid_for(n * d, 1024 * 16), 1024, 0, sd>>>(
         B, n * d, t.bmax, t.bad);
     e = t.T2.L <= 9
             ? small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,
-                           t.T2.ent, t.side)
+                           t.T2.ent, sd)
             : col_tables(B, d, nullptr, d, n, t.T2.L, t.T2, side_scratch,
-                         need_side, t.side);
-    const hipError_t ej = hipEventRecord(t.join, t.side);
+                         need_side, sd);
+    const hipError_t ej =
+        one_stream ? hipSuccess : hipEventRecord(t.join, sd);
     if (e == hipSuccess) e = ej;
     if (e != hipSuccess) return e;
   }
@@ -1135,7 +1162,7 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
             : col_tables(A, d, t.na, d, m, t.T1.L, t.T1, scratch_buf.p,
                          need, st);
   // the B side joins here; without B (MIPS) only the A side is built
-  if (B) {
+  if (B && !one_stream) {
     const hipError_t ew = hipStreamWaitEvent(st, t.join, 0);
     if (e == hipSuccess) e = ew;
   }
