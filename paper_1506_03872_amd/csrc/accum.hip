@@ -42,11 +42,23 @@ static inline unsigned acc_blocks(int64_t n, int per) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// pairs per final bin aimed at (MAD_ACC_TARGET overrides it: 256 .. 4096,
+// read once; the result does not depend on it)
+static int64_t acc_target() {
+  static const int64_t v = [] {
+    const char* e = getenv("MAD_ACC_TARGET");
+    const long x = e ? atol(e) : 512;
+    return (int64_t)(x >= 256 && x <= 4096 ? x : 512);
+  }();
+  return v;
+}
+
 // bits of the bin index: B1 for the global partition, B2 for the second
-// partition inside each first-level bin, so that bins hold ~512 pairs
+// partition inside each first-level bin, so that bins hold about
+// acc_target() pairs
 static int acc_total_bits(int64_t s) {
   int b = 0;
-  while (b < kAccMaxBits + kAcc2MaxBits && (int64_t(512) << b) < s) ++b;
+  while (b < kAccMaxBits + kAcc2MaxBits && (acc_target() << b) < s) ++b;
   return b;
 }
 

@@ -112,3 +112,26 @@ def test_screening_mode_recall(mad_gpu, prec):
     scale = (np.abs(A[got // n].astype(np.float64)) *
              np.abs(B[got % n].astype(np.float64))).sum(1)
     assert np.all(np.abs(res["c"].cpu().numpy() - c64) <= TOL * scale)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_vector_scales(mad_gpu, prec):
+    # rows of very different magnitude (fp8 takes a power-of-two scale per
+    # vector, applied inside the MFMA), zero rows, and a d that is not a
+    # multiple of the K chunk: the certified low-precision result must be
+    # the fp32 one
+    g = np.random.default_rng(11)
+    m, n, d, t = 700, 900, 70, 40
+    A = g.standard_normal((m, d)).astype(np.float32)
+    B = g.standard_normal((n, d)).astype(np.float32)
+    A *= (10.0 ** g.integers(-30, 4, size=(m, 1))).astype(np.float32)
+    B *= (10.0 ** g.integers(-3, 3, size=(n, 1))).astype(np.float32)
+    A[5] = 0.0
+    B[7] = 0.0
+    a, b = to_dev(A), to_dev(B)
+    r32, _ = mad_gpu.bruteforce_topk(a, b, t, precision=0)
+    rlo, st = mad_gpu.bruteforce_topk(a, b, t, precision=prec)
+    print("stats", prec, st, flush=True)
+    assert np.array_equal(keys_of(rlo, n), keys_of(r32, n))
+    assert np.array_equal(rlo["c"].cpu().numpy(), r32["c"].cpu().numpy())
+    check_against_exact(A, B, r32, t)
