@@ -356,7 +356,79 @@ def bench_csr(args, cfg, data, mad):
         "cpu_baseline": None,
     }
     plan.close()
+    if not args.no_recall:
+        line["recall_reduced_size"] = csr_recall(args, cfg, mad)
     print(json.dumps(line))
+
+
+def csr_recall(args, cfg, mad, scale=0.02):
+    """Threshold-recall@t of the sparse path on the same distributions at
+    2% of the vector counts (d unchanged), where the exact top t is one FP64
+    GEMM of the densified inputs on the GPU: s on a x10 grid, t' = t'(cfg)
+    capped at the positive pairs."""
+    import numpy as np
+    import torch
+    import workloads
+    _, data = workloads.make(args.config, seed=args.seed, scale=scale)
+    a, b, m, n = data["a"], data["b"], data["m"], data["n"]
+    d, t = cfg["d"], cfg["t"]
+    log("sparse recall at m = n = %d: exact top-%d" % (m, t))
+
+    def dense64(x, rows):
+        ptr, idx, val = x
+        M = torch.zeros((rows, d), dtype=torch.float64, device="cuda")
+        r = torch.repeat_interleave(torch.arange(rows, device="cuda"),
+                                    torch.from_numpy(np.diff(ptr)).cuda())
+        M[r, torch.from_numpy(idx.astype(np.int64)).cuda()] = \
+            torch.from_numpy(val).cuda().double()
+        return M
+
+    Ad, Bd = dense64(a, m), dense64(b, n)
+    Cm = (Ad @ Bd.t()).abs_().flatten()
+    tau = float(torch.topk(Cm, t).values[-1])
+    del Ad, Bd, Cm
+    torch.cuda.empty_cache()
+
+    def c_exact(i, j):
+        ap, ai, av = a
+        bp, bi, bv = b
+        out = np.empty(len(i))
+        for q, (x, y) in enumerate(zip(i.tolist(), j.tolist())):
+            ia, va = ai[ap[x]:ap[x + 1]], av[ap[x]:ap[x + 1]]
+            ib, vb = bi[bp[y]:bp[y + 1]], bv[bp[y]:bp[y + 1]]
+            _, xa, xb = np.intersect1d(ia, ib, return_indices=True)
+            out[q] = float(np.dot(va[xa].astype(np.float64),
+                                  vb[xb].astype(np.float64)))
+        return out
+
+    ta = tuple(torch.from_numpy(x).cuda() for x in a)
+    tb = tuple(torch.from_numpy(x).cuda() for x in b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = mad.Plan.csr(ta, tb, m, n, d)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    res = []
+    for s in (10 ** 5, 316_228, 10 ** 6, 3_162_278, 10 ** 7, 31_622_777,
+              10 ** 8):
+        plan.topk(t=t, s=s, t_prime=cfg["t_prime"], seed=args.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.topk(t=t, s=s, t_prime=cfg["t_prime"], seed=args.seed)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        i_arr, j_arr = r["i"].cpu().numpy(), r["j"].cpu().numpy()
+        c64 = c_exact(i_arr, j_arr)
+        rec = float(np.count_nonzero(np.abs(c64) >= tau)) / t
+        res.append({"s": s, "recall_at_t": rec, "returned": int(len(i_arr)),
+                    "ms_topk": round(ms, 3)})
+        log("sparse recall s=%d: %.3f (%.2f ms)" % (s, rec, ms))
+    plan.close()
+    return {"m": m, "n": n, "d": d, "t": t, "t_prime": cfg["t_prime"],
+            "tau": tau, "seed": args.seed,
+            "plan_build_ms": round(build_ms, 2),
+            "exact": "FP64 GEMM of the densified inputs (GPU)",
+            "sweep": res}
 
 
 def main():
