@@ -147,61 +147,48 @@ struct GemmArgs {
   unsigned long long* ccount;
 };
 
+// the MFMA operands of one K step: rows (l mod 32) of the wave's two
+// 32-row blocks of A and of B, K group l / 32
+template <int P> struct Frag;
+template <> struct Frag<kF32> { typedef float T; T a[2], b[2]; };
+template <> struct Frag<kBF16> { typedef bf8v T; T a[2], b[2]; };
+template <> struct Frag<kFP8> { typedef i8v T; T a[2], b[2]; };
+
 template <int P>
-__device__ __forceinline__ void mfma_step(const char* la, const char* lb,
-                                          int koff_bytes, f16v (&acc)[2][2],
-                                          int lane, const int (&sa)[2],
-                                          const int (&sb)[2]) {
+__device__ __forceinline__ void frag_load(const char* la, const char* lb,
+                                          int koff_bytes, int lane,
+                                          Frag<P>& f) {
   const int r = lane & 31, g = lane >> 5;
-  if (P == kF32) {
-    float a[2], b[2];
+  using PT = PrecT<P>;
+  constexpr int gb = PT::KS / 2 * PT::EB;  // bytes of one K group
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-      a[bi] = *(const float*)(la + (bi * 32 + r) * kLdsStride + koff_bytes +
-                              g * 4);
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-      b[bj] = *(const float*)(lb + (bj * 32 + r) * kLdsStride + koff_bytes +
-                              g * 4);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi], b[bj],
-                                                          acc[bi][bj], 0, 0, 0);
-  } else if (P == kBF16) {
-    bf8v a[2], b[2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-      a[bi] = *(const bf8v*)(la + (bi * 32 + r) * kLdsStride + koff_bytes +
-                             g * 16);
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-      b[bj] = *(const bf8v*)(lb + (bj * 32 + r) * kLdsStride + koff_bytes +
-                             g * 16);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-  } else {
-    i8v a[2], b[2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-      a[bi] = *(const i8v*)(la + (bi * 32 + r) * kLdsStride + koff_bytes +
-                            g * 32);
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-      b[bj] = *(const i8v*)(lb + (bj * 32 + r) * kLdsStride + koff_bytes +
-                            g * 32);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            a[bi], b[bj], acc[bi][bj], 0, 0, 0, sa[bi], 0, sb[bj]);
+  for (int u = 0; u < 2; ++u) {
+    typedef typename Frag<P>::T T;
+    f.a[u] = *(const T*)(la + (u * 32 + r) * kLdsStride + koff_bytes +
+                         g * gb);
+    f.b[u] = *(const T*)(lb + (u * 32 + r) * kLdsStride + koff_bytes +
+                         g * gb);
   }
+}
+
+template <int P>
+__device__ __forceinline__ void frag_mma(const Frag<P>& f, f16v (&acc)[2][2],
+                                         const int (&sa)[2],
+                                         const int (&sb)[2]) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      if constexpr (P == kF32)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+            f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0);
+      else if constexpr (P == kBF16)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0);
+      else
+        acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+            f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0, sa[bi], 0, sb[bj]);
+    }
 }
 
 // monotone 11-bit digit of a non-negative float (exponent and the top 3
@@ -328,9 +315,18 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
       MAD_BF_GLOAD(li0, lj0, lkb)
       const char* la = lds_a[cur] + (wr * 64) * kLdsStride;
       const char* lb = lds_b[cur] + (wc * 64) * kLdsStride;
+      // the next K step's operands are read from LDS while the current
+      // step's MFMAs run
+      constexpr int nks = PT::KC / PT::KS;
+      Frag<P> fr[2];
+      frag_load<P>(la, lb, 0, lane, fr[0]);
 #pragma unroll
-      for (int ks = 0; ks < PT::KC / PT::KS; ++ks)
-        mfma_step<P>(la, lb, ks * PT::KS * PT::EB, acc, lane, sa, sb);
+      for (int ks = 0; ks < nks; ++ks) {
+        if (ks + 1 < nks)
+          frag_load<P>(la, lb, (ks + 1) * PT::KS * PT::EB, lane,
+                       fr[(ks + 1) & 1]);
+        frag_mma<P>(fr[ks & 1], acc, sa, sb);
+      }
       if (more) {
         MAD_BF_LSTORE(cur ^ 1)
       }
