@@ -720,6 +720,7 @@ static hipError_t build_alias(const uint64_t* q, const double* tot, int64_t S,
 // so they carry no branch)
 constexpr int kColGroup = 32;
 
+template <bool SCALE>
 __global__ __launch_bounds__(64) void k_col_runtot(const float* X, int64_t d,
                                                    const double* scale,
                                                    int64_t S, int64_t N,
@@ -738,16 +739,17 @@ __global__ __launch_bounds__(64) void k_col_runtot(const float* X, int64_t d,
     for (int u = 0; u < kColGroup; ++u) {
       const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
       xv[u] = X[r * d + segc];
-      sv[u] = scale ? scale[r] : 1.0;
+      sv[u] = SCALE ? scale[r] : 1.0;
     }
+    // no branch per item: the additions stay one dependent chain and the
+    // rest interleaves
 #pragma unroll
     for (int u = 0; u < kColGroup; ++u) {
       const int64_t r = g0 + u;
-      if (r < r1) {
-        const double w = scale ? fabs((double)xv[u]) * sv[u]
-                               : fabs((double)xv[u]);
-        l = r == r0 ? w : l + w;
-      }
+      const double w = SCALE ? fabs((double)xv[u]) * sv[u]
+                             : fabs((double)xv[u]);
+      const double lw = r == r0 ? w : l + w;
+      l = r < r1 ? lw : l;
     }
   }
   if (seg < S) rtot[c * S + seg] = l;
@@ -793,7 +795,7 @@ __global__ __launch_bounds__(64) void k_col_runoffsets(const double* rtot,
 // a time (one per half-wave, lane = item), ballots give every entry its
 // place and each table's lights and heavies of the group are stored as
 // contiguous runs.
-template <bool LISTS>
+template <bool LISTS, bool SCALE>
 __global__ __launch_bounds__(64) void k_col_walk(
     const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
     int L, const double* E, const double* tot, int64_t s0, int64_t ns,
@@ -813,6 +815,7 @@ __global__ __launch_bounds__(64) void k_col_walk(
   const int64_t seg = s0 + tc;
   const double T = tot[seg];
   const bool live = T > 0.0;
+  const double Tq = live ? T : 1.0;  // dead tables: no item is taken
   const int K = L + kCapBits;
   const int64_t r0 = c * kRun;
   const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;  // items of this run
@@ -837,36 +840,40 @@ __global__ __launch_bounds__(64) void k_col_walk(
       for (int u = 0; u < kColGroup; ++u) {
         const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
         xv[u] = X[r * d + seg];
-        sv[u] = scale ? scale[r] : 1.0;
+        sv[u] = SCALE ? scale[r] : 1.0;
+      }
+    } else {  // padding slots only
+#pragma unroll
+      for (int u = 0; u < kColGroup; ++u) {
+        xv[u] = 0.0f;
+        sv[u] = 1.0;
       }
     }
     if (LISTS) {
       cnt0[lane][0] = nl;
       cnt0[lane][1] = nh;
     }
+    // no branch per item: only the additions of l form a dependent chain,
+    // so the divisions of consecutive items overlap
 #pragma unroll
     for (int u = 0; u < kColGroup; ++u) {
       const int64_t r = g0 + u;
-      uint64_t q = 0;
-      uint32_t sg = 0;
-      if (r < r1 && live) {
-        const double w = scale ? fabs((double)xv[u]) * sv[u]
-                               : fabs((double)xv[u]);
-        l = r == r0 ? w : l + w;
-        const uint64_t F = (uint64_t)floor(ldexp((Ec + l) / T, K));
-        q = F - Fp;
-        Fp = F;
-        sg = sign_bit(xv[u]);
-      }
-      if (q < kCap) {
-        if (LISTS) tv[u][lane] = da;
-        ++nl;
-        da += kCap - q;
-      } else {
-        ea += q - kCap;
-        if (LISTS) tv[u][lane] = ea | (1ull << 63);
-        ++nh;
-      }
+      const bool ok = live && r < r1;
+      const double w = SCALE ? fabs((double)xv[u]) * sv[u]
+                             : fabs((double)xv[u]);
+      const double lw = r == r0 ? w : l + w;
+      l = ok ? lw : l;
+      const uint64_t F = (uint64_t)floor(ldexp((Ec + l) / Tq, K));
+      const uint64_t q = ok ? F - Fp : 0ull;
+      Fp = ok ? F : Fp;
+      const uint32_t sg = ok ? sign_bit(xv[u]) : 0u;
+      const bool light = q < kCap;
+      const uint64_t ea2 = light ? ea : ea + (q - kCap);
+      if (LISTS) tv[u][lane] = light ? da : (ea2 | (1ull << 63));
+      da = light ? da + (kCap - q) : da;
+      ea = ea2;
+      nl += light ? 1 : 0;
+      nh += light ? 0 : 1;
       if (LISTS) ti[u][lane] = (uint32_t)r | (sg << 31);
     }
     if (LISTS) {
@@ -930,11 +937,21 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
   int64_t per = (int64_t)(left / per_tab);
   if (per < 1) return hipErrorOutOfMemory;
   const int64_t tiles = (S + 63) / 64;
-  k_col_runtot<<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S, N, rtot);
+  if (scale)
+    k_col_runtot<true><<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S,
+                                                             N, rtot);
+  else
+    k_col_runtot<false><<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S,
+                                                              N, rtot);
   k_col_runoffsets<<<(unsigned)S, 64, 0, st>>>(rtot, S, R, E, f.tot);
-  k_col_walk<false><<<(unsigned)(B * tiles), 64, 0, st>>>(
-      X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
-      nullptr);
+  if (scale)
+    k_col_walk<false, true><<<(unsigned)(B * tiles), 64, 0, st>>>(
+        X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
+        nullptr);
+  else
+    k_col_walk<false, false><<<(unsigned)(B * tiles), 64, 0, st>>>(
+        X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
+        nullptr);
   for (int64_t s0 = 0; s0 < S; s0 += per) {
     const int64_t ns = S - s0 < per ? S - s0 : per;
     const int64_t slots = ns * Np;
@@ -951,8 +968,12 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
     Quad* bsb = bs + s0 * B;
     k_alias_blockscan<<<(unsigned)ns, 256, 0, st>>>(bsb, ns, B, NL, NH, Dt);
     const int64_t btiles = (ns + 63) / 64;
-    k_col_walk<true><<<(unsigned)(B * btiles), 64, 0, st>>>(
-        X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
+    if (scale)
+      k_col_walk<true, true><<<(unsigned)(B * btiles), 64, 0, st>>>(
+          X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
+    else
+      k_col_walk<true, false><<<(unsigned)(B * btiles), 64, 0, st>>>(
+          X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
     const int64_t nedge = ns * (Np / kMergeBlk + 1);
     k_alias_edges<<<grid_for(nedge, 256), 256, 0, st>>>(Ld, He, NL, NH, ns, L,
                                                         edges);
