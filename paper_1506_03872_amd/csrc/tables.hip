@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
           T = T + rt[tb * 4 + c];
         }
       const bool live = have && T > 0.0;
-      if (have && lane == 0) tot[seg] = T;
+      if (have && lane == 0 && tot) tot[seg] = T;  // tot may be null
       if (have && !live)  // dead table: never sampled, entries zero
         for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
       uint64_t F[SPL];
