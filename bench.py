@@ -600,6 +600,11 @@ def main():
         "stats": {"wnorm": stats["wnorm"], "closed": closed,
                   "distinct": stats["distinct"], "n_pos": stats["n_pos"],
                   "n_cand": stats["n_cand"]},
+        # closed diamonds per second of the sampling kernel, and candidates
+        # verified per second of Alg. 3 (selection + verification + top t)
+        "closed_per_s": round(closed / (sampler_ms * 1e-3), 1),
+        "pairs_verified_per_s": round(
+            stats["n_cand"] / (float(ph[:, 2].mean()) * 1e-3), 1),
         "roofline": roofline,
         "cpu_baseline": base,
     }
