@@ -237,3 +237,31 @@ def test_one_shot_entry_point(mad_gpu):
     g = mad_gpu.topk(to_dev(A), to_dev(B), t=20, s=60_000, t_prime=400, seed=5)
     o = oracle.Plan.dense(A, B).topk(seed=5, s=60_000, t_prime=400, t=20)
     _check_topk(A, B, g, o, 20)
+
+
+def test_large_column_tables_bitexact(mad_gpu):
+    # columns of 2^20 < N <= 2^21 items and 33 of them per side: 69M slots
+    # per family, more than one batch of alias lists (2^26 slots), as at
+    # the 1e6-vector sizes; tables and a sample stream against the oracle
+    import time
+    A, B = workloads.dense_gaussian(1_050_001, 1_040_003, 33, seed=12)
+    t0 = time.perf_counter()
+    gp, op = make_plans(mad_gpu, A, B)
+    say("plans built in %.1f s" % (time.perf_counter() - t0))
+    gna, gnb, gv, gom = gp.norms()
+    ona, onb, ov, oom = op.norms()
+    assert np.array_equal(gnb, onb) and np.array_equal(gv, ov)
+    assert np.array_equal(gom, oom)
+    checks = [(0, 0), (1, 0), (1, 16), (1, 32), (2, 0), (2, 31), (3, 1_050_000)]
+    for which, idx in checks:
+        gthr, gal, _ = gp.table(which, idx)
+        othr, oal, _, _, _, _ = op.table(which, idx)
+        assert np.array_equal(gthr, othr), (which, idx)
+        assert np.array_equal(gal, oal), (which, idx)
+    s = 1_000_000
+    F = op.fix_exponent(s)
+    g = gp.samples(seed=5, l0=0, count=20_000, F=F)
+    o = op.samples(5, 0, 20_000, F)
+    for key in ("k", "i", "j", "kp", "inc"):
+        assert np.array_equal(g[key], o[key]), key
+    gp.close()
