@@ -83,12 +83,23 @@ def _dense_as_csr():
     return workloads.dense_to_csr(A), workloads.dense_to_csr(B), 400, 350, 30
 
 
+def _powerlaw_big():
+    # the top coordinates carry ~1e5 entries: tables of 2^17-2^18 slots in
+    # the multi-workgroup pipeline, as at the full sparse sizes
+    m, n, d = 200_000, 190_000, 20_000
+    a = workloads.powerlaw_csr(m, d, 20, 1.5, seed=15, role=0)
+    b = workloads.powerlaw_csr(n, d, 20, 1.5, seed=15, role=1)
+    return a, b, m, n, d
+
+
 CASES = {"powerlaw": _powerlaw, "ragged": _ragged, "zeros": _explicit_zeros,
          "d1": _d1, "dense_as_csr": _dense_as_csr}
+# tables and sample streams only
+CASES_BIG = {"powerlaw_big": _powerlaw_big}
 
 
 def make(mad, name):
-    a, b, m, n, d = CASES[name]()
+    a, b, m, n, d = {**CASES, **CASES_BIG}[name]()
     say("case", name, "m n d", m, n, d, "nnz", len(a[1]), len(b[1]))
     gp = mad.Plan.csr(tuple(to_dev(x) for x in a), tuple(to_dev(x) for x in b),
                       m, n, d)
@@ -100,7 +111,7 @@ def _dense(x, rows, d):
     return workloads.csr_to_dense(x[0], x[1], x[2], rows, d)
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name", list(CASES) + list(CASES_BIG))
 def test_norms_and_tables_bitexact(mad_gpu, name):
     gp, op, a, b, m, n, d = make(mad_gpu, name)
     g = gp.norms()
@@ -127,7 +138,7 @@ def test_norms_and_tables_bitexact(mad_gpu, name):
     gp.close()
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name", list(CASES) + list(CASES_BIG))
 def test_sample_stream_bitexact(mad_gpu, name):
     gp, op, a, b, m, n, d = make(mad_gpu, name)
     s = 200_000
