@@ -270,17 +270,49 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
 #define MAD_BF_LSTORE(BUF)                                                   \
   MAD_BF_LSTORE1(0, BUF) MAD_BF_LSTORE1(1, BUF) MAD_BF_LSTORE1(2, BUF)       \
   MAD_BF_LSTORE1(3, BUF)
+// full tiles (no row past the end): the 4 pieces of an operand are 32 rows
+// apart, so one base pointer per tile serves every stage
+#define MAD_BF_FULL(I0, J0) ((I0) + kBM <= g.m_rows && (J0) + kBN <= g.n)
+#define MAD_BF_PA(I0) (Ab + ((I0) + trow) * g.a_stride_rows * row_bytes + seg)
+#define MAD_BF_PB(J0) (Bb + ((J0) + trow) * row_bytes + seg)
+#define MAD_BF_GLOADF(PA, PB, KB)                                            \
+  {                                                                          \
+    ra0 = *(const uint4*)((PA) + (KB));                                      \
+    ra1 = *(const uint4*)((PA) + astep + (KB));                              \
+    ra2 = *(const uint4*)((PA) + 2 * astep + (KB));                          \
+    ra3 = *(const uint4*)((PA) + 3 * astep + (KB));                          \
+    rb0 = *(const uint4*)((PB) + (KB));                                      \
+    rb1 = *(const uint4*)((PB) + bstep + (KB));                              \
+    rb2 = *(const uint4*)((PB) + 2 * bstep + (KB));                          \
+    rb3 = *(const uint4*)((PB) + 3 * bstep + (KB));                          \
+  }
+  const int64_t trow = t >> 3;
+  const int64_t astep = 32 * g.a_stride_rows * row_bytes;
+  const int64_t bstep = 32 * row_bytes;
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
   int64_t tile = v;
   int64_t i0 = 0, j0 = 0;
+  bool full = false;
+  const char* pa = Ab;
+  const char* pb = Bb;
   if (tile < ntiles) {
     gemm_coords(tile, tiles_m, tiles_n, i0, j0);
-    MAD_BF_GLOAD(i0, j0, 0)
+    full = MAD_BF_FULL(i0, j0);
+    pa = MAD_BF_PA(i0);
+    pb = MAD_BF_PB(j0);
+    if (full) {
+      MAD_BF_GLOADF(pa, pb, 0)
+    } else {
+      MAD_BF_GLOAD(i0, j0, 0)
+    }
   }
   while (tile < ntiles) {
     const int64_t next = tile + G;
     int64_t ni0 = 0, nj0 = 0;
     if (next < ntiles) gemm_coords(next, tiles_m, tiles_n, ni0, nj0);
+    const bool nfull = next < ntiles && MAD_BF_FULL(ni0, nj0);
+    const char* npa = MAD_BF_PA(ni0);
+    const char* npb = MAD_BF_PB(nj0);
     // fp8: the per-vector scales of the rows this lane feeds the MFMA
     int sa[2] = {127, 127}, sb[2] = {127, 127};
     if (P == kFP8) {
@@ -309,10 +341,17 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
       // harmless reload of this tile's first: unconditional loads keep
       // ra / rb in registers
       const bool more = st + 1 < nst;
-      const int64_t li0 = more ? i0 : (next < ntiles ? ni0 : i0);
-      const int64_t lj0 = more ? j0 : (next < ntiles ? nj0 : j0);
+      const bool nx = !more && next < ntiles;
+      const int64_t li0 = nx ? ni0 : i0;
+      const int64_t lj0 = nx ? nj0 : j0;
       const int64_t lkb = more ? (st + 1) * kRowBytes : 0;
-      MAD_BF_GLOAD(li0, lj0, lkb)
+      if (nx ? nfull : full) {
+        const char* lpa = nx ? npa : pa;
+        const char* lpb = nx ? npb : pb;
+        MAD_BF_GLOADF(lpa, lpb, lkb)
+      } else {
+        MAD_BF_GLOAD(li0, lj0, lkb)
+      }
       const char* la = lds_a[cur] + (wr * 64) * kLdsStride;
       const char* lb = lds_b[cur] + (wc * 64) * kLdsStride;
       // the next K step's operands are read from LDS while the current
@@ -389,6 +428,9 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
     tile = next;
     i0 = ni0;
     j0 = nj0;
+    full = nfull;
+    pa = npa;
+    pb = npb;
   }
   if (HIST) {
     __syncthreads();
@@ -398,6 +440,10 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
 }
 #undef MAD_BF_GLOAD1
 #undef MAD_BF_GLOAD
+#undef MAD_BF_FULL
+#undef MAD_BF_PA
+#undef MAD_BF_PB
+#undef MAD_BF_GLOADF
 #undef MAD_BF_LSTORE1
 #undef MAD_BF_LSTORE
 
