@@ -410,15 +410,15 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   for (int r = t; r < nb2; r += kAcc2Threads) h[r] = 0;
   __syncthreads();
-  for (int64_t e0 = lo + t; e0 < hi; e0 += kAcc2Threads * 4) {
-    uint64_t key[4];
+  for (int64_t e0 = lo + t; e0 < hi; e0 += kAcc2Threads * 8) {
+    uint64_t key[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int64_t e = e0 + (int64_t)u * kAcc2Threads;
       key[u] = e < hi ? ik[e] : 0ull;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (e0 + (int64_t)u * kAcc2Threads < hi)
         atomicAdd(&h[(uint32_t)((mix64(key[u]) << B1) >> (64 - B2))], 1u);
   }
@@ -453,18 +453,38 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
   // place, a chunk of kChunk2 pairs at a time: the chunk is sorted by
   // sub-bin in LDS, then each sub-bin's share is stored as one run at its
   // cursor (h[r], relative to lo), which then advances by that share
+  // the next chunk's pairs are loaded while this one is placed (clamped
+  // to the bin's last pair, so the loads carry no branch)
+  uint64_t nkey[4] = {0ull, 0ull, 0ull, 0ull};
+  float nval[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (hi > lo) {  // uniform: an empty bin loads nothing
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int64_t e = lo + (int64_t)u * kAcc2Threads + t;
+      e = e < hi ? e : hi - 1;
+      nkey[u] = ik[e];
+      nval[u] = iv[e];
+    }
+  }
   for (int64_t c0 = lo; c0 < hi; c0 += kChunk2) {
-    for (int r = t; r < nb2; r += kAcc2Threads) cc[r] = 0;
-    __syncthreads();
     uint64_t key[4];
     float val[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      key[u] = nkey[u];
+      val[u] = nval[u];
+      int64_t e = c0 + kChunk2 + (int64_t)u * kAcc2Threads + t;
+      e = e < hi ? e : hi - 1;
+      nkey[u] = ik[e];
+      nval[u] = iv[e];
+    }
+    for (int r = t; r < nb2; r += kAcc2Threads) cc[r] = 0;
+    __syncthreads();
     uint32_t sub[4], rank[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t e = c0 + (int64_t)u * kAcc2Threads + t;
       const bool in = e < hi;
-      key[u] = in ? ik[e] : 0ull;
-      val[u] = in ? iv[e] : 0.0f;
       sub[u] = in ? (uint32_t)((mix64(key[u]) << B1) >> (64 - B2)) : 0u;
       rank[u] = in ? atomicAdd(&cc[sub[u]], 1u) : 0u;
     }
