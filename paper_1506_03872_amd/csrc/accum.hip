@@ -12,7 +12,8 @@
 //   scan     exclusive prefix of the tile counts in bin-major order;
 //   place    every closed pair written into its bin's range;
 //   split    (large s) one workgroup per bin partitions it again by the next
-//            B2 hash bits, so that bins hold about 1024 pairs;
+//            B2 hash bits, so that bins hold about 512 pairs; above 8 bits
+//            in two splits (each storing runs of ~16+ pairs per sub-bin);
 //   reduce   one workgroup per bin sums equal keys in an LDS hash table and
 //            appends the distinct (key, x) to the output list.  A bin with
 //            more distinct keys than the LDS table holds is split by the
@@ -30,7 +31,9 @@ constexpr int kAccThreads = 512;
 constexpr int kAccPer = 8;                // pairs per thread of a tile
 constexpr int kAccTile = kAccThreads * kAccPer;  // count / place tile
 constexpr int kAccMaxBits = 8;            // first level: up to 256 bins
-constexpr int kAcc2MaxBits = 12;          // second level: up to 4096 sub-bins
+constexpr int kAcc2MaxBits = 12;          // one split: up to 4096 sub-bins
+constexpr int kAccSplitBits = 8;          // above this, two splits
+constexpr int kAccMaxTotalBits = kAccMaxBits + 14;
 constexpr int kRedThreads = 256;
 // LDS table of a reduce workgroup: 1024 slots, 4096 or 8192 when the bins
 // hold more pairs than the partition bits can bring below ~400
@@ -58,7 +61,7 @@ static int64_t acc_target() {
 // acc_target() pairs
 static int acc_total_bits(int64_t s) {
   int b = 0;
-  while (b < kAccMaxBits + kAcc2MaxBits && (acc_target() << b) < s) ++b;
+  while (b < kAccMaxTotalBits && (acc_target() << b) < s) ++b;
   return b;
 }
 
@@ -534,14 +537,14 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
   }
 }
 
-// the LDS table size for bins of about `per_bin` pairs (load <= ~0.4);
+// the LDS table size for bins of about `per_bin` pairs (load <= ~0.5);
 // MAD_ACC_SLOTS = 1024, 4096 or 8192 forces one (the result is the same)
 static int reduce_slots(int64_t per_bin) {
   if (const char* e = getenv("MAD_ACC_SLOTS")) {
     const int v = atoi(e);
     if (v == 1024 || v == 4096 || v == 8192) return v;
   }
-  return per_bin <= 384 ? 1024 : per_bin <= 1536 ? 4096 : 8192;
+  return per_bin <= 512 ? 1024 : per_bin <= 1536 ? 4096 : 8192;
 }
 
 static void launch_reduce(int64_t per_bin, int64_t bins, const uint64_t* pk,
@@ -607,13 +610,27 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
                                                             starts);
     launch_reduce(n >> B1, nb1, placed, placed_v, starts, B1, bmax, s_for_F,
                   okey, oval, bin_distinct, st);
-  } else {
+  } else if (B2 <= kAccSplitBits) {
     k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
                                                             starts1);
     k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
         placed, placed_v, starts1, B1, B2, keys, vals, starts);
     launch_reduce(n >> (B1 + B2), nb1 << B2, keys, vals, starts, B1 + B2,
                   bmax, s_for_F, okey, oval, bin_distinct, st);
+  } else {
+    // two splits of at most kAccSplitBits bits each, so that a chunk of
+    // kChunk2 pairs still stores runs of ~16 or more pairs per sub-bin;
+    // the middle starts live in bin_distinct until the reduce writes it
+    const int Ba = (B2 + 1) / 2, Bb = B2 - Ba;
+    uint64_t* starts_mid = bin_distinct;
+    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
+                                                            starts1);
+    k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
+        placed, placed_v, starts1, B1, Ba, keys, vals, starts_mid);
+    k_acc_split2<<<(unsigned)(nb1 << Ba), kAcc2Threads, 0, st>>>(
+        keys, vals, starts_mid, B1 + Ba, Bb, placed, placed_v, starts);
+    launch_reduce(n >> (B1 + B2), nb1 << B2, placed, placed_v, starts,
+                  B1 + B2, bmax, s_for_F, okey, oval, bin_distinct, st);
   }
   // entries written = closed pairs = the end of the last bin
   k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count,

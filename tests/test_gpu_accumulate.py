@@ -145,3 +145,15 @@ def test_reduce_table_sizes(mad_gpu, slots):
         assert run(mad_gpu, keys, vals, 18) == 10_000
     finally:
         del os.environ["MAD_ACC_SLOTS"]
+
+
+def test_two_splits_after_the_first_partition(mad_gpu):
+    # 3.6e7 pairs: 2^17 final bins of ~275 pairs, 9 bits below the first
+    # level's 8, taken in two splits (5 + 4 bits)
+    g = np.random.default_rng(7)
+    n = 36_000_000
+    keys = g.integers(0, 40_000_000_000, n, dtype=np.int64)
+    keys[: n // 4] = g.integers(0, 3_000_000, n // 4)   # repeated keys
+    keys[g.random(n) < 0.15] = EMPTY
+    vals = (g.standard_normal(n) * 1e-2).astype(np.float32)
+    say("distinct", run(mad_gpu, keys, vals, 28))
