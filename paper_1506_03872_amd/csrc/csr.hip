@@ -1451,10 +1451,27 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   return a;
 }
 
+// MAD_CSR_GRID caps the sampling grid and MAD_CSR_UNROLL (2, 4, 8, 16)
+// sets the samples per thread in flight (8 measured best: the draws are
+// chains of dependent random loads); neither changes the result
 static unsigned csr_grid(int64_t count, int per_thread) {
+  static const int64_t cap = [] {
+    const char* e = getenv("MAD_CSR_GRID");
+    const long v = e ? atol(e) : 8192;
+    return (int64_t)(v >= 256 && v <= (1 << 20) ? v : 8192);
+  }();
   int64_t blocks = (count + 256LL * per_thread - 1) / (256LL * per_thread);
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > cap) blocks = cap;
   return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+static int csr_unroll() {
+  static const int u = [] {
+    const char* e = getenv("MAD_CSR_UNROLL");
+    const int v = e ? atoi(e) : 8;
+    return v == 2 || v == 4 || v == 16 ? v : 8;
+  }();
+  return u;
 }
 
 static size_t csr_t0_lds(const CsrTables& t) {
@@ -1468,9 +1485,21 @@ hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
                              hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
-  k_sample_csr<4, false><<<csr_grid(count, 4), 256, csr_t0_lds(t), st>>>(
-      a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, (uint64_t)h.cap - 1,
-      h.pkeys, h.pvals, ctr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  switch (csr_unroll()) {
+#define MAD_CSR_CASE(UU)                                                     \
+  case UU:                                                                   \
+    k_sample_csr<UU, false><<<csr_grid(count, UU), 256, csr_t0_lds(t), st>>>( \
+        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals,                     \
+        (uint64_t)h.cap - 1, h.pkeys, h.pvals, ctr, nullptr, nullptr,        \
+        nullptr, nullptr, nullptr);                                          \
+    break;
+    MAD_CSR_CASE(2)
+    MAD_CSR_CASE(4)
+    MAD_CSR_CASE(16)
+    default:
+    MAD_CSR_CASE(8)
+#undef MAD_CSR_CASE
+  }
   return hipGetLastError();
 }
 
