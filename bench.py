@@ -192,6 +192,32 @@ def bench_mips(args, cfg, data, mad):
     wall = (time.perf_counter() - t0) * 1e3 / args.steps
     ms = ev0.elapsed_time(ev1) / args.steps
     st = plan.mips_stats(nq)
+    ref_out, ref_n = out.clone(), n_out.clone()
+    # the same batch with each verification precision (bf16 / fp8 screen
+    # before fp32): ms per batch, fp32 rows read, identical results
+    vprec = {}
+    for name, prec in (("fp32", mad.MAD_FP32), ("bf16", mad.MAD_BF16),
+                       ("fp8_e4m3", mad.MAD_FP8_E4M3)):
+        plan.set_verify_precision(prec)
+        plan.batch_raw(Q, s_q, tp_q, t, args.seed, out, n_out)
+        torch.cuda.synchronize()
+        e0v = torch.cuda.Event(enable_timing=True)
+        e1v = torch.cuda.Event(enable_timing=True)
+        e0v.record()
+        for _ in range(args.steps):
+            plan.batch_raw(Q, s_q, tp_q, t, args.seed, out, n_out)
+        e1v.record()
+        torch.cuda.synchronize()
+        vs = plan.verify_stats()
+        vprec[name] = {"ms_per_batch": round(e0v.elapsed_time(e1v) /
+                                             args.steps, 3),
+                       "n_cand": vs["n_cand"],
+                       "n_reranked_fp32": vs["n_reranked"],
+                       "same_result_as_fp32": bool(
+                           torch.equal(n_out, ref_n) and
+                           torch.equal(out, ref_out))}
+        log("MIPS verify %s: %s" % (name, vprec[name]))
+    plan.set_verify_precision(mad.MAD_FP32)
     # phase split from an eager run of the same batch
     tplan = mad.MipsPlan.create(A, flags=mad.MAD_FLAG_TIMING)
     tplan.set_config(tuned["chunk"], tuned["unroll"], tuned["grid"])
@@ -257,6 +283,7 @@ def bench_mips(args, cfg, data, mad):
                   "n_cand_total": int(st["n_cand"].sum())},
         "pairs_verified_per_s": round(float(st["n_cand"].sum()) /
                                       (ph[2] * 1e-3), 1),
+        "verify_precision": vprec,
         "roofline": roofline,
         "cpu_baseline": None,
     }

@@ -151,13 +151,16 @@ int mad_plan_topk(mad_plan* plan, int64_t t, int64_t s, int64_t t_prime,
  *                 lower bound are verified in fp32.  The result is the same
  *                 as with MAD_FP32, with fewer fp32 rows read.
  * Builds the copies (device memory, kept in the plan and rebuilt by
- * mad_plan_refresh).  MAD_EUNSUPPORTED for sparse plans.
+ * mad_plan_refresh).  On a MIPS plan the same screen applies to each
+ * query's candidates in mips_topk_batch (the database copy is built here,
+ * the queries' copies in every batch).  MAD_EUNSUPPORTED for sparse plans.
  * ------------------------------------------------------------------------- */
 int mad_plan_set_verify_precision(mad_plan* plan, int precision, void* stream);
 
 /* Candidates of the last mad_plan_topk (host outputs, synchronises):
  * n_cand = |Omega_t'|, n_reranked = how many were verified in fp32 (equal
- * to n_cand under MAD_FP32 verification).  Either pointer may be NULL. */
+ * to n_cand under MAD_FP32 verification); on a MIPS plan, both summed over
+ * the queries of the last batch.  Either pointer may be NULL. */
 int mad_plan_verify_stats(mad_plan* plan, int64_t* n_cand,
                           int64_t* n_reranked);
 

@@ -82,6 +82,10 @@ struct MipsState {
   uint64_t g_seed = 0;
   int g_chunk = -1, g_unroll = -1, g_grid = -1;
   int64_t g_layout = -1;
+  // low-precision copies of the batch's queries (screened verification)
+  mad::DeviceBuffer qlp, qlpi;
+  int g_prec = -1;
+  const void* g_qlp = nullptr;
   int64_t layout_version = 0;
   bool ran = false;
 };
@@ -128,7 +132,7 @@ static void mips_free(MipsState* ms) {
   mad::DeviceBuffer* bufs[] = {&ms->qscratch, &ms->qinfo, &ms->order,
                                &ms->chunks, &ms->hkeys, &ms->hvals, &ms->cx,
                                &ms->ck, &ms->sx, &ms->sk, &ms->sc, &ms->sab,
-                               &ms->qstats, &ms->ctr};
+                               &ms->qstats, &ms->ctr, &ms->qlp, &ms->qlpi};
   for (mad::DeviceBuffer* b : bufs) mad::dev_free(*b);
   delete ms;
 }
@@ -263,8 +267,9 @@ int mad_plan_refresh(mad_plan* p, void* stream) {
     int64_t kp = 0;
     HIP_TRY(mad::lowp_prepare(p->A, p->m, p->d, p->verify_prec, p->lpA,
                               p->lpIA, &kp, st), "low-precision copies");
-    HIP_TRY(mad::lowp_prepare(p->B, p->n, p->d, p->verify_prec, p->lpB,
-                              p->lpIB, &kp, st), "low-precision copies");
+    if (p->B)
+      HIP_TRY(mad::lowp_prepare(p->B, p->n, p->d, p->verify_prec, p->lpB,
+                                p->lpIB, &kp, st), "low-precision copies");
   }
   record(p, 1, st);
   p->timed_tables = p->ev[0] != nullptr;
@@ -509,16 +514,18 @@ int mad_plan_set_verify_precision(mad_plan* p, int precision, void* stream) {
   if (precision != MAD_FP32 && precision != MAD_BF16 &&
       precision != MAD_FP8_E4M3)
     return fail(MAD_EINVAL, "unknown precision %d", precision);
-  if (p->kind != 0 && precision != MAD_FP32)
-    return fail(MAD_EUNSUPPORTED, "low-precision verification needs a dense plan");
+  if (p->kind == 2 && precision != MAD_FP32)
+    return fail(MAD_EUNSUPPORTED,
+                "low-precision verification needs a dense or MIPS plan");
   p->verify_prec = precision;
   if (precision == MAD_FP32) return MAD_OK;
   hipStream_t st = (hipStream_t)stream;
   int64_t kp = 0;
   HIP_TRY(mad::lowp_prepare(p->A, p->m, p->d, precision, p->lpA, p->lpIA, &kp,
                             st), "low-precision copies");
-  HIP_TRY(mad::lowp_prepare(p->B, p->n, p->d, precision, p->lpB, p->lpIB, &kp,
-                            st), "low-precision copies");
+  if (p->B)  // a MIPS plan's queries are converted per batch
+    HIP_TRY(mad::lowp_prepare(p->B, p->n, p->d, precision, p->lpB, p->lpIB,
+                              &kp, st), "low-precision copies");
   p->lv.A = p->lpA.p;
   p->lv.B = p->lpB.p;
   p->lv.ia = (const mad::VecInfo*)p->lpIA.p;
@@ -532,6 +539,21 @@ int mad_plan_set_verify_precision(mad_plan* p, int precision, void* stream) {
 
 int mad_plan_verify_stats(mad_plan* p, int64_t* n_cand, int64_t* n_reranked) {
   if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind == 1) {  // MIPS: totals over the queries of the last batch
+    if (!p->mips->ran) return fail(MAD_EINVAL, "no batch has run");
+    HIP_TRY(hipDeviceSynchronize(), "verify stats");
+    std::vector<mad::MipsQueryStats> qs((size_t)p->mips->nq);
+    HIP_TRY(hipMemcpy(qs.data(), p->mips->qstats.p, qs.size() * sizeof qs[0],
+                      hipMemcpyDeviceToHost), "verify stats");
+    int64_t nc = 0, nf = 0;
+    for (const auto& x : qs) {
+      nc += x.n_cand;
+      nf += x.n_fp32;
+    }
+    if (n_cand) *n_cand = nc;
+    if (n_reranked) *n_reranked = nf;
+    return MAD_OK;
+  }
   if (!p->ran) return fail(MAD_EINVAL, "no mad_plan_topk has run");
   HIP_TRY(hipDeviceSynchronize(), "verify stats");
   int64_t cnt[9];
@@ -1046,6 +1068,17 @@ static mad::MipsArgs mips_args(mad_plan* p, const float* Q, uint64_t seed,
   a.qstats = (mad::MipsQueryStats*)ms->qstats.p;
   a.out = out;
   a.n_out = n_out;
+  if (p->verify_prec != MAD_FP32) {
+    a.lp = p->verify_prec;
+    a.Alp = p->lv.A;
+    a.ia = p->lv.ia;
+    a.Qlp = ms->qlp.p;
+    a.iq = (const mad::VecInfo*)ms->qlpi.p;
+    a.Kp = p->lv.Kp;
+    a.kappa = p->lv.kappa;
+    a.onepu = p->lv.onepu;
+    a.d_f = p->lv.d_f;
+  }
   return a;
 }
 
@@ -1063,6 +1096,12 @@ static hipError_t mips_enqueue(mad_plan* p, const mad::MipsArgs& a,
                                    ms->qscratch.p, ms->qscratch.bytes, st)) !=
           hipSuccess)
     return e;
+  if (a.lp) {  // the queries' low-precision rows (buffers sized already)
+    int64_t kp = 0;
+    if ((e = mad::lowp_prepare(a.Q, a.nq, a.d, a.lp, ms->qlp, ms->qlpi, &kp,
+                               st)) != hipSuccess)
+      return e;
+  }
   if (events) {
     record(p, 1, st);
     record(p, 2, st);
@@ -1118,6 +1157,14 @@ int mips_topk_batch(mad_plan* p, const float* Q, int64_t nq,
   hipStream_t st = (hipStream_t)stream;
   if ((rc = mips_prepare(p, nq, s_per_query, tprime_per_query, t)) != MAD_OK)
     return rc;
+  if (p->verify_prec != MAD_FP32) {  // outside any capture: no allocation there
+    const int64_t kc = p->verify_prec == MAD_BF16 ? 64 : 128;
+    const int64_t eb = p->verify_prec == MAD_BF16 ? 2 : 1;
+    const int64_t kp = (p->d + kc - 1) / kc * kc;
+    HIP_TRY(mad::dev_alloc(ms->qlp, (size_t)(nq * kp * eb)), "query copies");
+    HIP_TRY(mad::dev_alloc(ms->qlpi, (size_t)nq * sizeof(mad::VecInfo)),
+            "query copies");
+  }
   const mad::MipsArgs a = mips_args(p, Q, seed, out, n_out);
   ms->ran = true;
   if (p->flags & MAD_FLAG_TIMING) {  // eager, with phase events
@@ -1129,7 +1176,8 @@ int mips_topk_batch(mad_plan* p, const float* Q, int64_t nq,
                      ms->g_nout == n_out && ms->g_seed == seed &&
                      ms->g_chunk == ms->chunk && ms->g_unroll == ms->unroll &&
                      ms->g_grid == ms->grid &&
-                     ms->g_layout == ms->layout_version;
+                     ms->g_layout == ms->layout_version &&
+                     ms->g_prec == p->verify_prec && ms->g_qlp == ms->qlp.p;
   if (!fresh) {
     mips_drop_graph(ms);
     HIP_TRY(hipStreamBeginCapture(ms->cap_stream,
@@ -1156,6 +1204,8 @@ int mips_topk_batch(mad_plan* p, const float* Q, int64_t nq,
     ms->g_unroll = ms->unroll;
     ms->g_grid = ms->grid;
     ms->g_layout = ms->layout_version;
+    ms->g_prec = p->verify_prec;
+    ms->g_qlp = ms->qlp.p;
   }
   HIP_TRY(hipGraphLaunch(ms->exec, st), "launching the MIPS graph");
   return MAD_OK;

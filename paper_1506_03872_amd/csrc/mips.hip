@@ -336,6 +336,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
       a.n_out[q] = qi.live ? 0 : -1;
       a.qstats[q].n_pos = 0;
       a.qstats[q].n_cand = 0;
+      a.qstats[q].n_fp32 = 0;
     }
     return;
   }
@@ -390,14 +391,67 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
   }
   if (nsel > qi.scap) nsel = qi.scap;
   __syncthreads();
+  const int lane = t & 63, wv = t >> 6, grp = lane >> 4, gl = lane & 15;
+  const int64_t tq = a.t < nsel ? a.t : nsel;
+  // low-precision screen (when the plan asks for one and more than t
+  // candidates remain): c^ of every candidate from the bf16 / fp8 rows and
+  // the bound mg on |c^ - c_fp32|; tau <= the t-th largest lower bound
+  // |c^| - mg; only candidates with |c^| + mg >= tau are verified in fp32.
+  // Every other candidate has |c_fp32| < tau <= the fp32 |c| of t others,
+  // so the top t is the one the fp32 verification of all of them gives.
+  const bool screen = a.lp != 0 && nsel > tq;
+  float tau = 0.0f;
+  if (screen) {
+    const int64_t rowb = a.Kp * (a.lp == 1 ? 2 : 1);  // bytes per row
+    const uint4* qrow = (const uint4*)((const char*)a.Qlp + q * rowb);
+    const VecInfo vq = a.iq[q];
+    for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += kPostWaves * 4) {
+      const int64_t e = e0 + grp;
+      const bool ok = e < nsel;
+      const int64_t i = (int64_t)sk[ok ? e : e0];
+      const uint4* arow = (const uint4*)((const char*)a.Alp + i * rowb);
+      float acc = 0.0f;
+      for (int64_t c16 = gl; c16 < rowb / 16; c16 += 16)
+        acc = lowp_dot16(arow[c16], qrow[c16], a.lp, acc);
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (ok && gl == 0) {
+        const VecInfo va = a.ia[i];
+        const float c = acc * va.inv_s * vq.inv_s;
+        const float mg = a.kappa * va.n2 * vq.n2 +
+                         a.onepu * (va.eta * vq.n1 + vq.eta * va.n1) +
+                         a.d_f * va.eta * vq.eta;
+        const float lo = fabsf(c) - mg;
+        sab[e] = __float_as_uint(lo > 0.0f ? lo : 0.0f);
+        sc[e] = fabsf(c) + mg;
+      }
+    }
+    __syncthreads();
+    // the selection's prefix of the t-th largest lower bound, lower bits
+    // zero: at most that bound
+    const SelThr th = block_select(sab, sk, nsel, tq, 32, ps);
+    tau = __uint_as_float((uint32_t)th.pp);
+    __syncthreads();
+  }
+  if (t == 0) ps.base = 0;
+  __syncthreads();
   // post2: c = a_i . q in fp32; 16 lanes per candidate and 4 candidates
   // per wave, rows read as float4 when d is a multiple of 4
-  const int lane = t & 63, wv = t >> 6, grp = lane >> 4, gl = lane & 15;
   const bool vec = (a.d & 3) == 0 && ((uintptr_t)a.A & 15) == 0;
+  unsigned nfp = 0;
   for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += kPostWaves * 4) {
     const int64_t e = e0 + grp;
     const bool ok = e < nsel;
-    const float* ar = a.A + (int64_t)sk[ok ? e : e0] * a.d;
+    const bool need = ok && (!screen || sc[e] >= tau);
+    if (!need) {
+      if (ok && gl == 0) {  // screened out: never among the top t
+        sc[e] = 0.0f;
+        sab[e] = 0;
+      }
+      continue;
+    }
+    nfp += gl == 0;
+    const float* ar = a.A + (int64_t)sk[e] * a.d;
     float acc = 0.0f;
     if (vec) {
       for (int64_t k = gl * 4; k < a.d; k += 64) {
@@ -413,14 +467,15 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
     }
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (ok && gl == 0) {
+    if (gl == 0) {
       sc[e] = acc;
       sab[e] = __float_as_uint(fabsf(acc));
     }
   }
+  if (nfp) atomicAdd((unsigned long long*)&ps.base, (unsigned long long)nfp);
   __syncthreads();
+  const int64_t n_fp32 = (int64_t)ps.base;
   // post3: the t largest |c|, ties by i ascending
-  const int64_t tq = a.t < nsel ? a.t : nsel;
   SelThr thr3{0, 0, 0, 0, 0};
   const bool cut3 = nsel > tq;
   if (cut3) thr3 = block_select(sab, sk, nsel, tq, 32, ps);
@@ -466,6 +521,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
     a.n_out[q] = tq;
     a.qstats[q].n_pos = npos;
     a.qstats[q].n_cand = nsel;
+    a.qstats[q].n_fp32 = n_fp32;
   }
 }
 

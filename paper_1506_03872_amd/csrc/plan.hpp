@@ -245,7 +245,11 @@ struct MipsChunk {
 struct MipsQueryStats {
   int64_t n_pos;   // |Omega_s|: keys with x > 0
   int64_t n_cand;  // verified candidates
+  int64_t n_fp32;  // candidates verified in fp32 (n_cand without screening)
+  int64_t pad;
 };
+
+struct VecInfo;
 
 struct MipsArgs {
   // database tables (A side of a dense plan) and the query stage-0 tables
@@ -274,6 +278,16 @@ struct MipsArgs {
   MipsQueryStats* qstats;
   void* out;       // nq x t mad_pair
   int64_t* n_out;  // nq
+  // low-precision screening of the candidates (lp = 1 bf16, 2 fp8; 0 none):
+  // rows of Kp elements of the database and of the queries, their VecInfo,
+  // and the constants of the error bound
+  int lp = 0;
+  const void* Alp = nullptr;
+  const VecInfo* ia = nullptr;
+  const void* Qlp = nullptr;
+  const VecInfo* iq = nullptr;
+  int64_t Kp = 0;
+  float kappa = 0.0f, onepu = 0.0f, d_f = 0.0f;
 };
 
 hipError_t launch_mips_query_info(const float* Q, int64_t nq, int64_t d,
@@ -318,6 +332,37 @@ struct VecInfo {
   float eta;    // absolute rounding floor of one element
   float inv_s;  // 1 / scale applied before rounding
 };
+
+// fp32 sum, added to acc, of the products of 16 bytes of two low-precision
+// rows: 8 bf16 values (prec 1) or 16 fp8-e4m3 values (prec 2) each
+__device__ __forceinline__ float lowp_dot16(const uint4 x, const uint4 y,
+                                            int prec, float acc) {
+  const uint32_t xa[4] = {x.x, x.y, x.z, x.w};
+  const uint32_t ya[4] = {y.x, y.y, y.z, y.w};
+  if (prec == 1) {  // bf16: 8 per load
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc = fmaf(__uint_as_float(xa[q] << 16), __uint_as_float(ya[q] << 16),
+                 acc);
+      acc = fmaf(__uint_as_float(xa[q] & 0xFFFF0000u),
+                 __uint_as_float(ya[q] & 0xFFFF0000u), acc);
+    }
+  } else {  // fp8 e4m3: 16 per load
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 0),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 0), acc);
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 1),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 1), acc);
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 2),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 2), acc);
+      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 3),
+                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 3), acc);
+    }
+  }
+  return acc;
+}
+
 
 // low-precision copies of A and B (rows of Kp elements) for the
 // verification filter, with the margin constants of their error bound

@@ -500,6 +500,7 @@ __global__ __launch_bounds__(256) void k_verify_csr(const uint64_t* key2,
   block_hist_flush(h, hist);
 }
 
+
 // ---------------------------------------------------------------------------
 // low-precision filter of Omega_t' (between post1 and post2): c^ from the
 // bf16 / fp8 copies with an a-priori bound mg on |c^ - c_fp32| (input
@@ -509,34 +510,6 @@ __global__ __launch_bounds__(256) void k_verify_csr(const uint64_t* key2,
 // |c_fp32| >= tau, so dropping it leaves the fp32 top t unchanged.
 // 16 lanes per candidate, 16-byte loads.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float lowp_dot16(const uint4 x, const uint4 y,
-                                            int prec, float acc) {
-  const uint32_t xa[4] = {x.x, x.y, x.z, x.w};
-  const uint32_t ya[4] = {y.x, y.y, y.z, y.w};
-  if (prec == 1) {  // bf16: 8 per load
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      acc = fmaf(__uint_as_float(xa[q] << 16), __uint_as_float(ya[q] << 16),
-                 acc);
-      acc = fmaf(__uint_as_float(xa[q] & 0xFFFF0000u),
-                 __uint_as_float(ya[q] & 0xFFFF0000u), acc);
-    }
-  } else {  // fp8 e4m3: 16 per load
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 0),
-                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 0), acc);
-      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 1),
-                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 1), acc);
-      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 2),
-                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 2), acc);
-      acc = fmaf(__builtin_amdgcn_cvt_f32_fp8((int)xa[q], 3),
-                 __builtin_amdgcn_cvt_f32_fp8((int)ya[q], 3), acc);
-    }
-  }
-  return acc;
-}
-
 __global__ __launch_bounds__(256) void k_verify_lowp(const uint64_t* key2,
                                                      int64_t* counts,
                                                      LowpView v, int64_t n,

@@ -212,3 +212,40 @@ def test_invalid_arguments(mad_gpu):
     empty = gp.batch(Qd[:0], S[:0], TP[:0], 5)
     assert empty == []
     gp.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_low_precision_screen_keeps_results(mad_gpu, prec):
+    # bf16 / fp8 screening of each query's candidates before the fp32
+    # verification: the top t (indices, c, x) must be exactly the fp32 one,
+    # in graph replays and eagerly, and bf16 must skip most fp32 rows
+    A, Q = _db(m=4000, d=64, nq=8, seed=4)
+    Qd = to_dev(Q)
+    for flags in (0, mad_gpu.MAD_FLAG_TIMING):
+        gp = mad_gpu.MipsPlan.create(to_dev(A), flags=flags)
+        ref = gp.batch(Qd, S, TP, T, seed=SEED)
+        st0 = gp.verify_stats()
+        assert st0["n_reranked"] == st0["n_cand"]
+        gp.set_verify_precision(prec)
+        for rep in range(2):
+            got = gp.batch(Qd, S, TP, T, seed=SEED)
+            for q in range(len(S)):
+                if ref[q] is None:
+                    assert got[q] is None
+                    continue
+                for key in ("i", "c", "x"):
+                    assert np.array_equal(got[q][key].cpu().numpy(),
+                                          ref[q][key].cpu().numpy()), (q, key)
+        st = gp.verify_stats()
+        say("flags", flags, "prec", prec, st0, st)
+        assert st["n_cand"] == st0["n_cand"]
+        assert st["n_reranked"] <= st["n_cand"]
+        if prec == 1:
+            assert st["n_reranked"] < st["n_cand"] // 4
+        gp.set_verify_precision(mad_gpu.MAD_FP32)
+        back = gp.batch(Qd, S, TP, T, seed=SEED)
+        for q in range(len(S)):
+            if ref[q] is not None:
+                assert np.array_equal(back[q]["i"].cpu().numpy(),
+                                      ref[q]["i"].cpu().numpy())
+        gp.close()
