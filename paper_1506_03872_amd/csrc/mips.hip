@@ -405,25 +405,45 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
     const int64_t rowb = a.Kp * (a.lp == 1 ? 2 : 1);  // bytes per row
     const uint4* qrow = (const uint4*)((const char*)a.Qlp + q * rowb);
     const VecInfo vq = a.iq[q];
-    for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += kPostWaves * 4) {
-      const int64_t e = e0 + grp;
-      const bool ok = e < nsel;
-      const int64_t i = (int64_t)sk[ok ? e : e0];
-      const uint4* arow = (const uint4*)((const char*)a.Alp + i * rowb);
-      float acc = 0.0f;
-      for (int64_t c16 = gl; c16 < rowb / 16; c16 += 16)
-        acc = lowp_dot16(arow[c16], qrow[c16], a.lp, acc);
+    // kScrU rounds of 4 candidates per wave at once, as in post2 below
+    constexpr int kScrU = 4;
+    const int64_t round = kPostWaves * 4;
+    for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += round * kScrU) {
+      const uint4* arow[kScrU];
+      int64_t iu[kScrU];
+      float acc[kScrU];
 #pragma unroll
-      for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      if (ok && gl == 0) {
-        const VecInfo va = a.ia[i];
-        const float c = acc * va.inv_s * vq.inv_s;
-        const float mg = a.kappa * va.n2 * vq.n2 +
-                         a.onepu * (va.eta * vq.n1 + vq.eta * va.n1) +
-                         a.d_f * va.eta * vq.eta;
-        const float lo = fabsf(c) - mg;
-        sab[e] = __float_as_uint(lo > 0.0f ? lo : 0.0f);
-        sc[e] = fabsf(c) + mg;
+      for (int u = 0; u < kScrU; ++u) {
+        const int64_t e = e0 + grp + u * round;
+        iu[u] = (int64_t)sk[e < nsel ? e : e0];
+        arow[u] = (const uint4*)((const char*)a.Alp + iu[u] * rowb);
+        acc[u] = 0.0f;
+      }
+      for (int64_t c16 = gl; c16 < rowb / 16; c16 += 16) {
+        const uint4 y = qrow[c16];
+        uint4 x[kScrU];
+#pragma unroll
+        for (int u = 0; u < kScrU; ++u) x[u] = arow[u][c16];
+#pragma unroll
+        for (int u = 0; u < kScrU; ++u)
+          acc[u] = lowp_dot16(x[u], y, a.lp, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kScrU; ++u) {
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1)
+          acc[u] += __shfl_xor(acc[u], off, 64);
+        const int64_t e = e0 + grp + u * round;
+        if (e < nsel && gl == 0) {
+          const VecInfo va = a.ia[iu[u]];
+          const float c = acc[u] * va.inv_s * vq.inv_s;
+          const float mg = a.kappa * va.n2 * vq.n2 +
+                           a.onepu * (va.eta * vq.n1 + vq.eta * va.n1) +
+                           a.d_f * va.eta * vq.eta;
+          const float lo = fabsf(c) - mg;
+          sab[e] = __float_as_uint(lo > 0.0f ? lo : 0.0f);
+          sc[e] = fabsf(c) + mg;
+        }
       }
     }
     __syncthreads();
@@ -435,41 +455,63 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
   }
   if (t == 0) ps.base = 0;
   __syncthreads();
-  // post2: c = a_i . q in fp32; 16 lanes per candidate and 4 candidates
-  // per wave, rows read as float4 when d is a multiple of 4
+  // post2: c = a_i . q in fp32; 16 lanes per candidate, 4 candidates per
+  // wave and kVerU rounds of them at once (their row loads in flight
+  // together), rows read as float4 when d is a multiple of 4
+  constexpr int kVerU = 4;
+  const int64_t round = kPostWaves * 4;  // candidates per block round
   const bool vec = (a.d & 3) == 0 && ((uintptr_t)a.A & 15) == 0;
   unsigned nfp = 0;
-  for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += kPostWaves * 4) {
-    const int64_t e = e0 + grp;
-    const bool ok = e < nsel;
-    const bool need = ok && (!screen || sc[e] >= tau);
-    if (!need) {
-      if (ok && gl == 0) {  // screened out: never among the top t
+  for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += round * kVerU) {
+    bool need[kVerU];
+    const float* ar[kVerU];
+    float acc[kVerU];
+#pragma unroll
+    for (int u = 0; u < kVerU; ++u) {
+      const int64_t e = e0 + grp + u * round;
+      const bool ok = e < nsel;
+      need[u] = ok && (!screen || sc[e] >= tau);
+      if (ok && !need[u] && gl == 0) {  // screened out: never in the top t
         sc[e] = 0.0f;
         sab[e] = 0;
       }
-      continue;
+      ar[u] = a.A + (int64_t)sk[need[u] ? e : e0] * a.d;
+      acc[u] = 0.0f;
     }
-    nfp += gl == 0;
-    const float* ar = a.A + (int64_t)sk[e] * a.d;
-    float acc = 0.0f;
     if (vec) {
       for (int64_t k = gl * 4; k < a.d; k += 64) {
-        const float4 x = *(const float4*)(ar + k);
         const float4 y = *(const float4*)(qs + k);
-        acc = fmaf(x.x, y.x, acc);
-        acc = fmaf(x.y, y.y, acc);
-        acc = fmaf(x.z, y.z, acc);
-        acc = fmaf(x.w, y.w, acc);
+        float4 x[kVerU];
+#pragma unroll
+        for (int u = 0; u < kVerU; ++u)
+          x[u] = need[u] ? *(const float4*)(ar[u] + k)
+                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < kVerU; ++u) {
+          acc[u] = fmaf(x[u].x, y.x, acc[u]);
+          acc[u] = fmaf(x[u].y, y.y, acc[u]);
+          acc[u] = fmaf(x[u].z, y.z, acc[u]);
+          acc[u] = fmaf(x[u].w, y.w, acc[u]);
+        }
       }
     } else {
-      for (int64_t k = gl; k < a.d; k += 16) acc = fmaf(ar[k], qs[k], acc);
+#pragma unroll
+      for (int u = 0; u < kVerU; ++u)
+        if (need[u])
+          for (int64_t k = gl; k < a.d; k += 16)
+            acc[u] = fmaf(ar[u][k], qs[k], acc[u]);
     }
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (gl == 0) {
-      sc[e] = acc;
-      sab[e] = __float_as_uint(fabsf(acc));
+    for (int u = 0; u < kVerU; ++u) {
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1)
+        acc[u] += __shfl_xor(acc[u], off, 64);
+      if (need[u] && gl == 0) {
+        const int64_t e = e0 + grp + u * round;
+        sc[e] = acc[u];
+        sab[e] = __float_as_uint(fabsf(acc[u]));
+        ++nfp;
+      }
     }
   }
   if (nfp) atomicAdd((unsigned long long*)&ps.base, (unsigned long long)nfp);
