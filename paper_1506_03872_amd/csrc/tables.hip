@@ -423,12 +423,12 @@ static hipError_t small_tables(W w, int64_t S, int64_t N, int L, double* tot,
   if (S <= 0 || N <= 0) return hipSuccess;
   const int Np = 1 << L;
   // the most tables per block (a power of two, 4 .. 64) within the LDS
-  // budget; about 20 KB measured best (MAD_SMALL_LDS overrides it for
+  // budget; about 32 KB measured best (MAD_SMALL_LDS overrides it for
   // tuning)
   static const size_t budget = [] {
     const char* e = getenv("MAD_SMALL_LDS");
-    const long v = e ? atol(e) : 20480;
-    return (size_t)(v >= 4096 && v <= 65536 ? v : 20480);
+    const long v = e ? atol(e) : 32768;
+    return (size_t)(v >= 4096 && v <= 65536 ? v : 32768);
   }();
   auto lds_for = [Np](int tb) {
     return ((size_t)tb * (Np + 1) + (size_t)tb * 4 + (size_t)Np * 10) * 8;
