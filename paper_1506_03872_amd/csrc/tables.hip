@@ -789,20 +789,23 @@ __global__ __launch_bounds__(64) void k_col_runoffsets(const double* rtot,
 // One wave per (slot run c, 64 consecutive tables of [s0, s0 + ns)), lane
 // = table.  LISTS = false: the run's statistics into bs[t * B + c];
 // LISTS = true: bs holds the exclusive offsets and the lists are written
-// (positions relative to table t's base t << L).  Each group of kColGroup
-// items passes through LDS as (list value with the heavy flag in bit 63,
-// slot id with the sign in bit 31) per (item, table); then, two tables at
-// a time (one per half-wave, lane = item), ballots give every entry its
-// place and each table's lights and heavies of the group are stored as
+// (positions relative to table t's base t << L).  Each group of 16 items
+// passes through LDS as (list value with the heavy flag in bit 63, slot id
+// with the sign in bit 31) per (item, table); then, four tables at a time
+// (one per quarter-wave, lane = item), ballots give every entry its place
+// and each table's lights and heavies of the group are stored as
 // contiguous runs.
 template <bool LISTS, bool SCALE>
 __global__ __launch_bounds__(64) void k_col_walk(
     const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
     int L, const double* E, const double* tot, int64_t s0, int64_t ns,
     Quad* bs, uint64_t* Ld, uint32_t* Li, uint64_t* He, uint32_t* Hi) {
-  static_assert(kColGroup == 32, "two tables per wave in the write-out");
-  __shared__ uint64_t tv[LISTS ? kColGroup : 1][65];
-  __shared__ uint32_t ti[LISTS ? kColGroup : 1][65];
+  // items per group: 32 for the statistics; 16 for the lists, so that the
+  // LDS staging (12.5 KB) lets more waves share a CU
+  constexpr int G = LISTS ? 16 : kColGroup;
+  static_assert(G == 16 || !LISTS, "four tables per wave in the write-out");
+  __shared__ uint64_t tv[LISTS ? G : 1][65];
+  __shared__ uint32_t ti[LISTS ? G : 1][65];
   __shared__ uint64_t cnt0[LISTS ? 64 : 1][2];  // lights / heavies before
   const int64_t B = (int64_t(1) << L) / kRun;  // slot runs per table
   const int64_t tiles = (ns + 63) / 64;
@@ -832,19 +835,19 @@ __global__ __launch_bounds__(64) void k_col_walk(
     ea = o.se;
   }
   double l = 0.0;
-  for (int64_t g0 = r0; g0 < r0 + kRun; g0 += kColGroup) {
-    float xv[kColGroup];
-    double sv[kColGroup];
+  for (int64_t g0 = r0; g0 < r0 + kRun; g0 += G) {
+    float xv[G];
+    double sv[G];
     if (g0 < r1) {
 #pragma unroll
-      for (int u = 0; u < kColGroup; ++u) {
+      for (int u = 0; u < G; ++u) {
         const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
         xv[u] = X[r * d + seg];
         sv[u] = SCALE ? scale[r] : 1.0;
       }
     } else {  // padding slots only
 #pragma unroll
-      for (int u = 0; u < kColGroup; ++u) {
+      for (int u = 0; u < G; ++u) {
         xv[u] = 0.0f;
         sv[u] = 1.0;
       }
@@ -856,7 +859,7 @@ __global__ __launch_bounds__(64) void k_col_walk(
     // no branch per item: only the additions of l form a dependent chain,
     // so the divisions of consecutive items overlap
 #pragma unroll
-    for (int u = 0; u < kColGroup; ++u) {
+    for (int u = 0; u < G; ++u) {
       const int64_t r = g0 + u;
       const bool ok = live && r < r1;
       const double w = SCALE ? fabs((double)xv[u]) * sv[u]
@@ -878,12 +881,12 @@ __global__ __launch_bounds__(64) void k_col_walk(
     }
     if (LISTS) {
       __syncthreads();
-      // write-out: half-wave h takes table j = p2 + h, lane & 31 = item
-      const int h = lane >> 5, u = lane & 31;
+      // write-out: quarter-wave h takes table j = p4 + h, lane & 15 = item
+      const int h = lane >> 4, u = lane & 15;
       const uint64_t lt = (1ull << lane) - 1;
-      const uint64_t half = h ? 0xFFFFFFFF00000000ull : 0xFFFFFFFFull;
-      for (int p2 = 0; p2 < 64; p2 += 2) {
-        const int j = p2 + h;
+      const uint64_t half = 0xFFFFull << (16 * h);
+      for (int p4 = 0; p4 < 64; p4 += 4) {
+        const int j = p4 + h;
         const bool ok = t0 + j < ns;
         const uint64_t v = tv[u][j];
         const uint32_t id = ti[u][j];
