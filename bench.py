@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--unit-values", action="store_true",
+                    help="sparse configs: every stored value 1 (0/1 inputs)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the time-to-recall sweep")
     return ap.parse_args()
@@ -307,6 +309,9 @@ def bench_csr(args, cfg, data, mad):
     import numpy as np
     import torch
     a, b, m, n = data["a"], data["b"], data["m"], data["n"]
+    if args.unit_values:
+        a = (a[0], a[1], np.ones_like(a[2]))
+        b = (b[0], b[1], np.ones_like(b[2]))
     d = cfg["d"]
     s, tp, t = cfg["s"], cfg["t_prime"], cfg["t"]
     ta = tuple(torch.from_numpy(x).cuda() for x in a)
@@ -357,7 +362,9 @@ def bench_csr(args, cfg, data, mad):
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+int64", "data": "synthetic",
-        "config": {"workload": "powerlaw_csr_%s" % args.config, "m": m,
+        "config": {"workload": "powerlaw_csr_%s%s" % (
+                       "unit_" if args.unit_values else "", args.config),
+                   "m": m,
                    "n": n, "d": d, "nnz_per_vector": cfg["nnz"],
                    "zipf": cfg["zipf"], "s": s, "t_prime": tp, "t": t,
                    "seed": args.seed},

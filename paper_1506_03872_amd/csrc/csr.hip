@@ -1102,6 +1102,7 @@ void csr_tables_free(CsrTables& t) {
   t.om = nullptr;
   t.bmax = nullptr;
   t.bad = nullptr;
+  t.b_unit = nullptr;
   dev_free(t.work);
 }
 
@@ -1192,7 +1193,27 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
 }
 
 // the tables from the transposes and the layouts already in place
+// 1 in *flag unless some stored value differs from 1 (then 0): for 0/1
+// inputs a fourth edge that is present is 1, and the sampler skips its load
+__global__ void k_unit_check(const float* v, int64_t n, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += stride)
+    if (v[e] != 1.0f) {
+      *flag = 0;  // every writer stores the same value
+      return;
+    }
+}
+
 static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
+  // B's unit-value flag lives in the spare words of t.bad's allocation
+  t.b_unit = t.bad + 32;
+  hipError_t eu = launch_fill_u64((uint64_t*)t.b_unit, 1, 1ull, st);
+  if (eu != hipSuccess) return eu;
+  if (t.nnzB > 0)
+    k_unit_check<<<blocks_of(t.nnzB, 256 * 16) < 1024
+                       ? blocks_of(t.nnzB, 256 * 16) : 1024,
+                   256, 0, st>>>(t.in.b_val, t.nnzB, t.b_unit);
   hipError_t e;
   const int64_t d = t.d;
   // T3 (totals na), T1 (weights |a_ki| na_i, totals v), T2 (totals nb), T0
@@ -1227,6 +1248,7 @@ struct CsrSampleArgs {
   uint64_t seed, qid;
   int64_t l0, count;
   int gram;  // B = A: key of the pair with i < j, diagonal left out
+  const int* b_unit;  // 1: every value of B is 1 (no fourth-edge value load)
 };
 
 __device__ __forceinline__ Drawn draw16(const Ent16& e, uint64_t U) {
@@ -1262,6 +1284,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
   __syncthreads();
   const uint64_t* T0 = t0_lds ? t0s : a.T0;
   const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
+  const bool unit = *a.b_unit != 0;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long nclosed = 0, ncreated = 0;
@@ -1324,7 +1347,9 @@ __global__ __launch_bounds__(256) void k_sample_csr(
         const int64_t mid = (l + h) >> 1;
         if (a.in.b_idx[mid] < key) l = mid + 1; else h = mid;
       }
-      v[u] = (l < hi[u] && a.in.b_idx[l] == key) ? a.in.b_val[l] : 0.0f;
+      v[u] = (l < hi[u] && a.in.b_idx[l] == key)
+                 ? (unit ? 1.0f : a.in.b_val[l])
+                 : 0.0f;
     }
     int64_t inc[U];
     bool closed[U];
@@ -1448,6 +1473,7 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.l0 = l0;
   a.count = count;
   a.gram = t.gram;
+  a.b_unit = t.b_unit;
   return a;
 }
 

@@ -187,6 +187,7 @@ struct CsrTables {
   double* om = nullptr;   // d
   float* bmax = nullptr;  // 1
   int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
+  int* b_unit = nullptr;  // 1: every stored value of B is 1 (in bad's block)
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.3)
   bool validated = false; // the structure passed a check on this plan

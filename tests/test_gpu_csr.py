@@ -92,8 +92,18 @@ def _powerlaw_big():
     return a, b, m, n, d
 
 
+def _unit_values():
+    # 0/1 inputs: every stored value is 1, so the sampler takes a present
+    # fourth edge as 1 without loading it; A keeps one value of 2 so that
+    # only B is all ones (the flag is B's)
+    a, b, m, n, d = _powerlaw()
+    av = np.ones_like(a[2])
+    av[3] = 2.0
+    return (a[0], a[1], av), (b[0], b[1], np.ones_like(b[2])), m, n, d
+
+
 CASES = {"powerlaw": _powerlaw, "ragged": _ragged, "zeros": _explicit_zeros,
-         "d1": _d1, "dense_as_csr": _dense_as_csr}
+         "d1": _d1, "dense_as_csr": _dense_as_csr, "unit": _unit_values}
 # tables and sample streams only
 CASES_BIG = {"powerlaw_big": _powerlaw_big}
 
