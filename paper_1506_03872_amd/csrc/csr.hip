@@ -434,7 +434,11 @@ struct ColItems {  // T1 / T2: vectors with an entry at k; item = vector
   const float* tval;
   const uint32_t* trow;
   const double* scale;  // na for T1, null for T2
+  // T1: the weights |a_ki| na_i computed once per build (k_col_scaled), so
+  // that the passes over the table do not each gather na
+  const double* wpre = nullptr;
   __device__ double w(int64_t p) const {
+    if (wpre) return wpre[p];
     const double a = fabs((double)tval[p]);
     return scale ? a * scale[trow[p]] : a;
   }
@@ -1091,13 +1095,14 @@ void csr_tables_free(CsrTables& t) {
   ragged_free(t.T3);
   family_free_pub(t.T0);
   void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
-                t.bt_val, t.bt_src, t.om, t.bmax, t.bad};
+                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
   t.at_row = t.bt_row = nullptr;
   t.at_val = t.bt_val = nullptr;
   t.at_src = t.bt_src = nullptr;
+  t.at_w = nullptr;
   t.structured = false;
   t.om = nullptr;
   t.bmax = nullptr;
@@ -1124,6 +1129,7 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = hipMalloc(&t.bt_val, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_src, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = hipMalloc(&t.bt_src, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.at_w, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
       return e;
   }
@@ -1205,6 +1211,15 @@ __global__ void k_unit_check(const float* v, int64_t n, int* flag) {
     }
 }
 
+// w[p] = |tval[p]| * scale[trow[p]]: the same product ColItems forms
+__global__ void k_col_scaled(const float* tval, const uint32_t* trow,
+                             const double* scale, int64_t n, double* w) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += stride)
+    w[p] = fabs((double)tval[p]) * scale[trow[p]];
+}
+
 static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
   // B's unit-value flag lives in the spare words of t.bad's allocation
   t.b_unit = t.bad + 32;
@@ -1218,8 +1233,15 @@ static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
   const int64_t d = t.d;
   // T3 (totals na), T1 (weights |a_ki| na_i, totals v), T2 (totals nb), T0
   if ((e = ragged_build(t.T3, RowItems{t.in.a_val, t.in.a_idx}, t.work.p,
-                        st)) != hipSuccess ||
-      (e = ragged_build(t.T1, ColItems{t.at_val, t.at_row, t.T3.tot},
+                        st)) != hipSuccess)
+    return e;
+  if (t.nnzA > 0)
+    k_col_scaled<<<blocks_of(t.nnzA, 256 * 8) < 2048
+                       ? blocks_of(t.nnzA, 256 * 8) : 2048,
+                   256, 0, st>>>(t.at_val, t.at_row, t.T3.tot, t.nnzA,
+                                 t.at_w);
+  if ((e = ragged_build(t.T1,
+                        ColItems{t.at_val, t.at_row, t.T3.tot, t.at_w},
                         t.work.p, st)) != hipSuccess ||
       (e = ragged_build(t.T2, ColItems{t.bt_val, t.bt_row, nullptr},
                         t.work.p, st)) != hipSuccess)

@@ -198,6 +198,7 @@ struct CsrTables {
   bool structured = false;
   uint32_t* at_src = nullptr; // nnzA
   uint32_t* bt_src = nullptr; // nnzB
+  double* at_w = nullptr;     // nnzA: T1 weights |a_ki| na_i of this build
 };
 
 // Allocates and builds every table (synchronises: the layout of the
