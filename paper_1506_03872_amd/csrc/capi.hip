@@ -104,7 +104,7 @@ struct mad_plan {
   mad::DeviceBuffer lpA, lpB, lpIA, lpIB;
   mad::LowpView lv{};
   // workspace of mad_plan_topk
-  mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, misc, ord, acc;
+  mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, cr, misc, ord, acc;
   mad::HashTable h;
   bool pairs = false;  // X built from per-sample pairs (else a hash table)
   mad::HashTable h_run;  // X as the last run left it
@@ -163,6 +163,7 @@ static void plan_free_all(mad_plan* p) {
   mad::dev_free(p->cx2);
   mad::dev_free(p->ck2);
   mad::dev_free(p->cc);
+  mad::dev_free(p->cr);
   mad::dev_free(p->misc);
   mad::dev_free(p->ord);
   mad::dev_free(p->acc);
@@ -319,6 +320,8 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   int64_t ccap = pairs > 1 ? pairs : 1;
   if (ccap < 4 * t2 + 4 * tp2) ccap = 4 * t2 + 4 * tp2;
   const int64_t ccap2 = tp2 > 1 ? tp2 : 1;
+  // post1's refined boundary list (one digit's bin of a long boundary list)
+  const int64_t rcap = ccap < (int64_t(1) << 21) ? ccap : (int64_t(1) << 21);
   (void)hipDeviceSynchronize();
   hipError_t e;
   if ((e = mad::dev_alloc(p->hk, 8 * (size_t)hcap)) != hipSuccess ||
@@ -328,6 +331,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
       (e = mad::dev_alloc(p->cx2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->ck2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->cc, 4 * (size_t)ccap2)) != hipSuccess ||
+      (e = mad::dev_alloc(p->cr, 16 * (size_t)rcap)) != hipSuccess ||
       (e = mad::dev_alloc(p->misc, mad::kSelStateBytes + 4 * mad::kSelBins +
                                        256 + 256)) != hipSuccess ||
       (p->kind == 0 &&
@@ -350,6 +354,9 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   p->w.c = (float*)p->cc.p;
   p->w.cap = ccap;
   p->w.cap2 = ccap2;
+  p->w.rx = (uint64_t*)p->cr.p;
+  p->w.rkey = p->w.rx + rcap;
+  p->w.rcap = rcap;
   char* misc = (char*)p->misc.p;
   p->w.state = misc;
   p->w.hist = (unsigned*)(misc + mad::kSelStateBytes);

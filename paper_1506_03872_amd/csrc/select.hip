@@ -45,6 +45,21 @@ struct Coarse {
   int64_t bin;    // boundary bin (-1: take everything)
 };
 
+// post1 boundary refinement: one full-grid radix pass over a long boundary
+// list (ties of x leave millions of elements in one coarse bin), so that the
+// single-workgroup step 3 starts from one digit's bin of it
+struct Refine {
+  uint64_t xand, xor_, kand, kor;  // over the boundary list (k_score_split)
+  uint64_t mask, prefix;           // the chosen digit's bin and bits above
+  int64_t key_phase;               // 1: the digit is one of the key's
+  int64_t active;                  // refined list in use
+  unsigned long long nout;         // refined list length
+  int64_t pad[3];
+};
+static_assert(3 * sizeof(Coarse) + sizeof(Refine) <= kSelStateBytes,
+              "select state");
+constexpr int kRefineMin = 4096;   // shorter lists go to step 3 as they are
+
 static inline unsigned blocks_for(int64_t n, int per_block, int cap) {
   int64_t g = (n + per_block - 1) / per_block;
   if (g > cap) g = cap;
@@ -107,16 +122,13 @@ __global__ __launch_bounds__(kHistThreads) void k_score_hist(
 // step 2a (one block): the boundary bin from the histogram, then clear it.
 // The element count is *n_ptr, or the histogram's total when n_ptr is
 // null; n_store (if set) receives it.
-__global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
-                                                       const int64_t* n_ptr,
-                                                       int64_t k,
-                                                       Coarse* out,
-                                                       int64_t* n_store) {
-  __shared__ unsigned long long part[256];
+__global__ __launch_bounds__(256) void k_coarse_decide(
+    unsigned* hist, const int64_t* n_ptr, int64_t k, Coarse* out,
+    int64_t* n_store, Refine* rf = nullptr) {
+  __shared__ unsigned long long wsum[4];
   __shared__ int chosen;
   __shared__ unsigned long long before;
-  __shared__ long long total;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   if (t == 0) chosen = -1;
   // thread t owns 8 consecutive bins in descending order
   unsigned v[8];
@@ -125,21 +137,17 @@ __global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
     v[q] = hist[kBins - 1 - (t * 8 + q)];
     sum += v[q];
   }
-  part[t] = sum;
+  const unsigned long long winc = wave_incl_scan(sum);
+  if (lane == 63) wsum[wv] = winc;
   __syncthreads();
-  if (t == 0) {
-    unsigned long long acc = 0;
-    for (int u = 0; u < 256; ++u) {
-      const unsigned long long x = part[u];
-      part[u] = acc;
-      acc += x;
-    }
-    total = (long long)acc;
+  unsigned long long woff = 0, total = 0;
+  for (int w = 0; w < 4; ++w) {
+    woff += w < wv ? wsum[w] : 0ull;
+    total += wsum[w];
   }
-  __syncthreads();
   const int64_t n = n_ptr ? *n_ptr : (int64_t)total;
   if (n > k) {
-    unsigned long long acc = part[t];
+    unsigned long long acc = woff + winc - sum;
     for (int q = 0; q < 8; ++q) {
       if ((long long)acc < k && (long long)(acc + v[q]) >= k) {
         chosen = kBins - 1 - (t * 8 + q);
@@ -151,6 +159,12 @@ __global__ __launch_bounds__(256) void k_coarse_decide(unsigned* hist,
   __syncthreads();
   for (int b = t; b < kBins; b += 256) hist[b] = 0;  // ready for reuse
   if (t == 0) {
+    if (rf) {
+      rf->xand = rf->kand = ~0ull;
+      rf->xor_ = rf->kor = 0ull;
+      rf->active = 0;
+      rf->nout = 0ull;
+    }
     if (n_store) *n_store = n;
     out->n = n;
     out->k = k;
@@ -201,11 +215,13 @@ __global__ __launch_bounds__(256) void k_score_split(
     const uint64_t* hkeys, const int64_t* hvals, int64_t cap,
     const int64_t* live, const Coarse* cz, uint64_t* wx, uint64_t* wkey,
     int64_t wcap, uint64_t* bx, uint64_t* bkey, int64_t bcap,
-    int64_t* counts) {
+    int64_t* counts, Refine* rf) {
   __shared__ unsigned long long sx[2][kStage];
   __shared__ unsigned long long sk[2][kStage];
   __shared__ unsigned scnt[2];
   __shared__ unsigned long long gbase[2];
+  __shared__ unsigned long long red[4][4];
+  uint64_t xa = ~0ull, xo = 0ull, ka = ~0ull, ko = 0ull;
   const Coarse c = *cz;
   if (live && *live < cap) cap = *live;
   const int t = threadIdx.x;
@@ -233,8 +249,15 @@ __global__ __launch_bounds__(256) void k_score_split(
         const int L = (c.bin < 0 || bin > c.bin) ? 0 : (bin == c.bin ? 1 : -1);
         if (L < 0) continue;
         const unsigned p = atomicAdd(&scnt[L], 1u);
+        const uint64_t kk = hkeys[b0 + t + (int64_t)u * 256];
         sx[L][p] = (unsigned long long)v[u];
-        sk[L][p] = hkeys[b0 + t + (int64_t)u * 256];
+        sk[L][p] = kk;
+        if (L) {
+          xa &= (uint64_t)v[u];
+          xo |= (uint64_t)v[u];
+          ka &= kk;
+          ko |= kk;
+        }
       }
     }
     __syncthreads();
@@ -263,6 +286,175 @@ __global__ __launch_bounds__(256) void k_score_split(
       __syncthreads();
     }
   }
+  // and / or of the boundary elements: one set of atomics per block that
+  // holds any
+  for (int off = 32; off > 0; off >>= 1) {
+    xa &= __shfl_xor(xa, off, 64);
+    xo |= __shfl_xor(xo, off, 64);
+    ka &= __shfl_xor(ka, off, 64);
+    ko |= __shfl_xor(ko, off, 64);
+  }
+  const int wv = t >> 6;
+  if ((t & 63) == 0) {
+    red[0][wv] = xa;
+    red[1][wv] = xo;
+    red[2][wv] = ka;
+    red[3][wv] = ko;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < 4; ++w) {
+      xa &= red[0][w];
+      xo |= red[1][w];
+      ka &= red[2][w];
+      ko |= red[3][w];
+    }
+    if (xo != 0ull) {  // boundary elements have x > 0
+      atomicAnd((unsigned long long*)&rf->xand, (unsigned long long)xa);
+      atomicOr((unsigned long long*)&rf->xor_, (unsigned long long)xo);
+      atomicAnd((unsigned long long*)&rf->kand, (unsigned long long)ka);
+      atomicOr((unsigned long long*)&rf->kor, (unsigned long long)ko);
+    }
+  }
+}
+
+// the refinement digit: the 11 bits below the highest bit in which the
+// boundary list's x values differ, or its keys when every x is equal
+struct RefineDigit {
+  bool key_phase;
+  int shift;
+  uint64_t above;   // bits above the digit, shared by the whole list
+  uint64_t common;  // their value
+};
+
+__device__ __forceinline__ RefineDigit refine_digit(const Refine& r) {
+  RefineDigit g;
+  const uint64_t dx = r.xand ^ r.xor_;
+  g.key_phase = dx == 0ull;
+  const uint64_t diff = g.key_phase ? (r.kand ^ r.kor) : dx;
+  const int hd = diff ? 63 - __clzll((long long)diff) : 0;
+  g.shift = hd >= kDigit - 1 ? hd - (kDigit - 1) : 0;
+  g.above = hd < 63 ? ~0ull << (hd + 1) : 0ull;
+  g.common = (g.key_phase ? r.kand : r.xand) & g.above;
+  return g;
+}
+
+// is the boundary list refined: long, and not taken whole
+__device__ __forceinline__ bool refine_wanted(const Coarse& c, int64_t nb) {
+  return c.bin >= 0 && c.k_rem > 0 && c.k_rem < nb && nb > kRefineMin;
+}
+
+// refinement 1/3: histogram of the digit over the boundary list
+constexpr int kRefineThreads = 1024;
+
+__global__ __launch_bounds__(kRefineThreads) void k_refine_hist(
+    const Coarse* cz, const Refine* rf, const uint64_t* bx,
+    const uint64_t* bkey, int64_t bcap, const int64_t* counts,
+    unsigned* hist) {
+  __shared__ unsigned h[kBins];
+  int64_t nb = counts[kCntBound];
+  if (nb > bcap) nb = bcap;
+  if (!refine_wanted(*cz, nb)) return;
+  const RefineDigit g = refine_digit(*rf);
+  const uint64_t* v = g.key_phase ? bkey : bx;
+  for (int b = threadIdx.x; b < kBins; b += kRefineThreads) h[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kRefineThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kRefineThreads + threadIdx.x;
+       e < nb; e += stride)
+    atomicAdd(&h[(v[e] >> g.shift) & kDigitMask], 1u);
+  block_hist_flush(h, hist);
+}
+
+// refinement 2/3 (one block): the bin of the digit that holds the k_rem-th
+// element in selection order (x descending, or key ascending); clears the
+// histogram
+__global__ __launch_bounds__(kRefineThreads) void k_refine_decide(
+    Coarse* cz, Refine* rf, const int64_t* counts, int64_t bcap,
+    int64_t rcap, unsigned* hist) {
+  __shared__ unsigned long long wsum[kRefineThreads / 64];
+  __shared__ int chosen;
+  __shared__ unsigned long long before;
+  int64_t nb = counts[kCntBound];
+  if (nb > bcap) nb = bcap;
+  const Coarse c = *cz;
+  if (!refine_wanted(c, nb)) return;
+  const RefineDigit g = refine_digit(*rf);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // thread t owns positions 2t and 2t+1 of the selection order
+  const int b0 = g.key_phase ? 2 * t : kBins - 1 - 2 * t;
+  const int b1 = g.key_phase ? 2 * t + 1 : kBins - 2 - 2 * t;
+  const unsigned v0 = hist[b0], v1 = hist[b1];
+  const unsigned long long pair = (unsigned long long)v0 + v1;
+  const unsigned long long winc = wave_incl_scan(pair);
+  if (lane == 63) wsum[wv] = winc;
+  if (t == 0) chosen = -1;
+  __syncthreads();
+  unsigned long long woff = 0;
+  for (int w = 0; w < wv; ++w) woff += wsum[w];
+  const unsigned long long excl = woff + winc - pair;
+  const int64_t k = c.k_rem;
+  if ((int64_t)excl < k && (int64_t)(excl + v0) >= k) {
+    chosen = b0;
+    before = excl;
+  } else if ((int64_t)(excl + v0) < k && (int64_t)(excl + v0 + v1) >= k) {
+    chosen = b1;
+    before = excl + v0;
+  }
+  __syncthreads();
+  const int b = chosen;
+  const unsigned nbin = b >= 0 ? hist[b] : 0u;
+  __syncthreads();
+  hist[b0] = 0;
+  hist[b1] = 0;
+  // a bin longer than the refined list's room stays unrefined (step 3 then
+  // reads the whole list)
+  if (t == 0 && b >= 0 && (int64_t)nbin <= rcap) {
+    rf->mask = g.above | (kDigitMask << g.shift);
+    rf->prefix = g.common | ((uint64_t)b << g.shift);
+    rf->key_phase = g.key_phase ? 1 : 0;
+    rf->active = 1;
+    cz->k_rem = k - (int64_t)before;
+  }
+}
+
+// refinement 3/3: elements ordered before the chosen bin join the winners,
+// the bin's elements form the refined list
+__global__ __launch_bounds__(256) void k_refine_split(
+    const Refine* rf, const uint64_t* bx, const uint64_t* bkey, int64_t bcap,
+    int64_t* counts, uint64_t* wx, uint64_t* wkey, int64_t wcap,
+    unsigned long long* nout, uint64_t* rx, uint64_t* rkey, int64_t rcap) {
+  __shared__ unsigned wcount[4];
+  __shared__ unsigned long long wbase[5];
+  if (!rf->active) return;
+  int64_t nb = counts[kCntBound];
+  if (nb > bcap) nb = bcap;
+  const uint64_t mask = rf->mask, prefix = rf->prefix;
+  const bool kp = rf->key_phase != 0;
+  for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < nb;
+       b0 += (int64_t)gridDim.x * 256) {
+    const int64_t e = b0 + threadIdx.x;
+    uint64_t p = 0, kk = 0;
+    bool better = false, match = false;
+    if (e < nb) {
+      p = bx[e];
+      kk = bkey[e];
+      const uint64_t m = (kp ? kk : p) & mask;
+      better = kp ? m < prefix : m > prefix;
+      match = m == prefix;
+    }
+    const int64_t sw = block_append(
+        better, (unsigned long long*)&counts[kCntWin], wcount, wbase);
+    if (better && sw < wcap) {
+      wx[sw] = p;
+      wkey[sw] = kk;
+    }
+    const int64_t sr = block_append(match, nout, wcount, wbase);
+    if (match && sr < rcap) {
+      rx[sr] = p;
+      rkey[sr] = kk;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +469,9 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
     const Coarse* cz, const uint64_t* bx, const uint64_t* bkey,
     const uint64_t* bextra, const float* bc, int64_t bcap, int64_t* counts,
     int win_slot, uint64_t* ox, uint64_t* okey, uint64_t* oextra, float* oc,
-    int64_t ocap, int out_count_slot) {
+    int64_t ocap, int out_count_slot, const Refine* rf = nullptr,
+    const uint64_t* rx = nullptr, const uint64_t* rkey = nullptr,
+    int64_t rcap = 0) {
   __shared__ unsigned h[kBins];
   __shared__ unsigned long long wsum[kFineThreads / 64];
   __shared__ uint64_t lx[kFineLds], lk[kFineLds];
@@ -290,6 +484,11 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
   const int64_t nwin = counts[win_slot] < ocap ? counts[win_slot] : ocap;
   int64_t nb = counts[kCntBound];
   if (nb > bcap) nb = bcap;
+  if (rf && rf->active) {  // the refined list (no extra / c columns)
+    bx = rx;
+    bkey = rkey;
+    nb = (int64_t)rf->nout < rcap ? (int64_t)rf->nout : rcap;
+  }
   const bool none = c.bin < 0 || c.k_rem <= 0;
   int64_t k_rem = none ? 0 : c.k_rem;
   // the list in LDS when it fits
@@ -863,15 +1062,25 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   // ---- post1: top t' of x over x > 0 ------------------------------------
   k_score_hist<<<blocks_for(h.cap, kHistThreads * 16, kHistBlocks),
                  kHistThreads, 0, st>>>(h.vals, h.cap, h.live, w.hist);
+  Refine* rf = (Refine*)(cz + 3);
   k_coarse_decide<<<1, 256, 0, st>>>(w.hist, nullptr, t_prime, cz,
-                                     &counts[kCntPos]);
+                                     &counts[kCntPos], rf);
   // winners go straight to (x2, key2); the boundary bin to (x, key)
   k_score_split<<<blocks_for(h.cap, 256 * 16, 512), 256, 0, st>>>(
       h.keys, h.vals, h.cap, h.live, cz, w.x2, w.key2, w.cap2, w.x, w.key,
-      w.cap, counts);
+      w.cap, counts, rf);
+  // a long boundary list: one digit of it on the whole grid (each kernel
+  // returns at once otherwise)
+  k_refine_hist<<<256, kRefineThreads, 0, st>>>(cz, rf, w.x, w.key, w.cap,
+                                                counts, w.hist);
+  k_refine_decide<<<1, kRefineThreads, 0, st>>>(cz, rf, counts, w.cap,
+                                                w.rcap, w.hist);
+  k_refine_split<<<1024, 256, 0, st>>>(rf, w.x, w.key, w.cap, counts, w.x2,
+                                       w.key2, w.cap2, &rf->nout, w.rx,
+                                       w.rkey, w.rcap);
   k_fine_select<<<1, kFineThreads, 0, st>>>(
       cz, w.x, w.key, nullptr, nullptr, w.cap, counts, kCntWin, w.x2, w.key2,
-      nullptr, nullptr, w.cap2, kCntCand);
+      nullptr, nullptr, w.cap2, kCntCand, rf, w.rx, w.rkey, w.rcap);
   // ---- low-precision filter of Omega_t' ----------------------------------
   if (lowp) {
     e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
