@@ -16,6 +16,9 @@
 //      element are taken outright, that bin's elements go to a boundary list;
 //   3. one workgroup selects exactly the remaining count from the boundary
 //      list with 11-bit radix passes over the primary and then the key.
+// In post1 a boundary list of more than kRefineMin elements first gets one
+// such radix pass on the whole grid (histogram, decision, split), so that
+// step 3 reads one digit's bin of it.
 #include "mad_common.hpp"
 #include "plan.hpp"
 
