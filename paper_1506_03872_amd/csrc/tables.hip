@@ -585,32 +585,58 @@ __global__ __launch_bounds__(256) void k_alias_merge(
   __shared__ uint32_t sLi[kMergeBlk + 1], sHi[kMergeBlk + 1];
   const int64_t Np = int64_t(1) << L;
   const int64_t blocks_per = Np / kMergeBlk;
-  const int64_t segl = blockIdx.x / blocks_per;
-  const int64_t bi = blockIdx.x % blocks_per;
+  // workgroups go to the 8 XCDs in turn: give each XCD a contiguous run of
+  // blocks, so that a table's scattered entry writes meet in one L2
+  const int64_t nbk = gridDim.x;
+  const int64_t lb = nbk % 8 == 0
+                         ? (int64_t)(blockIdx.x % 8) * (nbk / 8) + blockIdx.x / 8
+                         : (int64_t)blockIdx.x;
+  const int64_t segl = lb / blocks_per;
+  const int64_t bi = lb % blocks_per;
   const int64_t seg = seg0 + segl;
   const int64_t d0 = bi * kMergeBlk;
   uint64_t* et = ent + (seg << L);
-  if (!(tot[seg] > 0.0)) {  // dead table: never sampled, entries zero
+  // the table's figures and the block's edges in one round of loads
+  const int64_t* ed = edges + segl * (blocks_per + 1) + bi;
+  const double tt = tot[seg];
+  const int64_t NL = (int64_t)NLa[segl], NH = (int64_t)NHa[segl];
+  const uint64_t Dt = Dta[segl];
+  const int64_t e0 = ed[0], e1 = ed[1];
+  if (!(tt > 0.0)) {  // dead table: never sampled, entries zero
     for (int u = threadIdx.x; u < kMergeBlk; u += 256) et[d0 + u] = 0ull;
     return;
   }
   const int64_t tb = segl << L;
-  const int64_t NL = (int64_t)NLa[segl], NH = (int64_t)NHa[segl];
-  const uint64_t Dt = Dta[segl];
   const uint64_t* D = Ld + tb;
   const uint64_t* E = He + tb;
-  const int64_t* ed = edges + segl * (blocks_per + 1) + bi;
-  const int64_t a0 = ed[0], b0 = d0 - ed[0];
-  const int64_t na = ed[1] - a0, nb = (d0 + kMergeBlk - ed[1]) - b0;
+  const int64_t a0 = e0, b0 = d0 - e0;
+  const int64_t na = e1 - a0, nb = (d0 + kMergeBlk - e1) - b0;
   // slices, plus one element past each end (the next D bounds a light's
-  // quantum; the next heavy id closes a heavy)
-  for (int u = threadIdx.x; u <= na; u += 256) {
-    sD[u] = a0 + u < NL ? D[a0 + u] : Dt;
-    sLi[u] = a0 + u < NL ? Li[tb + a0 + u] : 0u;
+  // quantum; the next heavy id closes a heavy): every load issued before
+  // the first LDS store
+  constexpr int kSl = (kMergeBlk + 1 + 255) / 256;
+  uint64_t rD[kSl], rE[kSl];
+  uint32_t rL[kSl], rH[kSl];
+#pragma unroll
+  for (int k = 0; k < kSl; ++k) {
+    const int64_t u = threadIdx.x + 256 * k;
+    const bool la = u <= na && a0 + u < NL, hb = u <= nb && b0 + u < NH;
+    rD[k] = la ? D[a0 + u] : Dt;
+    rL[k] = la ? Li[tb + a0 + u] : 0u;
+    rE[k] = hb ? E[b0 + u] : ~0ull;
+    rH[k] = hb ? Hi[tb + b0 + u] : 0u;
   }
-  for (int u = threadIdx.x; u <= nb; u += 256) {
-    sE[u] = b0 + u < NH ? E[b0 + u] : ~0ull;
-    sHi[u] = b0 + u < NH ? Hi[tb + b0 + u] : 0u;
+#pragma unroll
+  for (int k = 0; k < kSl; ++k) {
+    const int64_t u = threadIdx.x + 256 * k;
+    if (u <= na) {
+      sD[u] = rD[k];
+      sLi[u] = rL[k];
+    }
+    if (u <= nb) {
+      sE[u] = rE[k];
+      sHi[u] = rH[k];
+    }
   }
   __syncthreads();
   // this thread's split inside the block's slices
