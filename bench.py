@@ -496,8 +496,9 @@ def csr_recall(args, cfg, mad, scale=0.02):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not "
-              "supported (the multi-GPU design is described in DESIGN.md)"
+        print("bench.py: the library runs on one GPU; --gpus %d is not "
+              "supported (the score table and the selection would shard by "
+              "a hash of (i, j); that path is not built)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

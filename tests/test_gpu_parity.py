@@ -3,8 +3,10 @@ inputs, through the C ABI.
 
 Bar: integer and index results (tables, per-sample streams, scores X, the
 candidate set Omega_t') are bit-exact; fp32 dot products match the oracle's
-FP64 values within 1e-5 of sum_k |a_ik b_jk| (the fp32 dot-product error
-scale); the final top-t equals the oracle's except for swaps
+FP64 values within 1e-5 of sum_k |a_ik b_jk| (fp32 accumulation over d
+terms errs by at most about d * 2^-24 times that sum, which is below 1e-5
+for d <= 160; at d = 600 the case relies on the typical error, which grows
+like sqrt(d) * 2^-24); the final top-t equals the oracle's except for swaps
 among pairs whose |c| differ by less than that tolerance."""
 import sys
 
