@@ -33,8 +33,9 @@
 extern "C" {
 #endif
 
-/* One result pair.  c = a_i . b_j computed in fp32 (Alg. 3 line "post2");
- * x = the sampler's score x_ij (Alg. 2 line "dx") converted to fp32. */
+/* One result pair.  c = a_i . b_j computed in fp32 (the verification of
+ * Alg. 3);
+ * x = the sampler's score x_ij (the score update of Alg. 2) converted to fp32. */
 typedef struct mad_pair {
   int64_t i;
   int64_t j;
@@ -76,7 +77,7 @@ enum {
 typedef struct mad_plan mad_plan;
 
 /* ---------------------------------------------------------------------------
- * mad_plan_create_dense -- preprocessing of Alg. 2 (line "dw" and the
+ * mad_plan_create_dense -- preprocessing of Alg. 2 (the weights w_ki and the
  * cumulative tables of Sec. 3.3 "Preprocessing" / Sec. 5.2) for dense A, B.
  *
  * Builds, in FP64 on the GPU, na_i = ||a_i||_1, nb_k = ||B_k*||_1,
@@ -139,7 +140,7 @@ int mad_plan_topk(mad_plan* plan, int64_t t, int64_t s, int64_t t_prime,
 
 /* ---------------------------------------------------------------------------
  * mad_plan_set_verify_precision -- arithmetic of the verification of Alg. 3
- * line "post2" for later mad_plan_topk calls on a dense plan:
+ * verification of Alg. 3 for later mad_plan_topk calls on a dense plan:
  *   MAD_FP32      (default) fp32 dot products of every candidate;
  *   MAD_BF16, MAD_FP8_E4M3  every candidate is first computed from bf16 /
  *                 fp8-e4m3 copies of A and B (per-vector power-of-two scale
@@ -175,7 +176,7 @@ void mad_plan_destroy(mad_plan* plan);
 
 /* ---------------------------------------------------------------------------
  * Plan statistics of the last mad_plan_topk (host outputs, synchronises):
- *   wnorm    ||W||_1 (FP64, Alg. 2 line "dw" summed)
+ *   wnorm    ||W||_1 (FP64, the weights w_ki of Alg. 2, summed)
  *   closed   closed three-paths (diamonds) among the s samples
  *   distinct pairs with at least one closed diamond (nnz(X) <= s, Sec. 3.1)
  *   n_pos    pairs with x_ij > 0 (|Omega_s|, Alg. 3)
@@ -347,7 +348,7 @@ int mad_debug_table(mad_plan* plan, int which, int64_t idx, uint32_t* thr,
 int mad_debug_norms(mad_plan* plan, double* na, double* nb, double* v,
                     double* om);
 
-/* Per-sample stream of samples l0 .. l0+count-1 (Alg. 2 lines ds1..dx):
+/* Per-sample stream of samples l0 .. l0+count-1 (the draws and the score update of Alg. 2):
  * k, i, j, kp (device int32) and inc (device int64: the fixed-point
  * increment, 0 when b_k'j = 0).  F is the fixed-point exponent to use;
  * qid is the query word of the counter (0 for MAD). */
@@ -356,8 +357,8 @@ int mad_debug_samples(mad_plan* plan, uint64_t seed, uint64_t qid,
                       int32_t* i, int32_t* j, int32_t* kp, int64_t* inc,
                       void* stream);
 
-/* The score accumulation alone, for tests (the pair form of Alg. 2 line
- * "dx"): over n pairs (keys: device uint64, ~0 = none; vals: device fp32)
+/* The score accumulation alone, for tests (the pair form of the score update of
+ * Alg. 2): over n pairs (keys: device uint64, ~0 = none; vals: device fp32)
  * every key's sum of rne(val * 2^F) as int64, written unordered to
  * out_keys / out_x (device int64, capacity cap); *n_out (host) = number of
  * distinct keys.  The inputs are not modified.  Synchronises;

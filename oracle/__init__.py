@@ -164,7 +164,8 @@ def fix_exponent(bmax: float, s: int) -> int:
 # plans
 # --------------------------------------------------------------------------
 class Plan:
-    """Tables of Alg. 2 line "dw" for one (A, B); see the C file's header."""
+    """Tables for the weights w_ki of Alg. 2, for one (A, B); see the C file's
+    header."""
 
     def __init__(self, handle, m, n, d, keep):
         self._h = handle
@@ -277,8 +278,8 @@ class Plan:
 
     def topk(self, seed: int, s: int, t_prime: int, t: int, F: int | None = None,
              qid: int = 0):
-        """Alg. 2 + Alg. 3.  Returns a dict with Omega_{t'} (post1 order) and
-        Omega_t (post3 order) as key / x_fix / c arrays."""
+        """Alg. 2 + Alg. 3.  Returns a dict with Omega_{t'} (candidate selection order) and
+        Omega_t (final selection order) as key / x_fix / c arrays."""
         if F is None:
             F = self.fix_exponent(s)
         tp_key = np.zeros(max(t_prime, 1), np.int64)

@@ -7,8 +7,8 @@
  *
  * What it computes (Ballard, Kolda, Pinar, Seshadhri, "Diamond Sampling for
  * Approximate Maximum All-pairs Dot-product (MAD) Search"):
- *   - Alg. 2 (diamond sampling, general inputs): the weights of line "dw",
- *     the s draws of lines "ds1".."ds3" and the score update of line "dx";
+ *   - Alg. 2 (diamond sampling, general inputs): the weights w_ki,
+ *     the s draws and the score update;
  *   - Alg. 3 (postprocessing): top-t' of X over {x_ij > 0}, exact dot
  *     products of those candidates, top-t of the result;
  *   - the exhaustive t-MAD answer (Definition 1) by brute force.
@@ -21,7 +21,7 @@
  *   R2  (k,i) is drawn in two stages: k with weight nb_k * v_k, then i given
  *       k with weight |a_ki| * na_i, where na_i = ||a_i||_1, nb_k = ||B_k*||_1
  *       and v_k = sum_i |a_ki| na_i.  The product of the two stage
- *       probabilities is w_ki / ||W||_1 of Alg. 2 line "ds1" exactly
+ *       probabilities is exactly w_ki / ||W||_1, the draw of (k, i) in Alg. 2
  *       (Lemma 1's proof factors the same way).
  *   R3  every FP64 sum and prefix sum uses the two-level run order of
  *       prefix_runs() below; products are single IEEE roundings.
@@ -32,14 +32,14 @@
  *   R5  random numbers: one Philox4x64-10 block per sample l, counter
  *       (l, qid, 0, 0), key (seed, 0); word 0 draws k, word 1 draws i,
  *       word 2 draws j, word 3 draws k'.
- *   R6  the sign factor of line "dx" is the XOR of the three IEEE sign bits
+ *   R6  the sign factor of the score update is the XOR of the three IEEE sign bits
  *       (the line reads sgn(a_ki b_kj a_k'i); Lemma 2's statement and proof
  *       misprint its subscripts, and its algebra needs the line's form).
  *   R7  scores are exact int64 fixed point: inc = sign * rne(b_k'j * 2^F)
  *       with F = 62 - e_b - ceil(log2 max(s,2)), max|b| < 2^e_b.
  *   R8  ties in both selections of Alg. 3 are broken by (i, j) ascending,
  *       and the final ranking is by |c_ij| (Definition 1 asks for the
- *       largest |a_i . b_j|; Alg. 3 line "post3" prints c_ij).
+ *       largest |a_i . b_j|; Alg. 3 (final selection) prints c_ij).
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
  */
@@ -334,7 +334,8 @@ static void trans_free(otrans *t) {
 }
 
 /* ------------------------------------------------------------------------
- * The oracle plan: everything Alg. 2 line "dw" and the draws need.
+ * The oracle plan: everything that the weights w_ki of Alg. 2 and the
+ * draws need.
  *   na[i]  = ||a_i||_1         total of T3[i]
  *   nb[k]  = ||B_k*||_1        total of T2[k]
  *   v[k]   = sum_i |a_ki| na_i total of T1[k]
@@ -355,7 +356,7 @@ static void plan_build_aside(orc_plan *p) {
   int64_t m = p->m, d = p->d;
   p->na = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
   p->T3 = (otable *)calloc((size_t)(m > 0 ? m : 1), sizeof(otable));
-  /* T3[i]: k' given i with weight |a_k'i| (Alg. 2 line "ds3") */
+  /* T3[i]: k' given i with weight |a_k'i| (the draw of k' in Alg. 2) */
   for (int64_t i = 0; i < m; ++i) {
     int64_t e0 = p->A.ptr[i], N = p->A.ptr[i + 1] - e0;
     double *w = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
@@ -384,7 +385,7 @@ static void plan_build_bside(orc_plan *p) {
   trans_build(&p->Bt, &p->B);
   p->nb = (double *)calloc((size_t)(d > 0 ? d : 1), sizeof(double));
   p->T2 = (otable *)calloc((size_t)(d > 0 ? d : 1), sizeof(otable));
-  /* T2[k]: j given k with weight |b_kj| (Alg. 2 line "ds2") */
+  /* T2[k]: j given k with weight |b_kj| (the draw of j in Alg. 2) */
   for (int64_t k = 0; k < d; ++k) {
     int64_t e0 = p->Bt.ptr[k], N = p->Bt.ptr[k + 1] - e0;
     double *w = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
@@ -512,7 +513,7 @@ static int sign_bit(float x) {
 }
 
 /* ------------------------------------------------------------------------
- * One iteration of the sampling loop of Alg. 2 (lines "ds1".."dx") for
+ * One iteration of the sampling loop of Alg. 2 (its draws and score update) for
  * sample l.  Returns 1 and fills *inc when the three-path closes
  * (b_k'j != 0), else 0.  k, i, j, kp are always filled.
  * ---------------------------------------------------------------------- */
@@ -521,12 +522,12 @@ static int one_sample(const orc_plan *p, uint64_t seed, uint64_t qid,
                       int32_t *j_, int32_t *kp_, int64_t *inc) {
   uint64_t ctr[4] = {l, qid, 0, 0}, key[2] = {seed, 0}, U[4];
   orc_philox4x64_10(ctr, key, U);
-  /* ds1: (k, i) with probability w_ki / ||W||_1, in two stages (R2) */
+  /* draw of (k, i): with probability w_ki / ||W||_1, in two stages (R2) */
   int64_t k = table_draw(&p->T0, U[0]);
   int64_t i = table_draw(&p->T1[k], U[1]);
-  /* ds2: j with probability |b_kj| / ||B_k*||_1 */
+  /* draw of j: with probability |b_kj| / ||B_k*||_1 */
   int64_t j = table_draw(&p->T2[k], U[2]);
-  /* ds3: k' with probability |a_k'i| / ||a_i||_1 */
+  /* draw of k': with probability |a_k'i| / ||a_i||_1 */
   int64_t kp = table_draw(&p->T3[i], U[3]);
   *k_ = (int32_t)k; *i_ = (int32_t)i; *j_ = (int32_t)j; *kp_ = (int32_t)kp;
   /* dx: x_ij += sgn(a_ki b_kj a_k'i) b_k'j */
@@ -652,14 +653,14 @@ int64_t orc_plan_scores(const orc_plan *p, uint64_t seed, uint64_t qid,
  * ---------------------------------------------------------------------- */
 typedef struct { int64_t key; int64_t x; double c; } cand;
 
-/* post1 order: x descending, then key (i, j) ascending (R8) */
+/* candidate selection order: x descending, then key (i, j) ascending (R8) */
 static int cmp_post1(const void *a, const void *b) {
   const cand *u = (const cand *)a, *v = (const cand *)b;
   if (u->x != v->x) return u->x > v->x ? -1 : 1;
   return (u->key > v->key) - (u->key < v->key);
 }
 
-/* post3 order: |c| descending, then key ascending (R8) */
+/* final selection order: |c| descending, then key ascending (R8) */
 static int cmp_post3(const void *a, const void *b) {
   const cand *u = (const cand *)a, *v = (const cand *)b;
   double x = fabs(u->c), y = fabs(v->c);
@@ -685,8 +686,8 @@ static double exact_dot(const orc_plan *p, int64_t i, int64_t j) {
   return c;
 }
 
-/* Full Alg. 2 + Alg. 3 for one (B, qid).  Outputs Omega_{t'} in post1
- * order (tp_* arrays, cap t_prime) and Omega_t in post3 order (t_* arrays,
+/* Full Alg. 2 + Alg. 3 for one (B, qid).  Outputs Omega_{t'} in candidate selection
+ * order (tp_* arrays, cap t_prime) and Omega_t in final selection order (t_* arrays,
  * cap t).  Returns |Omega_t|; *n_tp gets |Omega_{t'}|, *n_pos |Omega_s|,
  * *closed the number of closed three-paths. */
 int64_t orc_plan_topk(const orc_plan *p, uint64_t seed, uint64_t qid,
@@ -707,10 +708,10 @@ int64_t orc_plan_topk(const orc_plan *p, uint64_t seed, uint64_t qid,
     }
   free(X);
   if (n_pos) *n_pos = np;
-  /* post1: top-t' of X */
+  /* candidate selection: top-t' of X */
   qsort(c, (size_t)np, sizeof(cand), cmp_post1);
   int64_t ntp = np < t_prime ? np : t_prime;
-  /* post2: exact dot products of the candidates */
+  /* verification: exact dot products of the candidates */
   for (int64_t e = 0; e < ntp; ++e)
     c[e].c = exact_dot(p, c[e].key / p->n, c[e].key % p->n);
   for (int64_t e = 0; e < ntp; ++e) {
@@ -719,7 +720,7 @@ int64_t orc_plan_topk(const orc_plan *p, uint64_t seed, uint64_t qid,
     if (tp_c) tp_c[e] = c[e].c;
   }
   if (n_tp) *n_tp = ntp;
-  /* post3: top-t of the candidates by |c| */
+  /* final selection: top-t of the candidates by |c| */
   qsort(c, (size_t)ntp, sizeof(cand), cmp_post3);
   int64_t nt = ntp < t ? ntp : t;
   for (int64_t e = 0; e < nt; ++e) {

@@ -1,5 +1,5 @@
-// accum.hip -- the score matrix X of Alg. 2 (line "dx") built from the
-// closed samples without per-sample global atomics.
+// accum.hip -- the score matrix X, filled by the score update of Alg. 2, built
+// from the closed samples without per-sample global atomics.
 //
 // Sample l writes its pair at index l of two arrays: the key i*n + j
 // (EMPTY when the three-path is open) and the fourth edge b_k'j as fp32 with

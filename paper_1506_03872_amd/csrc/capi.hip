@@ -315,12 +315,12 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   // slots, rounded up to a power of two
   const int64_t hcap = use_pairs ? (s2 > 1 ? s2 : 1)
                                  : next_pow2(2 * (pairs > 512 ? pairs : 512));
-  // candidates / boundary lists: post1 needs |Omega_s| <= pairs entries,
-  // post3 needs 4 t (final set) + 4 t' (boundary of the candidates)
+  // candidates / boundary lists: candidate selection needs |Omega_s| <= pairs entries,
+  // final selection needs 4 t (final set) + 4 t' (boundary of the candidates)
   int64_t ccap = pairs > 1 ? pairs : 1;
   if (ccap < 4 * t2 + 4 * tp2) ccap = 4 * t2 + 4 * tp2;
   const int64_t ccap2 = tp2 > 1 ? tp2 : 1;
-  // post1's refined boundary list (one digit's bin of a long boundary list)
+  // candidate selection's refined boundary list (one digit's bin of a long boundary list)
   const int64_t rcap = ccap < (int64_t(1) << 21) ? ccap : (int64_t(1) << 21);
   (void)hipDeviceSynchronize();
   hipError_t e;

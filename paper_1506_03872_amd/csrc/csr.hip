@@ -3,7 +3,7 @@
 // rating experiments (Sec. 6).
 //
 // Preprocessing builds the same four stage distributions as the dense plan
-// (Alg. 2 line "dw" in the two-stage form), but over the non-zeros only:
+// (the weights w_ki of Alg. 2 in the two-stage form), but over the non-zeros only:
 //   T3[i]  over the entries of a_i            weight |a_k'i|
 //   T1[k]  over the vectors i with an entry k weight |a_ki| na_i
 //   T2[k]  over the vectors j with an entry k weight |b_kj|

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
     return;
   }
   for (int64_t k = t; k < a.d; k += kPostThreads) qs[k] = a.Q[q * a.d + k];
-  // post1 (Omega_s): keys with x > 0, compacted in slot order
+  // candidate selection (Omega_s): keys with x > 0, compacted in slot order
   const uint32_t* hk = a.hkeys + qi.hoff;
   const int64_t* hv = a.hvals + qi.hoff;
   uint64_t* cx = a.cx + qi.coff;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
   }
   int64_t npos = (int64_t)ps.base;
   if (npos > qi.ccap) npos = qi.ccap;  // cannot happen: distinct <= s_q, m
-  // post1 (Omega_t'): the t'_q largest x, ties by i ascending
+  // candidate selection (Omega_t'): the t'_q largest x, ties by i ascending
   uint64_t* sx = a.sx + qi.soff;
   uint32_t* sk = a.sk + qi.soff;
   float* sc = a.sc + qi.soff;
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
     const int64_t rowb = a.Kp * (a.lp == 1 ? 2 : 1);  // bytes per row
     const uint4* qrow = (const uint4*)((const char*)a.Qlp + q * rowb);
     const VecInfo vq = a.iq[q];
-    // kScrU rounds of 4 candidates per wave at once, as in post2 below
+    // kScrU rounds of 4 candidates per wave at once, as in verification below
     constexpr int kScrU = 4;
     const int64_t round = kPostWaves * 4;
     for (int64_t e0 = (int64_t)wv * 4; e0 < nsel; e0 += round * kScrU) {
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
   }
   if (t == 0) ps.base = 0;
   __syncthreads();
-  // post2: c = a_i . q in fp32; 16 lanes per candidate, 4 candidates per
+  // verification: c = a_i . q in fp32; 16 lanes per candidate, 4 candidates per
   // wave and kVerU rounds of them at once (their row loads in flight
   // together), rows read as float4 when d is a multiple of 4
   constexpr int kVerU = 4;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kPostThreads) void k_mips_post(MipsArgs a) {
   if (nfp) atomicAdd((unsigned long long*)&ps.base, (unsigned long long)nfp);
   __syncthreads();
   const int64_t n_fp32 = (int64_t)ps.base;
-  // post3: the t largest |c|, ties by i ascending
+  // final selection: the t largest |c|, ties by i ascending
   SelThr thr3{0, 0, 0, 0, 0};
   const bool cut3 = nsel > tq;
   if (cut3) thr3 = block_select(sab, sk, nsel, tq, 32, ps);

@@ -1,4 +1,4 @@
-// sampler.hip -- the sampling loop of Alg. 2 (lines "ds1".."dx") for dense
+// sampler.hip -- the sampling loop of Alg. 2 (its draws and score update) for dense
 // inputs.  Each sample either writes its (key, increment) pair at its own
 // index (pair form; X is then summed by accum.hip) or adds its increment to
 // an open-addressing hash table X (hash form).  Samples can run in k order
@@ -7,7 +7,7 @@
 // Sample l uses the Philox4x64-10 block with counter (l, qid, 0, 0) and key
 // (seed, 0): word 0 draws k from T0, word 1 draws i from T1[k], word 2 draws
 // j from T2[k], word 3 draws k' from T3[i] (the two-stage form of line
-// "ds1": k with weight ||B_k*||_1 v_k, then i with weight |a_ki| ||a_i||_1).
+// the draw of (k, i): k with weight ||B_k*||_1 v_k, then i with weight |a_ki| ||a_i||_1).
 // The alias entries carry the sign bits of a_ki, b_kj and a_k'i, so the only
 // value read from the inputs is the fourth edge b_k'j.  A closed three-path
 // (b_k'j != 0) adds sgn(a_ki b_kj a_k'i) * rne(b_k'j * 2^F) to the int64
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
   while (GROUPED ? ch < ch_hi : base < a.count) {
     OneSample smp[U];
     uint64_t U1[U], U2[U], U3[U];
-    // ds1 (stage 0): k from the LDS copy of T0
+    // draw of k (stage 0): from the LDS copy of T0
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = base + (int64_t)u * nthreads;
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       U2[u] = r.w2;
       U3[u] = r.w3;
     }
-    // ds1 (stage 1) and ds2: i from T1[k], j from T2[k]
+    // draws of i (stage 1) and j: i from T1[k], j from T2[k]
     uint64_t e1[U], e2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       smp[u].j = dj.pos;
       sgn[u] = di.sgn ^ dj.sgn;
     }
-    // ds3: k' from T3[i]
+    // draw of k': from T3[i]
     uint64_t e3[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)

@@ -1,22 +1,22 @@
 // select.hip -- Alg. 3 postprocessing on the GPU.
 //
-//   post1  Omega_s = pairs with x_ij > 0; Omega_t' = the t' largest by x,
-//          ties by key (i*n + j) ascending;
-//   post2  c_ij = a_i . b_j in fp32 for each candidate;
-//   post3  Omega_t = the t largest by |c|, ties by key ascending, written in
-//          that order.
+//   candidate selection  Omega_s = pairs with x_ij > 0; Omega_t' = the t'
+//                        largest by x, ties by key (i*n + j) ascending;
+//   verification         c_ij = a_i . b_j in fp32 for each candidate;
+//   final selection      Omega_t = the t largest by |c|, ties by key
+//                        ascending, written in that order.
 //
 // Each selection of k elements by (primary descending, key ascending) runs
 // in three steps, with every count kept in device memory:
-//   1. while the elements are produced (the score table scan for post1, the
-//      verification kernel for post3) a 2048-bin histogram of a monotone
+//   1. while the elements are produced (the score table scan for candidate selection, the
+//      verification kernel for final selection) a 2048-bin histogram of a monotone
 //      "float" digit of the primary (its highest set bit and the 5 bits
 //      below it) is accumulated;
 //   2. one pass splits the elements: bins above the bin that holds the k-th
 //      element are taken outright, that bin's elements go to a boundary list;
 //   3. one workgroup selects exactly the remaining count from the boundary
 //      list with 11-bit radix passes over the primary and then the key.
-// In post1 a boundary list of more than kRefineMin elements first gets one
+// In candidate selection a boundary list of more than kRefineMin elements first gets one
 // such radix pass on the whole grid (histogram, decision, split), so that
 // step 3 reads one digit's bin of it.
 #include "mad_common.hpp"
@@ -48,7 +48,7 @@ struct Coarse {
   int64_t bin;    // boundary bin (-1: take everything)
 };
 
-// post1 boundary refinement: one full-grid radix pass over a long boundary
+// candidate selection boundary refinement: one full-grid radix pass over a long boundary
 // list (ties of x leave millions of elements in one coarse bin), so that the
 // single-workgroup step 3 starts from one digit's bin of it
 struct Refine {
@@ -90,7 +90,7 @@ __device__ void block_hist_flush(unsigned* lds, unsigned* gh) {
 }
 
 // ---------------------------------------------------------------------------
-// post1 step 1: histogram of x > 0 straight from the score table (the
+// candidate selection step 1: histogram of x > 0 straight from the score table (the
 // number of positive scores is the histogram's total)
 // ---------------------------------------------------------------------------
 // The grid is small (kHistBlocks workgroups of 1024 threads): every block
@@ -207,7 +207,7 @@ __device__ __forceinline__ int64_t block_append(bool take,
 }
 
 // ---------------------------------------------------------------------------
-// post1 step 2b: split the score table (winners -> w*, boundary -> b*).
+// candidate selection step 2b: split the score table (winners -> w*, boundary -> b*).
 // Each block stages its finds in LDS and reserves output space once per
 // flush: one global atomic per list and flush, not per wave or element.
 // ---------------------------------------------------------------------------
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
 }
 
 // ---------------------------------------------------------------------------
-// post2: c = a_i . b_j in fp32, one wave per candidate; histogram of |c|
+// verification: c = a_i . b_j in fp32, one wave per candidate; histogram of |c|
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
                                                 const int64_t* counts,
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
   block_hist_flush(h, hist);
 }
 
-// post2 for sparse vectors: one wave per candidate, each lane takes entries
+// verification for sparse vectors: one wave per candidate, each lane takes entries
 // of a_i and finds their coordinate in b_j by binary search
 __global__ __launch_bounds__(256) void k_verify_csr(const uint64_t* key2,
                                                     const int64_t* counts,
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k_verify_csr(const uint64_t* key2,
 
 
 // ---------------------------------------------------------------------------
-// low-precision filter of Omega_t' (between post1 and post2): c^ from the
+// low-precision filter of Omega_t' (between candidate selection and verification): c^ from the
 // bf16 / fp8 copies with an a-priori bound mg on |c^ - c_fp32| (input
 // rounding, fp32 accumulation, and the fp32 re-rank's own error).  With
 // tau <= the t-th largest lower bound |c^| - mg, a candidate whose upper
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(256) void k_lowp_filter(
   }
 }
 
-// the kept candidates become Omega for post2 / post3
+// the kept candidates become Omega for verification / final selection
 __global__ void k_lowp_copy(const uint64_t* key, const uint64_t* x,
                             uint64_t* key2, uint64_t* x2, int64_t* counts) {
   const int64_t kept = counts[kCntBound];
@@ -809,7 +809,7 @@ __global__ void k_lowp_copy(const uint64_t* key, const uint64_t* x,
   }
 }
 
-// post3 step 2b: split the candidates
+// final selection step 2b: split the candidates
 __global__ __launch_bounds__(256) void k_cand_split(
     const Coarse* cz, const uint64_t* absbits, const uint64_t* key2,
     const uint64_t* x2, const float* c, int64_t cap2, uint64_t* fp,
@@ -1062,7 +1062,7 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
     post_fills(w, f);
     if ((e = launch_fill_multi(f, st)) != hipSuccess) return e;
   }
-  // ---- post1: top t' of x over x > 0 ------------------------------------
+  // ---- candidate selection: top t' of x over x > 0 ------------------------------------
   k_score_hist<<<blocks_for(h.cap, kHistThreads * 16, kHistBlocks),
                  kHistThreads, 0, st>>>(h.vals, h.cap, h.live, w.hist);
   Refine* rf = (Refine*)(cz + 3);
@@ -1097,15 +1097,15 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
     k_lowp_copy<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
         w.x, w.key, w.key2, w.x2, counts);
   }
-  // ---- post2: fp32 dot products and the |c| histogram --------------------
-  // (|c| bits go to w.x, free after post1)
+  // ---- verification: fp32 dot products and the |c| histogram --------------------
+  // (|c| bits go to w.x, free after candidate selection)
   if (csr)
     k_verify_csr<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
         w.key2, counts, *csr, n, w.cap2, w.c, w.x, w.hist);
   else
     k_verify<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
         w.key2, counts, A, B, n, d, w.cap2, w.c, w.x, w.hist);
-  // ---- post3: top t by |c| ----------------------------------------------
+  // ---- final selection: top t by |c| ----------------------------------------------
   e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
   if (e != hipSuccess) return e;
   k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntCand], t, cz + 1,

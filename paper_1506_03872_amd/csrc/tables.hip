@@ -1,5 +1,5 @@
-// tables.hip -- preprocessing of Alg. 2 (line "dw") on the GPU: FP64 norms
-// and stage weights, integer quanta from the normalised cumulative sums
+// tables.hip -- preprocessing for the weights w_ki of Alg. 2 on the GPU: FP64
+// norms and stage weights, integer quanta from the normalised cumulative sums
 // (Sec. 3.3 "Preprocessing", Sec. 5.2), and alias tables (the alias method
 // named in Sec. 5.1) built in parallel.
 //
@@ -1174,7 +1174,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   hipStream_t sd = one_stream ? st : t.side;
   if (B && !one_stream && (e = hipEventRecord(t.fork, st)) != hipSuccess)
     return e;
-  // T3[i]: k' given i, weight |a_k'i|; totals na_i (Alg. 2 line "ds3")
+  // T3[i]: k' given i, weight |a_k'i|; totals na_i (the draw of k' in
+  // Alg. 2)
   // (enqueued before the B side so that this stream has work at once)
   if (t.T3.L <= 9) {
     e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
@@ -1186,7 +1187,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   }
   if (e != hipSuccess) return e;
   // B side on the side stream: max |b| (and the finiteness check), then
-  // T2[k]: j given k, weight |b_kj|; totals nb_k (Alg. 2 line "ds2")
+  // T2[k]: j given k, weight |b_kj|; totals nb_k (the draw of j in
+  // Alg. 2)
   if (B) {
     if (!one_stream && (e = hipStreamWaitEvent(sd, t.fork, 0)) != hipSuccess)
       return e;
@@ -1217,7 +1219,8 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
     if (e == hipSuccess) e = ew;
   }
   if (e != hipSuccess || !B) return e;
-  // T0: k with weight nb_k v_k; total ||W||_1 (Alg. 2 lines "dw", "ds1")
+  // T0: k with weight nb_k v_k; total ||W||_1 (the weights w_ki
+  // of Alg. 2 and its draw of (k, i))
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
     if (t.T0.L <= 9) {

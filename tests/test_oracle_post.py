@@ -49,12 +49,12 @@ def test_post1_selects_largest_scores_with_tie_break():
     order = np.lexsort((keys[pos], -xfix[pos]))[:tp]
     assert np.array_equal(r["tp_key"], keys[pos][order])
     assert np.array_equal(r["tp_x"], xfix[pos][order])
-    # post2: exact FP64 dot products of the candidates
+    # verification: exact FP64 dot products of the candidates
     n = B.shape[0]
     c = (A[r["tp_key"] // n].astype(np.float64) *
          B[r["tp_key"] % n].astype(np.float64)).sum(1)
     assert np.allclose(r["tp_c"], c, rtol=1e-13, atol=1e-12)
-    # post3: top-t by |c| among the candidates
+    # final selection: top-t by |c| among the candidates
     o3 = np.lexsort((r["tp_key"], -np.abs(r["tp_c"])))[:20]
     assert np.array_equal(r["key"], r["tp_key"][o3])
 
@@ -82,7 +82,7 @@ def test_fixed_point_scores_are_exact_sums():
         if inc != 0:
             ref[int(kk)] = ref.get(int(kk), 0) + int(inc)
     assert dict(zip(keys.tolist(), xfix.tolist())) == ref
-    # each increment is sgn(a_ki b_kj a_k'i) * b_k'j (line "dx") scaled by
+    # each increment is sgn(a_ki b_kj a_k'i) * b_k'j (the score update of Alg. 2) scaled by
     # 2^F and rounded to the nearest integer (halves to even)
     v = B[r["j"], r["kp"]].astype(np.float64)
     sg = np.sign(A[r["i"], r["k"]]) * np.sign(B[r["j"], r["k"]]) * \

@@ -104,7 +104,7 @@ def test_lemma2_expectation():
 
 
 def test_lemma2_rejects_a_dropped_sign():
-    # if the sign factor of line "dx" were dropped, E[x_ij/s] would be
+    # if the sign factor of the score update were dropped, E[x_ij/s] would be
     # sum_{k,k'} Pr * |b_k'j|-weighted terms instead of c^2 / W; the z-test
     # separates the two by far more than its threshold
     A, B = workloads.tiny(3, 3, 4, seed=21)
