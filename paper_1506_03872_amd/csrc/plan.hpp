@@ -321,7 +321,7 @@ struct SelectWork {
 
 // SelectWork::counts slots
 enum { kCountPos = 0, kCountDistinct = 1, kCountCand = 2, kCountFinal = 3 };
-constexpr size_t kSelStateBytes = 256;
+constexpr size_t kSelStateBytes = 512;
 constexpr int kSelBins = 2048;
 
 hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,

@@ -16,9 +16,9 @@
 //      element are taken outright, that bin's elements go to a boundary list;
 //   3. one workgroup selects exactly the remaining count from the boundary
 //      list with 11-bit radix passes over the primary and then the key.
-// In candidate selection a boundary list of more than kRefineMin elements first gets one
-// such radix pass on the whole grid (histogram, decision, split), so that
-// step 3 reads one digit's bin of it.
+// A boundary list of more than kRefineMin elements first gets one such
+// radix pass on the whole grid (histogram, decision, split), so that step 3
+// reads one digit's bin of it.
 #include "mad_common.hpp"
 #include "plan.hpp"
 
@@ -59,9 +59,13 @@ struct Refine {
   unsigned long long nout;         // refined list length
   int64_t pad[3];
 };
-static_assert(3 * sizeof(Coarse) + sizeof(Refine) <= kSelStateBytes,
+// select state: three Coarse (candidate selection, final selection,
+// low-precision filter), then a Refine for each of the two selections
+static_assert(3 * sizeof(Coarse) + 2 * sizeof(Refine) <= kSelStateBytes,
               "select state");
 constexpr int kRefineMin = 4096;   // shorter lists go to step 3 as they are
+constexpr int64_t kRefineFinalMin = 16384;  // t' above which the final
+                                            // selection may refine
 
 static inline unsigned blocks_for(int64_t n, int per_block, int cap) {
   int64_t g = (n + per_block - 1) / per_block;
@@ -206,6 +210,44 @@ __device__ __forceinline__ int64_t block_append(bool take,
   return slot;
 }
 
+// and / or of a block's boundary elements into rf (256 threads, all of
+// them; any: this thread saw one): one set of atomics per block that holds
+// any
+__device__ void block_and_or(bool any, uint64_t xa, uint64_t xo, uint64_t ka,
+                             uint64_t ko, unsigned long long (*red)[4],
+                             Refine* rf) {
+  const int t = threadIdx.x;
+  if (!__syncthreads_or(any)) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    xa &= __shfl_xor(xa, off, 64);
+    xo |= __shfl_xor(xo, off, 64);
+    ka &= __shfl_xor(ka, off, 64);
+    ko |= __shfl_xor(ko, off, 64);
+  }
+  const int wv = t >> 6;
+  if ((t & 63) == 0) {
+    red[0][wv] = xa;
+    red[1][wv] = xo;
+    red[2][wv] = ka;
+    red[3][wv] = ko;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < 4; ++w) {
+      xa &= red[0][w];
+      xo |= red[1][w];
+      ka &= red[2][w];
+      ko |= red[3][w];
+    }
+    {
+      atomicAnd((unsigned long long*)&rf->xand, (unsigned long long)xa);
+      atomicOr((unsigned long long*)&rf->xor_, (unsigned long long)xo);
+      atomicAnd((unsigned long long*)&rf->kand, (unsigned long long)ka);
+      atomicOr((unsigned long long*)&rf->kor, (unsigned long long)ko);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // candidate selection step 2b: split the score table (winners -> w*, boundary -> b*).
 // Each block stages its finds in LDS and reserves output space once per
@@ -225,6 +267,7 @@ __global__ __launch_bounds__(256) void k_score_split(
   __shared__ unsigned long long gbase[2];
   __shared__ unsigned long long red[4][4];
   uint64_t xa = ~0ull, xo = 0ull, ka = ~0ull, ko = 0ull;
+  bool any = false;
   const Coarse c = *cz;
   if (live && *live < cap) cap = *live;
   const int t = threadIdx.x;
@@ -256,6 +299,7 @@ __global__ __launch_bounds__(256) void k_score_split(
         sx[L][p] = (unsigned long long)v[u];
         sk[L][p] = kk;
         if (L) {
+          any = true;
           xa &= (uint64_t)v[u];
           xo |= (uint64_t)v[u];
           ka &= kk;
@@ -289,36 +333,7 @@ __global__ __launch_bounds__(256) void k_score_split(
       __syncthreads();
     }
   }
-  // and / or of the boundary elements: one set of atomics per block that
-  // holds any
-  for (int off = 32; off > 0; off >>= 1) {
-    xa &= __shfl_xor(xa, off, 64);
-    xo |= __shfl_xor(xo, off, 64);
-    ka &= __shfl_xor(ka, off, 64);
-    ko |= __shfl_xor(ko, off, 64);
-  }
-  const int wv = t >> 6;
-  if ((t & 63) == 0) {
-    red[0][wv] = xa;
-    red[1][wv] = xo;
-    red[2][wv] = ka;
-    red[3][wv] = ko;
-  }
-  __syncthreads();
-  if (t == 0) {
-    for (int w = 1; w < 4; ++w) {
-      xa &= red[0][w];
-      xo |= red[1][w];
-      ka &= red[2][w];
-      ko |= red[3][w];
-    }
-    if (xo != 0ull) {  // boundary elements have x > 0
-      atomicAnd((unsigned long long*)&rf->xand, (unsigned long long)xa);
-      atomicOr((unsigned long long*)&rf->xor_, (unsigned long long)xo);
-      atomicAnd((unsigned long long*)&rf->kand, (unsigned long long)ka);
-      atomicOr((unsigned long long*)&rf->kor, (unsigned long long)ko);
-    }
-  }
+  block_and_or(any, xa, xo, ka, ko, red, rf);
 }
 
 // the refinement digit: the 11 bits below the highest bit in which the
@@ -423,10 +438,13 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_decide(
 
 // refinement 3/3: elements ordered before the chosen bin join the winners,
 // the bin's elements form the refined list
+// (the final selection's lists also carry x and c: bextra / bc, when set)
 __global__ __launch_bounds__(256) void k_refine_split(
-    const Refine* rf, const uint64_t* bx, const uint64_t* bkey, int64_t bcap,
-    int64_t* counts, uint64_t* wx, uint64_t* wkey, int64_t wcap,
-    unsigned long long* nout, uint64_t* rx, uint64_t* rkey, int64_t rcap) {
+    const Refine* rf, const uint64_t* bx, const uint64_t* bkey,
+    const uint64_t* bextra, const float* bc, int64_t bcap, int64_t* counts,
+    uint64_t* wx, uint64_t* wkey, uint64_t* wextra, float* wc, int64_t wcap,
+    unsigned long long* nout, uint64_t* rx, uint64_t* rkey, uint64_t* rextra,
+    float* rc, int64_t rcap) {
   __shared__ unsigned wcount[4];
   __shared__ unsigned long long wbase[5];
   if (!rf->active) return;
@@ -451,11 +469,15 @@ __global__ __launch_bounds__(256) void k_refine_split(
     if (better && sw < wcap) {
       wx[sw] = p;
       wkey[sw] = kk;
+      if (bextra) wextra[sw] = bextra[e];
+      if (bc) wc[sw] = bc[e];
     }
     const int64_t sr = block_append(match, nout, wcount, wbase);
     if (match && sr < rcap) {
       rx[sr] = p;
       rkey[sr] = kk;
+      if (bextra) rextra[sr] = bextra[e];
+      if (bc) rc[sr] = bc[e];
     }
   }
 }
@@ -474,6 +496,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
     int win_slot, uint64_t* ox, uint64_t* okey, uint64_t* oextra, float* oc,
     int64_t ocap, int out_count_slot, const Refine* rf = nullptr,
     const uint64_t* rx = nullptr, const uint64_t* rkey = nullptr,
+    const uint64_t* rextra = nullptr, const float* rc = nullptr,
     int64_t rcap = 0) {
   __shared__ unsigned h[kBins];
   __shared__ unsigned long long wsum[kFineThreads / 64];
@@ -487,9 +510,11 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
   const int64_t nwin = counts[win_slot] < ocap ? counts[win_slot] : ocap;
   int64_t nb = counts[kCntBound];
   if (nb > bcap) nb = bcap;
-  if (rf && rf->active) {  // the refined list (no extra / c columns)
+  if (rf && rf->active) {  // the refined list
     bx = rx;
     bkey = rkey;
+    bextra = rextra;
+    bc = rc;
     nb = (int64_t)rf->nout < rcap ? (int64_t)rf->nout : rcap;
   }
   const bool none = c.bin < 0 || c.k_rem <= 0;
@@ -814,9 +839,13 @@ __global__ __launch_bounds__(256) void k_cand_split(
     const Coarse* cz, const uint64_t* absbits, const uint64_t* key2,
     const uint64_t* x2, const float* c, int64_t cap2, uint64_t* fp,
     uint64_t* fkey, uint64_t* fx, float* fc, int64_t tcap, uint64_t* bp,
-    uint64_t* bkey, uint64_t* bx, float* bc, int64_t bcap, int64_t* counts) {
+    uint64_t* bkey, uint64_t* bx, float* bc, int64_t bcap, int64_t* counts,
+    Refine* rf = nullptr) {
   __shared__ unsigned wcount[4];
   __shared__ unsigned long long wbase[5];
+  __shared__ unsigned long long red[4][4];
+  uint64_t xa = ~0ull, xo = 0ull, ka = ~0ull, ko = 0ull;
+  bool any = false;
   const Coarse cc = *cz;
   const int64_t n = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -838,12 +867,19 @@ __global__ __launch_bounds__(256) void k_cand_split(
     const int64_t bs = block_append(
         bnd, (unsigned long long*)&counts[kCntBound], wcount, wbase);
     if (bnd && bs < bcap) {
+      const uint64_t kk = key2[e];
       bp[bs] = p;
-      bkey[bs] = key2[e];
+      bkey[bs] = kk;
       bx[bs] = x2[e];
       bc[bs] = c[e];
+      any = true;
+      xa &= p;
+      xo |= p;
+      ka &= kk;
+      ko |= kk;
     }
   }
+  if (rf) block_and_or(any, xa, xo, ka, ko, red, rf);
 }
 
 // rank sort of the final set by (|c| desc, key asc) into mad_pair order
@@ -1078,12 +1114,13 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
                                                 counts, w.hist);
   k_refine_decide<<<1, kRefineThreads, 0, st>>>(cz, rf, counts, w.cap,
                                                 w.rcap, w.hist);
-  k_refine_split<<<1024, 256, 0, st>>>(rf, w.x, w.key, w.cap, counts, w.x2,
-                                       w.key2, w.cap2, &rf->nout, w.rx,
-                                       w.rkey, w.rcap);
+  k_refine_split<<<1024, 256, 0, st>>>(
+      rf, w.x, w.key, nullptr, nullptr, w.cap, counts, w.x2, w.key2, nullptr,
+      nullptr, w.cap2, &rf->nout, w.rx, w.rkey, nullptr, nullptr, w.rcap);
   k_fine_select<<<1, kFineThreads, 0, st>>>(
       cz, w.x, w.key, nullptr, nullptr, w.cap, counts, kCntWin, w.x2, w.key2,
-      nullptr, nullptr, w.cap2, kCntCand, rf, w.rx, w.rkey, w.rcap);
+      nullptr, nullptr, w.cap2, kCntCand, rf, w.rx, w.rkey, nullptr, nullptr,
+      w.rcap);
   // ---- low-precision filter of Omega_t' ----------------------------------
   if (lowp) {
     e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
@@ -1108,8 +1145,9 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   // ---- final selection: top t by |c| ----------------------------------------------
   e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
   if (e != hipSuccess) return e;
+  Refine* rf2 = rf + 1;
   k_coarse_decide<<<1, 256, 0, st>>>(w.hist, &counts[kCntCand], t, cz + 1,
-                                     nullptr);
+                                     nullptr, rf2);
   // final set in w.key[0 .. 4t): |c| bits, key, x, c; boundary after it
   uint64_t* fp = w.key;
   uint64_t* fkey = w.key + t;
@@ -1122,10 +1160,29 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   float* bc = (float*)(bx + bcap);
   k_cand_split<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
       cz + 1, w.x, w.key2, w.x2, w.c, w.cap2, fp, fkey, fx, fc, t, bp, bkey,
-      bx, bc, bcap, counts);
+      bx, bc, bcap, counts, rf2);
+  // a long boundary list of tied |c|: one digit of it on the whole grid;
+  // the refined list (|c| bits, key, x, c) in the refinement buffer, half
+  // as many entries as for the candidate selection.  The boundary holds at
+  // most t' entries: below kRefineFinalMin the three launches (which would
+  // return at once or save little) are left out.
+  const int64_t rcap2 = w.rcap / 2;
+  uint64_t* rp = w.rx;
+  uint64_t* rk = rp + rcap2;
+  uint64_t* rxx = rk + rcap2;
+  float* rc = (float*)(rxx + rcap2);
+  if (t_prime > kRefineFinalMin) {
+    k_refine_hist<<<256, kRefineThreads, 0, st>>>(cz + 1, rf2, bp, bkey, bcap,
+                                                  counts, w.hist);
+    k_refine_decide<<<1, kRefineThreads, 0, st>>>(cz + 1, rf2, counts, bcap,
+                                                  rcap2, w.hist);
+    k_refine_split<<<1024, 256, 0, st>>>(rf2, bp, bkey, bx, bc, bcap, counts,
+                                         fp, fkey, fx, fc, t, &rf2->nout, rp,
+                                         rk, rxx, rc, rcap2);
+  }
   k_fine_select<<<1, kFineThreads, 0, st>>>(
       cz + 1, bp, bkey, bx, bc, bcap, counts, kCntWin, fp, fkey, fx, fc, t,
-      kCntFinal);
+      kCntFinal, rf2, rp, rk, rxx, rc, rcap2);
   k_final_sort<<<blocks_for(t, 256, 1 << 30), 256, 0, st>>>(
       fkey, fx, fc, counts, t, n, bmax, s, x_shift, (PairOut*)out, n_out);
   return hipGetLastError();

@@ -1,12 +1,13 @@
-"""GPU parity of Alg. 3's first selection (the t' largest scores, ties by key)
-when the coarse bin that holds the t'-th score is long.
+"""GPU parity of Alg. 3's selections (the t' largest scores, then the t
+largest |c|, ties by key) when the coarse bin that holds the boundary
+element is long.
 
 The library refines such a boundary list with one full-grid radix pass (on
-the x values when they differ inside the bin, on the keys when they are all
-equal) before the single-workgroup exact selection.  Each case here is
-chosen so that the bin holding the t'-th positive score has more than 4096
-elements, which the test checks on the oracle's scores, and the candidate
-set must match the oracle's bit for bit."""
+the primary values when they differ inside the bin, on the keys when they
+are all equal) before the single-workgroup exact selection.  Each case here
+is chosen so that the boundary bin has more than 4096 elements, which the
+test checks on the oracle's results; the candidate set must match the
+oracle's bit for bit, and so must the final pairs where c is exact."""
 import sys
 
 import numpy as np
@@ -139,4 +140,27 @@ def test_long_boundary_repeat_calls_agree(mad_gpu):
         runs.append(gp.candidates()[0])
     assert np.array_equal(runs[0], runs[2]) and np.array_equal(runs[0], runs[3])
     assert len(runs[1]) == 100
+    gp.close()
+
+
+def test_long_final_boundary_exact(mad_gpu):
+    """The final selection (top t by |c|, ties by key) with 12,124 candidates
+    tied at the t-th |c|: 0/1 inputs make every c an integer, exact in fp32
+    as in FP64, so the t pairs and their order must equal the oracle's."""
+    A, B = (np.ascontiguousarray(x, np.float32)
+            for x in workloads.binary(700, 900, 48, density=0.3, seed=5))
+    n = B.shape[0]
+    s, tp, t = 1_000_000, 100_000, 20_000
+    op = oracle.Plan.dense(A, B)
+    o = op.topk(seed=42, s=s, t_prime=tp, t=t)
+    c = np.abs(o["tp_c"])
+    tv = np.sort(c)[::-1][t - 1]
+    say("final boundary: t-th |c|", tv, "tied", int((c == tv).sum()))
+    assert (c == tv).sum() > REFINE_MIN
+    gp = mad_gpu.Plan.dense(to_dev(A), to_dev(B))
+    for rep in range(2):  # the second call starts from the first's state
+        g = gp.topk(t=t, s=s, t_prime=tp, seed=42)
+        gkey = g["i"].cpu().numpy() * n + g["j"].cpu().numpy()
+        assert np.array_equal(gkey, o["key"]), rep
+        assert np.array_equal(g["c"].cpu().numpy().astype(np.float64), o["c"]), rep
     gp.close()
