@@ -437,47 +437,85 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_decide(
 }
 
 // refinement 3/3: elements ordered before the chosen bin join the winners,
-// the bin's elements form the refined list
-// (the final selection's lists also carry x and c: bextra / bc, when set)
+// the bin's elements form the refined list (the final selection's lists
+// also carry x and c: bextra / bc, when set).  Elements are classified from
+// the one column that orders them; each block stages the indices it keeps
+// in LDS and reserves output space once per flush (kept elements are rare:
+// a global atomic per block and round would serialise on the counters),
+// then gathers the kept elements' columns.
+constexpr int kRsU = 4;          // elements per thread and round
+constexpr int kRsStage = 2048;   // staged indices per list
+
 __global__ __launch_bounds__(256) void k_refine_split(
     const Refine* rf, const uint64_t* bx, const uint64_t* bkey,
     const uint64_t* bextra, const float* bc, int64_t bcap, int64_t* counts,
     uint64_t* wx, uint64_t* wkey, uint64_t* wextra, float* wc, int64_t wcap,
     unsigned long long* nout, uint64_t* rx, uint64_t* rkey, uint64_t* rextra,
     float* rc, int64_t rcap) {
-  __shared__ unsigned wcount[4];
-  __shared__ unsigned long long wbase[5];
+  __shared__ long long sidx[2][kRsStage];
+  __shared__ unsigned scnt[2];
+  __shared__ unsigned long long gbase[2];
   if (!rf->active) return;
   int64_t nb = counts[kCntBound];
   if (nb > bcap) nb = bcap;
   const uint64_t mask = rf->mask, prefix = rf->prefix;
   const bool kp = rf->key_phase != 0;
-  for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < nb;
-       b0 += (int64_t)gridDim.x * 256) {
-    const int64_t e = b0 + threadIdx.x;
-    uint64_t p = 0, kk = 0;
-    bool better = false, match = false;
-    if (e < nb) {
-      p = bx[e];
-      kk = bkey[e];
-      const uint64_t m = (kp ? kk : p) & mask;
-      better = kp ? m < prefix : m > prefix;
-      match = m == prefix;
+  const uint64_t* ord = kp ? bkey : bx;
+  const int t = threadIdx.x;
+  if (t == 0) scnt[0] = scnt[1] = 0;
+  __syncthreads();
+  uint64_t* ox[2] = {wx, rx};
+  uint64_t* okey[2] = {wkey, rkey};
+  uint64_t* oext[2] = {wextra, rextra};
+  float* oc[2] = {wc, rc};
+  const int64_t ocap[2] = {wcap, rcap};
+  unsigned long long* ctr[2] = {(unsigned long long*)&counts[kCntWin], nout};
+  const int64_t step = 256 * kRsU;
+  const int64_t stride = (int64_t)gridDim.x * step;
+  for (int64_t b0 = (int64_t)blockIdx.x * step; b0 < nb + stride;
+       b0 += stride) {
+    const bool last = b0 >= nb;  // one extra (uniform) round to flush
+    if (!last) {
+      uint64_t v[kRsU];
+#pragma unroll
+      for (int u = 0; u < kRsU; ++u) {
+        const int64_t e = b0 + t + (int64_t)u * 256;
+        v[u] = e < nb ? ord[e] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kRsU; ++u) {
+        const int64_t e = b0 + t + (int64_t)u * 256;
+        if (e >= nb) continue;
+        const uint64_t m = v[u] & mask;
+        const int L = (kp ? m < prefix : m > prefix) ? 0 : (m == prefix ? 1 : -1);
+        if (L < 0) continue;
+        sidx[L][atomicAdd(&scnt[L], 1u)] = (long long)e;
+      }
     }
-    const int64_t sw = block_append(
-        better, (unsigned long long*)&counts[kCntWin], wcount, wbase);
-    if (better && sw < wcap) {
-      wx[sw] = p;
-      wkey[sw] = kk;
-      if (bextra) wextra[sw] = bextra[e];
-      if (bc) wc[sw] = bc[e];
-    }
-    const int64_t sr = block_append(match, nout, wcount, wbase);
-    if (match && sr < rcap) {
-      rx[sr] = p;
-      rkey[sr] = kk;
-      if (bextra) rextra[sr] = bextra[e];
-      if (bc) rc[sr] = bc[e];
+    __syncthreads();
+    const unsigned n0 = scnt[0], n1 = scnt[1];
+    if (last || n0 > kRsStage - step || n1 > kRsStage - step) {
+      if (t < 2) {
+        const unsigned nl = t ? n1 : n0;
+        gbase[t] = nl ? atomicAdd(ctr[t], (unsigned long long)nl) : 0ull;
+      }
+      __syncthreads();
+      for (int L = 0; L < 2; ++L) {
+        const unsigned nl = L ? n1 : n0;
+        for (unsigned i = t; i < nl; i += 256) {
+          const int64_t e = (int64_t)sidx[L][i];
+          const int64_t d = (int64_t)gbase[L] + i;
+          if (d < ocap[L]) {
+            ox[L][d] = bx[e];
+            okey[L][d] = bkey[e];
+            if (bextra) oext[L][d] = bextra[e];
+            if (bc) oc[L][d] = bc[e];
+          }
+        }
+      }
+      __syncthreads();
+      if (t == 0) scnt[0] = scnt[1] = 0;
+      __syncthreads();
     }
   }
 }
