@@ -324,8 +324,9 @@ def bench_csr(args, cfg, data, mad):
     # creation validated the inputs; the timed refreshes skip the NaN / Inf
     # scan (the structure of the sparse inputs is checked on every build)
     plan.close()
-    plan = mad.Plan.csr(ta, tb, m, n, d,
-                        flags=mad.MAD_FLAG_TIMING | mad.MAD_FLAG_NO_CHECK)
+    # timed steps without the phase events; a second plan with them for the
+    # phase times
+    plan = mad.Plan.csr(ta, tb, m, n, d, flags=mad.MAD_FLAG_NO_CHECK)
     out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
     n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
 
@@ -342,6 +343,14 @@ def bench_csr(args, cfg, data, mad):
         step()
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    timed_out = out.clone()
+    plan.close()
+    plan = mad.Plan.csr(ta, tb, m, n, d,
+                        flags=mad.MAD_FLAG_TIMING | mad.MAD_FLAG_NO_CHECK)
+    step()
+    torch.cuda.synchronize()
+    if not torch.equal(out, timed_out):
+        raise SystemExit("the timing plan's result differs from the timed one")
     phases = []
     for _ in range(min(args.steps, 5)):
         step()
@@ -530,8 +539,10 @@ def main():
     # NaN / Inf check (and the host synchronisation that reports it)
     if not (bool(torch.isfinite(A).all()) and bool(torch.isfinite(B).all())):
         raise SystemExit("synthetic inputs hold NaN or Inf")
-    plan = mad.Plan.dense(A, B,
-                          flags=mad.MAD_FLAG_TIMING | mad.MAD_FLAG_NO_CHECK)
+    # the timed steps run on a plan without phase events (each event is a
+    # marker on the stream, about 2% of a C2 step); a second plan with them
+    # then gives the phase times and the sampling kernel's time
+    plan = mad.Plan.dense(A, B, flags=mad.MAD_FLAG_NO_CHECK)
     out = torch.empty((t, 3), dtype=torch.int64, device=dev)
     n_out = torch.zeros(1, dtype=torch.int64, device=dev)
 
@@ -550,6 +561,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    timed_out = out.clone()
+    plan.close()
+    plan = mad.Plan.dense(A, B,
+                          flags=mad.MAD_FLAG_TIMING | mad.MAD_FLAG_NO_CHECK)
+    step()
+    torch.cuda.synchronize()
+    if not torch.equal(out, timed_out):
+        raise SystemExit("the timing plan's result differs from the timed one")
     # phase times from the plan's events, in steps of their own (reading
     # them synchronises every step)
     phases = []
