@@ -133,7 +133,9 @@ int mad_plan_refresh(mad_plan* plan, void* stream);
  * Candidates are the pairs with x_ij > 0, the top t' of them by x
  * (ties by (i, j) ascending) are verified with fp32 dot products.
  * The first call for a given size allocates workspace; later calls with
- * the same or smaller (s, t', t) neither allocate nor synchronise.
+ * the same or smaller (s, t', t) neither allocate nor synchronise.  The
+ * workspace grows with s (score table, per-sample pairs, candidate lists)
+ * and holds up to 32 MiB more for refining a long boundary of tied scores.
  * ------------------------------------------------------------------------- */
 int mad_plan_topk(mad_plan* plan, int64_t t, int64_t s, int64_t t_prime,
                   uint64_t seed, mad_pair* out, int64_t* n_out, void* stream);
