@@ -688,8 +688,8 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_select(
 }
 
 // ---------------------------------------------------------------------------
-// verification: c = a_i . b_j in fp32, one wave per candidate; histogram of |c|
-// ---------------------------------------------------------------------------
+// verification: c = a_i . b_j in fp32, 16 lanes per candidate (four per
+// wave), 16-byte loads when the rows allow them; histogram of |c|
 __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
                                                 const int64_t* counts,
                                                 const float* A, const float* B,
@@ -701,19 +701,37 @@ __global__ __launch_bounds__(256) void k_verify(const uint64_t* key2,
   for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
   __syncthreads();
   const int64_t ncand = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t e = wave; e < ncand; e += nwaves) {
-    const uint64_t kk = key2[e];
-    const int64_t i = (int64_t)(kk / (uint64_t)n);
-    const int64_t j = (int64_t)(kk % (uint64_t)n);
-    const float* a = A + i * d;
-    const float* b = B + j * d;
+  const int q = threadIdx.x & 15;
+  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+  const bool vec = (d & 3) == 0 && ((uintptr_t)A & 15) == 0 &&
+                   ((uintptr_t)B & 15) == 0;
+  // the 16 lanes of a group share e, so they run the same rounds
+  for (int64_t e = grp; e < ncand; e += ngrp) {
     float acc = 0.0f;
-    for (int64_t k = lane; k < d; k += 64) acc = fmaf(a[k], b[k], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) {
+    {
+      const uint64_t kk = key2[e];
+      const int64_t i = (int64_t)(kk / (uint64_t)n);
+      const int64_t j = (int64_t)(kk % (uint64_t)n);
+      const float* a = A + i * d;
+      const float* b = B + j * d;
+      if (vec) {
+        const float4* a4 = (const float4*)a;
+        const float4* b4 = (const float4*)b;
+        for (int64_t k = q; k < d / 4; k += 16) {
+          const float4 x = a4[k], y = b4[k];
+          acc = fmaf(x.x, y.x, acc);
+          acc = fmaf(x.y, y.y, acc);
+          acc = fmaf(x.z, y.z, acc);
+          acc = fmaf(x.w, y.w, acc);
+        }
+      } else {
+        for (int64_t k = q; k < d; k += 16) acc = fmaf(a[k], b[k], acc);
+      }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (q == 0) {
       c[e] = acc;
       const uint64_t ab = __float_as_uint(fabsf(acc));
       absbits[e] = ab;
@@ -1083,7 +1101,7 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
   // the candidate count goes where the verification kernel reads it
   e = launch_fill_u64((uint64_t*)&counts[kCntCand], 1, (uint64_t)count, st);
   if (e != hipSuccess) return e;
-  k_verify<<<blocks_for(cnt * 64, 256, 2048), 256, 0, st>>>(
+  k_verify<<<blocks_for(cnt * 16, 256, 2048), 256, 0, st>>>(
       keys, counts, A, B, n, d, cnt, c, absbits, hist);
   k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], t, cz,
                                      nullptr);
@@ -1178,7 +1196,7 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
     k_verify_csr<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
         w.key2, counts, *csr, n, w.cap2, w.c, w.x, w.hist);
   else
-    k_verify<<<blocks_for(t_prime * 64, 256, 2048), 256, 0, st>>>(
+    k_verify<<<blocks_for(t_prime * 16, 256, 2048), 256, 0, st>>>(
         w.key2, counts, A, B, n, d, w.cap2, w.c, w.x, w.hist);
   // ---- final selection: top t by |c| ----------------------------------------------
   e = launch_fill_u64((uint64_t*)&counts[kCntBound], 2, 0ull, st);
