@@ -331,7 +331,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
       (e = mad::dev_alloc(p->cx2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->ck2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->cc, 4 * (size_t)ccap2)) != hipSuccess ||
-      (e = mad::dev_alloc(p->cr, 16 * (size_t)rcap)) != hipSuccess ||
+      (e = mad::dev_alloc(p->cr, 16 * (size_t)rcap + 65536)) != hipSuccess ||
       (e = mad::dev_alloc(p->misc, mad::kSelStateBytes + 4 * mad::kSelBins +
                                        256 + 256)) != hipSuccess ||
       (p->kind == 0 &&
@@ -357,6 +357,8 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   p->w.rx = (uint64_t*)p->cr.p;
   p->w.rkey = p->w.rx + rcap;
   p->w.rcap = rcap;
+  // the two splits' and / or slots (2 x 1024 blocks x 4 words) after it
+  p->w.part = (uint64_t*)((char*)p->cr.p + 16 * (size_t)rcap);
   char* misc = (char*)p->misc.p;
   p->w.state = misc;
   p->w.hist = (unsigned*)(misc + mad::kSelStateBytes);

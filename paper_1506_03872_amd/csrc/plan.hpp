@@ -314,6 +314,7 @@ struct SelectWork {
   void* state = nullptr;     // device select state
   unsigned int* hist = nullptr;
   int64_t* counts = nullptr; // device counters
+  uint64_t* part = nullptr;  // per-block and / or slots of the two splits
   uint64_t* rx = nullptr;    // refined boundary list of candidate selection (x, key)
   uint64_t* rkey = nullptr;
   int64_t rcap = 0;          // its capacity

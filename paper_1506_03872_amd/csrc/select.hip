@@ -52,7 +52,6 @@ struct Coarse {
 // list (ties of x leave millions of elements in one coarse bin), so that the
 // single-workgroup step 3 starts from one digit's bin of it
 struct Refine {
-  uint64_t xand, xor_, kand, kor;  // over the boundary list (k_score_split)
   uint64_t mask, prefix;           // the chosen digit's bin and bits above
   int64_t key_phase;               // 1: the digit is one of the key's
   int64_t active;                  // refined list in use
@@ -64,6 +63,9 @@ struct Refine {
 static_assert(3 * sizeof(Coarse) + 2 * sizeof(Refine) <= kSelStateBytes,
               "select state");
 constexpr int kRefineMin = 4096;   // shorter lists go to step 3 as they are
+constexpr int kRefineThreads = 1024;
+constexpr int kRefineThreadsMax = 1024;
+constexpr int kPartBlocks = 1024;  // and / or slots per selection
 constexpr int64_t kRefineFinalMin = 16384;  // t' above which the final
                                             // selection may refine
 
@@ -167,8 +169,6 @@ __global__ __launch_bounds__(256) void k_coarse_decide(
   for (int b = t; b < kBins; b += 256) hist[b] = 0;  // ready for reuse
   if (t == 0) {
     if (rf) {
-      rf->xand = rf->kand = ~0ull;
-      rf->xor_ = rf->kor = 0ull;
       rf->active = 0;
       rf->nout = 0ull;
     }
@@ -210,14 +210,14 @@ __device__ __forceinline__ int64_t block_append(bool take,
   return slot;
 }
 
-// and / or of a block's boundary elements into rf (256 threads, all of
-// them; any: this thread saw one): one set of atomics per block that holds
-// any
-__device__ void block_and_or(bool any, uint64_t xa, uint64_t xo, uint64_t ka,
+// and / or of a block's boundary elements (256 threads, all of them) into
+// its own slot part[4 * blockIdx.x ..]: no atomics (a few hundred blocks
+// on the same four words would serialise); the refinement kernels reduce
+// the slots when they run
+__device__ void block_and_or(uint64_t xa, uint64_t xo, uint64_t ka,
                              uint64_t ko, unsigned long long (*red)[4],
-                             Refine* rf) {
+                             uint64_t* part) {
   const int t = threadIdx.x;
-  if (!__syncthreads_or(any)) return;
   for (int off = 32; off > 0; off >>= 1) {
     xa &= __shfl_xor(xa, off, 64);
     xo |= __shfl_xor(xo, off, 64);
@@ -239,12 +239,11 @@ __device__ void block_and_or(bool any, uint64_t xa, uint64_t xo, uint64_t ka,
       ka &= red[2][w];
       ko |= red[3][w];
     }
-    {
-      atomicAnd((unsigned long long*)&rf->xand, (unsigned long long)xa);
-      atomicOr((unsigned long long*)&rf->xor_, (unsigned long long)xo);
-      atomicAnd((unsigned long long*)&rf->kand, (unsigned long long)ka);
-      atomicOr((unsigned long long*)&rf->kor, (unsigned long long)ko);
-    }
+    uint64_t* o = part + 4 * (int64_t)blockIdx.x;
+    o[0] = xa;
+    o[1] = xo;
+    o[2] = ka;
+    o[3] = ko;
   }
 }
 
@@ -260,14 +259,13 @@ __global__ __launch_bounds__(256) void k_score_split(
     const uint64_t* hkeys, const int64_t* hvals, int64_t cap,
     const int64_t* live, const Coarse* cz, uint64_t* wx, uint64_t* wkey,
     int64_t wcap, uint64_t* bx, uint64_t* bkey, int64_t bcap,
-    int64_t* counts, Refine* rf) {
+    int64_t* counts, uint64_t* part) {
   __shared__ unsigned long long sx[2][kStage];
   __shared__ unsigned long long sk[2][kStage];
   __shared__ unsigned scnt[2];
   __shared__ unsigned long long gbase[2];
   __shared__ unsigned long long red[4][4];
   uint64_t xa = ~0ull, xo = 0ull, ka = ~0ull, ko = 0ull;
-  bool any = false;
   const Coarse c = *cz;
   if (live && *live < cap) cap = *live;
   const int t = threadIdx.x;
@@ -299,7 +297,6 @@ __global__ __launch_bounds__(256) void k_score_split(
         sx[L][p] = (unsigned long long)v[u];
         sk[L][p] = kk;
         if (L) {
-          any = true;
           xa &= (uint64_t)v[u];
           xo |= (uint64_t)v[u];
           ka &= kk;
@@ -333,7 +330,7 @@ __global__ __launch_bounds__(256) void k_score_split(
       __syncthreads();
     }
   }
-  block_and_or(any, xa, xo, ka, ko, red, rf);
+  block_and_or(xa, xo, ka, ko, red, part);
 }
 
 // the refinement digit: the 11 bits below the highest bit in which the
@@ -345,15 +342,45 @@ struct RefineDigit {
   uint64_t common;  // their value
 };
 
-__device__ __forceinline__ RefineDigit refine_digit(const Refine& r) {
+// the digit from the split blocks' and / or slots (every thread of the
+// block calls it; blocks without boundary elements hold the identities)
+__device__ RefineDigit refine_digit(const uint64_t* part, int nblk) {
+  __shared__ unsigned long long r4[4][kRefineThreadsMax / 64];
+  uint64_t xa = ~0ull, xo = 0ull, ka = ~0ull, ko = 0ull;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    xa &= part[4 * b];
+    xo |= part[4 * b + 1];
+    ka &= part[4 * b + 2];
+    ko |= part[4 * b + 3];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    xa &= __shfl_xor(xa, off, 64);
+    xo |= __shfl_xor(xo, off, 64);
+    ka &= __shfl_xor(ka, off, 64);
+    ko |= __shfl_xor(ko, off, 64);
+  }
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    r4[0][wv] = xa;
+    r4[1][wv] = xo;
+    r4[2][wv] = ka;
+    r4[3][wv] = ko;
+  }
+  __syncthreads();
+  for (int w = 0; w < nw; ++w) {
+    xa &= r4[0][w];
+    xo |= r4[1][w];
+    ka &= r4[2][w];
+    ko |= r4[3][w];
+  }
   RefineDigit g;
-  const uint64_t dx = r.xand ^ r.xor_;
+  const uint64_t dx = xa ^ xo;
   g.key_phase = dx == 0ull;
-  const uint64_t diff = g.key_phase ? (r.kand ^ r.kor) : dx;
+  const uint64_t diff = g.key_phase ? (ka ^ ko) : dx;
   const int hd = diff ? 63 - __clzll((long long)diff) : 0;
   g.shift = hd >= kDigit - 1 ? hd - (kDigit - 1) : 0;
   g.above = hd < 63 ? ~0ull << (hd + 1) : 0ull;
-  g.common = (g.key_phase ? r.kand : r.xand) & g.above;
+  g.common = (g.key_phase ? ka : xa) & g.above;
   return g;
 }
 
@@ -363,17 +390,16 @@ __device__ __forceinline__ bool refine_wanted(const Coarse& c, int64_t nb) {
 }
 
 // refinement 1/3: histogram of the digit over the boundary list
-constexpr int kRefineThreads = 1024;
 
 __global__ __launch_bounds__(kRefineThreads) void k_refine_hist(
-    const Coarse* cz, const Refine* rf, const uint64_t* bx,
+    const Coarse* cz, const uint64_t* part, int nblk, const uint64_t* bx,
     const uint64_t* bkey, int64_t bcap, const int64_t* counts,
     unsigned* hist) {
   __shared__ unsigned h[kBins];
   int64_t nb = counts[kCntBound];
   if (nb > bcap) nb = bcap;
   if (!refine_wanted(*cz, nb)) return;
-  const RefineDigit g = refine_digit(*rf);
+  const RefineDigit g = refine_digit(part, nblk);
   const uint64_t* v = g.key_phase ? bkey : bx;
   for (int b = threadIdx.x; b < kBins; b += kRefineThreads) h[b] = 0;
   __syncthreads();
@@ -388,8 +414,8 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_hist(
 // element in selection order (x descending, or key ascending); clears the
 // histogram
 __global__ __launch_bounds__(kRefineThreads) void k_refine_decide(
-    Coarse* cz, Refine* rf, const int64_t* counts, int64_t bcap,
-    int64_t rcap, unsigned* hist) {
+    Coarse* cz, Refine* rf, const uint64_t* part, int nblk,
+    const int64_t* counts, int64_t bcap, int64_t rcap, unsigned* hist) {
   __shared__ unsigned long long wsum[kRefineThreads / 64];
   __shared__ int chosen;
   __shared__ unsigned long long before;
@@ -397,7 +423,7 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_decide(
   if (nb > bcap) nb = bcap;
   const Coarse c = *cz;
   if (!refine_wanted(c, nb)) return;
-  const RefineDigit g = refine_digit(*rf);
+  const RefineDigit g = refine_digit(part, nblk);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   // thread t owns positions 2t and 2t+1 of the selection order
   const int b0 = g.key_phase ? 2 * t : kBins - 1 - 2 * t;
@@ -896,12 +922,11 @@ __global__ __launch_bounds__(256) void k_cand_split(
     const uint64_t* x2, const float* c, int64_t cap2, uint64_t* fp,
     uint64_t* fkey, uint64_t* fx, float* fc, int64_t tcap, uint64_t* bp,
     uint64_t* bkey, uint64_t* bx, float* bc, int64_t bcap, int64_t* counts,
-    Refine* rf = nullptr) {
+    uint64_t* part = nullptr) {
   __shared__ unsigned wcount[4];
   __shared__ unsigned long long wbase[5];
   __shared__ unsigned long long red[4][4];
   uint64_t xa = ~0ull, xo = 0ull, ka = ~0ull, ko = 0ull;
-  bool any = false;
   const Coarse cc = *cz;
   const int64_t n = counts[kCntCand] < cap2 ? counts[kCntCand] : cap2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -928,14 +953,13 @@ __global__ __launch_bounds__(256) void k_cand_split(
       bkey[bs] = kk;
       bx[bs] = x2[e];
       bc[bs] = c[e];
-      any = true;
       xa &= p;
       xo |= p;
       ka &= kk;
       ko |= kk;
     }
   }
-  if (rf) block_and_or(any, xa, xo, ka, ko, red, rf);
+  if (part) block_and_or(xa, xo, ka, ko, red, part);
 }
 
 // rank sort of the final set by (|c| desc, key asc) into mad_pair order
@@ -1161,15 +1185,16 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   k_coarse_decide<<<1, 256, 0, st>>>(w.hist, nullptr, t_prime, cz,
                                      &counts[kCntPos], rf);
   // winners go straight to (x2, key2); the boundary bin to (x, key)
-  k_score_split<<<blocks_for(h.cap, 256 * 16, 512), 256, 0, st>>>(
-      h.keys, h.vals, h.cap, h.live, cz, w.x2, w.key2, w.cap2, w.x, w.key,
-      w.cap, counts, rf);
+  const unsigned nsplit = blocks_for(h.cap, 256 * 16, 512);
+  k_score_split<<<nsplit, 256, 0, st>>>(h.keys, h.vals, h.cap, h.live, cz,
+                                        w.x2, w.key2, w.cap2, w.x, w.key,
+                                        w.cap, counts, w.part);
   // a long boundary list: one digit of it on the whole grid (each kernel
   // returns at once otherwise)
-  k_refine_hist<<<256, kRefineThreads, 0, st>>>(cz, rf, w.x, w.key, w.cap,
-                                                counts, w.hist);
-  k_refine_decide<<<1, kRefineThreads, 0, st>>>(cz, rf, counts, w.cap,
-                                                w.rcap, w.hist);
+  k_refine_hist<<<256, kRefineThreads, 0, st>>>(
+      cz, w.part, (int)nsplit, w.x, w.key, w.cap, counts, w.hist);
+  k_refine_decide<<<1, kRefineThreads, 0, st>>>(
+      cz, rf, w.part, (int)nsplit, counts, w.cap, w.rcap, w.hist);
   k_refine_split<<<1024, 256, 0, st>>>(
       rf, w.x, w.key, nullptr, nullptr, w.cap, counts, w.x2, w.key2, nullptr,
       nullptr, w.cap2, &rf->nout, w.rx, w.rkey, nullptr, nullptr, w.rcap);
@@ -1214,9 +1239,11 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   uint64_t* bkey = bp + bcap;
   uint64_t* bx = bkey + bcap;
   float* bc = (float*)(bx + bcap);
-  k_cand_split<<<blocks_for(t_prime, 256 * 4, 1024), 256, 0, st>>>(
-      cz + 1, w.x, w.key2, w.x2, w.c, w.cap2, fp, fkey, fx, fc, t, bp, bkey,
-      bx, bc, bcap, counts, rf2);
+  const unsigned ncs = blocks_for(t_prime, 256 * 4, 1024);
+  uint64_t* part2 = w.part + 4 * kPartBlocks;
+  k_cand_split<<<ncs, 256, 0, st>>>(cz + 1, w.x, w.key2, w.x2, w.c, w.cap2,
+                                    fp, fkey, fx, fc, t, bp, bkey, bx, bc,
+                                    bcap, counts, part2);
   // a long boundary list of tied |c|: one digit of it on the whole grid;
   // the refined list (|c| bits, key, x, c) in the refinement buffer, half
   // as many entries as for the candidate selection.  The boundary holds at
@@ -1228,10 +1255,10 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   uint64_t* rxx = rk + rcap2;
   float* rc = (float*)(rxx + rcap2);
   if (t_prime > kRefineFinalMin) {
-    k_refine_hist<<<256, kRefineThreads, 0, st>>>(cz + 1, rf2, bp, bkey, bcap,
-                                                  counts, w.hist);
-    k_refine_decide<<<1, kRefineThreads, 0, st>>>(cz + 1, rf2, counts, bcap,
-                                                  rcap2, w.hist);
+    k_refine_hist<<<256, kRefineThreads, 0, st>>>(
+        cz + 1, part2, (int)ncs, bp, bkey, bcap, counts, w.hist);
+    k_refine_decide<<<1, kRefineThreads, 0, st>>>(
+        cz + 1, rf2, part2, (int)ncs, counts, bcap, rcap2, w.hist);
     k_refine_split<<<1024, 256, 0, st>>>(rf2, bp, bkey, bx, bc, bcap, counts,
                                          fp, fkey, fx, fc, t, &rf2->nout, rp,
                                          rk, rxx, rc, rcap2);
