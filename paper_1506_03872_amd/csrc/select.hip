@@ -993,9 +993,14 @@ __global__ __launch_bounds__(256) void k_final_sort(
       sk[o] = fkey[o0 + o];
     }
     __syncthreads();
-    if (e < nf)
-      for (int64_t o = 0; o < no; ++o)
-        rank += sa[o] > ae || (sa[o] == ae && sk[o] < ke);
+    if (e < nf) {
+      const int nn = (int)no;
+      int r = 0;
+#pragma unroll 8
+      for (int o = 0; o < nn; ++o)
+        r += (sa[o] > ae || (sa[o] == ae && sk[o] < ke)) ? 1 : 0;
+      rank += r;
+    }
   }
   if (e < nf) {
     PairOut p;
