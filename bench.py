@@ -1,4 +1,4 @@
-"""Benchmark: diamond sampling (Alg. 2 + Alg. 3) on one MI355X.
+"""Benchmark: diamond sampling (Alg. 3 with Alg. 2) on one MI355X.
 
 A step is one pass of the whole hot path over the resident inputs:
 mad_plan_refresh (norms, stage weights, quanta, alias tables) followed by
@@ -139,7 +139,7 @@ def cpu_baseline(A, B, cfg, seed):
     return dict(value=cfg["s"] / (t2 - t0), unit="samples/s", cores=1,
                 kind="oracle",
                 sample="one full step of the same workload (tables + s=%d "
-                       "samples + Alg. 3), single-threaded C oracle: %.1f s "
+                       "samples + Alg. 2), single-threaded C oracle: %.1f s "
                        "(tables %.1f s)" % (cfg["s"], t2 - t0, t1 - t0)), r
 
 
@@ -683,7 +683,7 @@ def main():
                   "distinct": stats["distinct"], "n_pos": stats["n_pos"],
                   "n_cand": stats["n_cand"]},
         # closed diamonds per second of the sampling kernel, and candidates
-        # verified per second of Alg. 3 (selection + verification + top t)
+        # verified per second of Alg. 2 (selection + verification + top t)
         "closed_per_s": round(closed / (sampler_ms * 1e-3), 1),
         "pairs_verified_per_s": round(
             stats["n_cand"] / (float(ph[:, 2].mean()) * 1e-3), 1),
@@ -696,7 +696,7 @@ def main():
 
 def verify_precisions(args, mad, plan, step, out, n_out, recall_of,
                       c_error):
-    """Whole steps under each verification precision of Alg. 3 (fp32 rows
+    """Whole steps under each verification precision of Alg. 2 (fp32 rows
     for every candidate, or bf16 / fp8 screening with error bounds first):
     ms per step, candidates re-ranked in fp32, and whether the top-t is the
     same pair list as under fp32 verification."""
@@ -774,7 +774,7 @@ def bruteforce_report(mad, A, B, t, recall_of, c_error):
 
 def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, bf,
                    target=0.95, seeds=5):
-    """Median wall time of whole steps (tables + sampling + Alg. 3) to reach
+    """Median wall time of whole steps (tables + sampling + Alg. 2) to reach
     mean threshold-recall@t >= target over `seeds` seeds, s on a x sqrt(10)
     grid, against the MFMA brute force (median of 5).  The sweep stops when
     a step takes 10x the fp32 brute force."""

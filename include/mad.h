@@ -4,8 +4,8 @@
  * Problem (Ballard, Kolda, Pinar, Seshadhri, "Diamond Sampling for
  * Approximate Maximum All-pairs Dot-product (MAD) Search", Definition 1):
  * given vectors a_1..a_m and b_1..b_n in R^d, find the t pairs (i, j) with
- * the largest |a_i . b_j|.  The library runs diamond sampling (Alg. 2) and
- * its postprocessing (Alg. 3) on one GPU, plus an exhaustive brute force.
+ * the largest |a_i . b_j|.  The library runs diamond sampling (Alg. 3) and
+ * its postprocessing (Alg. 2) on one GPU, plus an exhaustive brute force.
  *
  * Conventions for every entry point:
  *  - Layout: vectors are ROWS.  A is m x d row-major fp32 (a_i = A[i*d ..]),
@@ -34,8 +34,8 @@ extern "C" {
 #endif
 
 /* One result pair.  c = a_i . b_j computed in fp32 (the verification of
- * Alg. 3);
- * x = the sampler's score x_ij (the score update of Alg. 2) converted to fp32. */
+ * Alg. 2);
+ * x = the sampler's score x_ij (the score update of Alg. 3) converted to fp32. */
 typedef struct mad_pair {
   int64_t i;
   int64_t j;
@@ -65,8 +65,8 @@ enum {
    * values.  Builds then never synchronise with the host. */
   MAD_FLAG_NO_CHECK = 1u << 0,
   MAD_FLAG_TIMING = 1u << 1,   /* record HIP events around each phase      */
-  /* Gram matrix (Sec. 3.3, equal inputs): B must be A (same arrays, n = m).
-   * The scores are symmetrised before Alg. 3, X <- (X + X^T) / 2, kept as
+  /* Gram matrix (Sec. 3.2.2, equal inputs): B must be A (same arrays, n = m).
+   * The scores are symmetrised before Alg. 2, X <- (X + X^T) / 2, kept as
    * the exact sum x_ij + x_ji under the pair with i < j, and the diagonal
    * (a vector with itself) is left out, as in the paper's A^T A
    * experiments; results list pairs with i < j and report x = (x_ij +
@@ -77,7 +77,7 @@ enum {
 typedef struct mad_plan mad_plan;
 
 /* ---------------------------------------------------------------------------
- * mad_plan_create_dense -- preprocessing of Alg. 2 (the weights w_ki and the
+ * mad_plan_create_dense -- preprocessing of Alg. 3 (the weights w_ki and the
  * cumulative tables of Sec. 3.3 "Preprocessing" / Sec. 5.2) for dense A, B.
  *
  * Builds, in FP64 on the GPU, na_i = ||a_i||_1, nb_k = ||B_k*||_1,
@@ -119,15 +119,15 @@ int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
 int mad_plan_refresh(mad_plan* plan, void* stream);
 
 /* ---------------------------------------------------------------------------
- * mad_plan_topk -- Alg. 2 sampling loop + Alg. 3 postprocessing.
- *   s        number of three-path samples (Alg. 2 loop over l), s >= 0
- *   t_prime  budget of exact dot products (Alg. 3), t_prime >= t
+ * mad_plan_topk -- Alg. 3 sampling loop + Alg. 2 postprocessing.
+ *   s        number of three-path samples (Alg. 3 loop over l), s >= 0
+ *   t_prime  budget of exact dot products (Alg. 2), t_prime >= t
  *   t        number of pairs returned, t >= 1, t <= m*n
  *   seed     Philox key word 0
  *   out      (device) capacity t, filled in order of |c| descending, then
  *            (i, j) ascending
  *   n_out    (device) one int64: number of pairs written (<= t; fewer when
- *            fewer than t pairs have a positive score, Alg. 3)
+ *            fewer than t pairs have a positive score, Alg. 2)
  * Scores: x_ij accumulates sgn(a_ki b_kj a_k'i) b_k'j as int64 fixed point
  * with 2^F units, F = 62 - e - ceil(log2 max(s, 2)) where max|b| < 2^e.
  * Candidates are the pairs with x_ij > 0, the top t' of them by x
@@ -141,8 +141,8 @@ int mad_plan_topk(mad_plan* plan, int64_t t, int64_t s, int64_t t_prime,
                   uint64_t seed, mad_pair* out, int64_t* n_out, void* stream);
 
 /* ---------------------------------------------------------------------------
- * mad_plan_set_verify_precision -- arithmetic of the verification of Alg. 3
- * verification of Alg. 3 for later mad_plan_topk calls on a dense plan:
+ * mad_plan_set_verify_precision -- arithmetic of the verification of Alg. 2
+ * for later mad_plan_topk calls on a dense plan:
  *   MAD_FP32      (default) fp32 dot products of every candidate;
  *   MAD_BF16, MAD_FP8_E4M3  every candidate is first computed from bf16 /
  *                 fp8-e4m3 copies of A and B (per-vector power-of-two scale
@@ -178,10 +178,10 @@ void mad_plan_destroy(mad_plan* plan);
 
 /* ---------------------------------------------------------------------------
  * Plan statistics of the last mad_plan_topk (host outputs, synchronises):
- *   wnorm    ||W||_1 (FP64, the weights w_ki of Alg. 2, summed)
+ *   wnorm    ||W||_1 (FP64, the weights w_ki of Alg. 3, summed)
  *   closed   closed three-paths (diamonds) among the s samples
  *   distinct pairs with at least one closed diamond (nnz(X) <= s, Sec. 3.1)
- *   n_pos    pairs with x_ij > 0 (|Omega_s|, Alg. 3)
+ *   n_pos    pairs with x_ij > 0 (|Omega_s|, Alg. 2)
  *   n_cand   verified candidates (|Omega_t'|)
  * Any pointer may be NULL.
  * ------------------------------------------------------------------------- */
@@ -193,9 +193,9 @@ int mad_plan_stats(mad_plan* plan, double* wnorm, int64_t* closed,
  * mad_plan_refresh / mad_plan_topk of a plan made with MAD_FLAG_TIMING,
  * measured with HIP events recorded on the launch stream:
  *   ms[0] table construction (mad_plan_refresh or creation)
- *   ms[1] sampling kernel (Alg. 2 loop; with the hash form of X it
+ *   ms[1] sampling kernel (Alg. 3 loop; with the hash form of X it
  *         includes the score table updates)
- *   ms[2] postprocessing (Alg. 3: selections, verification, output)
+ *   ms[2] postprocessing (Alg. 2: selections, verification, output)
  *   ms[3] clearing the score table before sampling (hash form)
  *   ms[4] score accumulation from the per-sample pairs (pair form)
  *   ms[5] the sampling kernel alone (ms[1] less the k-order passes; dense
@@ -259,10 +259,10 @@ int mad_probe_memory(int kind, void* buf, int64_t nwords, int64_t nops,
 
 /* ---------------------------------------------------------------------------
  * MIPS (maximum inner product search): Sec. 2 notes that MAD with a single
- * vector on one side is MIPS, and Sec. 6 runs Alg. 2 + Alg. 3 once per
+ * vector on one side is MIPS, and Sec. 6 runs Alg. 3 with Alg. 2 once per
  * query vector with a sample budget s and a dot-product budget t'.
  *
- * mips_plan_create -- preprocessing of the database side of Alg. 2:
+ * mips_plan_create -- preprocessing of the database side of Alg. 3:
  * na_i = ||a_i||_1, v_k, and the alias tables T1[k] (i given k, weight
  * |a_ki| na_i) and T3[i] (k' given i, weight |a_k'i|), shared by every
  * query.  A (device) m x d fp32 row-major, borrowed as by
@@ -350,7 +350,7 @@ int mad_debug_table(mad_plan* plan, int which, int64_t idx, uint32_t* thr,
 int mad_debug_norms(mad_plan* plan, double* na, double* nb, double* v,
                     double* om);
 
-/* Per-sample stream of samples l0 .. l0+count-1 (the draws and the score update of Alg. 2):
+/* Per-sample stream of samples l0 .. l0+count-1 (the draws and the score update of Alg. 3):
  * k, i, j, kp (device int32) and inc (device int64: the fixed-point
  * increment, 0 when b_k'j = 0).  F is the fixed-point exponent to use;
  * qid is the query word of the counter (0 for MAD). */
@@ -360,7 +360,7 @@ int mad_debug_samples(mad_plan* plan, uint64_t seed, uint64_t qid,
                       void* stream);
 
 /* The score accumulation alone, for tests (the pair form of the score update of
- * Alg. 2): over n pairs (keys: device uint64, ~0 = none; vals: device fp32)
+ * Alg. 3): over n pairs (keys: device uint64, ~0 = none; vals: device fp32)
  * every key's sum of rne(val * 2^F) as int64, written unordered to
  * out_keys / out_x (device int64, capacity cap); *n_out (host) = number of
  * distinct keys.  The inputs are not modified.  Synchronises;

@@ -1,4 +1,4 @@
-"""CPU oracle for diamond sampling (Alg. 2 + Alg. 3) and exhaustive t-MAD.
+"""CPU oracle for diamond sampling (Alg. 3 with Alg. 2) and exhaustive t-MAD.
 
 TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may use this package; the product library
@@ -164,7 +164,7 @@ def fix_exponent(bmax: float, s: int) -> int:
 # plans
 # --------------------------------------------------------------------------
 class Plan:
-    """Tables for the weights w_ki of Alg. 2, for one (A, B); see the C file's
+    """Tables for the weights w_ki of Alg. 3, for one (A, B); see the C file's
     header."""
 
     def __init__(self, handle, m, n, d, keep):
@@ -204,8 +204,8 @@ class Plan:
         self._keep = (self._keep[0], B) if len(self._keep) == 2 else self._keep
 
     def set_gram(self, gram: bool = True):
-        """B = A: X <- (X + X^T) / 2 before Alg. 3 (kept as x_ij + x_ji
-        on i < j), diagonal dropped (Sec. 3.3)."""
+        """B = A: X <- (X + X^T) / 2 before Alg. 2 (kept as x_ij + x_ji
+        on i < j), diagonal dropped (Sec. 3.2.2)."""
         lib().orc_plan_set_gram(self._h, 1 if gram else 0)
 
     def close(self):
@@ -278,7 +278,7 @@ class Plan:
 
     def topk(self, seed: int, s: int, t_prime: int, t: int, F: int | None = None,
              qid: int = 0):
-        """Alg. 2 + Alg. 3.  Returns a dict with Omega_{t'} (candidate selection order) and
+        """Alg. 3 with Alg. 2.  Returns a dict with Omega_{t'} (candidate selection order) and
         Omega_t (final selection order) as key / x_fix / c arrays."""
         if F is None:
             F = self.fix_exponent(s)

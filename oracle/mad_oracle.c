@@ -7,9 +7,9 @@
  *
  * What it computes (Ballard, Kolda, Pinar, Seshadhri, "Diamond Sampling for
  * Approximate Maximum All-pairs Dot-product (MAD) Search"):
- *   - Alg. 2 (diamond sampling, general inputs): the weights w_ki,
+ *   - Alg. 3 (diamond sampling, general inputs): the weights w_ki,
  *     the s draws and the score update;
- *   - Alg. 3 (postprocessing): top-t' of X over {x_ij > 0}, exact dot
+ *   - Alg. 2 (postprocessing): top-t' of X over {x_ij > 0}, exact dot
  *     products of those candidates, top-t of the result;
  *   - the exhaustive t-MAD answer (Definition 1) by brute force.
  *
@@ -21,7 +21,7 @@
  *   R2  (k,i) is drawn in two stages: k with weight nb_k * v_k, then i given
  *       k with weight |a_ki| * na_i, where na_i = ||a_i||_1, nb_k = ||B_k*||_1
  *       and v_k = sum_i |a_ki| na_i.  The product of the two stage
- *       probabilities is exactly w_ki / ||W||_1, the draw of (k, i) in Alg. 2
+ *       probabilities is exactly w_ki / ||W||_1, the draw of (k, i) in Alg. 3
  *       (Lemma 1's proof factors the same way).
  *   R3  every FP64 sum and prefix sum uses the two-level run order of
  *       prefix_runs() below; products are single IEEE roundings.
@@ -37,9 +37,9 @@
  *       misprint its subscripts, and its algebra needs the line's form).
  *   R7  scores are exact int64 fixed point: inc = sign * rne(b_k'j * 2^F)
  *       with F = 62 - e_b - ceil(log2 max(s,2)), max|b| < 2^e_b.
- *   R8  ties in both selections of Alg. 3 are broken by (i, j) ascending,
+ *   R8  ties in both selections of Alg. 2 are broken by (i, j) ascending,
  *       and the final ranking is by |c_ij| (Definition 1 asks for the
- *       largest |a_i . b_j|; Alg. 3 (final selection) prints c_ij).
+ *       largest |a_i . b_j|; Alg. 2 (final selection) prints c_ij).
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
  */
@@ -334,7 +334,7 @@ static void trans_free(otrans *t) {
 }
 
 /* ------------------------------------------------------------------------
- * The oracle plan: everything that the weights w_ki of Alg. 2 and the
+ * The oracle plan: everything that the weights w_ki of Alg. 3 and the
  * draws need.
  *   na[i]  = ||a_i||_1         total of T3[i]
  *   nb[k]  = ||B_k*||_1        total of T2[k]
@@ -349,14 +349,14 @@ typedef struct orc_plan {
   otable T0;
   otable *T1, *T2, *T3;
   float bmax;   /* max |b| over all entries */
-  int gram;     /* B = A: symmetrise X and drop the diagonal (Sec. 3.3) */
+  int gram;     /* B = A: symmetrise X and drop the diagonal (Sec. 3.2.2) */
 } orc_plan;
 
 static void plan_build_aside(orc_plan *p) {
   int64_t m = p->m, d = p->d;
   p->na = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
   p->T3 = (otable *)calloc((size_t)(m > 0 ? m : 1), sizeof(otable));
-  /* T3[i]: k' given i with weight |a_k'i| (the draw of k' in Alg. 2) */
+  /* T3[i]: k' given i with weight |a_k'i| (the draw of k' in Alg. 3) */
   for (int64_t i = 0; i < m; ++i) {
     int64_t e0 = p->A.ptr[i], N = p->A.ptr[i + 1] - e0;
     double *w = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
@@ -385,7 +385,7 @@ static void plan_build_bside(orc_plan *p) {
   trans_build(&p->Bt, &p->B);
   p->nb = (double *)calloc((size_t)(d > 0 ? d : 1), sizeof(double));
   p->T2 = (otable *)calloc((size_t)(d > 0 ? d : 1), sizeof(otable));
-  /* T2[k]: j given k with weight |b_kj| (the draw of j in Alg. 2) */
+  /* T2[k]: j given k with weight |b_kj| (the draw of j in Alg. 3) */
   for (int64_t k = 0; k < d; ++k) {
     int64_t e0 = p->Bt.ptr[k], N = p->Bt.ptr[k + 1] - e0;
     double *w = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
@@ -513,7 +513,7 @@ static int sign_bit(float x) {
 }
 
 /* ------------------------------------------------------------------------
- * One iteration of the sampling loop of Alg. 2 (its draws and score update) for
+ * One iteration of the sampling loop of Alg. 3 (its draws and score update) for
  * sample l.  Returns 1 and fills *inc when the three-path closes
  * (b_k'j != 0), else 0.  k, i, j, kp are always filled.
  * ---------------------------------------------------------------------- */
@@ -569,7 +569,7 @@ static int cmp_kv_key(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
-/* Sec. 3.3, equal inputs: X <- (X + X^T) / 2 before Alg. 3.  Kept exact as
+/* Sec. 3.2.2, equal inputs: X <- (X + X^T) / 2 before Alg. 2.  Kept exact as
  * the integer sum x_ij + x_ji (twice the symmetric entry) under the key of
  * the pair with i < j; the diagonal (a vector paired with itself) is
  * dropped, as in the paper's A^T A experiments.  X is sorted by key; the
@@ -649,7 +649,7 @@ int64_t orc_plan_scores(const orc_plan *p, uint64_t seed, uint64_t qid,
 }
 
 /* ------------------------------------------------------------------------
- * Alg. 3 postprocessing.
+ * Alg. 2 postprocessing.
  * ---------------------------------------------------------------------- */
 typedef struct { int64_t key; int64_t x; double c; } cand;
 
@@ -686,7 +686,7 @@ static double exact_dot(const orc_plan *p, int64_t i, int64_t j) {
   return c;
 }
 
-/* Full Alg. 2 + Alg. 3 for one (B, qid).  Outputs Omega_{t'} in candidate selection
+/* Full Alg. 3 with Alg. 2 for one (B, qid).  Outputs Omega_{t'} in candidate selection
  * order (tp_* arrays, cap t_prime) and Omega_t in final selection order (t_* arrays,
  * cap t).  Returns |Omega_t|; *n_tp gets |Omega_{t'}|, *n_pos |Omega_s|,
  * *closed the number of closed three-paths. */

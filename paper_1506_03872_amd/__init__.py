@@ -137,7 +137,7 @@ def unpack_pairs(raw, n):
 
 
 class Plan:
-    """Owning handle of a mad_plan (tables of Alg. 2 for one A, B)."""
+    """Owning handle of a mad_plan (tables of Alg. 3 for one A, B)."""
 
     def __init__(self, handle, keep, m, n, d):
         self._h = handle
@@ -313,7 +313,7 @@ class Plan:
 
 
 class MipsPlan(Plan):
-    """Owning handle of a MIPS plan: the database tables (A side of Alg. 2)
+    """Owning handle of a MIPS plan: the database tables (A side of Alg. 3)
     shared by batches of queries."""
 
     @classmethod

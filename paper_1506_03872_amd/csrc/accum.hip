@@ -1,4 +1,4 @@
-// accum.hip -- the score matrix X, filled by the score update of Alg. 2, built
+// accum.hip -- the score matrix X, filled by the score update of Alg. 3, built
 // from the closed samples without per-sample global atomics.
 //
 // Sample l writes its pair at index l of two arrays: the key i*n + j

@@ -1,5 +1,5 @@
 // capi.hip -- the C ABI (include/mad.h): argument checks, plan lifetime,
-// workspace management and the launch sequence of Alg. 2 + Alg. 3.
+// workspace management and the launch sequence of Alg. 3 with Alg. 2.
 #include <stdarg.h>
 #include <stdlib.h>
 #include <stdio.h>

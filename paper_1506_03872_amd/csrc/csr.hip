@@ -3,7 +3,7 @@
 // rating experiments (Sec. 6).
 //
 // Preprocessing builds the same four stage distributions as the dense plan
-// (the weights w_ki of Alg. 2 in the two-stage form), but over the non-zeros only:
+// (the weights w_ki of Alg. 3 in the two-stage form), but over the non-zeros only:
 //   T3[i]  over the entries of a_i            weight |a_k'i|
 //   T1[k]  over the vectors i with an entry k weight |a_ki| na_i
 //   T2[k]  over the vectors j with an entry k weight |b_kj|
@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       for (int u = 0; u < U; ++u) {
         uint64_t ii = i[u], jj = j[u];
         ins[u] = closed[u];
-        if (a.gram) {  // Sec. 3.3: X + X^T on i < j, diagonal dropped
+        if (a.gram) {  // Sec. 3.2.2: X + X^T on i < j, diagonal dropped
           if (ii == jj) ins[u] = false;
           if (ii > jj) {
             const uint64_t tmp = ii;

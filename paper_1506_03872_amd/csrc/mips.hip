@@ -2,7 +2,7 @@
 // sampling.
 //
 // A MIPS query is the MAD problem with a single vector on the B side
-// (Sec. 2: a one-column matrix gives MIPS; Sec. 6 runs Alg. 2 once per
+// (Sec. 2: a one-column matrix gives MIPS; Sec. 6 runs Alg. 3 once per
 // query column).  Query q with budget s_q is exactly the general plan with
 // B = {q}: the database tables T1 (i given k) and T3 (k' given i) are shared,
 // stage 0 draws k with weight |q_k| v_k from the query's own table, the j
@@ -17,7 +17,7 @@
 //                       (contiguous l ranges of one query), with the query
 //                       row and its stage-0 table staged in LDS;
 //   k_mips_post         one workgroup per query (largest budgets first):
-//                       Alg. 3 on the query's score table -- keys with
+//                       Alg. 2 on the query's score table -- keys with
 //                       x > 0, the t'_q largest (ties by i), fp32 dot
 //                       products, the t largest |c| (ties by i), in order.
 #include "mad_common.hpp"

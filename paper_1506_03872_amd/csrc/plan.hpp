@@ -40,7 +40,7 @@ struct DenseTables {
   double* om = nullptr;  // d
   float* bmax = nullptr; // 1
   int* bad = nullptr;    // 1
-  int gram = 0;          // B = A, symmetrised scores (Sec. 3.3)
+  int gram = 0;          // B = A, symmetrised scores (Sec. 3.2.2)
   // the B-side family T2 is built on a stream of its own, forked from and
   // joined back into the caller's stream
   hipStream_t side = nullptr;
@@ -189,7 +189,7 @@ struct CsrTables {
   int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
   int* b_unit = nullptr;  // 1: every stored value of B is 1 (in bad's block)
   DeviceBuffer work;      // transposes' and tables' scratch
-  int gram = 0;           // B = A, symmetrised scores (Sec. 3.3)
+  int gram = 0;           // B = A, symmetrised scores (Sec. 3.2.2)
   bool validated = false; // the structure passed a check on this plan
   // the transposes' structure (pointers, rows, and the source position of
   // each entry) and the table layouts depend only on the sparsity

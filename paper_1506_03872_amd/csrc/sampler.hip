@@ -1,8 +1,8 @@
-// sampler.hip -- the sampling loop of Alg. 2 (its draws and score update) for dense
+// sampler.hip -- the sampling loop of Alg. 3 (its draws and score update) for dense
 // inputs.  Each sample either writes its (key, increment) pair at its own
 // index (pair form; X is then summed by accum.hip) or adds its increment to
 // an open-addressing hash table X (hash form).  Samples can run in k order
-// (the grouping of Sec. 5.2, Alg. 4) so that T1[k] and T2[k] stay in L2.
+// (the grouping of Sec. 5.2) so that T1[k] and T2[k] stay in L2.
 //
 // Sample l uses the Philox4x64-10 block with counter (l, qid, 0, 0) and key
 // (seed, 0): word 0 draws k from T0, word 1 draws i from T1[k], word 2 draws
@@ -43,8 +43,7 @@ struct OneSample {
   bool closed;
 };
 
-// Samples in k order (the locality ordering of Sec. 5.2, Alg. 4's first
-// step): `ell` lists sample offsets sorted by their stage-0 draw k.  The
+// Samples in k order (the first reordering of the locality scheme of Sec. 5.2): `ell` lists sample offsets sorted by their stage-0 draw k.  The
 // sampling launch then gives each XCD (workgroups are dispatched to the 8
 // XCDs round robin) a contiguous eighth of that list, walked in order by
 // its workgroups, so the rows T1[k] and T2[k] being drawn from stay in that
@@ -165,7 +164,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
       for (int u = 0; u < U; ++u) {
         uint64_t ii = smp[u].i, jj = smp[u].j;
         ins[u] = smp[u].closed;
-        if (a.gram) {  // Sec. 3.3: X + X^T on i < j, diagonal dropped
+        if (a.gram) {  // Sec. 3.2.2: X + X^T on i < j, diagonal dropped
           if (ii == jj) ins[u] = false;
           if (ii > jj) {
             const uint64_t tmp = ii;

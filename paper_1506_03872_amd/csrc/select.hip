@@ -1,4 +1,4 @@
-// select.hip -- Alg. 3 postprocessing on the GPU.
+// select.hip -- Alg. 2 postprocessing on the GPU.
 //
 //   candidate selection  Omega_s = pairs with x_ij > 0; Omega_t' = the t'
 //                        largest by x, ties by key (i*n + j) ascending;

@@ -1,4 +1,4 @@
-// tables.hip -- preprocessing for the weights w_ki of Alg. 2 on the GPU: FP64
+// tables.hip -- preprocessing for the weights w_ki of Alg. 3 on the GPU: FP64
 // norms and stage weights, integer quanta from the normalised cumulative sums
 // (Sec. 3.3 "Preprocessing", Sec. 5.2), and alias tables (the alias method
 // named in Sec. 5.1) built in parallel.
@@ -1175,7 +1175,7 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   if (B && !one_stream && (e = hipEventRecord(t.fork, st)) != hipSuccess)
     return e;
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (the draw of k' in
-  // Alg. 2)
+  // Alg. 3)
   // (enqueued before the B side so that this stream has work at once)
   if (t.T3.L <= 9) {
     e = small_tables(WRowAbs{A, d}, m, d, t.T3.L, t.T3.tot, t.T3.ent, st);
@@ -1188,7 +1188,7 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   if (e != hipSuccess) return e;
   // B side on the side stream: max |b| (and the finiteness check), then
   // T2[k]: j given k, weight |b_kj|; totals nb_k (the draw of j in
-  // Alg. 2)
+  // Alg. 3)
   if (B) {
     if (!one_stream && (e = hipStreamWaitEvent(sd, t.fork, 0)) != hipSuccess)
       return e;
@@ -1220,7 +1220,7 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   }
   if (e != hipSuccess || !B) return e;
   // T0: k with weight nb_k v_k; total ||W||_1 (the weights w_ki
-  // of Alg. 2 and its draw of (k, i))
+  // of Alg. 3 and its draw of (k, i))
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
     if (t.T0.L <= 9) {

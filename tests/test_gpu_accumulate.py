@@ -1,4 +1,4 @@
-"""GPU checks of the score accumulation (the pair form of the score update of Alg. 2)
+"""GPU checks of the score accumulation (the pair form of the score update of Alg. 3)
 through mad_debug_accumulate, against a numpy group-by of the same pairs:
 every key's sum of rne(v 2^F) in int64, bit for bit.  Cases reach the
 paths that sampled inputs rarely do: one key taking half of the pairs,

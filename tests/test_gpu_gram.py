@@ -1,4 +1,4 @@
-"""GPU parity of the Gram variant (Sec. 3.3, B = A): symmetrised scores
+"""GPU parity of the Gram variant (Sec. 3.2.2, B = A): symmetrised scores
 x_ij + x_ji on i < j with the diagonal left out, against the oracle's Gram
 mode, for dense and sparse inputs.  Scores and candidates bit-exact; the
 final pairs as for the general plan."""

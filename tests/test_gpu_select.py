@@ -1,4 +1,4 @@
-"""GPU parity of Alg. 3's selections (the t' largest scores, then the t
+"""GPU parity of Alg. 2's selections (the t' largest scores, then the t
 largest |c|, ties by key) when the coarse bin that holds the boundary
 element is long.
 

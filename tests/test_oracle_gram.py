@@ -1,5 +1,5 @@
-"""Pins for the oracle's Gram variant (Sec. 3.3, B = A): X <- (X + X^T)/2
-before Alg. 3, kept exact as x_ij + x_ji on the pair i < j, the diagonal
+"""Pins for the oracle's Gram variant (Sec. 3.2.2, B = A): X <- (X + X^T)/2
+before Alg. 2, kept exact as x_ij + x_ji on the pair i < j, the diagonal
 dropped.  Checked by the symmetrised Lemma 2 expectation and by the
 conservation of the off-diagonal mass of the plain X from the same
 samples."""

@@ -1,4 +1,4 @@
-"""Pins for the oracle's postprocessing (Alg. 3), its fixed-point scores and
+"""Pins for the oracle's postprocessing (Alg. 2), its fixed-point scores and
 its exhaustive t-MAD."""
 import numpy as np
 import pytest
@@ -26,7 +26,7 @@ def test_bruteforce_tie_break_by_pair_index():
 
 
 def test_topk_equals_exhaustive_when_every_pair_is_a_candidate():
-    # with t' = mn and enough samples that every top-t pair has x > 0, Alg. 3
+    # with t' = mn and enough samples that every top-t pair has x > 0, Alg. 2
     # returns exactly the exhaustive top-t
     A, B = workloads.planted(25, 30, 6, n_planted=5, seed=2)[:2]
     p = oracle.Plan.dense(A, B)
@@ -82,7 +82,7 @@ def test_fixed_point_scores_are_exact_sums():
         if inc != 0:
             ref[int(kk)] = ref.get(int(kk), 0) + int(inc)
     assert dict(zip(keys.tolist(), xfix.tolist())) == ref
-    # each increment is sgn(a_ki b_kj a_k'i) * b_k'j (the score update of Alg. 2) scaled by
+    # each increment is sgn(a_ki b_kj a_k'i) * b_k'j (the score update of Alg. 3) scaled by
     # 2^F and rounded to the nearest integer (halves to even)
     v = B[r["j"], r["kp"]].astype(np.float64)
     sg = np.sign(A[r["i"], r["k"]]) * np.sign(B[r["j"], r["k"]]) * \

@@ -1,4 +1,4 @@
-"""Statistical and closed-form pins for the oracle's sampler (Alg. 2):
+"""Statistical and closed-form pins for the oracle's sampler (Alg. 3):
 Lemma 1 (three-path probability), Lemma 2 (expectation of x_ij), the binary
 diamond count of Sec. 3.1, a one-coordinate closed form and Theorem 4's
 separation.  Every check uses fixed seeds, so each outcome is deterministic;

@@ -1,5 +1,5 @@
 """Pins for the oracle's sums, integer quanta, alias tables and the weights of
-Alg. 2 (the weights w_ki)."""
+Alg. 3 (the weights w_ki)."""
 import math
 
 import numpy as np
@@ -182,7 +182,7 @@ def test_plan_norms_and_wnorm_closed_form():
     A64, B64 = A.astype(np.float64), B.astype(np.float64)
     assert np.allclose(na, np.abs(A64).sum(1), rtol=1e-14)
     assert np.allclose(nb, np.abs(B64).sum(0), rtol=1e-14)
-    W = np.abs(A64) * na[:, None] * nb[None, :]      # w_ki of Alg. 2
+    W = np.abs(A64) * na[:, None] * nb[None, :]      # w_ki of Alg. 3
     assert np.allclose(v, (np.abs(A64) * na[:, None]).sum(0), rtol=1e-14)
     assert np.allclose(om, nb * v, rtol=1e-15)
     assert p.wnorm == pytest.approx(W.sum(), rel=1e-13)
