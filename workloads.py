@@ -32,6 +32,7 @@ WORKLOAD_IDS = {
     "binary": 6,
     "nonneg": 7,
     "tiny": 8,
+    "ragged_csr": 9,
 }
 
 
@@ -112,6 +113,30 @@ def powerlaw_csr(rows: int, d: int, nnz_per_vec: int, zipf_a: float = 1.5,
     val *= np.where(g.random((rows, z)) < 0.5, -1.0, 1.0).astype(np.float32)
     ptr = np.arange(rows + 1, dtype=np.int64) * z
     return ptr, idx.astype(np.int32).ravel(), val.ravel()
+
+
+def ragged_csr(m: int, n: int, d: int, seed: int = 0, density: float = 0.2):
+    """Small ragged sparse inputs for the sparse-path checks: A (m vectors)
+    and B (n vectors) as CSR over d coordinates, each entry stored with
+    probability ``density``, N(0,1) values.  The first vector of each side
+    is empty, the last coordinate is stored by no vector of either side,
+    and about one stored entry in ten is an explicit zero.  Returns
+    (a_csr, b_csr, m, n, d)."""
+    out = []
+    for role, rows in ((0, m), (1, n)):
+        g = rng("ragged_csr", role, seed)
+        mask = g.random((rows, d)) < density
+        mask[0] = False
+        mask[:, d - 1] = False
+        X = g.standard_normal((rows, d)).astype(np.float32)
+        zero = mask & (g.random((rows, d)) < 0.1)
+        X[~mask] = 0.0
+        X[zero] = 0.0
+        ptr = np.zeros(rows + 1, np.int64)
+        ptr[1:] = np.cumsum(mask.sum(axis=1))
+        r, c = np.nonzero(mask)
+        out.append((ptr, c.astype(np.int32), X[r, c].astype(np.float32)))
+    return out[0], out[1], m, n, d
 
 
 def csr_to_dense(ptr, idx, val, rows: int, d: int) -> np.ndarray:
