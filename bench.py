@@ -26,10 +26,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one dense sample: three 8-byte alias entries (T1[k],
-# T2[k], T3[i]; T0 sits in LDS) + the 4-byte fourth edge b_k'j read, and
-# the sample's 12-byte pair (8-byte key, 4-byte signed fourth edge) written.
+# T2[k], T3[i]; T0 sits in LDS) + the 4-byte fourth edge b_k'j, 28 bytes.
+# The design also writes each sample's 12-byte pair (8-byte key, 4-byte
+# signed fourth edge) for the score accumulation; that write is reported
+# beside the roofline, not counted in it.
 SAMPLE_READ_BYTES = 3 * 8 + 4
 PAIR_WRITE_BYTES = 12
+# worker processes of the all-cores oracle baseline (the host share of one
+# GPU)
+CPU_WORKERS_MAX = 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sample_dense_traffic.json")
 SAMPLER_SRC = os.path.join(ROOT, "paper_1506_03872_amd", "csrc",
                            "sampler.hip")
@@ -128,19 +133,77 @@ def exact_topk_gpu(A, B, t):
     return best_k.cpu().numpy(), best_v.cpu().numpy()
 
 
-def cpu_baseline(A, B, cfg, seed):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_range(job):
+    """Worker of the all-cores oracle baseline: the closed samples of one
+    range of l as (key, increment) arrays.  Each worker regenerates the
+    seeded inputs and builds its own oracle tables (part of the timed work)."""
+    import numpy as np
     import oracle
+    import workloads
+    config, data_seed, sample_seed, l0, cnt, F = job
+    _, data = workloads.make(config, seed=data_seed)
+    A, B = data["A"], data["B"]
+    p = oracle.Plan.dense(A, B)
+    r = p.samples(sample_seed, l0, cnt, F)
+    p.close()
+    closed = r["inc"] != 0
+    n = B.shape[0]
+    return (r["i"][closed].astype(np.int64) * n + r["j"][closed],
+            r["inc"][closed])
+
+
+def cpu_baseline(A, B, cfg, args):
+    """The oracle on the host for one whole step of the workload (tables, s
+    samples, Alg. 2): once on one thread, once split over worker processes
+    by ranges of l (each worker builds its tables; X is merged exactly)."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle
+    seed = args.seed
+    s, tp, t = cfg["s"], cfg["t_prime"], cfg["t"]
     t0 = time.perf_counter()
     p = oracle.Plan.dense(A, B)
     t1 = time.perf_counter()
-    r = p.topk(seed=seed, s=cfg["s"], t_prime=cfg["t_prime"], t=cfg["t"])
+    r1 = p.topk(seed=seed, s=s, t_prime=tp, t=t)
     t2 = time.perf_counter()
+    one = t2 - t0
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(ncpu, CPU_WORKERS_MAX))
+    F = p.fix_exponent(s)
+    bounds = np.linspace(0, s, workers + 1).astype(np.int64)
+    jobs = [(args.config, args.seed, seed, int(bounds[w]),
+             int(bounds[w + 1] - bounds[w]), F) for w in range(workers)]
+    t3 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        parts = pool.map(_oracle_range, jobs)
+    keys, x = oracle.merge_scores(parts)
+    rw = p.post(keys, x, tp, t)
+    t4 = time.perf_counter()
     p.close()
-    return dict(value=cfg["s"] / (t2 - t0), unit="samples/s", cores=1,
+    allc = t4 - t3
+    if not (np.array_equal(rw["key"], r1["key"]) and
+            np.array_equal(rw["tp_key"], r1["tp_key"])):
+        raise SystemExit("the split oracle run differs from the single one")
+    return dict(value=s / allc, unit="samples/s", cores=workers,
                 kind="oracle",
                 sample="one full step of the same workload (tables + s=%d "
-                       "samples + Alg. 2), single-threaded C oracle: %.1f s "
-                       "(tables %.1f s)" % (cfg["s"], t2 - t0, t1 - t0)), r
+                       "samples + Alg. 2): %d worker processes over ranges "
+                       "of l, each building its own tables, X merged exactly "
+                       "(%.2f s)" % (s, workers, allc),
+                host_cpu_count=ncpu, cpu_model=cpu_model(),
+                one_thread={"value": s / one, "seconds": round(one, 2),
+                            "tables_seconds": round(t1 - t0, 2)}), r1
 
 
 # algorithmic bytes of one MIPS sample: the T1[k] and T3[i] alias entries
@@ -583,7 +646,7 @@ def main():
     res = mad.unpack_pairs(out, int(n_out.item()))
 
     closed = stats["closed"]
-    alg_bytes = (SAMPLE_READ_BYTES + PAIR_WRITE_BYTES) * s
+    alg_bytes = SAMPLE_READ_BYTES * s
     achieved = alg_bytes / (sampler_ms * 1e-3) / 1e9
     traffic = measured_traffic(s)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2),
@@ -592,27 +655,23 @@ def main():
                 "traffic": traffic,
                 "kernel": "k_sample_dense",
                 "kernel_ms": round(sampler_ms, 4),
-                "algorithmic_bytes_per_launch": alg_bytes}
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "algorithmic_bytes_per_sample": SAMPLE_READ_BYTES,
+                "pair_write_bytes_per_launch": PAIR_WRITE_BYTES * s}
 
     log("%.3f ms/step" % ms_per_step)
     log("memory ceilings")
     ceil = memory_ceilings(mad)
-    # random-access bound of one dense sample: three random 8-byte alias
-    # entries, one random 4-byte fourth edge, one streamed 16-byte pair
-    # (about one copy operation of 8 + 8 bytes)
-    t_sample = (3.0 / ceil["rand_load_8B"] + 1.0 / ceil["rand_load_4B"] +
-                1.0 / ceil["stream_copy_8B"]) * 1e-9
-    bound_rate = 1.0 / t_sample
     if traffic:
-        roofline["line_traffic_GBps"] = round(traffic / (sampler_ms * 1e-3)
-                                              / 1e9, 1)
-        roofline["line_traffic_frac"] = round(
-            roofline["line_traffic_GBps"] / HBM_PEAK_GBS, 4)
-    roofline["random_access"] = {
-        "ceilings_Gops": {k: round(v, 3) for k, v in ceil.items()},
-        "bound_samples_per_s": round(bound_rate, 1),
-        "sampler_samples_per_s": round(s / (sampler_ms * 1e-3), 1),
-        "frac": round(s / (sampler_ms * 1e-3) / bound_rate, 4)}
+        roofline["traffic_GBps"] = round(traffic / (sampler_ms * 1e-3) / 1e9,
+                                         1)
+        roofline["traffic_frac_of_peak"] = round(
+            roofline["traffic_GBps"] / HBM_PEAK_GBS, 4)
+        roofline["traffic_bytes_per_sample"] = round(traffic / s, 1)
+    # reference rates of uniform random accesses over a 512 MB buffer (not a
+    # bound of the sampler, whose ordered draws hit L2 and the MALL)
+    roofline["random_access_reference_Gops"] = {
+        k: round(v, 3) for k, v in ceil.items()}
     extra = {}
     if not args.no_recall:
         log("exact top-t for recall")
@@ -652,7 +711,7 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        base, _ = cpu_baseline(A_h, B_h, cfg, args.seed)
+        base, _ = cpu_baseline(A_h, B_h, cfg, args)
 
     line = {
         "metric": "diamond samples/s + time-to-recall@0.95 vs MFMA brute "
@@ -807,10 +866,20 @@ def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, bf,
                                                 pt["ms_end_to_end"]))
         if pt["recall_mean"] >= target:
             reached = pt
+            stop = "recall %.2f reached" % target
             break
         nxt = int(round(s * 10 ** 0.5))
-        # the score table holds 2 min(s, mn) 16-byte slots: stay below 64 GB
-        if pt["ms_end_to_end"] > limit or 32 * nxt > (64 << 30):
+        if pt["ms_end_to_end"] > limit:
+            stop = ("step time %.1f ms > 10x the fp32 brute force (%.1f ms)"
+                    % (pt["ms_end_to_end"], limit))
+            break
+        # workspace of the next s (pairs, partition, score table, about 64
+        # bytes per sample): stay below 64 GiB
+        if 64 * nxt > (64 << 30):
+            stop = ("next s = %d would need about %.0f GiB of workspace "
+                    "(cap 64 GiB); last step %.1f ms, 10x brute force is "
+                    "%.1f ms" % (nxt, 64 * nxt / 2 ** 30,
+                                 pt["ms_end_to_end"], limit))
             break
         s = nxt
     best = max(sweep, key=lambda p: p["recall_mean"])
@@ -821,7 +890,10 @@ def time_to_recall(args, mad, plan, A, B, t, tp, recall_of, bf,
             "ms_at_target_amortized": (reached["ms_amortized"]
                                        if reached else None),
             "best_recall": best["recall_mean"], "best_s": best["s"],
-            "stop_rule": "step time > 10x fp32 brute force (%.1f ms)" % limit,
+            "stop_rule": "stop when recall reaches the target, a step takes "
+                         "10x the fp32 brute force, or the workspace cap is "
+                         "reached",
+            "stop_reason": stop,
             "sweep": sweep}
 
 

@@ -167,6 +167,34 @@ int mad_plan_set_verify_precision(mad_plan* plan, int precision, void* stream);
 int mad_plan_verify_stats(mad_plan* plan, int64_t* n_cand,
                           int64_t* n_reranked);
 
+/* ---------------------------------------------------------------------------
+ * Launch choices of a MAD plan.  None changes a result: scores are exact
+ * int64 sums, so X, the candidates and the output are the same under every
+ * setting; they exist for measurement and for tests of each code path.
+ *   MAD_OPT_ACCUM          how X (the score update of Alg. 3) is built:
+ *                          MAD_ACCUM_PAIRS (default): every sample writes
+ *                          its (key, signed fourth edge) pair and the pairs
+ *                          are summed per key after a hash partition;
+ *                          MAD_ACCUM_HASH: the sampler adds each increment
+ *                          into an open-addressing table with int64 atomics.
+ *                          Dense and sparse plans.
+ *   MAD_OPT_SAMPLER_ORDER  dense plans, d <= 1024: 1 (default) draws the
+ *                          samples grouped by their stage-0 coordinate k
+ *                          (the reordering of Sec. 5.2), 0 in index order.
+ *   MAD_OPT_ORDER_CHUNK    dense plans: samples per ordering pass, a power
+ *                          of two in [2^12, 2^28] (default 2^28); longer
+ *                          runs are ordered in consecutive chunks.
+ * The process defaults come from the environment (MAD_ACCUM=hash,
+ * MAD_SAMPLER_ORDER=0).  A change takes effect at the next mad_plan_topk,
+ * which then re-sizes its workspace (allocates and synchronises once).
+ * MAD_EINVAL for an unknown option or value, MAD_EUNSUPPORTED for an option
+ * the plan's kind does not have; MIPS plans have none of these options.
+ * ------------------------------------------------------------------------- */
+enum { MAD_OPT_ACCUM = 0, MAD_OPT_SAMPLER_ORDER = 1, MAD_OPT_ORDER_CHUNK = 2 };
+enum { MAD_ACCUM_PAIRS = 0, MAD_ACCUM_HASH = 1 };
+int mad_plan_set_option(mad_plan* plan, int option, int64_t value);
+int mad_plan_get_option(mad_plan* plan, int option, int64_t* value);
+
 /* One-shot form of the two calls above for dense inputs:
  * create + topk + destroy.  Synchronises `stream` before returning. */
 int mad_topk(const float* A, int64_t m, const float* B, int64_t n, int64_t d,

@@ -87,6 +87,9 @@ def _declare(L):
     L.orc_plan_topk.argtypes = [_P, _u64, _u64, _i64, _i64, _i64, C.c_int,
                                 _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_plan_topk.restype = _i64
+    L.orc_plan_post.argtypes = [_P, _P, _P, _i64, _i64, _i64, _P, _P, _P, _P,
+                                _P, _P, _P, _P]
+    L.orc_plan_post.restype = _i64
     L.orc_bruteforce_dense.argtypes = [_P, _i64, _P, _i64, _i64, _i64, _P, _P]
     L.orc_bruteforce_dense.restype = _i64
 
@@ -299,6 +302,47 @@ class Plan:
         return dict(F=F, tp_key=tp_key[:n_tp], tp_x=tp_x[:n_tp],
                     tp_c=tp_c[:n_tp], key=t_key[:nt], x=t_x[:nt],
                     c=t_c[:nt], n_pos=npos.value, closed=closed.value)
+
+
+    def post(self, keys, xfix, t_prime: int, t: int):
+        """Alg. 2 on a given score matrix X (keys i*n + j, int64 x_fix, any
+        order): the same outputs as ``topk`` without its sampling."""
+        keys = np.ascontiguousarray(keys, dtype=np.int64)
+        xfix = np.ascontiguousarray(xfix, dtype=np.int64)
+        tp_key = np.zeros(max(t_prime, 1), np.int64)
+        tp_x = np.zeros(max(t_prime, 1), np.int64)
+        tp_c = np.zeros(max(t_prime, 1), np.float64)
+        t_key = np.zeros(max(t, 1), np.int64)
+        t_x = np.zeros(max(t, 1), np.int64)
+        t_c = np.zeros(max(t, 1), np.float64)
+        ntp = C.c_int64()
+        npos = C.c_int64()
+        nt = lib().orc_plan_post(self._h, _ptr(keys), _ptr(xfix), len(keys),
+                                 t_prime, t, _ptr(tp_key), _ptr(tp_x),
+                                 _ptr(tp_c), C.byref(ntp), _ptr(t_key),
+                                 _ptr(t_x), _ptr(t_c), C.byref(npos))
+        n_tp = ntp.value
+        return dict(tp_key=tp_key[:n_tp], tp_x=tp_x[:n_tp], tp_c=tp_c[:n_tp],
+                    key=t_key[:nt], x=t_x[:nt], c=t_c[:nt],
+                    n_pos=npos.value)
+
+
+def merge_scores(parts):
+    """X from per-range sample streams: concatenate the (key, inc) pairs of
+    closed samples and sum each key's increments (exact int64 sums, so the
+    split into ranges does not matter)."""
+    keys = np.concatenate([p[0] for p in parts]) if parts else \
+        np.zeros(0, np.int64)
+    inc = np.concatenate([p[1] for p in parts]) if parts else \
+        np.zeros(0, np.int64)
+    order = np.argsort(keys, kind="stable")
+    keys, inc = keys[order], inc[order]
+    if len(keys) == 0:
+        return keys, inc
+    first = np.ones(len(keys), bool)
+    first[1:] = keys[1:] != keys[:-1]
+    starts = np.nonzero(first)[0]
+    return keys[starts], np.add.reduceat(inc, starts)
 
 
 # --------------------------------------------------------------------------

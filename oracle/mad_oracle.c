@@ -686,27 +686,24 @@ static double exact_dot(const orc_plan *p, int64_t i, int64_t j) {
   return c;
 }
 
-/* Full Alg. 3 with Alg. 2 for one (B, qid).  Outputs Omega_{t'} in candidate selection
- * order (tp_* arrays, cap t_prime) and Omega_t in final selection order (t_* arrays,
- * cap t).  Returns |Omega_t|; *n_tp gets |Omega_{t'}|, *n_pos |Omega_s|,
- * *closed the number of closed three-paths. */
-int64_t orc_plan_topk(const orc_plan *p, uint64_t seed, uint64_t qid,
-                      int64_t s, int64_t t_prime, int64_t t, int F,
-                      int64_t *tp_key, int64_t *tp_x, double *tp_c,
-                      int64_t *n_tp, int64_t *t_key, int64_t *t_x,
-                      double *t_c, int64_t *n_pos, int64_t *closed) {
-  kv *X;
-  int64_t nd = build_scores(p, seed, qid, s, F, &X, closed);
+/* Alg. 2 on a given score matrix X (nd entries (key, x_fix), any order):
+ * Omega_s = {x > 0}, its top t' by (x desc, key asc), their exact dot
+ * products, and the top t by |c|.  Outputs as for orc_plan_topk.  Returns
+ * |Omega_t|. */
+int64_t orc_plan_post(const orc_plan *p, const int64_t *keys,
+                      const int64_t *xfix, int64_t nd, int64_t t_prime,
+                      int64_t t, int64_t *tp_key, int64_t *tp_x, double *tp_c,
+                      int64_t *n_tp, int64_t *t_key, int64_t *t_x, double *t_c,
+                      int64_t *n_pos) {
   cand *c = (cand *)malloc(sizeof(cand) * (size_t)(nd > 0 ? nd : 1));
   int64_t np = 0;
   for (int64_t e = 0; e < nd; ++e)
-    if (X[e].inc > 0) { /* Omega_s = {x_ij > 0} */
-      c[np].key = X[e].key;
-      c[np].x = X[e].inc;
+    if (xfix[e] > 0) { /* Omega_s = {x_ij > 0} */
+      c[np].key = keys[e];
+      c[np].x = xfix[e];
       c[np].c = 0.0;
       ++np;
     }
-  free(X);
   if (n_pos) *n_pos = np;
   /* candidate selection: top-t' of X */
   qsort(c, (size_t)np, sizeof(cand), cmp_post1);
@@ -729,6 +726,31 @@ int64_t orc_plan_topk(const orc_plan *p, uint64_t seed, uint64_t qid,
     if (t_c) t_c[e] = c[e].c;
   }
   free(c);
+  return nt;
+}
+
+/* Full Alg. 3 with Alg. 2 for one (B, qid).  Outputs Omega_{t'} in
+ * candidate selection order (tp_* arrays, cap t_prime) and Omega_t in final
+ * selection order (t_* arrays, cap t).  Returns |Omega_t|; *n_tp gets
+ * |Omega_{t'}|, *n_pos |Omega_s|, *closed the number of closed three-paths. */
+int64_t orc_plan_topk(const orc_plan *p, uint64_t seed, uint64_t qid,
+                      int64_t s, int64_t t_prime, int64_t t, int F,
+                      int64_t *tp_key, int64_t *tp_x, double *tp_c,
+                      int64_t *n_tp, int64_t *t_key, int64_t *t_x,
+                      double *t_c, int64_t *n_pos, int64_t *closed) {
+  kv *X;
+  int64_t nd = build_scores(p, seed, qid, s, F, &X, closed);
+  int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd > 0 ? nd : 1));
+  int64_t *xfix = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd > 0 ? nd : 1));
+  for (int64_t e = 0; e < nd; ++e) {
+    keys[e] = X[e].key;
+    xfix[e] = X[e].inc;
+  }
+  free(X);
+  int64_t nt = orc_plan_post(p, keys, xfix, nd, t_prime, t, tp_key, tp_x,
+                             tp_c, n_tp, t_key, t_x, t_c, n_pos);
+  free(keys);
+  free(xfix);
   return nt;
 }
 

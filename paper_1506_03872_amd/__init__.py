@@ -19,6 +19,8 @@ MAD_OK, MAD_EINVAL, MAD_ENOMEM, MAD_EHIP, MAD_EOVERFLOW, MAD_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 MAD_FP32, MAD_BF16, MAD_FP8_E4M3 = 0, 1, 2
 MAD_FLAG_NONE, MAD_FLAG_NO_CHECK, MAD_FLAG_TIMING, MAD_FLAG_GRAM = 0, 1, 2, 4
+MAD_OPT_ACCUM, MAD_OPT_SAMPLER_ORDER, MAD_OPT_ORDER_CHUNK = 0, 1, 2
+MAD_ACCUM_PAIRS, MAD_ACCUM_HASH = 0, 1
 
 # every symbol include/mad.h declares
 EXPORTS = (
@@ -30,7 +32,8 @@ EXPORTS = (
     "mad_bruteforce_topk", "mips_plan_create", "mips_topk_batch",
     "mips_get_config", "mips_set_config", "mips_autotune", "mips_stats",
     "mips_debug_scores", "mad_plan_set_verify_precision",
-    "mad_plan_verify_stats", "mad_debug_accumulate",
+    "mad_plan_verify_stats", "mad_debug_accumulate", "mad_plan_set_option",
+    "mad_plan_get_option",
 )
 
 
@@ -80,6 +83,8 @@ def lib():
                                           _i64, _i64, _P, _P, _P, _P]
         L.mad_plan_set_verify_precision.argtypes = [_P, C.c_int, _P]
         L.mad_plan_verify_stats.argtypes = [_P, _P, _P]
+        L.mad_plan_set_option.argtypes = [_P, C.c_int, _i64]
+        L.mad_plan_get_option.argtypes = [_P, C.c_int, _P]
         L.mips_plan_create.argtypes = [_P, _i64, _i64, _u32, _P,
                                        C.POINTER(_P)]
         L.mips_topk_batch.argtypes = [_P, _P, _i64, _P, _P, _i64, _u64, _P,
@@ -214,6 +219,15 @@ class Plan:
     def set_verify_precision(self, precision, stream=None):
         _check(lib().mad_plan_set_verify_precision(self._h, precision,
                                                    _stream(stream)))
+
+    def set_option(self, option, value):
+        """mad_plan_set_option: a launch choice (MAD_OPT_*), result-invariant."""
+        _check(lib().mad_plan_set_option(self._h, option, value))
+
+    def get_option(self, option):
+        v = C.c_int64()
+        _check(lib().mad_plan_get_option(self._h, option, C.byref(v)))
+        return v.value
 
     def verify_stats(self):
         nc, nr = C.c_int64(), C.c_int64()

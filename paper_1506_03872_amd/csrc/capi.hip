@@ -107,6 +107,10 @@ struct mad_plan {
   mad::DeviceBuffer hk, hv, cx, ck, cx2, ck2, cc, cr, misc, ord, acc;
   mad::HashTable h;
   bool pairs = false;  // X built from per-sample pairs (else a hash table)
+  // launch choices (result-invariant): how X is built and the sampler's
+  // ordering; defaults from the environment, changed by mad_plan_set_option
+  int opt_accum = -1;  // MAD_ACCUM_PAIRS or MAD_ACCUM_HASH (-1: default)
+  mad::SampleOptions sopt;
   mad::HashTable h_run;  // X as the last run left it
   mad::SelectWork w;
   mad::SampleCounters* ctr = nullptr;
@@ -217,6 +221,7 @@ int mad_plan_create_dense(const float* A, int64_t m, const float* B,
   p->n = n;
   p->d = d;
   p->flags = flags;
+  p->sopt = mad::sample_options_default();
   hipError_t e = mad::dense_tables_alloc(p->dt, m, n, d);
   p->dt.gram = (flags & MAD_FLAG_GRAM) ? 1 : 0;
   if (e == hipSuccess && (flags & MAD_FLAG_TIMING))
@@ -287,13 +292,19 @@ void mad_plan_destroy(mad_plan* p) {
 
 // How X is built (result-invariant): from per-sample pairs by partitioned
 // accumulation (default), or in an open-addressing hash table updated by the
-// sampler with atomics (MAD_ACCUM=hash).
-static bool accum_pairs() {
-  static const bool v = [] {
+// sampler with atomics (process default MAD_ACCUM=hash; per plan through
+// mad_plan_set_option).
+static int accum_default() {
+  static const int v = [] {
     const char* e = getenv("MAD_ACCUM");
-    return !(e && strcmp(e, "hash") == 0);
+    return (e && strcmp(e, "hash") == 0) ? MAD_ACCUM_HASH : MAD_ACCUM_PAIRS;
   }();
   return v;
+}
+
+static bool accum_pairs(const mad_plan* p) {
+  const int a = p->opt_accum < 0 ? accum_default() : p->opt_accum;
+  return a == MAD_ACCUM_PAIRS;
 }
 
 // per-sample pairs: 8-byte keys, then 4-byte values (16-byte aligned end)
@@ -309,7 +320,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   const int64_t t2 = t > p->ws_t ? t : p->ws_t;
   const double mn = (double)p->m * (double)p->n;
   const int64_t pairs = (double)s2 < mn ? s2 : (int64_t)mn;
-  const bool use_pairs = accum_pairs();
+  const bool use_pairs = accum_pairs(p);
   // pair form: X is a table of s entries (each bin of pairs leaves its
   // distinct keys in its own range); hash form: a table of twice min(s, mn)
   // slots, rounded up to a power of two
@@ -335,7 +346,8 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
       (e = mad::dev_alloc(p->misc, mad::kSelStateBytes + 4 * mad::kSelBins +
                                        256 + 256)) != hipSuccess ||
       (p->kind == 0 &&
-       (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(s2, p->d))) !=
+       (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(s2, p->d,
+                                                           p->sopt))) !=
            hipSuccess) ||
       (use_pairs &&
        (e = mad::dev_alloc(p->acc, pair_bytes(s2) + mad::accum_bytes(s2))) !=
@@ -419,8 +431,8 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
             "sampling");
   else
     HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, h,
-                                     p->ctr, p->ord.p, p->ord.bytes, p->ev[7],
-                                     st),
+                                     p->ctr, p->ord.p, p->ord.bytes, p->sopt,
+                                     p->ev[7], st),
             "sampling");
   record(p, 4, st);
   if (p->pairs) {
@@ -449,6 +461,65 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   p->last_s = s;
   p->ran = true;
   return MAD_OK;
+}
+
+int mad_plan_set_option(mad_plan* p, int option, int64_t value) {
+  g_err.clear();
+  if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind == 1) return fail(MAD_EINVAL, "not a MAD plan");
+  switch (option) {
+    case MAD_OPT_ACCUM:
+      if (value != MAD_ACCUM_PAIRS && value != MAD_ACCUM_HASH)
+        return fail(MAD_EINVAL, "MAD_OPT_ACCUM takes MAD_ACCUM_PAIRS or "
+                    "MAD_ACCUM_HASH");
+      if ((int)value != (p->opt_accum < 0 ? accum_default() : p->opt_accum))
+        p->ws_s = p->ws_tp = p->ws_t = -1;  // workspace of the other form
+      p->opt_accum = (int)value;
+      return MAD_OK;
+    case MAD_OPT_SAMPLER_ORDER: {
+      if (p->kind != 0)
+        return fail(MAD_EUNSUPPORTED, "sampler ordering is a dense-plan option");
+      mad::SampleOptions o = p->sopt;
+      o.order = (int)value;
+      if (value < 0 || value > 1 || !mad::sample_options_valid(o))
+        return fail(MAD_EINVAL, "MAD_OPT_SAMPLER_ORDER takes 0 or 1");
+      p->sopt = o;
+      p->ws_s = p->ws_tp = p->ws_t = -1;
+      return MAD_OK;
+    }
+    case MAD_OPT_ORDER_CHUNK: {
+      if (p->kind != 0)
+        return fail(MAD_EUNSUPPORTED, "sampler ordering is a dense-plan option");
+      mad::SampleOptions o = p->sopt;
+      o.chunk = value;
+      if (!mad::sample_options_valid(o))
+        return fail(MAD_EINVAL, "MAD_OPT_ORDER_CHUNK takes a power of two in "
+                    "[2^12, 2^28]");
+      p->sopt = o;
+      p->ws_s = p->ws_tp = p->ws_t = -1;
+      return MAD_OK;
+    }
+    default:
+      return fail(MAD_EINVAL, "unknown option %d", option);
+  }
+}
+
+int mad_plan_get_option(mad_plan* p, int option, int64_t* value) {
+  if (!p || !value) return fail(MAD_EINVAL, "plan and value are required");
+  if (p->kind == 1) return fail(MAD_EINVAL, "not a MAD plan");
+  switch (option) {
+    case MAD_OPT_ACCUM:
+      *value = accum_pairs(p) ? MAD_ACCUM_PAIRS : MAD_ACCUM_HASH;
+      return MAD_OK;
+    case MAD_OPT_SAMPLER_ORDER:
+      *value = p->kind == 0 ? p->sopt.order : 0;
+      return MAD_OK;
+    case MAD_OPT_ORDER_CHUNK:
+      *value = p->kind == 0 ? p->sopt.chunk : 0;
+      return MAD_OK;
+    default:
+      return fail(MAD_EINVAL, "unknown option %d", option);
+  }
 }
 
 int mad_topk(const float* A, int64_t m, const float* B, int64_t n, int64_t d,

@@ -109,9 +109,19 @@ struct SampleCounters {
   unsigned long long pad[5];
 };
 
-// order_ws (order_bytes >= sample_order_bytes(count, d)) enables the
-// k-ordered sampling launch; null samples in index order
-size_t sample_order_bytes(int64_t count, int64_t d);
+// Launch choices of the dense sampler (they never change a result):
+// order 0 draws samples in index order, 1 in k order (samples counting-
+// sorted by their stage-0 draw, in chunks of `chunk` samples, a power of
+// two in [2^12, 2^28]).
+struct SampleOptions {
+  int order = 1;
+  int64_t chunk = int64_t(1) << 28;
+};
+SampleOptions sample_options_default();
+bool sample_options_valid(const SampleOptions& o);
+// order_ws (order_bytes >= sample_order_bytes(count, d, o)) enables the
+// ordered sampling launch; otherwise samples run in index order
+size_t sample_order_bytes(int64_t count, int64_t d, const SampleOptions& o);
 // main_start (optional) is recorded between the k-ordering passes and the
 // sampling kernel
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,
@@ -119,7 +129,8 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                int64_t count, int64_t s_for_F,
                                HashTable h, SampleCounters* ctr,
                                void* order_ws, size_t order_bytes,
-                               hipEvent_t main_start, hipStream_t st);
+                               const SampleOptions& o, hipEvent_t main_start,
+                               hipStream_t st);
 hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      uint64_t seed, uint64_t qid, int64_t l0,
                                      int64_t count, int F, int32_t* k,

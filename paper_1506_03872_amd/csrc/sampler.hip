@@ -22,7 +22,8 @@ namespace mad {
 
 constexpr int kT0Lds = 4096;  // stage-0 table kept in LDS up to this size
 constexpr int64_t kOrderMaxD = 1024;          // k ordering for d up to this
-constexpr int64_t kOrderChunk = int64_t(1) << 28;  // samples per ordering
+constexpr int64_t kOrderChunkMin = int64_t(1) << 12;
+constexpr int64_t kOrderChunkMax = int64_t(1) << 28;  // samples per ordering
 
 struct DenseSampleArgs {
   const uint64_t* T0;
@@ -469,9 +470,9 @@ __global__ __launch_bounds__(256) void k_order_starts(const uint32_t* tot,
   }
 }
 
-size_t sample_order_bytes(int64_t count, int64_t d) {
-  if (d > kOrderMaxD) return 0;
-  const int64_t c = count < kOrderChunk ? count : kOrderChunk;
+size_t sample_order_bytes(int64_t count, int64_t d, const SampleOptions& o) {
+  if (d > kOrderMaxD || o.order == 0) return 0;
+  const int64_t c = count < o.chunk ? count : o.chunk;
   const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
   return (size_t)c * 6 + (size_t)nblk * d * 4 + (size_t)d * 8 + 2048;
 }
@@ -479,14 +480,23 @@ size_t sample_order_bytes(int64_t count, int64_t d) {
 // The k order is on by default for d <= kOrderMaxD: on dense 1e5 x 1e5 x
 // 100 with s = 1e7 it takes the sampling kernel from 0.75 to 0.52 ms (the
 // rows T1[k], T2[k] being drawn from stay in the XCD's L2) for about 0.1
-// ms of ordering passes.  MAD_SAMPLER_ORDER=0 turns it off and
-// MAD_SAMPLER_G8 sets the workgroups per XCD (both result-invariant).
-static int order_enabled() {
-  static int v = [] {
+// ms of ordering passes.  The process default comes from MAD_SAMPLER_ORDER
+// (0 turns it off); a plan can change it (mad_plan_set_option).
+// MAD_SAMPLER_G8 sets the workgroups per XCD.  None changes a result.
+SampleOptions sample_options_default() {
+  static const SampleOptions v = [] {
+    SampleOptions o;
     const char* e = getenv("MAD_SAMPLER_ORDER");
-    return e ? atoi(e) : 1;
+    o.order = e ? atoi(e) : 1;
+    if (o.order != 0 && o.order != 1) o.order = 1;
+    return o;
   }();
   return v;
+}
+
+bool sample_options_valid(const SampleOptions& o) {
+  return (o.order == 0 || o.order == 1) && o.chunk >= kOrderChunkMin &&
+         o.chunk <= kOrderChunkMax && (o.chunk & (o.chunk - 1)) == 0;
 }
 
 static int order_g8() {
@@ -502,13 +512,14 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F, HashTable h,
                                SampleCounters* ctr, void* order_ws,
-                               size_t order_bytes, hipEvent_t main_start,
-                               hipStream_t st) {
+                               size_t order_bytes, const SampleOptions& o,
+                               hipEvent_t main_start, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const size_t lds = t0_lds_bytes(t);
   const uint64_t hm = (uint64_t)h.cap - 1;
-  const bool ordered = order_enabled() && t.d <= kOrderMaxD && order_ws &&
-                       order_bytes >= sample_order_bytes(count, t.d) &&
+  const int64_t chunk = o.chunk;
+  const bool ordered = o.order == 1 && t.d <= kOrderMaxD && order_ws &&
+                       order_bytes >= sample_order_bytes(count, t.d, o) &&
                        (int64_t(1) << t.T0.L) <= kT0Lds;
   if (!ordered) {
     if (main_start) (void)hipEventRecord(main_start, st);
@@ -531,11 +542,11 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     }
     return hipGetLastError();
   }
-  // ordered: chunks of at most kOrderChunk samples
+  // ordered: chunks of at most `chunk` samples
   const int64_t d = t.d;
   const size_t lds_ord = ((size_t)8 << t.T0.L) + 4 * (size_t)d;
-  for (int64_t c0 = 0; c0 < count; c0 += kOrderChunk) {
-    const int64_t c = count - c0 < kOrderChunk ? count - c0 : kOrderChunk;
+  for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+    const int64_t c = count - c0 < chunk ? count - c0 : chunk;
     const DenseSampleArgs a = dense_args(t, B, seed, qid, l0 + c0, c);
     const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
     char* p = (char*)order_ws;

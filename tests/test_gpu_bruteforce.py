@@ -81,6 +81,12 @@ def test_low_precision_screen_matches_fp32(mad_gpu, prec):
     print("stats", prec, st, flush=True)
     assert np.array_equal(keys_of(rlo, 12000), keys_of(r32, 12000))
     assert np.array_equal(rlo["c"].cpu().numpy(), r32["c"].cpu().numpy())
+    # and against the oracle's exact FP64 answer
+    check_against_exact(A, B, rlo, 200)
+    n = 12000
+    got = keys_of(rlo, n)
+    c64 = (A[got // n].astype(np.float64) * B[got % n].astype(np.float64)).sum(1)
+    assert np.all(np.abs(rlo["c"].cpu().numpy() - c64) <= TOL * np.abs(c64))
 
 
 def test_planted_pairs_found(mad_gpu):
@@ -135,3 +141,4 @@ def test_mixed_vector_scales(mad_gpu, prec):
     assert np.array_equal(keys_of(rlo, n), keys_of(r32, n))
     assert np.array_equal(rlo["c"].cpu().numpy(), r32["c"].cpu().numpy())
     check_against_exact(A, B, r32, t)
+    check_against_exact(A, B, rlo, t)

@@ -236,6 +236,12 @@ def test_low_precision_screen_keeps_results(mad_gpu, prec):
                 for key in ("i", "c", "x"):
                     assert np.array_equal(got[q][key].cpu().numpy(),
                                           ref[q][key].cpu().numpy()), (q, key)
+            if rep == 0 and flags == 0:  # against the oracle, query by query
+                for q in range(len(S)):
+                    if got[q] is None or q == 5 or S[q] == 0:
+                        continue
+                    o, _, _, _ = _oracle_query(A, Q[q], q, S[q], TP[q], T)
+                    _check_query(A, q, Q[q], got[q], o, T)
         st = gp.verify_stats()
         say("flags", flags, "prec", prec, st0, st)
         assert st["n_cand"] == st0["n_cand"]

@@ -129,6 +129,8 @@ def _check_topk(A, B, gres, ores, t):
     # every returned c within tolerance of its FP64 value
     c64 = (A[gkey // n].astype(np.float64) * B[gkey % n].astype(np.float64)).sum(1)
     assert np.all(np.abs(gc - c64) <= TOL * _c_scale(A, B, gkey) + 1e-30)
+    # the floating-point bar of the scores: 1e-5 relative to c itself
+    assert np.all(np.abs(gc - c64) <= TOL * np.abs(c64))
     if np.array_equal(gkey, ores["key"]):
         return
     # otherwise: same set up to pairs within tolerance of the boundary

@@ -2,13 +2,17 @@
 candidate filtering with an a-priori error bound, then fp32 verification of
 the survivors.  The filter is certified, so the final top t must equal the
 fp32-verification result bit for bit (indices, c and x), while fewer
-candidates reach the fp32 pass."""
+candidates reach the fp32 pass; and every result is also checked against
+the oracle's (same pairs, c within 1e-5 relative of its FP64 value)."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import workloads
+
+TOL = 1e-5
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +62,7 @@ def test_lowp_filter_keeps_fp32_result(mad_gpu, name):
     t, s, tp = 50, 2_000_000, 4000
     ref, vs32, st32 = _run(mad_gpu, A, B, 0, t, s, tp)
     assert vs32["n_reranked"] == vs32["n_cand"] == st32["n_cand"]
+    o = None
     for prec in (mad_gpu.MAD_BF16, mad_gpu.MAD_FP8_E4M3):
         got, vs, st = _run(mad_gpu, A, B, prec, t, s, tp)
         say(name, "prec", prec, "cand", vs["n_cand"], "fp32 re-ranked",
@@ -69,6 +74,34 @@ def test_lowp_filter_keeps_fp32_result(mad_gpu, name):
             assert np.array_equal(got[k], ref[k]), (prec, k)
         if prec == mad_gpu.MAD_BF16 and name != "integers":
             assert vs["n_reranked"] < vs["n_cand"] // 2
+        if o is None:
+            o = oracle.Plan.dense(A, B).topk(seed=5, s=s, t_prime=tp, t=t)
+        _check_oracle(A, B, got, o)
+
+
+def _check_oracle(A, B, got, o):
+    """The low-precision run against the oracle's run (same seed, s, t'
+    and t): the same candidates feed the same exact top t, whose c agree
+    within 1e-5 of the FP64 value."""
+    n = B.shape[0]
+    gkey = got["i"].astype(np.int64) * n + got["j"]
+    assert len(gkey) == len(o["key"])
+    c64 = (A[gkey // n].astype(np.float64) *
+           B[gkey % n].astype(np.float64)).sum(1)
+    assert np.all(np.abs(got["c"].astype(np.float64) - c64)
+                  <= TOL * np.abs(c64))
+    if np.array_equal(gkey, o["key"]):
+        assert np.array_equal(got["x"].astype(np.float64),
+                              np.ldexp(o["x"].astype(np.float64), -o["F"])
+                              .astype(np.float32).astype(np.float64))
+        return
+    # otherwise only swaps at the t-th |c| within the fp32 error scale
+    tau = np.abs(o["c"]).min()
+    scale = (np.abs(A[gkey // n].astype(np.float64)) *
+             np.abs(B[gkey % n].astype(np.float64))).sum(1)
+    for kk, c, sc in zip(gkey.tolist(), c64.tolist(), scale.tolist()):
+        if kk not in set(o["key"].tolist()):
+            assert abs(abs(c) - tau) <= 2 * TOL * sc, kk
 
 
 def test_precision_setting_validation(mad_gpu):

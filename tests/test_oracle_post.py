@@ -114,3 +114,25 @@ def test_threshold_recall():
     k, c = oracle.exact_topk(A, B, 10)
     assert oracle.threshold_recall(k, A, B, c, 10) == 1.0
     assert oracle.threshold_recall(k[:5], A, B, c, 10) == 0.5
+
+
+def test_scores_merged_from_sample_ranges_and_post():
+    # X is an exact int64 sum, so sampling [0, s) in ranges and summing each
+    # key's increments gives the same X, and Alg. 2 on it the same output
+    A, B = workloads.dense_gaussian(60, 45, 7, seed=8)
+    p = oracle.Plan.dense(A, B)
+    s, tp, t = 50_000, 300, 12
+    F = p.fix_exponent(s)
+    keys, xfix, _ = p.scores(seed=6, s=s, F=F)
+    parts = []
+    for l0, cnt in ((0, 7001), (7001, 20000), (27001, 22999)):
+        r = p.samples(6, l0, cnt, F)
+        closed = r["inc"] != 0
+        parts.append((r["i"][closed].astype(np.int64) * 45 + r["j"][closed],
+                      r["inc"][closed]))
+    mk, mx = oracle.merge_scores(parts)
+    assert np.array_equal(mk, keys) and np.array_equal(mx, xfix)
+    full = p.topk(seed=6, s=s, t_prime=tp, t=t)
+    post = p.post(mk[::-1].copy(), mx[::-1].copy(), tp, t)  # any order
+    for k in ("tp_key", "tp_x", "tp_c", "key", "x", "c", "n_pos"):
+        assert np.array_equal(post[k], full[k]), k
