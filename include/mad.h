@@ -180,7 +180,11 @@ int mad_plan_verify_stats(mad_plan* plan, int64_t* n_cand,
  *                          Dense and sparse plans.
  *   MAD_OPT_SAMPLER_ORDER  dense plans, d <= 1024: 1 (default) draws the
  *                          samples grouped by their stage-0 coordinate k
- *                          (the reordering of Sec. 5.2), 0 in index order.
+ *                          (the first reordering of Sec. 5.2); 2 also
+ *                          reorders them by i for the k' draw and by j for
+ *                          the fourth edge (the whole scheme of Sec. 5.2;
+ *                          pair form of X only, else it runs as 1); 0 draws
+ *                          them in index order.
  *   MAD_OPT_ORDER_CHUNK    dense plans: samples per ordering pass, a power
  *                          of two in [2^12, 2^28] (default 2^28); longer
  *                          runs are ordered in consecutive chunks.

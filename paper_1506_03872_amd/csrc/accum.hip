@@ -393,8 +393,9 @@ __global__ void k_acc_starts1(const uint64_t* offs, int64_t tiles, int B1,
 }
 
 // second level: one workgroup per first-level bin partitions its pairs by
-// the next B2 hash bits (LDS counts, scan, place) and writes the sub-bin
-// starts; starts2[(b << B2) + r] for every sub-bin, starts2[end] = n
+// the B2 hash bits below the B1 bits already used (LDS counts, scan, place)
+// and writes the sub-bin starts; starts2[(b << B2) + r] for every sub-bin,
+// starts2[bins << B2] = the end of the last bin
 constexpr int kAcc2Threads = 1024;
 constexpr int kChunk2 = 4 * kAcc2Threads;
 
@@ -450,8 +451,8 @@ __global__ __launch_bounds__(kAcc2Threads) void k_acc_split2(
     }
     ex += v[u];
   }
-  if (b == (int64_t(1) << B1) - 1 && t == 0)
-    starts2[(int64_t)1 << (B1 + B2)] = starts1[b + 1];
+  if (b == (int64_t)gridDim.x - 1 && t == 0)
+    starts2[(b + 1) << B2] = starts1[b + 1];
   __syncthreads();
   // place, a chunk of kChunk2 pairs at a time: the chunk is sorted by
   // sub-bin in LDS, then each sub-bin's share is stored as one run at its
@@ -635,6 +636,68 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
   // entries written = closed pairs = the end of the last bin
   k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, nb1 << B2, o_count,
                                 starts + (nb1 << B2), o_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate_grouped(uint64_t* keys, float* vals, int64_t n,
+                                     const uint64_t* gstarts, int64_t G,
+                                     const float* bmax, int64_t s_for_F,
+                                     void* work, size_t work_bytes,
+                                     uint64_t* okey, int64_t* oval,
+                                     int64_t* o_count, int64_t* o_len,
+                                     hipStream_t st) {
+  if (n <= 0 || G < 1 || !gstarts)
+    return launch_accumulate(keys, vals, n, bmax, s_for_F, work, work_bytes,
+                             okey, oval, o_count, o_len, st);
+  if (work_bytes < accum_bytes(n)) return hipErrorInvalidValue;
+  // the groups stand for the first gb bits of the hashed form: split each
+  // by the hash bits that bring its bins to about acc_target() pairs
+  int gb = 0;
+  while ((int64_t(1) << gb) < G) ++gb;
+  const int T = acc_total_bits(n);
+  // more groups than bins of the hashed form (few pairs): its layout would
+  // not hold the group starts, and the groups would be tiny anyway
+  if (gb > T)
+    return launch_accumulate(keys, vals, n, bmax, s_for_F, work, work_bytes,
+                             okey, oval, o_count, o_len, st);
+  const int B2 = T - gb;
+  char* p = (char*)work;
+  uint64_t* placed = (uint64_t*)p;
+  p += (size_t)n * 8;
+  float* placed_v = (float*)p;
+  p += ((size_t)n * 4 + 15) / 16 * 16;
+  const int B1h = acc_b1(n);
+  const int64_t tiles = (n + kAccTile - 1) / kAccTile;
+  p += ((size_t)(tiles << B1h) + 1) * 8;  // the count array of the other form
+  uint64_t* starts = (uint64_t*)p;
+  p += (((size_t)1 << T) + 1) * 8;
+  p += (((size_t)1 << T) + 1) * 8;  // first-level starts of the other form
+  uint64_t* bin_distinct = (uint64_t*)p;
+  const int64_t bins = G << B2;
+  if (B2 == 0) {
+    launch_reduce(n / G, G, keys, vals, gstarts, 0, bmax, s_for_F, okey, oval,
+                  bin_distinct, st);
+    k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, G, o_count, gstarts + G,
+                                  o_len);
+    return hipGetLastError();
+  }
+  if (B2 <= kAccSplitBits) {
+    k_acc_split2<<<(unsigned)G, kAcc2Threads, 0, st>>>(
+        keys, vals, gstarts, 0, B2, placed, placed_v, starts);
+    launch_reduce(n / bins, bins, placed, placed_v, starts, B2, bmax, s_for_F,
+                  okey, oval, bin_distinct, st);
+  } else {
+    const int Ba = (B2 + 1) / 2, Bb = B2 - Ba;
+    uint64_t* starts_mid = bin_distinct;
+    k_acc_split2<<<(unsigned)G, kAcc2Threads, 0, st>>>(
+        keys, vals, gstarts, 0, Ba, placed, placed_v, starts_mid);
+    k_acc_split2<<<(unsigned)(G << Ba), kAcc2Threads, 0, st>>>(
+        placed, placed_v, starts_mid, Ba, Bb, keys, vals, starts);
+    launch_reduce(n / bins, bins, keys, vals, starts, B2, bmax, s_for_F, okey,
+                  oval, bin_distinct, st);
+  }
+  k_acc_sum<<<1, 1024, 0, st>>>(bin_distinct, bins, o_count, starts + bins,
+                                o_len);
   return hipGetLastError();
 }
 

@@ -346,7 +346,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
       (e = mad::dev_alloc(p->misc, mad::kSelStateBytes + 4 * mad::kSelBins +
                                        256 + 256)) != hipSuccess ||
       (p->kind == 0 &&
-       (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(s2, p->d,
+       (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(p->dt, s2,
                                                            p->sopt))) !=
            hipSuccess) ||
       (use_pairs &&
@@ -426,23 +426,31 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
     HIP_TRY(mad::launch_fill_multi(f, st), "clearing counters");
   }
   record(p, 3, st);
+  mad::PairGroups groups;
   if (p->kind == 2)
     HIP_TRY(mad::launch_sample_csr(p->ct, seed, 0, 0, s, s, h, p->ctr, st),
             "sampling");
   else
     HIP_TRY(mad::launch_sample_dense(p->dt, p->B, seed, 0, 0, s, s, h,
                                      p->ctr, p->ord.p, p->ord.bytes, p->sopt,
-                                     p->ev[7], st),
+                                     &groups, p->ev[7], st),
             "sampling");
   record(p, 4, st);
   if (p->pairs) {
     const size_t pb = pair_bytes(s);
-    HIP_TRY(mad::launch_accumulate(h.pkeys, h.pvals, s, plan_bmax(p), s,
-                                   (char*)p->acc.p + pb, p->acc.bytes - pb,
-                                   h.keys, h.vals,
-                                   (int64_t*)&p->ctr->distinct,
-                                   (int64_t*)&p->ctr->entries, st),
-            "accumulating X");
+    if (groups.starts)
+      HIP_TRY(mad::launch_accumulate_grouped(
+                  h.pkeys, h.pvals, s, groups.starts, groups.G, plan_bmax(p),
+                  s, (char*)p->acc.p + pb, p->acc.bytes - pb, h.keys, h.vals,
+                  (int64_t*)&p->ctr->distinct, (int64_t*)&p->ctr->entries, st),
+              "accumulating X");
+    else
+      HIP_TRY(mad::launch_accumulate(h.pkeys, h.pvals, s, plan_bmax(p), s,
+                                     (char*)p->acc.p + pb, p->acc.bytes - pb,
+                                     h.keys, h.vals,
+                                     (int64_t*)&p->ctr->distinct,
+                                     (int64_t*)&p->ctr->entries, st),
+              "accumulating X");
     h.live = (const int64_t*)&p->ctr->entries;
   }
   h.pkeys = nullptr;
@@ -481,8 +489,8 @@ int mad_plan_set_option(mad_plan* p, int option, int64_t value) {
         return fail(MAD_EUNSUPPORTED, "sampler ordering is a dense-plan option");
       mad::SampleOptions o = p->sopt;
       o.order = (int)value;
-      if (value < 0 || value > 1 || !mad::sample_options_valid(o))
-        return fail(MAD_EINVAL, "MAD_OPT_SAMPLER_ORDER takes 0 or 1");
+      if (value < 0 || value > 2 || !mad::sample_options_valid(o))
+        return fail(MAD_EINVAL, "MAD_OPT_SAMPLER_ORDER takes 0, 1 or 2");
       p->sopt = o;
       p->ws_s = p->ws_tp = p->ws_t = -1;
       return MAD_OK;

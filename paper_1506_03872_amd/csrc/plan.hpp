@@ -101,6 +101,16 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
                              const float* bmax, int64_t s_for_F, void* work,
                              size_t work_bytes, uint64_t* okey, int64_t* oval,
                              int64_t* o_count, int64_t* o_len, hipStream_t st);
+// the same when the pairs already come in G groups that no key spans
+// (gstarts: device, G + 1 offsets): the groups are the first partition
+// level, the hash partition of the other form is skipped
+hipError_t launch_accumulate_grouped(uint64_t* keys, float* vals, int64_t n,
+                                     const uint64_t* gstarts, int64_t G,
+                                     const float* bmax, int64_t s_for_F,
+                                     void* work, size_t work_bytes,
+                                     uint64_t* okey, int64_t* oval,
+                                     int64_t* o_count, int64_t* o_len,
+                                     hipStream_t st);
 
 struct SampleCounters {
   unsigned long long closed;    // closed three-paths (diamonds)
@@ -112,25 +122,34 @@ struct SampleCounters {
 // Launch choices of the dense sampler (they never change a result):
 // order 0 draws samples in index order, 1 in k order (samples counting-
 // sorted by their stage-0 draw, in chunks of `chunk` samples, a power of
-// two in [2^12, 2^28]).
+// two in [2^12, 2^28]), 2 in k order followed by the passes grouped by i
+// and by j (the locality scheme of Sec. 5.2; pair form of X only).
 struct SampleOptions {
   int order = 1;
   int64_t chunk = int64_t(1) << 28;
 };
 SampleOptions sample_options_default();
 bool sample_options_valid(const SampleOptions& o);
-// order_ws (order_bytes >= sample_order_bytes(count, d, o)) enables the
+// order_ws (order_bytes >= sample_order_bytes(t, count, o)) enables the
 // ordered sampling launch; otherwise samples run in index order
-size_t sample_order_bytes(int64_t count, int64_t d, const SampleOptions& o);
+size_t sample_order_bytes(const DenseTables& t, int64_t count,
+                          const SampleOptions& o);
+// Pairs left grouped by blocks of j (one chunk, not Gram): group g holds
+// pairs [starts[g], starts[g+1]) of the pair arrays, starts (device) has
+// G + 1 entries.  starts == nullptr when the pairs are not grouped.
+struct PairGroups {
+  const uint64_t* starts = nullptr;
+  int64_t G = 0;
+};
 // main_start (optional) is recorded between the k-ordering passes and the
-// sampling kernel
+// sampling kernel(s); groups (optional) receives the grouping of the pairs
 hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                uint64_t seed, uint64_t qid, int64_t l0,
                                int64_t count, int64_t s_for_F,
                                HashTable h, SampleCounters* ctr,
                                void* order_ws, size_t order_bytes,
-                               const SampleOptions& o, hipEvent_t main_start,
-                               hipStream_t st);
+                               const SampleOptions& o, PairGroups* groups,
+                               hipEvent_t main_start, hipStream_t st);
 hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      uint64_t seed, uint64_t qid, int64_t l0,
                                      int64_t count, int F, int32_t* k,

@@ -470,33 +470,426 @@ __global__ __launch_bounds__(256) void k_order_starts(const uint32_t* tot,
   }
 }
 
-size_t sample_order_bytes(int64_t count, int64_t d, const SampleOptions& o) {
-  if (d > kOrderMaxD || o.order == 0) return 0;
-  const int64_t c = count < o.chunk ? count : o.chunk;
-  const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
-  return (size_t)c * 6 + (size_t)nblk * d * 4 + (size_t)d * 8 + 2048;
+// ---------------------------------------------------------------------------
+// The locality pipeline (Sec. 5.2): after the k order, each sample is drawn
+// in three passes, each over records grouped for the table it reads:
+//   pass A (k order)   Philox, k (T0), i (T1[k]), j (T2[k]); record
+//                      R1 = {U3, i, j | sign} grouped by the block of i;
+//   pass B (i groups)  k' (T3[i]); record R2 = {i, j | sign, k'} grouped
+//                      by the block of j;
+//   pass C (j groups)  the fourth edge b_k'j (row j of B) and the sample's
+//                      (key, signed fourth edge) pair.
+// A pass writes each tile of records sorted by group, with the tile's group
+// counts; a column scan of the counts gives every (group, tile) run its
+// place in the grouped stream, and a scatter moves the runs there.  The
+// next pass reads that stream in order, the tiles of each XCD contiguous,
+// so the table rows of the groups it works on stay in that XCD's L2.  The
+// pairs come out grouped by j, which the score accumulation takes as its
+// first partition level.  Results do not depend on any of this: every
+// sample is a function of (seed, l) and X is an exact int64 sum.
+// ---------------------------------------------------------------------------
+constexpr int kPipeU = 8;
+constexpr int kPipeTile = 256 * kPipeU;  // records per tile
+constexpr int kPipeMaxG = 1024;          // groups per pass
+// table bytes per group: T3 rows of an i group, B rows of a j group (the j
+// groups are also the first level of the score accumulation, whose
+// per-group split wants a few hundred of them)
+constexpr int64_t kPipeSliceT3 = 1 << 20;
+constexpr int64_t kPipeSliceB = 1 << 18;
+
+struct PipeR1 {
+  uint64_t u3;  // Philox word 3 (slot and coin of the k' draw)
+  uint32_t i;
+  uint32_t js;  // j | sign(a_ki b_kj) << 31
+};
+
+struct PipeR2 {
+  uint32_t i;
+  uint32_t js;  // j | sign(a_ki b_kj a_k'i) << 31
+  uint32_t kp;
+};
+
+// group shifts: rows per group a power of two with about kPipeSliceBytes
+// of table rows, and at most kPipeMaxG groups
+static int pipe_shift(int64_t rows, int64_t row_bytes, int64_t slice) {
+  int sh = 0;
+  while (sh < 31 && ((int64_t(2) << sh) * row_bytes <= slice)) ++sh;
+  while (((rows + (int64_t(1) << sh) - 1) >> sh) > kPipeMaxG) ++sh;
+  return sh;
 }
 
-// The k order is on by default for d <= kOrderMaxD: on dense 1e5 x 1e5 x
-// 100 with s = 1e7 it takes the sampling kernel from 0.75 to 0.52 ms (the
-// rows T1[k], T2[k] being drawn from stay in the XCD's L2) for about 0.1
-// ms of ordering passes.  The process default comes from MAD_SAMPLER_ORDER
-// (0 turns it off); a plan can change it (mad_plan_set_option).
-// MAD_SAMPLER_G8 sets the workgroups per XCD.  None changes a result.
+struct PipeShape {
+  int gsh_i = 0, gsh_j = 0;
+  int64_t Gi = 1, Gj = 1;
+};
+
+static PipeShape pipe_shape(const DenseTables& t) {
+  PipeShape p;
+  p.gsh_i = pipe_shift(t.m, (int64_t)8 << t.T3.L, kPipeSliceT3);
+  p.gsh_j = pipe_shift(t.n, 4 * t.d, kPipeSliceB);
+  p.Gi = (t.m + (int64_t(1) << p.gsh_i) - 1) >> p.gsh_i;
+  p.Gj = (t.n + (int64_t(1) << p.gsh_j) - 1) >> p.gsh_j;
+  return p;
+}
+
+// exclusive prefix of c[0 .. G) in place (G <= kPipeMaxG, 256 threads, 4
+// per thread); returns nothing, c[g] becomes the start of group g
+__device__ __forceinline__ void pipe_block_scan(uint32_t* c, int G,
+                                                uint32_t* wt) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  uint32_t v[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g = t * 4 + q;
+    v[q] = g < G ? c[g] : 0u;
+    sum += v[q];
+  }
+  const uint32_t inc = wave_incl_scan(sum);
+  if (lane == 63) wt[wv] = inc;
+  __syncthreads();
+  uint32_t ex = inc - sum;
+  for (int w = 0; w < wv; ++w) ex += wt[w];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g = t * 4 + q;
+    if (g < G) c[g] = ex;
+    ex += v[q];
+  }
+  __syncthreads();
+}
+
+// tile index of a workgroup's q-th step: each XCD (blockIdx % 8) walks a
+// contiguous eighth of the tiles
+struct XcdWalk {
+  int64_t t, t_hi, step;
+  __device__ XcdWalk(int64_t ntiles) {
+    const int64_t xcd = blockIdx.x & 7;
+    t = xcd * ntiles / 8 + (blockIdx.x >> 3);
+    t_hi = (xcd + 1) * ntiles / 8;
+    step = gridDim.x >> 3;
+  }
+};
+
+// pass A: draws of k, i, j in k order; R1 tiles sorted by the group of i,
+// counts cnt[tile * G + g]
+__global__ __launch_bounds__(256) void k_pipe_ij(DenseSampleArgs a,
+                                                 const double* wtot,
+                                                 const uint32_t* ell,
+                                                 int64_t ntiles, int gsh,
+                                                 int G, PipeR1* out,
+                                                 uint32_t* cnt) {
+  __shared__ uint64_t t0s[kOrderMaxD];
+  __shared__ PipeR1 srec[kPipeTile];
+  __shared__ uint32_t gc[kPipeMaxG];
+  __shared__ uint32_t wt[4];
+  // ||W||_1 = 0: nothing can be drawn; records carry i = j = 0 (in range)
+  // and the last pass writes no pair
+  const bool live_w = wtot[0] > 0.0;
+  const int N0 = 1 << a.L0;
+  for (int e = threadIdx.x; e < N0; e += 256) t0s[e] = a.T0[e];
+  for (XcdWalk w(ntiles); w.t < w.t_hi; w.t += w.step) {
+    for (int g = threadIdx.x; g < G; g += 256) gc[g] = 0;
+    __syncthreads();
+    const int64_t base = w.t * kPipeTile;
+    PipeR1 rec[kPipeU];
+    uint32_t grp[kPipeU], rank[kPipeU];
+    uint64_t U1[kPipeU], U2[kPipeU];
+    uint32_t kk[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      const int64_t ec = e < a.count ? e : 0;
+      const uint64_t l = (uint64_t)(a.l0 + (int64_t)ell[ec]);
+      const Philox4 r = philox4x64_10(l, a.qid, 0ull, 0ull, a.seed, 0ull);
+      const uint32_t s0 = slot_of(r.w0, a.L0);
+      kk[u] = draw_entry(t0s[s0], s0, r.w0).pos;
+      U1[u] = r.w1;
+      U2[u] = r.w2;
+      rec[u].u3 = r.w3;
+    }
+    uint64_t e1[kPipeU], e2[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      e1[u] = a.T1[((uint64_t)kk[u] << a.L1) + slot_of(U1[u], a.L1)];
+      e2[u] = a.T2[((uint64_t)kk[u] << a.L2) + slot_of(U2[u], a.L2)];
+    }
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      Drawn di = draw_entry(e1[u], slot_of(U1[u], a.L1), U1[u]);
+      Drawn dj = draw_entry(e2[u], slot_of(U2[u], a.L2), U2[u]);
+      if (!live_w) di.pos = dj.pos = 0;
+      rec[u].i = di.pos;
+      rec[u].js = dj.pos | ((di.sgn ^ dj.sgn) << 31);
+      grp[u] = di.pos >> gsh;
+      rank[u] = e < a.count ? atomicAdd(&gc[grp[u]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < G; g += 256)
+      cnt[w.t * G + g] = gc[g];
+    __syncthreads();
+    pipe_block_scan(gc, G, wt);
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      if (e < a.count) srec[gc[grp[u]] + rank[u]] = rec[u];
+    }
+    __syncthreads();
+    const int64_t n = a.count - base < kPipeTile ? a.count - base : kPipeTile;
+    for (int p = threadIdx.x; p < n; p += 256) out[base + p] = srec[p];
+    __syncthreads();
+  }
+}
+
+// pass B: k' from T3[i] over the i-grouped stream; R2 tiles sorted by the
+// group of j
+__global__ __launch_bounds__(256) void k_pipe_kp(const uint64_t* T3, int L3,
+                                                 const double* wtot,
+                                                 const PipeR1* in,
+                                                 int64_t count, int64_t ntiles,
+                                                 int gsh, int G, PipeR2* out,
+                                                 uint32_t* cnt) {
+  __shared__ PipeR2 srec[kPipeTile];
+  __shared__ uint32_t gc[kPipeMaxG];
+  __shared__ uint32_t wt[4];
+  const bool live_w = wtot[0] > 0.0;
+  for (XcdWalk w(ntiles); w.t < w.t_hi; w.t += w.step) {
+    for (int g = threadIdx.x; g < G; g += 256) gc[g] = 0;
+    __syncthreads();
+    const int64_t base = w.t * kPipeTile;
+    PipeR1 r1[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      r1[u] = in[e < count ? e : 0];
+    }
+    uint64_t e3[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u)
+      e3[u] = T3[((uint64_t)r1[u].i << L3) + slot_of(r1[u].u3, L3)];
+    PipeR2 rec[kPipeU];
+    uint32_t grp[kPipeU], rank[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      const Drawn dk = draw_entry(e3[u], slot_of(r1[u].u3, L3), r1[u].u3);
+      rec[u].i = r1[u].i;
+      rec[u].js = r1[u].js ^ (dk.sgn << 31);
+      rec[u].kp = live_w ? dk.pos : 0u;
+      grp[u] = (r1[u].js & kLow31) >> gsh;
+      rank[u] = e < count ? atomicAdd(&gc[grp[u]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < G; g += 256)
+      cnt[w.t * G + g] = gc[g];
+    __syncthreads();
+    pipe_block_scan(gc, G, wt);
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      if (e < count) srec[gc[grp[u]] + rank[u]] = rec[u];
+    }
+    __syncthreads();
+    const int64_t n = count - base < kPipeTile ? count - base : kPipeTile;
+    for (int p = threadIdx.x; p < n; p += 256) out[base + p] = srec[p];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ uint32_t pipe_group(const PipeR1& r, int gsh) {
+  return r.i >> gsh;
+}
+__device__ __forceinline__ uint32_t pipe_group(const PipeR2& r, int gsh) {
+  return (r.js & kLow31) >> gsh;
+}
+
+// the runs of each tile (sorted by group) to their places in the grouped
+// stream: run (g, tile) starts at start[g] + pre[tile * G + g], where pre
+// is the column prefix of the tile counts
+template <typename R>
+__global__ __launch_bounds__(256) void k_pipe_scatter(
+    const R* in, int64_t count, int gsh, int G, const uint32_t* pre,
+    const uint32_t* start, R* out) {
+  __shared__ uint16_t sg[kPipeTile];
+  __shared__ uint32_t first[kPipeMaxG];
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * kPipeTile;
+  const int n = count - base < kPipeTile ? (int)(count - base) : kPipeTile;
+  R rec[kPipeU];
+  uint32_t grp[kPipeU];
+#pragma unroll
+  for (int u = 0; u < kPipeU; ++u) {
+    const int p = u * 256 + threadIdx.x;
+    if (p < n) {
+      rec[u] = in[base + p];
+      grp[u] = pipe_group(rec[u], gsh);
+      sg[p] = (uint16_t)grp[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPipeU; ++u) {
+    const int p = u * 256 + threadIdx.x;
+    if (p < n && (p == 0 || sg[p - 1] != grp[u])) first[grp[u]] = (uint32_t)p;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPipeU; ++u) {
+    const int p = u * 256 + threadIdx.x;
+    if (p < n) {
+      const uint32_t g = grp[u];
+      const uint64_t d = (uint64_t)start[g] + pre[tile * G + g] +
+                         (uint32_t)p - first[g];
+      out[d] = rec[u];
+    }
+  }
+}
+
+// pass C: the fourth edge over the j-grouped stream and each sample's pair
+__global__ __launch_bounds__(256) void k_pipe_edge(const PipeR2* in,
+                                                   int64_t count,
+                                                   int64_t ntiles,
+                                                   const float* B, int64_t d,
+                                                   int64_t n, int gram,
+                                                   const double* wtot,
+                                                   uint64_t* pkeys,
+                                                   float* pvals,
+                                                   SampleCounters* ctr) {
+  const bool live_w = wtot[0] > 0.0;
+  unsigned long long nclosed = 0;
+  for (XcdWalk w(ntiles); w.t < w.t_hi; w.t += w.step) {
+    const int64_t base = w.t * kPipeTile;
+    PipeR2 r[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      r[u] = in[e < count ? e : 0];
+    }
+    float v[kPipeU];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u)
+      v[u] = B[(int64_t)(r[u].js & kLow31) * d + r[u].kp];
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int64_t e = base + u * 256 + threadIdx.x;
+      if (e >= count) continue;
+      uint64_t ii = r[u].i, jj = r[u].js & kLow31;
+      const bool closed = live_w && v[u] != 0.0f;
+      bool ins = closed;
+      if (gram) {  // Sec. 3.2.2: X + X^T on i < j, diagonal dropped
+        if (ii == jj) ins = false;
+        if (ii > jj) {
+          const uint64_t tmp = ii;
+          ii = jj;
+          jj = tmp;
+        }
+      }
+      nclosed += closed;
+      __builtin_nontemporal_store(
+          (unsigned long long)(ins ? ii * (uint64_t)n + jj : kEmptyKey),
+          (unsigned long long*)(pkeys + e));
+      __builtin_nontemporal_store((r[u].js >> 31) ? -v[u] : v[u], pvals + e);
+    }
+  }
+  __shared__ unsigned long long part[4];
+  nclosed = wave_sum(nclosed);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nclosed;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long c = part[0] + part[1] + part[2] + part[3];
+    if (c) atomicAdd(&ctr->closed, c);
+  }
+}
+
+// first-level bins of the score accumulation: the j groups' starts as
+// 64-bit offsets, starts[G] = count
+__global__ void k_pipe_starts64(const uint32_t* start, int G, int64_t count,
+                                uint64_t* out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < G) out[g] = start[g];
+  if (g == G) out[g] = (uint64_t)count;
+}
+
+// workspace of the pipeline passes for a chunk of c samples
+struct PipeLayout {
+  PipeR1* ra;      // tile-major records of pass A, then of pass B
+  PipeR1* rb;      // the i-grouped stream, then the j-grouped one
+  uint32_t *ca, *ta, *sa;  // pass A: tile counts, group totals, starts
+  uint32_t *cb, *tb, *sb;  // pass B
+  uint64_t* starts64;      // first-level bins of the accumulation
+  size_t bytes;
+};
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static PipeLayout pipe_layout(char* base, int64_t c, const PipeShape& ps) {
+  PipeLayout L;
+  const int64_t nt = (c + kPipeTile - 1) / kPipeTile;
+  char* p = base;
+  L.ra = (PipeR1*)p; p += align256((size_t)c * sizeof(PipeR1));
+  L.rb = (PipeR1*)p; p += align256((size_t)c * sizeof(PipeR1));
+  L.ca = (uint32_t*)p; p += align256((size_t)nt * ps.Gi * 4);
+  L.ta = (uint32_t*)p; p += align256((size_t)ps.Gi * 4);
+  L.sa = (uint32_t*)p; p += align256((size_t)ps.Gi * 4);
+  L.cb = (uint32_t*)p; p += align256((size_t)nt * ps.Gj * 4);
+  L.tb = (uint32_t*)p; p += align256((size_t)ps.Gj * 4);
+  L.sb = (uint32_t*)p; p += align256((size_t)ps.Gj * 4);
+  L.starts64 = (uint64_t*)p; p += align256((size_t)(ps.Gj + 1) * 8);
+  L.bytes = (size_t)(p - base);
+  return L;
+}
+
+static size_t korder_bytes(int64_t c, int64_t d) {
+  const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
+  return align256((size_t)c * 4) + align256((size_t)c * 2) +
+         (size_t)nblk * d * 4 + (size_t)d * 8 + 2048;
+}
+
+size_t sample_order_bytes(const DenseTables& t, int64_t count,
+                          const SampleOptions& o) {
+  if (t.d > kOrderMaxD || o.order == 0) return 0;
+  const int64_t c = count < o.chunk ? count : o.chunk;
+  size_t b = align256(korder_bytes(c, t.d));
+  if (o.order == 2) b += pipe_layout(nullptr, c, pipe_shape(t)).bytes;
+  return b;
+}
+
+// Samples run in k order by default for d <= kOrderMaxD: one sampling
+// kernel whose T1[k], T2[k] rows stay in the XCD's L2 (on dense 1e5 x 1e5
+// x 100 with s = 1e7 it takes the kernel from 0.75 to 0.50 ms for 0.1 ms of
+// ordering passes).  Order 2, the three passes grouped by k, i and j,
+// moves 216 instead of 348 bytes per sample there but takes longer: HBM
+// serves random 128-byte lines nearly at its streaming rate, so the
+// records, scans and scatters of the grouping cost more than the random
+// lines they save.  Order 0 draws in index order.  The process default
+// comes from MAD_SAMPLER_ORDER; a plan can change it (mad_plan_set_option).
+// MAD_SAMPLER_G8 and MAD_PIPE_G8 set workgroups per XCD.  None changes a
+// result.
 SampleOptions sample_options_default() {
   static const SampleOptions v = [] {
     SampleOptions o;
     const char* e = getenv("MAD_SAMPLER_ORDER");
     o.order = e ? atoi(e) : 1;
-    if (o.order != 0 && o.order != 1) o.order = 1;
+    if (o.order < 0 || o.order > 2) o.order = 1;
     return o;
   }();
   return v;
 }
 
 bool sample_options_valid(const SampleOptions& o) {
-  return (o.order == 0 || o.order == 1) && o.chunk >= kOrderChunkMin &&
+  return o.order >= 0 && o.order <= 2 && o.chunk >= kOrderChunkMin &&
          o.chunk <= kOrderChunkMax && (o.chunk & (o.chunk - 1)) == 0;
+}
+
+// workgroups per XCD of the pipeline passes (MAD_PIPE_G8, 8 .. 1024;
+// result-invariant)
+static int pipe_g8() {
+  static int v = [] {
+    const char* e = getenv("MAD_PIPE_G8");
+    const int x = e ? atoi(e) : 96;
+    return x >= 8 && x <= 1024 ? x : 96;
+  }();
+  return v;
 }
 
 static int order_g8() {
@@ -513,14 +906,18 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
                                int64_t count, int64_t s_for_F, HashTable h,
                                SampleCounters* ctr, void* order_ws,
                                size_t order_bytes, const SampleOptions& o,
-                               hipEvent_t main_start, hipStream_t st) {
+                               PairGroups* groups, hipEvent_t main_start,
+                               hipStream_t st) {
+  if (groups) *groups = PairGroups{};
   if (count <= 0) return hipSuccess;
   const size_t lds = t0_lds_bytes(t);
   const uint64_t hm = (uint64_t)h.cap - 1;
   const int64_t chunk = o.chunk;
-  const bool ordered = o.order == 1 && t.d <= kOrderMaxD && order_ws &&
-                       order_bytes >= sample_order_bytes(count, t.d, o) &&
+  const bool ordered = o.order >= 1 && t.d <= kOrderMaxD && order_ws &&
+                       order_bytes >= sample_order_bytes(t, count, o) &&
                        (int64_t(1) << t.T0.L) <= kT0Lds;
+  // the pipeline writes pairs, so it needs the pair form of X
+  const bool pipe = ordered && o.order == 2 && h.pkeys != nullptr;
   if (!ordered) {
     if (main_start) (void)hipEventRecord(main_start, st);
     const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
@@ -545,15 +942,15 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
   // ordered: chunks of at most `chunk` samples
   const int64_t d = t.d;
   const size_t lds_ord = ((size_t)8 << t.T0.L) + 4 * (size_t)d;
+  const PipeShape ps = pipe_shape(t);
   for (int64_t c0 = 0; c0 < count; c0 += chunk) {
     const int64_t c = count - c0 < chunk ? count - c0 : chunk;
     const DenseSampleArgs a = dense_args(t, B, seed, qid, l0 + c0, c);
     const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
     char* p = (char*)order_ws;
     uint32_t* ell = (uint32_t*)p;
-    uint16_t* kbuf = (uint16_t*)(p + ((size_t)c * 4 + 255) / 256 * 256);
-    uint32_t* cnt =
-        (uint32_t*)((char*)kbuf + ((size_t)c * 2 + 255) / 256 * 256);
+    uint16_t* kbuf = (uint16_t*)(p + align256((size_t)c * 4));
+    uint32_t* cnt = (uint32_t*)((char*)kbuf + align256((size_t)c * 2));
     uint32_t* tot = cnt + nblk * d;
     uint32_t* start = tot + d;
     k_order_count<<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, kbuf);
@@ -563,15 +960,52 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     k_order_place<<<(unsigned)nblk, 256, lds_place, st>>>(a, cnt, start, kbuf,
                                                          ell);
     if (main_start && c0 == 0) (void)hipEventRecord(main_start, st);
-    GroupOrder go{ell, 256 * 4};
     int64_t g8 = order_g8();
-    const int64_t nch = (c + go.chunk - 1) / go.chunk;
-    if (g8 * 8 > nch) g8 = (nch + 7) / 8;
-    if (g8 < 1) g8 = 1;
-    k_sample_dense<4, false, true><<<(unsigned)(8 * g8), 256, lds, st>>>(
-        a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm,
-        h.pkeys ? h.pkeys + c0 : nullptr, h.pvals ? h.pvals + c0 : nullptr,
-        ctr, nullptr, nullptr, nullptr, nullptr, nullptr, go);
+    if (pipe) {
+      const PipeLayout L =
+          pipe_layout((char*)order_ws + align256(korder_bytes(c, d)), c, ps);
+      const int64_t nt = (c + kPipeTile - 1) / kPipeTile;
+      int64_t gp = pipe_g8();
+      if (gp * 8 > nt) gp = (nt + 7) / 8;
+      if (gp < 1) gp = 1;
+      const unsigned grid = (unsigned)(8 * gp);
+      const int Gi = (int)ps.Gi, Gj = (int)ps.Gj;
+      // pass A, then the i-grouped stream
+      k_pipe_ij<<<grid, 256, 0, st>>>(a, t.T0.tot, ell, nt, ps.gsh_i, Gi,
+                                      L.ra, L.ca);
+      k_order_colscan<<<(unsigned)Gi, 256, 0, st>>>(L.ca, nt, Gi, L.ta);
+      k_order_starts<<<1, 256, 0, st>>>(L.ta, Gi, L.sa);
+      k_pipe_scatter<PipeR1><<<(unsigned)nt, 256, 0, st>>>(
+          L.ra, c, ps.gsh_i, Gi, L.ca, L.sa, L.rb);
+      // pass B, then the j-grouped stream
+      PipeR2* r2t = (PipeR2*)L.ra;
+      PipeR2* r2s = (PipeR2*)L.rb;
+      k_pipe_kp<<<grid, 256, 0, st>>>(t.T3.ent, t.T3.L, t.T0.tot, L.rb, c, nt,
+                                      ps.gsh_j, Gj, r2t, L.cb);
+      k_order_colscan<<<(unsigned)Gj, 256, 0, st>>>(L.cb, nt, Gj, L.tb);
+      k_order_starts<<<1, 256, 0, st>>>(L.tb, Gj, L.sb);
+      k_pipe_scatter<PipeR2><<<(unsigned)nt, 256, 0, st>>>(
+          r2t, c, ps.gsh_j, Gj, L.cb, L.sb, r2s);
+      // pass C: the pairs, in j-grouped order
+      k_pipe_edge<<<grid, 256, 0, st>>>(r2s, c, nt, B, d, t.n, t.gram,
+                                        t.T0.tot, h.pkeys + c0, h.pvals + c0,
+                                        ctr);
+      if (groups && c == count && !t.gram) {
+        k_pipe_starts64<<<(unsigned)((Gj + 256) / 256), 256, 0, st>>>(
+            L.sb, Gj, c, L.starts64);
+        groups->starts = L.starts64;
+        groups->G = Gj;
+      }
+    } else {
+      GroupOrder go{ell, 256 * 4};
+      const int64_t nch = (c + go.chunk - 1) / go.chunk;
+      if (g8 * 8 > nch) g8 = (nch + 7) / 8;
+      if (g8 < 1) g8 = 1;
+      k_sample_dense<4, false, true><<<(unsigned)(8 * g8), 256, lds, st>>>(
+          a, t.T0.tot, t.bmax, s_for_F, 0, h.keys, h.vals, hm,
+          h.pkeys ? h.pkeys + c0 : nullptr, h.pvals ? h.pvals + c0 : nullptr,
+          ctr, nullptr, nullptr, nullptr, nullptr, nullptr, go);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

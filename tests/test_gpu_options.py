@@ -1,8 +1,8 @@
 """GPU parity of every launch choice of a MAD plan against the oracle.
 
 The score matrix X can be built from per-sample pairs or by hash atomics,
-and dense samples can run in index order or grouped by k in chunks of any
-power-of-two size.  None of these may change a result, so under each the
+and dense samples can run in index order, grouped by k, or in the three
+passes grouped by k, by i and by j, in chunks of any power-of-two size.  None of these may change a result, so under each the
 score table X and the candidate set Omega_t' must equal the oracle's bit for
 bit, and the returned top t must agree with it (c within 1e-5 relative).
 The chunked case uses chunks far smaller than the default so that one call
@@ -73,9 +73,11 @@ def _with_zeros():
     return A, B
 
 
-# (accumulation, sampler order, ordering chunk)
-SETTINGS = [(1, 1, 1 << 28), (0, 0, 1 << 28), (1, 0, 1 << 28),
-            (0, 1, 1 << 12), (1, 1, 1 << 13)]
+# (accumulation, sampler order, ordering chunk); order 2 with the hash form
+# runs as order 1
+SETTINGS = [(0, 2, 1 << 28), (0, 2, 1 << 12), (1, 2, 1 << 28),
+            (1, 1, 1 << 28), (0, 0, 1 << 28), (1, 0, 1 << 28),
+            (0, 1, 1 << 12), (1, 1, 1 << 13), (0, 1, 1 << 28)]
 
 
 @pytest.mark.parametrize("name", list(DENSE))
@@ -116,7 +118,7 @@ def test_switching_choices_on_one_plan(mad_gpu):
     A, B = workloads.dense_gaussian(900, 800, 16, seed=22)
     gp = mad.Plan.dense(to_dev(A), to_dev(B))
     op = oracle.Plan.dense(A, B)
-    for acc, order, chunk in SETTINGS + [(0, 1, 1 << 28)]:
+    for acc, order, chunk in SETTINGS + [(0, 2, 1 << 28)]:
         gp.set_option(mad.MAD_OPT_ACCUM, acc)
         gp.set_option(mad.MAD_OPT_SAMPLER_ORDER, order)
         gp.set_option(mad.MAD_OPT_ORDER_CHUNK, chunk)
