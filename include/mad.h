@@ -401,6 +401,23 @@ int mad_debug_accumulate(const uint64_t* keys, const float* vals, int64_t n,
                          int F, int64_t* out_keys, int64_t* out_x,
                          int64_t cap, int64_t* n_out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * mad_accumulate_noalloc -- mad_debug_accumulate for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops): the same sums, per key, of rne(vals[e] * 2^F) over the n pairs
+ * (keys (device) uint64, ~0 = none; vals (device) fp32), written to
+ * out_keys / out_x (device int64, capacity n, unordered); *n_out (device
+ * int64) = number of distinct keys.  The inputs are not modified.
+ * Allocates nothing and does not synchronise: its workspace is a static
+ * device array of 12 MiB that each GPU holds until the process ends, so n
+ * is at most 2^18 (MAD_EINVAL above).  Calls that overlap on one GPU share
+ * that array and race: serialise them (one stream, or events).  The first
+ * call on a device looks up the array's address there.  0 <= F <= 62.
+ * ------------------------------------------------------------------------- */
+int mad_accumulate_noalloc(const uint64_t* keys, const float* vals, int64_t n,
+                           int F, int64_t* out_keys, int64_t* out_x,
+                           int64_t* n_out, void* stream);
+
 /* Score table X of the last mad_plan_topk: every pair with a closed
  * diamond, unordered.  keys (device int64, i*n + j), xfix (device int64),
  * capacity cap; *n (host) = number of pairs; *F (host) = fixed-point

@@ -33,7 +33,7 @@ EXPORTS = (
     "mips_get_config", "mips_set_config", "mips_autotune", "mips_stats",
     "mips_debug_scores", "mad_plan_set_verify_precision",
     "mad_plan_verify_stats", "mad_debug_accumulate", "mad_plan_set_option",
-    "mad_plan_get_option",
+    "mad_plan_get_option", "mad_accumulate_noalloc",
 )
 
 
@@ -83,6 +83,8 @@ def lib():
                                           _i64, _i64, _P, _P, _P, _P]
         L.mad_plan_set_verify_precision.argtypes = [_P, C.c_int, _P]
         L.mad_plan_verify_stats.argtypes = [_P, _P, _P]
+        L.mad_accumulate_noalloc.argtypes = [_P, _P, _i64, C.c_int, _P, _P,
+                                             _P, _P]
         L.mad_plan_set_option.argtypes = [_P, C.c_int, _i64]
         L.mad_plan_get_option.argtypes = [_P, C.c_int, _P]
         L.mips_plan_create.argtypes = [_P, _i64, _i64, _u32, _P,
@@ -479,6 +481,23 @@ def debug_accumulate(keys, vals, F):
     x = ox[:got.value].cpu().numpy()
     o = np.argsort(k, kind="stable")
     return k[o], x[o]
+
+
+def accumulate_noalloc(keys, vals, F, out_keys, out_x, n_out, stream=None):
+    """mad_accumulate_noalloc: the score accumulation in the library's static
+    workspace (no device allocation, no synchronisation).  keys (CUDA int64,
+    -1 = none) and vals (CUDA float32) of n <= 2^18 pairs; out_keys, out_x
+    (CUDA int64, capacity n) and n_out (CUDA int64, one entry) receive the
+    distinct keys, their sums and their count."""
+    import torch
+    n = int(keys.numel())
+    kp = _dev(keys, torch.int64, "keys") if n else None
+    vp = _dev(vals, torch.float32, "vals") if n else None
+    okp = _dev(out_keys, torch.int64, "out_keys") if n else None
+    oxp = _dev(out_x, torch.int64, "out_x") if n else None
+    _check(lib().mad_accumulate_noalloc(kp, vp, n, F, okp, oxp,
+                                        _dev(n_out, torch.int64, "n_out"),
+                                        _stream(stream)))
 
 
 def probe_memory(kind, buf, nops, seed=0, stream=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -825,6 +826,118 @@ int mad_debug_accumulate(const uint64_t* keys, const float* vals, int64_t n,
   if (e != hipSuccess) return hip_fail(e, "debug accumulate");
   *n_out = got;
   if (out_keys && got > cap) return fail(MAD_EOVERFLOW, "capacity too small");
+  return MAD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free score accumulation.  Its workspace is a file-scope device
+// array: every GPU holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked
+// up once per device (hipGetSymbolAddress, with that device current) and
+// only that address is passed to kernels and copies.  Calls that overlap on
+// one GPU share the array and race; each call overwrites what it uses.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 18;
+constexpr size_t kNoAllocScratchBytes = size_t(12) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+struct NoAllocLayout {
+  uint64_t* k2;
+  float* v2;
+  uint64_t* okey;
+  int64_t* oval;
+  int64_t* cnt;
+  char* work;
+  size_t work_bytes;
+  size_t total;
+};
+
+NoAllocLayout noalloc_layout(char* base, int64_t n) {
+  const int64_t nn = n > 1 ? n : 1;
+  NoAllocLayout L;
+  char* q = base;
+  L.k2 = (uint64_t*)q; q += (8 * (size_t)nn + 255) / 256 * 256;
+  L.v2 = (float*)q; q += (4 * (size_t)nn + 255) / 256 * 256;
+  L.okey = (uint64_t*)q; q += (8 * (size_t)nn + 255) / 256 * 256;
+  L.oval = (int64_t*)q; q += (8 * (size_t)nn + 255) / 256 * 256;
+  L.cnt = (int64_t*)q; q += 256;
+  L.work = q;
+  L.work_bytes = mad::accum_bytes(nn);
+  L.total = (size_t)(q - base) + L.work_bytes;
+  return L;
+}
+
+// the device address of this device's scratch array (looked up once)
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(MAD_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                      "looking up the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MAD_OK;
+}
+
+}  // namespace
+
+int mad_accumulate_noalloc(const uint64_t* keys, const float* vals, int64_t n,
+                           int F, int64_t* out_keys, int64_t* out_x,
+                           int64_t* n_out, void* stream) {
+  g_err.clear();
+  if (n < 0) return fail(MAD_EINVAL, "n must be >= 0");
+  if (n > kNoAllocMaxPairs)
+    return fail(MAD_EINVAL, "n = %lld pairs exceeds the static workspace "
+                "(at most %lld pairs)", (long long)n,
+                (long long)kNoAllocMaxPairs);
+  if (!n_out) return fail(MAD_EINVAL, "n_out is required");
+  if (n && (!keys || !vals || !out_keys || !out_x))
+    return fail(MAD_EINVAL, "keys, vals, out_keys and out_x are required");
+  if (F < 0 || F > 62) return fail(MAD_EINVAL, "F must be in [0, 62]");
+  void* base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc != MAD_OK) return rc;
+  const NoAllocLayout L = noalloc_layout((char*)base, n);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(MAD_EOVERFLOW, "the static workspace is too small for %lld "
+                "pairs", (long long)n);
+  hipStream_t st = (hipStream_t)stream;
+  if (n == 0) {
+    HIP_TRY(mad::launch_fill_u64((uint64_t*)n_out, 1, 0ull, st),
+            "accumulate (no allocation)");
+    return MAD_OK;
+  }
+  // the accumulation overwrites its pairs: it works on copies
+  HIP_TRY(hipMemcpyAsync(L.k2, keys, 8 * (size_t)n, hipMemcpyDeviceToDevice,
+                         st), "accumulate (no allocation)");
+  HIP_TRY(hipMemcpyAsync(L.v2, vals, 4 * (size_t)n, hipMemcpyDeviceToDevice,
+                         st), "accumulate (no allocation)");
+  HIP_TRY(mad::launch_accumulate(L.k2, L.v2, n, nullptr, F, L.work,
+                                 L.work_bytes, L.okey, L.oval, L.cnt,
+                                 L.cnt + 1, st),
+          "accumulate (no allocation)");
+  mad::HashTable h;
+  h.keys = L.okey;
+  h.vals = L.oval;
+  h.cap = n;
+  h.live = L.cnt + 1;
+  HIP_TRY(mad::launch_dump_scores(h, out_keys, out_x, n, n_out, st),
+          "accumulate (no allocation)");
   return MAD_OK;
 }
 
