@@ -71,7 +71,19 @@ enum {
    * (a vector with itself) is left out, as in the paper's A^T A
    * experiments; results list pairs with i < j and report x = (x_ij +
    * x_ji) / 2. */
-  MAD_FLAG_GRAM = 1u << 2
+  MAD_FLAG_GRAM = 1u << 2,
+  /* Squared matrix (Sec. 3.2.3, equal symmetric inputs): B must be A (same
+   * arrays) with m = n = d and A == A^T (checked unless MAD_FLAG_NO_CHECK;
+   * MAD_EINVAL otherwise), so C = A^2.  Every closed three-path also adds
+   * its increment to x_kk' (the paper adds half to x_ij and half to x_kk'),
+   * then the scores are symmetrised and the diagonal is left out as with
+   * MAD_FLAG_GRAM, which this flag implies.  The kept score of i < j is
+   * 2 (x_ij + x_ji) in those full increments; results report x as the
+   * symmetrised entry of the paper, (x_ij + x_ji) / 2 with half
+   * increments.  F is taken for 2s updates.  X is built from pairs only
+   * (MAD_OPT_ACCUM = MAD_ACCUM_HASH is MAD_EUNSUPPORTED) and the sampler
+   * runs in k order at most. */
+  MAD_FLAG_SQUARE = 1u << 3
 };
 
 typedef struct mad_plan mad_plan;

@@ -55,6 +55,8 @@ def _declare(L):
     L.orc_prefix.argtypes = [_P, _i64, _P]
     L.orc_plan_set_gram.argtypes = [_P, C.c_int]
     L.orc_plan_set_gram.restype = None
+    L.orc_plan_set_square.argtypes = [_P, C.c_int]
+    L.orc_plan_set_square.restype = None
     L.orc_run_length.argtypes = []
     L.orc_run_length.restype = C.c_int
     L.orc_quanta.argtypes = [_P, _i64, _P]
@@ -211,6 +213,13 @@ class Plan:
         on i < j), diagonal dropped (Sec. 3.2.2)."""
         lib().orc_plan_set_gram(self._h, 1 if gram else 0)
 
+    def set_square(self, square: bool = True):
+        """B = A symmetric (C = A^2): each closed sample also updates
+        x_kk' (Sec. 3.2.3), then X is symmetrised as for set_gram; the
+        stored score of i < j is four times the symmetrised entry and F is
+        taken for 2s updates."""
+        lib().orc_plan_set_square(self._h, 1 if square else 0)
+
     def close(self):
         if self._h:
             lib().orc_plan_free(self._h)
@@ -271,7 +280,7 @@ class Plan:
 
     def scores(self, seed: int, s: int, F: int, qid: int = 0):
         """Sorted (key, x_fix) of every pair with a closed diamond."""
-        cap = max(int(s), 1)
+        cap = max(2 * int(s), 1)
         keys = np.zeros(cap, np.int64)
         x = np.zeros(cap, np.int64)
         closed = C.c_int64()

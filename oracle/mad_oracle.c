@@ -350,6 +350,8 @@ typedef struct orc_plan {
   otable *T1, *T2, *T3;
   float bmax;   /* max |b| over all entries */
   int gram;     /* B = A: symmetrise X and drop the diagonal (Sec. 3.2.2) */
+  int square;   /* B = A symmetric, C = A^2: two updates per sample
+                   (Sec. 3.2.3), then the symmetrisation of gram */
 } orc_plan;
 
 static void plan_build_aside(orc_plan *p) {
@@ -502,8 +504,10 @@ int orc_fix_exponent(float bmax, int64_t s) {
   return 62 - eb - ls;
 }
 
+/* The squared variant adds two increments per sample, so its exponent is
+ * taken for 2s updates (no int64 sum can overflow). */
 int orc_plan_fix_exponent(const orc_plan *p, int64_t s) {
-  return orc_fix_exponent(p->bmax, s);
+  return orc_fix_exponent(p->bmax, p->square ? 2 * s : s);
 }
 
 static int sign_bit(float x) {
@@ -608,24 +612,42 @@ static int64_t symmetrise(kv *X, int64_t nd, int64_t n) {
 
 void orc_plan_set_gram(orc_plan *p, int gram) { p->gram = gram; }
 
+/* Sec. 3.2.3, equal symmetric inputs (C = A^2, B = A, A symmetric, m = d):
+ * every closed sample updates x_ij and x_kk' by half of its increment each,
+ * then X is symmetrised as in the Gram case.  Kept exact by adding the full
+ * increment to both keys: the stored score of a pair i < j is then
+ * 2 (x_ij + x_ji), four times the symmetrised entry, which orders the pairs
+ * the same way. */
+void orc_plan_set_square(orc_plan *p, int square) {
+  p->square = square;
+  if (square) p->gram = 1;
+}
+
 static int64_t build_scores(const orc_plan *p, uint64_t seed, uint64_t qid,
                             int64_t s, int F, kv **out, int64_t *closed_out) {
-  kv *all = (kv *)malloc(sizeof(kv) * (size_t)(s > 0 ? s : 1));
-  int64_t nc = 0;
+  const int64_t per = p->square ? 2 : 1;
+  kv *all = (kv *)malloc(sizeof(kv) * (size_t)(s > 0 ? per * s : 1));
+  int64_t nc = 0, nkv = 0;
   if (p->T0.live) {
     for (int64_t l = 0; l < s; ++l) {
       int32_t k, i, j, kp;
       int64_t inc;
       if (one_sample(p, seed, qid, (uint64_t)l, F, &k, &i, &j, &kp, &inc)) {
-        all[nc].key = (int64_t)i * p->n + j;
-        all[nc].inc = inc;
+        all[nkv].key = (int64_t)i * p->n + j;
+        all[nkv].inc = inc;
+        ++nkv;
+        if (p->square) { /* the second update, of x_kk' */
+          all[nkv].key = (int64_t)k * p->n + kp;
+          all[nkv].inc = inc;
+          ++nkv;
+        }
         ++nc;
       }
     }
   }
-  qsort(all, (size_t)nc, sizeof(kv), cmp_kv_key);
+  qsort(all, (size_t)nkv, sizeof(kv), cmp_kv_key);
   int64_t nd = 0;
-  for (int64_t e = 0; e < nc; ++e) {
+  for (int64_t e = 0; e < nkv; ++e) {
     if (nd > 0 && all[nd - 1].key == all[e].key) all[nd - 1].inc += all[e].inc;
     else all[nd++] = all[e];
   }

@@ -19,6 +19,7 @@ MAD_OK, MAD_EINVAL, MAD_ENOMEM, MAD_EHIP, MAD_EOVERFLOW, MAD_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 MAD_FP32, MAD_BF16, MAD_FP8_E4M3 = 0, 1, 2
 MAD_FLAG_NONE, MAD_FLAG_NO_CHECK, MAD_FLAG_TIMING, MAD_FLAG_GRAM = 0, 1, 2, 4
+MAD_FLAG_SQUARE = 8
 MAD_OPT_ACCUM, MAD_OPT_SAMPLER_ORDER, MAD_OPT_ORDER_CHUNK = 0, 1, 2
 MAD_ACCUM_PAIRS, MAD_ACCUM_HASH = 0, 1
 

@@ -213,6 +213,9 @@ int mad_plan_create_dense(const float* A, int64_t m, const float* B,
     return fail(MAD_EINVAL, "A and B must be device pointers");
   if ((flags & MAD_FLAG_GRAM) && (A != B || m != n))
     return fail(MAD_EINVAL, "MAD_FLAG_GRAM needs B == A (same pointer, n == m)");
+  if ((flags & MAD_FLAG_SQUARE) && (A != B || m != n || m != d))
+    return fail(MAD_EINVAL, "MAD_FLAG_SQUARE needs B == A (same pointer) and "
+                "m == n == d");
   mad_plan* p = new (std::nothrow) mad_plan();
   if (!p) return fail(MAD_ENOMEM, "host allocation failed");
   p->kind = 0;
@@ -224,7 +227,8 @@ int mad_plan_create_dense(const float* A, int64_t m, const float* B,
   p->flags = flags;
   p->sopt = mad::sample_options_default();
   hipError_t e = mad::dense_tables_alloc(p->dt, m, n, d);
-  p->dt.gram = (flags & MAD_FLAG_GRAM) ? 1 : 0;
+  p->dt.square = (flags & MAD_FLAG_SQUARE) ? 1 : 0;
+  p->dt.gram = ((flags & MAD_FLAG_GRAM) || p->dt.square) ? 1 : 0;
   if (e == hipSuccess && (flags & MAD_FLAG_TIMING))
     for (hipEvent_t& ev : p->ev)
       if ((e = hipEventCreate(&ev)) != hipSuccess) break;
@@ -263,6 +267,16 @@ int mad_plan_refresh(mad_plan* p, void* stream) {
       return fail(MAD_EINVAL, "A or B holds NaN or Inf");
     }
     if (e != hipSuccess) return hip_fail(e, "building sparse tables");
+    if (p->ct.square && check) {
+      int sym = 0;
+      HIP_TRY(mad::launch_check_csr_symmetric(p->ct, p->ct.bad + 4, st),
+              "symmetry check");
+      HIP_TRY(hipMemcpyAsync(&sym, p->ct.bad + 4, sizeof sym,
+                             hipMemcpyDeviceToHost, st), "symmetry check");
+      HIP_TRY(hipStreamSynchronize(st), "symmetry check");
+      if (sym)
+        return fail(MAD_EINVAL, "MAD_FLAG_SQUARE needs a symmetric A");
+    }
     record(p, 1, st);
     p->timed_tables = p->ev[0] != nullptr;
     p->ran = false;
@@ -281,7 +295,16 @@ int mad_plan_refresh(mad_plan* p, void* stream) {
   record(p, 1, st);
   p->timed_tables = p->ev[0] != nullptr;
   p->ran = false;
-  return check_bad_inputs(p, st);
+  if (p->dt.square && check)
+    HIP_TRY(mad::launch_check_symmetric(p->A, p->m, p->dt.bad + 4, st),
+            "symmetry check");
+  int rc = check_bad_inputs(p, st);
+  if (rc != MAD_OK || !p->dt.square || !check) return rc;
+  int sym = 0;
+  HIP_TRY(hipMemcpy(&sym, p->dt.bad + 4, sizeof sym, hipMemcpyDeviceToHost),
+          "symmetry check");
+  if (sym) return fail(MAD_EINVAL, "MAD_FLAG_SQUARE needs a symmetric A");
+  return MAD_OK;
 }
 
 void mad_plan_destroy(mad_plan* p) {
@@ -303,7 +326,17 @@ static int accum_default() {
   return v;
 }
 
+static bool plan_square(const mad_plan* p) {
+  return p->kind == 2 ? p->ct.square != 0 : p->dt.square != 0;
+}
+
+// samples in s' updates of X: two per sample for the squared variant
+static int64_t plan_updates(const mad_plan* p, int64_t s) {
+  return plan_square(p) ? 2 * s : s;
+}
+
 static bool accum_pairs(const mad_plan* p) {
+  if (plan_square(p)) return true;  // two pairs per sample: pair form only
   const int a = p->opt_accum < 0 ? accum_default() : p->opt_accum;
   return a == MAD_ACCUM_PAIRS;
 }
@@ -317,15 +350,16 @@ static size_t pair_bytes(int64_t s) {
 static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   if (s <= p->ws_s && tp <= p->ws_tp && t <= p->ws_t) return MAD_OK;
   const int64_t s2 = s > p->ws_s ? s : p->ws_s;
+  const int64_t u2 = plan_updates(p, s2);  // updates of X (pairs)
   const int64_t tp2 = tp > p->ws_tp ? tp : p->ws_tp;
   const int64_t t2 = t > p->ws_t ? t : p->ws_t;
   const double mn = (double)p->m * (double)p->n;
-  const int64_t pairs = (double)s2 < mn ? s2 : (int64_t)mn;
+  const int64_t pairs = (double)u2 < mn ? u2 : (int64_t)mn;
   const bool use_pairs = accum_pairs(p);
   // pair form: X is a table of s entries (each bin of pairs leaves its
   // distinct keys in its own range); hash form: a table of twice min(s, mn)
   // slots, rounded up to a power of two
-  const int64_t hcap = use_pairs ? (s2 > 1 ? s2 : 1)
+  const int64_t hcap = use_pairs ? (u2 > 1 ? u2 : 1)
                                  : next_pow2(2 * (pairs > 512 ? pairs : 512));
   // candidates / boundary lists: candidate selection needs |Omega_s| <= pairs entries,
   // final selection needs 4 t (final set) + 4 t' (boundary of the candidates)
@@ -351,7 +385,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
                                                            p->sopt))) !=
            hipSuccess) ||
       (use_pairs &&
-       (e = mad::dev_alloc(p->acc, pair_bytes(s2) + mad::accum_bytes(s2))) !=
+       (e = mad::dev_alloc(p->acc, pair_bytes(u2) + mad::accum_bytes(u2))) !=
            hipSuccess)) {
     p->ws_s = p->ws_tp = p->ws_t = -1;
     return hip_fail(e, "allocating workspace");
@@ -408,10 +442,15 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   if (rc != MAD_OK) return rc;
   record(p, 2, st);
   mad::HashTable h = p->h;
+  const int64_t nu = plan_updates(p, s);  // pairs written: s or 2s
   if (p->pairs) {
     h.pkeys = (uint64_t*)p->acc.p;
-    h.pvals = (float*)((char*)p->acc.p + 8 * (size_t)s);
-    h.cap = s;
+    h.pvals = (float*)((char*)p->acc.p + 8 * (size_t)nu);
+    h.cap = nu;
+    if (plan_square(p)) {  // the (k, k') pairs in the second half
+      h.pkeys2 = h.pkeys + s;
+      h.pvals2 = h.pvals + s;
+    }
   } else {
     HIP_TRY(mad::launch_fill_u64(h.keys, h.cap, mad::kEmptyKey, st),
             "clearing X");
@@ -438,7 +477,7 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
             "sampling");
   record(p, 4, st);
   if (p->pairs) {
-    const size_t pb = pair_bytes(s);
+    const size_t pb = pair_bytes(nu);
     if (groups.starts)
       HIP_TRY(mad::launch_accumulate_grouped(
                   h.pkeys, h.pvals, s, groups.starts, groups.G, plan_bmax(p),
@@ -446,7 +485,7 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
                   (int64_t*)&p->ctr->distinct, (int64_t*)&p->ctr->entries, st),
               "accumulating X");
     else
-      HIP_TRY(mad::launch_accumulate(h.pkeys, h.pvals, s, plan_bmax(p), s,
+      HIP_TRY(mad::launch_accumulate(h.pkeys, h.pvals, nu, plan_bmax(p), nu,
                                      (char*)p->acc.p + pb, p->acc.bytes - pb,
                                      h.keys, h.vals,
                                      (int64_t*)&p->ctr->distinct,
@@ -461,8 +500,11 @@ int mad_plan_topk(mad_plan* p, int64_t t, int64_t s, int64_t t_prime,
   HIP_TRY(mad::launch_postprocess(h, p->A, p->B,
                                   p->kind == 2 ? &p->ct.in : nullptr,
                                   p->verify_prec != MAD_FP32 ? &p->lv : nullptr,
-                                  p->n, p->d, tp_eff, t, plan_bmax(p), s,
-                                  (p->flags & MAD_FLAG_GRAM) ? 1 : 0, p->w,
+                                  p->n, p->d, tp_eff, t, plan_bmax(p), nu,
+                                  plan_square(p)
+                                      ? 2
+                                      : (p->flags & MAD_FLAG_GRAM) ? 1 : 0,
+                                  p->w,
                                   out, n_out, true, st),
           "postprocessing");
   record(p, 5, st);
@@ -481,6 +523,9 @@ int mad_plan_set_option(mad_plan* p, int option, int64_t value) {
       if (value != MAD_ACCUM_PAIRS && value != MAD_ACCUM_HASH)
         return fail(MAD_EINVAL, "MAD_OPT_ACCUM takes MAD_ACCUM_PAIRS or "
                     "MAD_ACCUM_HASH");
+      if (value == MAD_ACCUM_HASH && plan_square(p))
+        return fail(MAD_EUNSUPPORTED, "the squared variant builds X from "
+                    "pairs only");
       if ((int)value != (p->opt_accum < 0 ? accum_default() : p->opt_accum))
         p->ws_s = p->ws_tp = p->ws_t = -1;  // workspace of the other form
       p->opt_accum = (int)value;
@@ -660,7 +705,7 @@ int mad_fix_exponent(mad_plan* p, int64_t s, int* F) {
   HIP_TRY(hipDeviceSynchronize(), "fix exponent");
   HIP_TRY(hipMemcpy(&bmax, plan_bmax(p), sizeof(float), hipMemcpyDeviceToHost),
           "fix exponent");
-  *F = mad::fix_exponent(bmax, s);
+  *F = mad::fix_exponent(bmax, plan_updates(p, s));
   return MAD_OK;
 }
 
@@ -1039,6 +1084,11 @@ int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
   if ((flags & MAD_FLAG_GRAM) &&
       (a_ptr != b_ptr || a_idx != b_idx || a_val != b_val || m != n))
     return fail(MAD_EINVAL, "MAD_FLAG_GRAM needs B == A (same arrays, n == m)");
+  if ((flags & MAD_FLAG_SQUARE) &&
+      (a_ptr != b_ptr || a_idx != b_idx || a_val != b_val || m != n ||
+       m != d))
+    return fail(MAD_EINVAL, "MAD_FLAG_SQUARE needs B == A (same arrays) and "
+                "m == n == d");
   mad_plan* p = new (std::nothrow) mad_plan();
   if (!p) return fail(MAD_ENOMEM, "host allocation failed");
   p->kind = 2;
@@ -1052,7 +1102,8 @@ int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
   p->ct.nnzA = nnzA;
   p->ct.nnzB = nnzB;
   p->ct.in = mad::CsrView{a_ptr, a_idx, a_val, b_ptr, b_idx, b_val};
-  p->ct.gram = (flags & MAD_FLAG_GRAM) ? 1 : 0;
+  p->ct.square = (flags & MAD_FLAG_SQUARE) ? 1 : 0;
+  p->ct.gram = ((flags & MAD_FLAG_GRAM) || p->ct.square) ? 1 : 0;
   hipError_t e = hipSuccess;
   if (flags & MAD_FLAG_TIMING)
     for (hipEvent_t& ev : p->ev)

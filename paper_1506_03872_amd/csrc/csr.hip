@@ -1271,6 +1271,10 @@ struct CsrSampleArgs {
   int64_t l0, count;
   int gram;  // B = A: key of the pair with i < j, diagonal left out
   const int* b_unit;  // 1: every value of B is 1 (no fourth-edge value load)
+  // squared variant (Sec. 3.2.3): the second pair of sample e, keyed by
+  // (k, k') like the first, goes to pk2[e] / pv2[e] (pair form only)
+  uint64_t* pk2;
+  float* pv2;
 };
 
 __device__ __forceinline__ Drawn draw16(const Ent16& e, uint64_t U) {
@@ -1295,8 +1299,10 @@ __global__ __launch_bounds__(256) void k_sample_csr(
   if (!(wtot[0] > 0.0)) {  // ||W||_1 = 0: nothing can be sampled
     if (pkeys)
       for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-           e < a.count; e += (int64_t)gridDim.x * blockDim.x)
+           e < a.count; e += (int64_t)gridDim.x * blockDim.x) {
         pkeys[e] = kEmptyKey;
+        if (a.pk2) a.pk2[e] = kEmptyKey;
+      }
     return;
   }
   const int N0 = 1 << a.L0;
@@ -1424,6 +1430,20 @@ __global__ __launch_bounds__(256) void k_sample_csr(
                 (unsigned long long)(ins[u] ? key[u] : kEmptyKey),
                 (unsigned long long*)(pkeys + e));
             __builtin_nontemporal_store(sg[u] ? -v[u] : v[u], pvals + e);
+            if (a.pk2) {  // Sec. 3.2.3: the same increment to x_kk'
+              uint64_t kk = k[u], kq = kp[u];
+              bool ins2 = closed[u] && kk != kq;  // diagonal left out
+              if (kk > kq) {
+                const uint64_t tmp = kk;
+                kk = kq;
+                kq = tmp;
+              }
+              __builtin_nontemporal_store(
+                  (unsigned long long)(ins2 ? kk * (uint64_t)a.n + kq
+                                            : kEmptyKey),
+                  (unsigned long long*)(a.pk2 + e));
+              __builtin_nontemporal_store(sg[u] ? -v[u] : v[u], a.pv2 + e);
+            }
           }
           pend[u] = false;
         }
@@ -1477,6 +1497,37 @@ __global__ __launch_bounds__(256) void k_sample_csr(
   }
 }
 
+// the squared variant needs A == A^T: the compressed rows of A must equal
+// its transpose (per coordinate, the vectors in ascending order with their
+// values) entry for entry; *flag = 1 on any difference
+__global__ void k_check_csr_symmetric(const int64_t* ptr, const int32_t* idx,
+                                      const float* val, const int64_t* tptr,
+                                      const uint32_t* trow, const float* tval,
+                                      int64_t rows, int64_t nnz, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool diff = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       e <= rows || e < nnz; e += stride) {
+    if (e <= rows && ptr[e] != tptr[e]) diff = true;
+    if (e < nnz && (idx[e] != (int32_t)trow[e] || val[e] != tval[e]))
+      diff = true;
+  }
+  if (diff) *flag = 1;
+}
+
+hipError_t launch_check_csr_symmetric(const CsrTables& t, int* flag,
+                                      hipStream_t st) {
+  hipError_t e = launch_fill_u64((uint64_t*)flag, 1, 0ull, st);
+  if (e != hipSuccess) return e;
+  const int64_t work = (t.m + 1 > t.nnzA ? t.m + 1 : t.nnzA);
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_check_csr_symmetric<<<(unsigned)(blocks < 1 ? 1 : blocks), 256, 0, st>>>(
+      t.in.a_ptr, t.in.a_idx, t.in.a_val, t.at_ptr, t.at_row, t.at_val, t.m,
+      t.nnzA, flag);
+  return hipGetLastError();
+}
+
 static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
                               int64_t l0, int64_t count) {
   CsrSampleArgs a;
@@ -1496,6 +1547,8 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.count = count;
   a.gram = t.gram;
   a.b_unit = t.b_unit;
+  a.pk2 = nullptr;
+  a.pv2 = nullptr;
   return a;
 }
 
@@ -1532,7 +1585,9 @@ hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
                              HashTable h, SampleCounters* ctr,
                              hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  const CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
+  CsrSampleArgs a = csr_args(t, seed, qid, l0, count);
+  a.pk2 = h.pkeys2;
+  a.pv2 = h.pvals2;
   switch (csr_unroll()) {
 #define MAD_CSR_CASE(UU)                                                     \
   case UU:                                                                   \

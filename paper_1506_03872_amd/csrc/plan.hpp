@@ -41,6 +41,7 @@ struct DenseTables {
   float* bmax = nullptr; // 1
   int* bad = nullptr;    // 1
   int gram = 0;          // B = A, symmetrised scores (Sec. 3.2.2)
+  int square = 0;        // B = A symmetric: x_kk' updated too (Sec. 3.2.3)
   // the B-side family T2 is built on a stream of its own, forked from and
   // joined back into the caller's stream
   hipStream_t side = nullptr;
@@ -53,6 +54,9 @@ void dense_tables_free(DenseTables& t);
 hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
                               bool check, DeviceBuffer& scratch,
                               hipStream_t st);
+// *flag (device, 8-byte aligned) = 1 unless the m x m matrix A equals A^T
+hipError_t launch_check_symmetric(const float* A, int64_t m, int* flag,
+                                  hipStream_t st);
 
 // MIPS: per-query stage-0 tables (S = nq tables over d coordinates, weight
 // |q_k| v_k); scratch only when 2^ceil(log2 d) > 512
@@ -88,6 +92,9 @@ struct HashTable {
   const int64_t* live = nullptr;
   uint64_t* pkeys = nullptr;
   float* pvals = nullptr;
+  // squared variant: sample e's second pair (key of (k, k')) at pkeys2[e]
+  uint64_t* pkeys2 = nullptr;
+  float* pvals2 = nullptr;
 };
 
 // sum of the increments rne(vals[e] 2^F) per key over n pairs (key EMPTY:
@@ -220,6 +227,7 @@ struct CsrTables {
   int* b_unit = nullptr;  // 1: every stored value of B is 1 (in bad's block)
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.2.2)
+  int square = 0;         // B = A symmetric: x_kk' updated too (Sec. 3.2.3)
   bool validated = false; // the structure passed a check on this plan
   // the transposes' structure (pointers, rows, and the source position of
   // each entry) and the table layouts depend only on the sparsity
@@ -235,6 +243,10 @@ struct CsrTables {
 // sparse tables is planned on the host).  Returns hipErrorInvalidValue when
 // the inputs are malformed or hold NaN/Inf, with t.bad set.
 hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st);
+// *flag (device, 8-byte aligned) = 1 unless A's compressed rows equal its
+// transpose (A == A^T); after csr_tables_build
+hipError_t launch_check_csr_symmetric(const CsrTables& t, int* flag,
+                                      hipStream_t st);
 void csr_tables_free(CsrTables& t);
 hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
                              int64_t l0, int64_t count, int64_t s_for_F,

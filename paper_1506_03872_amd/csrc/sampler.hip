@@ -36,7 +36,28 @@ struct DenseSampleArgs {
   uint64_t seed, qid;
   int64_t l0, count;
   int gram;  // B = A: key of the pair with i < j, diagonal left out
+  // squared variant (Sec. 3.2.3): the second pair of sample e, keyed by
+  // (k, k') like the first, goes to pk2[e] / pv2[e] (pair form only)
+  uint64_t* pk2;
+  float* pv2;
 };
+
+// key of an update of x_ab: a*n + b, or for symmetrised scores the key of
+// (min, max) with the diagonal left out (kEmptyKey)
+__device__ __forceinline__ uint64_t pair_key(uint64_t a, uint64_t b,
+                                             uint64_t n, int gram,
+                                             bool closed) {
+  if (!closed) return kEmptyKey;
+  if (gram) {
+    if (a == b) return kEmptyKey;
+    if (a > b) {
+      const uint64_t t = a;
+      a = b;
+      b = t;
+    }
+  }
+  return a * n + b;
+}
 
 struct OneSample {
   uint32_t k, i, j, kp;
@@ -65,8 +86,10 @@ __global__ __launch_bounds__(256) void k_sample_dense(
   if (!(wtot[0] > 0.0)) {  // ||W||_1 = 0: nothing can be sampled
     if (pkeys)
       for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-           e < a.count; e += (int64_t)gridDim.x * blockDim.x)
+           e < a.count; e += (int64_t)gridDim.x * blockDim.x) {
         pkeys[e] = kEmptyKey;
+        if (a.pk2) a.pk2[e] = kEmptyKey;
+      }
     return;
   }
   const int N0 = 1 << a.L0;
@@ -190,6 +213,13 @@ __global__ __launch_bounds__(256) void k_sample_dense(
                 (unsigned long long)(ins[u] ? key[u] : kEmptyKey),
                 (unsigned long long*)(pkeys + e));
             __builtin_nontemporal_store(sgn[u] ? -v[u] : v[u], pvals + e);
+            if (a.pk2) {  // Sec. 3.2.3: the same increment to x_kk'
+              __builtin_nontemporal_store(
+                  (unsigned long long)pair_key(smp[u].k, smp[u].kp, a.n,
+                                               a.gram, smp[u].closed),
+                  (unsigned long long*)(a.pk2 + e));
+              __builtin_nontemporal_store(sgn[u] ? -v[u] : v[u], a.pv2 + e);
+            }
           }
           pend[u] = false;
         }
@@ -270,6 +300,8 @@ static DenseSampleArgs dense_args(const DenseTables& t, const float* B,
   a.l0 = l0;
   a.count = count;
   a.gram = t.gram;
+  a.pk2 = nullptr;
+  a.pv2 = nullptr;
   return a;
 }
 
@@ -916,11 +948,15 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
   const bool ordered = o.order >= 1 && t.d <= kOrderMaxD && order_ws &&
                        order_bytes >= sample_order_bytes(t, count, o) &&
                        (int64_t(1) << t.T0.L) <= kT0Lds;
-  // the pipeline writes pairs, so it needs the pair form of X
-  const bool pipe = ordered && o.order == 2 && h.pkeys != nullptr;
+  // the pipeline writes one pair per sample, so it needs the pair form of
+  // X and not the squared variant
+  const bool pipe = ordered && o.order == 2 && h.pkeys != nullptr &&
+                    !t.square;
   if (!ordered) {
     if (main_start) (void)hipEventRecord(main_start, st);
-    const DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
+    DenseSampleArgs a = dense_args(t, B, seed, qid, l0, count);
+    a.pk2 = h.pkeys2;
+    a.pv2 = h.pvals2;
     switch (sampler_unroll()) {
 #define MAD_SAMPLE_CASE(UU)                                                \
   case UU:                                                                 \
@@ -945,7 +981,9 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
   const PipeShape ps = pipe_shape(t);
   for (int64_t c0 = 0; c0 < count; c0 += chunk) {
     const int64_t c = count - c0 < chunk ? count - c0 : chunk;
-    const DenseSampleArgs a = dense_args(t, B, seed, qid, l0 + c0, c);
+    DenseSampleArgs a = dense_args(t, B, seed, qid, l0 + c0, c);
+    a.pk2 = h.pkeys2 ? h.pkeys2 + c0 : nullptr;
+    a.pv2 = h.pvals2 ? h.pvals2 + c0 : nullptr;
     const int64_t nblk = (c + kOrdPer - 1) / kOrdPer;
     char* p = (char*)order_ws;
     uint32_t* ell = (uint32_t*)p;

@@ -1017,6 +1017,42 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
 // ---------------------------------------------------------------------------
 // dense plan tables
 // ---------------------------------------------------------------------------
+// A == A^T for the squared variant (m x m): *flag = 1 on any difference.
+// One workgroup per 64 x 64 tile pair (tile (bx, by) with bx <= by and its
+// mirror), both staged in LDS so that every global read is coalesced.
+__global__ __launch_bounds__(256) void k_check_symmetric(const float* A,
+                                                         int64_t m,
+                                                         int* flag) {
+  __shared__ float t1[64][65];
+  __shared__ float t2[64][65];
+  const int64_t bx = blockIdx.x, by = blockIdx.y;
+  if (bx > by) return;
+  const int64_t r0 = by * 64, c0 = bx * 64;  // tile rows r0.., cols c0..
+  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
+    const int r = q >> 6, c = q & 63;
+    const int64_t i = r0 + r, k = c0 + c;
+    t1[r][c] = (i < m && k < m) ? A[i * m + k] : 0.0f;
+    const int64_t i2 = c0 + r, k2 = r0 + c;  // the mirror tile
+    t2[r][c] = (i2 < m && k2 < m) ? A[i2 * m + k2] : 0.0f;
+  }
+  __syncthreads();
+  bool diff = false;
+  for (int q = threadIdx.x; q < 64 * 64; q += 256) {
+    const int r = q >> 6, c = q & 63;
+    if (t1[r][c] != t2[c][r]) diff = true;
+  }
+  if (diff) *flag = 1;
+}
+
+hipError_t launch_check_symmetric(const float* A, int64_t m, int* flag,
+                                  hipStream_t st) {
+  hipError_t e = launch_fill_u64((uint64_t*)flag, 1, 0ull, st);
+  if (e != hipSuccess) return e;
+  const unsigned g = (unsigned)((m + 63) / 64);
+  k_check_symmetric<<<dim3(g, g), 256, 0, st>>>(A, m, flag);
+  return hipGetLastError();
+}
+
 hipError_t dev_alloc(DeviceBuffer& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return hipSuccess;
   dev_free(b);

@@ -33,6 +33,7 @@ WORKLOAD_IDS = {
     "nonneg": 7,
     "tiny": 8,
     "ragged_csr": 9,
+    "symmetric": 10,
 }
 
 
@@ -137,6 +138,22 @@ def ragged_csr(m: int, n: int, d: int, seed: int = 0, density: float = 0.2):
         r, c = np.nonzero(mask)
         out.append((ptr, c.astype(np.int32), X[r, c].astype(np.float32)))
     return out[0], out[1], m, n, d
+
+
+def symmetric(m: int, density: float = 0.3, seed: int = 0,
+              weighted: bool = True):
+    """A symmetric m x m matrix (an undirected graph's adjacency, as in the
+    A^2 link-prediction workload of Sec. 6): each pair i <= j is an edge with
+    probability ``density``; weights N(0,1) (or 1 when not weighted)."""
+    g = rng("symmetric", 0, seed)
+    upper = np.triu(g.random((m, m)) < density)
+    if weighted:
+        W = g.standard_normal((m, m)).astype(np.float32)
+    else:
+        W = np.ones((m, m), np.float32)
+    A = np.where(upper, W, np.float32(0.0))
+    A = np.triu(A) + np.triu(A, 1).T
+    return np.ascontiguousarray(A, dtype=np.float32)
 
 
 def csr_to_dense(ptr, idx, val, rows: int, d: int) -> np.ndarray:
