@@ -57,6 +57,9 @@ def parse():
                     help="sparse configs: every stored value 1 (0/1 inputs)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the time-to-recall sweep")
+    ap.add_argument("--binary", type=float, default=0.0,
+                    help="dense configs: 0/1 inputs of the same shape with "
+                         "this density (the binary inputs of Alg. 1)")
     return ap.parse_args()
 
 
@@ -151,9 +154,13 @@ def _oracle_range(job):
     import numpy as np
     import oracle
     import workloads
-    config, data_seed, sample_seed, l0, cnt, F = job
-    _, data = workloads.make(config, seed=data_seed)
-    A, B = data["A"], data["B"]
+    config, data_seed, sample_seed, l0, cnt, F, binary = job
+    cfg, data = workloads.make(config, seed=data_seed)
+    if binary:
+        A, B = workloads.binary(cfg["m"], cfg["n"], cfg["d"], binary,
+                                seed=data_seed)
+    else:
+        A, B = data["A"], data["B"]
     p = oracle.Plan.dense(A, B)
     r = p.samples(sample_seed, l0, cnt, F)
     p.close()
@@ -183,7 +190,8 @@ def cpu_baseline(A, B, cfg, args):
     F = p.fix_exponent(s)
     bounds = np.linspace(0, s, workers + 1).astype(np.int64)
     jobs = [(args.config, args.seed, seed, int(bounds[w]),
-             int(bounds[w + 1] - bounds[w]), F) for w in range(workers)]
+             int(bounds[w + 1] - bounds[w]), F, args.binary)
+            for w in range(workers)]
     t3 = time.perf_counter()
     with mp.get_context("spawn").Pool(workers) as pool:
         parts = pool.map(_oracle_range, jobs)
@@ -592,6 +600,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     A_h, B_h = data["A"], data["B"]
+    if args.binary:
+        A_h, B_h = workloads.binary(A_h.shape[0], B_h.shape[0], A_h.shape[1],
+                                    args.binary, seed=args.seed)
+        data = {"A": A_h, "B": B_h}
     s, tp, t = cfg["s"], cfg["t_prime"], cfg["t"]
     dev = torch.device("cuda:0")
     A = torch.from_numpy(A_h).to(dev)
@@ -727,7 +739,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+int64",
         "data": "synthetic",
-        "config": {"workload": "dense_planted_%s" % args.config,
+        "config": {"workload": ("dense_binary%g_%s" % (args.binary,
+                                                          args.config)
+                                if args.binary else
+                                "dense_planted_%s" % args.config),
                    "m": m, "n": n, "d": d, "s": s, "t_prime": tp, "t": t,
                    "n_planted": int(len(data.get("planted_i", []))),
                    "seed": args.seed},

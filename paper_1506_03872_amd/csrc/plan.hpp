@@ -39,7 +39,12 @@ struct DenseTables {
   double* v = nullptr;   // == T1.tot
   double* om = nullptr;  // d
   float* bmax = nullptr; // 1
-  int* bad = nullptr;    // 1
+  int* bad = nullptr;    // 1 (block of 64 ints: bad[4] symmetry, bad[6]
+                         // B binary)
+  // binary inputs (Alg. 1): when every entry of B is 0 or 1 (bad[6] == 1),
+  // bit j*d + k of bbits is b_jk and the sampler reads the fourth edge
+  // from these n*d bits (an L2-sized array) instead of from B
+  uint32_t* bbits = nullptr;
   int gram = 0;          // B = A, symmetrised scores (Sec. 3.2.2)
   int square = 0;        // B = A symmetric: x_kk' updated too (Sec. 3.2.3)
   // the B-side family T2 is built on a stream of its own, forked from and

@@ -40,7 +40,21 @@ struct DenseSampleArgs {
   // (k, k') like the first, goes to pk2[e] / pv2[e] (pair form only)
   uint64_t* pk2;
   float* pv2;
+  // binary B (Alg. 1): when *bbin == 1 the fourth edge is bit j*d + k' of
+  // bbits, an array of n*d bits that stays in L2, instead of B[j*d + k']
+  const uint32_t* bbits;
+  const int* bbin;
 };
+
+// the fourth edge b_k'j: from the bitmap of a binary B, else from B
+__device__ __forceinline__ float fourth_edge(const float* B,
+                                             const uint32_t* bbits, bool bin,
+                                             int64_t d, uint32_t j,
+                                             uint32_t kp) {
+  const int64_t e = (int64_t)j * d + kp;
+  if (bin) return (float)((bbits[e >> 5] >> (e & 31)) & 1u);
+  return B[e];
+}
 
 // key of an update of x_ab: a*n + b, or for symmetrised scores the key of
 // (min, max) with the diagonal left out (kEmptyKey)
@@ -99,6 +113,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
   __syncthreads();
   const uint64_t* T0 = t0_lds ? t0s : a.T0;
   const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
+  const bool binB = a.bbin && *a.bbin == 1;
 
   // ungrouped: grid-stride over samples; grouped: chunks of the k-sorted
   // list, XCD x = blockIdx % 8 takes chunks [x, x+1) * nch / 8 in order
@@ -158,7 +173,7 @@ __global__ __launch_bounds__(256) void k_sample_dense(
     float v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      v[u] = a.B[(int64_t)smp[u].j * a.d + smp[u].kp];
+      v[u] = fourth_edge(a.B, a.bbits, binB, a.d, smp[u].j, smp[u].kp);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = base + (int64_t)u * nthreads;
@@ -280,6 +295,16 @@ __global__ __launch_bounds__(256) void k_sample_dense(
   }
 }
 
+// the fourth edge of a binary B from its bitmap (default), or from B
+// itself with MAD_BINARY_BITMAP=0 (for measurement; same results)
+static bool binary_bitmap_enabled() {
+  static const bool v = [] {
+    const char* e = getenv("MAD_BINARY_BITMAP");
+    return !(e && atoi(e) == 0);
+  }();
+  return v;
+}
+
 static DenseSampleArgs dense_args(const DenseTables& t, const float* B,
                                   uint64_t seed, uint64_t qid, int64_t l0,
                                   int64_t count) {
@@ -302,6 +327,8 @@ static DenseSampleArgs dense_args(const DenseTables& t, const float* B,
   a.gram = t.gram;
   a.pk2 = nullptr;
   a.pv2 = nullptr;
+  a.bbits = t.bbits;
+  a.bbin = t.bad && binary_bitmap_enabled() ? t.bad + 6 : nullptr;
   return a;
 }
 
@@ -784,10 +811,13 @@ __global__ __launch_bounds__(256) void k_pipe_edge(const PipeR2* in,
                                                    const float* B, int64_t d,
                                                    int64_t n, int gram,
                                                    const double* wtot,
+                                                   const uint32_t* bbits,
+                                                   const int* bbin,
                                                    uint64_t* pkeys,
                                                    float* pvals,
                                                    SampleCounters* ctr) {
   const bool live_w = wtot[0] > 0.0;
+  const bool binB = bbin && *bbin == 1;
   unsigned long long nclosed = 0;
   for (XcdWalk w(ntiles); w.t < w.t_hi; w.t += w.step) {
     const int64_t base = w.t * kPipeTile;
@@ -800,7 +830,7 @@ __global__ __launch_bounds__(256) void k_pipe_edge(const PipeR2* in,
     float v[kPipeU];
 #pragma unroll
     for (int u = 0; u < kPipeU; ++u)
-      v[u] = B[(int64_t)(r[u].js & kLow31) * d + r[u].kp];
+      v[u] = fourth_edge(B, bbits, binB, d, r[u].js & kLow31, r[u].kp);
 #pragma unroll
     for (int u = 0; u < kPipeU; ++u) {
       const int64_t e = base + u * 256 + threadIdx.x;
@@ -1026,8 +1056,8 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
           r2t, c, ps.gsh_j, Gj, L.cb, L.sb, r2s);
       // pass C: the pairs, in j-grouped order
       k_pipe_edge<<<grid, 256, 0, st>>>(r2s, c, nt, B, d, t.n, t.gram,
-                                        t.T0.tot, h.pkeys + c0, h.pvals + c0,
-                                        ctr);
+                                        t.T0.tot, a.bbits, a.bbin,
+                                        h.pkeys + c0, h.pvals + c0, ctr);
       if (groups && c == count && !t.gram) {
         k_pipe_starts64<<<(unsigned)((Gj + 256) / 256), 256, 0, st>>>(
             L.sb, Gj, c, L.starts64);

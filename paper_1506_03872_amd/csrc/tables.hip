@@ -1017,6 +1017,28 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
 // ---------------------------------------------------------------------------
 // dense plan tables
 // ---------------------------------------------------------------------------
+// Binary inputs (Alg. 1): bit w*32 + q of bits is 1 when entry w*32 + q of
+// B is 1; *flag = 0 when some entry is neither 0 nor 1 (the sampler then
+// reads B itself).  One 32-bit word per thread.
+__global__ __launch_bounds__(256) void k_binary_bitmap(const float* B,
+                                                       int64_t n,
+                                                       uint32_t* bits,
+                                                       int* flag) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e0 = w * 32;
+  if (e0 >= n) return;
+  uint32_t word = 0;
+  bool other = false;
+  const int cnt = n - e0 < 32 ? (int)(n - e0) : 32;
+  for (int q = 0; q < cnt; ++q) {
+    const float v = B[e0 + q];
+    word |= (uint32_t)(v == 1.0f) << q;
+    other |= v != 0.0f && v != 1.0f;
+  }
+  bits[w] = word;
+  if (other) *flag = 0;
+}
+
 // A == A^T for the squared variant (m x m): *flag = 1 on any difference.
 // One workgroup per 64 x 64 tile pair (tile (bx, by) with bx <= by and its
 // mirror), both staged in LDS so that every global read is coalesced.
@@ -1106,6 +1128,9 @@ hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,
     return e;
   if ((e = hipMalloc(&t.bmax, 256)) != hipSuccess) return e;
   if ((e = hipMalloc(&t.bad, 256)) != hipSuccess) return e;
+  if ((e = hipMalloc(&t.bbits, 4 * (size_t)((n * d + 31) / 32))) !=
+      hipSuccess)
+    return e;
   if ((e = hipStreamCreateWithFlags(&t.side, hipStreamNonBlocking)) !=
       hipSuccess)
     return e;
@@ -1123,6 +1148,8 @@ void dense_tables_free(DenseTables& t) {
   if (t.om) (void)hipFree(t.om);
   if (t.bmax) (void)hipFree(t.bmax);
   if (t.bad) (void)hipFree(t.bad);
+  if (t.bbits) (void)hipFree(t.bbits);
+  t.bbits = nullptr;
   if (t.fork) (void)hipEventDestroy(t.fork);
   if (t.join) (void)hipEventDestroy(t.join);
   if (t.side) (void)hipStreamDestroy(t.side);
@@ -1191,8 +1218,10 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
     FillBatch f{};
     f.p[0] = (uint64_t*)t.bmax;
     f.p[1] = (uint64_t*)t.bad;
-    f.n[0] = f.n[1] = 1;
-    f.count = 2;
+    f.p[2] = (uint64_t*)(t.bad + 6);  // B binary until an entry says not
+    f.n[0] = f.n[1] = f.n[2] = 1;
+    f.v[2] = 1;
+    f.count = 3;
     if ((e = launch_fill_multi(f, st)) != hipSuccess) return e;
   }
   if (check)
@@ -1231,6 +1260,11 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
     k_scan_inputs<<<grid_for(n * d, 1024 * 16) > 256 ? 256
                         : grid_for(n * d, 1024 * 16), 1024, 0, sd>>>(
         B, n * d, t.bmax, t.bad);
+    {
+      const int64_t words = (n * d + 31) / 32;
+      k_binary_bitmap<<<(unsigned)((words + 255) / 256), 256, 0, sd>>>(
+          B, n * d, t.bbits, t.bad + 6);
+    }
     e = t.T2.L <= 9
             ? small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,
                            t.T2.ent, sd)

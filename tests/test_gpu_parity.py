@@ -52,8 +52,20 @@ CASES = {
     "wide_d": lambda: workloads.dense_gaussian(300, 500, 600, seed=4),
     "zeros": lambda: _with_zeros(),
     "binary": lambda: workloads.binary(700, 900, 48, density=0.3, seed=5),
+    # binary B with a signed A: the fourth edge comes from B's bitmap
+    "binary_b": lambda: (workloads.dense_gaussian(800, 1, 40, seed=9)[0],
+                         workloads.binary(1, 1000, 40, density=0.25,
+                                          seed=9)[1]),
+    # one entry of 2 keeps B off the bitmap
+    "almost_binary": lambda: _almost_binary(),
     "tiny": lambda: workloads.tiny(3, 2, 1, seed=6),
 }
+
+
+def _almost_binary():
+    A, B = workloads.binary(600, 700, 33, density=0.3, seed=10)
+    B[17, 5] = 2.0
+    return A, B
 
 
 def _with_zeros():
