@@ -286,6 +286,49 @@ int mad_bruteforce_topk(const float* A, int64_t m, const float* B, int64_t n,
                         void* stream);
 
 /* ---------------------------------------------------------------------------
+ * mad_bruteforce_topk_csr -- exhaustive t-MAD (Definition 1) for sparse
+ * inputs, the exact baseline of Sec. 5.3 whose cost is the number of
+ * wedges (pairs of entries that share a coordinate).  The coordinates with
+ * the most wedges ("heavy", deg_A(k) deg_B(k) largest) are copied into
+ * dense columns and their part of every a_i . b_j goes through the matrix
+ * core brute force (certified filter, `precision` as in
+ * mad_bruteforce_topk); the wedges of the other coordinates are listed and
+ * summed per pair.  A lower bound on the t-th largest |c| (exact values of
+ * the heavy part's top candidates) prunes both parts, and the union of
+ * their candidates is re-ranked with fp32 sparse dot products: the result
+ * is the top t by |c| of the pairs with c != 0 (ties by (i, j) ascending),
+ * as for mad_plan_topk, x = 0.
+ *   CSR arrays as for mad_plan_create_csr (device; validated, MAD_EINVAL
+ *   when malformed or non-finite).  heavy: number of heavy coordinates, 0
+ *   to take the fewest (a multiple of 64) that leave at most 2^30 light
+ *   wedges; MAD_EUNSUPPORTED when that needs more than 4096.
+ *   out, n_out (device) as for mad_plan_topk; stats (host, optional).
+ * Memory: dense copies of 4 (m + n) H bytes and about 40 bytes per light
+ * wedge.  Synchronises; keeps a process-wide workspace between calls.
+ * ------------------------------------------------------------------------- */
+typedef struct mad_bf_csr_stats {
+  double ms_split;          /* degrees, split, dense copies, light lists   */
+  double ms_heavy;          /* brute force of the heavy part, its bound    */
+  double ms_light;          /* light wedges summed per pair, pruning       */
+  double ms_final;          /* union of the candidates, exact re-rank      */
+  int64_t heavy;            /* heavy coordinates                            */
+  int64_t wedges;           /* sum over k of deg_A(k) deg_B(k)              */
+  int64_t light_wedges;     /* wedges at light coordinates (listed)         */
+  int64_t heavy_candidates; /* pairs kept by the heavy part's filter        */
+  int64_t light_candidates; /* pairs sharing a light coordinate kept        */
+  int64_t candidates;       /* distinct pairs re-ranked                     */
+  float tau;                /* the lower bound used for the t-th |c|        */
+} mad_bf_csr_stats;
+
+int mad_bruteforce_topk_csr(const int64_t* a_ptr, const int32_t* a_idx,
+                            const float* a_val, int64_t m,
+                            const int64_t* b_ptr, const int32_t* b_idx,
+                            const float* b_val, int64_t n, int64_t d,
+                            int precision, int64_t t, int64_t heavy,
+                            mad_pair* out, int64_t* n_out,
+                            mad_bf_csr_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------------
  * mad_probe_memory -- measurement kernels for the memory ceilings the
  * sampler works against (used by the benchmark's roofline).  buf (device)
  * holds nwords 64-bit words, nwords a power of two; nops operations at

@@ -393,6 +393,23 @@ def exact_topk(A: np.ndarray, B: np.ndarray, t: int, block: int = 4096):
     return best_k, best_c
 
 
+def exact_topk_sparse(a, b, m: int, n: int, d: int, t: int):
+    """t-MAD of sparse inputs (Definition 1) restricted to the pairs with
+    c != 0: C = A B^T as a sparse FP64 product (scipy), then the top t by
+    |c| descending, key i*n + j ascending.  a, b = (ptr, idx, val)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(a[2], np.float64), np.asarray(a[1]),
+                       np.asarray(a[0])), shape=(m, d))
+    B = sp.csr_matrix((np.asarray(b[2], np.float64), np.asarray(b[1]),
+                       np.asarray(b[0])), shape=(n, d))
+    Cm = (A @ B.T).tocoo()
+    keep = Cm.data != 0
+    keys = Cm.row[keep].astype(np.int64) * n + Cm.col[keep].astype(np.int64)
+    c = Cm.data[keep]
+    order = np.lexsort((keys, -np.abs(c)))[:t]
+    return keys[order], c[order]
+
+
 def threshold_recall(found_keys, A, B, exact_c, t: int) -> float:
     """Recall by threshold: the fraction of t whose exact |c| reaches the
     exact t-th largest |c| (every correct answer under ties scores 1)."""

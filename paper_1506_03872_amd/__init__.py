@@ -35,6 +35,7 @@ EXPORTS = (
     "mips_debug_scores", "mad_plan_set_verify_precision",
     "mad_plan_verify_stats", "mad_debug_accumulate", "mad_plan_set_option",
     "mad_plan_get_option", "mad_accumulate_noalloc",
+    "mad_bruteforce_topk_csr",
 )
 
 
@@ -86,6 +87,9 @@ def lib():
         L.mad_plan_verify_stats.argtypes = [_P, _P, _P]
         L.mad_accumulate_noalloc.argtypes = [_P, _P, _i64, C.c_int, _P, _P,
                                              _P, _P]
+        L.mad_bruteforce_topk_csr.argtypes = [_P, _P, _P, _i64, _P, _P, _P,
+                                              _i64, _i64, C.c_int, _i64,
+                                              _i64, _P, _P, _P, _P]
         L.mad_plan_set_option.argtypes = [_P, C.c_int, _i64]
         L.mad_plan_get_option.argtypes = [_P, C.c_int, _P]
         L.mips_plan_create.argtypes = [_P, _i64, _i64, _u32, _P,
@@ -457,6 +461,37 @@ def bruteforce_topk(A, B, t, precision=MAD_FP32, t_screen=0, stream=None):
         precision, t, t_screen, C.c_void_p(out.data_ptr()),
         C.c_void_p(n_out.data_ptr()), C.byref(st), _stream(stream)))
     stats = {f: getattr(st, f) for f, _ in BfStats._fields_}
+    return unpack_pairs(out, int(n_out.item())), stats
+
+
+class BfCsrStats(C.Structure):
+    _fields_ = [("ms_split", C.c_double), ("ms_heavy", C.c_double),
+                ("ms_light", C.c_double), ("ms_final", C.c_double),
+                ("heavy", C.c_int64), ("wedges", C.c_int64),
+                ("light_wedges", C.c_int64),
+                ("heavy_candidates", C.c_int64),
+                ("light_candidates", C.c_int64), ("candidates", C.c_int64),
+                ("tau", C.c_float)]
+
+
+def bruteforce_topk_csr(a, b, m, n, d, t, precision=MAD_FP32, heavy=0,
+                        stream=None):
+    """Exhaustive top-t by |a_i . b_j| of sparse inputs (synchronises): a, b
+    are (ptr int64, idx int32, val fp32) CUDA tensors of the compressed
+    rows.  Returns (dict of i, j, c, x, stats dict)."""
+    import torch
+    (ap, ai, av), (bp, bi, bv) = a, b
+    out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = BfCsrStats()
+    _check(lib().mad_bruteforce_topk_csr(
+        _dev(ap, torch.int64, "a_ptr"), _dev_opt(ai, torch.int32, "a_idx"),
+        _dev_opt(av, torch.float32, "a_val"), m,
+        _dev(bp, torch.int64, "b_ptr"), _dev_opt(bi, torch.int32, "b_idx"),
+        _dev_opt(bv, torch.float32, "b_val"), n, d, precision, t, heavy,
+        C.c_void_p(out.data_ptr()), C.c_void_p(n_out.data_ptr()),
+        C.byref(st), _stream(stream)))
+    stats = {f: getattr(st, f) for f, _ in BfCsrStats._fields_}
     return unpack_pairs(out, int(n_out.item())), stats
 
 

@@ -551,6 +551,16 @@ hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,
                            int64_t n, int64_t d, int prec, int64_t t,
                            int64_t cap_hint, void* out, int64_t* n_out,
                            BfStats* stats, hipStream_t st) {
+  return bruteforce_run(A, m, B, n, d, prec, t, cap_hint, -1.0f, out, n_out,
+                        nullptr, nullptr, stats, st);
+}
+
+hipError_t bruteforce_run(const float* A, int64_t m, const float* B,
+                          int64_t n, int64_t d, int prec, int64_t t,
+                          int64_t cap_hint, float tau_user, void* out,
+                          int64_t* n_out, const uint64_t** cand_keys,
+                          int64_t* cand_count, BfStats* stats,
+                          hipStream_t st) {
   hipError_t e;
   int KC = prec == kF32 ? 32 : prec == kBF16 ? 64 : 128;
   int EB = prec == kF32 ? 4 : prec == kBF16 ? 2 : 1;
@@ -619,13 +629,23 @@ hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,
   a.ckey = nullptr;
   a.ccap = 0;
   a.ccount = ccount;
-  if (prec == kF32) launch_gemm<kF32>(a, true, st);
-  else if (prec == kBF16) launch_gemm<kBF16>(a, true, st);
-  else launch_gemm<kFP8>(a, true, st);
-  // pass A's subset holds about 1/stride of the pairs
-  const int64_t target =
-      screen ? (cap_hint + stride - 1) / stride : t;
-  k_bf_tau<<<1, 64, 0, st>>>(hist, target, tau_bits);
+  if (tau_user >= 0.0f) {
+    // a threshold given by the caller (a lower bound it knows for the t-th
+    // largest |c|): pass B keeps every pair that may reach it
+    uint32_t tb;
+    memcpy(&tb, &tau_user, 4);
+    if ((e = launch_fill_u64((uint64_t*)tau_bits, 1, (uint64_t)tb, st)) !=
+        hipSuccess)
+      return e;
+  } else {
+    if (prec == kF32) launch_gemm<kF32>(a, true, st);
+    else if (prec == kBF16) launch_gemm<kBF16>(a, true, st);
+    else launch_gemm<kFP8>(a, true, st);
+    // pass A's subset holds about 1/stride of the pairs
+    const int64_t target =
+        screen ? (cap_hint + stride - 1) / stride : t;
+    k_bf_tau<<<1, 64, 0, st>>>(hist, target, tau_bits);
+  }
   (void)hipEventRecord(ev[1], st);
   // the largest margin over all pairs, for pass B's pre-test
   {
@@ -673,6 +693,8 @@ hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,
   (void)hipEventRecord(ev[2], st);
   int64_t nre = (int64_t)count;
   const uint64_t* rkeys = (const uint64_t*)w.keys.p;
+  if (cand_keys) *cand_keys = rkeys;
+  if (cand_count) *cand_count = nre;
   if (e == hipSuccess && screen && nre > cap_hint) {
     // the t_screen survivors with the largest computed |c|
     if ((e = dev_alloc(w.sel, (size_t)cap_hint * 8)) == hipSuccess)
@@ -682,10 +704,10 @@ hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,
     rkeys = (const uint64_t*)w.sel.p;
     nre = cap_hint;
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && out) {
     // final: fp32 re-rank and the exact top t of the re-ranked pairs
     e = launch_rerank_topk(rkeys, nre, A, B, n, d, t < nre ? t : nre, w.fin,
-                           out, n_out, st);
+                           out, n_out, nullptr, st);
   }
   (void)hipEventRecord(ev[3], st);
   if (e == hipSuccess) e = hipEventSynchronize(ev[3]);

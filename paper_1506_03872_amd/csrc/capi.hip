@@ -1059,6 +1059,67 @@ int mad_bruteforce_topk(const float* A, int64_t m, const float* B, int64_t n,
   return MAD_OK;
 }
 
+int mad_bruteforce_topk_csr(const int64_t* a_ptr, const int32_t* a_idx,
+                            const float* a_val, int64_t m,
+                            const int64_t* b_ptr, const int32_t* b_idx,
+                            const float* b_val, int64_t n, int64_t d,
+                            int precision, int64_t t, int64_t heavy,
+                            mad_pair* out, int64_t* n_out,
+                            mad_bf_csr_stats* stats, void* stream) {
+  g_err.clear();
+  if (m < 1 || n < 1 || d < 1 || m >= (int64_t(1) << 31) ||
+      n >= (int64_t(1) << 31) || d >= (int64_t(1) << 31))
+    return fail(MAD_EINVAL, "need 1 <= m, n, d < 2^31");
+  if (t < 1 || (double)t > (double)m * (double)n)
+    return fail(MAD_EINVAL, "need 1 <= t <= m*n");
+  if (heavy < 0) return fail(MAD_EINVAL, "heavy must be >= 0");
+  if (precision != MAD_FP32 && precision != MAD_BF16 &&
+      precision != MAD_FP8_E4M3)
+    return fail(MAD_EINVAL, "unknown precision %d", precision);
+  if (!out || !n_out) return fail(MAD_EINVAL, "out and n_out are required");
+  if (!is_device_ptr(a_ptr) || !is_device_ptr(b_ptr))
+    return fail(MAD_EINVAL, "CSR pointer arrays must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t nnzA = 0, nnzB = 0;
+  HIP_TRY(hipMemcpy(&nnzA, a_ptr + m, 8, hipMemcpyDeviceToHost), "reading nnz");
+  HIP_TRY(hipMemcpy(&nnzB, b_ptr + n, 8, hipMemcpyDeviceToHost), "reading nnz");
+  if (nnzA < 0 || nnzB < 0 || nnzA >= (int64_t(1) << 31) ||
+      nnzB >= (int64_t(1) << 31))
+    return fail(MAD_EINVAL, "need 0 <= nnz < 2^31 (a_ptr[m], b_ptr[n])");
+  if ((nnzA && (!is_device_ptr(a_idx) || !is_device_ptr(a_val))) ||
+      (nnzB && (!is_device_ptr(b_idx) || !is_device_ptr(b_val))))
+    return fail(MAD_EINVAL, "CSR arrays must be device pointers");
+  const mad::CsrView in{a_ptr, a_idx, a_val, b_ptr, b_idx, b_val};
+  static mad::DeviceBuffer flag;
+  HIP_TRY(mad::dev_alloc(flag, 256), "brute force");
+  hipError_t e = mad::csr_validate(in, m, n, d, nnzA, nnzB, (int*)flag.p, st);
+  if (e == hipErrorInvalidValue)
+    return fail(MAD_EINVAL, "malformed CSR input or non-finite values");
+  if (e != hipSuccess) return hip_fail(e, "brute force");
+  mad::BfCsrStats bs;
+  memset(&bs, 0, sizeof bs);
+  e = mad::bruteforce_topk_csr(in, m, n, d, nnzA, nnzB, precision, t, heavy,
+                               out, n_out, &bs, st);
+  if (e == hipErrorNotSupported)
+    return fail(MAD_EUNSUPPORTED, "the split would need more than 4096 heavy "
+                "coordinates or 2^30 light wedges");
+  if (e != hipSuccess) return hip_fail(e, "sparse brute force");
+  if (stats) {
+    stats->ms_split = bs.ms_split;
+    stats->ms_heavy = bs.ms_heavy;
+    stats->ms_light = bs.ms_light;
+    stats->ms_final = bs.ms_final;
+    stats->heavy = bs.heavy;
+    stats->wedges = bs.wedges;
+    stats->light_wedges = bs.light_wedges;
+    stats->heavy_candidates = bs.heavy_candidates;
+    stats->light_candidates = bs.light_candidates;
+    stats->candidates = bs.candidates;
+    stats->tau = bs.tau;
+  }
+  return MAD_OK;
+}
+
 int mad_plan_create_csr(const int64_t* a_ptr, const int32_t* a_idx,
                         const float* a_val, int64_t m, const int64_t* b_ptr,
                         const int32_t* b_idx, const float* b_val, int64_t n,

@@ -1528,6 +1528,23 @@ hipError_t launch_check_csr_symmetric(const CsrTables& t, int* flag,
   return hipGetLastError();
 }
 
+hipError_t csr_validate(const CsrView& in, int64_t m, int64_t n, int64_t d,
+                        int64_t nnzA, int64_t nnzB, int* flag,
+                        hipStream_t st) {
+  hipError_t e = launch_fill_u64((uint64_t*)flag, 1, 0ull, st);
+  if (e != hipSuccess) return e;
+  k_csr_check<<<blocks_of(m, 256), 256, 0, st>>>(in.a_ptr, in.a_idx, in.a_val,
+                                                  m, d, nnzA, nullptr, flag);
+  k_csr_check<<<blocks_of(n, 256), 256, 0, st>>>(in.b_ptr, in.b_idx, in.b_val,
+                                                  n, d, nnzB, nullptr, flag);
+  int bad = 0;
+  if ((e = hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  return bad ? hipErrorInvalidValue : hipSuccess;
+}
+
 static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
                               int64_t l0, int64_t count) {
   CsrSampleArgs a;

@@ -248,6 +248,11 @@ struct CsrTables {
 // sparse tables is planned on the host).  Returns hipErrorInvalidValue when
 // the inputs are malformed or hold NaN/Inf, with t.bad set.
 hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st);
+// structure and finiteness of sparse inputs (flag: device, 8-byte aligned
+// scratch); hipErrorInvalidValue when malformed or non-finite.  Synchronises.
+hipError_t csr_validate(const CsrView& in, int64_t m, int64_t n, int64_t d,
+                        int64_t nnzA, int64_t nnzB, int* flag,
+                        hipStream_t st);
 // *flag (device, 8-byte aligned) = 1 unless A's compressed rows equal its
 // transpose (A == A^T); after csr_tables_build
 hipError_t launch_check_csr_symmetric(const CsrTables& t, int* flag,
@@ -454,10 +459,13 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
 
 // fp32 re-rank of candidate keys (count known on the host) and the exact
 // top t by |c| into mad_pair records; buf is grown as needed
+// (csr: sparse inputs, the dot products then come from their compressed
+// rows and A, B, d are unused)
 hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
                               const float* A, const float* B, int64_t n,
                               int64_t d, int64_t t, DeviceBuffer& buf,
-                              void* out, int64_t* n_out, hipStream_t st);
+                              void* out, int64_t* n_out, const CsrView* csr,
+                              hipStream_t st);
 
 // the k keys with the largest |v| (ties by key ascending) into out_keys
 // (device, capacity k), unordered; count known on the host
@@ -481,5 +489,34 @@ hipError_t bruteforce_topk(const float* A, int64_t m, const float* B,
                            int64_t n, int64_t d, int prec, int64_t t,
                            int64_t cap_hint, void* out, int64_t* n_out,
                            BfStats* stats, hipStream_t st);
+// the same with the pass-B threshold given (tau_user >= 0, pass A skipped)
+// and the survivors of pass B returned (device keys i*n + j in a
+// process-wide buffer valid until the next call, and their count); out may
+// be null to skip the final selection
+hipError_t bruteforce_run(const float* A, int64_t m, const float* B,
+                          int64_t n, int64_t d, int prec, int64_t t,
+                          int64_t cap_hint, float tau_user, void* out,
+                          int64_t* n_out, const uint64_t** cand_keys,
+                          int64_t* cand_count, BfStats* stats,
+                          hipStream_t st);
+
+// ---- exact_csr.hip ----------------------------------------------------
+// exhaustive t-MAD of sparse inputs: the coordinates with the most wedges
+// through the brute force (dense copies of their columns), the others'
+// wedges listed and summed per pair; exact top t of the union of both
+// parts' candidates (sparse dot products).  heavy_req > 0 fixes the number
+// of heavy coordinates.  hipErrorNotSupported when more than 4096 heavy
+// coordinates or 2^30 light wedges would be needed.  Synchronises.
+struct BfCsrStats {
+  double ms_split, ms_heavy, ms_light, ms_final;
+  int64_t heavy, wedges, light_wedges;
+  int64_t heavy_candidates, light_candidates, candidates;
+  float tau;
+};
+hipError_t bruteforce_topk_csr(const CsrView& in, int64_t m, int64_t n,
+                               int64_t d, int64_t nnzA, int64_t nnzB,
+                               int prec, int64_t t, int64_t heavy_req,
+                               void* out, int64_t* n_out, BfCsrStats* stats,
+                               hipStream_t st);
 
 }  // namespace mad

@@ -1107,7 +1107,8 @@ hipError_t launch_select_keys_by_absval(const uint64_t* keys, const float* v,
 hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
                               const float* A, const float* B, int64_t n,
                               int64_t d, int64_t t, DeviceBuffer& buf,
-                              void* out, int64_t* n_out, hipStream_t st) {
+                              void* out, int64_t* n_out, const CsrView* csr,
+                              hipStream_t st) {
   // layout: counts, Coarse, hist, x2 (zeros), c, |c| bits, final + boundary
   const int64_t cnt = count > 1 ? count : 1;
   const size_t need = 256 + 256 + kBins * 4 + (size_t)cnt * (8 + 4 + 8) +
@@ -1130,8 +1131,12 @@ hipError_t launch_rerank_topk(const uint64_t* keys, int64_t count,
   // the candidate count goes where the verification kernel reads it
   e = launch_fill_u64((uint64_t*)&counts[kCntCand], 1, (uint64_t)count, st);
   if (e != hipSuccess) return e;
-  k_verify<<<blocks_for(cnt * 16, 256, 2048), 256, 0, st>>>(
-      keys, counts, A, B, n, d, cnt, c, absbits, hist);
+  if (csr)
+    k_verify_csr<<<blocks_for(cnt * 64, 256, 2048), 256, 0, st>>>(
+        keys, counts, *csr, n, cnt, c, absbits, hist);
+  else
+    k_verify<<<blocks_for(cnt * 16, 256, 2048), 256, 0, st>>>(
+        keys, counts, A, B, n, d, cnt, c, absbits, hist);
   k_coarse_decide<<<1, 256, 0, st>>>(hist, &counts[kCntCand], t, cz,
                                      nullptr);
   uint64_t* fp = key;

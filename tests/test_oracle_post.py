@@ -136,3 +136,18 @@ def test_scores_merged_from_sample_ranges_and_post():
     post = p.post(mk[::-1].copy(), mx[::-1].copy(), tp, t)  # any order
     for k in ("tp_key", "tp_x", "tp_c", "key", "x", "c", "n_pos"):
         assert np.array_equal(post[k], full[k]), k
+
+
+def test_sparse_exact_topk_equals_dense_definition():
+    # the sparse product of the oracle against the plain dense definition
+    # on the same (densified) inputs, pairs with c != 0
+    a, b, m, n, d = workloads.ragged_csr(70, 90, 30, seed=12, density=0.15)
+    A = workloads.csr_to_dense(*a, m, d)
+    B = workloads.csr_to_dense(*b, n, d)
+    ks, cs = oracle.exact_topk_sparse(a, b, m, n, d, 40)
+    kd, cd = oracle.bruteforce_dense(A, B, 40)
+    nz = cd != 0
+    assert np.array_equal(ks, kd[nz][:len(ks)])
+    assert np.allclose(cs, cd[nz][:len(ks)], rtol=1e-13, atol=0)
+    assert len(ks) == min(40, int(np.count_nonzero(
+        A.astype(np.float64) @ B.astype(np.float64).T)))
