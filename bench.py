@@ -57,6 +57,8 @@ def parse():
                     help="sparse configs: every stored value 1 (0/1 inputs)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the time-to-recall sweep")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="leave the sparse C3 summary out of the dense line")
     ap.add_argument("--binary", type=float, default=0.0,
                     help="dense configs: 0/1 inputs of the same shape with "
                          "this density (the binary inputs of Alg. 1)")
@@ -471,106 +473,124 @@ def bench_csr(args, cfg, data, mad):
     }
     plan.close()
     if not args.no_recall:
-        line["recall_reduced_size"] = csr_recall(args, cfg, mad)
+        line["recall"] = csr_recall(args, cfg, mad, a, b, m, n)
     print(json.dumps(line))
 
 
-def csr_recall(args, cfg, mad, scale=0.02):
-    """Threshold-recall@t of the sparse path on the same distributions at
-    2% of the vector counts (d unchanged), where the exact top t is one FP64
-    GEMM of the densified inputs on the GPU: s on a x sqrt(10) grid, mean
-    recall over seeds 0..4 and the median top-k time, with the MFMA brute
-    force on the densified inputs for comparison."""
+def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
+    """Threshold-recall@t of the sparse path at the full size against the
+    exact sparse brute force (mad_bruteforce_topk_csr, bf16 certified
+    filter, median of 3 runs): s on a x sqrt(10) grid, mean recall over
+    seeds 0..4 and the median time of those top-k calls; time-to-recall
+    end to end (plan build + top-k) and amortized (top-k only)."""
     import numpy as np
     import torch
-    import workloads
-    _, data = workloads.make(args.config, seed=args.seed, scale=scale)
-    a, b, m, n = data["a"], data["b"], data["m"], data["n"]
-    d, t = cfg["d"], cfg["t"]
-    log("sparse recall at m = n = %d: exact top-%d" % (m, t))
-
-    def dense64(x, rows):
-        ptr, idx, val = x
-        M = torch.zeros((rows, d), dtype=torch.float64, device="cuda")
-        r = torch.repeat_interleave(torch.arange(rows, device="cuda"),
-                                    torch.from_numpy(np.diff(ptr)).cuda())
-        M[r, torch.from_numpy(idx.astype(np.int64)).cuda()] = \
-            torch.from_numpy(val).cuda().double()
-        return M
-
-    Ad, Bd = dense64(a, m), dense64(b, n)
-    Cm = (Ad @ Bd.t()).abs_().flatten()
-    tau = float(torch.topk(Cm, t).values[-1])
-    del Cm
-    # the library's MFMA brute force on the densified inputs, for the
-    # time-to-recall comparison (median of 3)
-    A32, B32 = Ad.float(), Bd.float()
-    del Ad, Bd
-    torch.cuda.empty_cache()
-    bf = {}
-    for name, prec, ts in (("fp32", mad.MAD_FP32, 0),
-                           ("bf16_screen", mad.MAD_BF16, 20 * t)):
-        times = []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            mad.bruteforce_topk(A32, B32, t, precision=prec, t_screen=ts)
-            torch.cuda.synchronize()
-            times.append((time.perf_counter() - t0) * 1e3)
-        bf[name] = round(float(np.median(times)), 3)
-        log("sparse reduced brute force %s: %.2f ms" % (name, bf[name]))
-    del A32, B32
-    torch.cuda.empty_cache()
-
-    def c_exact(i, j):
-        ap, ai, av = a
-        bp, bi, bv = b
-        out = np.empty(len(i))
-        for q, (x, y) in enumerate(zip(i.tolist(), j.tolist())):
-            ia, va = ai[ap[x]:ap[x + 1]], av[ap[x]:ap[x + 1]]
-            ib, vb = bi[bp[y]:bp[y + 1]], bv[bp[y]:bp[y + 1]]
-            _, xa, xb = np.intersect1d(ia, ib, return_indices=True)
-            out[q] = float(np.dot(va[xa].astype(np.float64),
-                                  vb[xb].astype(np.float64)))
-        return out
-
+    d, t, tp = cfg["d"], cfg["t"], cfg["t_prime"]
     ta = tuple(torch.from_numpy(x).cuda() for x in a)
     tb = tuple(torch.from_numpy(x).cuda() for x in b)
+    times, res, st = [], None, None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, st = mad.bruteforce_topk_csr(ta, tb, m, n, d, t,
+                                          precision=mad.MAD_BF16)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    bf_ms = float(np.median(times))
+    if len(res["c"]) < t:
+        raise SystemExit("the exact sparse result has fewer than t pairs")
+    tau = float(np.abs(res["c"].cpu().numpy()).min())
+    log("sparse exact top-%d: %.1f ms (heavy %d, light wedges %d), tau %.2f"
+        % (t, bf_ms, st["heavy"], st["light_wedges"], tau))
+    own = plan is None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = mad.Plan.csr(ta, tb, m, n, d)
+    if own:
+        plan = mad.Plan.csr(ta, tb, m, n, d, flags=mad.MAD_FLAG_NO_CHECK)
+    plan.refresh()
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    res = []
-    for s in (10 ** 5, 316_228, 10 ** 6, 3_162_278, 10 ** 7, 31_622_777,
-              10 ** 8):
-        # mean recall over seeds 0..4, median time of those 5 top-k calls
-        plan.topk(t=t, s=s, t_prime=cfg["t_prime"], seed=0)
-        recs, times = [], []
+    sweep, hit = [], None
+    for s in (10 ** 6, 3_162_278, 10 ** 7, 31_622_777, 10 ** 8, 316_227_766,
+              10 ** 9):
+        plan.topk(t=t, s=s, t_prime=tp, seed=0)
+        recs, tms = [], []
         for seed in range(5):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = plan.topk(t=t, s=s, t_prime=cfg["t_prime"], seed=seed)
+            r = plan.topk(t=t, s=s, t_prime=tp, seed=seed)
             torch.cuda.synchronize()
-            times.append((time.perf_counter() - t0) * 1e3)
-            i_arr, j_arr = r["i"].cpu().numpy(), r["j"].cpu().numpy()
-            c64 = c_exact(i_arr, j_arr)
-            recs.append(float(np.count_nonzero(np.abs(c64) >= tau)) / t)
-        rec, ms = float(np.mean(recs)), float(np.median(times))
-        res.append({"s": s, "recall_at_t": round(rec, 4),
-                    "ms_topk": round(ms, 3)})
-        log("sparse recall s=%d: %.3f (%.2f ms)" % (s, rec, ms))
-    plan.close()
-    hit = next((p for p in res if p["recall_at_t"] >= 0.95), None)
-    return {"m": m, "n": n, "d": d, "t": t, "t_prime": cfg["t_prime"],
-            "tau": tau, "seeds": [0, 1, 2, 3, 4],
+            tms.append((time.perf_counter() - t0) * 1e3)
+            # the returned c are fp32 sparse dot products, as the
+            # brute force's: recall by threshold on them
+            recs.append(float(np.count_nonzero(
+                np.abs(r["c"].cpu().numpy()) >= tau)) / t)
+        pt = {"s": s, "recall_at_t": round(float(np.mean(recs)), 4),
+              "ms_topk": round(float(np.median(tms)), 3)}
+        sweep.append(pt)
+        log("sparse recall s=%d: %.3f (%.2f ms)" % (s, pt["recall_at_t"],
+                                                   pt["ms_topk"]))
+        if pt["recall_at_t"] >= 0.95:
+            hit = pt
+            break
+    if own:
+        plan.close()
+    return {"m": m, "n": n, "d": d, "t": t, "t_prime": tp, "tau": tau,
+            "seeds": [0, 1, 2, 3, 4],
+            "exact": "mad_bruteforce_topk_csr (heavy coordinates through "
+                     "the bf16 certified MFMA brute force, light wedges "
+                     "listed), median of 3",
+            "exact_bruteforce_ms": round(bf_ms, 1),
+            "exact_stats": {k: (round(v, 3) if isinstance(v, float) else v)
+                            for k, v in st.items()},
             "plan_build_ms": round(build_ms, 2),
             "time_to_recall_0.95": None if hit is None else {
                 "s": hit["s"], "ms_topk": hit["ms_topk"],
-                "ms_end_to_end": round(build_ms + hit["ms_topk"], 3)},
-            "bruteforce_densified_ms": bf,
-            "exact": "FP64 GEMM of the densified inputs (GPU)",
-            "sweep": res}
+                "ms_end_to_end": round(build_ms + hit["ms_topk"], 3),
+                "speedup_vs_exact_end_to_end": round(
+                    bf_ms / (build_ms + hit["ms_topk"]), 1)},
+            "sweep": sweep}
+
+
+def sparse_summary(args, mad):
+    """The sparse workload (C3 at full size) inside the default line: one
+    timed whole step at its s, and recall / time-to-recall against the
+    exact sparse brute force."""
+    import numpy as np
+    import torch
+    import workloads
+    log("generating C3 (sparse)")
+    cfg, data = workloads.make("C3", seed=args.seed)
+    a, b, m, n = data["a"], data["b"], data["m"], data["n"]
+    d, s, tp, t = cfg["d"], cfg["s"], cfg["t_prime"], cfg["t"]
+    ta = tuple(torch.from_numpy(x).cuda() for x in a)
+    tb = tuple(torch.from_numpy(x).cuda() for x in b)
+    plan = mad.Plan.csr(ta, tb, m, n, d)
+    plan.close()
+    plan = mad.Plan.csr(ta, tb, m, n, d, flags=mad.MAD_FLAG_NO_CHECK)
+    out = torch.empty((t, 3), dtype=torch.int64, device="cuda")
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def step():
+        plan.refresh()
+        plan.topk_raw(t, s, tp, args.seed, out, n_out)
+
+    step()
+    torch.cuda.synchronize()
+    steps = 5
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    log("sparse C3 step %.2f ms" % ms)
+    rec = csr_recall(args, cfg, mad, a, b, m, n, plan=plan)
+    plan.close()
+    return {"workload": "powerlaw_csr_C3", "m": m, "n": n, "d": d,
+            "nnz_per_vector": cfg["nnz"], "s": s, "t_prime": tp, "t": t,
+            "ms_per_step": round(ms, 3),
+            "samples_per_s": round(s / (ms * 1e-3), 1),
+            "recall": rec}
 
 
 def main():
@@ -713,7 +733,8 @@ def main():
             extra["planted_found"] = len(pk & set(keys.tolist()))
             extra["planted_total"] = len(pk)
         extra["verify_precision"] = verify_precisions(
-            args, mad, plan, step, out, n_out, recall_of, c_error)
+            args, mad, plan, step, out, n_out, recall_of, c_error, A_h, B_h,
+            tp)
         extra["bruteforce"] = bruteforce_report(mad, A, B, t, recall_of,
                                                 c_error)
         if not args.no_sweep:
@@ -724,6 +745,10 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         base, _ = cpu_baseline(A_h, B_h, cfg, args)
+    if not args.no_recall and not args.no_sparse and not args.binary:
+        del A, B
+        torch.cuda.empty_cache()
+        extra["sparse_C3"] = sparse_summary(args, mad)
 
     line = {
         "metric": "diamond samples/s + time-to-recall@0.95 vs MFMA brute "
@@ -769,7 +794,7 @@ def main():
 
 
 def verify_precisions(args, mad, plan, step, out, n_out, recall_of,
-                      c_error):
+                      c_error, A_h, B_h, tp):
     """Whole steps under each verification precision of Alg. 2 (fp32 rows
     for every candidate, or bf16 / fp8 screening with error bounds first):
     ms per step, candidates re-ranked in fp32, and whether the top-t is the
@@ -801,10 +826,37 @@ def verify_precisions(args, mad, plan, step, out, n_out, recall_of,
                      "max_rel_err_c_vs_fp64": c_error(
                          i_arr, j_arr, r["c"].cpu().numpy()),
                      "same_top_t_as_fp32": bool(np.array_equal(got, ref))}
+        if prec != mad.MAD_FP32:
+            res[name]["screen"] = screen_error(plan, A_h, B_h, [tp])
         log("verify %s: %.2f ms, %d of %d candidates re-ranked in fp32" %
             (name, ms, vs["n_reranked"], vs["n_cand"]))
     plan.set_verify_precision(mad.MAD_FP32)
     return res
+
+
+def screen_error(plan, A_h, B_h, plan_tp):
+    """The low-precision screen values c^ of the last call's candidates
+    against FP64, next to their a-priori bounds (margin >= |c^ - c_fp32|,
+    and |c_fp32 - c| is far smaller)."""
+    import numpy as np
+    import torch
+    xk, xx, _ = plan.scores()            # Omega_t': the top t' of X
+    pos = xx > 0
+    keys = xk[pos][np.lexsort((xk[pos], -xx[pos]))][:plan_tp[0]]
+    n = B_h.shape[0]
+    ch, mg = plan.lowp_screen(torch.from_numpy(keys).cuda())
+    i, j = keys // n, keys % n
+    c64 = (A_h[i].astype(np.float64) * B_h[j].astype(np.float64)).sum(1)
+    err = np.abs(ch.astype(np.float64) - c64)
+    ratio = err / np.maximum(mg.astype(np.float64), 1e-300)
+    return {"pairs": int(len(keys)),
+            "max_abs_err_vs_fp64": float(err.max()) if len(err) else None,
+            "max_rel_err_vs_fp64": float((err / np.abs(c64)).max())
+            if len(err) else None,
+            "median_bound": float(np.median(mg)) if len(mg) else None,
+            "max_err_over_bound": float(ratio.max()) if len(err) else None,
+            "median_err_over_bound": float(np.median(ratio))
+            if len(err) else None}
 
 
 def bruteforce_report(mad, A, B, t, recall_of, c_error):

@@ -485,6 +485,14 @@ int mad_debug_scores(mad_plan* plan, int64_t* keys, int64_t* xfix,
 int mad_debug_candidates(mad_plan* plan, int64_t* keys, int64_t* xfix,
                          float* c, int64_t cap, int64_t* n);
 
+/* Low-precision screen of pairs (measurement of the verification filter of
+ * mad_plan_set_verify_precision): for each key i*n + j (device int64),
+ * chat = the bf16 / fp8 value c^ of a_i . b_j and margin = its a-priori
+ * bound on |c^ - c_fp32| (device fp32 arrays of count).  Needs a dense
+ * plan with MAD_BF16 or MAD_FP8_E4M3 verification.  Enqueued on stream. */
+int mad_debug_lowp_screen(mad_plan* plan, const int64_t* keys, int64_t count,
+                          float* chat, float* margin, void* stream);
+
 /* Fixed-point exponent F the plan uses for s samples (host). */
 int mad_fix_exponent(mad_plan* plan, int64_t s, int* F);
 

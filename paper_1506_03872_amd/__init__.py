@@ -35,7 +35,7 @@ EXPORTS = (
     "mips_debug_scores", "mad_plan_set_verify_precision",
     "mad_plan_verify_stats", "mad_debug_accumulate", "mad_plan_set_option",
     "mad_plan_get_option", "mad_accumulate_noalloc",
-    "mad_bruteforce_topk_csr",
+    "mad_bruteforce_topk_csr", "mad_debug_lowp_screen",
 )
 
 
@@ -90,6 +90,7 @@ def lib():
         L.mad_bruteforce_topk_csr.argtypes = [_P, _P, _P, _i64, _P, _P, _P,
                                               _i64, _i64, C.c_int, _i64,
                                               _i64, _P, _P, _P, _P]
+        L.mad_debug_lowp_screen.argtypes = [_P, _P, _i64, _P, _P, _P]
         L.mad_plan_set_option.argtypes = [_P, C.c_int, _i64]
         L.mad_plan_get_option.argtypes = [_P, C.c_int, _P]
         L.mips_plan_create.argtypes = [_P, _i64, _i64, _u32, _P,
@@ -313,6 +314,20 @@ class Plan:
         x = x[:n.value].cpu().numpy()
         o = np.argsort(keys, kind="stable")
         return keys[o], x[o], F.value
+
+    def lowp_screen(self, keys, stream=None):
+        """(c^, margin) of the low-precision screen for CUDA int64 keys
+        i*n + j (plan with bf16 / fp8 verification), as numpy arrays."""
+        import torch
+        n = int(keys.numel())
+        ch = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        mg = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        _check(lib().mad_debug_lowp_screen(
+            self._h, _dev_opt(keys, torch.int64, "keys"), n,
+            C.c_void_p(ch.data_ptr()), C.c_void_p(mg.data_ptr()),
+            _stream(stream)))
+        torch.cuda.synchronize()
+        return ch[:n].cpu().numpy(), mg[:n].cpu().numpy()
 
     def candidates(self):
         """Omega_t' of the last topk, sorted by key: keys, x_fix, c."""

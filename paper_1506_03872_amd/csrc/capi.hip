@@ -699,6 +699,23 @@ int mad_plan_verify_stats(mad_plan* p, int64_t* n_cand, int64_t* n_reranked) {
   return MAD_OK;
 }
 
+int mad_debug_lowp_screen(mad_plan* p, const int64_t* keys, int64_t count,
+                          float* chat, float* margin, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MAD_EINVAL, "plan is NULL");
+  if (p->kind != 0) return fail(MAD_EINVAL, "needs a dense MAD plan");
+  if (p->verify_prec == MAD_FP32)
+    return fail(MAD_EINVAL, "the plan verifies in fp32 (no screen)");
+  if (count < 0) return fail(MAD_EINVAL, "count must be >= 0");
+  if (count && (!keys || !chat || !margin))
+    return fail(MAD_EINVAL, "keys, chat and margin are required");
+  HIP_TRY(mad::launch_lowp_screen_values((const uint64_t*)keys, count, p->lv,
+                                         p->n, chat, margin,
+                                         (hipStream_t)stream),
+          "screen values");
+  return MAD_OK;
+}
+
 int mad_fix_exponent(mad_plan* p, int64_t s, int* F) {
   if (!p || !F) return fail(MAD_EINVAL, "plan and F are required");
   float bmax = 0.0f;

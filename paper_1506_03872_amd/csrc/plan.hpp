@@ -441,6 +441,11 @@ hipError_t lowp_prepare(const float* X, int64_t rows, int64_t d, int prec,
                         DeviceBuffer& data, DeviceBuffer& info, int64_t* Kp,
                         hipStream_t st);
 void lowp_consts(int prec, int64_t d, float* kappa, float* onepu);
+// c^ and its a-priori margin for given pair keys (select.hip)
+hipError_t launch_lowp_screen_values(const uint64_t* keys, int64_t count,
+                                     const LowpView& v, int64_t n,
+                                     float* chat, float* margin,
+                                     hipStream_t st);
 
 // csr: sparse inputs for the verification (A, B unused), or null; lowp:
 // low-precision filter of the candidates before the fp32 verification, or

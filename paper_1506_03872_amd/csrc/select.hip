@@ -875,6 +875,52 @@ __global__ __launch_bounds__(256) void k_verify_lowp(const uint64_t* key2,
   }
 }
 
+// the screen value c^ and its margin mg of given pairs (the arithmetic of
+// k_verify_lowp, for measuring c^ against FP64 next to its bound)
+__global__ __launch_bounds__(256) void k_lowp_screen_values(
+    const uint64_t* keys, int64_t count, LowpView v, int64_t n, float* chat,
+    float* margin) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4, gl = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int eb = v.prec == 1 ? 2 : 1;
+  const int64_t row_bytes = v.Kp * eb;
+  for (int64_t e0 = wave * 4; e0 < count; e0 += nwaves * 4) {
+    const int64_t e = e0 + grp;
+    const bool ok = e < count;
+    const uint64_t kk = keys[ok ? e : e0];
+    const int64_t i = (int64_t)(kk / (uint64_t)n);
+    const int64_t j = (int64_t)(kk % (uint64_t)n);
+    const char* ar = (const char*)v.A + i * row_bytes;
+    const char* br = (const char*)v.B + j * row_bytes;
+    float acc = 0.0f;
+    for (int64_t b0 = (int64_t)gl * 16; b0 < row_bytes; b0 += 256) {
+      const uint4 x = *(const uint4*)(ar + b0);
+      const uint4 y = *(const uint4*)(br + b0);
+      acc = lowp_dot16(x, y, v.prec, acc);
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (ok && gl == 0) {
+      const VecInfo va = v.ia[i], vb = v.ib[j];
+      chat[e] = acc * va.inv_s * vb.inv_s;
+      margin[e] = v.kappa * va.n2 * vb.n2 +
+                  v.onepu * (va.eta * vb.n1 + vb.eta * va.n1) +
+                  v.d_f * va.eta * vb.eta;
+    }
+  }
+}
+
+hipError_t launch_lowp_screen_values(const uint64_t* keys, int64_t count,
+                                     const LowpView& v, int64_t n,
+                                     float* chat, float* margin,
+                                     hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_lowp_screen_values<<<blocks_for(count * 16, 256, 2048), 256, 0, st>>>(
+      keys, count, v, n, chat, margin);
+  return hipGetLastError();
+}
+
 // keep the candidates whose upper bound reaches tau (lower edge of the bin
 // of the t-th largest lower bound; 0 when fewer than t are positive)
 __global__ __launch_bounds__(256) void k_lowp_filter(

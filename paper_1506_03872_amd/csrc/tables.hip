@@ -1017,26 +1017,27 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
 // ---------------------------------------------------------------------------
 // dense plan tables
 // ---------------------------------------------------------------------------
-// Binary inputs (Alg. 1): bit w*32 + q of bits is 1 when entry w*32 + q of
-// B is 1; *flag = 0 when some entry is neither 0 nor 1 (the sampler then
-// reads B itself).  One 32-bit word per thread.
+// Binary inputs (Alg. 1): bit e of bits is 1 when entry e of B is 1;
+// *flag = 0 when some entry is neither 0 nor 1 (the sampler then reads B
+// itself).  Each wave reads 64 consecutive entries per step (coalesced) and
+// writes their two 32-bit words from its ballots.
 __global__ __launch_bounds__(256) void k_binary_bitmap(const float* B,
                                                        int64_t n,
                                                        uint32_t* bits,
                                                        int* flag) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t e0 = w * 32;
-  if (e0 >= n) return;
-  uint32_t word = 0;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   bool other = false;
-  const int cnt = n - e0 < 32 ? (int)(n - e0) : 32;
-  for (int q = 0; q < cnt; ++q) {
-    const float v = B[e0 + q];
-    word |= (uint32_t)(v == 1.0f) << q;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t e = base + lane;
+    const float v = e < n ? B[e] : 0.0f;
+    const uint64_t one = __ballot(v == 1.0f);
     other |= v != 0.0f && v != 1.0f;
+    if (lane < 2 && base + 32 * lane < n)
+      bits[(base >> 5) + lane] = (uint32_t)(one >> (32 * lane));
   }
-  bits[w] = word;
-  if (other) *flag = 0;
+  if (__ballot(other) && lane == 0) *flag = 0;
 }
 
 // A == A^T for the squared variant (m x m): *flag = 1 on any difference.
@@ -1261,9 +1262,11 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
                         : grid_for(n * d, 1024 * 16), 1024, 0, sd>>>(
         B, n * d, t.bmax, t.bad);
     {
-      const int64_t words = (n * d + 31) / 32;
-      k_binary_bitmap<<<(unsigned)((words + 255) / 256), 256, 0, sd>>>(
-          B, n * d, t.bbits, t.bad + 6);
+      const int64_t waves = (n * d + 63) / 64;
+      int64_t blocks = (waves + 3) / 4;
+      if (blocks > 4096) blocks = 4096;
+      k_binary_bitmap<<<(unsigned)blocks, 256, 0, sd>>>(B, n * d, t.bbits,
+                                                        t.bad + 6);
     }
     e = t.T2.L <= 9
             ? small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,

@@ -116,3 +116,28 @@ def test_precision_setting_validation(mad_gpu):
     r2 = p.topk(t=5, s=20000, t_prime=100)
     assert np.array_equal(r["i"].cpu().numpy(), r2["i"].cpu().numpy())
     p.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_screen_error_within_its_bound(mad_gpu, prec):
+    # every candidate's bf16 / fp8 value c^ lies within its a-priori margin
+    # of the fp32 product, measured here against FP64 (the fp32 rounding is
+    # far below the margin's own slack)
+    import torch
+    A, B = CASES["planted_wide"]()
+    p = mad_gpu.Plan.dense(to_dev(A), to_dev(B))
+    p.set_verify_precision(prec)
+    p.topk(t=50, s=2_000_000, t_prime=4000, seed=5)
+    xk, xx, _ = p.scores()           # Omega_t': the top t' of X
+    pos = xx > 0
+    keys = xk[pos][np.lexsort((xk[pos], -xx[pos]))][:4000]
+    ch, mg = p.lowp_screen(torch.from_numpy(keys).cuda())
+    n = B.shape[0]
+    c64 = (A[keys // n].astype(np.float64) *
+           B[keys % n].astype(np.float64)).sum(1)
+    err = np.abs(ch.astype(np.float64) - c64)
+    say("prec", prec, "pairs", len(keys), "max err/bound",
+        float((err / mg).max()))
+    assert len(keys) > 1000
+    assert np.all(err <= mg)
+    p.close()
