@@ -510,9 +510,9 @@ def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
     plan.refresh()
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    sweep, hit = [], None
-    for s in (10 ** 6, 3_162_278, 10 ** 7, 31_622_777, 10 ** 8, 316_227_766,
-              10 ** 9):
+    sweep, hit, stop = [], None, None
+    s = 10 ** 6
+    while True:
         plan.topk(t=t, s=s, t_prime=tp, seed=0)
         recs, tms = [], []
         for seed in range(5):
@@ -532,7 +532,22 @@ def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
                                                    pt["ms_topk"]))
         if pt["recall_at_t"] >= 0.95:
             hit = pt
+            stop = "recall 0.95 reached"
             break
+        if pt["ms_topk"] > bf_ms:
+            stop = ("top-k time %.1f ms > the exact brute force (%.1f ms)"
+                    % (pt["ms_topk"], bf_ms))
+            break
+        nxt = int(round(s * 10 ** 0.5))
+        # workspace of the next s (pairs, partition, score table, about 64
+        # bytes per sample): stay below 64 GiB
+        if 64 * nxt > (64 << 30):
+            stop = ("next s = %d would need about %.0f GiB of workspace "
+                    "(cap 64 GiB); last top-k %.1f ms, exact brute force "
+                    "%.1f ms" % (nxt, 64 * nxt / 2 ** 30, pt["ms_topk"],
+                                 bf_ms))
+            break
+        s = nxt
     if own:
         plan.close()
     return {"m": m, "n": n, "d": d, "t": t, "t_prime": tp, "tau": tau,
@@ -549,6 +564,10 @@ def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
                 "ms_end_to_end": round(build_ms + hit["ms_topk"], 3),
                 "speedup_vs_exact_end_to_end": round(
                     bf_ms / (build_ms + hit["ms_topk"]), 1)},
+            "stop_rule": "s grows by sqrt(10) from 1e6 until recall reaches "
+                         "0.95, a top-k call takes longer than the exact "
+                         "brute force, or the workspace cap is reached",
+            "stop_reason": stop,
             "sweep": sweep}
 
 
