@@ -9,15 +9,30 @@ namespace mad {
 
 constexpr uint64_t kQMask = ~(1ull << 63);
 
+// Integer quanta in FP64: while K = L + 31 <= 52, every F_r, q_r, deficit
+// and excess and each of their sums is an integer below 2^52, so FP64 holds
+// them exactly and its adds, subtractions and comparisons are exact;
+// exact_u52 turns such an integer into its u64 with one add and one mask.
+constexpr int kF64MaxL = 52 - kCapBits;
+constexpr double kCapD = 2147483648.0;  // 2^31
+
+__device__ __forceinline__ uint64_t exact_u52(double x) {
+  return (uint64_t)__double_as_longlong(x + 4503599627370496.0) &
+         ((1ull << 52) - 1);
+}
+
 // One wave builds the alias table of one table from its quanta qv (lane
 // holds slots lane*SPL ..) and sign bits sg; LDS scratch Ld/He (2^L u64
 // each) and Hi (2^L u32) belongs to this wave.  Every wave of the block
 // calls this (it synchronises the block once).  Each slot r is handed to
-// emit(r, thr, sign_self, alias_position, sign_alias).
-template <int SPL, class Emit>
+// emit(r, thr, sign_self, alias_position, sign_alias).  With HAVE_F the
+// caller passes Fb = F before the lane's first slot (the sum of all quanta
+// before it): the excess before the lane then follows from the deficit
+// before it, sum (C - q) = first C - Fb, and one 64-bit scan suffices.
+template <int SPL, bool HAVE_F = false, class Emit>
 __device__ void wave_alias(const uint64_t (&qv)[SPL], const uint32_t (&sg)[SPL],
                            bool active, int L, uint64_t* Ld, uint64_t* He,
-                           uint32_t* Hi, Emit emit) {
+                           uint32_t* Hi, Emit emit, uint64_t Fb = 0) {
   const int Np = 1 << L;
   const int lane = threadIdx.x & 63;
   uint32_t nl = 0, nh = 0;
@@ -30,14 +45,32 @@ __device__ void wave_alias(const uint64_t (&qv)[SPL], const uint32_t (&sg)[SPL],
       else { ++nh; se += qv[s] - kCap; }
     }
   }
-  // light and heavy counts share one scan (each total is at most 2^L <=
-  // 512, so 16 bits apiece)
-  const uint32_t c_in = wave_incl_scan(nl | (nh << 16));
-  const uint64_t sd_in = wave_incl_scan(sd), se_in = wave_incl_scan(se);
-  const uint32_t c_all = __shfl(c_in, 63, 64);
-  const uint32_t NL = c_all & 0xFFFFu, NH = c_all >> 16;
-  uint32_t lp = (c_in & 0xFFFFu) - nl, hp = (c_in >> 16) - nh;
-  uint64_t da = sd_in - sd, ea = se_in - se;
+  uint32_t NL, NH, lp, hp;
+  uint64_t da, ea;
+  if (HAVE_F) {
+    const uint32_t c_in = wave_scan_dpp(nl);
+    const uint64_t sd_in = wave_scan_dpp(sd);
+    NL = __shfl(c_in, 63, 64);
+    lp = c_in - nl;
+    const uint32_t first = active ? (uint32_t)(lane * SPL) : 0u;
+    const uint32_t before = first < (uint32_t)Np ? first : (uint32_t)Np;
+    NH = active ? (uint32_t)Np - NL : 0u;
+    hp = before - lp;
+    da = sd_in - sd;
+    ea = da - (uint64_t)before * kCap + Fb;
+  } else {
+    // light and heavy counts share one scan (each total is at most 2^L <=
+    // 512, so 16 bits apiece)
+    const uint32_t c_in = wave_incl_scan(nl | (nh << 16));
+    const uint64_t sd_in = wave_incl_scan(sd), se_in = wave_incl_scan(se);
+    const uint32_t c_all = __shfl(c_in, 63, 64);
+    NL = c_all & 0xFFFFu;
+    NH = c_all >> 16;
+    lp = (c_in & 0xFFFFu) - nl;
+    hp = (c_in >> 16) - nh;
+    da = sd_in - sd;
+    ea = se_in - se;
+  }
   uint32_t mypos[SPL];
 #pragma unroll
   for (int s = 0; s < SPL; ++s) {

@@ -125,6 +125,35 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   return v;
 }
 
+// Inclusive scan over the 64 lanes by DPP moves (GFX9 controls: row_shr
+// by 1, 2, 4 and 8 within each row of 16 lanes, then row_bcast:15 into
+// rows 1 and 3 and row_bcast:31 into rows 2 and 3); lanes without a source
+// add 0.  No LDS round trip per step, unlike the shuffle scan above.  Every
+// lane of the wave must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_from(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF,
+                                               false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_from(uint64_t v) {
+  const uint32_t lo = dpp_from<CTRL, ROWS>((uint32_t)v);
+  const uint32_t hi = dpp_from<CTRL, ROWS>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_scan_dpp(T v) {
+  v += dpp_from<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_from<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_from<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_from<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_from<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_from<0x143, 0xC>(v);  // row_bcast:31
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -372,7 +372,8 @@ __global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
     }
     __syncthreads();
     // ---- phase 2 -----------------------------------------------------------
-    for (int t0 = 0; t0 < TB; t0 += 4) {  // every wave runs every round
+    // every wave runs every round (ntab is the same for the whole block)
+    for (int t0 = 0; t0 < ntab; t0 += 4) {
       const int tb = t0 + wv;
       const int64_t seg = seg0 + tb;
       const bool have = tb < TB && seg < S;
@@ -387,31 +388,33 @@ __global__ __launch_bounds__(256) void k_small_tables(W w, int64_t S,
       if (have && lane == 0 && tot) tot[seg] = T;  // tot may be null
       if (have && !live)  // dead table: never sampled, entries zero
         for (int r = lane; r < Np; r += 64) ent[(seg << L) + r] = 0ull;
+      // F_r exact in FP64 (K <= 40 here); slots past the items keep F of
+      // the last item, 2^K, so their quanta are zero
       uint64_t F[SPL];
       uint32_t sg[SPL];
 #pragma unroll
       for (int s = 0; s < SPL; ++s) {
         const int r = lane * SPL + s;
-        F[s] = 0;
+        F[s] = live ? (uint64_t)1 << K : 0ull;
         sg[s] = 0;
         if (live && r < N) {
           const uint64_t raw = lb[tb * ld + r];
           const double lr = __longlong_as_double((long long)(raw & kQMask));
-          F[s] = (uint64_t)floor(ldexp((Ec[r / kRun] + lr) / T, K));
+          F[s] = exact_u52(floor(ldexp((Ec[r / kRun] + lr) / T, K)));
           sg[s] = (uint32_t)(raw >> 63);
         }
       }
       uint64_t Fp = __shfl_up(F[SPL - 1], 1, 64);
       if (lane == 0) Fp = 0;
+      const uint64_t Fb = Fp;  // the sum of the quanta before this lane
       uint64_t qv[SPL];
 #pragma unroll
       for (int s = 0; s < SPL; ++s) {
-        const int r = lane * SPL + s;
-        qv[s] = live && r < N ? F[s] - Fp : 0ull;
+        qv[s] = F[s] - Fp;
         Fp = F[s];
       }
-      wave_alias<SPL>(qv, sg, live, L, Ld, He, Hi,
-                      EmitPacked{ent + ((have ? seg : 0) << L)});
+      wave_alias<SPL, true>(qv, sg, live, L, Ld, He, Hi,
+                            EmitPacked{ent + ((have ? seg : 0) << L)}, Fb);
       __syncthreads();  // the wave's alias scratch is reused next round
     }
   }
@@ -456,8 +459,8 @@ constexpr int kAliasBlk = 1024;
 __device__ Quad block_excl_scan(Quad& v) {
   __shared__ Quad wtot[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  Quad inc{wave_incl_scan(v.nl), wave_incl_scan(v.nh), wave_incl_scan(v.sd),
-           wave_incl_scan(v.se)};
+  Quad inc{wave_scan_dpp(v.nl), wave_scan_dpp(v.nh), wave_scan_dpp(v.sd),
+           wave_scan_dpp(v.se)};
   if (lane == 63) wtot[wv] = inc;
   __syncthreads();
   Quad off{0, 0, 0, 0}, all{0, 0, 0, 0};
@@ -562,7 +565,9 @@ __global__ __launch_bounds__(256) void k_alias_scatter(
 constexpr int kMergeP = 4;
 constexpr int kMergeBlk = 256 * kMergeP;
 
-// merge-path split of every block edge (kMergeBlk positions apart)
+// merge-path split of every block edge (kMergeBlk positions apart), one
+// binary search per thread (a 64-lane search per edge was tried: it reads
+// 64 scattered lines per round and took twice as long)
 __global__ void k_alias_edges(const uint64_t* Ld, const uint64_t* He,
                               const uint64_t* NLa, const uint64_t* NHa,
                               int64_t ntab, int L, int64_t* edges) {
@@ -782,31 +787,43 @@ __global__ __launch_bounds__(64) void k_col_runtot(const float* X, int64_t d,
 }
 
 // E_c (c < R) and T per table: E_0 = 0, E_{c+1} = E_c + rtot_c, T = E_R.
-// One 64-thread block per table: the run totals are gathered into LDS in
-// parallel, then one lane adds them left to right.
+// One 256-thread block per table: the run totals are gathered into LDS in
+// parallel, then one lane adds them left to right, 16 at a time through
+// registers so that its LDS reads do not wait on its own writes.
 constexpr int kOffChunk = 2048;
+constexpr int kOffBatch = 16;
 
-__global__ __launch_bounds__(64) void k_col_runoffsets(const double* rtot,
-                                                       int64_t S, int64_t R,
-                                                       double* E,
-                                                       double* tot) {
+__global__ __launch_bounds__(256) void k_col_runoffsets(const double* rtot,
+                                                        int64_t S, int64_t R,
+                                                        double* E,
+                                                        double* tot) {
   __shared__ double buf[kOffChunk];
   const int64_t seg = blockIdx.x;
-  double e = 0.0;  // lane 0's running offset
+  double e = 0.0;  // thread 0's running offset
   for (int64_t c0 = 0; c0 < R; c0 += kOffChunk) {
-    const int64_t nc = R - c0 < kOffChunk ? R - c0 : kOffChunk;
-    for (int64_t u = threadIdx.x; u < nc; u += 64)
-      buf[u] = rtot[(c0 + u) * S + seg];
+    const int nc = (int)(R - c0 < kOffChunk ? R - c0 : kOffChunk);
+    // padded with zeros to whole batches: e + 0 = e exactly
+    const int ncp = (nc + kOffBatch - 1) / kOffBatch * kOffBatch;
+    for (int u = threadIdx.x; u < ncp; u += 256)
+      buf[u] = u < nc ? rtot[(c0 + u) * S + seg] : 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int64_t u = 0; u < nc; ++u) {
-        const double x = buf[u];
-        buf[u] = e;  // E_c
-        e = e + x;
+      for (int u0 = 0; u0 < ncp; u0 += kOffBatch) {
+        double x[kOffBatch];
+#pragma unroll
+        for (int j = 0; j < kOffBatch; ++j) x[j] = buf[u0 + j];
+#pragma unroll
+        for (int j = 0; j < kOffBatch; ++j) {
+          const double ej = e;  // E_c
+          e = e + x[j];
+          x[j] = ej;
+        }
+#pragma unroll
+        for (int j = 0; j < kOffBatch; ++j) buf[u0 + j] = x[j];
       }
     }
     __syncthreads();
-    for (int64_t u = threadIdx.x; u < nc; u += 64) E[(c0 + u) * S + seg] = buf[u];
+    for (int u = threadIdx.x; u < nc; u += 256) E[(c0 + u) * S + seg] = buf[u];
     __syncthreads();
   }
   if (threadIdx.x == 0) tot[seg] = e;
@@ -820,8 +837,11 @@ __global__ __launch_bounds__(64) void k_col_runoffsets(const double* rtot,
 // with the sign in bit 31) per (item, table); then, four tables at a time
 // (one per quarter-wave, lane = item), ballots give every entry its place
 // and each table's lights and heavies of the group are stored as
-// contiguous runs.
-template <bool LISTS, bool SCALE>
+// contiguous runs.  F64 selects the exact FP64 arithmetic (L <= kF64MaxL).
+// (Splitting each run over four waves, each first re-adding the run-local
+// prefix before its quarter, was measured slower: the walks are bound by
+// their instruction issue, not by the latency one wave sees.)
+template <bool LISTS, bool SCALE, bool F64>
 __global__ __launch_bounds__(64) void k_col_walk(
     const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
     int L, const double* E, const double* tot, int64_t s0, int64_t ns,
@@ -849,18 +869,25 @@ __global__ __launch_bounds__(64) void k_col_walk(
   const int64_t r0 = c * kRun;
   const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;  // items of this run
   const int64_t R = (N + kRun - 1) / kRun;
-  const double Ec = c < R ? E[c * S + seg] : 0.0;
-  uint64_t Fp = 0;
-  if (live && c > 0 && c < R) Fp = (uint64_t)floor(ldexp(Ec / T, K));
+  const double Ec = live && c < R ? E[c * S + seg] : 0.0;
+  // F of the item before the run: floor(2^K E_c / T), 0 in the first run
+  const bool first = !(live && c > 0 && c < R);
+  const double Fstart = first ? 0.0 : floor(ldexp(Ec / T, K));
+  uint64_t Fp = (uint64_t)Fstart;
+  double Fpd = Fstart;
   uint64_t nl = 0, nh = 0, da = 0, ea = 0;
+  double dad = 0.0, ead = 0.0;
   if (LISTS) {
     const Quad o = bs[tc * B + c];
     nl = o.nl;
     nh = o.nh;
     da = o.sd;
     ea = o.se;
+    dad = (double)o.sd;  // exact: below 2^52 on the F64 path
+    ead = (double)o.se;
   }
   double l = 0.0;
+  uint32_t nlr = 0;  // lights of this run so far (F64 statistics)
   for (int64_t g0 = r0; g0 < r0 + kRun; g0 += G) {
     float xv[G];
     double sv[G];
@@ -882,28 +909,54 @@ __global__ __launch_bounds__(64) void k_col_walk(
       cnt0[lane][0] = nl;
       cnt0[lane][1] = nh;
     }
-    // no branch per item: only the additions of l form a dependent chain,
-    // so the divisions of consecutive items overlap
+    if (F64) {
+      // no branch per item: items past the run's end (and every item of a
+      // dead table) weigh 0 and leave l, F and the sums unchanged apart
+      // from a zero quantum
 #pragma unroll
-    for (int u = 0; u < G; ++u) {
-      const int64_t r = g0 + u;
-      const bool ok = live && r < r1;
-      const double w = SCALE ? fabs((double)xv[u]) * sv[u]
-                             : fabs((double)xv[u]);
-      const double lw = r == r0 ? w : l + w;
-      l = ok ? lw : l;
-      const uint64_t F = (uint64_t)floor(ldexp((Ec + l) / Tq, K));
-      const uint64_t q = ok ? F - Fp : 0ull;
-      Fp = ok ? F : Fp;
-      const uint32_t sg = ok ? sign_bit(xv[u]) : 0u;
-      const bool light = q < kCap;
-      const uint64_t ea2 = light ? ea : ea + (q - kCap);
-      if (LISTS) tv[u][lane] = light ? da : (ea2 | (1ull << 63));
-      da = light ? da + (kCap - q) : da;
-      ea = ea2;
-      nl += light ? 1 : 0;
-      nh += light ? 0 : 1;
-      if (LISTS) ti[u][lane] = (uint32_t)r | (sg << 31);
+      for (int u = 0; u < G; ++u) {
+        const int64_t r = g0 + u;
+        const float x = live && r < r1 ? xv[u] : 0.0f;
+        const double w = SCALE ? fabs((double)x) * sv[u] : fabs((double)x);
+        l = l + w;
+        const double F = floor(ldexp((Ec + l) / Tq, K));
+        const double q = F - Fpd;
+        Fpd = F;
+        const bool light = q < kCapD;
+        const double dex = dad;  // the light's exclusive deficit prefix
+        dad = dad + fmax(kCapD - q, 0.0);
+        ead = ead + fmax(q - kCapD, 0.0);
+        nlr += light ? 1u : 0u;
+        if (LISTS) {
+          tv[u][lane] = light ? exact_u52(dex)
+                              : (exact_u52(ead) | (1ull << 63));
+          ti[u][lane] = (uint32_t)r | (sign_bit(x) << 31);
+        }
+      }
+    } else {
+      // no branch per item: only the additions of l form a dependent
+      // chain, so the divisions of consecutive items overlap
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int64_t r = g0 + u;
+        const bool ok = live && r < r1;
+        const double w = SCALE ? fabs((double)xv[u]) * sv[u]
+                               : fabs((double)xv[u]);
+        const double lw = r == r0 ? w : l + w;
+        l = ok ? lw : l;
+        const uint64_t F = (uint64_t)floor(ldexp((Ec + l) / Tq, K));
+        const uint64_t q = ok ? F - Fp : 0ull;
+        Fp = ok ? F : Fp;
+        const uint32_t sg = ok ? sign_bit(xv[u]) : 0u;
+        const bool light = q < kCap;
+        const uint64_t ea2 = light ? ea : ea + (q - kCap);
+        if (LISTS) tv[u][lane] = light ? da : (ea2 | (1ull << 63));
+        da = light ? da + (kCap - q) : da;
+        ea = ea2;
+        nl += light ? 1 : 0;
+        nh += light ? 0 : 1;
+        if (LISTS) ti[u][lane] = (uint32_t)r | (sg << 31);
+      }
     }
     if (LISTS) {
       __syncthreads();
@@ -933,9 +986,20 @@ __global__ __launch_bounds__(64) void k_col_walk(
         }
       }
       __syncthreads();
+      if (F64) {  // this group's counts, for the next group's positions
+        nl += nlr;
+        nh += G - nlr;
+        nlr = 0;
+      }
     }
   }
-  if (!LISTS && mine) bs[tc * B + c] = Quad{nl, nh, da, ea};
+  if (!LISTS && mine) {
+    if (F64)
+      bs[tc * B + c] = Quad{nlr, (uint64_t)(kRun - nlr), exact_u52(dad),
+                            exact_u52(ead)};
+    else
+      bs[tc * B + c] = Quad{nl, nh, da, ea};
+  }
 }
 
 // scratch of col_tables: run totals and offsets (2 R S doubles), the run
@@ -972,13 +1036,23 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
   else
     k_col_runtot<false><<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S,
                                                               N, rtot);
-  k_col_runoffsets<<<(unsigned)S, 64, 0, st>>>(rtot, S, R, E, f.tot);
-  if (scale)
-    k_col_walk<false, true><<<(unsigned)(B * tiles), 64, 0, st>>>(
+  k_col_runoffsets<<<(unsigned)S, 256, 0, st>>>(rtot, S, R, E, f.tot);
+  const bool f64 = L <= kF64MaxL;
+  const unsigned sgrid = (unsigned)(B * tiles);
+  if (scale && f64)
+    k_col_walk<false, true, true><<<sgrid, 64, 0, st>>>(
+        X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
+        nullptr);
+  else if (scale)
+    k_col_walk<false, true, false><<<sgrid, 64, 0, st>>>(
+        X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
+        nullptr);
+  else if (f64)
+    k_col_walk<false, false, true><<<sgrid, 64, 0, st>>>(
         X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
         nullptr);
   else
-    k_col_walk<false, false><<<(unsigned)(B * tiles), 64, 0, st>>>(
+    k_col_walk<false, false, false><<<sgrid, 64, 0, st>>>(
         X, d, scale, S, N, L, E, f.tot, 0, S, bs, nullptr, nullptr, nullptr,
         nullptr);
   for (int64_t s0 = 0; s0 < S; s0 += per) {
@@ -997,11 +1071,18 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
     Quad* bsb = bs + s0 * B;
     k_alias_blockscan<<<(unsigned)ns, 256, 0, st>>>(bsb, ns, B, NL, NH, Dt);
     const int64_t btiles = (ns + 63) / 64;
-    if (scale)
-      k_col_walk<true, true><<<(unsigned)(B * btiles), 64, 0, st>>>(
+    const unsigned lgrid = (unsigned)(B * btiles);
+    if (scale && f64)
+      k_col_walk<true, true, true><<<lgrid, 64, 0, st>>>(
+          X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
+    else if (scale)
+      k_col_walk<true, true, false><<<lgrid, 64, 0, st>>>(
+          X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
+    else if (f64)
+      k_col_walk<true, false, true><<<lgrid, 64, 0, st>>>(
           X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
     else
-      k_col_walk<true, false><<<(unsigned)(B * btiles), 64, 0, st>>>(
+      k_col_walk<true, false, false><<<lgrid, 64, 0, st>>>(
           X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
     const int64_t nedge = ns * (Np / kMergeBlk + 1);
     k_alias_edges<<<grid_for(nedge, 256), 256, 0, st>>>(Ld, He, NL, NH, ns, L,
