@@ -451,6 +451,15 @@ static hipError_t small_tables(W w, int64_t S, int64_t N, int L, double* tot,
   return hipGetLastError();
 }
 
+// Workgroups go to the 8 XCDs in turn; this remaps block b so that each
+// XCD takes a contiguous run of logical blocks (when the grid is a
+// multiple of 8), which keeps neighbouring blocks' writes to a shared line,
+// and their reads of a shared line, in one L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t nbk = gridDim.x, b = blockIdx.x;
+  return nbk % 8 == 0 ? (b % 8) * (nbk / 8) + b / 8 : b;
+}
+
 // large tables (2^L >= 1024 slots): blocks of 1024 slots (256 threads x 4)
 // never straddle a table
 constexpr int kAliasBlk = 1024;
@@ -590,12 +599,9 @@ __global__ __launch_bounds__(256) void k_alias_merge(
   __shared__ uint32_t sLi[kMergeBlk + 1], sHi[kMergeBlk + 1];
   const int64_t Np = int64_t(1) << L;
   const int64_t blocks_per = Np / kMergeBlk;
-  // workgroups go to the 8 XCDs in turn: give each XCD a contiguous run of
-  // blocks, so that a table's scattered entry writes meet in one L2
-  const int64_t nbk = gridDim.x;
-  const int64_t lb = nbk % 8 == 0
-                         ? (int64_t)(blockIdx.x % 8) * (nbk / 8) + blockIdx.x / 8
-                         : (int64_t)blockIdx.x;
+  // each XCD takes a contiguous run of blocks, so that a table's scattered
+  // entry writes meet in one L2
+  const int64_t lb = xcd_block();
   const int64_t segl = lb / blocks_per;
   const int64_t bi = lb % blocks_per;
   const int64_t seg = seg0 + segl;
@@ -837,7 +843,8 @@ __global__ __launch_bounds__(256) void k_col_runoffsets(const double* rtot,
 // with the sign in bit 31) per (item, table); then, four tables at a time
 // (one per quarter-wave, lane = item), ballots give every entry its place
 // and each table's lights and heavies of the group are stored as
-// contiguous runs.  F64 selects the exact FP64 arithmetic (L <= kF64MaxL).
+// contiguous runs.  F64 selects the exact FP64 arithmetic of the
+// statistics (L <= kF64MaxL; the lists are then written by k_col_lists).
 // (Splitting each run over four waves, each first re-adding the run-local
 // prefix before its quarter, was measured slower: the walks are bound by
 // their instruction issue, not by the latency one wave sees.)
@@ -850,13 +857,15 @@ __global__ __launch_bounds__(64) void k_col_walk(
   // LDS staging (12.5 KB) lets more waves share a CU
   constexpr int G = LISTS ? 16 : kColGroup;
   static_assert(G == 16 || !LISTS, "four tables per wave in the write-out");
+  static_assert(!(LISTS && F64), "the F64 lists are k_col_lists");
   __shared__ uint64_t tv[LISTS ? G : 1][65];
   __shared__ uint32_t ti[LISTS ? G : 1][65];
   __shared__ uint64_t cnt0[LISTS ? 64 : 1][2];  // lights / heavies before
   const int64_t B = (int64_t(1) << L) / kRun;  // slot runs per table
   const int64_t tiles = (ns + 63) / 64;
-  const int64_t c = blockIdx.x / tiles;
-  const int64_t t0 = (blockIdx.x % tiles) * 64;
+  const int64_t lb = xcd_block();
+  const int64_t c = lb / tiles;
+  const int64_t t0 = (lb % tiles) * 64;
   const int lane = threadIdx.x;
   const int64_t t = t0 + lane;
   const bool mine = t < ns;
@@ -923,15 +932,9 @@ __global__ __launch_bounds__(64) void k_col_walk(
         const double q = F - Fpd;
         Fpd = F;
         const bool light = q < kCapD;
-        const double dex = dad;  // the light's exclusive deficit prefix
         dad = dad + fmax(kCapD - q, 0.0);
         ead = ead + fmax(q - kCapD, 0.0);
         nlr += light ? 1u : 0u;
-        if (LISTS) {
-          tv[u][lane] = light ? exact_u52(dex)
-                              : (exact_u52(ead) | (1ull << 63));
-          ti[u][lane] = (uint32_t)r | (sign_bit(x) << 31);
-        }
       }
     } else {
       // no branch per item: only the additions of l form a dependent
@@ -986,11 +989,6 @@ __global__ __launch_bounds__(64) void k_col_walk(
         }
       }
       __syncthreads();
-      if (F64) {  // this group's counts, for the next group's positions
-        nl += nlr;
-        nh += G - nlr;
-        nlr = 0;
-      }
     }
   }
   if (!LISTS && mine) {
@@ -999,6 +997,123 @@ __global__ __launch_bounds__(64) void k_col_walk(
                             exact_u52(ead)};
     else
       bs[tc * B + c] = Quad{nl, nh, da, ea};
+  }
+}
+
+constexpr int kListGroup = 32;  // items per write-out group
+
+// The lists walk on the exact FP64 path (L <= kF64MaxL), one wave per (slot
+// run c, 64 consecutive tables of [s0, s0 + ns)), lane = table: each lane
+// knows its table's running light and heavy counts, so it gives each item
+// its list position itself.  A group of G items then passes through LDS as
+// (value with the heavy flag in bit 63, slot id with the sign in bit 31,
+// position), and 64 / G tables at a time (G lanes each, lane = item) are
+// stored, each table's lights and heavies of the group as contiguous runs.
+// 32-item groups write 200 MB per C2 family where 16-item groups wrote
+// 247 MB (157 MB of entries): longer runs leave fewer partly written
+// lines.  (Packing id and position into one word, or 64-item groups, were
+// not faster.)  Groups wholly inside the run's items load without
+// clamping.
+template <bool SCALE>
+__global__ __launch_bounds__(64) void k_col_lists(
+    const float* X, int64_t d, const double* scale, int64_t S, int64_t N,
+    int L, const double* E, const double* tot, int64_t s0, int64_t ns,
+    const Quad* bs, uint64_t* Ld, uint32_t* Li, uint64_t* He, uint32_t* Hi) {
+  constexpr int G = kListGroup;
+  constexpr int P = 64 / G;  // tables per write-out round
+  __shared__ uint64_t tv[G][65];
+  __shared__ uint32_t ti[G][65];
+  __shared__ uint32_t tp[G][65];
+  const int64_t B = (int64_t(1) << L) / kRun;  // slot runs per table
+  const int64_t tiles = (ns + 63) / 64;
+  const int64_t lb = xcd_block();
+  const int64_t c = lb / tiles;
+  const int64_t t0 = (lb % tiles) * 64;
+  const int lane = threadIdx.x;
+  const int64_t t = t0 + lane;
+  const int64_t tc = t < ns ? t : ns - 1;
+  const int64_t seg = s0 + tc;
+  const double T = tot[seg];
+  const bool live = T > 0.0;
+  const double Tq = live ? T : 1.0;  // dead tables: no item is taken
+  const int K = L + kCapBits;
+  const int64_t r0 = c * kRun;
+  const int64_t r1 = N < r0 + kRun ? N : r0 + kRun;  // items of this run
+  const int64_t R = (N + kRun - 1) / kRun;
+  const double Ec = live && c < R ? E[c * S + seg] : 0.0;
+  const bool first = !(live && c > 0 && c < R);
+  double Fp = first ? 0.0 : floor(ldexp(Ec / T, K));
+  const Quad o = bs[tc * B + c];
+  uint32_t nl = (uint32_t)o.nl, nh = (uint32_t)o.nh;  // below 2^L
+  double da = (double)o.sd;  // exact: below 2^52
+  double ea = (double)o.se;
+  double l = 0.0;
+  const float* xs = X + seg;
+  for (int64_t g0 = r0; g0 < r0 + kRun; g0 += G) {
+    float xv[G];
+    double sv[G];
+    if (g0 + G <= r1) {
+      const float* xg = xs + g0 * d;
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        xv[u] = xg[(int64_t)u * d];
+        sv[u] = SCALE ? scale[g0 + u] : 1.0;
+      }
+    } else if (g0 < r1) {
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int64_t r = g0 + u < r1 ? g0 + u : r1 - 1;
+        xv[u] = xs[r * d];
+        sv[u] = SCALE ? scale[r] : 1.0;
+      }
+    } else {  // padding slots only
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        xv[u] = 0.0f;
+        sv[u] = 1.0;
+      }
+    }
+    // items past the run's end (and every item of a dead table) weigh 0
+    // and leave l, F and the sums unchanged apart from a zero quantum
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int64_t r = g0 + u;
+      const float x = live && r < r1 ? xv[u] : 0.0f;
+      const double w = SCALE ? fabs((double)x) * sv[u] : fabs((double)x);
+      l = l + w;
+      const double F = floor(ldexp((Ec + l) / Tq, K));
+      const double q = F - Fp;
+      Fp = F;
+      const bool light = q < kCapD;
+      const double dex = da;  // the light's exclusive deficit prefix
+      da = da + fmax(kCapD - q, 0.0);
+      ea = ea + fmax(q - kCapD, 0.0);
+      tv[u][lane] = light ? exact_u52(dex) : (exact_u52(ea) | (1ull << 63));
+      ti[u][lane] = (uint32_t)r | (sign_bit(x) << 31);
+      tp[u][lane] = light ? nl : nh;
+      nl += light ? 1u : 0u;
+      nh += light ? 0u : 1u;
+    }
+    __syncthreads();
+    // write-out: lane group h of G lanes takes table j = p + h, lane % G =
+    // item
+    const int h = lane / G, u = lane % G;
+    for (int p = 0; p < 64; p += P) {
+      const int j = p + h;
+      const uint64_t v = tv[u][j];
+      const uint32_t id = ti[u][j];
+      const int64_t at = ((t0 + j) << L) + tp[u][j];
+      if (t0 + j < ns) {
+        if (v >> 63) {
+          He[at] = v & ~(1ull << 63);
+          Hi[at] = id;
+        } else {
+          Ld[at] = v;
+          Li[at] = id;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1073,13 +1188,13 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
     const int64_t btiles = (ns + 63) / 64;
     const unsigned lgrid = (unsigned)(B * btiles);
     if (scale && f64)
-      k_col_walk<true, true, true><<<lgrid, 64, 0, st>>>(
+      k_col_lists<true><<<lgrid, 64, 0, st>>>(
           X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
     else if (scale)
       k_col_walk<true, true, false><<<lgrid, 64, 0, st>>>(
           X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
     else if (f64)
-      k_col_walk<true, false, true><<<lgrid, 64, 0, st>>>(
+      k_col_lists<false><<<lgrid, 64, 0, st>>>(
           X, d, scale, S, N, L, E, f.tot, s0, ns, bsb, Ld, Li, He, Hi);
     else
       k_col_walk<true, false, false><<<lgrid, 64, 0, st>>>(
