@@ -377,7 +377,8 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
       (e = mad::dev_alloc(p->cx2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->ck2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->cc, 4 * (size_t)ccap2)) != hipSuccess ||
-      (e = mad::dev_alloc(p->cr, 16 * (size_t)rcap + 65536)) != hipSuccess ||
+      (e = mad::dev_alloc(p->cr, 16 * (size_t)rcap + mad::kPartBytes)) !=
+           hipSuccess ||
       (e = mad::dev_alloc(p->misc, mad::kSelStateBytes + 4 * mad::kSelBins +
                                        256 + 256)) != hipSuccess ||
       (p->kind == 0 &&

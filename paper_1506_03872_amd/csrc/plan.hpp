@@ -375,6 +375,10 @@ struct SelectWork {
 // SelectWork::counts slots
 enum { kCountPos = 0, kCountDistinct = 1, kCountCand = 2, kCountFinal = 3 };
 constexpr size_t kSelStateBytes = 512;
+// and / or slots of the selection's two block splits: 4 words for each of
+// at most kPartBlocks blocks per split
+constexpr int kPartBlocks = 1024;
+constexpr size_t kPartBytes = 2 * 4 * sizeof(uint64_t) * (size_t)kPartBlocks;
 constexpr int kSelBins = 2048;
 
 hipError_t launch_dump_scores(const HashTable& h, int64_t* keys,

@@ -65,7 +65,6 @@ static_assert(3 * sizeof(Coarse) + 2 * sizeof(Refine) <= kSelStateBytes,
 constexpr int kRefineMin = 4096;   // shorter lists go to step 3 as they are
 constexpr int kRefineThreads = 1024;
 constexpr int kRefineThreadsMax = 1024;
-constexpr int kPartBlocks = 1024;  // and / or slots per selection
 constexpr int64_t kRefineFinalMin = 16384;  // t' above which the final
                                             // selection may refine
 
@@ -1242,6 +1241,7 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
                                      &counts[kCntPos], rf);
   // winners go straight to (x2, key2); the boundary bin to (x, key)
   const unsigned nsplit = blocks_for(h.cap, 256 * 16, 512);
+  static_assert(512 <= kPartBlocks, "one and / or slot per split block");
   k_score_split<<<nsplit, 256, 0, st>>>(h.keys, h.vals, h.cap, h.live, cz,
                                         w.x2, w.key2, w.cap2, w.x, w.key,
                                         w.cap, counts, w.part);
@@ -1296,6 +1296,7 @@ hipError_t launch_postprocess(const HashTable& h, const float* A,
   uint64_t* bx = bkey + bcap;
   float* bc = (float*)(bx + bcap);
   const unsigned ncs = blocks_for(t_prime, 256 * 4, 1024);
+  static_assert(1024 <= kPartBlocks, "one and / or slot per split block");
   uint64_t* part2 = w.part + 4 * kPartBlocks;
   k_cand_split<<<ncs, 256, 0, st>>>(cz + 1, w.x, w.key2, w.x2, w.c, w.cap2,
                                     fp, fkey, fx, fc, t, bp, bkey, bx, bc,
