@@ -336,6 +336,19 @@ def bench_mips(args, cfg, data, mad):
         e1.record()
         torch.cuda.synchronize()
         extra["torch_fp32_gemm_topk_ms"] = round(e0.elapsed_time(e1), 3)
+    # score updates against the probe ceiling of a CAS followed by an add
+    # on one random 16-byte entry (each closed sample makes at least one
+    # such pair; a probe past a taken slot adds a CAS)
+    log("memory ceilings")
+    ceil = memory_ceilings(mad)
+    upd = closed / (ph[1] * 1e-3)
+    cas_add = ceil["rand_cas_then_add_16B"] * 1e9
+    extra["score_updates"] = {
+        "closed_per_s": round(upd, 1),
+        "cas_then_add_ceiling_per_s": round(cas_add, 1),
+        "frac_of_ceiling": round(upd / cas_add, 4),
+        "note": "the sampling kernel also makes two random alias-entry "
+                "loads per sample, so it cannot reach this ceiling"}
     line = {
         "metric": "MIPS batch: diamond samples/s (queries/s, recall@10)",
         "value": round(S / (ms * 1e-3), 1),
