@@ -347,8 +347,10 @@ def bench_mips(args, cfg, data, mad):
         "closed_per_s": round(upd, 1),
         "cas_then_add_ceiling_per_s": round(cas_add, 1),
         "frac_of_ceiling": round(upd / cas_add, 4),
-        "note": "the sampling kernel also makes two random alias-entry "
-                "loads per sample, so it cannot reach this ceiling"}
+        "note": "each closed sample makes one CAS and one add on its "
+                "query's table (one more CAS per taken slot passed); the "
+                "kernel also makes two random alias-entry loads per "
+                "sample"}
     line = {
         "metric": "MIPS batch: diamond samples/s (queries/s, recall@10)",
         "value": round(S / (ms * 1e-3), 1),
