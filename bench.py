@@ -526,9 +526,16 @@ def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     sweep, hit, stop = [], None, None
+    # what torch's allocator holds from the dense part goes back to the
+    # device, so that the largest s can have its workspace
+    torch.cuda.empty_cache()
     s = 10 ** 6
     while True:
-        plan.topk(t=t, s=s, t_prime=tp, seed=0)
+        try:
+            plan.topk(t=t, s=s, t_prime=tp, seed=0)
+        except mad.MadError as err:
+            stop = "s = %d: workspace allocation failed (%s)" % (s, err)
+            break
         recs, tms = [], []
         for seed in range(5):
             torch.cuda.synchronize()
@@ -554,14 +561,21 @@ def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
                     % (pt["ms_topk"], bf_ms))
             break
         nxt = int(round(s * 10 ** 0.5))
-        # workspace of the next s (pairs, partition, score table, about 64
-        # bytes per sample): stay below 64 GiB
-        if 64 * nxt > (64 << 30):
-            stop = ("next s = %d would need about %.0f GiB of workspace "
-                    "(cap 64 GiB); last top-k %.1f ms, exact brute force "
-                    "%.1f ms" % (nxt, 64 * nxt / 2 ** 30, pt["ms_topk"],
-                                 bf_ms))
-            break
+        # workspace of the next s (pairs and the accumulation's partition,
+        # which the selection's boundary lists reuse, and the score table:
+        # about 44 bytes per sample): stay below 200 GiB of the GPU's
+        # 288 GB; past the last grid point that fits, one more point at the
+        # largest s that does
+        s_max = int((200 << 30) / 44) // 10 ** 8 * 10 ** 8
+        if nxt > s_max:
+            if s < 0.9 * s_max:
+                nxt = s_max
+            else:
+                stop = ("next s = %d would need about %.0f GiB of workspace "
+                        "(cap 200 GiB); last top-k %.1f ms, exact brute "
+                        "force %.1f ms" % (nxt, 44 * nxt / 2 ** 30,
+                                           pt["ms_topk"], bf_ms))
+                break
         s = nxt
     if own:
         plan.close()
@@ -581,7 +595,9 @@ def csr_recall(args, cfg, mad, a, b, m, n, plan=None):
                     bf_ms / (build_ms + hit["ms_topk"]), 1)},
             "stop_rule": "s grows by sqrt(10) from 1e6 until recall reaches "
                          "0.95, a top-k call takes longer than the exact "
-                         "brute force, or the workspace cap is reached",
+                         "brute force, or the workspace cap (200 GiB) or "
+                         "the device memory is reached; the last point is "
+                         "the largest s within the cap",
             "stop_reason": stop,
             "sweep": sweep}
 

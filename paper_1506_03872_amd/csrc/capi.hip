@@ -368,12 +368,24 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   const int64_t ccap2 = tp2 > 1 ? tp2 : 1;
   // candidate selection's refined boundary list (one digit's bin of a long boundary list)
   const int64_t rcap = ccap < (int64_t(1) << 21) ? ccap : (int64_t(1) << 21);
+  // pair form: the pairs and the accumulation's partition are dead once X
+  // is built, so the candidate selection's boundary lists (x, key) reuse
+  // that region when it is large enough (16 bytes per sample less)
+  const size_t acc_bytes = use_pairs ? pair_bytes(u2) + mad::accum_bytes(u2)
+                                     : 0;
+  const bool c_in_acc = use_pairs && 16 * (size_t)ccap <= acc_bytes;
   (void)hipDeviceSynchronize();
+  if (c_in_acc) {
+    mad::dev_free(p->cx);
+    mad::dev_free(p->ck);
+  }
   hipError_t e;
   if ((e = mad::dev_alloc(p->hk, 8 * (size_t)hcap)) != hipSuccess ||
       (e = mad::dev_alloc(p->hv, 8 * (size_t)hcap)) != hipSuccess ||
-      (e = mad::dev_alloc(p->cx, 8 * (size_t)ccap)) != hipSuccess ||
-      (e = mad::dev_alloc(p->ck, 8 * (size_t)ccap)) != hipSuccess ||
+      (!c_in_acc &&
+       (e = mad::dev_alloc(p->cx, 8 * (size_t)ccap)) != hipSuccess) ||
+      (!c_in_acc &&
+       (e = mad::dev_alloc(p->ck, 8 * (size_t)ccap)) != hipSuccess) ||
       (e = mad::dev_alloc(p->cx2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->ck2, 8 * (size_t)ccap2)) != hipSuccess ||
       (e = mad::dev_alloc(p->cc, 4 * (size_t)ccap2)) != hipSuccess ||
@@ -385,9 +397,7 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
        (e = mad::dev_alloc(p->ord, mad::sample_order_bytes(p->dt, s2,
                                                            p->sopt))) !=
            hipSuccess) ||
-      (use_pairs &&
-       (e = mad::dev_alloc(p->acc, pair_bytes(u2) + mad::accum_bytes(u2))) !=
-           hipSuccess)) {
+      (use_pairs && (e = mad::dev_alloc(p->acc, acc_bytes)) != hipSuccess)) {
     p->ws_s = p->ws_tp = p->ws_t = -1;
     return hip_fail(e, "allocating workspace");
   }
@@ -395,8 +405,8 @@ static int ensure_workspace(mad_plan* p, int64_t s, int64_t tp, int64_t t) {
   p->h.vals = (int64_t*)p->hv.p;
   p->h.cap = hcap;
   p->pairs = use_pairs;
-  p->w.x = (uint64_t*)p->cx.p;
-  p->w.key = (uint64_t*)p->ck.p;
+  p->w.x = c_in_acc ? (uint64_t*)p->acc.p : (uint64_t*)p->cx.p;
+  p->w.key = c_in_acc ? p->w.x + ccap : (uint64_t*)p->ck.p;
   p->w.x2 = (uint64_t*)p->cx2.p;
   p->w.key2 = (uint64_t*)p->ck2.p;
   p->w.c = (float*)p->cc.p;
