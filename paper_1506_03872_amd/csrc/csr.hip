@@ -448,16 +448,19 @@ struct ColItems {  // T1 / T2: vectors with an entry at k; item = vector
 
 template <class W>
 struct EmitItems {
-  Ent16* et;
+  Ent32* et;
   W w;
   int64_t o;
   int64_t N;
+  const uint64_t* pay;  // payload per item, or null (none)
   __device__ void operator()(int r, uint32_t thr, uint32_t ss, uint32_t al,
                              uint32_t sa) const {
-    Ent16 e;
+    Ent32 e;
     e.w = pack_entry(thr, ss, al, sa);
     e.self = r < N ? w.item(o + r) : 0u;
     e.alias = w.item(o + (int64_t)al);
+    e.pself = pay && r < N ? pay[e.self] : 0ull;
+    e.palias = pay ? pay[e.alias] : 0ull;
     et[r] = e;
   }
 };
@@ -547,7 +550,8 @@ __global__ __launch_bounds__(64) void k_ragged_lane_quanta(
 template <int SPL, class W>
 __global__ __launch_bounds__(256) void k_ragged_alias(
     W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
-    int64_t count, const double* tot, const uint64_t* q, Ent16* ent) {
+    int64_t count, const double* tot, const uint64_t* q, Ent32* ent,
+    const uint64_t* pay) {
   extern __shared__ uint64_t smem64[];
   constexpr int NpMax = 64 * SPL;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(256) void k_ragged_alias(
   const int Np = 1 << L;
   const bool active = mine && tot[seg] > 0.0;
   if (mine && !active)  // dead table: never sampled, entries zero
-    for (int r = lane; r < Np; r += 64) ent[so + r] = Ent16{0ull, 0u, 0u};
+    for (int r = lane; r < Np; r += 64) ent[so + r] = Ent32{0ull, 0u, 0u, 0ull, 0ull};
   uint64_t qv[SPL];
   uint32_t sg[SPL];
 #pragma unroll
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(256) void k_ragged_alias(
   wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * NpMax,
                   smem64 + (int64_t)wv * 2 * NpMax + NpMax,
                   (uint32_t*)(smem64 + 8 * NpMax) + (int64_t)wv * NpMax,
-                  EmitItems<W>{ent + so, w, o, N});
+                  EmitItems<W>{ent + so, w, o, N, pay});
 }
 
 // ---------------------------------------------------------------------------
@@ -835,17 +839,18 @@ template <class W>
 __global__ __launch_bounds__(256) void k_big_merge(W w, const BigInfo* big,
                                                    const uint32_t* btab,
                                                    const double* tot,
-                                                   BigScratch sc, Ent16* ent) {
+                                                   BigScratch sc, Ent32* ent,
+                                                   const uint64_t* pay) {
   __shared__ uint64_t sD[kBigBlk + 1], sE[kBigBlk + 1];
   __shared__ uint32_t sLi[kBigBlk + 1], sHi[kBigBlk + 1];
   const uint32_t bt = btab[blockIdx.x];
   const BigInfo B = big[bt];
   const int64_t bi = (int64_t)blockIdx.x - B.so / kBigBlk;
   const int64_t d0 = bi * kBigBlk;
-  Ent16* et = ent + B.so;
+  Ent32* et = ent + B.so;
   if (!(tot[B.s] > 0.0)) {  // dead table: never sampled, entries zero
     for (int u = threadIdx.x; u < kBigBlk; u += 256)
-      et[d0 + u] = Ent16{0ull, 0u, 0u};
+      et[d0 + u] = Ent32{0ull, 0u, 0u, 0ull, 0ull};
     return;
   }
   const int64_t NL = (int64_t)sc.NL[bt], NH = (int64_t)sc.NH[bt];
@@ -873,7 +878,7 @@ __global__ __launch_bounds__(256) void k_big_merge(W w, const BigInfo* big,
     if (sD[mid] <= sE[dl - mid - 1]) lo = mid + 1; else hi = mid;
   }
   int64_t a = lo, b = dl - lo;
-  const EmitItems<W> emit{et, w, B.o, B.N};
+  const EmitItems<W> emit{et, w, B.o, B.N, pay};
   for (int step = 0; step < kBigMergeP; ++step) {
     if (a < na && (b >= nb || sD[a] <= sE[b])) {
       const uint32_t id = sLi[a];
@@ -975,7 +980,7 @@ static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
   const size_t b_ids = al256(4 * (size_t)(R.cls_off[4] + 1));
   if ((e = dev_alloc(R.lay, b_meta + b_big + b_btab + b_run + b_ids)) !=
           hipSuccess ||
-      (e = dev_alloc(R.ent_buf, sizeof(Ent16) * (size_t)(ss > 0 ? ss : 1))) !=
+      (e = dev_alloc(R.ent_buf, sizeof(Ent32) * (size_t)(ss > 0 ? ss : 1))) !=
           hipSuccess ||
       (e = dev_alloc(R.tot_buf, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess)
     return e;
@@ -985,7 +990,7 @@ static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
   R.btab = (uint32_t*)(p + b_meta + b_big);
   R.runtab = (uint32_t*)(p + b_meta + b_big + b_btab);
   R.small_ids = (uint32_t*)(p + b_meta + b_big + b_btab + b_run);
-  R.ent = (Ent16*)R.ent_buf.p;
+  R.ent = (Ent32*)R.ent_buf.p;
   R.tot = (double*)R.tot_buf.p;
   std::vector<char> host(b_meta + b_big + b_btab + b_run + b_ids, 0);
   memcpy(host.data(), meta.data(), 8 * meta.size());
@@ -1047,7 +1052,7 @@ static BigScratch big_carve(void* p, const Ragged& R) {
 
 template <class W>
 static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
-                               hipStream_t st) {
+                               hipStream_t st, const uint64_t* pay = nullptr) {
   if (R.S <= 0) return hipSuccess;
   const int64_t* c = R.cls_off;
   uint64_t* qs = (uint64_t*)((char*)scratch + small_q_offset(R));
@@ -1056,16 +1061,16 @@ static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
         w, R.off, R.meta, R.small_ids, c[4], R.tot, qs);
   if (c[1] > c[0])
     k_ragged_alias<1, W><<<blocks_of(c[1] - c[0], 4), 256, 4 * 64 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, qs, R.ent);
+        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, qs, R.ent, pay);
   if (c[2] > c[1])
     k_ragged_alias<2, W><<<blocks_of(c[2] - c[1], 4), 256, 4 * 128 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, qs, R.ent);
+        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, qs, R.ent, pay);
   if (c[3] > c[2])
     k_ragged_alias<4, W><<<blocks_of(c[3] - c[2], 4), 256, 4 * 256 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, qs, R.ent);
+        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, qs, R.ent, pay);
   if (c[4] > c[3])
     k_ragged_alias<8, W><<<blocks_of(c[4] - c[3], 4), 256, 4 * 512 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, qs, R.ent);
+        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, qs, R.ent, pay);
   if (R.nbig > 0) {
     const BigScratch sc = big_carve(scratch, R);
     const BigInfo* big = (const BigInfo*)R.big;
@@ -1078,7 +1083,8 @@ static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
     k_big_scatter<<<nblk, 256, 0, st>>>(big, R.btab, sc);
     k_big_edges<<<blocks_of(R.edges, 256), 256, 0, st>>>(big, R.nbig,
                                                          R.edges, sc);
-    k_big_merge<W><<<nblk, 256, 0, st>>>(w, big, R.btab, R.tot, sc, R.ent);
+    k_big_merge<W><<<nblk, 256, 0, st>>>(w, big, R.btab, R.tot, sc, R.ent,
+                                         pay);
   }
   return hipGetLastError();
 }
@@ -1095,7 +1101,7 @@ void csr_tables_free(CsrTables& t) {
   ragged_free(t.T3);
   family_free_pub(t.T0);
   void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
-                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad};
+                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.bpack};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
@@ -1108,10 +1114,25 @@ void csr_tables_free(CsrTables& t) {
   t.bmax = nullptr;
   t.bad = nullptr;
   t.b_unit = nullptr;
+  t.bpack = nullptr;
+  t.bpack_ok = nullptr;
   dev_free(t.work);
 }
 
 static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st);
+
+// b_j's compressed row as start | length << 40; *ok = 0 when a row does not
+// fit (the sampler then loads b_ptr)
+__global__ void k_pack_rows(const int64_t* ptr, int64_t rows, uint64_t* pk,
+                            int* ok) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t s = ptr[r], len = ptr[r + 1] - s;
+  const bool fits = s >= 0 && s < (int64_t(1) << 40) && len >= 0 &&
+                    len < (int64_t(1) << 24);
+  pk[r] = fits ? (uint64_t)s | ((uint64_t)len << 40) : 0ull;
+  if (!fits) *ok = 0;  // every writer stores the same value
+}
 
 hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
   hipError_t e;
@@ -1130,6 +1151,7 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = hipMalloc(&t.at_src, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = hipMalloc(&t.bt_src, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_w, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bpack, 8 * (size_t)(n + 1))) != hipSuccess ||
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
       return e;
   }
@@ -1172,6 +1194,14 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
     if ((bad & 2) || (check && (bad & 1))) return hipErrorInvalidValue;
     t.validated = true;
   }
+  // B's rows packed for the T2 payload (structure only)
+  t.bpack_ok = t.bad + 34;
+  if ((e = launch_fill_u64((uint64_t*)t.bpack_ok, 1, 1ull, st)) !=
+      hipSuccess)
+    return e;
+  if (n > 0)
+    k_pack_rows<<<blocks_of(n, 256), 256, 0, st>>>(t.in.b_ptr, n, t.bpack,
+                                                   t.bpack_ok);
   // transposes
   const int64_t nz = t.nnzA > t.nnzB ? t.nnzA : t.nnzB;
   if ((e = dev_alloc(t.work, sort_bytes(nz))) != hipSuccess) return e;
@@ -1240,11 +1270,12 @@ static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
                        ? blocks_of(t.nnzA, 256 * 8) : 2048,
                    256, 0, st>>>(t.at_val, t.at_row, t.T3.tot, t.nnzA,
                                  t.at_w);
+  // T1's payload: T3's meta word of the drawn i; T2's: b_j's packed row
   if ((e = ragged_build(t.T1,
                         ColItems{t.at_val, t.at_row, t.T3.tot, t.at_w},
-                        t.work.p, st)) != hipSuccess ||
+                        t.work.p, st, t.T3.meta)) != hipSuccess ||
       (e = ragged_build(t.T2, ColItems{t.bt_val, t.bt_row, nullptr},
-                        t.work.p, st)) != hipSuccess)
+                        t.work.p, st, t.bpack)) != hipSuccess)
     return e;
   k_stage0_csr<<<blocks_of(d, 256), 256, 0, st>>>(t.T2.tot, t.T1.tot, d,
                                                   t.om);
@@ -1260,28 +1291,35 @@ struct CsrSampleArgs {
   const uint64_t* T0;
   int L0;
   const uint64_t* m1;
-  const Ent16* e1;
+  const Ent32* e1;
   const uint64_t* m2;
-  const Ent16* e2;
+  const Ent32* e2;
   const uint64_t* m3;
-  const Ent16* e3;
+  const Ent32* e3;
   CsrView in;
   int64_t n;
   uint64_t seed, qid;
   int64_t l0, count;
   int gram;  // B = A: key of the pair with i < j, diagonal left out
   const int* b_unit;  // 1: every value of B is 1 (no fourth-edge value load)
+  const int* bpack_ok;  // 1: T2's payloads hold b_j's rows (else b_ptr)
   // squared variant (Sec. 3.2.3): the second pair of sample e, keyed by
   // (k, k') like the first, goes to pk2[e] / pv2[e] (pair form only)
   uint64_t* pk2;
   float* pv2;
 };
 
-__device__ __forceinline__ Drawn draw16(const Ent16& e, uint64_t U) {
+__device__ __forceinline__ Drawn draw16(const Ent32& e, uint64_t U) {
   const uint32_t lo = (uint32_t)e.w, hi = (uint32_t)(e.w >> 32);
   const uint32_t coin = (uint32_t)U & kLow31;
   const bool self = coin < (lo & kLow31);
   return {self ? e.self : e.alias, (self ? lo : hi) >> 31};
+}
+
+// the drawn item's payload (the same coin as draw16)
+__device__ __forceinline__ uint64_t draw_pay(const Ent32& e, uint64_t U) {
+  const uint32_t coin = (uint32_t)U & kLow31;
+  return coin < ((uint32_t)e.w & kLow31) ? e.pself : e.palias;
 }
 
 __device__ __forceinline__ uint64_t meta_slot(uint64_t mt, uint64_t U) {
@@ -1313,6 +1351,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
   const uint64_t* T0 = t0_lds ? t0s : a.T0;
   const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
   const bool unit = *a.b_unit != 0;
+  const bool packed = *a.bpack_ok != 0;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long nclosed = 0, ncreated = 0;
@@ -1335,13 +1374,14 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       mt1[u] = a.m1[k[u]];
       mt2[u] = a.m2[k[u]];
     }
-    Ent16 x1[U], x2[U];
+    Ent32 x1[U], x2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       x1[u] = a.e1[meta_slot(mt1[u], W1[u])];
       x2[u] = a.e2[meta_slot(mt2[u], W2[u])];
     }
-    uint64_t mt3[U];
+    // T3's meta of i and b_j's row come with the drawn entries (payloads)
+    uint64_t mt3[U], pj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const Drawn di = draw16(x1[u], W1[u]);
@@ -1349,15 +1389,21 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       i[u] = di.pos;
       j[u] = dj.pos;
       sg[u] = di.sgn ^ dj.sgn;
-      mt3[u] = a.m3[i[u]];
+      mt3[u] = draw_pay(x1[u], W1[u]);
+      pj[u] = draw_pay(x2[u], W2[u]);
     }
     int64_t lo[U], hi[U];
-    Ent16 x3[U];
+    Ent32 x3[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       x3[u] = a.e3[meta_slot(mt3[u], W3[u])];
-      lo[u] = a.in.b_ptr[j[u]];
-      hi[u] = a.in.b_ptr[j[u] + 1];
+      if (packed) {
+        lo[u] = (int64_t)(pj[u] & ((1ull << 40) - 1));
+        hi[u] = lo[u] + (int64_t)(pj[u] >> 40);
+      } else {
+        lo[u] = a.in.b_ptr[j[u]];
+        hi[u] = a.in.b_ptr[j[u] + 1];
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1564,6 +1610,7 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.count = count;
   a.gram = t.gram;
   a.b_unit = t.b_unit;
+  a.bpack_ok = t.bpack_ok;
   a.pk2 = nullptr;
   a.pv2 = nullptr;
   return a;

@@ -169,13 +169,19 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t* inc, hipStream_t st);
 
 // ---- csr.hip -------------------------------------------------------------
-// A 16-byte alias entry of a sparse table: the packed word of a dense entry
-// (threshold, alias position, two sign bits) plus the item ids (vector or
-// coordinate) of the slot's own item and of its alias.
-struct Ent16 {
+// A 32-byte alias entry of a sparse table: the packed word of a dense entry
+// (threshold, alias position, two sign bits), the item ids (vector or
+// coordinate) of the slot's own item and of its alias, and a payload per
+// item that the sampler needs next and would otherwise load from another
+// array: for T1 (items i) the meta word of T3[i], for T2 (items j) b_j's
+// compressed row as start | length << 40 (T3: none).  The entry sits in one
+// cache line, so the payload costs no extra line per draw.
+struct Ent32 {
   uint64_t w;
   uint32_t self;
   uint32_t alias;
+  uint64_t pself;
+  uint64_t palias;
 };
 
 constexpr uint64_t kSlotMask = (1ull << 56) - 1;
@@ -191,7 +197,7 @@ struct Ragged {
   int64_t cls_off[5] = {0, 0, 0, 0, 0};  // small tables by slots per lane
   const int64_t* off = nullptr;  // S + 1 (device)
   uint64_t* meta = nullptr;      // S (device)
-  Ent16* ent = nullptr;          // slots (device)
+  Ent32* ent = nullptr;          // slots (device)
   double* tot = nullptr;         // S table totals (device)
   void* big = nullptr;           // per big table layout (device)
   uint32_t* btab = nullptr;      // big table of each 1024-slot block
@@ -230,6 +236,11 @@ struct CsrTables {
   float* bmax = nullptr;  // 1
   int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
   int* b_unit = nullptr;  // 1: every stored value of B is 1 (in bad's block)
+  // B's rows packed as start | length << 40 (the T2 payload), and 1 in
+  // *bpack_ok when every row fits (start < 2^40, length < 2^24); else the
+  // sampler loads b_ptr
+  uint64_t* bpack = nullptr;
+  int* bpack_ok = nullptr;  // in bad's block
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.2.2)
   int square = 0;         // B = A symmetric: x_kk' updated too (Sec. 3.2.3)
