@@ -382,15 +382,15 @@ def bench_mips(args, cfg, data, mad):
     print(json.dumps(line))
 
 
-# algorithmic bytes of one sparse sample: stage-0 entry (8 B, L2 resident
-# for d = 1e5), three table metas (8 B each), three 16-byte alias entries,
-# the two row pointers of b_j, its coordinate list searched (log2 nnz_j + 1
-# four-byte loads) and the fourth-edge value, then the 12-byte pair
-# written
+# bytes one sparse sample reads and writes: stage-0 entry (8 B, L2 resident
+# for d = 1e5), the metas of T1[k] and T2[k] (8 B each), three 32-byte alias
+# entries (T1's and T2's carry T3's meta of i and b_j's row), b_j's
+# coordinate list searched (log2 nnz_j + 1 four-byte loads) and the
+# fourth-edge value, then the 12-byte pair written
 def csr_sample_bytes(nnz_per_vec):
     import math
     probes = int(math.ceil(math.log2(max(nnz_per_vec, 2)))) + 1
-    return 8 + 3 * 8 + 3 * 16 + 16 + 4 * probes + 4 + PAIR_WRITE_BYTES
+    return 8 + 2 * 8 + 3 * 32 + 4 * probes + 4 + PAIR_WRITE_BYTES
 
 
 def bench_csr(args, cfg, data, mad):
