@@ -452,15 +452,17 @@ struct EmitItems {
   W w;
   int64_t o;
   int64_t N;
-  const uint64_t* pay;  // payload per item, or null (none)
+  // payload per item position (pay[p] belongs to the item at position p,
+  // so a table's payloads are as contiguous as its items), or null
+  const uint64_t* pay;
   __device__ void operator()(int r, uint32_t thr, uint32_t ss, uint32_t al,
                              uint32_t sa) const {
     Ent32 e;
     e.w = pack_entry(thr, ss, al, sa);
     e.self = r < N ? w.item(o + r) : 0u;
     e.alias = w.item(o + (int64_t)al);
-    e.pself = pay && r < N ? pay[e.self] : 0ull;
-    e.palias = pay ? pay[e.alias] : 0ull;
+    e.pself = pay && r < N ? pay[o + r] : 0ull;
+    e.palias = pay ? pay[o + (int64_t)al] : 0ull;
     et[r] = e;
   }
 };
@@ -1101,7 +1103,8 @@ void csr_tables_free(CsrTables& t) {
   ragged_free(t.T3);
   family_free_pub(t.T0);
   void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
-                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.bpack};
+                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.bpack,
+                t.at_pay, t.bt_pay};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
@@ -1116,6 +1119,7 @@ void csr_tables_free(CsrTables& t) {
   t.b_unit = nullptr;
   t.bpack = nullptr;
   t.bpack_ok = nullptr;
+  t.at_pay = t.bt_pay = nullptr;
   dev_free(t.work);
 }
 
@@ -1132,6 +1136,15 @@ __global__ void k_pack_rows(const int64_t* ptr, int64_t rows, uint64_t* pk,
                     len < (int64_t(1) << 24);
   pk[r] = fits ? (uint64_t)s | ((uint64_t)len << 40) : 0ull;
   if (!fits) *ok = 0;  // every writer stores the same value
+}
+
+// out[p] = pay[item[p]]: the payload of the item at each transpose position
+__global__ void k_gather_pay(const uint32_t* item, int64_t n,
+                             const uint64_t* pay, uint64_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += stride)
+    out[p] = pay[item[p]];
 }
 
 hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
@@ -1152,6 +1165,8 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = hipMalloc(&t.bt_src, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_w, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = hipMalloc(&t.bpack, 8 * (size_t)(n + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.at_pay, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bt_pay, 8 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
       return e;
   }
@@ -1218,6 +1233,15 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
       (e = ragged_layout(t.T1, t.at_ptr, d, st)) != hipSuccess ||
       (e = ragged_layout(t.T2, t.bt_ptr, d, st)) != hipSuccess)
     return e;
+  // the T1 / T2 payloads by transpose position (structure only)
+  if (t.nnzA > 0)
+    k_gather_pay<<<blocks_of(t.nnzA, 256 * 8) < 2048
+                       ? blocks_of(t.nnzA, 256 * 8) : 2048,
+                   256, 0, st>>>(t.at_row, t.nnzA, t.T3.meta, t.at_pay);
+  if (t.nnzB > 0)
+    k_gather_pay<<<blocks_of(t.nnzB, 256 * 8) < 2048
+                       ? blocks_of(t.nnzB, 256 * 8) : 2048,
+                   256, 0, st>>>(t.bt_row, t.nnzB, t.bpack, t.bt_pay);
   size_t need = ragged_scratch_bytes(t.T3);
   need = std::max(need, ragged_scratch_bytes(t.T1));
   need = std::max(need, ragged_scratch_bytes(t.T2));
@@ -1273,9 +1297,9 @@ static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
   // T1's payload: T3's meta word of the drawn i; T2's: b_j's packed row
   if ((e = ragged_build(t.T1,
                         ColItems{t.at_val, t.at_row, t.T3.tot, t.at_w},
-                        t.work.p, st, t.T3.meta)) != hipSuccess ||
+                        t.work.p, st, t.at_pay)) != hipSuccess ||
       (e = ragged_build(t.T2, ColItems{t.bt_val, t.bt_row, nullptr},
-                        t.work.p, st, t.bpack)) != hipSuccess)
+                        t.work.p, st, t.bt_pay)) != hipSuccess)
     return e;
   k_stage0_csr<<<blocks_of(d, 256), 256, 0, st>>>(t.T2.tot, t.T1.tot, d,
                                                   t.om);

@@ -241,6 +241,10 @@ struct CsrTables {
   // sampler loads b_ptr
   uint64_t* bpack = nullptr;
   int* bpack_ok = nullptr;  // in bad's block
+  // the payloads by transpose position: at_pay[p] = T3 meta of at_row[p],
+  // bt_pay[p] = bpack[bt_row[p]] (structure only)
+  uint64_t* at_pay = nullptr;
+  uint64_t* bt_pay = nullptr;
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.2.2)
   int square = 0;         // B = A symmetric: x_kk' updated too (Sec. 3.2.3)
