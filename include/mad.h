@@ -366,6 +366,8 @@ int mips_plan_create(const float* A, int64_t m, int64_t d, uint32_t flags,
  * s = s_per_query[q], t' = tprime_per_query[q], the same t and seed, and
  * Philox counter word 1 = q: its own stage-0 table (weight |q_k| v_k), its
  * own fixed-point exponent F_q from max|q_k| and s_q, scores keyed by i.
+ * A score shares a 64-bit slot with its key, so F_q is the general plan's
+ * exponent minus kb, the bit length of m (the scores stay exact).
  *   Q                  (device) nq x d fp32 row-major; 0 <= nq < 2^31
  *   s_per_query        (host) nq budgets, 0 <= s_q < 2^31
  *   tprime_per_query   (host) nq candidate budgets, each >= t

@@ -80,6 +80,8 @@ def _declare(L):
     L.orc_fix_exponent.restype = C.c_int
     L.orc_plan_fix_exponent.argtypes = [_P, _i64]
     L.orc_plan_fix_exponent.restype = C.c_int
+    L.orc_plan_fix_exponent_keyed.argtypes = [_P, _i64, C.c_int]
+    L.orc_plan_fix_exponent_keyed.restype = C.c_int
     L.orc_plan_samples.argtypes = [_P, _u64, _u64, _i64, _i64, C.c_int,
                                    _P, _P, _P, _P, _P]
     L.orc_plan_samples.restype = _i64
@@ -263,7 +265,12 @@ class Plan:
                          None, None)
         return thr, al, item[:N.value], N.value, bool(live.value), tot.value
 
-    def fix_exponent(self, s: int) -> int:
+    def fix_exponent(self, s: int, key_bits: int = 0) -> int:
+        """F of reading R7; key_bits > 0: a score that shares its 64-bit
+        word with a key of that many bits."""
+        if key_bits:
+            return lib().orc_plan_fix_exponent_keyed(self._h, int(s),
+                                                     int(key_bits))
         return lib().orc_plan_fix_exponent(self._h, int(s))
 
     def samples(self, seed: int, l0: int, count: int, F: int, qid: int = 0):

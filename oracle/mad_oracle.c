@@ -36,7 +36,8 @@
  *       (the line reads sgn(a_ki b_kj a_k'i); Lemma 2's statement and proof
  *       misprint its subscripts, and its algebra needs the line's form).
  *   R7  scores are exact int64 fixed point: inc = sign * rne(b_k'j * 2^F)
- *       with F = 62 - e_b - ceil(log2 max(s,2)), max|b| < 2^e_b.
+ *       with F = 62 - e_b - ceil(log2 max(s,2)), max|b| < 2^e_b.  Where a
+ *       score shares a 64-bit word with a kb-bit key, F is lowered by kb.
  *   R8  ties in both selections of Alg. 2 are broken by (i, j) ascending,
  *       and the final ranking is by |c_ij| (Definition 1 asks for the
  *       largest |a_i . b_j|; Alg. 2 (final selection) prints c_ij).
@@ -508,6 +509,13 @@ int orc_fix_exponent(float bmax, int64_t s) {
  * taken for 2s updates (no int64 sum can overflow). */
 int orc_plan_fix_exponent(const orc_plan *p, int64_t s) {
   return orc_fix_exponent(p->bmax, p->square ? 2 * s : s);
+}
+
+/* R7 for a score kept beside a kb-bit key in one 64-bit word: 64 - kb bits
+ * remain for it, so the exponent is lower by kb and any sum of s
+ * increments still lies within 2^(62 - kb). */
+int orc_plan_fix_exponent_keyed(const orc_plan *p, int64_t s, int kb) {
+  return orc_plan_fix_exponent(p, s) - kb;
 }
 
 static int sign_bit(float x) {

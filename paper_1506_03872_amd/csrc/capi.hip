@@ -64,7 +64,7 @@ int64_t next_pow2(int64_t v) {
 struct MipsState {
   mad::Family T0q;  // stage-0 table per query (capacity nq_cap tables)
   int64_t nq_cap = 0;
-  mad::DeviceBuffer qscratch, qinfo, order, chunks, hkeys, hvals, cx, ck, sx,
+  mad::DeviceBuffer qscratch, qinfo, order, chunks, hash, cx, ck, sx,
       sk, sc, sab, qstats, ctr;
   // layout of the prepared batch
   std::vector<int64_t> s, tp;
@@ -135,7 +135,7 @@ static void mips_free(MipsState* ms) {
   if (ms->cap_stream) (void)hipStreamDestroy(ms->cap_stream);
   mad::family_free_pub(ms->T0q);
   mad::DeviceBuffer* bufs[] = {&ms->qscratch, &ms->qinfo, &ms->order,
-                               &ms->chunks, &ms->hkeys, &ms->hvals, &ms->cx,
+                               &ms->chunks, &ms->hash, &ms->cx,
                                &ms->ck, &ms->sx, &ms->sk, &ms->sc, &ms->sab,
                                &ms->qstats, &ms->ctr, &ms->qlp, &ms->qlpi};
   for (mad::DeviceBuffer* b : bufs) mad::dev_free(*b);
@@ -1342,8 +1342,7 @@ static int mips_prepare(mad_plan* p, int64_t nq, const int64_t* s,
       (e = mad::dev_alloc(ms->qinfo, nqa * sizeof(mad::MipsQuery))) != hipSuccess ||
       (e = mad::dev_alloc(ms->order, nqa * 4)) != hipSuccess ||
       (e = mad::dev_alloc(ms->chunks, (ch.size() + 1) * sizeof(mad::MipsChunk))) != hipSuccess ||
-      (e = mad::dev_alloc(ms->hkeys, (size_t)(hs + 2) * 4)) != hipSuccess ||
-      (e = mad::dev_alloc(ms->hvals, (size_t)(hs + 1) * 8)) != hipSuccess ||
+      (e = mad::dev_alloc(ms->hash, (size_t)(hs + 1) * 8)) != hipSuccess ||
       (e = mad::dev_alloc(ms->cx, (size_t)(cs + 1) * 8)) != hipSuccess ||
       (e = mad::dev_alloc(ms->ck, (size_t)(cs + 1) * 4)) != hipSuccess ||
       (e = mad::dev_alloc(ms->sx, (size_t)(ss + 1) * 8)) != hipSuccess ||
@@ -1375,6 +1374,13 @@ static int mips_prepare(mad_plan* p, int64_t nq, const int64_t* s,
   return MAD_OK;
 }
 
+// bits of a MIPS score slot's key field: i + 1 <= m < 2^kb
+static int mips_key_bits(int64_t m) {
+  int kb = 1;
+  while ((int64_t(1) << kb) <= m) ++kb;
+  return kb;
+}
+
 static mad::MipsArgs mips_args(mad_plan* p, const float* Q, uint64_t seed,
                                void* out, int64_t* n_out) {
   MipsState* ms = p->mips;
@@ -1397,8 +1403,8 @@ static mad::MipsArgs mips_args(mad_plan* p, const float* Q, uint64_t seed,
   a.order = (const int32_t*)ms->order.p;
   a.chunks = (const mad::MipsChunk*)ms->chunks.p;
   a.nchunks = ms->nchunks;
-  a.hkeys = (uint32_t*)ms->hkeys.p;
-  a.hvals = (int64_t*)ms->hvals.p;
+  a.hslot = (uint64_t*)ms->hash.p;
+  a.kb = mips_key_bits(p->m);
   a.cx = (uint64_t*)ms->cx.p;
   a.ck = (uint32_t*)ms->ck.p;
   a.sx = (uint64_t*)ms->sx.p;
@@ -1430,7 +1436,7 @@ static hipError_t mips_enqueue(mad_plan* p, const mad::MipsArgs& a,
   MipsState* ms = p->mips;
   hipError_t e;
   if (events) record(p, 0, st);
-  if ((e = mad::launch_mips_query_info(a.Q, a.nq, a.d,
+  if ((e = mad::launch_mips_query_info(a.Q, a.nq, a.d, a.kb,
                                        (mad::MipsQuery*)ms->qinfo.p, st)) !=
           hipSuccess ||
       (e = mad::query_tables_build(a.Q, a.nq, a.d, p->dt.v, ms->T0q,
@@ -1447,9 +1453,7 @@ static hipError_t mips_enqueue(mad_plan* p, const mad::MipsArgs& a,
     record(p, 1, st);
     record(p, 2, st);
   }
-  if ((e = mad::launch_fill_u64((uint64_t*)ms->hkeys.p, (ms->hslots + 1) / 2,
-                                ~0ull, st)) != hipSuccess ||
-      (e = mad::launch_fill_u64((uint64_t*)ms->hvals.p, ms->hslots, 0ull,
+  if ((e = mad::launch_fill_u64((uint64_t*)ms->hash.p, ms->hslots, 0ull,
                                 st)) != hipSuccess ||
       (e = mad::launch_fill_u64((uint64_t*)ms->ctr.p, 8, 0ull, st)) !=
           hipSuccess)

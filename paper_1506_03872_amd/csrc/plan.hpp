@@ -335,8 +335,10 @@ struct MipsArgs {
   const int32_t* order;  // queries by descending budget
   const MipsChunk* chunks;
   int64_t nchunks;
-  uint32_t* hkeys;
-  int64_t* hvals;
+  // score slots of the queries' tables: key i + 1 in the low kb bits, the
+  // score x (fixed point) in the high 64 - kb bits; 0 is an empty slot
+  uint64_t* hslot;
+  int kb;
   uint64_t* cx;  // candidate scores
   uint32_t* ck;  // candidate keys (i)
   uint64_t* sx;  // verified: scores
@@ -360,7 +362,7 @@ struct MipsArgs {
 };
 
 hipError_t launch_mips_query_info(const float* Q, int64_t nq, int64_t d,
-                                  MipsQuery* qi, hipStream_t st);
+                                  int kb, MipsQuery* qi, hipStream_t st);
 hipError_t launch_sample_mips(const MipsArgs& a, int unroll, int grid,
                               hipStream_t st);
 hipError_t launch_mips_post(const MipsArgs& a, hipStream_t st);

@@ -70,8 +70,11 @@ def _check_query(A, q, qvec, g, o, t):
 
 
 def _oracle_query(A, qvec, q, s, tp, t, seed=SEED):
+    # a batch keeps each score beside its key i + 1 in one 64-bit slot, so
+    # its exponent is taken with the key's bits (the bit length of m)
     op = oracle.Plan.dense(A, qvec[None, :].copy())
-    o = op.topk(seed=seed, s=int(s), t_prime=int(tp), t=t, qid=q)
+    F = op.fix_exponent(int(s), key_bits=int(A.shape[0]).bit_length())
+    o = op.topk(seed=seed, s=int(s), t_prime=int(tp), t=t, F=F, qid=q)
     keys, x, closed = op.scores(seed=seed, s=int(s), F=o["F"], qid=q)
     op.close()
     return o, keys, x, closed
@@ -255,3 +258,29 @@ def test_low_precision_screen_keeps_results(mad_gpu, prec):
                 assert np.array_equal(back[q]["i"].cpu().numpy(),
                                       ref[q]["i"].cpu().numpy())
         gp.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tied_scores_take_the_digit_selection(mad_gpu, prec):
+    # Every database row is +v or -v, so every candidate has the same |c|
+    # and the final top t is decided by i alone, among more candidates than
+    # the post kernel's LDS list holds (2048); with the bf16 screen, every
+    # candidate also survives it.  Both take the general selection paths.
+    m, d = 5000, 16
+    V, Qg = workloads.dense_gaussian(1, 2, d, seed=7)
+    sgn = np.where((np.arange(m) * 2654435761) % 7 < 3, -1.0, 1.0)
+    A = (sgn[:, None] * V[0][None, :]).astype(np.float32)
+    s = np.array([40000, 30000], np.int64)
+    tp = np.array([10**6, 10**6], np.int64)
+    gp = mad_gpu.MipsPlan.create(to_dev(A))
+    if prec:
+        gp.set_verify_precision(prec)
+    res = gp.batch(to_dev(Qg), s, tp, T, seed=SEED)
+    st = gp.mips_stats(2)
+    for q in range(2):
+        say("query", q, "candidates", int(st["n_cand"][q]))
+        assert st["n_cand"][q] > 2048
+        o, _, _, _ = _oracle_query(A, Qg[q], q, s[q], tp[q], T)
+        assert np.array_equal(res[q]["i"].cpu().numpy(), o["key"])
+        _check_query(A, q, Qg[q], res[q], o, T)
+    gp.close()

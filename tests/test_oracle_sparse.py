@@ -258,3 +258,27 @@ def test_mips_form_matches_general_plan_with_one_vector():
     for key in ("k", "i", "j", "kp", "inc"):
         assert np.array_equal(a[key], b[key])
     assert np.all(a["j"] == 0)
+
+
+@pytest.mark.parametrize("kb", [0, 1, 20, 31])
+def test_keyed_exponent_keeps_every_score_in_its_bits(kb):
+    # Reading R7 with a kb-bit key beside the score: a signed field of
+    # 64 - kb bits holds [-2^(63-kb), 2^(63-kb)).  The largest score s
+    # increments can reach is s rne(max|b| 2^F), every sample on one pair
+    # with the largest |b|; it must stay within 2^(62-kb).
+    for bmax in (1e-3, 0.75, 1.0, 1.5, 2.0, 3.999, 4.0, 1e3):
+        p = oracle.Plan.dense(np.ones((1, 1), np.float32),
+                              np.full((1, 1), bmax, np.float32))
+        for s in (1, 2, 3, 1000, 1024, 1025, 10**5):
+            F = p.fix_exponent(s, key_bits=kb)
+            assert F == p.fix_exponent(s) - kb
+            top = s * np.rint(np.ldexp(np.float64(np.float32(bmax)), F))
+            assert top <= 2.0 ** (62 - kb)
+        # m = n = d = 1: every sample is the same diamond, x = s * inc
+        s = 1000
+        F = p.fix_exponent(s, key_bits=kb)
+        keys, x, closed = p.scores(seed=3, s=s, F=F)
+        inc = int(np.rint(np.ldexp(np.float64(np.float32(bmax)), F)))
+        assert closed == s and keys.tolist() == [0]
+        assert int(x[0]) == s * inc and abs(int(x[0])) <= 2 ** (62 - kb)
+        p.close()
