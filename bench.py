@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--binary", type=float, default=0.0,
                     help="dense configs: 0/1 inputs of the same shape with "
                          "this density (the binary inputs of Alg. 1)")
+    ap.add_argument("--ceilings-sweep", action="store_true",
+                    help="print the memory probe rates over buffers of "
+                         "0.25 MB to 512 MB (one JSON line each) and exit")
     return ap.parse_args()
 
 
@@ -660,6 +663,14 @@ def main():
     import paper_1506_03872_amd as mad
     import workloads
 
+    if args.ceilings_sweep:
+        for lw in (15, 18, 21, 23, 25, 26):
+            r = memory_ceilings(mad, footprint_words=1 << lw)
+            print(json.dumps({"footprint_MB": (8 << lw) / 2**20,
+                              "G_ops_per_s": {k: round(v, 2)
+                                              for k, v in r.items()}}),
+                  flush=True)
+        return
     log("generating %s" % args.config)
     cfg, data = workloads.make(args.config, seed=args.seed)
     if cfg["kind"] == "mips":

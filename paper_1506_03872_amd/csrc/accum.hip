@@ -7,9 +7,10 @@
 // (exact in int64, rint is odd).  So the sampler needs no atomics and a
 // pair takes 12 bytes.  X is the sum of the increments per key, computed
 // as:
-//   count    per tile of pairs, a histogram of the bin = top B1 bits of
-//            mix64(key) (bins are disjoint in keys); open samples dropped;
-//   scan     exclusive prefix of the tile counts in bin-major order;
+//   count    per group of tiles of pairs, a histogram of the bin = top B1
+//            bits of mix64(key) (bins are disjoint in keys); open samples
+//            dropped;
+//   scan     exclusive prefix of the group counts in bin-major order;
 //   place    every closed pair written into its bin's range;
 //   split    (large s) one workgroup per bin partitions it again by the next
 //            B2 hash bits, so that bins hold about 512 pairs; above 8 bits
@@ -84,108 +85,130 @@ __device__ __forceinline__ uint32_t bin_of(uint64_t key, int B) {
   return B ? (uint32_t)(mix64(key) >> (64 - B)) : 0u;
 }
 
-// count: per tile, histogram of bins -> cnt[bin * tiles + tile]; the
-// entry after the last, cnt[tiles << B], is set to 0 so that the exclusive
-// scan leaves the number of closed pairs there.  Each thread loads its
-// kAccPer pairs of the tile before any of them is counted.
+// Count and place walk the pairs in tiles of kAccTile; a workgroup takes a
+// group of consecutive tiles (about kAccGroups groups in all, enough to
+// fill the chip), so that the per-(bin, group) counts and offsets are
+// written and read once per group instead of once per tile: a tile's share
+// of a bin follows the shares of the group's earlier tiles, through a
+// per-bin cursor kept in LDS.
+constexpr int64_t kAccGroups = 2048;
+
+static inline int64_t acc_group_tiles(int64_t tiles) {
+  const int64_t g = tiles / kAccGroups;
+  return g < 1 ? 1 : g;
+}
+
+// count: per group, histogram of bins -> cnt[bin * groups + group]; the
+// entry after the last, cnt[groups << B], is set to 0 so that the
+// exclusive scan leaves the number of closed pairs there.  Each thread
+// loads its kAccPer pairs of a tile before any of them is counted.
 __global__ __launch_bounds__(kAccThreads) void k_acc_count(
-    const uint64_t* pk, int64_t n, int B, int64_t tiles, uint64_t* cnt) {
-  // pk: the keys
+    const uint64_t* pk, int64_t n, int B, int64_t gt, int64_t groups,
+    uint64_t* cnt) {
+  // pk: the keys; gt: tiles per group
   __shared__ unsigned h[1 << kAccMaxBits];
   const int nb = 1 << B;
   for (int b = threadIdx.x; b < nb; b += kAccThreads) h[b] = 0;
   __syncthreads();
-  const int64_t t0 = (int64_t)blockIdx.x * kAccTile + threadIdx.x;
-  uint64_t key[kAccPer];
+  const int64_t tiles = (n + kAccTile - 1) / kAccTile;
+  const int64_t tl0 = (int64_t)blockIdx.x * gt;
+  const int64_t tl1 = tl0 + gt < tiles ? tl0 + gt : tiles;
+  for (int64_t tile = tl0; tile < tl1; ++tile) {
+    const int64_t t0 = tile * kAccTile + threadIdx.x;
+    uint64_t key[kAccPer];
 #pragma unroll
-  for (int u = 0; u < kAccPer; ++u) {
-    const int64_t e = t0 + (int64_t)u * kAccThreads;
-    key[u] = e < n ? pk[e] : kEmptyKey;
+    for (int u = 0; u < kAccPer; ++u) {
+      const int64_t e = t0 + (int64_t)u * kAccThreads;
+      key[u] = e < n ? pk[e] : kEmptyKey;
+    }
+#pragma unroll
+    for (int u = 0; u < kAccPer; ++u)
+      if (key[u] != kEmptyKey) atomicAdd(&h[bin_of(key[u], B)], 1u);
   }
-#pragma unroll
-  for (int u = 0; u < kAccPer; ++u)
-    if (key[u] != kEmptyKey) atomicAdd(&h[bin_of(key[u], B)], 1u);
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += kAccThreads)
-    cnt[(int64_t)b * tiles + blockIdx.x] = h[b];
-  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[tiles << B] = 0;
+    cnt[(int64_t)b * groups + blockIdx.x] = h[b];
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[groups << B] = 0;
 }
 
-// place: every pair into its bin's range.  The tile is first sorted by bin
+// place: every pair into its bin's range.  Each tile is first sorted by bin
 // in LDS (the order inside a tile's share of a bin does not matter), so
-// that each bin's share is stored as one contiguous run.
+// that each bin's share is stored as one contiguous run at the bin's
+// cursor, which then advances by the share.
 __global__ __launch_bounds__(kAccThreads) void k_acc_place(
-    const uint64_t* pk, const float* pv, int64_t n, int B, int64_t tiles,
-    const uint64_t* offs, uint64_t* ok, float* ov) {
+    const uint64_t* pk, const float* pv, int64_t n, int B, int64_t gt,
+    int64_t groups, const uint64_t* offs, uint64_t* ok, float* ov) {
   __shared__ unsigned long long base[1 << kAccMaxBits];
-  __shared__ unsigned h[1 << kAccMaxBits];
+  __shared__ unsigned h[(1 << kAccMaxBits) + 1];  // h[nb]: the tile's total
   __shared__ unsigned long long sk[kAccTile];
   __shared__ float sv[kAccTile];
   __shared__ unsigned char sb[kAccTile];
   const int nb = 1 << B;
-  for (int b = threadIdx.x; b < nb; b += kAccThreads) {
-    h[b] = 0;
-    base[b] = offs[(int64_t)b * tiles + blockIdx.x];
-  }
-  const int64_t t0 = (int64_t)blockIdx.x * kAccTile;
-  uint64_t key[kAccPer];
-  float val[kAccPer];
-  uint32_t bin[kAccPer], rank[kAccPer];
+  for (int b = threadIdx.x; b < nb; b += kAccThreads)
+    base[b] = offs[(int64_t)b * groups + blockIdx.x];
+  const int64_t tiles = (n + kAccTile - 1) / kAccTile;
+  const int64_t tl0 = (int64_t)blockIdx.x * gt;
+  const int64_t tl1 = tl0 + gt < tiles ? tl0 + gt : tiles;
+  for (int64_t tile = tl0; tile < tl1; ++tile) {
+    for (int b = threadIdx.x; b < nb; b += kAccThreads) h[b] = 0;
+    const int64_t t0 = tile * kAccTile;
+    uint64_t key[kAccPer];
+    float val[kAccPer];
+    uint32_t bin[kAccPer], rank[kAccPer];
 #pragma unroll
-  for (int u = 0; u < kAccPer; ++u) {
-    const int64_t e = t0 + u * kAccThreads + threadIdx.x;
-    key[u] = e < n ? pk[e] : kEmptyKey;
-    val[u] = e < n ? pv[e] : 0.0f;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < kAccPer; ++u) {
-    bin[u] = key[u] == kEmptyKey ? 0u : bin_of(key[u], B);
-    rank[u] = key[u] == kEmptyKey ? 0u : atomicAdd(&h[bin[u]], 1u);
-  }
-  __syncthreads();
-  // local starts: exclusive prefix of h (nb <= 256: one wave, 4 per lane)
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    unsigned v[4], sum = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = lane * 4 + q;
-      v[q] = b < nb ? h[b] : 0u;
-      sum += v[q];
+    for (int u = 0; u < kAccPer; ++u) {
+      const int64_t e = t0 + u * kAccThreads + threadIdx.x;
+      key[u] = e < n ? pk[e] : kEmptyKey;
+      val[u] = e < n ? pv[e] : 0.0f;
     }
-    unsigned ex = wave_incl_scan(sum) - sum;
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = lane * 4 + q;
-      if (b < nb) h[b] = ex;
-      ex += v[q];
+    for (int u = 0; u < kAccPer; ++u) {
+      bin[u] = key[u] == kEmptyKey ? 0u : bin_of(key[u], B);
+      rank[u] = key[u] == kEmptyKey ? 0u : atomicAdd(&h[bin[u]], 1u);
     }
-  }
-  __syncthreads();
+    __syncthreads();
+    // local starts: exclusive prefix of h (nb <= 256: one wave, 4 per
+    // lane); h[nb] = the tile's closed pairs
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      unsigned v[4], sum = 0;
 #pragma unroll
-  for (int u = 0; u < kAccPer; ++u) {
-    if (key[u] == kEmptyKey) continue;
-    const unsigned p = h[bin[u]] + rank[u];
-    sk[p] = key[u];
-    sv[p] = val[u];
-    sb[p] = (unsigned char)bin[u];
-  }
-  // the tile's closed pairs are sk[0 .. total), total = its non-EMPTY keys
-  __shared__ unsigned total;
-  if (threadIdx.x == 0) total = 0;
-  __syncthreads();
-  unsigned mine = 0;
+      for (int q = 0; q < 4; ++q) {
+        const int b = lane * 4 + q;
+        v[q] = b < nb ? h[b] : 0u;
+        sum += v[q];
+      }
+      unsigned ex = wave_incl_scan(sum) - sum;
 #pragma unroll
-  for (int u = 0; u < kAccPer; ++u) mine += key[u] != kEmptyKey;
-  mine = wave_sum(mine);
-  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&total, mine);
-  __syncthreads();
-  for (unsigned i = threadIdx.x; i < total; i += kAccThreads) {
-    const unsigned b = sb[i];
-    const int64_t d = (int64_t)base[b] + (int64_t)(i - h[b]);
-    ok[d] = sk[i];
-    ov[d] = sv[i];
+      for (int q = 0; q < 4; ++q) {
+        const int b = lane * 4 + q;
+        if (b < nb) h[b] = ex;
+        ex += v[q];
+      }
+      if (lane == 63) h[nb] = ex;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kAccPer; ++u) {
+      if (key[u] == kEmptyKey) continue;
+      const unsigned p = h[bin[u]] + rank[u];
+      sk[p] = key[u];
+      sv[p] = val[u];
+      sb[p] = (unsigned char)bin[u];
+    }
+    __syncthreads();
+    const unsigned total = h[nb];
+    for (unsigned i = threadIdx.x; i < total; i += kAccThreads) {
+      const unsigned b = sb[i];
+      const int64_t d = (int64_t)base[b] + (int64_t)(i - h[b]);
+      ok[d] = sk[i];
+      ov[d] = sv[i];
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kAccThreads)
+      base[b] += h[b + 1] - h[b];
+    __syncthreads();
   }
 }
 
@@ -384,12 +407,12 @@ static hipError_t acc_scan(uint64_t* a, int64_t n, uint64_t* tmp,
   return hipGetLastError();
 }
 
-// first-level bin starts: starts[b] = offs[b * tiles] (b <= nb; the last
+// first-level bin starts: starts[b] = offs[b * groups] (b <= nb; the last
 // is the number of closed pairs)
-__global__ void k_acc_starts1(const uint64_t* offs, int64_t tiles, int B1,
+__global__ void k_acc_starts1(const uint64_t* offs, int64_t groups, int B1,
                               uint64_t* starts) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b <= (int64_t(1) << B1)) starts[b] = offs[b * tiles];
+  if (b <= (int64_t(1) << B1)) starts[b] = offs[b * groups];
 }
 
 // second level: one workgroup per first-level bin partitions its pairs by
@@ -585,7 +608,9 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
   if (work_bytes < accum_bytes(n)) return hipErrorInvalidValue;
   const int B1 = acc_b1(n), B2 = acc_b2(n);
   const int64_t tiles = (n + kAccTile - 1) / kAccTile;
-  const int64_t ncnt = tiles << B1;
+  const int64_t gt = acc_group_tiles(tiles);
+  const int64_t groups = (tiles + gt - 1) / gt;
+  const int64_t ncnt = groups << B1;
   const int64_t nb1 = int64_t(1) << B1;
   char* p = (char*)work;
   uint64_t* placed = (uint64_t*)p;
@@ -593,7 +618,7 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
   float* placed_v = (float*)p;
   p += ((size_t)n * 4 + 15) / 16 * 16;
   uint64_t* cnt = (uint64_t*)p;
-  p += ((size_t)ncnt + 1) * 8;
+  p += ((size_t)(tiles << B1) + 1) * 8;  // room for one group per tile
   uint64_t* starts = (uint64_t*)p;
   p += (((size_t)1 << (B1 + B2)) + 1) * 8;
   uint64_t* starts1 = (uint64_t*)p;
@@ -601,18 +626,18 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
   uint64_t* bin_distinct = (uint64_t*)p;
   p += (((size_t)1 << (B1 + B2)) + 1) * 8;
   uint64_t* tmp = (uint64_t*)p;  // scan partial sums
-  k_acc_count<<<(unsigned)tiles, kAccThreads, 0, st>>>(keys, n, B1, tiles,
-                                                       cnt);
+  k_acc_count<<<(unsigned)groups, kAccThreads, 0, st>>>(keys, n, B1, gt,
+                                                        groups, cnt);
   if ((e = acc_scan(cnt, ncnt + 1, tmp, st)) != hipSuccess) return e;
-  k_acc_place<<<(unsigned)tiles, kAccThreads, 0, st>>>(
-      keys, vals, n, B1, tiles, cnt, placed, placed_v);
+  k_acc_place<<<(unsigned)groups, kAccThreads, 0, st>>>(
+      keys, vals, n, B1, gt, groups, cnt, placed, placed_v);
   if (B2 == 0) {
-    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
+    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, groups, B1,
                                                             starts);
     launch_reduce(n >> B1, nb1, placed, placed_v, starts, B1, bmax, s_for_F,
                   okey, oval, bin_distinct, st);
   } else if (B2 <= kAccSplitBits) {
-    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
+    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, groups, B1,
                                                             starts1);
     k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
         placed, placed_v, starts1, B1, B2, keys, vals, starts);
@@ -624,7 +649,7 @@ hipError_t launch_accumulate(uint64_t* keys, float* vals, int64_t n,
     // the middle starts live in bin_distinct until the reduce writes it
     const int Ba = (B2 + 1) / 2, Bb = B2 - Ba;
     uint64_t* starts_mid = bin_distinct;
-    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, tiles, B1,
+    k_acc_starts1<<<acc_blocks(nb1 + 1, 256), 256, 0, st>>>(cnt, groups, B1,
                                                             starts1);
     k_acc_split2<<<(unsigned)nb1, kAcc2Threads, 0, st>>>(
         placed, placed_v, starts1, B1, Ba, keys, vals, starts_mid);
