@@ -51,6 +51,15 @@ struct DenseTables {
   // joined back into the caller's stream
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // T0 (of at most 512 slots) is built on `aux` as soon as the T1 and T2
+  // totals exist (events t1tot, t2tot), beside the rest of T1 and T2; the
+  // sampler's first order passes then run on `aux` too (order_done), once
+  // the previous sampling launch is done with the order buffers (sampled).
+  // t0_aux: the last build put T0 there.
+  hipStream_t aux = nullptr;
+  hipEvent_t t1tot = nullptr, t2tot = nullptr, t0done = nullptr;
+  hipEvent_t order_done = nullptr, sampled = nullptr;
+  int t0_aux = 0;
 };
 
 hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,

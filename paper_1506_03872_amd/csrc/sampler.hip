@@ -1021,12 +1021,26 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     uint32_t* cnt = (uint32_t*)((char*)kbuf + align256((size_t)c * 2));
     uint32_t* tot = cnt + nblk * d;
     uint32_t* start = tot + d;
-    k_order_count<<<(unsigned)nblk, 256, lds_ord, st>>>(a, cnt, kbuf);
-    k_order_colscan<<<(unsigned)d, 256, 0, st>>>(cnt, nblk, d, tot);
-    k_order_starts<<<1, 256, 0, st>>>(tot, d, start);
+    // the first chunk's order needs only T0: when the build put T0 on the
+    // aux stream, the order passes follow it there, beside the rest of the
+    // table build, once the previous launch has sampled from the buffers
+    const bool on_aux = t.t0_aux && c0 == 0;
+    hipStream_t os = on_aux ? t.aux : st;
+    if (on_aux) {
+      const hipError_t ew = hipStreamWaitEvent(t.aux, t.sampled, 0);
+      if (ew != hipSuccess) return ew;
+    }
+    k_order_count<<<(unsigned)nblk, 256, lds_ord, os>>>(a, cnt, kbuf);
+    k_order_colscan<<<(unsigned)d, 256, 0, os>>>(cnt, nblk, d, tot);
+    k_order_starts<<<1, 256, 0, os>>>(tot, d, start);
     const size_t lds_place = 8 * (size_t)d + 6 * (size_t)kOrdPer;
-    k_order_place<<<(unsigned)nblk, 256, lds_place, st>>>(a, cnt, start, kbuf,
+    k_order_place<<<(unsigned)nblk, 256, lds_place, os>>>(a, cnt, start, kbuf,
                                                          ell);
+    if (on_aux) {
+      hipError_t ew = hipEventRecord(t.order_done, t.aux);
+      if (ew == hipSuccess) ew = hipStreamWaitEvent(st, t.order_done, 0);
+      if (ew != hipSuccess) return ew;
+    }
     if (main_start && c0 == 0) (void)hipEventRecord(main_start, st);
     int64_t g8 = order_g8();
     if (pipe) {
@@ -1077,7 +1091,8 @@ hipError_t launch_sample_dense(const DenseTables& t, const float* B,
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  // the order buffers are free again once this launch's samplers are done
+  return t.t0_aux ? hipEventRecord(t.sampled, st) : hipSuccess;
 }
 
 hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,

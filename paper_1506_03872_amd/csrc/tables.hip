@@ -1131,7 +1131,7 @@ static size_t col_tables_fixed_bytes(int64_t S, int64_t N, int L) {
 static hipError_t col_tables(const float* X, int64_t d, const double* scale,
                              int64_t S, int64_t N, int L, Family& f,
                              void* scratch, size_t scratch_bytes,
-                             hipStream_t st) {
+                             hipStream_t st, hipEvent_t tot_ready = nullptr) {
   const int64_t R = (N + kRun - 1) / kRun;
   const int64_t Np = int64_t(1) << L;
   const int64_t B = Np / kRun;
@@ -1155,6 +1155,10 @@ static hipError_t col_tables(const float* X, int64_t d, const double* scale,
     k_col_runtot<false><<<(unsigned)(R * tiles), 64, 0, st>>>(X, d, scale, S,
                                                               N, rtot);
   k_col_runoffsets<<<(unsigned)S, 256, 0, st>>>(rtot, S, R, E, f.tot);
+  if (tot_ready) {  // the family's totals are final from here on
+    const hipError_t e = hipEventRecord(tot_ready, st);
+    if (e != hipSuccess) return e;
+  }
   const bool f64 = L <= kF64MaxL;
   const unsigned sgrid = (unsigned)(B * tiles);
   if (scale && f64)
@@ -1332,12 +1336,16 @@ hipError_t dense_tables_alloc(DenseTables& t, int64_t m, int64_t n,
       hipSuccess)
     return e;
   if ((e = hipStreamCreateWithFlags(&t.side, hipStreamNonBlocking)) !=
-      hipSuccess)
+          hipSuccess ||
+      (e = hipStreamCreateWithFlags(&t.aux, hipStreamNonBlocking)) !=
+          hipSuccess)
     return e;
-  if ((e = hipEventCreateWithFlags(&t.fork, hipEventDisableTiming)) !=
-      hipSuccess)
-    return e;
-  return hipEventCreateWithFlags(&t.join, hipEventDisableTiming);
+  for (hipEvent_t* ev : {&t.fork, &t.join, &t.t1tot, &t.t2tot, &t.t0done,
+                         &t.order_done, &t.sampled})
+    if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) !=
+        hipSuccess)
+      return e;
+  return hipSuccess;
 }
 
 void dense_tables_free(DenseTables& t) {
@@ -1350,14 +1358,18 @@ void dense_tables_free(DenseTables& t) {
   if (t.bad) (void)hipFree(t.bad);
   if (t.bbits) (void)hipFree(t.bbits);
   t.bbits = nullptr;
-  if (t.fork) (void)hipEventDestroy(t.fork);
-  if (t.join) (void)hipEventDestroy(t.join);
+  for (hipEvent_t* ev : {&t.fork, &t.join, &t.t1tot, &t.t2tot, &t.t0done,
+                         &t.order_done, &t.sampled}) {
+    if (*ev) (void)hipEventDestroy(*ev);
+    *ev = nullptr;
+  }
   if (t.side) (void)hipStreamDestroy(t.side);
+  if (t.aux) (void)hipStreamDestroy(t.aux);
   t.om = nullptr;
   t.bmax = nullptr;
   t.bad = nullptr;
-  t.fork = t.join = nullptr;
-  t.side = nullptr;
+  t.side = t.aux = nullptr;
+  t.t0_aux = 0;
 }
 
 static size_t run_doubles(int64_t S, int64_t N) {
@@ -1439,6 +1451,10 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   hipStream_t sd = one_stream ? st : t.side;
   if (B && !one_stream && (e = hipEventRecord(t.fork, st)) != hipSuccess)
     return e;
+  // T0 on the aux stream (it needs no scratch when it has at most 512
+  // slots), started by the T1 and T2 totals
+  const bool t0_aux = B && !one_stream && t.T0.L <= 9;
+  t.t0_aux = 0;
   // T3[i]: k' given i, weight |a_k'i|; totals na_i (the draw of k' in
   // Alg. 3)
   // (enqueued before the B side so that this stream has work at once)
@@ -1467,11 +1483,14 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
       k_binary_bitmap<<<(unsigned)blocks, 256, 0, sd>>>(B, n * d, t.bbits,
                                                         t.bad + 6);
     }
-    e = t.T2.L <= 9
-            ? small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,
-                           t.T2.ent, sd)
-            : col_tables(B, d, nullptr, d, n, t.T2.L, t.T2, side_scratch,
-                         need_side, sd);
+    if (t.T2.L <= 9) {
+      e = small_tables(WColAbs{B, d, nullptr}, d, n, t.T2.L, t.T2.tot,
+                       t.T2.ent, sd);
+      if (e == hipSuccess && t0_aux) e = hipEventRecord(t.t2tot, sd);
+    } else {
+      e = col_tables(B, d, nullptr, d, n, t.T2.L, t.T2, side_scratch,
+                     need_side, sd, t0_aux ? t.t2tot : nullptr);
+    }
     const hipError_t ej =
         one_stream ? hipSuccess : hipEventRecord(t.join, sd);
     if (e == hipSuccess) e = ej;
@@ -1479,20 +1498,38 @@ hipError_t dense_tables_build(DenseTables& t, const float* A, const float* B,
   }
 
   // T1[k]: i given k, weight |a_ki| na_i; totals v_k
-  if (e == hipSuccess)
-    e = t.T1.L <= 9
-            ? small_tables(WColAbs{A, d, t.na}, d, m, t.T1.L, t.T1.tot,
-                           t.T1.ent, st)
-            : col_tables(A, d, t.na, d, m, t.T1.L, t.T1, scratch_buf.p,
-                         need, st);
+  if (e == hipSuccess) {
+    if (t.T1.L <= 9) {
+      e = small_tables(WColAbs{A, d, t.na}, d, m, t.T1.L, t.T1.tot, t.T1.ent,
+                       st);
+      if (e == hipSuccess && t0_aux) e = hipEventRecord(t.t1tot, st);
+    } else {
+      e = col_tables(A, d, t.na, d, m, t.T1.L, t.T1, scratch_buf.p, need, st,
+                     t0_aux ? t.t1tot : nullptr);
+    }
+  }
+  // T0: k with weight nb_k v_k; total ||W||_1 (the weights w_ki
+  // of Alg. 3 and its draw of (k, i)).  On the aux stream it runs beside
+  // the rest of T1 and T2, and the caller's stream waits for it.
+  if (e == hipSuccess && t0_aux) {
+    if ((e = hipStreamWaitEvent(t.aux, t.t1tot, 0)) != hipSuccess ||
+        (e = hipStreamWaitEvent(t.aux, t.t2tot, 0)) != hipSuccess)
+      return e;
+    k_stage0_weights<<<grid_for(d, 256), 256, 0, t.aux>>>(t.nb, t.v, d,
+                                                          t.om);
+    if ((e = small_tables(WExplicit{t.om}, 1, d, t.T0.L, t.T0.tot, t.T0.ent,
+                          t.aux)) != hipSuccess ||
+        (e = hipEventRecord(t.t0done, t.aux)) != hipSuccess)
+      return e;
+    t.t0_aux = 1;
+  }
   // the B side joins here; without B (MIPS) only the A side is built
   if (B && !one_stream) {
     const hipError_t ew = hipStreamWaitEvent(st, t.join, 0);
     if (e == hipSuccess) e = ew;
   }
-  if (e != hipSuccess || !B) return e;
-  // T0: k with weight nb_k v_k; total ||W||_1 (the weights w_ki
-  // of Alg. 3 and its draw of (k, i))
+  if (e == hipSuccess && t.t0_aux) e = hipStreamWaitEvent(st, t.t0done, 0);
+  if (e != hipSuccess || !B || t.t0_aux) return e;
   if (e == hipSuccess) {
     k_stage0_weights<<<grid_for(d, 256), 256, 0, st>>>(t.nb, t.v, d, t.om);
     if (t.T0.L <= 9) {
