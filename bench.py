@@ -299,6 +299,7 @@ def bench_mips(args, cfg, data, mad):
     # phase split from an eager run of the same batch
     tplan = mad.MipsPlan.create(A, flags=mad.MAD_FLAG_TIMING)
     tplan.set_config(tuned["chunk"], tuned["unroll"], tuned["grid"])
+    tplan.set_table_factor(tuned["slots"])
     tplan.batch_raw(Q, s_q, tp_q, t, args.seed, out, n_out)
     tplan.batch_raw(Q, s_q, tp_q, t, args.seed, out, n_out)
     ph = tplan.phase_ms()

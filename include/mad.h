@@ -396,14 +396,33 @@ int mips_topk_batch(mad_plan* plan, const float* Q, int64_t nq,
 int mips_get_config(mad_plan* plan, int* chunk, int* unroll, int* grid);
 int mips_set_config(mad_plan* plan, int chunk, int unroll, int grid);
 
+/* Score-table slots per possible key of a query (2, 4 or 8; default 2):
+ * query q's open-addressing table holds factor * max(min(s_q, m), 512)
+ * slots rounded up to a power of two.  A larger table passes fewer taken
+ * slots per insert but takes longer to clear and to scan; results never
+ * change.  A new factor re-plans the next batch. */
+int mips_get_table_factor(mad_plan* plan, int* slots_per_key);
+int mips_set_table_factor(mad_plan* plan, int slots_per_key);
+
 /* Autotuner: runs the batch (arguments as mips_topk_batch) under a set of
- * launch shapes, `reps` timed replays each, keeps the fastest in the plan
- * and reports its time per batch in *best_ms (host, optional).  Results
- * are identical under every shape.  Synchronises. */
+ * launch shapes and table factors, `reps` timed replays each, keeps the
+ * fastest in the plan and reports its time per batch in *best_ms (host,
+ * optional).  Results are identical under every shape.  Synchronises.
+ * With a choice file (mips_autotune_cache), a batch whose signature (the
+ * device's architecture, m, d, nq, the sum and largest of the s_q, the
+ * sum of the t'_q, t and the verification precision) is in the file takes
+ * the stored choice and its time without any trial; otherwise the tuned
+ * choice is appended to the file (MAD_EINVAL when it cannot be written). */
 int mips_autotune(mad_plan* plan, const float* Q, int64_t nq,
                   const int64_t* s_per_query, const int64_t* tprime_per_query,
                   int64_t t, uint64_t seed, mad_pair* out, int64_t* n_out,
                   int reps, void* stream, double* best_ms);
+
+/* Text file of the autotuner's choices for this plan (host path, copied;
+ * NULL or "" = none): one line per signature, "<signature> | chunk unroll
+ * grid slots_per_key ms"; the last line of a signature counts.  Calls that
+ * write one file from several processes at once may interleave lines. */
+int mips_autotune_cache(mad_plan* plan, const char* path);
 
 /* Statistics of the last batch (synchronises): n_pos[q] = |Omega_s| and
  * n_cand[q] = verified candidates (host arrays of nq, optional), closed

@@ -36,6 +36,7 @@ EXPORTS = (
     "mad_plan_verify_stats", "mad_debug_accumulate", "mad_plan_set_option",
     "mad_plan_get_option", "mad_accumulate_noalloc",
     "mad_bruteforce_topk_csr", "mad_debug_lowp_screen",
+    "mips_get_table_factor", "mips_set_table_factor", "mips_autotune_cache",
 )
 
 
@@ -101,6 +102,9 @@ def lib():
         L.mips_set_config.argtypes = [_P, C.c_int, C.c_int, C.c_int]
         L.mips_autotune.argtypes = [_P, _P, _i64, _P, _P, _i64, _u64, _P, _P,
                                     C.c_int, _P, _P]
+        L.mips_get_table_factor.argtypes = [_P, _P]
+        L.mips_set_table_factor.argtypes = [_P, C.c_int]
+        L.mips_autotune_cache.argtypes = [_P, C.c_char_p]
         L.mips_stats.argtypes = [_P, _P, _P, _P, _P]
         L.mips_debug_scores.argtypes = [_P, _i64, _P, _P, _i64, _P, _P]
         _lib = L
@@ -408,6 +412,19 @@ class MipsPlan(Plan):
     def set_config(self, chunk, unroll, grid):
         _check(lib().mips_set_config(self._h, chunk, unroll, grid))
 
+    def table_factor(self):
+        f = C.c_int()
+        _check(lib().mips_get_table_factor(self._h, C.byref(f)))
+        return f.value
+
+    def set_table_factor(self, slots_per_key):
+        _check(lib().mips_set_table_factor(self._h, slots_per_key))
+
+    def set_autotune_cache(self, path):
+        """File of the autotuner's choices (None: none)."""
+        _check(lib().mips_autotune_cache(
+            self._h, None if path is None else str(path).encode()))
+
     def autotune(self, Q, s, tp, t, seed=0, reps=2, stream=None):
         import torch
         s, tp = self._budgets(s, tp)
@@ -421,7 +438,7 @@ class MipsPlan(Plan):
             tp.ctypes.data_as(_P), t, seed, _dev(out, torch.int64, "out"),
             _dev(n_out, torch.int64, "n_out"), reps, _stream(stream),
             C.byref(best)))
-        return dict(self.config(), ms=best.value)
+        return dict(self.config(), slots=self.table_factor(), ms=best.value)
 
     def mips_stats(self, nq):
         import numpy as np

@@ -70,9 +70,11 @@ struct MipsState {
   std::vector<int64_t> s, tp;
   int64_t nq = -1, t = -1;
   int64_t hslots = 0, nchunks = 0;
-  int chunk_prepared = -1;
-  // launch shape (result-invariant)
-  int chunk = 4096, unroll = 4, grid = 2048;
+  int chunk_prepared = -1, slots_prepared = -1;
+  // launch shape and score-table slots per possible key (result-invariant)
+  int chunk = 4096, unroll = 4, grid = 2048, slots = 2;
+  // file of the autotuner's choices ("" = none)
+  std::string tune_cache;
   // captured graph and what it was captured for
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -192,6 +194,76 @@ static int check_bad_inputs(mad_plan* p, hipStream_t st) {
   if (bad) return fail(MAD_EINVAL, "A or B holds NaN or Inf");
   return MAD_OK;
 }
+
+namespace {
+
+// what a tuned choice depends on: the device, the database shape and the
+// batch's budgets (their count, sum and largest), t and the verification
+// precision
+std::string tune_signature(mad_plan* p, int64_t nq, const int64_t* s,
+                           const int64_t* tp, int64_t t) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return std::string();
+  long long ssum = 0, smax = 0, tsum = 0;
+  for (int64_t q = 0; q < nq; ++q) {
+    ssum += s[q];
+    smax = s[q] > smax ? s[q] : smax;
+    tsum += tp[q];
+  }
+  char buf[512];
+  snprintf(buf, sizeof buf,
+           "%s m=%lld d=%lld nq=%lld s_sum=%lld s_max=%lld tp_sum=%lld "
+           "t=%lld prec=%d",
+           prop.gcnArchName, (long long)p->m, (long long)p->d, (long long)nq,
+           ssum, smax, tsum, (long long)t, p->verify_prec);
+  for (char* c = buf; *c; ++c)
+    if (*c == '|' || *c == '\n') *c = '_';
+  return std::string(buf);
+}
+
+struct TuneChoice {
+  int chunk, unroll, grid, slots;
+  double ms;
+};
+
+// the last line of the file for this signature: "<signature> | chunk
+// unroll grid slots ms"; lines that do not parse are skipped
+bool tune_lookup(const std::string& path, const std::string& sig,
+                 TuneChoice* c) {
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char* bar = strstr(line, " | ");
+    if (!bar) continue;
+    if ((size_t)(bar - line) != sig.size() ||
+        strncmp(line, sig.c_str(), sig.size()) != 0)
+      continue;
+    TuneChoice x;
+    if (sscanf(bar + 3, "%d %d %d %d %lf", &x.chunk, &x.unroll, &x.grid,
+               &x.slots, &x.ms) == 5) {
+      *c = x;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+bool tune_append(const std::string& path, const std::string& sig,
+                 const TuneChoice& c) {
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return false;
+  const int n = fprintf(f, "%s | %d %d %d %d %.4f\n", sig.c_str(), c.chunk,
+                        c.unroll, c.grid, c.slots, c.ms);
+  return fclose(f) == 0 && n > 0;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1283,6 +1355,7 @@ static int mips_prepare(mad_plan* p, int64_t nq, const int64_t* s,
   MipsState* ms = p->mips;
   const bool same = nq == ms->nq && t == ms->t &&
                     ms->chunk_prepared == ms->chunk &&
+                    ms->slots_prepared == ms->slots &&
                     std::equal(s, s + nq, ms->s.begin()) &&
                     std::equal(tp, tp + nq, ms->tp.begin());
   if (same) return MAD_OK;
@@ -1300,7 +1373,8 @@ static int mips_prepare(mad_plan* p, int64_t nq, const int64_t* s,
     const int64_t sc1 = sq > 0 ? sq : 1;
     if (tpe > sc1) tpe = sc1;
     if (tpe < t) tpe = t;
-    const int64_t hcap = next_pow2(2 * (pairs > 512 ? pairs : 512));
+    const int64_t hcap =
+        next_pow2((int64_t)ms->slots * (pairs > 512 ? pairs : 512));
     x.s = sq;
     x.tp = tpe;
     x.hoff = hs;
@@ -1370,6 +1444,7 @@ static int mips_prepare(mad_plan* p, int64_t nq, const int64_t* s,
   ms->hslots = hs;
   ms->nchunks = (int64_t)ch.size();
   ms->chunk_prepared = ms->chunk;
+  ms->slots_prepared = ms->slots;
   ++ms->layout_version;
   return MAD_OK;
 }
@@ -1577,11 +1652,30 @@ int mips_set_config(mad_plan* p, int chunk, int unroll, int grid) {
   return MAD_OK;
 }
 
+int mips_get_table_factor(mad_plan* p, int* slots_per_key) {
+  if (!p || p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  if (slots_per_key) *slots_per_key = p->mips->slots;
+  return MAD_OK;
+}
+
+int mips_set_table_factor(mad_plan* p, int slots_per_key) {
+  if (!p || p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  if (slots_per_key != 2 && slots_per_key != 4 && slots_per_key != 8)
+    return fail(MAD_EINVAL, "slots per key must be 2, 4 or 8");
+  p->mips->slots = slots_per_key;
+  return MAD_OK;
+}
+
+int mips_autotune_cache(mad_plan* p, const char* path) {
+  if (!p || p->kind != 1) return fail(MAD_EINVAL, "not a MIPS plan");
+  p->mips->tune_cache = path ? path : "";
+  return MAD_OK;
+}
+
 int mips_autotune(mad_plan* p, const float* Q, int64_t nq,
                   const int64_t* s_per_query, const int64_t* tprime_per_query,
                   int64_t t, uint64_t seed, mad_pair* out, int64_t* n_out,
                   int reps, void* stream, double* best_ms) {
-  g_err.clear();
   int rc = mips_check_batch(p, Q, nq, s_per_query, tprime_per_query, t, out,
                             n_out);
   if (rc != MAD_OK) return rc;
@@ -1591,18 +1685,32 @@ int mips_autotune(mad_plan* p, const float* Q, int64_t nq,
   if (reps < 1) reps = 1;
   hipStream_t st = (hipStream_t)stream;
   MipsState* ms = p->mips;
+  std::string sig;
+  if (!ms->tune_cache.empty()) {
+    sig = tune_signature(p, nq, s_per_query, tprime_per_query, t);
+    if (sig.empty()) return fail(MAD_EHIP, "autotune: device properties");
+    TuneChoice c;
+    if (tune_lookup(ms->tune_cache, sig, &c) &&
+        mips_set_config(p, c.chunk, c.unroll, c.grid) == MAD_OK &&
+        mips_set_table_factor(p, c.slots) == MAD_OK) {
+      if (best_ms) *best_ms = c.ms;
+      return MAD_OK;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0), "autotune");
   HIP_TRY(hipEventCreate(&e1), "autotune");
   static const int chunks[] = {1024, 4096, 16384, 65536};
   static const int unrolls[] = {2, 4, 8};
   static const int grids[] = {1024, 2048, 4096};
+  static const int factors[] = {2, 4};
   double best = 1e300;
-  int bc = ms->chunk, bu = ms->unroll, bg = ms->grid;
-  auto trial = [&](int c, int u, int g) -> int {
+  int bc = ms->chunk, bu = ms->unroll, bg = ms->grid, bf = ms->slots;
+  auto trial = [&](int c, int u, int g, int f) -> int {
     ms->chunk = c;
     ms->unroll = u;
     ms->grid = g;
+    ms->slots = f;
     int r = mips_topk_batch(p, Q, nq, s_per_query, tprime_per_query, t, seed,
                             out, n_out, stream);  // warm (and capture)
     if (r != MAD_OK) return r;
@@ -1621,23 +1729,34 @@ int mips_autotune(mad_plan* p, const float* Q, int64_t nq,
       bc = c;
       bu = u;
       bg = g;
+      bf = f;
     }
     return MAD_OK;
   };
-  // chunk and unroll at the default grid, then the grid
+  // chunk and unroll at the default grid and table factor, then the grid,
+  // then the table factor
+  const int f0 = ms->slots;
   for (int c : chunks)
     for (int u : unrolls)
-      if ((rc = trial(c, u, 2048)) != MAD_OK) break;
+      if ((rc = trial(c, u, 2048, f0)) != MAD_OK) break;
   if (rc == MAD_OK)
     for (int g : grids)
-      if (g != 2048 && (rc = trial(bc, bu, g)) != MAD_OK) break;
+      if (g != 2048 && (rc = trial(bc, bu, g, f0)) != MAD_OK) break;
+  if (rc == MAD_OK)
+    for (int f : factors)
+      if (f != f0 && (rc = trial(bc, bu, bg, f)) != MAD_OK) break;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ms->chunk = bc;
   ms->unroll = bu;
   ms->grid = bg;
+  ms->slots = bf;
   if (rc != MAD_OK) return rc;
   if (best_ms) *best_ms = best;
+  if (!sig.empty() &&
+      !tune_append(ms->tune_cache, sig, TuneChoice{bc, bu, bg, bf, best}))
+    return fail(MAD_EINVAL, "autotune: cannot append to %s",
+                ms->tune_cache.c_str());
   return MAD_OK;
 }
 

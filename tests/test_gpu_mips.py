@@ -284,3 +284,54 @@ def test_tied_scores_take_the_digit_selection(mad_gpu, prec):
         assert np.array_equal(res[q]["i"].cpu().numpy(), o["key"])
         _check_query(A, q, Qg[q], res[q], o, T)
     gp.close()
+
+
+def test_table_factor_and_choice_file(mad_gpu, tmp_path):
+    # The score tables' slots per key never change a result.  With a
+    # choice file, a second plan takes the first plan's tuned choice for
+    # the same batch without trials, and the file keeps one line.
+    A, Q = _db(m=2000, d=32, nq=8, seed=6)
+    Qd = to_dev(Q)
+    gp = mad_gpu.MipsPlan.create(to_dev(A))
+    ref = gp.batch(Qd, S, TP, T, seed=SEED)
+    ref_x = {q: gp.query_scores(q) for q in (3, 4)}
+    for f in (4, 8, 2):
+        gp.set_table_factor(f)
+        assert gp.table_factor() == f
+        got = gp.batch(Qd, S, TP, T, seed=SEED)
+        for q in range(len(S)):
+            if ref[q] is None:
+                assert got[q] is None
+                continue
+            for key in ("i", "c", "x"):
+                assert np.array_equal(got[q][key].cpu().numpy(),
+                                      ref[q][key].cpu().numpy()), (f, q, key)
+        for q in (3, 4):
+            k, x, F = gp.query_scores(q)
+            assert np.array_equal(k, ref_x[q][0])
+            assert np.array_equal(x, ref_x[q][1]) and F == ref_x[q][2]
+    with pytest.raises(mad_gpu.MadError):
+        gp.set_table_factor(3)
+    path = tmp_path / "mips_choices.txt"
+    gp.set_autotune_cache(path)
+    first = gp.autotune(Qd, S, TP, T, seed=SEED, reps=1)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and " | " in lines[0]
+    say("tuned", first, lines[0])
+    gp2 = mad_gpu.MipsPlan.create(to_dev(A))
+    gp2.set_autotune_cache(path)
+    second = gp2.autotune(Qd, S, TP, T, seed=SEED, reps=1)
+    for key in ("chunk", "unroll", "grid", "slots"):
+        assert second[key] == first[key], key
+    assert abs(second["ms"] - first["ms"]) < 1e-3
+    assert len(path.read_text().splitlines()) == 1
+    got = gp2.batch(Qd, S, TP, T, seed=SEED)
+    for q in range(len(S)):
+        if ref[q] is not None:
+            assert np.array_equal(got[q]["i"].cpu().numpy(),
+                                  ref[q]["i"].cpu().numpy())
+    # another batch (other budgets) is tuned and appended
+    gp2.autotune(Qd, S + 1, TP + 1, T, seed=SEED, reps=1)
+    assert len(path.read_text().splitlines()) == 2
+    gp.close()
+    gp2.close()
