@@ -142,3 +142,28 @@ def test_mixed_vector_scales(mad_gpu, prec):
     assert np.array_equal(rlo["c"].cpu().numpy(), r32["c"].cpu().numpy())
     check_against_exact(A, B, r32, t)
     check_against_exact(A, B, rlo, t)
+
+
+def test_benchmark_ground_truth_matches_the_oracle(gpu):
+    # The benchmark's recall ground truth (FP64 products on the GPU in row
+    # blocks, torch.topk) against the oracle's exact top t on the same
+    # inputs: the same pairs and |c| within FP64 rounding of each other.
+    import torch
+    import bench
+    A, B = workloads.dense_gaussian(700, 1500, 48, seed=9)
+    t = 50
+    k, v = bench.exact_topk_gpu(torch.from_numpy(A).cuda(),
+                                torch.from_numpy(B).cuda(), t)
+    k_ex, c_ex = oracle.exact_topk(A, B, t)
+    assert np.array_equal(np.sort(k), np.sort(k_ex))
+    assert np.allclose(np.sort(v)[::-1], np.sort(np.abs(c_ex))[::-1],
+                       rtol=1e-12, atol=0)
+    # the per-query form used for the MIPS recall
+    Q = B[:6]
+    idx, val = bench.exact_topk_rows(torch.from_numpy(A).cuda(),
+                                     torch.from_numpy(Q).cuda(), 10, blk=4)
+    for q in range(len(Q)):
+        kq, cq = oracle.exact_topk(A, Q[q:q + 1], 10)
+        assert np.array_equal(np.sort(idx[q]), np.sort(kq))  # n = 1: key = i
+        assert np.allclose(np.sort(val[q])[::-1], np.sort(np.abs(cq))[::-1],
+                           rtol=1e-12, atol=0)
