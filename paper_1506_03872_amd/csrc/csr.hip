@@ -1103,8 +1103,8 @@ void csr_tables_free(CsrTables& t) {
   ragged_free(t.T3);
   family_free_pub(t.T0);
   void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
-                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.bpack,
-                t.at_pay, t.bt_pay};
+                t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.at_pay,
+                t.bh, t.bh_slot};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
@@ -1116,26 +1116,45 @@ void csr_tables_free(CsrTables& t) {
   t.om = nullptr;
   t.bmax = nullptr;
   t.bad = nullptr;
-  t.b_unit = nullptr;
-  t.bpack = nullptr;
-  t.bpack_ok = nullptr;
-  t.at_pay = t.bt_pay = nullptr;
+  t.at_pay = nullptr;
+  t.bh = nullptr;
+  t.bh_slot = nullptr;
+  t.bh_mask = 0;
   dev_free(t.work);
 }
 
 static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st);
 
-// b_j's compressed row as start | length << 40; *ok = 0 when a row does not
-// fit (the sampler then loads b_ptr)
-__global__ void k_pack_rows(const int64_t* ptr, int64_t rows, uint64_t* pk,
-                            int* ok) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const int64_t s = ptr[r], len = ptr[r + 1] - s;
-  const bool fits = s >= 0 && s < (int64_t(1) << 40) && len >= 0 &&
-                    len < (int64_t(1) << 24);
-  pk[r] = fits ? (uint64_t)s | ((uint64_t)len << 40) : 0ull;
-  if (!fits) *ok = 0;  // every writer stores the same value
+// B's entries into the hash table: one thread per row j, each entry's key
+// j d + k + 1 claimed by compare-and-swap at its first free slot from
+// mix64(key) (linear probing; the table is at most half full), its slot
+// kept in bslot[e].  Keys are unique in a valid structure; a repeated one
+// finds its own slot.
+__global__ void k_bhash_insert(const int64_t* ptr, const int32_t* idx,
+                               int64_t rows, int64_t d, BSlot* bh,
+                               uint64_t mask, uint32_t* bslot) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= rows) return;
+  for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) {
+    const uint64_t key = (uint64_t)j * (uint64_t)d + (uint64_t)idx[e] + 1;
+    uint64_t sl = mix64(key) & mask;
+    while (true) {
+      const unsigned long long prev = atomicCAS(
+          (unsigned long long*)&bh[sl].key, 0ull, (unsigned long long)key);
+      if (prev == 0ull || prev == key) break;
+      sl = (sl + 1) & mask;
+    }
+    bslot[e] = (uint32_t)sl;
+  }
+}
+
+// the values of B's entries into their slots (every build)
+__global__ void k_bhash_vals(const float* val, const uint32_t* bslot,
+                             int64_t n, BSlot* bh) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += stride)
+    bh[bslot[e]].val = val[e];
 }
 
 // out[p] = pay[item[p]]: the payload of the item at each transpose position
@@ -1164,10 +1183,14 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = hipMalloc(&t.at_src, 4 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = hipMalloc(&t.bt_src, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_w, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
-        (e = hipMalloc(&t.bpack, 8 * (size_t)(n + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_pay, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
-        (e = hipMalloc(&t.bt_pay, 8 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
+      return e;
+    int64_t cap = 1024;
+    while (cap < 2 * t.nnzB) cap <<= 1;
+    t.bh_mask = (uint64_t)(cap - 1);
+    if ((e = hipMalloc(&t.bh, sizeof(BSlot) * (size_t)cap)) != hipSuccess ||
+        (e = hipMalloc(&t.bh_slot, 4 * (size_t)(t.nnzB + 1))) != hipSuccess)
       return e;
   }
   if (!check && t.structured) {
@@ -1209,14 +1232,14 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
     if ((bad & 2) || (check && (bad & 1))) return hipErrorInvalidValue;
     t.validated = true;
   }
-  // B's rows packed for the T2 payload (structure only)
-  t.bpack_ok = t.bad + 34;
-  if ((e = launch_fill_u64((uint64_t*)t.bpack_ok, 1, 1ull, st)) !=
-      hipSuccess)
+  // B's entries into the hash table (structure only; the values follow in
+  // every build)
+  if ((e = launch_fill_u64((uint64_t*)t.bh, 2 * (int64_t)(t.bh_mask + 1),
+                           0ull, st)) != hipSuccess)
     return e;
   if (n > 0)
-    k_pack_rows<<<blocks_of(n, 256), 256, 0, st>>>(t.in.b_ptr, n, t.bpack,
-                                                   t.bpack_ok);
+    k_bhash_insert<<<blocks_of(n, 256), 256, 0, st>>>(
+        t.in.b_ptr, t.in.b_idx, n, d, t.bh, t.bh_mask, t.bh_slot);
   // transposes
   const int64_t nz = t.nnzA > t.nnzB ? t.nnzA : t.nnzB;
   if ((e = dev_alloc(t.work, sort_bytes(nz))) != hipSuccess) return e;
@@ -1233,15 +1256,11 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
       (e = ragged_layout(t.T1, t.at_ptr, d, st)) != hipSuccess ||
       (e = ragged_layout(t.T2, t.bt_ptr, d, st)) != hipSuccess)
     return e;
-  // the T1 / T2 payloads by transpose position (structure only)
+  // the T1 payloads by transpose position (structure only)
   if (t.nnzA > 0)
     k_gather_pay<<<blocks_of(t.nnzA, 256 * 8) < 2048
                        ? blocks_of(t.nnzA, 256 * 8) : 2048,
                    256, 0, st>>>(t.at_row, t.nnzA, t.T3.meta, t.at_pay);
-  if (t.nnzB > 0)
-    k_gather_pay<<<blocks_of(t.nnzB, 256 * 8) < 2048
-                       ? blocks_of(t.nnzB, 256 * 8) : 2048,
-                   256, 0, st>>>(t.bt_row, t.nnzB, t.bpack, t.bt_pay);
   size_t need = ragged_scratch_bytes(t.T3);
   need = std::max(need, ragged_scratch_bytes(t.T1));
   need = std::max(need, ragged_scratch_bytes(t.T2));
@@ -1250,19 +1269,6 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
   if ((e = dev_alloc(t.work, need)) != hipSuccess) return e;
   t.structured = true;
   return csr_tables_from_transposes(t, st);
-}
-
-// the tables from the transposes and the layouts already in place
-// 1 in *flag unless some stored value differs from 1 (then 0): for 0/1
-// inputs a fourth edge that is present is 1, and the sampler skips its load
-__global__ void k_unit_check(const float* v, int64_t n, int* flag) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += stride)
-    if (v[e] != 1.0f) {
-      *flag = 0;  // every writer stores the same value
-      return;
-    }
 }
 
 // w[p] = |tval[p]| * scale[trow[p]]: the same product ColItems forms
@@ -1274,15 +1280,13 @@ __global__ void k_col_scaled(const float* tval, const uint32_t* trow,
     w[p] = fabs((double)tval[p]) * scale[trow[p]];
 }
 
+// the tables from the transposes and the layouts already in place
 static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
-  // B's unit-value flag lives in the spare words of t.bad's allocation
-  t.b_unit = t.bad + 32;
-  hipError_t eu = launch_fill_u64((uint64_t*)t.b_unit, 1, 1ull, st);
-  if (eu != hipSuccess) return eu;
+  // this build's values of B's entries into their hash slots
   if (t.nnzB > 0)
-    k_unit_check<<<blocks_of(t.nnzB, 256 * 16) < 1024
-                       ? blocks_of(t.nnzB, 256 * 16) : 1024,
-                   256, 0, st>>>(t.in.b_val, t.nnzB, t.b_unit);
+    k_bhash_vals<<<blocks_of(t.nnzB, 256 * 8) < 2048
+                       ? blocks_of(t.nnzB, 256 * 8) : 2048,
+                   256, 0, st>>>(t.in.b_val, t.bh_slot, t.nnzB, t.bh);
   hipError_t e;
   const int64_t d = t.d;
   // T3 (totals na), T1 (weights |a_ki| na_i, totals v), T2 (totals nb), T0
@@ -1294,12 +1298,13 @@ static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
                        ? blocks_of(t.nnzA, 256 * 8) : 2048,
                    256, 0, st>>>(t.at_val, t.at_row, t.T3.tot, t.nnzA,
                                  t.at_w);
-  // T1's payload: T3's meta word of the drawn i; T2's: b_j's packed row
+  // T1's payload: T3's meta word of the drawn i (T2 needs none: the fourth
+  // edge comes from the hash table of B's entries)
   if ((e = ragged_build(t.T1,
                         ColItems{t.at_val, t.at_row, t.T3.tot, t.at_w},
                         t.work.p, st, t.at_pay)) != hipSuccess ||
       (e = ragged_build(t.T2, ColItems{t.bt_val, t.bt_row, nullptr},
-                        t.work.p, st, t.bt_pay)) != hipSuccess)
+                        t.work.p, st)) != hipSuccess)
     return e;
   k_stage0_csr<<<blocks_of(d, 256), 256, 0, st>>>(t.T2.tot, t.T1.tot, d,
                                                   t.om);
@@ -1325,8 +1330,9 @@ struct CsrSampleArgs {
   uint64_t seed, qid;
   int64_t l0, count;
   int gram;  // B = A: key of the pair with i < j, diagonal left out
-  const int* b_unit;  // 1: every value of B is 1 (no fourth-edge value load)
-  const int* bpack_ok;  // 1: T2's payloads hold b_j's rows (else b_ptr)
+  const BSlot* bh;      // B's entries by key j d + k + 1 (see CsrTables)
+  uint64_t bh_mask;
+  int64_t d;
   // squared variant (Sec. 3.2.3): the second pair of sample e, keyed by
   // (k, k') like the first, goes to pk2[e] / pv2[e] (pair form only)
   uint64_t* pk2;
@@ -1374,8 +1380,6 @@ __global__ __launch_bounds__(256) void k_sample_csr(
   __syncthreads();
   const uint64_t* T0 = t0_lds ? t0s : a.T0;
   const int F = DEBUG ? F_debug : fix_exponent(*bmax, s_for_F);
-  const bool unit = *a.b_unit != 0;
-  const bool packed = *a.bpack_ok != 0;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long nclosed = 0, ncreated = 0;
@@ -1404,8 +1408,8 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       x1[u] = a.e1[meta_slot(mt1[u], W1[u])];
       x2[u] = a.e2[meta_slot(mt2[u], W2[u])];
     }
-    // T3's meta of i and b_j's row come with the drawn entries (payloads)
-    uint64_t mt3[U], pj[U];
+    // T3's meta of i comes with the drawn T1 entry (its payload)
+    uint64_t mt3[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const Drawn di = draw16(x1[u], W1[u]);
@@ -1414,40 +1418,50 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       j[u] = dj.pos;
       sg[u] = di.sgn ^ dj.sgn;
       mt3[u] = draw_pay(x1[u], W1[u]);
-      pj[u] = draw_pay(x2[u], W2[u]);
     }
-    int64_t lo[U], hi[U];
     Ent32 x3[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      x3[u] = a.e3[meta_slot(mt3[u], W3[u])];
-      if (packed) {
-        lo[u] = (int64_t)(pj[u] & ((1ull << 40) - 1));
-        hi[u] = lo[u] + (int64_t)(pj[u] >> 40);
-      } else {
-        lo[u] = a.in.b_ptr[j[u]];
-        hi[u] = a.in.b_ptr[j[u] + 1];
-      }
-    }
+    for (int u = 0; u < U; ++u) x3[u] = a.e3[meta_slot(mt3[u], W3[u])];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const Drawn dk = draw16(x3[u], W3[u]);
       kp[u] = dk.pos;
       sg[u] ^= dk.sgn;
     }
-    // dx: the fourth edge b_k'j by binary search among b_j's coordinates
+    // dx: the fourth edge b_k'j from the table of B's entries (0 when b_j
+    // stores no coordinate k'); every sample's first probe is in flight at
+    // once, the rare further probes follow
     float v[U];
+    uint64_t hkey[U], hs[U];
+    bool pend[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int64_t l = lo[u], h = hi[u];
-      const int32_t key = (int32_t)kp[u];
-      while (l < h) {
-        const int64_t mid = (l + h) >> 1;
-        if (a.in.b_idx[mid] < key) l = mid + 1; else h = mid;
+      hkey[u] = (uint64_t)j[u] * (uint64_t)a.d + (uint64_t)kp[u] + 1;
+      hs[u] = mix64(hkey[u]) & a.bh_mask;
+      v[u] = 0.0f;
+      pend[u] = true;
+    }
+    bool anyp = true;
+    while (anyp) {
+      uint4 hw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pend[u]) hw[u] = *(const uint4*)(a.bh + hs[u]);
+      anyp = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!pend[u]) continue;
+        const uint64_t kk = (uint64_t)hw[u].x | ((uint64_t)hw[u].y << 32);
+        if (kk == hkey[u]) {
+          v[u] = __uint_as_float(hw[u].z);
+          pend[u] = false;
+        } else if (kk == 0ull) {
+          pend[u] = false;
+        } else {
+          hs[u] = (hs[u] + 1) & a.bh_mask;
+          anyp = true;
+        }
       }
-      v[u] = (l < hi[u] && a.in.b_idx[l] == key)
-                 ? (unit ? 1.0f : a.in.b_val[l])
-                 : 0.0f;
     }
     int64_t inc[U];
     bool closed[U];
@@ -1633,8 +1647,9 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.l0 = l0;
   a.count = count;
   a.gram = t.gram;
-  a.b_unit = t.b_unit;
-  a.bpack_ok = t.bpack_ok;
+  a.bh = t.bh;
+  a.bh_mask = t.bh_mask;
+  a.d = t.d;
   a.pk2 = nullptr;
   a.pv2 = nullptr;
   return a;

@@ -230,6 +230,13 @@ struct CsrView {
 // an entry at k (weight |b_kj|), T3[i] over the coordinates of a_i (weight
 // |a_k'i|).  The transposes list, per coordinate, its vectors in ascending
 // order with their values.
+// one slot of the table of B's stored entries (CsrTables::bh)
+struct BSlot {
+  uint64_t key;  // j d + k + 1 of entry b_jk; 0: empty
+  float val;     // b_jk
+  uint32_t pad;
+};
+
 struct CsrTables {
   int64_t m = 0, n = 0, d = 0, nnzA = 0, nnzB = 0;
   CsrView in{};
@@ -244,16 +251,17 @@ struct CsrTables {
   double* om = nullptr;   // d
   float* bmax = nullptr;  // 1
   int* bad = nullptr;     // 1: non-finite value, 2: malformed structure
-  int* b_unit = nullptr;  // 1: every stored value of B is 1 (in bad's block)
-  // B's rows packed as start | length << 40 (the T2 payload), and 1 in
-  // *bpack_ok when every row fits (start < 2^40, length < 2^24); else the
-  // sampler loads b_ptr
-  uint64_t* bpack = nullptr;
-  int* bpack_ok = nullptr;  // in bad's block
-  // the payloads by transpose position: at_pay[p] = T3 meta of at_row[p],
-  // bt_pay[p] = bpack[bt_row[p]] (structure only)
+  // the T1 payloads by transpose position: at_pay[p] = T3 meta of
+  // at_row[p] (structure only)
   uint64_t* at_pay = nullptr;
-  uint64_t* bt_pay = nullptr;
+  // B's stored entries in an open-addressing table of 16-byte slots keyed
+  // by j d + k + 1, at most half full: the fourth edge b_jk' is one probe
+  // of about one line instead of a search of b_j's coordinates and a load
+  // of its value.  bh_slot[e] = the slot of B's entry e (structure only);
+  // every build rewrites the values.
+  BSlot* bh = nullptr;
+  uint32_t* bh_slot = nullptr;
+  uint64_t bh_mask = 0;
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.2.2)
   int square = 0;         // B = A symmetric: x_kk' updated too (Sec. 3.2.3)
