@@ -828,12 +828,17 @@ int mad_debug_table(mad_plan* p, int which, int64_t idx, uint32_t* thr,
     if (!thr && !alias && !item) return MAD_OK;
     if (cap < Np) return fail(MAD_EINVAL, "capacity %lld < %lld slots",
                               (long long)cap, (long long)Np);
-    std::vector<mad::Ent32> host((size_t)Np);
-    HIP_TRY(hipMemcpy(host.data(), R->ent + (mt & mad::kSlotMask),
-                      sizeof(mad::Ent32) * (size_t)Np, hipMemcpyDeviceToHost),
+    // entries of R->esz bytes, each starting with the packed word and the
+    // two item ids
+    std::vector<char> host((size_t)Np * (size_t)R->esz);
+    HIP_TRY(hipMemcpy(host.data(),
+                      (const char*)R->ent +
+                          (int64_t)(mt & mad::kSlotMask) * R->esz,
+                      host.size(), hipMemcpyDeviceToHost),
             "debug table");
     for (int64_t r = 0; r < Np; ++r) {
-      const mad::Ent32& x = host[(size_t)r];
+      mad::Ent16 x;
+      memcpy(&x, host.data() + (size_t)r * (size_t)R->esz, sizeof x);
       if (thr) thr[r] = (uint32_t)x.w & mad::kLow31;
       if (alias) alias[r] = x.alias;
       if (item) item[r] = (int32_t)x.self;

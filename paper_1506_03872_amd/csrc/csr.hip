@@ -448,7 +448,8 @@ struct ColItems {  // T1 / T2: vectors with an entry at k; item = vector
 
 template <class W>
 struct EmitItems {
-  Ent32* et;
+  void* et;  // the table's first entry
+  int esz;   // 32: Ent32 with payloads, else Ent16
   W w;
   int64_t o;
   int64_t N;
@@ -457,15 +458,33 @@ struct EmitItems {
   const uint64_t* pay;
   __device__ void operator()(int r, uint32_t thr, uint32_t ss, uint32_t al,
                              uint32_t sa) const {
-    Ent32 e;
-    e.w = pack_entry(thr, ss, al, sa);
-    e.self = r < N ? w.item(o + r) : 0u;
-    e.alias = w.item(o + (int64_t)al);
-    e.pself = pay && r < N ? pay[o + r] : 0ull;
-    e.palias = pay ? pay[o + (int64_t)al] : 0ull;
-    et[r] = e;
+    const uint64_t pw = pack_entry(thr, ss, al, sa);
+    const uint32_t self = r < N ? w.item(o + r) : 0u;
+    const uint32_t alias = w.item(o + (int64_t)al);
+    if (esz == 32) {
+      Ent32 e;
+      e.w = pw;
+      e.self = self;
+      e.alias = alias;
+      e.pself = pay && r < N ? pay[o + r] : 0ull;
+      e.palias = pay ? pay[o + (int64_t)al] : 0ull;
+      ((Ent32*)et)[r] = e;
+    } else {
+      ((Ent16*)et)[r] = Ent16{pw, self, alias};
+    }
   }
 };
+
+// zero entries [r0, r1) of a table (dead tables: never sampled)
+__device__ __forceinline__ void zero_entries(void* et, int esz, int64_t r0,
+                                             int64_t r1, int64_t step) {
+  for (int64_t r = r0; r < r1; r += step) {
+    if (esz == 32)
+      ((Ent32*)et)[r] = Ent32{0ull, 0u, 0u, 0ull, 0ull};
+    else
+      ((Ent16*)et)[r] = Ent16{0ull, 0u, 0u};
+  }
+}
 
 __device__ __forceinline__ int spl_of(int L) {
   return L <= 6 ? 1 : (L == 7 ? 2 : (L == 8 ? 4 : 8));
@@ -552,7 +571,7 @@ __global__ __launch_bounds__(64) void k_ragged_lane_quanta(
 template <int SPL, class W>
 __global__ __launch_bounds__(256) void k_ragged_alias(
     W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
-    int64_t count, const double* tot, const uint64_t* q, Ent32* ent,
+    int64_t count, const double* tot, const uint64_t* q, void* ent, int esz,
     const uint64_t* pay) {
   extern __shared__ uint64_t smem64[];
   constexpr int NpMax = 64 * SPL;
@@ -567,8 +586,9 @@ __global__ __launch_bounds__(256) void k_ragged_alias(
   const int64_t N = off[seg + 1] - o;
   const int Np = 1 << L;
   const bool active = mine && tot[seg] > 0.0;
+  char* et = (char*)ent + so * esz;
   if (mine && !active)  // dead table: never sampled, entries zero
-    for (int r = lane; r < Np; r += 64) ent[so + r] = Ent32{0ull, 0u, 0u, 0ull, 0ull};
+    zero_entries(et, esz, lane, Np, 64);
   uint64_t qv[SPL];
   uint32_t sg[SPL];
 #pragma unroll
@@ -581,7 +601,7 @@ __global__ __launch_bounds__(256) void k_ragged_alias(
   wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * NpMax,
                   smem64 + (int64_t)wv * 2 * NpMax + NpMax,
                   (uint32_t*)(smem64 + 8 * NpMax) + (int64_t)wv * NpMax,
-                  EmitItems<W>{ent + so, w, o, N, pay});
+                  EmitItems<W>{et, esz, w, o, N, pay});
 }
 
 // ---------------------------------------------------------------------------
@@ -841,7 +861,8 @@ template <class W>
 __global__ __launch_bounds__(256) void k_big_merge(W w, const BigInfo* big,
                                                    const uint32_t* btab,
                                                    const double* tot,
-                                                   BigScratch sc, Ent32* ent,
+                                                   BigScratch sc, void* ent,
+                                                   int esz,
                                                    const uint64_t* pay) {
   __shared__ uint64_t sD[kBigBlk + 1], sE[kBigBlk + 1];
   __shared__ uint32_t sLi[kBigBlk + 1], sHi[kBigBlk + 1];
@@ -849,10 +870,9 @@ __global__ __launch_bounds__(256) void k_big_merge(W w, const BigInfo* big,
   const BigInfo B = big[bt];
   const int64_t bi = (int64_t)blockIdx.x - B.so / kBigBlk;
   const int64_t d0 = bi * kBigBlk;
-  Ent32* et = ent + B.so;
+  char* et = (char*)ent + B.so * esz;
   if (!(tot[B.s] > 0.0)) {  // dead table: never sampled, entries zero
-    for (int u = threadIdx.x; u < kBigBlk; u += 256)
-      et[d0 + u] = Ent32{0ull, 0u, 0u, 0ull, 0ull};
+    zero_entries(et, esz, d0 + threadIdx.x, d0 + kBigBlk, 256);
     return;
   }
   const int64_t NL = (int64_t)sc.NL[bt], NH = (int64_t)sc.NH[bt];
@@ -880,7 +900,7 @@ __global__ __launch_bounds__(256) void k_big_merge(W w, const BigInfo* big,
     if (sD[mid] <= sE[dl - mid - 1]) lo = mid + 1; else hi = mid;
   }
   int64_t a = lo, b = dl - lo;
-  const EmitItems<W> emit{et, w, B.o, B.N, pay};
+  const EmitItems<W> emit{et, esz, w, B.o, B.N, pay};
   for (int step = 0; step < kBigMergeP; ++step) {
     if (a < na && (b >= nb || sD[a] <= sE[b])) {
       const uint32_t id = sLi[a];
@@ -919,7 +939,8 @@ static void ragged_free(Ragged& R) {
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
-                                hipStream_t st) {
+                                int esz, hipStream_t st) {
+  R.esz = esz;
   std::vector<int64_t> off((size_t)S + 1);
   hipError_t e = hipMemcpyAsync(off.data(), off_dev, off.size() * 8,
                                 hipMemcpyDeviceToHost, st);
@@ -982,7 +1003,7 @@ static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
   const size_t b_ids = al256(4 * (size_t)(R.cls_off[4] + 1));
   if ((e = dev_alloc(R.lay, b_meta + b_big + b_btab + b_run + b_ids)) !=
           hipSuccess ||
-      (e = dev_alloc(R.ent_buf, sizeof(Ent32) * (size_t)(ss > 0 ? ss : 1))) !=
+      (e = dev_alloc(R.ent_buf, (size_t)esz * (size_t)(ss > 0 ? ss : 1))) !=
           hipSuccess ||
       (e = dev_alloc(R.tot_buf, 8 * (size_t)(S > 0 ? S : 1))) != hipSuccess)
     return e;
@@ -992,7 +1013,7 @@ static hipError_t ragged_layout(Ragged& R, const int64_t* off_dev, int64_t S,
   R.btab = (uint32_t*)(p + b_meta + b_big);
   R.runtab = (uint32_t*)(p + b_meta + b_big + b_btab);
   R.small_ids = (uint32_t*)(p + b_meta + b_big + b_btab + b_run);
-  R.ent = (Ent32*)R.ent_buf.p;
+  R.ent = R.ent_buf.p;
   R.tot = (double*)R.tot_buf.p;
   std::vector<char> host(b_meta + b_big + b_btab + b_run + b_ids, 0);
   memcpy(host.data(), meta.data(), 8 * meta.size());
@@ -1063,16 +1084,16 @@ static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
         w, R.off, R.meta, R.small_ids, c[4], R.tot, qs);
   if (c[1] > c[0])
     k_ragged_alias<1, W><<<blocks_of(c[1] - c[0], 4), 256, 4 * 64 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, qs, R.ent, pay);
+        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, qs, R.ent, R.esz, pay);
   if (c[2] > c[1])
     k_ragged_alias<2, W><<<blocks_of(c[2] - c[1], 4), 256, 4 * 128 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, qs, R.ent, pay);
+        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, qs, R.ent, R.esz, pay);
   if (c[3] > c[2])
     k_ragged_alias<4, W><<<blocks_of(c[3] - c[2], 4), 256, 4 * 256 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, qs, R.ent, pay);
+        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, qs, R.ent, R.esz, pay);
   if (c[4] > c[3])
     k_ragged_alias<8, W><<<blocks_of(c[4] - c[3], 4), 256, 4 * 512 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, qs, R.ent, pay);
+        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, qs, R.ent, R.esz, pay);
   if (R.nbig > 0) {
     const BigScratch sc = big_carve(scratch, R);
     const BigInfo* big = (const BigInfo*)R.big;
@@ -1086,7 +1107,7 @@ static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
     k_big_edges<<<blocks_of(R.edges, 256), 256, 0, st>>>(big, R.nbig,
                                                          R.edges, sc);
     k_big_merge<W><<<nblk, 256, 0, st>>>(w, big, R.btab, R.tot, sc, R.ent,
-                                         pay);
+                                         R.esz, pay);
   }
   return hipGetLastError();
 }
@@ -1252,9 +1273,10 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
                          st)) != hipSuccess)
     return e;
   // layouts (host)
-  if ((e = ragged_layout(t.T3, t.in.a_ptr, m, st)) != hipSuccess ||
-      (e = ragged_layout(t.T1, t.at_ptr, d, st)) != hipSuccess ||
-      (e = ragged_layout(t.T2, t.bt_ptr, d, st)) != hipSuccess)
+  // T1's entries carry T3's meta (32 bytes); T2's and T3's carry no payload
+  if ((e = ragged_layout(t.T3, t.in.a_ptr, m, 16, st)) != hipSuccess ||
+      (e = ragged_layout(t.T1, t.at_ptr, d, 32, st)) != hipSuccess ||
+      (e = ragged_layout(t.T2, t.bt_ptr, d, 16, st)) != hipSuccess)
     return e;
   // the T1 payloads by transpose position (structure only)
   if (t.nnzA > 0)
@@ -1320,11 +1342,11 @@ struct CsrSampleArgs {
   const uint64_t* T0;
   int L0;
   const uint64_t* m1;
-  const Ent32* e1;
+  const Ent32* e1;  // T1: with T3's meta of each item
   const uint64_t* m2;
-  const Ent32* e2;
+  const Ent16* e2;
   const uint64_t* m3;
-  const Ent32* e3;
+  const Ent16* e3;
   CsrView in;
   int64_t n;
   uint64_t seed, qid;
@@ -1338,6 +1360,13 @@ struct CsrSampleArgs {
   uint64_t* pk2;
   float* pv2;
 };
+
+__device__ __forceinline__ Drawn draw16(const Ent16& e, uint64_t U) {
+  const uint32_t lo = (uint32_t)e.w, hi = (uint32_t)(e.w >> 32);
+  const uint32_t coin = (uint32_t)U & kLow31;
+  const bool self = coin < (lo & kLow31);
+  return {self ? e.self : e.alias, (self ? lo : hi) >> 31};
+}
 
 __device__ __forceinline__ Drawn draw16(const Ent32& e, uint64_t U) {
   const uint32_t lo = (uint32_t)e.w, hi = (uint32_t)(e.w >> 32);
@@ -1402,7 +1431,8 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       mt1[u] = a.m1[k[u]];
       mt2[u] = a.m2[k[u]];
     }
-    Ent32 x1[U], x2[U];
+    Ent32 x1[U];
+    Ent16 x2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       x1[u] = a.e1[meta_slot(mt1[u], W1[u])];
@@ -1419,7 +1449,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       sg[u] = di.sgn ^ dj.sgn;
       mt3[u] = draw_pay(x1[u], W1[u]);
     }
-    Ent32 x3[U];
+    Ent16 x3[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) x3[u] = a.e3[meta_slot(mt3[u], W3[u])];
 #pragma unroll
@@ -1635,11 +1665,11 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.T0 = t.T0.ent;
   a.L0 = t.T0.L;
   a.m1 = t.T1.meta;
-  a.e1 = t.T1.ent;
+  a.e1 = (const Ent32*)t.T1.ent;
   a.m2 = t.T2.meta;
-  a.e2 = t.T2.ent;
+  a.e2 = (const Ent16*)t.T2.ent;
   a.m3 = t.T3.meta;
-  a.e3 = t.T3.ent;
+  a.e3 = (const Ent16*)t.T3.ent;
   a.in = t.in;
   a.n = t.n;
   a.seed = seed;

@@ -178,13 +178,18 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t* inc, hipStream_t st);
 
 // ---- csr.hip -------------------------------------------------------------
-// A 32-byte alias entry of a sparse table: the packed word of a dense entry
-// (threshold, alias position, two sign bits), the item ids (vector or
-// coordinate) of the slot's own item and of its alias, and a payload per
-// item that the sampler needs next and would otherwise load from another
-// array: for T1 (items i) the meta word of T3[i], for T2 (items j) b_j's
-// compressed row as start | length << 40 (T3: none).  The entry sits in one
-// cache line, so the payload costs no extra line per draw.
+// Alias entries of the sparse tables.  A 16-byte entry (T2, T3) holds the
+// packed word of a dense entry (threshold, alias position, two sign bits)
+// and the item ids (vector or coordinate) of the slot's own item and of its
+// alias.  A 32-byte entry (T1) adds a payload per item that the sampler
+// needs next and would otherwise load from another array: the meta word of
+// T3[i] for its items i.  Either sits in one cache line, so the payload
+// costs no extra line per draw.
+struct Ent16 {
+  uint64_t w;
+  uint32_t self;
+  uint32_t alias;
+};
 struct Ent32 {
   uint64_t w;
   uint32_t self;
@@ -206,7 +211,8 @@ struct Ragged {
   int64_t cls_off[5] = {0, 0, 0, 0, 0};  // small tables by slots per lane
   const int64_t* off = nullptr;  // S + 1 (device)
   uint64_t* meta = nullptr;      // S (device)
-  Ent32* ent = nullptr;          // slots (device)
+  void* ent = nullptr;           // slots (device): Ent32 or Ent16
+  int esz = 16;                  // bytes per entry (32: with payloads)
   double* tot = nullptr;         // S table totals (device)
   void* big = nullptr;           // per big table layout (device)
   uint32_t* btab = nullptr;      // big table of each 1024-slot block
