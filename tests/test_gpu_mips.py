@@ -335,3 +335,25 @@ def test_table_factor_and_choice_file(mad_gpu, tmp_path):
     assert len(path.read_text().splitlines()) == 2
     gp.close()
     gp2.close()
+
+
+@pytest.mark.parametrize("m", [4095, 4096])
+def test_score_slot_key_width_at_its_boundary(mad_gpu, m):
+    # The key field of a score slot has kb = bit length of m bits and holds
+    # i + 1: m = 4095 fills a 12-bit field (i + 1 up to 4095 = 2^12 - 1),
+    # m = 4096 takes 13 bits.  The rows near the end of the database carry
+    # the largest keys; they are scaled up so that they are sampled.
+    A, Q, _ = workloads.mips(m, 16, 2, seed=8)
+    A[-8:] *= 6.0
+    s = np.array([60000, 30000], np.int64)
+    tp = np.array([10**6, 500], np.int64)
+    gp = mad_gpu.MipsPlan.create(to_dev(A))
+    res = gp.batch(to_dev(Q), s, tp, T, seed=SEED)
+    for q in range(2):
+        o, ok, ox, _ = _oracle_query(A, Q[q], q, s[q], tp[q], T)
+        gk, gx, F = gp.query_scores(q)
+        assert F == o["F"]
+        assert np.array_equal(gk, ok) and np.array_equal(gx, ox)
+        assert gk.max() >= m - 8  # the last rows' keys are in the table
+        _check_query(A, q, Q[q], res[q], o, T)
+    gp.close()
