@@ -11,13 +11,15 @@
 // T1 and T2 need, per coordinate, its vectors in ascending order: a stable
 // LSD radix sort of the entries by coordinate (4-bit digits) gives the
 // transposes.  Tables have 2^ceil(log2 N) slots of 16-byte entries that
-// carry the item ids, so a draw is one load.  Tables of at most 512 items
-// are built one wave per table; larger ones one workgroup per table
+// carry the item ids, so a draw is one load (T1's entries are 32 bytes:
+// they also carry T3's meta word of each item i).  Tables of at most 512
+// items are built one wave per table; larger ones one workgroup per table
 // (two-level FP64 sums, integer quanta, then the alias lists and their
 // merge, as in the dense builder).
 //
-// The sampler draws k, i, j, k' as the dense one does and finds the fourth
-// edge b_k'j by binary search among the coordinates of b_j.
+// The sampler draws k, i, j, k' as the dense one does and reads the fourth
+// edge b_k'j from an open-addressing table of B's entries keyed by
+// j d + k' + 1 (0 when b_j stores no coordinate k').
 #include <string.h>
 
 #include <algorithm>
