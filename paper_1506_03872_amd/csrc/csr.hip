@@ -1127,7 +1127,7 @@ void csr_tables_free(CsrTables& t) {
   family_free_pub(t.T0);
   void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
                 t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.at_pay,
-                t.bh, t.bh_slot};
+                t.bh};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
@@ -1141,7 +1141,6 @@ void csr_tables_free(CsrTables& t) {
   t.bad = nullptr;
   t.at_pay = nullptr;
   t.bh = nullptr;
-  t.bh_slot = nullptr;
   t.bh_mask = 0;
   dev_free(t.work);
 }
@@ -1150,12 +1149,12 @@ static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st);
 
 // B's entries into the hash table: one thread per row j, each entry's key
 // j d + k + 1 claimed by compare-and-swap at its first free slot from
-// mix64(key) (linear probing; the table is at most half full), its slot
-// kept in bslot[e].  Keys are unique in a valid structure; a repeated one
-// finds its own slot.
+// mix64(key) (linear probing; the table is at most half full), the slot
+// then noting the entry's position e.  Keys are unique in a valid
+// structure; a repeated one finds its own slot.
 __global__ void k_bhash_insert(const int64_t* ptr, const int32_t* idx,
                                int64_t rows, int64_t d, BSlot* bh,
-                               uint64_t mask, uint32_t* bslot) {
+                               uint64_t mask) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= rows) return;
   for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) {
@@ -1167,17 +1166,19 @@ __global__ void k_bhash_insert(const int64_t* ptr, const int32_t* idx,
       if (prev == 0ull || prev == key) break;
       sl = (sl + 1) & mask;
     }
-    bslot[e] = (uint32_t)sl;
+    bh[sl].e = (uint32_t)e;
   }
 }
 
-// the values of B's entries into their slots (every build)
-__global__ void k_bhash_vals(const float* val, const uint32_t* bslot,
-                             int64_t n, BSlot* bh) {
+// every build: each taken slot gathers its entry's value (the table is
+// read in order and the values of B, a smaller array, at random)
+__global__ void k_bhash_vals(const float* val, int64_t nslots, BSlot* bh) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += stride)
-    bh[bslot[e]].val = val[e];
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       s < nslots; s += stride) {
+    const uint4 w = *(const uint4*)(bh + s);
+    if (w.x | w.y) bh[s].val = val[w.w];
+  }
 }
 
 // out[p] = pay[item[p]]: the payload of the item at each transpose position
@@ -1212,8 +1213,7 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
     int64_t cap = 1024;
     while (cap < 2 * t.nnzB) cap <<= 1;
     t.bh_mask = (uint64_t)(cap - 1);
-    if ((e = hipMalloc(&t.bh, sizeof(BSlot) * (size_t)cap)) != hipSuccess ||
-        (e = hipMalloc(&t.bh_slot, 4 * (size_t)(t.nnzB + 1))) != hipSuccess)
+    if ((e = hipMalloc(&t.bh, sizeof(BSlot) * (size_t)cap)) != hipSuccess)
       return e;
   }
   if (!check && t.structured) {
@@ -1262,7 +1262,7 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
     return e;
   if (n > 0)
     k_bhash_insert<<<blocks_of(n, 256), 256, 0, st>>>(
-        t.in.b_ptr, t.in.b_idx, n, d, t.bh, t.bh_mask, t.bh_slot);
+        t.in.b_ptr, t.in.b_idx, n, d, t.bh, t.bh_mask);
   // transposes
   const int64_t nz = t.nnzA > t.nnzB ? t.nnzA : t.nnzB;
   if ((e = dev_alloc(t.work, sort_bytes(nz))) != hipSuccess) return e;
@@ -1307,10 +1307,12 @@ __global__ void k_col_scaled(const float* tval, const uint32_t* trow,
 // the tables from the transposes and the layouts already in place
 static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
   // this build's values of B's entries into their hash slots
-  if (t.nnzB > 0)
-    k_bhash_vals<<<blocks_of(t.nnzB, 256 * 8) < 2048
-                       ? blocks_of(t.nnzB, 256 * 8) : 2048,
-                   256, 0, st>>>(t.in.b_val, t.bh_slot, t.nnzB, t.bh);
+  if (t.nnzB > 0) {
+    const int64_t nsl = (int64_t)t.bh_mask + 1;
+    k_bhash_vals<<<blocks_of(nsl, 256 * 8) < 4096
+                       ? blocks_of(nsl, 256 * 8) : 4096,
+                   256, 0, st>>>(t.in.b_val, nsl, t.bh);
+  }
   hipError_t e;
   const int64_t d = t.d;
   // T3 (totals na), T1 (weights |a_ki| na_i, totals v), T2 (totals nb), T0

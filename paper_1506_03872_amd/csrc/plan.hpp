@@ -240,7 +240,7 @@ struct CsrView {
 struct BSlot {
   uint64_t key;  // j d + k + 1 of entry b_jk; 0: empty
   float val;     // b_jk
-  uint32_t pad;
+  uint32_t e;    // the entry's position in B's compressed arrays
 };
 
 struct CsrTables {
@@ -263,10 +263,9 @@ struct CsrTables {
   // B's stored entries in an open-addressing table of 16-byte slots keyed
   // by j d + k + 1, at most half full: the fourth edge b_jk' is one probe
   // of about one line instead of a search of b_j's coordinates and a load
-  // of its value.  bh_slot[e] = the slot of B's entry e (structure only);
-  // every build rewrites the values.
+  // of its value.  The keys and entry positions are structure; every
+  // build gathers the values.
   BSlot* bh = nullptr;
-  uint32_t* bh_slot = nullptr;
   uint64_t bh_mask = 0;
   DeviceBuffer work;      // transposes' and tables' scratch
   int gram = 0;           // B = A, symmetrised scores (Sec. 3.2.2)
