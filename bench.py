@@ -409,15 +409,16 @@ def bench_mips(args, cfg, data, mad):
 
 
 # bytes one sparse sample reads and writes: stage-0 entry (8 B, L2 resident
-# for d = 1e5), the metas of T1[k] and T2[k] (8 B each), T1's 32-byte alias
-# entry (with T3's meta of i), T2's and T3's 16-byte entries, the 16-byte
-# slot of B's entry table that holds b_jk' (or the empty slot that shows it
-# absent), then the 12-byte pair written
+# for d = 1e5), the metas of T1[k] and T2[k] (8 B each), T1's and T2's
+# 32-byte alias entries (with T3's meta of i and b_j's coordinate
+# signature), T3's 16-byte entry, the 16-byte slot of B's entry table that
+# holds b_jk' (counted for every sample, though the signature rules out
+# most absent k' without it), then the 12-byte pair written
 def csr_sample_bytes(nnz_per_vec):
     """Algorithmic bytes of one sparse sample (see above).  nnz_per_vec no
     longer enters: the fourth edge is one probe whatever the row's length."""
     del nnz_per_vec
-    return 8 + 2 * 8 + 32 + 2 * 16 + 16 + PAIR_WRITE_BYTES
+    return 8 + 2 * 8 + 2 * 32 + 16 + 16 + PAIR_WRITE_BYTES
 
 
 def bench_csr(args, cfg, data, mad):

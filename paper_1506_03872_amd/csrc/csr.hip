@@ -11,15 +11,17 @@
 // T1 and T2 need, per coordinate, its vectors in ascending order: a stable
 // LSD radix sort of the entries by coordinate (4-bit digits) gives the
 // transposes.  Tables have 2^ceil(log2 N) slots of 16-byte entries that
-// carry the item ids, so a draw is one load (T1's entries are 32 bytes:
-// they also carry T3's meta word of each item i).  Tables of at most 512
+// carry the item ids, so a draw is one load (T1's and T2's entries are 32
+// bytes: they also carry T3's meta word of each item i, and the coordinate
+// signature of each vector j).  Tables of at most 512
 // items are built one wave per table; larger ones one workgroup per table
 // (two-level FP64 sums, integer quanta, then the alias lists and their
 // merge, as in the dense builder).
 //
 // The sampler draws k, i, j, k' as the dense one does and reads the fourth
 // edge b_k'j from an open-addressing table of B's entries keyed by
-// j d + k' + 1 (0 when b_j stores no coordinate k').
+// j d + k' + 1 (0 when b_j stores no coordinate k').  The signature of b_j,
+// one bit per coordinate hash, settles most absent k' without a probe.
 #include <string.h>
 
 #include <algorithm>
@@ -34,6 +36,13 @@ namespace mad {
 static inline unsigned blocks_of(int64_t n, int per) {
   int64_t g = (n + per - 1) / per;
   return (unsigned)(g < 1 ? 1 : g);
+}
+
+// the signature bit of coordinate k: the top six bits of k times the
+// golden-ratio constant (Fibonacci hashing).  A vector's signature ORs the
+// bits of its coordinates, so a clear bit proves the coordinate absent.
+__host__ __device__ __forceinline__ uint64_t coord_bit(uint64_t k) {
+  return 1ull << ((k * 0x9E3779B97F4A7C15ull) >> 58);
 }
 
 static inline int ceil_log2_i(int64_t N) {
@@ -1127,7 +1136,7 @@ void csr_tables_free(CsrTables& t) {
   family_free_pub(t.T0);
   void* ps[] = {t.at_ptr, t.at_row, t.at_val, t.at_src, t.bt_ptr, t.bt_row,
                 t.bt_val, t.bt_src, t.at_w, t.om, t.bmax, t.bad, t.at_pay,
-                t.bh};
+                t.bsig, t.bt_pay, t.bh};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t.at_ptr = t.bt_ptr = nullptr;
@@ -1140,6 +1149,8 @@ void csr_tables_free(CsrTables& t) {
   t.bmax = nullptr;
   t.bad = nullptr;
   t.at_pay = nullptr;
+  t.bsig = nullptr;
+  t.bt_pay = nullptr;
   t.bh = nullptr;
   t.bh_mask = 0;
   dev_free(t.work);
@@ -1181,6 +1192,17 @@ __global__ void k_bhash_vals(const float* val, int64_t nslots, BSlot* bh) {
   }
 }
 
+// sig[j] = OR of coord_bit(k) over the coordinates k of vector j
+__global__ void k_row_sig(const int64_t* ptr, const int32_t* idx,
+                          int64_t rows, uint64_t* sig) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= rows) return;
+  uint64_t s = 0;
+  for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e)
+    s |= coord_bit((uint64_t)(uint32_t)idx[e]);
+  sig[j] = s;
+}
+
 // out[p] = pay[item[p]]: the payload of the item at each transpose position
 __global__ void k_gather_pay(const uint32_t* item, int64_t n,
                              const uint64_t* pay, uint64_t* out) {
@@ -1208,6 +1230,8 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
         (e = hipMalloc(&t.bt_src, 4 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_w, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
         (e = hipMalloc(&t.at_pay, 8 * (size_t)(t.nnzA + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bsig, 8 * (size_t)(n + 1))) != hipSuccess ||
+        (e = hipMalloc(&t.bt_pay, 8 * (size_t)(t.nnzB + 1))) != hipSuccess ||
         (e = family_alloc_pub(t.T0, 1, d)) != hipSuccess)
       return e;
     int64_t cap = 1024;
@@ -1275,16 +1299,24 @@ hipError_t csr_tables_build(CsrTables& t, bool check, hipStream_t st) {
                          st)) != hipSuccess)
     return e;
   // layouts (host)
-  // T1's entries carry T3's meta (32 bytes); T2's and T3's carry no payload
+  // T1's entries carry T3's meta and T2's the signature of b_j (32 bytes);
+  // T3's carry no payload
   if ((e = ragged_layout(t.T3, t.in.a_ptr, m, 16, st)) != hipSuccess ||
       (e = ragged_layout(t.T1, t.at_ptr, d, 32, st)) != hipSuccess ||
-      (e = ragged_layout(t.T2, t.bt_ptr, d, 16, st)) != hipSuccess)
+      (e = ragged_layout(t.T2, t.bt_ptr, d, 32, st)) != hipSuccess)
     return e;
-  // the T1 payloads by transpose position (structure only)
+  // the T1 and T2 payloads by transpose position (structure only)
   if (t.nnzA > 0)
     k_gather_pay<<<blocks_of(t.nnzA, 256 * 8) < 2048
                        ? blocks_of(t.nnzA, 256 * 8) : 2048,
                    256, 0, st>>>(t.at_row, t.nnzA, t.T3.meta, t.at_pay);
+  if (n > 0)
+    k_row_sig<<<blocks_of(n, 256), 256, 0, st>>>(t.in.b_ptr, t.in.b_idx, n,
+                                                 t.bsig);
+  if (t.nnzB > 0)
+    k_gather_pay<<<blocks_of(t.nnzB, 256 * 8) < 2048
+                       ? blocks_of(t.nnzB, 256 * 8) : 2048,
+                   256, 0, st>>>(t.bt_row, t.nnzB, t.bsig, t.bt_pay);
   size_t need = ragged_scratch_bytes(t.T3);
   need = std::max(need, ragged_scratch_bytes(t.T1));
   need = std::max(need, ragged_scratch_bytes(t.T2));
@@ -1324,13 +1356,13 @@ static hipError_t csr_tables_from_transposes(CsrTables& t, hipStream_t st) {
                        ? blocks_of(t.nnzA, 256 * 8) : 2048,
                    256, 0, st>>>(t.at_val, t.at_row, t.T3.tot, t.nnzA,
                                  t.at_w);
-  // T1's payload: T3's meta word of the drawn i (T2 needs none: the fourth
-  // edge comes from the hash table of B's entries)
+  // T1's payload: T3's meta word of the drawn i; T2's: the signature of
+  // the drawn j, which rules out most absent fourth edges before a probe
   if ((e = ragged_build(t.T1,
                         ColItems{t.at_val, t.at_row, t.T3.tot, t.at_w},
                         t.work.p, st, t.at_pay)) != hipSuccess ||
       (e = ragged_build(t.T2, ColItems{t.bt_val, t.bt_row, nullptr},
-                        t.work.p, st)) != hipSuccess)
+                        t.work.p, st, t.bt_pay)) != hipSuccess)
     return e;
   k_stage0_csr<<<blocks_of(d, 256), 256, 0, st>>>(t.T2.tot, t.T1.tot, d,
                                                   t.om);
@@ -1348,7 +1380,7 @@ struct CsrSampleArgs {
   const uint64_t* m1;
   const Ent32* e1;  // T1: with T3's meta of each item
   const uint64_t* m2;
-  const Ent16* e2;
+  const Ent32* e2;  // T2: with the coordinate signature of each item
   const uint64_t* m3;
   const Ent16* e3;
   CsrView in;
@@ -1435,15 +1467,15 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       mt1[u] = a.m1[k[u]];
       mt2[u] = a.m2[k[u]];
     }
-    Ent32 x1[U];
-    Ent16 x2[U];
+    Ent32 x1[U], x2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       x1[u] = a.e1[meta_slot(mt1[u], W1[u])];
       x2[u] = a.e2[meta_slot(mt2[u], W2[u])];
     }
-    // T3's meta of i comes with the drawn T1 entry (its payload)
-    uint64_t mt3[U];
+    // T3's meta of i comes with the drawn T1 entry, b_j's signature with
+    // the drawn T2 entry (their payloads)
+    uint64_t mt3[U], sj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const Drawn di = draw16(x1[u], W1[u]);
@@ -1452,6 +1484,7 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       j[u] = dj.pos;
       sg[u] = di.sgn ^ dj.sgn;
       mt3[u] = draw_pay(x1[u], W1[u]);
+      sj[u] = draw_pay(x2[u], W2[u]);
     }
     Ent16 x3[U];
 #pragma unroll
@@ -1463,19 +1496,21 @@ __global__ __launch_bounds__(256) void k_sample_csr(
       sg[u] ^= dk.sgn;
     }
     // dx: the fourth edge b_k'j from the table of B's entries (0 when b_j
-    // stores no coordinate k'); every sample's first probe is in flight at
-    // once, the rare further probes follow
+    // stores no coordinate k', which a clear bit of b_j's signature already
+    // proves); every sample's first probe is in flight at once, the rare
+    // further probes follow
     float v[U];
     uint64_t hkey[U], hs[U];
     bool pend[U];
+    bool anyp = false;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       hkey[u] = (uint64_t)j[u] * (uint64_t)a.d + (uint64_t)kp[u] + 1;
       hs[u] = mix64(hkey[u]) & a.bh_mask;
       v[u] = 0.0f;
-      pend[u] = true;
+      pend[u] = (sj[u] & coord_bit(kp[u])) != 0;
+      anyp |= pend[u];
     }
-    bool anyp = true;
     while (anyp) {
       uint4 hw[U];
 #pragma unroll
@@ -1671,7 +1706,7 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
   a.m1 = t.T1.meta;
   a.e1 = (const Ent32*)t.T1.ent;
   a.m2 = t.T2.meta;
-  a.e2 = (const Ent16*)t.T2.ent;
+  a.e2 = (const Ent32*)t.T2.ent;
   a.m3 = t.T3.meta;
   a.e3 = (const Ent16*)t.T3.ent;
   a.in = t.in;

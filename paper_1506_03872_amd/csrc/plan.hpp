@@ -181,10 +181,11 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
 // Alias entries of the sparse tables.  A 16-byte entry (T2, T3) holds the
 // packed word of a dense entry (threshold, alias position, two sign bits)
 // and the item ids (vector or coordinate) of the slot's own item and of its
-// alias.  A 32-byte entry (T1) adds a payload per item that the sampler
-// needs next and would otherwise load from another array: the meta word of
-// T3[i] for its items i.  Either sits in one cache line, so the payload
-// costs no extra line per draw.
+// alias.  A 32-byte entry (T1, T2) adds a payload per item that the sampler
+// needs next and would otherwise load from another array: for T1 the meta
+// word of T3[i] for its items i, for T2 the coordinate signature of b_j
+// for its items j (see coord_bit in csr.hip).  Either sits in one cache
+// line, so the payload costs no extra line per draw.
 struct Ent16 {
   uint64_t w;
   uint32_t self;
@@ -260,6 +261,10 @@ struct CsrTables {
   // the T1 payloads by transpose position: at_pay[p] = T3 meta of
   // at_row[p] (structure only)
   uint64_t* at_pay = nullptr;
+  // the T2 payloads by transpose position: bt_pay[p] = bsig[bt_row[p]],
+  // bsig[j] the OR of coord_bit(k) over b_j's coordinates (structure only)
+  uint64_t* bsig = nullptr;   // n
+  uint64_t* bt_pay = nullptr; // nnzB
   // B's stored entries in an open-addressing table of 16-byte slots keyed
   // by j d + k + 1, at most half full: the fourth edge b_jk' is one probe
   // of about one line instead of a search of b_j's coordinates and a load
