@@ -625,7 +625,7 @@ __global__ __launch_bounds__(256) void k_ragged_alias(
 //   scan     one workgroup per table: exclusive scan of its block stats
 //   scatter  light / heavy lists in slot order
 //   edges    merge-path split at every 1024th merged position
-//   merge    1024 merged positions per workgroup -> 16-byte entries
+//   merge    1024 merged positions per workgroup -> 16- or 32-byte entries
 // ---------------------------------------------------------------------------
 struct BigInfo {
   int64_t so;     // first slot (in the big region, a multiple of 1024)

@@ -178,7 +178,7 @@ hipError_t launch_sample_dense_debug(const DenseTables& t, const float* B,
                                      int64_t* inc, hipStream_t st);
 
 // ---- csr.hip -------------------------------------------------------------
-// Alias entries of the sparse tables.  A 16-byte entry (T2, T3) holds the
+// Alias entries of the sparse tables.  A 16-byte entry (T3) holds the
 // packed word of a dense entry (threshold, alias position, two sign bits)
 // and the item ids (vector or coordinate) of the slot's own item and of its
 // alias.  A 32-byte entry (T1, T2) adds a payload per item that the sampler
@@ -268,8 +268,9 @@ struct CsrTables {
   // B's stored entries in an open-addressing table of 16-byte slots keyed
   // by j d + k + 1, at most half full: the fourth edge b_jk' is one probe
   // of about one line instead of a search of b_j's coordinates and a load
-  // of its value.  The keys and entry positions are structure; every
-  // build gathers the values.
+  // of its value (and no probe when b_j's signature rules k' out).  The
+  // keys and entry positions are structure; every build gathers the
+  // values.
   BSlot* bh = nullptr;
   uint64_t bh_mask = 0;
   DeviceBuffer work;      // transposes' and tables' scratch
