@@ -1725,13 +1725,15 @@ static CsrSampleArgs csr_args(const CsrTables& t, uint64_t seed, uint64_t qid,
 }
 
 // MAD_CSR_GRID caps the sampling grid and MAD_CSR_UNROLL (2, 4, 8, 16)
-// sets the samples per thread in flight (8 measured best: the draws are
-// chains of dependent random loads); neither changes the result
+// sets the samples per thread in flight (the draws are chains of dependent
+// random loads; with T2's 32-byte entries four per thread and a grid of up
+// to 32768 blocks measured best, eight per thread holding half as many
+// waves); neither changes the result
 static unsigned csr_grid(int64_t count, int per_thread) {
   static const int64_t cap = [] {
     const char* e = getenv("MAD_CSR_GRID");
-    const long v = e ? atol(e) : 8192;
-    return (int64_t)(v >= 256 && v <= (1 << 20) ? v : 8192);
+    const long v = e ? atol(e) : 32768;
+    return (int64_t)(v >= 256 && v <= (1 << 20) ? v : 32768);
   }();
   int64_t blocks = (count + 256LL * per_thread - 1) / (256LL * per_thread);
   if (blocks > cap) blocks = cap;
@@ -1741,8 +1743,8 @@ static unsigned csr_grid(int64_t count, int per_thread) {
 static int csr_unroll() {
   static const int u = [] {
     const char* e = getenv("MAD_CSR_UNROLL");
-    const int v = e ? atoi(e) : 8;
-    return v == 2 || v == 4 || v == 16 ? v : 8;
+    const int v = e ? atoi(e) : 4;
+    return v == 2 || v == 8 || v == 16 ? v : 4;
   }();
   return u;
 }
@@ -1769,10 +1771,10 @@ hipError_t launch_sample_csr(const CsrTables& t, uint64_t seed, uint64_t qid,
         nullptr, nullptr, nullptr);                                          \
     break;
     MAD_CSR_CASE(2)
-    MAD_CSR_CASE(4)
+    MAD_CSR_CASE(8)
     MAD_CSR_CASE(16)
     default:
-    MAD_CSR_CASE(8)
+    MAD_CSR_CASE(4)
 #undef MAD_CSR_CASE
   }
   return hipGetLastError();
