@@ -506,85 +506,26 @@ static inline int spl_class_host(int L) {  // 0..3 for 1, 2, 4, 8 slots/lane
 }
 
 // ---------------------------------------------------------------------------
-// tables of at most 512 items.  Quanta: one lane per table (ids of every
-// small table), the total in the two-level order, then the prefix again
-// with F_r and q_r (sign bit in bit 63), into q at the table's slots.  Alias: one wave
-// per table of one slots-per-lane class; every wave of the block calls
-// wave_alias, which synchronises the block.
+// tables of at most 512 items, one wave per table of one slots-per-lane
+// class (every wave of the block runs every step: the block synchronises):
+//   the table's weights go to LDS (sign bit in bit 63), coalesced;
+//   lane c < R walks run c of kRun items left to right and overwrites them
+//   with the run-local prefixes l_r, its total going to LDS;
+//   E_c and T from the run totals in the two-level order (E_0 = 0, E_{c+1}
+//   = E_c + run c's total, T = E_R), then per slot in parallel F_r =
+//   floor(2^K (E_c + l_r) / T) and q_r = F_r - F_{r-1} (slots past the items
+//   keep F = 2^K, so their quanta are zero);
+//   wave_alias builds the table from the quanta in registers.
+// (The quanta used to come from a kernel with one lane per table walking
+// its items from global memory: about 0.3 ms per C3 family, spent in the
+// walks of the longest tables.)
 // ---------------------------------------------------------------------------
-template <class W>
-__global__ __launch_bounds__(64) void k_ragged_lane_quanta(
-    W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
-    int64_t count, double* tot, uint64_t* q) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= count) return;
-  const int64_t seg = ids[g];
-  const uint64_t mt = meta[seg];
-  const int L = (int)(mt >> 56);
-  const int64_t Np = int64_t(1) << L;
-  uint64_t* qs = q + (int64_t)(mt & kSlotMask);
-  const int64_t o = off[seg];
-  const int64_t N = off[seg + 1] - o;
-  // two-level order: l restarts at each run, P_r = E + l_r
-  double E = 0.0, l = 0.0;
-  for (int64_t r0 = 0; r0 < N; r0 += 8) {
-    double wv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) wv[u] = w.w(o + (r0 + u < N ? r0 + u : N - 1));
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t r = r0 + u;
-      if (r < N) {
-        if (r > 0 && r % kRun == 0) {
-          E = E + l;
-          l = 0.0;
-        }
-        l = l + wv[u];
-      }
-    }
-  }
-  const double T = E + l;
-  tot[seg] = T;
-  const bool live = T > 0.0;
-  const int K = L + kCapBits;
-  E = 0.0;
-  l = 0.0;
-  uint64_t Fp = 0;
-  for (int64_t r0 = 0; r0 < Np; r0 += 8) {
-    double wv[8];
-    uint32_t sv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t rr = o + (r0 + u < N ? r0 + u : N - 1);
-      wv[u] = live ? w.w(rr) : 0.0;
-      sv[u] = live ? w.sgn(rr) : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t r = r0 + u;
-      if (r >= Np) break;
-      uint64_t qq = 0;
-      if (live && r < N) {
-        if (r > 0 && r % kRun == 0) {
-          E = E + l;
-          l = 0.0;
-        }
-        l = l + wv[u];
-        const uint64_t F = (uint64_t)floor(ldexp((E + l) / T, K));
-        qq = (F - Fp) | ((uint64_t)sv[u] << 63);
-        Fp = F;
-      }
-      qs[r] = qq;
-    }
-  }
-}
-
 template <int SPL, class W>
 __global__ __launch_bounds__(256) void k_ragged_alias(
     W w, const int64_t* off, const uint64_t* meta, const uint32_t* ids,
-    int64_t count, const double* tot, const uint64_t* q, void* ent, int esz,
-    const uint64_t* pay) {
+    int64_t count, double* tot, void* ent, int esz, const uint64_t* pay) {
   extern __shared__ uint64_t smem64[];
+  __shared__ double rts[4][(512 + kRun - 1) / kRun];  // run totals per wave
   constexpr int NpMax = 64 * SPL;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * 4 + wv;
@@ -594,25 +535,74 @@ __global__ __launch_bounds__(256) void k_ragged_alias(
   const int L = (int)(mt >> 56);
   const int64_t so = (int64_t)(mt & kSlotMask);
   const int64_t o = off[seg];
-  const int64_t N = off[seg + 1] - o;
+  const int N = mine ? (int)(off[seg + 1] - o) : 0;  // at most 512
   const int Np = 1 << L;
-  const bool active = mine && tot[seg] > 0.0;
+  const int K = L + kCapBits;
+  uint64_t* Ld = smem64 + (int64_t)wv * 2 * NpMax;
+  uint64_t* He = Ld + NpMax;
+  uint32_t* Hi = (uint32_t*)(smem64 + 8 * NpMax) + (int64_t)wv * NpMax;
+  for (int r = lane; r < N; r += 64)
+    Ld[r] = (uint64_t)__double_as_longlong(w.w(o + r)) |
+            ((uint64_t)w.sgn(o + r) << 63);
+  __syncthreads();
+  const int R = (N + kRun - 1) / kRun;
+  if (lane < R) {
+    const int r0 = lane * kRun, r1 = N < r0 + kRun ? N : r0 + kRun;
+    double l = 0.0;
+    for (int x0 = r0; x0 < r1; x0 += 8) {
+      uint64_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = Ld[x0 + u < r1 ? x0 + u : r1 - 1];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = x0 + u;
+        if (r < r1) {
+          const double wr = __longlong_as_double((long long)(x[u] & kQMask));
+          l = r == r0 ? wr : l + wr;
+          Ld[r] = (uint64_t)__double_as_longlong(l) | (x[u] & ~kQMask);
+        }
+      }
+    }
+    rts[wv][lane] = l;
+  }
+  __syncthreads();
+  double Ec[(512 + kRun - 1) / kRun] = {};
+  double T = 0.0;
+  for (int c = 0; c < R; ++c) {
+    Ec[c] = T;
+    T = T + rts[wv][c];
+  }
+  const bool live = mine && T > 0.0;
+  if (mine && lane == 0) tot[seg] = T;
   char* et = (char*)ent + so * esz;
-  if (mine && !active)  // dead table: never sampled, entries zero
+  if (mine && !live)  // dead table: never sampled, entries zero
     zero_entries(et, esz, lane, Np, 64);
-  uint64_t qv[SPL];
+  uint64_t F[SPL];
   uint32_t sg[SPL];
 #pragma unroll
   for (int s = 0; s < SPL; ++s) {
     const int r = lane * SPL + s;
-    const uint64_t raw = active && r < Np ? q[so + r] : 0ull;
-    qv[s] = raw & kQMask;
-    sg[s] = (uint32_t)(raw >> 63);
+    F[s] = live ? (uint64_t)1 << K : 0ull;
+    sg[s] = 0;
+    if (live && r < N) {
+      const uint64_t raw = Ld[r];
+      const double lr = __longlong_as_double((long long)(raw & kQMask));
+      F[s] = (uint64_t)floor(ldexp((Ec[r / kRun] + lr) / T, K));
+      sg[s] = (uint32_t)(raw >> 63);
+    }
   }
-  wave_alias<SPL>(qv, sg, active, L, smem64 + (int64_t)wv * 2 * NpMax,
-                  smem64 + (int64_t)wv * 2 * NpMax + NpMax,
-                  (uint32_t*)(smem64 + 8 * NpMax) + (int64_t)wv * NpMax,
-                  EmitItems<W>{et, esz, w, o, N, pay});
+  uint64_t Fp = __shfl_up(F[SPL - 1], 1, 64);
+  if (lane == 0) Fp = 0;
+  const uint64_t Fb = Fp;  // the sum of the quanta before this lane
+  uint64_t qv[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    qv[s] = F[s] - Fp;
+    Fp = F[s];
+  }
+  __syncthreads();  // the prefixes are read; wave_alias reuses Ld
+  wave_alias<SPL, true>(qv, sg, live, L, Ld, He, Hi,
+                        EmitItems<W>{et, esz, w, o, N, pay}, Fb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,14 +1040,8 @@ static size_t big_scratch_bytes(const Ragged& R) {
          al256(8 * (size_t)(R.edges + 1)) + 256;
 }
 
-// quanta of the small tables live after the big-table scratch, indexed by
-// slot like the entries
-static size_t small_q_offset(const Ragged& R) {
-  return al256(big_scratch_bytes(R));
-}
-
 static size_t ragged_scratch_bytes(const Ragged& R) {
-  return small_q_offset(R) + al256(8 * (size_t)(R.slots + 1));
+  return al256(big_scratch_bytes(R));
 }
 
 static BigScratch big_carve(void* p, const Ragged& R) {
@@ -1089,22 +1073,22 @@ static hipError_t ragged_build(const Ragged& R, W w, void* scratch,
                                hipStream_t st, const uint64_t* pay = nullptr) {
   if (R.S <= 0) return hipSuccess;
   const int64_t* c = R.cls_off;
-  uint64_t* qs = (uint64_t*)((char*)scratch + small_q_offset(R));
-  if (c[4] > 0)
-    k_ragged_lane_quanta<W><<<blocks_of(c[4], 64), 64, 0, st>>>(
-        w, R.off, R.meta, R.small_ids, c[4], R.tot, qs);
   if (c[1] > c[0])
     k_ragged_alias<1, W><<<blocks_of(c[1] - c[0], 4), 256, 4 * 64 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, qs, R.ent, R.esz, pay);
+        w, R.off, R.meta, R.small_ids + c[0], c[1] - c[0], R.tot, R.ent,
+        R.esz, pay);
   if (c[2] > c[1])
     k_ragged_alias<2, W><<<blocks_of(c[2] - c[1], 4), 256, 4 * 128 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, qs, R.ent, R.esz, pay);
+        w, R.off, R.meta, R.small_ids + c[1], c[2] - c[1], R.tot, R.ent,
+        R.esz, pay);
   if (c[3] > c[2])
     k_ragged_alias<4, W><<<blocks_of(c[3] - c[2], 4), 256, 4 * 256 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, qs, R.ent, R.esz, pay);
+        w, R.off, R.meta, R.small_ids + c[2], c[3] - c[2], R.tot, R.ent,
+        R.esz, pay);
   if (c[4] > c[3])
     k_ragged_alias<8, W><<<blocks_of(c[4] - c[3], 4), 256, 4 * 512 * 20, st>>>(
-        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, qs, R.ent, R.esz, pay);
+        w, R.off, R.meta, R.small_ids + c[3], c[4] - c[3], R.tot, R.ent,
+        R.esz, pay);
   if (R.nbig > 0) {
     const BigScratch sc = big_carve(scratch, R);
     const BigInfo* big = (const BigInfo*)R.big;
