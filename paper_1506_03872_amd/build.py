@@ -30,13 +30,22 @@ FLAGS = [
 ]
 
 
+# per-source flags: the brute-force GEMM keeps its MFMA accumulators in
+# ordinary VGPRs (180 registers instead of 180 + 64 accumulation registers),
+# so its epilogue reads them without a copy out of the accumulation file
+EXTRA = {
+    "bruteforce.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src,
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s%s" % (src, r.stdout,

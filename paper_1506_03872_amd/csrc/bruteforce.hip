@@ -171,23 +171,26 @@ __device__ __forceinline__ void frag_load(const char* la, const char* lb,
   }
 }
 
-template <int P>
+// ZERO: the accumulators start from zero (the tile's first K step)
+template <int P, bool ZERO = false>
 __device__ __forceinline__ void frag_mma(const Frag<P>& f, f16v (&acc)[2][2],
                                          const int (&sa)[2],
                                          const int (&sb)[2]) {
+  const f16v zero = {};
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
+      const f16v c = ZERO ? zero : acc[bi][bj];
       if constexpr (P == kF32)
         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-            f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0);
+            f.a[bi], f.b[bj], c, 0, 0, 0);
       else if constexpr (P == kBF16)
         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0);
+            f.a[bi], f.b[bj], c, 0, 0, 0);
       else
         acc[bi][bj] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-            f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0, sa[bi], 0, sb[bj]);
+            f.a[bi], f.b[bj], c, 0, 0, 0, sa[bi], 0, sb[bj]);
     }
 }
 
@@ -328,13 +331,17 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
     }
     MAD_BF_LSTORE(0)
     __syncthreads();
+    // the tile's first MFMAs start from a zero C operand (no per-tile
+    // clearing of the 64 accumulators); a tile always has a stage (Kp >= 1)
     f16v acc[2][2];
+    if (nst == 0) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[bi][bj][e] = 0.0f;
+          for (int e = 0; e < 16; ++e) acc[bi][bj][e] = 0.0f;
+    }
     int cur = 0;
     for (int64_t st = 0; st < nst; ++st) {
       // the next stage, else the next tile's first, else (last tile) a
@@ -352,6 +359,10 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
       } else {
         MAD_BF_GLOAD(li0, lj0, lkb)
       }
+      // keep the loads issued here, ahead of the MFMAs: without this the
+      // compiler sinks them into the LDS store below, behind the stage's
+      // MFMAs, and every stage then waits out a full memory latency
+      asm volatile("" ::: "memory");
       const char* la = lds_a[cur] + (wr * 64) * kLdsStride;
       const char* lb = lds_b[cur] + (wc * 64) * kLdsStride;
       // the next K step's operands are read from LDS while the current
@@ -364,7 +375,10 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
         if (ks + 1 < nks)
           frag_load<P>(la, lb, (ks + 1) * PT::KS * PT::EB, lane,
                        fr[(ks + 1) & 1]);
-        frag_mma<P>(fr[ks & 1], acc, sa, sb);
+        if (ks == 0 && st == 0)
+          frag_mma<P, true>(fr[0], acc, sa, sb);
+        else
+          frag_mma<P>(fr[ks & 1], acc, sa, sb);
       }
       if (more) {
         MAD_BF_LSTORE(cur ^ 1)
