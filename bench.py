@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--bruteforce-only", action="store_true",
+                    help="dense configs: only the MFMA brute force per "
+                         "precision (ms, TFLOP/s, recall), one JSON line")
     ap.add_argument("--unit-values", action="store_true",
                     help="sparse configs: every stored value 1 (0/1 inputs)")
     ap.add_argument("--no-sweep", action="store_true",
@@ -731,6 +734,14 @@ def main():
     # NaN / Inf check (and the host synchronisation that reports it)
     if not (bool(torch.isfinite(A).all()) and bool(torch.isfinite(B).all())):
         raise SystemExit("synthetic inputs hold NaN or Inf")
+    if args.bruteforce_only:
+        # the MFMA brute force alone, per precision, on this workload
+        recall_of, c_error = recall_helpers(A, B, A_h, B_h, t)
+        bf = bruteforce_report(mad, A, B, t, recall_of, c_error)
+        print(json.dumps({"workload": "dense_planted_%s" % args.config,
+                          "m": m, "n": n, "d": d, "t": t,
+                          "bruteforce": bf}), flush=True)
+        return
     # the timed steps run on a plan without phase events (each event is a
     # marker on the stream, about 2% of a C2 step); a second plan with them
     # then gives the phase times and the sampling kernel's time
@@ -803,26 +814,7 @@ def main():
         k: round(v, 3) for k, v in ceil.items()}
     extra = {}
     if not args.no_recall:
-        log("exact top-t for recall")
-        ek, ev = exact_topk_gpu(A, B, t)
-        tau = float(np.sort(ev)[::-1][t - 1])
-
-        def recall_of(i_arr, j_arr):
-            keys = i_arr * n + j_arr
-            c64 = (A_h[keys // n].astype(np.float64) *
-                   B_h[keys % n].astype(np.float64)).sum(1)
-            return float(np.count_nonzero(np.abs(c64) >= tau)) / t, keys
-
-        def c_error(i_arr, j_arr, c_arr):
-            """largest |c - c64| / |c64| of reported dot products"""
-            if len(i_arr) == 0:
-                return None
-            c64 = (A_h[i_arr].astype(np.float64) *
-                   B_h[j_arr].astype(np.float64)).sum(1)
-            err = np.abs(c_arr.astype(np.float64) - c64) / np.maximum(
-                np.abs(c64), 1e-300)
-            return float(err.max())
-
+        recall_of, c_error = recall_helpers(A, B, A_h, B_h, t)
         rec, keys = recall_of(res["i"].cpu().numpy(), res["j"].cpu().numpy())
         extra["recall_at_t"] = rec
         if "planted_i" in data:
@@ -954,6 +946,35 @@ def screen_error(plan, A_h, B_h, plan_tp):
             "max_err_over_bound": float(ratio.max()) if len(err) else None,
             "median_err_over_bound": float(np.median(ratio))
             if len(err) else None}
+
+
+def recall_helpers(A, B, A_h, B_h, t):
+    """recall_of(i, j): the share of the exact top t's threshold that the
+    pairs reach (with their keys); c_error(i, j, c): the largest relative
+    error of reported dot products against FP64."""
+    import numpy as np
+    n = B_h.shape[0]
+    log("exact top-t for recall")
+    ek, ev = exact_topk_gpu(A, B, t)
+    tau = float(np.sort(ev)[::-1][t - 1])
+
+    def recall_of(i_arr, j_arr):
+        keys = i_arr * n + j_arr
+        c64 = (A_h[keys // n].astype(np.float64) *
+               B_h[keys % n].astype(np.float64)).sum(1)
+        return float(np.count_nonzero(np.abs(c64) >= tau)) / t, keys
+
+    def c_error(i_arr, j_arr, c_arr):
+        """largest |c - c64| / |c64| of reported dot products"""
+        if len(i_arr) == 0:
+            return None
+        c64 = (A_h[i_arr].astype(np.float64) *
+               B_h[j_arr].astype(np.float64)).sum(1)
+        err = np.abs(c_arr.astype(np.float64) - c64) / np.maximum(
+            np.abs(c64), 1e-300)
+        return float(err.max())
+
+    return recall_of, c_error
 
 
 def bruteforce_report(mad, A, B, t, recall_of, c_error):
