@@ -223,7 +223,10 @@ __device__ __forceinline__ void gemm_coords(int64_t tile, int64_t tiles_m,
   j0 = (within / band_rows) * kBN;
 }
 
-template <int P, bool HIST>
+// EARLY: the next stage's loads are issued ahead of the current stage's
+// MFMAs (pays with at most four stages per tile; with longer K the loads
+// issued after the MFMAs measured faster)
+template <int P, bool HIST, bool EARLY>
 __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
   using PT = PrecT<P>;
   __shared__ __attribute__((aligned(16))) char lds_a[2][kBM * kLdsStride];
@@ -361,8 +364,8 @@ __global__ __launch_bounds__(256) void k_gemm_topk(GemmArgs g) {
       }
       // keep the loads issued here, ahead of the MFMAs: without this the
       // compiler sinks them into the LDS store below, behind the stage's
-      // MFMAs, and every stage then waits out a full memory latency
-      asm volatile("" ::: "memory");
+      // MFMAs, and the stage then waits out a full memory latency
+      if constexpr (EARLY) asm volatile("" ::: "memory");
       const char* la = lds_a[cur] + (wr * 64) * kLdsStride;
       const char* lb = lds_b[cur] + (wc * 64) * kLdsStride;
       // the next K step's operands are read from LDS while the current
@@ -527,8 +530,15 @@ static void launch_gemm(const GemmArgs& a, bool hist, hipStream_t st) {
   }
   if (grid < 8) grid = 8;
 
-  if (hist) k_gemm_topk<P, true><<<(unsigned)grid, 256, 0, st>>>(a);
-  else k_gemm_topk<P, false><<<(unsigned)grid, 256, 0, st>>>(a);
+  // early loads for tiles of at most four K stages (128-byte slices)
+  const bool early = a.Kp * PrecT<P>::EB <= 4 * kRowBytes;
+  if (hist) {
+    if (early) k_gemm_topk<P, true, true><<<(unsigned)grid, 256, 0, st>>>(a);
+    else k_gemm_topk<P, true, false><<<(unsigned)grid, 256, 0, st>>>(a);
+  } else {
+    if (early) k_gemm_topk<P, false, true><<<(unsigned)grid, 256, 0, st>>>(a);
+    else k_gemm_topk<P, false, false><<<(unsigned)grid, 256, 0, st>>>(a);
+  }
 }
 
 hipError_t lowp_prepare(const float* X, int64_t rows, int64_t d, int prec,

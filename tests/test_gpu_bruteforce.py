@@ -70,6 +70,17 @@ def test_gaussian_fp32(mad_gpu, shape):
     check_against_exact(A, B, res, t)
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_long_k_matches_exact(mad_gpu, prec):
+    # d = 600: more than four 128-byte K stages per tile in every precision,
+    # the GEMM form that issues each stage's loads after its MFMAs
+    A, B = workloads.dense_gaussian(2500, 3100, 600, seed=11)
+    res, st = mad_gpu.bruteforce_topk(to_dev(A), to_dev(B), 40,
+                                      precision=prec)
+    print("stats", st, flush=True)
+    check_against_exact(A, B, res, 40)
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_low_precision_screen_matches_fp32(mad_gpu, prec):
     # the bf16 / fp8 screen with its error bound must return exactly the fp32
