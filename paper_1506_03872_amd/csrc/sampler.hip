@@ -129,12 +129,43 @@ __global__ __launch_bounds__(256) void k_sample_dense(
   while (GROUPED ? ch < ch_hi : base < a.count) {
     OneSample smp[U];
     uint64_t U1[U], U2[U], U3[U];
+    // the samples' indices l - l0 (positions e = base + 256 u)
+    uint64_t ls[U];
+    if constexpr (GROUPED) {
+      // from the k-sorted list: each thread loads U consecutive entries in
+      // one 16-byte load and passes them through LDS, so the U entries a
+      // thread draws arrive with one memory latency (separate loads were
+      // issued one after another, each waited for before the next)
+      static_assert(U == 4, "the grouped sampler takes four samples a thread");
+      __shared__ __attribute__((aligned(16))) uint32_t ell_s[256 * U];
+      const int64_t cb = ch * go.chunk;  // go.chunk == 256 U
+      const int64_t p = cb + (int64_t)threadIdx.x * U;
+      uint4 q;
+      if (p + U <= a.count) {
+        q = *(const uint4*)(go.ell + p);
+      } else {  // the last, partial chunk: entries past the end read as 0
+        q.x = p < a.count ? go.ell[p] : 0u;
+        q.y = p + 1 < a.count ? go.ell[p + 1] : 0u;
+        q.z = p + 2 < a.count ? go.ell[p + 2] : 0u;
+        q.w = p + 3 < a.count ? go.ell[p + 3] : 0u;
+      }
+      __syncthreads();  // the previous step's reads of ell_s are done
+      *(uint4*)(ell_s + threadIdx.x * U) = q;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        ls[u] = (uint64_t)(a.l0 + (int64_t)ell_s[threadIdx.x + u * 256]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + (int64_t)u * nthreads;
+        ls[u] = (uint64_t)(a.l0 + (e < a.count ? e : 0));
+      }
+    }
     // draw of k (stage 0): from the LDS copy of T0
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t e = base + (int64_t)u * nthreads;
-      const int64_t ec = e < a.count ? e : 0;
-      const uint64_t l = (uint64_t)(a.l0 + (GROUPED ? (int64_t)go.ell[ec] : ec));
+      const uint64_t l = ls[u];
       const Philox4 r = philox4x64_10(l, a.qid, 0ull, 0ull, a.seed, 0ull);
       const uint32_t s0 = slot_of(r.w0, a.L0);
       smp[u].k = draw_entry(T0[s0], s0, r.w0).pos;
